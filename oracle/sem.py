@@ -1,0 +1,134 @@
+"""One Split-Euler-Maruyama (SEM) step with random-finite-difference drift.
+
+Follows Sec. IV and Algorithm 1 of the paper, with these readings where the
+printed signs disagree with each other (the chain rule of eq. RFDsplit and
+the first term of eq. DriDef carry flipped signs; the correct expansion is
+dN = -N (dK^T) M^-1 K N + N K^T M^-1 (dM) M^-1 K N - N K^T M^-1 (dK) N):
+
+  1. W^FT_p = kT [W^f_p / L_p ; W^tau_p], L_p the largest marker-pair distance.
+  2. Constrained solve with force W^FT, homogeneous boundary data, no noise:
+     U^R = N W^FT, lambda^R = M^-1 K U^R, and v^R = +L^-1 S lambda^R (the fluid
+     velocity the solve returns).
+  3. q^+- = q +- (delta/2) L_p W^f ; theta^+- = Rotate(theta, +-(delta/2) W^tau).
+  4. f# = (1/delta)[S(Q+) - S(Q-)] lambda^R ; unconstrained Stokes solve v# = L^-1 f#.
+  5. D^KT = (1/delta)[K^T(Q+) - K^T(Q-)] lambda^R, D^K = (1/delta)[K(Q+) - K(Q-)] U^R,
+     D^J = (1/delta)[J(Q+) - J(Q-)] v^R, D^S = J(Q) v#.
+  6. Constrained solve with force F - D^KT, slip  slip + D^K - D^J - D^S, and
+     fluid forcing sqrt(2 kT eta / (dV dt)) DT W plus the moving-wall terms.
+  7. q <- q + dt u ; theta <- Rotate(theta, dt omega).
+A step whose new markers leave the open domain along a wall axis (or whose
+body centres come closer than ``min_body_dist``) is rejected and the state is
+left unchanged; the caller repeats it with fresh random numbers.
+"""
+from __future__ import annotations
+
+import dataclasses
+from typing import Optional
+
+import numpy as np
+
+from . import bodies as B
+from . import ib
+from . import mac
+from . import rng
+from .saddle import Saddle
+
+
+@dataclasses.dataclass
+class SEMResult:
+    accepted: bool
+    q: np.ndarray
+    theta: np.ndarray
+    U: np.ndarray
+    WFT: np.ndarray
+    UR: np.ndarray
+    lamR: np.ndarray
+    DKT: np.ndarray
+    DK: np.ndarray
+    DJ: np.ndarray
+    DS: np.ndarray
+    x_final: np.ndarray
+
+
+def sem_step(g: mac.Grid, r_ref, offsets, q, theta, FT, kT: float, dt: float, seed: int, step: int,
+             delta: float = 1e-5, slip: Optional[np.ndarray] = None, min_body_dist: float = 0.0,
+             tol: float = 1e-12, noise: bool = True) -> SEMResult:
+    q = np.asarray(q, dtype=np.float64).reshape(-1, 3)
+    theta = np.asarray(theta, dtype=np.float64).reshape(-1, 4)
+    nb = q.shape[0]
+    FT = np.asarray(FT, dtype=np.float64).reshape(nb, 6)
+    Lp = B.body_length(r_ref, offsets)
+
+    # 1. random forces and torques
+    Wf, Wt = rng.body_normals(seed, step, nb)
+    WFT = np.concatenate([kT * Wf / Lp[:, None], kT * Wt], axis=1)
+
+    # 2. RFD solve at Q^n (homogeneous data)
+    s0 = Saddle(g, q, theta, r_ref, offsets)
+    xR = s0.solve(s0.rhs(FT=WFT, include_bc=False), tol=tol)
+    vR, _, lamR, UR = s0.split(xR)
+
+    # 3. displaced configurations
+    qp = q + 0.5 * delta * Lp[:, None] * Wf
+    qm = q - 0.5 * delta * Lp[:, None] * Wf
+    thp = B.rotate(theta, 0.5 * delta * Wt)
+    thm = B.rotate(theta, -0.5 * delta * Wt)
+    rp = B.marker_positions(qp, thp, r_ref, offsets)
+    rm = B.marker_positions(qm, thm, r_ref, offsets)
+
+    # 4. unconstrained Stokes solve with the spread difference
+    Jp = ib.interpolation(g, rp)
+    Jm = ib.interpolation(g, rm)
+    fsharp = ((Jp.T @ lamR.ravel()) - (Jm.T @ lamR.ravel())) / (g.dV * delta)
+    sf = Saddle(g, q, theta, r_ref, offsets, fluid_only=True)
+    xs = sf.solve(sf.rhs(fluid=fsharp, include_bc=False), tol=tol)
+    vsharp = xs[sf.sl_v]
+
+    # 5. random finite differences
+    DKT = (B.apply_KT(thp, r_ref, offsets, lamR) - B.apply_KT(thm, r_ref, offsets, lamR)) / delta
+    DK = (B.apply_K(thp, r_ref, offsets, UR) - B.apply_K(thm, r_ref, offsets, UR)) / delta
+    DJ = ((Jp @ vR) - (Jm @ vR)).reshape(-1, 3) / delta
+    DS = (s0.J @ vsharp).reshape(-1, 3)
+
+    # 6. velocities with noise and drift
+    fluid = None
+    if noise and kT > 0.0:
+        W = rng.fluid_normals(seed, step, g.nW)
+        fluid = mac.noise_stress_divergence(g, W, kT, dt)
+    slip2 = DK - DJ - DS
+    if slip is not None:
+        slip2 = slip2 + np.asarray(slip).reshape(-1, 3)
+    x = s0.solve(s0.rhs(FT=FT - DKT, slip=slip2, fluid=fluid, include_bc=True), tol=tol)
+    U = s0.split(x)[3].copy()
+
+    # 7. update and rejection test
+    qn = q + dt * U[:, :3]
+    thn = B.rotate(theta, dt * U[:, 3:])
+    rn = B.marker_positions(qn, thn, r_ref, offsets)
+    ok = B.inside_open_domain(g, rn)
+    if ok and min_body_dist > 0.0 and nb > 1:
+        d = np.linalg.norm(qn[:, None, :] - qn[None, :, :], axis=2) + np.eye(nb) * 1e300
+        ok = bool(d.min() >= min_body_dist)
+    if not ok:
+        qn, thn = q.copy(), theta.copy()
+    return SEMResult(ok, qn, thn, U, WFT, UR.copy(), lamR.copy(), DKT, DK, DJ, DS, x)
+
+
+def drift_pointwise(g: mac.Grid, r_ref, offsets, q, theta, kT: float, seed: int, step: int,
+                    delta: float = 1e-5, tol: float = 1e-12):
+    """Brute-force RFD on N itself for the same random draw:
+    (1/delta)[N(Q+) - N(Q-)] W^FT, by two constrained solves at Q+ and Q-."""
+    q = np.asarray(q, dtype=np.float64).reshape(-1, 3)
+    theta = np.asarray(theta, dtype=np.float64).reshape(-1, 4)
+    nb = q.shape[0]
+    Lp = B.body_length(r_ref, offsets)
+    Wf, Wt = rng.body_normals(seed, step, nb)
+    WFT = np.concatenate([kT * Wf / Lp[:, None], kT * Wt], axis=1)
+    out = []
+    for sgn in (1.0, -1.0):
+        qs = q + sgn * 0.5 * delta * Lp[:, None] * Wf
+        ths = B.rotate(theta, sgn * 0.5 * delta * Wt)
+        s = Saddle(g, qs, ths, r_ref, offsets)
+        x = s.solve(s.rhs(FT=WFT, include_bc=False), tol=tol)
+        out.append(s.split(x)[3])
+    return (out[0] - out[1]) / delta

@@ -1,0 +1,187 @@
+"""Pins of the oracle's delta kernel, interpolation J and spreading S (paper Sec. III.B).
+
+* The 4-point kernel's defining moment conditions hold for every shift.
+* J reproduces linear fields exactly away from walls and, with the odd
+  reflection, linear fields that vanish on a wall (or equal the wall speed
+  on a moving wall) right up to the wall.
+* A brute-force coordinate-space J (ghost values from mirror coordinates,
+  plain loops) agrees with the assembled one on a tiny grid with corners.
+* Spreading conserves total force away from walls; J = dV S^T.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import ib, mac
+
+
+def test_kernel_moments():
+    rng = np.random.default_rng(0)
+    for r in rng.uniform(-3, 3, 200):
+        j = np.arange(math.floor(r) - 3, math.floor(r) + 4)
+        w = ib.phi4(r - j)
+        assert abs(w.sum() - 1.0) < 1e-14
+        assert abs(np.sum((r - j) * w)) < 1e-14
+        assert abs(np.sum(w * w) - 3.0 / 8.0) < 1e-14
+        assert abs(np.sum(w[j % 2 == 0]) - 0.5) < 1e-14
+    assert ib.phi4(np.array([2.0, -2.0, 2.5])).tolist() == [0.0, 0.0, 0.0]
+    assert abs(ib.phi4(np.array([1.0]))[0] - 0.25) < 1e-15
+
+
+def test_kernel_derivative():
+    x = np.linspace(-2.2, 2.2, 301)
+    eps = 1e-6
+    fd = (ib.phi4(x + eps) - ib.phi4(x - eps)) / (2 * eps)
+    assert np.abs(fd - ib.dphi4(x)).max() < 1e-6
+
+
+def _field_from_function(g, fn):
+    """Compact velocity whose component c at each unknown face equals fn(c, x, y, z)."""
+    v = np.zeros(g.nv)
+    for c in range(3):
+        k, j, i = np.meshgrid(np.arange(g.n[2]), np.arange(g.n[1]), np.arange(g.n[0]), indexing="ij")
+        pos = [i.ravel().astype(float), j.ravel().astype(float), k.ravel().astype(float)]
+        for a in range(3):
+            pos[a] = (pos[a] + (0.0 if a == c else 0.5)) * g.h
+        val = fn(c, *pos)
+        idx = g.face_index[c].ravel()
+        m = idx >= 0
+        v[g.face_offset[c] + idx[m]] = val[m]
+    return v
+
+
+def test_interp_linear_field_interior():
+    g = mac.Grid((12, 10, 14), (1, 1, 0), h=0.8)
+    rng = np.random.default_rng(1)
+    r = np.column_stack([rng.uniform(2.5 * g.h, (g.n[a] - 2.5) * g.h, 30) for a in range(3)])
+    A = rng.standard_normal((3, 3))
+    b0 = rng.standard_normal(3)
+    # periodic z: use a field linear in x, y only
+    A[:, 2] = 0.0
+    v = _field_from_function(g, lambda c, x, y, z: b0[c] + A[c, 0] * x + A[c, 1] * y)
+    Jv = (ib.interpolation(g, r) @ v).reshape(-1, 3)
+    exact = b0[None, :] + r[:, :2] @ A[:, :2].T
+    assert np.abs(Jv - exact).max() < 1e-12
+
+
+@pytest.mark.parametrize("axis", [0, 1, 2])
+def test_interp_reflection_at_wall(axis):
+    """A field linear in the wall-normal coordinate that vanishes on the wall is its
+    own odd reflection, so J is exact even when the support crosses the wall."""
+    g = mac.Grid((10, 10, 10), (1, 1, 1), h=1.0)
+    rng = np.random.default_rng(2 + axis)
+    r = rng.uniform(4.0, 6.0, size=(25, 3))
+    r[:, axis] = rng.uniform(0.05, 1.9, 25)          # within the kernel width of the lower wall
+    slope = np.array([0.7, -1.3, 2.1])
+    v = _field_from_function(g, lambda c, x, y, z: slope[c] * (x, y, z)[axis])
+    Jv = (ib.interpolation(g, r) @ v).reshape(-1, 3)
+    exact = slope[None, :] * r[:, axis][:, None]
+    assert np.abs(Jv - exact).max() < 1e-12
+    # upper wall: field vanishing at x_axis = L
+    L = g.n[axis] * g.h
+    r[:, axis] = L - r[:, axis]
+    v = _field_from_function(g, lambda c, x, y, z: slope[c] * (L - (x, y, z)[axis]))
+    Jv = (ib.interpolation(g, r) @ v).reshape(-1, 3)
+    exact = slope[None, :] * (L - r[:, axis])[:, None]
+    assert np.abs(Jv - exact).max() < 1e-12
+
+
+def test_interp_moving_wall_affine_term():
+    """u_x = U_w + s*z near a bottom wall sliding at U_w: J_0 v + J_bc is exact."""
+    Uw = 0.5
+    wv = np.zeros((3, 2, 3))
+    wv[2, 0, 0] = Uw
+    g = mac.Grid((8, 8, 8), (0, 1, 1), wall_vel=wv)
+    rng = np.random.default_rng(9)
+    r = rng.uniform(3.0, 5.0, size=(20, 3))
+    r[:, 2] = rng.uniform(0.1, 1.9, 20)
+    s = 0.37
+    v = _field_from_function(g, lambda c, x, y, z: (Uw + s * z) if c == 0 else 0.0 * z)
+    Jv = (ib.interpolation(g, r) @ v).reshape(-1, 3) + ib.interpolation_bc(g, r)
+    assert np.abs(Jv[:, 0] - (Uw + s * r[:, 2])).max() < 1e-12
+    assert np.abs(Jv[:, 1:]).max() < 1e-12
+
+
+def _brute_force_J(g, r, v):
+    """Plain loops: sum over every lattice point x_alpha within the kernel support
+    of delta_h(x_alpha - r) times the field value there, where a lattice point
+    outside a wall takes minus the value at its mirror coordinate (recursively
+    for corners) and a point on a wall face of the normal component is zero."""
+    vp = g.compact_to_padded(v).reshape(3, g.n[2], g.n[1], g.n[0])
+    L = [g.n[a] * g.h for a in range(3)]
+
+    def value(c, X):
+        X = list(X)
+        sign = 1.0
+        for a in range(3):
+            if g.bc[a] == mac.PERIODIC:
+                X[a] = X[a] % L[a]
+                continue
+            if X[a] < -1e-9:
+                X[a] = -X[a]; sign = -sign
+            elif X[a] > L[a] + 1e-9:
+                X[a] = 2 * L[a] - X[a]; sign = -sign
+            if a == c and (abs(X[a]) < 1e-9 or abs(X[a] - L[a]) < 1e-9):
+                return 0.0
+        idx = []
+        for a in range(3):
+            o = 0.0 if a == c else 0.5
+            ii = int(round(X[a] / g.h - o)) % g.n[a]
+            idx.append(ii)
+        return sign * vp[c, idx[2], idx[1], idx[0]]
+
+    out = np.zeros((r.shape[0], 3))
+    for m in range(r.shape[0]):
+        for c in range(3):
+            lo = [math.floor(r[m, a] / g.h - (0.0 if a == c else 0.5)) - 2 for a in range(3)]
+            acc = 0.0
+            for i in range(lo[0], lo[0] + 6):
+                for j in range(lo[1], lo[1] + 6):
+                    for k in range(lo[2], lo[2] + 6):
+                        X = [(i + (0.0 if c == 0 else 0.5)) * g.h,
+                             (j + (0.0 if c == 1 else 0.5)) * g.h,
+                             (k + (0.0 if c == 2 else 0.5)) * g.h]
+                        w = 1.0
+                        for a in range(3):
+                            w *= ib.phi4((r[m, a] - X[a]) / g.h)
+                        if w != 0.0:
+                            acc += w * value(c, X)
+            out[m, c] = acc
+    return out
+
+
+@pytest.mark.parametrize("bc", [(1, 1, 1), (0, 1, 1), (1, 0, 0)])
+def test_interp_brute_force(bc):
+    g = mac.Grid((6, 7, 6), bc, h=1.1)
+    rng = np.random.default_rng(11)
+    L = np.array(g.n) * g.h
+    # markers near corners and walls, and one in the middle
+    r = np.array([[0.3, 0.4, 0.2], [L[0] - 0.2, 0.7, L[2] - 0.5], [3.1, 3.9, 3.3],
+                  [0.9, L[1] - 0.3, 1.4], [L[0] - 1.6, L[1] - 1.7, 0.05]])
+    v = rng.standard_normal(g.nv)
+    Jv = (ib.interpolation(g, r) @ v).reshape(-1, 3)
+    assert np.abs(Jv - _brute_force_J(g, r, v)).max() < 1e-12
+
+
+def test_spread_conserves_force_and_adjointness():
+    g = mac.Grid((12, 12, 12), (1, 1, 1), h=0.5)
+    rng = np.random.default_rng(4)
+    r = rng.uniform(2.2 * g.h, 9.8 * g.h, size=(40, 3))
+    lam = rng.standard_normal((40, 3))
+    S = ib.spreading(g, r)
+    J = ib.interpolation(g, r)
+    f = g.compact_to_padded(S @ lam.ravel())
+    for c in range(3):
+        assert abs(g.dV * f[c].sum() - lam[:, c].sum()) < 1e-12
+    assert abs(J - g.dV * S.T).max() < 1e-15
+    v = rng.standard_normal(g.nv)
+    assert abs(np.dot(J @ v, lam.ravel()) - g.dV * np.dot(v, S @ lam.ravel())) < 1e-12
+
+
+def test_base_index_matches_floor():
+    g = mac.Grid((8, 8, 8), (1, 1, 1), h=0.5)
+    r = np.array([[0.5, 0.25, 1.0], [3.999, 0.01, 2.25]])
+    b0 = ib.base_index(g, r, 0)
+    # x: s = r/h (normal axis); y, z: s = r/h - 1/2
+    assert b0.tolist() == [[0, -1, 0], [6, -2, 3]]

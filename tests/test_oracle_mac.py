@@ -1,0 +1,169 @@
+"""Pins of the oracle's staggered-grid operators (paper Sec. III.A).
+
+Checked against what the mathematics fixes, not against the oracle itself:
+adjoint relations G = -D^T and Lm = DT GT (the ghost-cell Laplacian built
+independently), closed-form sine/cosine eigenpairs, and a manufactured
+divergence-free Stokes solution recovered by a solve.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import mac, saddle
+
+BCS = [(1, 1, 1), (0, 1, 1), (1, 0, 1), (0, 0, 1), (1, 0, 0)]
+
+
+@pytest.mark.parametrize("bc", BCS)
+def test_adjoint_relations(bc):
+    g = mac.Grid((5, 6, 4), bc, h=0.7)
+    D, G = mac.divergence(g), mac.gradient(g)
+    GT, DT = mac.vector_gradient(g), mac.tensor_divergence(g)
+    assert abs(G + D.T).max() == 0.0
+    assert abs(DT + GT.T).max() == 0.0
+    Lm = mac.vector_laplacian(g)
+    # ghost-cell stencil == DT GT (discrete fluctuation-dissipation balance)
+    assert abs(Lm - DT @ GT).max() < 1e-12
+    assert abs(Lm - Lm.T).max() < 1e-12
+    # D and G entries are exactly +-1/h
+    assert np.allclose(np.abs(D.data), 1.0 / g.h)
+
+
+def _mode_1d(N, kind, k, h):
+    if kind == "face_wall":      # faces 1..N-1 (compact), Dirichlet at 0, N
+        f = np.arange(1, N)
+        return np.sin(np.pi * k * f / N), -(4 / h**2) * math.sin(math.pi * k / (2 * N)) ** 2
+    if kind == "cell_wall":      # cells, odd ghosts
+        j = np.arange(N)
+        return np.sin(np.pi * k * (j + 0.5) / N), -(4 / h**2) * math.sin(math.pi * k / (2 * N)) ** 2
+    if kind == "cell_neumann":
+        j = np.arange(N)
+        return np.cos(np.pi * k * (j + 0.5) / N), -(4 / h**2) * math.sin(math.pi * k / (2 * N)) ** 2
+    j = np.arange(N)             # periodic
+    return np.cos(2 * np.pi * k * j / N), -(4 / h**2) * math.sin(math.pi * k / N) ** 2
+
+
+@pytest.mark.parametrize("bc", BCS)
+def test_vector_laplacian_eigenpairs(bc):
+    g = mac.Grid((6, 5, 7), bc, h=1.3)
+    Lm = mac.vector_laplacian(g)
+    rng = np.random.default_rng(3)
+    for c in range(3):
+        for _ in range(3):
+            vec = np.ones(1)
+            lam = 0.0
+            for a in (2, 1, 0):      # build [k][j][i] -> x fastest via kron
+                N = g.n[a]
+                if g.bc[a] == mac.PERIODIC:
+                    kind, k = "periodic", int(rng.integers(0, N))
+                elif a == c:
+                    kind, k = "face_wall", int(rng.integers(1, N))
+                else:
+                    kind, k = "cell_wall", int(rng.integers(1, N + 1))
+                m, l = _mode_1d(N, kind, k, g.h)
+                vec = np.kron(vec, m)
+                lam += l
+            full = np.zeros(g.nv)
+            full[g.face_offset[c]:g.face_offset[c] + g.nface[c]] = vec
+            out = Lm @ full
+            assert np.abs(out - lam * full).max() < 1e-12 * max(1.0, abs(lam))
+
+
+@pytest.mark.parametrize("bc", BCS)
+def test_scalar_laplacian_eigenpairs(bc):
+    g = mac.Grid((6, 5, 4), bc)
+    L = mac.scalar_laplacian(g)
+    rng = np.random.default_rng(5)
+    for _ in range(4):
+        vec = np.ones(1)
+        lam = 0.0
+        for a in (2, 1, 0):
+            N = g.n[a]
+            kind = "periodic" if g.bc[a] == mac.PERIODIC else "cell_neumann"
+            m, l = _mode_1d(N, kind, int(rng.integers(0, N)), g.h)
+            vec = np.kron(vec, m)
+            lam += l
+        assert np.abs(L @ vec - lam * vec).max() < 1e-12
+
+
+def _curl_field(g, rng):
+    """Divergence-free padded velocity: discrete curl of a random edge potential
+    that vanishes on wall node planes (so the normal velocity on walls is 0)."""
+    nx, ny, nz = g.n
+    nodes = [g.nodes(a) for a in range(3)]
+
+    def pot(dims, wall_axes):
+        p = rng.standard_normal(dims[::-1])
+        for a in wall_axes:
+            if g.bc[a] == mac.WALL:
+                sl = [slice(None)] * 3
+                sl[2 - a] = 0
+                p[tuple(sl)] = 0.0
+                sl[2 - a] = dims[a] - 1
+                p[tuple(sl)] = 0.0
+        return p
+
+    # psi_z on z-edges (node x, node y, cell z), psi_y on y-edges, psi_x on x-edges
+    pz = pot((nodes[0], nodes[1], nz), (0, 1))
+    py = pot((nodes[0], ny, nodes[2]), (0, 2))
+    px = pot((nx, nodes[1], nodes[2]), (1, 2))
+
+    def dnode(p, axis, N):
+        """difference p[n+1] - p[n] along an edge-node axis -> N values (wraps if periodic)."""
+        ax = 2 - axis
+        if p.shape[ax] == N:       # periodic: N nodes
+            return np.roll(p, -1, axis=ax) - p
+        return np.diff(p, axis=ax)
+
+    ux = np.zeros((nz, ny, nx)); uy = np.zeros((nz, ny, nx)); uz = np.zeros((nz, ny, nx))
+    # u_x = d psi_z / dy - d psi_y / dz  at (face x, cell y, cell z)
+    ux += dnode(pz, 1, ny)[:, :, :nx] - dnode(py, 2, nz)[:, :, :nx]
+    uy += dnode(px, 2, nz)[:, :ny, :] - dnode(pz, 0, nx)[:, :ny, :]
+    uz += dnode(py, 0, nx)[:nz, :, :] - dnode(px, 1, ny)[:nz, :, :]
+    return np.stack([ux, uy, uz]).reshape(3, -1) / g.h
+
+
+@pytest.mark.parametrize("bc", [(1, 1, 1), (0, 1, 1), (0, 0, 1)])
+def test_manufactured_stokes(bc):
+    g = mac.Grid((8, 6, 10), bc, h=1.0, eta=1.7)
+    rng = np.random.default_rng(7)
+    vpad = _curl_field(g, rng)
+    v = g.padded_to_compact(vpad)
+    # the potential vanishes on wall planes, so the dropped wall slots carry nothing
+    assert np.allclose(g.compact_to_padded(v), vpad)
+    D = mac.divergence(g)
+    assert np.abs(D @ v).max() < 1e-12
+    pi = rng.standard_normal(g.ncell)
+    pi -= pi.mean()
+    f = -g.eta * (mac.vector_laplacian(g) @ v) + mac.gradient(g) @ pi
+    s = saddle.Saddle(g, np.zeros((0, 3)), np.zeros((0, 4)), np.zeros((0, 3)), np.zeros(1, dtype=int),
+                      fluid_only=True)
+    b = s.rhs(fluid=f, include_bc=False)
+    x = s.solve_direct(b)
+    assert np.abs(x[s.sl_v] - v).max() < 1e-9
+    p = x[s.sl_p] - x[s.sl_p].mean()
+    assert np.abs(p - pi).max() < 1e-9
+    xf, info = s.solve_fgmres(b, tol=1e-12)
+    assert info["rel_residual"] < 1e-12
+    assert np.abs(xf[s.sl_v] - v).max() < 1e-9
+
+
+def test_noise_index_space_counts():
+    g = mac.Grid((4, 5, 6), (0, 1, 1))
+    dims = [g.family_dims(f) for f in range(9)]
+    assert dims[0] == (4, 5, 6)                 # xx on cells
+    assert dims[3] == (4, 6, 6)                 # xy: nodes along y (wall: N+1)
+    assert dims[5] == (4, 5, 6)                 # yx: nodes along x (periodic: N)
+    assert g.nW == sum(int(np.prod(d)) for d in dims)
+
+
+def test_moving_wall_rhs():
+    wv = np.zeros((3, 2, 3))
+    wv[2, 0, 0] = 0.5                           # bottom z wall slides along +x
+    g = mac.Grid((4, 4, 5), (0, 1, 1), eta=2.0, wall_vel=wv)
+    r = mac.moving_wall_rhs(g)
+    ux = g.compact_to_padded(r)[0].reshape(5, 4, 4)
+    assert np.allclose(ux[0], 2 * 2.0 * 0.5)
+    assert np.allclose(ux[1:], 0.0)
+    assert np.allclose(g.compact_to_padded(r)[1:], 0.0)
