@@ -1,0 +1,225 @@
+/*
+ * rbfib.h -- C ABI of the MI355X hot path of the Rigid-Body Fluctuating
+ * Immersed Boundary (RB-FIB) method (Sprinkle, Donev, Bhalla & Patankar,
+ * "Brownian dynamics of fully confined suspensions of rigid particles without
+ * Green's functions").
+ *
+ * What the library computes
+ * -------------------------
+ * For rigid bodies p with tracking points q_p and unit-quaternion orientations
+ * theta_p, made of markers r_i = q_p + R(theta_p) r_i^ref, suspended in a
+ * Stokes fluid on a staggered grid of Nx x Ny x Nz cells with a periodic or
+ * no-slip (possibly sliding) wall boundary per axis, the library applies and
+ * solves the constrained saddle-point system of eqs. (LangevinD1-D4):
+ *
+ *     [ -eta Lm   G   -S   0 ] [ v      ]   [ f_v                          ]
+ *     [   -D      0    0   0 ] [ pi     ] = [ 0                            ]
+ *     [   -J      0    0   K ] [ lambda ]   [ -slip + J_bc                 ]
+ *     [    0      0   K^T  0 ] [ U      ]   [ F                            ]
+ *
+ * (Sec. III: MAC operators Lm = DT GT, G = -D^*; interpolation J and spreading
+ * S through the Peskin 4-point kernel, J = dV S^*; (K U)_i = u_p + omega_p x
+ * (r_i - q_p), (K^T lambda)_p = [sum lambda_i; sum (r_i - q_p) x lambda_i]),
+ * and advances the bodies by the Split-Euler-Maruyama scheme of Algorithm 1
+ * with the random-finite-difference drift (Sec. IV).  Walls enter S and J by
+ * odd reflection of the kernel support; a wall sliding with tangential velocity
+ * U_w adds 2 eta U_w / h^2 to the momentum rows next to it and J_bc to the
+ * constraint rows.
+ *
+ * Conventions
+ * -----------
+ *  * All array arguments are DEVICE pointers owned by the caller, FP64,
+ *    contiguous, row-major, unless a comment says "host".  The library never
+ *    frees caller memory.  A context owns all workspace it allocates.
+ *  * Work is enqueued on the HIP stream given at creation.  Entry points that
+ *    return convergence or rejection information synchronise that stream
+ *    before returning; rbfib_apply_saddle, rbfib_markers and
+ *    rbfib_fluctuating_stress are asynchronous.
+ *  * Quaternions are scalar first (w, x, y, z).  Body arrays are [nb, 3]
+ *    (q), [nb, 4] (theta), [nb, 6] (forces/torques or velocities [u, omega]).
+ *    Marker arrays are [nm, 3].
+ *  * State vector (x, y of rbfib_apply_saddle; optional full solution of a
+ *    solve), per replica and concatenated over replicas in order:
+ *        [ u_x | u_y | u_z | pi | lambda (nm x 3) | U (nb x 6) ]
+ *    where each of u_x, u_y, u_z, pi has Nx*Ny*Nz entries, x fastest.  Entry
+ *    (i, j, k) of u_c is the c-face at coordinate i*h along c (cell centred
+ *    along the other axes).  Along a wall axis c the slot i_c = 0 is the wall
+ *    face: it is not an unknown, is ignored on input and is written as 0.
+ *    rbfib_layout returns the offsets.
+ *  * Batched contexts hold independent replicas (each its own grid and
+ *    bodies); bodies and markers of all replicas are concatenated in replica
+ *    order and rbfib_info arrays have one entry per replica.
+ *
+ * Errors
+ * ------
+ * Every int-returning call returns RBFIB_OK (0) or a negative code:
+ *   RBFIB_EINVAL   bad argument (sizes, no wall axis, periodic axis not a
+ *                  multiple of 4, too few cells, NULL pointer, bad options);
+ *   RBFIB_EREJECT  unphysical configuration: a marker outside the open domain
+ *                  along a wall axis, or body centres closer than
+ *                  opts.min_body_dist (the paper rejects and repeats such
+ *                  steps); state left unchanged;
+ *   RBFIB_ENOCONV  max_iter reached before tol; outputs hold the last iterate,
+ *                  info holds the residual reached;
+ *   RBFIB_ENUMERIC a NaN or Inf appeared in the Krylov recurrences;
+ *   RBFIB_EDEVICE  a HIP runtime call failed;
+ *   RBFIB_ENOMEM   device allocation failed.
+ * For batched calls the return value is the first non-OK replica status in
+ * replica order (EREJECT and ENOCONV) or a global failure; per-replica status
+ * is in info[r].status.
+ */
+#ifndef RBFIB_H
+#define RBFIB_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define RBFIB_OK        0
+#define RBFIB_EINVAL   -1
+#define RBFIB_EREJECT  -2
+#define RBFIB_ENOCONV  -3
+#define RBFIB_ENUMERIC -4
+#define RBFIB_EDEVICE  -5
+#define RBFIB_ENOMEM   -6
+
+#define RBFIB_PERIODIC 0
+#define RBFIB_WALL     1
+
+typedef struct rbfib_ctx rbfib_ctx;
+
+/* Grid and boundary conditions (Sec. III.A; Sec. VI for the sliding wall). */
+typedef struct {
+    int n[3];                  /* cells per axis, x y z                              */
+    int bc[3];                 /* RBFIB_PERIODIC or RBFIB_WALL per axis (>= 1 wall)   */
+    double h;                  /* cell width; dV = h^3                               */
+    double eta;                /* viscosity                                          */
+    double wall_vel[3][2][3];  /* [axis][0 low, 1 high][component]; tangential only  */
+} rbfib_grid;
+
+/* Rigid bodies as marker agglomerates (Sec. III.B).  Host memory, copied. */
+typedef struct {
+    int nb;                    /* number of bodies                                   */
+    int nm;                    /* number of markers (sum over bodies)                */
+    const int *marker_offset;  /* host [nb + 1], CSR body -> markers, offset[0] = 0  */
+    const double *r_ref;       /* host [nm, 3], body-frame marker offsets            */
+} rbfib_bodies;
+
+/* Solver options; rbfib_default_opts fills every field. */
+typedef struct {
+    double tol;                /* relative residual ||b - A x|| / ||b||  (1e-6)      */
+    int restart;               /* FGMRES restart length (30)                         */
+    int max_iter;              /* total iteration cap (600)                          */
+    int precond_fp32;          /* 1: multigrid preconditioner in FP32 (0)            */
+    int mg_sweeps;             /* damped-Jacobi sweeps before and after (2)          */
+    double mg_omega;           /* Jacobi damping (0.8)                               */
+    double blob_radius;        /* blob radius of the body block, units of h (1.25)   */
+    double rfd_delta;          /* random-finite-difference delta (1e-5)              */
+    double min_body_dist;      /* rejection distance between body centres (0 = off)  */
+    int check_every;           /* iterations between host convergence checks (4)    */
+} rbfib_opts;
+
+typedef struct {
+    int iters;                 /* FGMRES iterations (constrained solves summed)      */
+    double rel_residual;       /* true relative residual of the last solve           */
+    int status;                /* RBFIB_OK, RBFIB_ENOCONV, RBFIB_EREJECT, ...        */
+} rbfib_info;
+
+void rbfib_default_opts(rbfib_opts *opts);
+const char *rbfib_strerror(int code);
+/* Text of the last failure seen on this thread (HIP error string, allocation size). */
+const char *rbfib_last_error(void);
+
+/* One replica.  hip_stream: a hipStream_t (NULL = default stream). */
+int rbfib_create(const rbfib_grid *grid, const rbfib_bodies *bodies, const rbfib_opts *opts,
+                 void *hip_stream, rbfib_ctx **out);
+
+/* nrep independent replicas solved together (one launch per kernel step). */
+int rbfib_create_batch(int nrep, const rbfib_grid *grids, const rbfib_bodies *bodies,
+                       const rbfib_opts *opts, void *hip_stream, rbfib_ctx **out);
+
+void rbfib_destroy(rbfib_ctx *ctx);
+
+/* Update the solver options of an existing context (same fields as creation). */
+int rbfib_set_opts(rbfib_ctx *ctx, const rbfib_opts *opts);
+
+/* Length of one packed state vector (all replicas). */
+long long rbfib_state_size(const rbfib_ctx *ctx);
+
+/* Host out[nrep * 4]: offsets of u_x, pi, lambda and U of each replica. */
+int rbfib_layout(const rbfib_ctx *ctx, long long *out);
+
+/* Marker geometry at (q, theta) (Sec. II, III.B): r [nm, 3] = q_p + R(theta_p) r_ref,
+ * tile [nm] = linear index (x fastest, per replica) of the 4x4x4-cell tile holding
+ * floor(r / h) (wrapped on periodic axes), perm [nm] = markers stably sorted by tile
+ * (replica-local indices).  Any output may be NULL. */
+int rbfib_markers(rbfib_ctx *ctx, const double *q, const double *theta,
+                  double *r, int *tile, int *perm);
+
+/* y = A x for the homogeneous operator above at configuration (q, theta)
+ * (Algorithm 1 block matrix with the signs of eqs. D1-D4).  x and y are state
+ * vectors and must not alias.  Markers must lie inside the domain along wall
+ * axes (indices are clamped, never out of bounds, but the result is then
+ * meaningless). */
+int rbfib_apply_saddle(rbfib_ctx *ctx, const double *q, const double *theta,
+                       const double *x, double *y);
+
+/* Preconditioner z = P^-1 r (for inspection; the solver applies it internally). */
+int rbfib_precondition(rbfib_ctx *ctx, const double *q, const double *theta,
+                       const double *r, double *z);
+
+/* Deterministic mobility solve (eqs. D1-D4 with no noise): given forces and
+ * torques FT [nb, 6] and optional marker slip [nm, 3] (NULL = 0), returns the
+ * rigid velocities U [nb, 6] = N F - N K^T M^-1 slip (+ the response to sliding
+ * walls).  x_out (optional, state vector) receives the full solution (v, pi,
+ * lambda, U).  include_bc = 0 drops the wall-velocity terms.  info: host,
+ * one entry per replica (may be NULL). */
+int rbfib_solve_mobility(rbfib_ctx *ctx, const double *q, const double *theta,
+                         const double *FT, const double *slip, int include_bc,
+                         double *U, double *x_out, rbfib_info *info);
+
+/* Fluctuating-stress forcing sqrt(2 kT eta / (dV dt)) DT W (eq. DFHD) written
+ * into the velocity slots of the state vector f (other slots zeroed), with W
+ * i.i.d. N(0,1) from Philox4x32-10 (seed, stream 1, step) over the nine
+ * stress families xx, yy, zz, xy, xz, yx, yz, zx, zy: family (c, c) on cells,
+ * family (c, b) on edges with (N_b + 1 if wall else N_b) nodes along b, each
+ * x fastest; per replica, replica r uses step counter step and seed
+ * seed + r. */
+int rbfib_fluctuating_stress(rbfib_ctx *ctx, double kT, double dt, uint64_t seed,
+                             uint64_t step, double *f);
+
+/* One Split-Euler-Maruyama step (Algorithm 1): random forces and torques,
+ * RFD solve, unconstrained Stokes solve, random finite differences of K^T, K,
+ * J and S, the noisy constrained solve with force FT - D^KT and slip
+ * slip + D^K - D^J - D^S, then q += dt u, theta = Rotate(theta, dt omega).
+ * q and theta are updated in place only when the step is accepted.  FT are
+ * the deterministic forces at the current configuration (caller evaluated).
+ * U [nb, 6] receives U^n.  Replica r draws from seed + r. */
+int rbfib_sem_step(rbfib_ctx *ctx, double *q, double *theta, const double *FT,
+                   const double *slip, double kT, double dt, uint64_t seed, uint64_t step,
+                   double *U, rbfib_info *info);
+
+/* Vector-Jacobian product of U = N(q, theta) F (no slip, no wall motion):
+ * given Ubar = dL/dU [nb, 6], returns dFT = dL/dF [nb, 6], dq = dL/dq [nb, 3]
+ * and dphi [nb, 3], the gradient with respect to a lab-frame rotation vector
+ * applied to each body.  Re-solves the forward problem (the Krylov basis is
+ * recomputed, not stored) and solves the adjoint system, which has the same
+ * operator. */
+int rbfib_mobility_vjp(rbfib_ctx *ctx, const double *q, const double *theta, const double *FT,
+                       const double *Ubar, double *dFT, double *dq, double *dphi,
+                       rbfib_info *info);
+
+/* Average duration (ms) of the dominant kernel class over the last solve,
+ * measured with HIP events on the context stream; and its algorithmic bytes
+ * per launch.  which: 0 = fused MAC saddle apply, 1 = multigrid smoother sweep. */
+int rbfib_kernel_stats(rbfib_ctx *ctx, int which, double *avg_ms, double *bytes_per_launch,
+                       long long *launches);
+int rbfib_enable_timing(rbfib_ctx *ctx, int on);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RBFIB_H */

@@ -1,0 +1,283 @@
+"""Python binding of librbfib.so, the MI355X hot path of the RB-FIB method.
+
+Argument marshalling only: every step of the computation runs in the HIP
+library.  Functions carry the C names (``rbfib_create``, ``rbfib_apply_saddle``,
+``rbfib_solve_mobility``, ``rbfib_sem_step``, ...) and take torch tensors that
+live on the GPU (FP64, contiguous); PyTorch provides device memory and the
+stream only.  Importing this module raises if the library has not been built
+(``python paper_1901_06427_amd/build.py``): there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIBPATH = os.path.join(HERE, "librbfib.so")
+
+RBFIB_OK = 0
+RBFIB_EINVAL = -1
+RBFIB_EREJECT = -2
+RBFIB_ENOCONV = -3
+RBFIB_ENUMERIC = -4
+RBFIB_EDEVICE = -5
+RBFIB_ENOMEM = -6
+PERIODIC = 0
+WALL = 1
+
+EXPORTS = [
+    "rbfib_default_opts", "rbfib_strerror", "rbfib_last_error", "rbfib_create", "rbfib_create_batch",
+    "rbfib_destroy", "rbfib_set_opts", "rbfib_state_size", "rbfib_layout", "rbfib_markers",
+    "rbfib_apply_saddle", "rbfib_precondition", "rbfib_solve_mobility", "rbfib_fluctuating_stress",
+    "rbfib_sem_step", "rbfib_mobility_vjp", "rbfib_kernel_stats", "rbfib_enable_timing",
+]
+
+
+class rbfib_grid(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int * 3), ("bc", ctypes.c_int * 3), ("h", ctypes.c_double),
+                ("eta", ctypes.c_double), ("wall_vel", ctypes.c_double * 18)]
+
+
+class rbfib_bodies(ctypes.Structure):
+    _fields_ = [("nb", ctypes.c_int), ("nm", ctypes.c_int), ("marker_offset", ctypes.POINTER(ctypes.c_int)),
+                ("r_ref", ctypes.POINTER(ctypes.c_double))]
+
+
+class rbfib_opts(ctypes.Structure):
+    _fields_ = [("tol", ctypes.c_double), ("restart", ctypes.c_int), ("max_iter", ctypes.c_int),
+                ("precond_fp32", ctypes.c_int), ("mg_sweeps", ctypes.c_int), ("mg_omega", ctypes.c_double),
+                ("blob_radius", ctypes.c_double), ("rfd_delta", ctypes.c_double),
+                ("min_body_dist", ctypes.c_double), ("check_every", ctypes.c_int)]
+
+
+class rbfib_info(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int), ("rel_residual", ctypes.c_double), ("status", ctypes.c_int)]
+
+
+def _load():
+    if not os.path.exists(LIBPATH):
+        raise ImportError("librbfib.so is not built; run `python paper_1901_06427_amd/build.py` "
+                          "(the RB-FIB hot path has no CPU fallback)")
+    # PyTorch ships its own HIP runtime with the same soname; loading torch first
+    # makes the library bind to that one runtime instead of a second copy.
+    import torch  # noqa: F401
+    lib = ctypes.CDLL(LIBPATH)
+    P = ctypes.c_void_p
+    I = ctypes.c_int
+    D = ctypes.c_double
+    U64 = ctypes.c_uint64
+    sig = {
+        "rbfib_default_opts": (None, [ctypes.POINTER(rbfib_opts)]),
+        "rbfib_strerror": (ctypes.c_char_p, [I]),
+        "rbfib_last_error": (ctypes.c_char_p, []),
+        "rbfib_create": (I, [ctypes.POINTER(rbfib_grid), ctypes.POINTER(rbfib_bodies), ctypes.POINTER(rbfib_opts),
+                             P, ctypes.POINTER(P)]),
+        "rbfib_create_batch": (I, [I, ctypes.POINTER(rbfib_grid), ctypes.POINTER(rbfib_bodies),
+                                   ctypes.POINTER(rbfib_opts), P, ctypes.POINTER(P)]),
+        "rbfib_destroy": (None, [P]),
+        "rbfib_set_opts": (I, [P, ctypes.POINTER(rbfib_opts)]),
+        "rbfib_state_size": (ctypes.c_longlong, [P]),
+        "rbfib_layout": (I, [P, ctypes.POINTER(ctypes.c_longlong)]),
+        "rbfib_markers": (I, [P, P, P, P, P, P]),
+        "rbfib_apply_saddle": (I, [P, P, P, P, P]),
+        "rbfib_precondition": (I, [P, P, P, P, P]),
+        "rbfib_solve_mobility": (I, [P, P, P, P, P, I, P, P, ctypes.POINTER(rbfib_info)]),
+        "rbfib_fluctuating_stress": (I, [P, D, D, U64, U64, P]),
+        "rbfib_sem_step": (I, [P, P, P, P, P, D, D, U64, U64, P, ctypes.POINTER(rbfib_info)]),
+        "rbfib_mobility_vjp": (I, [P, P, P, P, P, P, P, P, ctypes.POINTER(rbfib_info)]),
+        "rbfib_kernel_stats": (I, [P, I, ctypes.POINTER(D), ctypes.POINTER(D), ctypes.POINTER(ctypes.c_longlong)]),
+        "rbfib_enable_timing": (I, [P, I]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    return lib
+
+
+_lib = _load()
+
+
+class RBFIBError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        self.code = code
+        msg = _lib.rbfib_strerror(code).decode()
+        detail = _lib.rbfib_last_error().decode()
+        super().__init__("%s failed: %s (%d)%s" % (where, msg, code, (" -- " + detail) if detail else ""))
+
+
+def _check(code: int, where: str, allow=()):
+    if code != RBFIB_OK and code not in allow:
+        raise RBFIBError(code, where)
+    return code
+
+
+def _ptr(t) -> Optional[int]:
+    if t is None:
+        return None
+    import torch
+    if not (t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
+        raise ValueError("expected a contiguous float64 CUDA tensor")
+    return t.data_ptr()
+
+
+def _iptr(t) -> Optional[int]:
+    if t is None:
+        return None
+    import torch
+    if not (t.is_cuda and t.dtype == torch.int32 and t.is_contiguous()):
+        raise ValueError("expected a contiguous int32 CUDA tensor")
+    return t.data_ptr()
+
+
+def rbfib_default_opts(**kw) -> rbfib_opts:
+    o = rbfib_opts()
+    _lib.rbfib_default_opts(ctypes.byref(o))
+    for k, v in kw.items():
+        setattr(o, k, v)
+    return o
+
+
+def make_grid(n, bc, h=1.0, eta=1.0, wall_vel=None) -> rbfib_grid:
+    g = rbfib_grid()
+    for a in range(3):
+        g.n[a] = int(n[a])
+        g.bc[a] = int(bc[a])
+    g.h = float(h)
+    g.eta = float(eta)
+    wv = np.zeros(18) if wall_vel is None else np.asarray(wall_vel, dtype=np.float64).ravel()
+    for i in range(18):
+        g.wall_vel[i] = float(wv[i])
+    return g
+
+
+class Context:
+    """Owns an rbfib_ctx (one replica or a batch) and the host copies it was built from."""
+
+    def __init__(self, grids: Sequence[rbfib_grid], r_refs: Sequence[np.ndarray], offsets: Sequence[np.ndarray],
+                 opts: Optional[rbfib_opts] = None, stream=None):
+        import torch
+        self.nrep = len(grids)
+        self._keep = []
+        garr = (rbfib_grid * self.nrep)(*grids)
+        barr = (rbfib_bodies * self.nrep)()
+        self.nb = 0
+        self.nm = 0
+        for r in range(self.nrep):
+            rr = np.ascontiguousarray(r_refs[r], dtype=np.float64).reshape(-1, 3)
+            off = np.ascontiguousarray(offsets[r], dtype=np.int32)
+            self._keep += [rr, off]
+            barr[r].nb = int(len(off) - 1)
+            barr[r].nm = int(rr.shape[0])
+            barr[r].marker_offset = off.ctypes.data_as(ctypes.POINTER(ctypes.c_int))
+            barr[r].r_ref = rr.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+            self.nb += barr[r].nb
+            self.nm += barr[r].nm
+        self.opts = opts if opts is not None else rbfib_default_opts()
+        if stream is None:
+            stream = torch.cuda.current_stream().cuda_stream
+        self.stream = stream
+        h = ctypes.c_void_p()
+        _check(_lib.rbfib_create_batch(self.nrep, garr, barr, ctypes.byref(self.opts), ctypes.c_void_p(stream),
+                                       ctypes.byref(h)), "rbfib_create_batch")
+        self.h = h
+        self.L = int(_lib.rbfib_state_size(h))
+        lay = (ctypes.c_longlong * (4 * self.nrep))()
+        _check(_lib.rbfib_layout(h, lay), "rbfib_layout")
+        self.layout = np.array(list(lay), dtype=np.int64).reshape(self.nrep, 4)
+
+    def close(self):
+        if getattr(self, "h", None):
+            _lib.rbfib_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def rbfib_create(grid: rbfib_grid, r_ref, offsets, opts=None, stream=None) -> Context:
+    return Context([grid], [r_ref], [offsets], opts, stream)
+
+
+def rbfib_create_batch(grids, r_refs, offsets, opts=None, stream=None) -> Context:
+    return Context(grids, r_refs, offsets, opts, stream)
+
+
+def rbfib_destroy(ctx: Context):
+    ctx.close()
+
+
+def rbfib_set_opts(ctx: Context, opts: rbfib_opts):
+    _check(_lib.rbfib_set_opts(ctx.h, ctypes.byref(opts)), "rbfib_set_opts")
+    ctx.opts = opts
+
+
+def rbfib_markers(ctx: Context, q, theta, r=None, tile=None, perm=None):
+    _check(_lib.rbfib_markers(ctx.h, _ptr(q), _ptr(theta), _ptr(r), _iptr(tile), _iptr(perm)), "rbfib_markers")
+
+
+def rbfib_apply_saddle(ctx: Context, q, theta, x, y):
+    _check(_lib.rbfib_apply_saddle(ctx.h, _ptr(q), _ptr(theta), _ptr(x), _ptr(y)), "rbfib_apply_saddle")
+
+
+def rbfib_precondition(ctx: Context, q, theta, r, z):
+    _check(_lib.rbfib_precondition(ctx.h, _ptr(q), _ptr(theta), _ptr(r), _ptr(z)), "rbfib_precondition")
+
+
+def _infos(n):
+    return (rbfib_info * n)()
+
+
+def rbfib_solve_mobility(ctx: Context, q, theta, FT, U, slip=None, x_out=None, include_bc=True,
+                         allow=(RBFIB_ENOCONV,)) -> List[rbfib_info]:
+    info = _infos(ctx.nrep)
+    code = _lib.rbfib_solve_mobility(ctx.h, _ptr(q), _ptr(theta), _ptr(FT), _ptr(slip), int(include_bc), _ptr(U),
+                                     _ptr(x_out), info)
+    _check(code, "rbfib_solve_mobility", allow)
+    return list(info)
+
+
+def rbfib_fluctuating_stress(ctx: Context, kT: float, dt: float, seed: int, step: int, f):
+    _check(_lib.rbfib_fluctuating_stress(ctx.h, float(kT), float(dt), int(seed), int(step), _ptr(f)),
+           "rbfib_fluctuating_stress")
+
+
+def rbfib_sem_step(ctx: Context, q, theta, FT, kT: float, dt: float, seed: int, step: int, U, slip=None,
+                   allow=(RBFIB_EREJECT, RBFIB_ENOCONV)) -> List[rbfib_info]:
+    info = _infos(ctx.nrep)
+    code = _lib.rbfib_sem_step(ctx.h, _ptr(q), _ptr(theta), _ptr(FT), _ptr(slip), float(kT), float(dt), int(seed),
+                               int(step), _ptr(U), info)
+    _check(code, "rbfib_sem_step", allow)
+    return list(info)
+
+
+def rbfib_mobility_vjp(ctx: Context, q, theta, FT, Ubar, dFT, dq, dphi,
+                       allow=(RBFIB_ENOCONV,)) -> List[rbfib_info]:
+    info = _infos(ctx.nrep)
+    code = _lib.rbfib_mobility_vjp(ctx.h, _ptr(q), _ptr(theta), _ptr(FT), _ptr(Ubar), _ptr(dFT), _ptr(dq),
+                                   _ptr(dphi), info)
+    _check(code, "rbfib_mobility_vjp", allow)
+    return list(info)
+
+
+def rbfib_enable_timing(ctx: Context, on: bool = True):
+    _check(_lib.rbfib_enable_timing(ctx.h, int(on)), "rbfib_enable_timing")
+
+
+def rbfib_kernel_stats(ctx: Context, which: int):
+    a = ctypes.c_double()
+    b = ctypes.c_double()
+    n = ctypes.c_longlong()
+    _check(_lib.rbfib_kernel_stats(ctx.h, int(which), ctypes.byref(a), ctypes.byref(b), ctypes.byref(n)),
+           "rbfib_kernel_stats")
+    return a.value, b.value, n.value
+
+
+def library_path() -> str:
+    return LIBPATH

@@ -1,0 +1,297 @@
+// Internal declarations of the RB-FIB HIP library (gfx950).
+//
+// Layout of a packed state vector per replica r (offsets in RepDev):
+//   off + 0*N .. : u_x  (N = nx*ny*nz slots, x fastest; slot i_x = 0 is the wall
+//                        face when x is a wall axis and always holds 0)
+//   off + 1*N .. : u_y,  off + 2*N : u_z,  off + 3*N : pi (cell centred)
+//   off + 4*N .. : lambda [nm, 3],  then U [nb, 6]
+// Multigrid level arrays hold the same four fields (u_x, u_y, u_z, pi) per level
+// in FP32 or FP64, component c at  level_off + c * N_level.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <vector>
+#include <string>
+
+#include "../../include/rbfib.h"
+
+#define RB_MAXLEV 12
+#define RB_TILE 4
+#define RB_BLOCK 256
+#define RB_CHUNK 2048          // Krylov elements per block (RB_BLOCK * 8)
+
+namespace rb {
+
+// ---------------------------------------------------------------- descriptors
+struct RepDev {
+    int n[3];
+    int bc[3];
+    double h, inv_h, eta, dV;
+    long long off;      // state offset of u_x
+    long long N;        // cells
+    long long len;      // state length 4N + 3nm + 6nb
+    int nb, nm, b0, m0; // bodies/markers and their global first index
+    int tdim[3];        // tile grid dims
+    int tile0;          // first global tile index
+    int nlev;
+    int movwall;
+    double wv[3][2][3];
+};
+
+struct LevDev {
+    int n[3];
+    double inv_h2[3];   // 1/h_a^2 per axis at this level
+    long long off;      // offset of this level's four fields in the level pool
+    long long N;
+};
+
+struct BlockEnt {       // one block of work: replica and local start index
+    int rep;
+    int comp;           // component (grid kernels) or unused
+    long long start;
+};
+
+struct ShapeDev {       // per distinct body shape: body-block preconditioner data
+    int nm;
+    long long minv_off; // (3nm)^2 doubles, body frame
+    long long mk_off;   // (3nm) x 6 doubles: Minv K_ref
+    long long n_off;    // 6x6 doubles: (K^T Minv K)^-1
+    long long rref_off; // body-frame offsets (3nm doubles)
+};
+
+// ---------------------------------------------------------------- device helpers
+__device__ __forceinline__ double phi4(double r) {
+    double a = fabs(r);
+    if (a <= 1.0) return (3.0 - 2.0 * a + sqrt(1.0 + 4.0 * a - 4.0 * a * a)) * 0.125;
+    if (a < 2.0) return (5.0 - 2.0 * a - sqrt(-7.0 + 12.0 * a - 4.0 * a * a)) * 0.125;
+    return 0.0;
+}
+
+__device__ __forceinline__ double dphi4(double r) {
+    double a = fabs(r);
+    double s = r > 0.0 ? 1.0 : (r < 0.0 ? -1.0 : 0.0);
+    if (a <= 1.0) return s * (-2.0 + (4.0 - 8.0 * a) / (2.0 * sqrt(1.0 + 4.0 * a - 4.0 * a * a))) * 0.125;
+    if (a < 2.0) return s * (-2.0 - (12.0 - 8.0 * a) / (2.0 * sqrt(-7.0 + 12.0 * a - 4.0 * a * a))) * 0.125;
+    return 0.0;
+}
+
+// Fold a raw support index p along an axis of N cells.  normal: the axis is the
+// face-normal axis of the velocity component.  Returns false when the point is a
+// wall face (contributes nothing).  sgn = -1 for each reflection; cross = 0 (none),
+// 1 (lower wall), 2 (upper wall).  Indices are clamped into [0, N) so that even an
+// invalid marker never addresses memory out of bounds.
+__device__ __forceinline__ bool fold_index(int p, int N, int bc, bool normal, int &idx, double &sgn, int &cross) {
+    sgn = 1.0;
+    cross = 0;
+    if (bc == RBFIB_PERIODIC) {
+        int q = p % N;
+        idx = q < 0 ? q + N : q;
+        return true;
+    }
+    bool ok = true;
+    if (normal) {
+        if (p == 0 || p == N) ok = false;
+        if (p < 0) { idx = -p; sgn = -1.0; cross = 1; }
+        else if (p > N) { idx = 2 * N - p; sgn = -1.0; cross = 2; }
+        else idx = p;
+    } else {
+        if (p < 0) { idx = -1 - p; sgn = -1.0; cross = 1; }
+        else if (p >= N) { idx = 2 * N - 1 - p; sgn = -1.0; cross = 2; }
+        else idx = p;
+    }
+    if (idx < 0) { idx = 0; ok = false; }
+    if (idx > N - 1) { idx = N - 1; ok = false; }
+    return ok;
+}
+
+__device__ __forceinline__ void quat_to_R(const double *th, double R[9]) {
+    double w = th[0], x = th[1], y = th[2], z = th[3];
+    double xx = x * x, yy = y * y, zz = z * z;
+    double xy = x * y, xz = x * z, yz = y * z;
+    double wx = w * x, wy = w * y, wz = w * z;
+    R[0] = 1.0 - 2.0 * (yy + zz); R[1] = 2.0 * (xy - wz);       R[2] = 2.0 * (xz + wy);
+    R[3] = 2.0 * (xy + wz);       R[4] = 1.0 - 2.0 * (xx + zz); R[5] = 2.0 * (yz - wx);
+    R[6] = 2.0 * (xz - wy);       R[7] = 2.0 * (yz + wx);       R[8] = 1.0 - 2.0 * (xx + yy);
+}
+
+// Rotate(theta, phi): left-multiply by the unit quaternion of the rotation vector phi.
+__device__ __forceinline__ void quat_rotate(const double *th, const double *phi, double *out) {
+    double ang = sqrt(phi[0] * phi[0] + phi[1] * phi[1] + phi[2] * phi[2]);
+    if (!(ang > 0.0)) { for (int k = 0; k < 4; ++k) out[k] = th[k]; return; }
+    double s = sin(0.5 * ang) / ang, c = cos(0.5 * ang);
+    double aw = c, ax = s * phi[0], ay = s * phi[1], az = s * phi[2];
+    double bw = th[0], bx = th[1], by = th[2], bz = th[3];
+    double w = aw * bw - (ax * bx + ay * by + az * bz);
+    double x = aw * bx + bw * ax + (ay * bz - az * by);
+    double y = aw * by + bw * ay + (az * bx - ax * bz);
+    double z = aw * bz + bw * az + (ax * by - ay * bx);
+    double nrm = sqrt(w * w + x * x + y * y + z * z);
+    out[0] = w / nrm; out[1] = x / nrm; out[2] = y / nrm; out[3] = z / nrm;
+}
+
+// ---------------------------------------------------------------- Philox4x32-10
+__device__ __forceinline__ void philox4x32_10(uint32_t c[4], uint32_t k0, uint32_t k1) {
+    for (int r = 0; r < 10; ++r) {
+        if (r > 0) { k0 += 0x9E3779B9u; k1 += 0xBB67AE85u; }
+        uint64_t p0 = (uint64_t)0xD2511F53u * c[0];
+        uint64_t p1 = (uint64_t)0xCD9E8D57u * c[2];
+        uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+        uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+        uint32_t n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
+        c[0] = n0; c[1] = lo1; c[2] = n2; c[3] = lo0;
+    }
+}
+
+// Standard normal number `index` of (seed, stream, step) by Box-Muller.
+__device__ __forceinline__ double philox_normal(uint64_t seed, uint32_t stream, uint64_t step, uint64_t index) {
+    uint64_t pair = index >> 1;
+    uint32_t c[4] = {(uint32_t)pair, stream, (uint32_t)step, (uint32_t)(step >> 32)};
+    philox4x32_10(c, (uint32_t)seed, (uint32_t)(seed >> 32));
+    uint64_t a = ((((uint64_t)c[1]) << 32) | c[0]) >> 12;
+    uint64_t b = ((((uint64_t)c[3]) << 32) | c[2]) >> 12;
+    double u1 = ((double)a + 0.5) * 0x1p-52;
+    double u2 = ((double)b + 0.5) * 0x1p-52;
+    double rho = sqrt(-2.0 * log(u1));
+    double ang = (2.0 * 3.141592653589793) * u2;
+    return (index & 1) ? rho * sin(ang) : rho * cos(ang);
+}
+
+// ---------------------------------------------------------------- host context
+struct MarkerSet {
+    double *r = nullptr;      // [nm, 3]
+    double *d = nullptr;      // [nm, 3] = R r_ref
+    int *tile = nullptr;      // [nm] global tile
+    int *perm = nullptr;      // [nm] global marker ids sorted by tile
+    int *tile_count = nullptr, *tile_start = nullptr, *tile_fill = nullptr;
+    int *active = nullptr;    // [ntiles] compacted active target tiles
+    int *n_active = nullptr;  // device scalar
+    int *flag = nullptr;      // [ntiles] scratch
+};
+
+struct Timing {
+    bool on = false;
+    std::vector<hipEvent_t> ev[2];
+    size_t used[2] = {0, 0};
+    double bytes[2] = {0, 0};
+    long long launches[2] = {0, 0};
+    double total_ms[2] = {0, 0};
+};
+
+struct Ctx {
+    hipStream_t stream = nullptr;
+    rbfib_opts opts;
+    int nrep = 0;
+    std::vector<RepDev> reps;
+    long long L = 0;          // state length
+    int nb = 0, nm = 0;
+    int ntiles = 0;
+    int maxlev = 0;
+    int max_body_nm = 1;                 // largest marker count of one body
+    std::vector<double> h_body_len;      // L_p per body (host copy)
+
+    // device descriptors
+    RepDev *d_reps = nullptr;
+    LevDev *d_levs = nullptr;            // [nrep * RB_MAXLEV]
+    std::vector<LevDev> levs;
+    int *d_marker_body = nullptr, *d_body_rep = nullptr, *d_body_off = nullptr;  // body_off: [nb+1] global marker offsets
+    int *d_tile_rep = nullptr;
+    double *d_rref = nullptr;            // [nm, 3]
+    int *d_body_shape = nullptr;
+    ShapeDev *d_shapes = nullptr;
+    double *d_shape_data = nullptr;
+    double *d_body_len = nullptr;        // L_p
+    double d_dummy = 0.0;
+
+    // block tables
+    BlockEnt *d_tab_cells = nullptr; int n_tab_cells = 0;         // level 0, all replicas, per cell chunk
+    BlockEnt *d_tab_vec = nullptr; int n_tab_vec = 0;             // state chunks
+    std::vector<int> vec_first, vec_nblk;                         // per replica block range
+    int *d_vec_first = nullptr, *d_vec_nblk = nullptr;
+    BlockEnt *d_tab_lev[RB_MAXLEV] = {nullptr};  int n_tab_lev[RB_MAXLEV] = {0};   // replicas with level l, not coarsest
+    BlockEnt *d_tab_crs[RB_MAXLEV] = {nullptr};  int n_tab_crs[RB_MAXLEV] = {0};   // replicas whose coarsest is l
+    BlockEnt *d_tab_all[RB_MAXLEV] = {nullptr};  int n_tab_all[RB_MAXLEV] = {0};   // replicas having level l
+    // coarse dense inverses
+    long long *d_coarse_off = nullptr;   // [nrep * 4] offset into coarse pools (doubles)
+    double *d_coarse64 = nullptr;
+    float *d_coarse32 = nullptr;
+    int max_coarse = 0;
+
+    // multigrid pools (x, b, t) in the chosen precision
+    long long lev_total = 0;
+    void *mg_x = nullptr, *mg_b = nullptr, *mg_t = nullptr;
+    bool mg_fp32 = false;
+
+    // marker sets: 0 = Q^n, 1 = Q+, 2 = Q-, 3 = new configuration
+    MarkerSet ms[4];
+    int *d_flags = nullptr;     // [4]: 0 reject/outside, 1 numeric
+    int *h_flags = nullptr;     // pinned host
+
+    // Krylov
+    int m = 0;
+    double *V = nullptr, *Z = nullptr, *W = nullptr;
+    double *xsol = nullptr, *rhs = nullptr, *tmp = nullptr, *fluid_tmp = nullptr;
+    double *partial = nullptr;  // [n_tab_vec * (m+1)]
+    double *H = nullptr, *cs = nullptr, *sn = nullptr, *gv = nullptr, *beta0 = nullptr, *hcol = nullptr, *yv = nullptr;
+    int *active = nullptr, *cyc_active = nullptr, *jf = nullptr, *status = nullptr, *iters = nullptr;
+    int *h_count = nullptr;     // pinned
+    double *d_resid = nullptr;  // [nrep]
+    int *d_count = nullptr;
+
+    // SEM scratch
+    double *q_buf[3] = {nullptr, nullptr, nullptr};      // q+, q-, q_new  [nb, 3]
+    double *th_buf[3] = {nullptr, nullptr, nullptr};     // [nb, 4]
+    double *Wf = nullptr, *Wt = nullptr, *WFT = nullptr, *Fp = nullptr, *slip_acc = nullptr, *UR = nullptr;
+    double *xR = nullptr, *xS = nullptr;
+
+    Timing timing;
+};
+
+// ---------------------------------------------------------------- launchers
+// grid / multigrid (grid.hip)
+void launch_apply_fluid(Ctx &c, const double *x, double *y);
+template <typename T> void launch_to_level0(Ctx &c, const double *src, T *b, int c0, int nc);
+template <typename T> void launch_smooth(Ctx &c, int lev, int c0, int nc, const T *xin, T *xout, const T *b, bool first);
+template <typename T> void launch_restrict(Ctx &c, int lev, int c0, int nc, const T *x, const T *b, T *bc);
+template <typename T> void launch_prolong(Ctx &c, int lev, int c0, int nc, const T *xc, T *xf);
+template <typename T> void launch_coarse(Ctx &c, int lev, int c0, int nc, const T *b, T *x);
+template <typename T> void launch_proj_div(Ctx &c, const T *xv, const double *r, T *bp, double *z);
+template <typename T> void launch_proj_correct(Ctx &c, const T *xv, const T *phi, double *z);
+void launch_noise(Ctx &c, double kT, double dt, uint64_t seed, uint64_t step, double *f, bool add);
+void launch_wall_rhs(Ctx &c, double *f);
+
+// immersed boundary and bodies (ib.hip)
+void launch_markers(Ctx &c, MarkerSet &ms, const double *q, const double *theta);
+void launch_spread(Ctx &c, MarkerSet &ms, const double *lam, double *y, double alpha);
+void launch_body_apply(Ctx &c, MarkerSet &ms, const double *q, const double *x, double *y);
+void launch_body_precond(Ctx &c, MarkerSet &ms, const double *theta, const double *r, double *z);
+void launch_interp(Ctx &c, MarkerSet &ms, const double *x, double *out, double alpha, bool accumulate);
+void launch_interp_bc(Ctx &c, MarkerSet &ms, double *out, double alpha);
+void launch_body_rfd(Ctx &c, double kT, double delta, uint64_t seed, uint64_t step);
+void launch_rfd_terms(Ctx &c, double delta, const double *FT);
+void launch_sem_rhs_lambda(Ctx &c, const double *slip, double *b);
+void launch_update_positions(Ctx &c, const double *q, const double *theta, const double *U, double dt);
+void launch_commit_positions(Ctx &c, double *q, double *theta);
+void launch_body_gradient(Ctx &c, MarkerSet &ms, const double *x, const double *xa, double *dq, double *dphi);
+void launch_copy_U(Ctx &c, const double *x, double *U, double scale);
+void launch_set_rhs(Ctx &c, const double *FT, const double *slip, double *b);
+
+// Krylov (krylov.hip)
+void launch_dots(Ctx &c, const double *V, int nvec, const double *w, double *out /*[nrep*(m+1)]*/, const int *mask);
+void launch_axpy_multi(Ctx &c, const double *V, int nvec, const double *coef, double *w, double sign, const int *mask);
+void launch_norm(Ctx &c, const double *w, double *out, const int *mask);
+void launch_scale(Ctx &c, const double *w, const double *s, double *out, const int *mask, bool inverse);
+void launch_axpby(Ctx &c, double a, const double *x, double b, const double *y, double *out, const int *mask);
+void launch_copy(Ctx &c, const double *x, double *y, const int *mask);
+void launch_zero(Ctx &c, double *y, const int *mask);
+void launch_givens(Ctx &c, int j, double tol);
+void launch_start_cycle(Ctx &c);
+void launch_trisolve_update(Ctx &c);
+void launch_zero_bodies(Ctx &c, double *y);   // zero the lambda and U slots
+
+template <typename T> void zero_device(Ctx &c, T *p, long long n);
+
+}  // namespace rb
+
+#define HIP_OK(expr) do { hipError_t e_ = (expr); if (e_ != hipSuccess) { rb_last_hip_error(e_, #expr, __FILE__, __LINE__); throw (int)RBFIB_EDEVICE; } } while (0)
+void rb_last_hip_error(hipError_t e, const char *what, const char *file, int line);

@@ -1,0 +1,549 @@
+// Staggered-grid kernels: the fused saddle-point fluid apply (-eta Lm v + G pi, -D v),
+// the geometric-multigrid pieces of the Stokes preconditioner (damped Jacobi,
+// restriction, prolongation, dense coarsest solve, projection step), the
+// fluctuating-stress forcing DT W and the sliding-wall terms.
+//
+// Discretisation (paper Sec. III.A): velocity on faces, pressure at cell centres,
+// G = -D^*, Lm = DT GT; on a wall axis the normal-velocity wall faces are not
+// unknowns and tangential ghosts are u_g = 2 U_w - u (the homogeneous operator
+// uses U_w = 0).  Every kernel is one thread per grid point, x fastest, so that a
+// wavefront reads 64 consecutive doubles of each field.
+#include "common.h"
+
+namespace rb {
+
+// Value of field u (component c, or 3 = pressure) at the neighbour of (i,j,k)
+// along axis a in direction d (+1/-1), with the boundary rule of the operator.
+template <typename T>
+__device__ __forceinline__ T nbr(const T *u, int c, int a, int d, int idx[3], const int n[3], const int bc[3],
+                                 T self, long long lin, long long stride) {
+    int p = idx[a] + d;
+    if (bc[a] == RBFIB_PERIODIC) {
+        if (p < 0) return u[lin + (long long)(n[a] - 1) * stride];
+        if (p >= n[a]) return u[lin - (long long)(n[a] - 1) * stride];
+        return u[lin + d * stride];
+    }
+    if (a == c) {                       // face-normal: wall faces are zero
+        if (p <= 0 || p >= n[a]) return (T)0;
+        return u[lin + d * stride];
+    }
+    if (p < 0 || p >= n[a]) return (c == 3) ? self : -self;   // Neumann (pressure) / odd ghost
+    return u[lin + d * stride];
+}
+
+// sum_a (u(+a) - 2u + u(-a)) * inv_h2[a]  and its diagonal coefficient.
+template <typename T>
+__device__ __forceinline__ T lap_point(const T *u, int c, int idx[3], const int n[3], const int bc[3],
+                                       const double ih2[3], long long lin, T &diag) {
+    T self = u[lin];
+    T acc = (T)0;
+    T dg = (T)0;
+    long long stride = 1;
+    for (int a = 0; a < 3; ++a) {
+        T up = nbr(u, c, a, +1, idx, n, bc, self, lin, stride);
+        T um = nbr(u, c, a, -1, idx, n, bc, self, lin, stride);
+        acc += (up - (T)2 * self + um) * (T)ih2[a];
+        T da = (T)-2;
+        if (bc[a] == RBFIB_WALL && a != c) {
+            T g = (c == 3) ? (T)1 : (T)-1;
+            if (idx[a] == 0) da += g;
+            if (idx[a] == n[a] - 1) da += g;
+        }
+        dg += da * (T)ih2[a];
+        stride *= n[a];
+    }
+    diag = dg;
+    return acc;
+}
+
+__device__ __forceinline__ bool pinned(int c, const int idx[3], const int bc[3]) {
+    return c < 3 && bc[c] == RBFIB_WALL && idx[c] == 0;
+}
+
+__device__ __forceinline__ void unlin(long long lin, const int n[3], int idx[3]) {
+    idx[0] = (int)(lin % n[0]);
+    long long t = lin / n[0];
+    idx[1] = (int)(t % n[1]);
+    idx[2] = (int)(t / n[1]);
+}
+
+// ------------------------------------------------------------------ fused fluid apply
+// y_c = -eta Lm_c v + (G pi)_c for c = x, y, z;  y_pi = -(D v).  Pinned slots -> 0.
+__global__ void k_apply_fluid(const RepDev *reps, const BlockEnt *tab, const double *__restrict__ x,
+                              double *__restrict__ y) {
+    BlockEnt be = tab[blockIdx.x];
+    const RepDev &R = reps[be.rep];
+    long long lin = be.start + threadIdx.x;
+    long long N = R.N;
+    if (lin >= N) return;
+    int idx[3];
+    unlin(lin, R.n, idx);
+    const double *u[3] = {x + R.off, x + R.off + N, x + R.off + 2 * N};
+    const double *p = x + R.off + 3 * N;
+    double ih = R.inv_h;
+    double ih2[3] = {ih * ih, ih * ih, ih * ih};
+    // pressure: cell lin; divergence uses faces lin and lin + e_c
+    double div = 0.0;
+    long long stride = 1;
+    for (int c = 0; c < 3; ++c) {
+        double lo = pinned(c, idx, R.bc) ? 0.0 : u[c][lin];
+        double hi;
+        int q = idx[c] + 1;
+        if (q < R.n[c]) hi = u[c][lin + stride];
+        else hi = (R.bc[c] == RBFIB_PERIODIC) ? u[c][lin - (long long)(R.n[c] - 1) * stride] : 0.0;
+        div += (hi - lo) * ih;
+        stride *= R.n[c];
+    }
+    y[R.off + 3 * N + lin] = -div;
+    stride = 1;
+    double pc = p[lin];
+    for (int c = 0; c < 3; ++c) {
+        double out = 0.0;
+        if (!pinned(c, idx, R.bc)) {
+            double dg;
+            double lap = lap_point<double>(u[c], c, idx, R.n, R.bc, ih2, lin, dg);
+            // neighbour values at pinned slots must read as zero
+            // (lap_point's face-normal rule already returns 0 for p <= 0)
+            double pm = (idx[c] > 0) ? p[lin - stride] : p[lin + (long long)(R.n[c] - 1) * stride];
+            out = -R.eta * lap + (pc - pm) * ih;
+        }
+        y[R.off + c * N + lin] = out;
+        stride *= R.n[c];
+    }
+}
+
+void launch_apply_fluid(Ctx &c, const double *x, double *y) {
+    hipLaunchKernelGGL(k_apply_fluid, dim3(c.n_tab_cells), dim3(RB_BLOCK), 0, c.stream, c.d_reps, c.d_tab_cells,
+                       x, y);
+}
+
+// ------------------------------------------------------------------ multigrid
+// Level pools hold 4 fields per (replica, level): comp c at lev.off + c * lev.N.
+template <typename T>
+__global__ void k_to_level0(const RepDev *reps, const LevDev *levs, const BlockEnt *tab, const double *src,
+                            T *b, int c0) {
+    BlockEnt be = tab[blockIdx.x];
+    int comp = c0 + blockIdx.y;
+    const RepDev &R = reps[be.rep];
+    long long lin = be.start + threadIdx.x;
+    if (lin >= R.N) return;
+    const LevDev &Lv = levs[be.rep * RB_MAXLEV];
+    b[Lv.off + comp * Lv.N + lin] = (T)src[R.off + comp * R.N + lin];
+}
+
+template <typename T>
+void launch_to_level0(Ctx &c, const double *src, T *b, int c0, int nc) {
+    hipLaunchKernelGGL(k_to_level0<T>, dim3(c.n_tab_cells, nc), dim3(RB_BLOCK), 0, c.stream, c.d_reps, c.d_levs,
+                       c.d_tab_cells, src, b, c0);
+}
+
+// Operator of component comp at a level: A = -eta Lm (velocity) or -L (pressure).
+template <typename T>
+__global__ void k_smooth(const RepDev *reps, const LevDev *levs, const BlockEnt *tab, int lev, int c0,
+                         const T *__restrict__ xin, T *__restrict__ xout, const T *__restrict__ b, double omega,
+                         int first) {
+    BlockEnt be = tab[blockIdx.x];
+    int comp = c0 + blockIdx.y;
+    const RepDev &R = reps[be.rep];
+    const LevDev &Lv = levs[be.rep * RB_MAXLEV + lev];
+    long long lin = be.start + threadIdx.x;
+    if (lin >= Lv.N) return;
+    int idx[3];
+    unlin(lin, Lv.n, idx);
+    long long base = Lv.off + comp * Lv.N;
+    if (pinned(comp, idx, R.bc)) { xout[base + lin] = (T)0; return; }
+    T s = (comp < 3) ? (T)(-R.eta) : (T)-1;
+    T dg, lap;
+    if (first) {
+        // x_in = 0: diagonal only
+        dg = (T)0;
+        for (int a = 0; a < 3; ++a) {
+            T da = (T)-2;
+            if (R.bc[a] == RBFIB_WALL && a != comp) {
+                T g = (comp == 3) ? (T)1 : (T)-1;
+                if (idx[a] == 0) da += g;
+                if (idx[a] == Lv.n[a] - 1) da += g;
+            }
+            dg += da * (T)Lv.inv_h2[a];
+        }
+        xout[base + lin] = (T)omega * b[base + lin] / (s * dg);
+        return;
+    }
+    lap = lap_point<T>(xin + base, comp, idx, Lv.n, R.bc, Lv.inv_h2, lin, dg);
+    T xv = xin[base + lin];
+    T res = b[base + lin] - s * lap;
+    xout[base + lin] = xv + (T)omega * res / (s * dg);
+}
+
+template <typename T>
+void launch_smooth(Ctx &c, int lev, int c0, int nc, const T *xin, T *xout, const T *b, bool first) {
+    if (c.n_tab_lev[lev] == 0) return;
+    hipLaunchKernelGGL(k_smooth<T>, dim3(c.n_tab_lev[lev], nc), dim3(RB_BLOCK), 0, c.stream, c.d_reps, c.d_levs,
+                       c.d_tab_lev[lev], lev, c0, xin, xout, b, c.opts.mg_omega, first ? 1 : 0);
+}
+
+// Residual of level lev restricted to level lev+1: face-normal axis full weighting
+// (1/4, 1/2, 1/4 on faces 2I-1, 2I, 2I+1), cell-centred axes averaging of the two
+// children; an axis that is not coarsened keeps its index.
+template <typename T>
+__device__ T residual_at(const RepDev &R, const LevDev &Lv, int comp, int i, int j, int k, const T *x, const T *b) {
+    int idx[3] = {i, j, k};
+    if (pinned(comp, idx, R.bc)) return (T)0;
+    long long lin = (long long)i + (long long)Lv.n[0] * ((long long)j + (long long)Lv.n[1] * k);
+    T dg;
+    T lap = lap_point<T>(x, comp, idx, Lv.n, R.bc, Lv.inv_h2, lin, dg);
+    T s = (comp < 3) ? (T)(-R.eta) : (T)-1;
+    return b[lin] - s * lap;
+}
+
+template <typename T>
+__global__ void k_restrict(const RepDev *reps, const LevDev *levs, const BlockEnt *tab, int lev, int c0,
+                           const T *__restrict__ x, const T *__restrict__ b, T *__restrict__ bc) {
+    BlockEnt be = tab[blockIdx.x];
+    int comp = c0 + blockIdx.y;
+    const RepDev &R = reps[be.rep];
+    const LevDev &F = levs[be.rep * RB_MAXLEV + lev];
+    const LevDev &C = levs[be.rep * RB_MAXLEV + lev + 1];
+    long long lin = be.start + threadIdx.x;
+    if (lin >= C.N) return;
+    int ci[3];
+    unlin(lin, C.n, ci);
+    long long cbase = C.off + comp * C.N;
+    if (pinned(comp, ci, R.bc)) { bc[cbase + lin] = (T)0; return; }
+    const T *xf = x + F.off + comp * F.N;
+    const T *bf = b + F.off + comp * F.N;
+    int fi[3][3];
+    T fw[3][3];
+    int cnt[3];
+    for (int a = 0; a < 3; ++a) {
+        if (F.n[a] == C.n[a]) { cnt[a] = 1; fi[a][0] = ci[a]; fw[a][0] = (T)1; continue; }
+        if (a == comp) {
+            cnt[a] = 3;
+            int f0 = 2 * ci[a];
+            int fm = f0 - 1;
+            if (fm < 0) fm += F.n[a];   // periodic wrap (wall: ci = 0 is pinned, excluded above)
+            int fp = f0 + 1;
+            if (fp >= F.n[a]) fp -= F.n[a];
+            fi[a][0] = fm; fw[a][0] = (T)0.25;
+            fi[a][1] = f0; fw[a][1] = (T)0.5;
+            fi[a][2] = fp; fw[a][2] = (T)0.25;
+        } else {
+            cnt[a] = 2;
+            fi[a][0] = 2 * ci[a]; fw[a][0] = (T)0.5;
+            fi[a][1] = 2 * ci[a] + 1; fw[a][1] = (T)0.5;
+        }
+    }
+    T acc = (T)0;
+    for (int kk = 0; kk < cnt[2]; ++kk)
+        for (int jj = 0; jj < cnt[1]; ++jj)
+            for (int ii = 0; ii < cnt[0]; ++ii) {
+                T w = fw[0][ii] * fw[1][jj] * fw[2][kk];
+                acc += w * residual_at<T>(R, F, comp, fi[0][ii], fi[1][jj], fi[2][kk], xf, bf);
+            }
+    bc[cbase + lin] = acc;
+}
+
+template <typename T>
+void launch_restrict(Ctx &c, int lev, int c0, int nc, const T *x, const T *b, T *bcoarse) {
+    if (c.n_tab_lev[lev] == 0) return;
+    // one thread per coarse point: use the table of level lev+1 restricted to replicas descending from lev
+    hipLaunchKernelGGL(k_restrict<T>, dim3(c.n_tab_all[lev + 1], nc), dim3(RB_BLOCK), 0, c.stream, c.d_reps,
+                       c.d_levs, c.d_tab_all[lev + 1], lev, c0, x, b, bcoarse);
+}
+
+// x_f += P x_c: face-normal axis linear (even faces copy, odd faces average),
+// cell-centred axes linear (3/4, 1/4) with odd ghosts for velocity at walls and
+// even ghosts for pressure.
+template <typename T>
+__global__ void k_prolong(const RepDev *reps, const LevDev *levs, const BlockEnt *tab, int lev, int c0,
+                          const T *__restrict__ xc, T *__restrict__ xf) {
+    BlockEnt be = tab[blockIdx.x];
+    int comp = c0 + blockIdx.y;
+    const RepDev &R = reps[be.rep];
+    const LevDev &F = levs[be.rep * RB_MAXLEV + lev];
+    const LevDev &C = levs[be.rep * RB_MAXLEV + lev + 1];
+    long long lin = be.start + threadIdx.x;
+    if (lin >= F.N) return;
+    int fi[3];
+    unlin(lin, F.n, fi);
+    if (pinned(comp, fi, R.bc)) return;
+    int ci[3][2];
+    T cw[3][2];
+    T cs[3][2];
+    int cnt[3];
+    for (int a = 0; a < 3; ++a) {
+        cs[a][0] = cs[a][1] = (T)1;
+        if (F.n[a] == C.n[a]) { cnt[a] = 1; ci[a][0] = fi[a]; cw[a][0] = (T)1; continue; }
+        int I = fi[a] >> 1;
+        if (a == comp) {
+            if ((fi[a] & 1) == 0) { cnt[a] = 1; ci[a][0] = I; cw[a][0] = (T)1; }
+            else {
+                cnt[a] = 2;
+                ci[a][0] = I; cw[a][0] = (T)0.5;
+                int J = I + 1;
+                if (J >= C.n[a]) {
+                    if (R.bc[a] == RBFIB_PERIODIC) J -= C.n[a];
+                    else { J = I; cs[a][1] = (T)0; }      // wall face: zero
+                }
+                ci[a][1] = J; cw[a][1] = (T)0.5;
+            }
+            // coarse slot 0 on a wall axis is the wall face (zero)
+            if (R.bc[a] == RBFIB_WALL) {
+                for (int t = 0; t < cnt[a]; ++t) if (ci[a][t] == 0) cs[a][t] = (T)0;
+            }
+        } else {
+            cnt[a] = 2;
+            ci[a][0] = I; cw[a][0] = (T)0.75;
+            int J = (fi[a] & 1) ? I + 1 : I - 1;
+            T g = (T)1;
+            if (J < 0 || J >= C.n[a]) {
+                if (R.bc[a] == RBFIB_PERIODIC) J = (J < 0) ? J + C.n[a] : J - C.n[a];
+                else { J = I; g = (comp == 3) ? (T)1 : (T)-1; }
+            }
+            ci[a][1] = J; cw[a][1] = (T)0.25; cs[a][1] = g;
+        }
+    }
+    const T *xcc = xc + C.off + comp * C.N;
+    T acc = (T)0;
+    for (int kk = 0; kk < cnt[2]; ++kk)
+        for (int jj = 0; jj < cnt[1]; ++jj)
+            for (int ii = 0; ii < cnt[0]; ++ii) {
+                T w = cw[0][ii] * cw[1][jj] * cw[2][kk] * cs[0][ii] * cs[1][jj] * cs[2][kk];
+                long long cl = (long long)ci[0][ii] + (long long)C.n[0] * ((long long)ci[1][jj] + (long long)C.n[1] * ci[2][kk]);
+                acc += w * xcc[cl];
+            }
+    xf[F.off + comp * F.N + lin] += acc;
+}
+
+template <typename T>
+void launch_prolong(Ctx &c, int lev, int c0, int nc, const T *xc, T *xf) {
+    if (c.n_tab_lev[lev] == 0) return;
+    hipLaunchKernelGGL(k_prolong<T>, dim3(c.n_tab_lev[lev], nc), dim3(RB_BLOCK), 0, c.stream, c.d_reps, c.d_levs,
+                       c.d_tab_lev[lev], lev, c0, xc, xf);
+}
+
+// Dense coarsest solve x = Ainv b, one workgroup per (replica, component).
+template <typename T>
+__global__ void k_coarse(const RepDev *reps, const LevDev *levs, const BlockEnt *tab, int lev, int c0,
+                         const long long *coff, const T *__restrict__ Ainv, const T *__restrict__ b,
+                         T *__restrict__ x) {
+    BlockEnt be = tab[blockIdx.x];
+    int comp = c0 + blockIdx.y;
+    const LevDev &Lv = levs[be.rep * RB_MAXLEV + lev];
+    extern __shared__ unsigned char smem_raw[];
+    T *bs = reinterpret_cast<T *>(smem_raw);
+    int m = (int)Lv.N;
+    const T *bb = b + Lv.off + comp * Lv.N;
+    for (int i = threadIdx.x; i < m; i += blockDim.x) bs[i] = bb[i];
+    __syncthreads();
+    const T *A = Ainv + coff[be.rep * 4 + comp];
+    T *xx = x + Lv.off + comp * Lv.N;
+    for (int i = threadIdx.x; i < m; i += blockDim.x) {
+        T acc = (T)0;
+        const T *row = A + (long long)i * m;
+        for (int j = 0; j < m; ++j) acc += row[j] * bs[j];
+        xx[i] = acc;
+    }
+}
+
+template <typename T> const T *coarse_pool(Ctx &c);
+template <> const double *coarse_pool<double>(Ctx &c) { return c.d_coarse64; }
+template <> const float *coarse_pool<float>(Ctx &c) { return c.d_coarse32; }
+
+template <typename T>
+void launch_coarse(Ctx &c, int lev, int c0, int nc, const T *b, T *x) {
+    if (c.n_tab_crs[lev] == 0) return;
+    size_t sh = sizeof(T) * (size_t)c.max_coarse;
+    hipLaunchKernelGGL(k_coarse<T>, dim3(c.n_tab_crs[lev], nc), dim3(RB_BLOCK), sh, c.stream, c.d_reps, c.d_levs,
+                       c.d_tab_crs[lev], lev, c0, c.d_coarse_off, coarse_pool<T>(c), b, x);
+}
+
+// ------------------------------------------------------------------ projection step
+// d = D x* + r_pi ;  b_p (level 0) = -d  (so that -L phi = -d) ;  z_pi = -eta d.
+template <typename T>
+__global__ void k_proj_div(const RepDev *reps, const LevDev *levs, const BlockEnt *tab, const T *__restrict__ xv,
+                           const double *__restrict__ r, T *__restrict__ bp, double *__restrict__ z) {
+    BlockEnt be = tab[blockIdx.x];
+    const RepDev &R = reps[be.rep];
+    const LevDev &Lv = levs[be.rep * RB_MAXLEV];
+    long long lin = be.start + threadIdx.x;
+    long long N = R.N;
+    if (lin >= N) return;
+    int idx[3];
+    unlin(lin, R.n, idx);
+    double div = 0.0;
+    long long stride = 1;
+    for (int c = 0; c < 3; ++c) {
+        const T *u = xv + Lv.off + c * Lv.N;
+        double lo = pinned(c, idx, R.bc) ? 0.0 : (double)u[lin];
+        double hi;
+        if (idx[c] + 1 < R.n[c]) hi = (double)u[lin + stride];
+        else hi = (R.bc[c] == RBFIB_PERIODIC) ? (double)u[lin - (long long)(R.n[c] - 1) * stride] : 0.0;
+        div += (hi - lo) * R.inv_h;
+        stride *= R.n[c];
+    }
+    double d = div + r[R.off + 3 * N + lin];
+    bp[Lv.off + 3 * Lv.N + lin] = (T)(-d);
+    z[R.off + 3 * N + lin] = -R.eta * d;
+}
+
+template <typename T>
+void launch_proj_div(Ctx &c, const T *xv, const double *r, T *bp, double *z) {
+    hipLaunchKernelGGL(k_proj_div<T>, dim3(c.n_tab_cells), dim3(RB_BLOCK), 0, c.stream, c.d_reps, c.d_levs,
+                       c.d_tab_cells, xv, r, bp, z);
+}
+
+// z_v = x* - G phi  (phi in the pressure slot of the level-0 pool).
+template <typename T>
+__global__ void k_proj_correct(const RepDev *reps, const LevDev *levs, const BlockEnt *tab, const T *__restrict__ xv,
+                               const T *__restrict__ phi, double *__restrict__ z) {
+    BlockEnt be = tab[blockIdx.x];
+    const RepDev &R = reps[be.rep];
+    const LevDev &Lv = levs[be.rep * RB_MAXLEV];
+    long long lin = be.start + threadIdx.x;
+    long long N = R.N;
+    if (lin >= N) return;
+    int idx[3];
+    unlin(lin, R.n, idx);
+    const T *ph = phi + Lv.off + 3 * Lv.N;
+    double pc = (double)ph[lin];
+    long long stride = 1;
+    for (int c = 0; c < 3; ++c) {
+        double out = 0.0;
+        if (!pinned(c, idx, R.bc)) {
+            double pm = (idx[c] > 0) ? (double)ph[lin - stride] : (double)ph[lin + (long long)(R.n[c] - 1) * stride];
+            out = (double)xv[Lv.off + c * Lv.N + lin] - (pc - pm) * R.inv_h;
+        }
+        z[R.off + c * N + lin] = out;
+        stride *= R.n[c];
+    }
+}
+
+template <typename T>
+void launch_proj_correct(Ctx &c, const T *xv, const T *phi, double *z) {
+    hipLaunchKernelGGL(k_proj_correct<T>, dim3(c.n_tab_cells), dim3(RB_BLOCK), 0, c.stream, c.d_reps, c.d_levs,
+                       c.d_tab_cells, xv, phi, z);
+}
+
+// ------------------------------------------------------------------ fluctuating stress
+// f_c(face) = scale * (DT W)_c = scale * [ (W_cc(cell f) - W_cc(cell f-1)) / h
+//            + sum_{b != c} (w(n+1) W_cb(node n+1) - w(n) W_cb(node n)) / h ]
+// where n is the cell index of the face along b and w = sqrt(2) on wall nodes.
+__device__ __forceinline__ int fam_index(int c, int b) {
+    if (c == b) return c;
+    // order: xy, xz, yx, yz, zx, zy
+    return 3 + 2 * c + ((b > c) ? b - 1 : b);
+}
+
+__device__ __forceinline__ double noise_W(uint64_t seed, uint64_t step, const RepDev &R, const long long *fam_off,
+                                          int fam, int c, int b, int i, int j, int k) {
+    int dims[3] = {R.n[0], R.n[1], R.n[2]};
+    if (b != c && R.bc[b] == RBFIB_WALL) dims[b] += 1;
+    long long lin = (long long)i + (long long)dims[0] * ((long long)j + (long long)dims[1] * k);
+    return philox_normal(seed, 1u, step, (uint64_t)(fam_off[fam] + lin));
+}
+
+__global__ void k_noise(const RepDev *reps, const BlockEnt *tab, double scale_base, uint64_t seed, uint64_t step,
+                        double *__restrict__ f, int add) {
+    BlockEnt be = tab[blockIdx.x];
+    const RepDev &R = reps[be.rep];
+    long long lin = be.start + threadIdx.x;
+    long long N = R.N;
+    if (lin >= N) return;
+    int idx[3];
+    unlin(lin, R.n, idx);
+    uint64_t rseed = seed + (uint64_t)be.rep;
+    long long fam_off[10];
+    fam_off[0] = 0;
+    const int FC[9] = {0, 1, 2, 0, 0, 1, 1, 2, 2};
+    const int FB[9] = {0, 1, 2, 1, 2, 0, 2, 0, 1};
+    for (int q = 0; q < 9; ++q) {
+        long long sz = 1;
+        for (int a = 0; a < 3; ++a) sz *= (long long)R.n[a] + ((a == FB[q] && FB[q] != FC[q] && R.bc[a] == RBFIB_WALL) ? 1 : 0);
+        fam_off[q + 1] = fam_off[q] + sz;
+    }
+    double scale = scale_base * sqrt(R.eta / R.dV);
+    const double SQ2 = 1.4142135623730951;
+    for (int c = 0; c < 3; ++c) {
+        double out = 0.0;
+        if (!pinned(c, idx, R.bc)) {
+            // family (c, c): cells idx and idx - e_c
+            int im[3] = {idx[0], idx[1], idx[2]};
+            im[c] -= 1;
+            if (im[c] < 0) im[c] += R.n[c];   // only reachable on periodic axes
+            double wp = noise_W(rseed, step, R, fam_off, fam_index(c, c), c, c, idx[0], idx[1], idx[2]);
+            double wm = noise_W(rseed, step, R, fam_off, fam_index(c, c), c, c, im[0], im[1], im[2]);
+            out += (wp - wm) * R.inv_h;
+            for (int b = 0; b < 3; ++b) {
+                if (b == c) continue;
+                int fam = fam_index(c, b);
+                int nb_ = idx[b];
+                int np = nb_ + 1;
+                double wlo = 1.0, whi = 1.0;
+                int pi3[3] = {idx[0], idx[1], idx[2]};
+                if (R.bc[b] == RBFIB_WALL) {
+                    if (nb_ == 0) wlo = SQ2;
+                    if (np == R.n[b]) whi = SQ2;
+                } else if (np == R.n[b]) np = 0;
+                double Wlo = noise_W(rseed, step, R, fam_off, fam, c, b, pi3[0], pi3[1], pi3[2]);
+                pi3[b] = np;
+                double Whi = noise_W(rseed, step, R, fam_off, fam, c, b, pi3[0], pi3[1], pi3[2]);
+                out += (whi * Whi - wlo * Wlo) * R.inv_h;
+            }
+            out *= scale;
+        }
+        double *dst = f + R.off + c * N + lin;
+        if (add) *dst += out; else *dst = out;
+    }
+    if (!add) f[R.off + 3 * N + lin] = 0.0;
+}
+
+void launch_noise(Ctx &c, double kT, double dt, uint64_t seed, uint64_t step, double *f, bool add) {
+    double scale_base = sqrt(2.0 * kT / dt);
+    hipLaunchKernelGGL(k_noise, dim3(c.n_tab_cells), dim3(RB_BLOCK), 0, c.stream, c.d_reps, c.d_tab_cells, scale_base,
+                       seed, step, f, add ? 1 : 0);
+}
+
+// Sliding walls: f_c += 2 eta U_w / h^2 on tangential faces adjacent to the wall.
+__global__ void k_wall_rhs(const RepDev *reps, const BlockEnt *tab, double *__restrict__ f) {
+    BlockEnt be = tab[blockIdx.x];
+    const RepDev &R = reps[be.rep];
+    if (!R.movwall) return;
+    long long lin = be.start + threadIdx.x;
+    long long N = R.N;
+    if (lin >= N) return;
+    int idx[3];
+    unlin(lin, R.n, idx);
+    for (int c = 0; c < 3; ++c) {
+        if (pinned(c, idx, R.bc)) continue;
+        double add = 0.0;
+        for (int a = 0; a < 3; ++a) {
+            if (a == c || R.bc[a] != RBFIB_WALL) continue;
+            if (idx[a] == 0) add += 2.0 * R.eta * R.wv[a][0][c] * R.inv_h * R.inv_h;
+            if (idx[a] == R.n[a] - 1) add += 2.0 * R.eta * R.wv[a][1][c] * R.inv_h * R.inv_h;
+        }
+        f[R.off + c * N + lin] += add;
+    }
+}
+
+void launch_wall_rhs(Ctx &c, double *f) {
+    hipLaunchKernelGGL(k_wall_rhs, dim3(c.n_tab_cells), dim3(RB_BLOCK), 0, c.stream, c.d_reps, c.d_tab_cells, f);
+}
+
+// explicit instantiations
+template void launch_to_level0<float>(Ctx &, const double *, float *, int, int);
+template void launch_to_level0<double>(Ctx &, const double *, double *, int, int);
+template void launch_smooth<float>(Ctx &, int, int, int, const float *, float *, const float *, bool);
+template void launch_smooth<double>(Ctx &, int, int, int, const double *, double *, const double *, bool);
+template void launch_restrict<float>(Ctx &, int, int, int, const float *, const float *, float *);
+template void launch_restrict<double>(Ctx &, int, int, int, const double *, const double *, double *);
+template void launch_prolong<float>(Ctx &, int, int, int, const float *, float *);
+template void launch_prolong<double>(Ctx &, int, int, int, const double *, double *);
+template void launch_coarse<float>(Ctx &, int, int, int, const float *, float *);
+template void launch_coarse<double>(Ctx &, int, int, int, const double *, double *);
+template void launch_proj_div<float>(Ctx &, const float *, const double *, float *, double *);
+template void launch_proj_div<double>(Ctx &, const double *, const double *, double *, double *);
+template void launch_proj_correct<float>(Ctx &, const float *, const float *, double *);
+template void launch_proj_correct<double>(Ctx &, const double *, const double *, double *);
+
+}  // namespace rb

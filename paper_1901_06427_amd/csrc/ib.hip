@@ -1,0 +1,552 @@
+// Immersed-boundary and rigid-body kernels (paper Sec. III.B, III.C):
+//   * marker geometry r_i = q_p + R(theta_p) r_i^ref and binning into 4^3-cell tiles;
+//   * spreading S as a deterministic GATHER: one workgroup per target tile pulls the
+//     markers of the (up to) 27 neighbouring tiles into LDS, folds their 4-point
+//     kernel weights onto the tile's 4-wide window per axis, and each thread owns
+//     one target face -- no atomics, fixed summation order;
+//   * interpolation J fused with K U and K^T lambda, one workgroup per body;
+//   * the per-body block of the preconditioner (dense body-frame blob mobility).
+// Walls fold the kernel support by odd reflection so that J = dV S^* holds exactly.
+#include "common.h"
+
+namespace rb {
+
+// ------------------------------------------------------------------ geometry
+// The marker position is computed with contraction disabled and in a fixed
+// operation order so that the integer cell/tile indices are reproducible.
+__device__ void marker_pos(const double *q, const double *th, const double *rr, double d[3], double r[3]) {
+#pragma clang fp contract(off)
+    double w = th[0], x = th[1], y = th[2], z = th[3];
+    double xx = x * x, yy = y * y, zz = z * z;
+    double xy = x * y, xz = x * z, yz = y * z;
+    double wx = w * x, wy = w * y, wz = w * z;
+    double R0 = 1.0 - 2.0 * (yy + zz), R1 = 2.0 * (xy - wz), R2 = 2.0 * (xz + wy);
+    double R3 = 2.0 * (xy + wz), R4 = 1.0 - 2.0 * (xx + zz), R5 = 2.0 * (yz - wx);
+    double R6 = 2.0 * (xz - wy), R7 = 2.0 * (yz + wx), R8 = 1.0 - 2.0 * (xx + yy);
+    double a = rr[0], b = rr[1], c = rr[2];
+    double t0 = R0 * a, t1 = R1 * b, t2 = R2 * c;
+    double t3 = R3 * a, t4 = R4 * b, t5 = R5 * c;
+    double t6 = R6 * a, t7 = R7 * b, t8 = R8 * c;
+    d[0] = (t0 + t1) + t2;
+    d[1] = (t3 + t4) + t5;
+    d[2] = (t6 + t7) + t8;
+    r[0] = q[0] + d[0];
+    r[1] = q[1] + d[1];
+    r[2] = q[2] + d[2];
+}
+
+__global__ void k_markers(const RepDev *reps, const int *marker_body, const int *body_rep, const double *q,
+                          const double *theta, const double *rref, int nm, double *r_out, double *d_out, int *tile,
+                          int *tile_count, int *flags) {
+    int m = blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= nm) return;
+    int p = marker_body[m];
+    const RepDev &R = reps[body_rep[p]];
+    double d[3], r[3];
+    marker_pos(q + 3 * p, theta + 4 * p, rref + 3 * m, d, r);
+    int cell[3];
+    bool outside = false;
+    for (int a = 0; a < 3; ++a) {
+        double s = r[a] * R.inv_h;
+        if (!(s == s) || fabs(s) > 1e9) { outside = true; s = 0.0; }
+        long long cc = (long long)floor(s);
+        if (R.bc[a] == RBFIB_PERIODIC) {
+            cc %= R.n[a];
+            if (cc < 0) cc += R.n[a];
+        } else {
+            double L = (double)R.n[a] * R.h;
+            if (!(r[a] > 0.0 && r[a] < L)) outside = true;
+            if (cc < 0) cc = 0;
+            if (cc > R.n[a] - 1) cc = R.n[a] - 1;
+        }
+        cell[a] = (int)cc;
+    }
+    int t = R.tile0 + (cell[0] >> 2) + R.tdim[0] * ((cell[1] >> 2) + R.tdim[1] * (cell[2] >> 2));
+    for (int a = 0; a < 3; ++a) { r_out[3 * m + a] = r[a]; d_out[3 * m + a] = d[a]; }
+    tile[m] = t;
+    atomicAdd(&tile_count[t], 1);
+    if (outside) atomicOr(&flags[0], 1 << 0);
+}
+
+// exclusive scan of tile counts (one workgroup), zero the fill counters
+__global__ void k_tile_scan(const int *count, int *start, int *fill, int ntiles) {
+    __shared__ int part[1024];
+    int per = (ntiles + blockDim.x - 1) / blockDim.x;
+    int b = threadIdx.x * per, e = min(ntiles, b + per);
+    int s = 0;
+    for (int i = b; i < e; ++i) s += count[i];
+    part[threadIdx.x] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int acc = 0;
+        for (int i = 0; i < (int)blockDim.x; ++i) { int v = part[i]; part[i] = acc; acc += v; }
+    }
+    __syncthreads();
+    int acc = part[threadIdx.x];
+    for (int i = b; i < e; ++i) { start[i] = acc; acc += count[i]; fill[i] = 0; }
+}
+
+__global__ void k_tile_place(const int *tile, const int *start, int *fill, int *perm, int nm) {
+    int m = blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= nm) return;
+    int t = tile[m];
+    int slot = start[t] + atomicAdd(&fill[t], 1);
+    perm[slot] = m;
+}
+
+// insertion sort of each tile's markers by id: a stable (tile, id) order
+__global__ void k_tile_sort(const int *start, const int *count, int *perm, int ntiles) {
+    int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= ntiles) return;
+    int b = start[t], n = count[t];
+    for (int i = 1; i < n; ++i) {
+        int v = perm[b + i];
+        int j = i - 1;
+        while (j >= 0 && perm[b + j] > v) { perm[b + j + 1] = perm[b + j]; --j; }
+        perm[b + j + 1] = v;
+    }
+}
+
+// neighbour tile offsets along one axis (deduplicated for short periodic axes)
+__device__ __forceinline__ int axis_neighbours(int t, int T, int bc, int out[3]) {
+    int k = 0;
+    if (bc == RBFIB_PERIODIC) {
+        if (T >= 3) { out[k++] = (t + T - 1) % T; out[k++] = t; out[k++] = (t + 1) % T; }
+        else if (T == 2) { out[k++] = t; out[k++] = 1 - t; }
+        else out[k++] = t;
+    } else {
+        for (int o = -1; o <= 1; ++o) if (t + o >= 0 && t + o < T) out[k++] = t + o;
+    }
+    return k;
+}
+
+__global__ void k_tile_active(const RepDev *reps, const int *tile_rep, const int *count, int *flag, int ntiles) {
+    int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= ntiles) return;
+    const RepDev &R = reps[tile_rep[t]];
+    int lt = t - R.tile0;
+    int tc[3] = {lt % R.tdim[0], (lt / R.tdim[0]) % R.tdim[1], lt / (R.tdim[0] * R.tdim[1])};
+    int nb[3][3], k[3];
+    for (int a = 0; a < 3; ++a) k[a] = axis_neighbours(tc[a], R.tdim[a], R.bc[a], nb[a]);
+    int f = 0;
+    for (int z = 0; z < k[2] && !f; ++z)
+        for (int y = 0; y < k[1] && !f; ++y)
+            for (int x = 0; x < k[0] && !f; ++x)
+                if (count[R.tile0 + nb[0][x] + R.tdim[0] * (nb[1][y] + R.tdim[1] * nb[2][z])] > 0) f = 1;
+    flag[t] = f;
+}
+
+// stable compaction of flagged tiles (one workgroup)
+__global__ void k_compact(const int *flag, int *list, int *n_out, int ntiles) {
+    __shared__ int part[1024];
+    int per = (ntiles + blockDim.x - 1) / blockDim.x;
+    int b = threadIdx.x * per, e = min(ntiles, b + per);
+    int s = 0;
+    for (int i = b; i < e; ++i) s += flag[i];
+    part[threadIdx.x] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int acc = 0;
+        for (int i = 0; i < (int)blockDim.x; ++i) { int v = part[i]; part[i] = acc; acc += v; }
+        *n_out = acc;
+    }
+    __syncthreads();
+    int acc = part[threadIdx.x];
+    for (int i = b; i < e; ++i) if (flag[i]) list[acc++] = i;
+}
+
+void launch_markers(Ctx &c, MarkerSet &ms, const double *q, const double *theta) {
+    HIP_OK(hipMemsetAsync(ms.tile_count, 0, sizeof(int) * c.ntiles, c.stream));
+    int nb = (c.nm + 255) / 256;
+    if (c.nm > 0)
+        hipLaunchKernelGGL(k_markers, dim3(nb), dim3(256), 0, c.stream, c.d_reps, c.d_marker_body, c.d_body_rep, q,
+                           theta, c.d_rref, c.nm, ms.r, ms.d, ms.tile, ms.tile_count, c.d_flags);
+    hipLaunchKernelGGL(k_tile_scan, dim3(1), dim3(1024), 0, c.stream, ms.tile_count, ms.tile_start, ms.tile_fill,
+                       c.ntiles);
+    if (c.nm > 0) {
+        hipLaunchKernelGGL(k_tile_place, dim3(nb), dim3(256), 0, c.stream, ms.tile, ms.tile_start, ms.tile_fill,
+                           ms.perm, c.nm);
+        hipLaunchKernelGGL(k_tile_sort, dim3((c.ntiles + 255) / 256), dim3(256), 0, c.stream, ms.tile_start,
+                           ms.tile_count, ms.perm, c.ntiles);
+    }
+    hipLaunchKernelGGL(k_tile_active, dim3((c.ntiles + 255) / 256), dim3(256), 0, c.stream, c.d_reps, c.d_tile_rep,
+                       ms.tile_count, ms.flag, c.ntiles);
+    hipLaunchKernelGGL(k_compact, dim3(1), dim3(1024), 0, c.stream, ms.flag, ms.active, ms.n_active, c.ntiles);
+}
+
+// ------------------------------------------------------------------ kernel weights
+// 1-D folded weights of one marker coordinate for component c along axis a:
+// raw support base..base+3, folded index and signed weight (0 when dropped).
+__device__ __forceinline__ void axis_weights(const RepDev &R, double ra, int c, int a, int idx[4], double w[4],
+                                             int cross[4]) {
+    double s = ra * R.inv_h - (a == c ? 0.0 : 0.5);
+    int b = (int)floor(s) - 1;
+    for (int q = 0; q < 4; ++q) {
+        int p = b + q;
+        double sg;
+        bool ok = fold_index(p, R.n[a], R.bc[a], a == c, idx[q], sg, cross[q]);
+        w[q] = ok ? sg * phi4(s - (double)p) : 0.0;
+    }
+}
+
+// (J u)_c at marker position rm; u points at component c of the replica's fluid block.
+__device__ double interp_comp(const RepDev &R, const double *rm, int c, const double *u) {
+    int idx[3][4], cr[3][4];
+    double w[3][4];
+    for (int a = 0; a < 3; ++a) axis_weights(R, rm[a], c, a, idx[a], w[a], cr[a]);
+    double acc = 0.0;
+    for (int z = 0; z < 4; ++z) {
+        if (w[2][z] == 0.0) continue;
+        for (int y = 0; y < 4; ++y) {
+            double wzy = w[2][z] * w[1][y];
+            if (wzy == 0.0) continue;
+            long long row = (long long)R.n[0] * ((long long)idx[1][y] + (long long)R.n[1] * idx[2][z]);
+            for (int x = 0; x < 4; ++x) acc += wzy * w[0][x] * u[row + idx[0][x]];
+        }
+    }
+    return acc;
+}
+
+// ------------------------------------------------------------------ spreading (gather)
+#define SP_CHUNK 64
+__global__ __launch_bounds__(256) void k_spread(const RepDev *reps, const int *tile_rep, const int *active,
+                                                const int *n_active, const int *tile_start, const int *tile_count,
+                                                const int *perm, const double *__restrict__ r,
+                                                const double *__restrict__ lam_state, const int *marker_body,
+                                                const int *body_rep, double *__restrict__ y, double alpha) {
+    __shared__ double Wt[SP_CHUNK][3][3][4];
+    __shared__ double Ls[SP_CHUNK][3];
+    __shared__ int Ms[SP_CHUNK];
+    __shared__ int nstart[27], ncnt[27], npre[28];
+    __shared__ int nn;
+    int tid = threadIdx.x;
+    int na = *n_active;
+    for (int it = blockIdx.x; it < na; it += gridDim.x) {
+        int t = active[it];
+        const RepDev &R = reps[tile_rep[t]];
+        int lt = t - R.tile0;
+        int tc[3] = {lt % R.tdim[0], (lt / R.tdim[0]) % R.tdim[1], lt / (R.tdim[0] * R.tdim[1])};
+        if (tid == 0) {
+            int nb[3][3], k[3];
+            for (int a = 0; a < 3; ++a) k[a] = axis_neighbours(tc[a], R.tdim[a], R.bc[a], nb[a]);
+            int cnt = 0;
+            npre[0] = 0;
+            for (int z = 0; z < k[2]; ++z)
+                for (int yy = 0; yy < k[1]; ++yy)
+                    for (int x = 0; x < k[0]; ++x) {
+                        int g = R.tile0 + nb[0][x] + R.tdim[0] * (nb[1][yy] + R.tdim[1] * nb[2][z]);
+                        nstart[cnt] = tile_start[g];
+                        ncnt[cnt] = tile_count[g];
+                        npre[cnt + 1] = npre[cnt] + ncnt[cnt];
+                        ++cnt;
+                    }
+            nn = cnt;
+        }
+        __syncthreads();
+        int M = npre[nn];
+        int c = tid >> 6, lx = tid & 3, ly = (tid >> 2) & 3, lz = (tid >> 4) & 3;
+        double acc = 0.0;
+        for (int base = 0; base < M; base += SP_CHUNK) {
+            int cnt = min(SP_CHUNK, M - base);
+            if (tid < cnt) {
+                int pos = base + tid;
+                int k = 0;
+                while (npre[k + 1] <= pos) ++k;
+                int m = perm[nstart[k] + pos - npre[k]];
+                Ms[tid] = m;
+            }
+            __syncthreads();
+            for (int task = tid; task < cnt * 9; task += blockDim.x) {
+                int j = task / 9, ca = task % 9, cc = ca / 3, a = ca % 3;
+                int m = Ms[j];
+                int idx[4], cr[4];
+                double w[4];
+                axis_weights(R, r[3 * m + a], cc, a, idx, w, cr);
+                double o[4] = {0.0, 0.0, 0.0, 0.0};
+                int t0 = 4 * tc[a];
+                for (int q = 0; q < 4; ++q) {
+                    int loc = idx[q] - t0;
+                    if (w[q] != 0.0 && loc >= 0 && loc < 4) o[loc] += w[q];
+                }
+                for (int q = 0; q < 4; ++q) Wt[j][cc][a][q] = o[q];
+            }
+            for (int task = tid; task < cnt * 3; task += blockDim.x) {
+                int j = task / 3, cc = task % 3;
+                int m = Ms[j];
+                const RepDev &Rm = reps[body_rep[marker_body[m]]];
+                Ls[j][cc] = lam_state[Rm.off + 4 * Rm.N + 3LL * (m - Rm.m0) + cc];
+            }
+            __syncthreads();
+            if (tid < 192) {
+                for (int j = 0; j < cnt; ++j)
+                    acc += Wt[j][c][0][lx] * Wt[j][c][1][ly] * Wt[j][c][2][lz] * Ls[j][c];
+            }
+            __syncthreads();
+        }
+        if (tid < 192 && M > 0) {
+            int g[3] = {4 * tc[0] + lx, 4 * tc[1] + ly, 4 * tc[2] + lz};
+            bool in = g[0] < R.n[0] && g[1] < R.n[1] && g[2] < R.n[2];
+            bool pin = R.bc[c] == RBFIB_WALL && g[c] == 0;
+            if (in && !pin) {
+                long long lin = (long long)g[0] + (long long)R.n[0] * ((long long)g[1] + (long long)R.n[1] * g[2]);
+                y[R.off + c * R.N + lin] += alpha * acc / R.dV;
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// y_fluid += alpha * S lambda, lambda read from the lambda slots of lam_state.
+void launch_spread(Ctx &c, MarkerSet &ms, const double *lam_state, double *y, double alpha) {
+    if (c.nm == 0) return;
+    int grid = std::min(c.ntiles, 2048);
+    hipLaunchKernelGGL(k_spread, dim3(grid), dim3(256), 0, c.stream, c.d_reps, c.d_tile_rep, ms.active, ms.n_active,
+                       ms.tile_start, ms.tile_count, ms.perm, ms.r, lam_state, c.d_marker_body, c.d_body_rep, y,
+                       alpha);
+}
+
+// ------------------------------------------------------------------ J, K, K^T per body
+// y_lambda = -J v + K U ;  y_U = K^T lambda  (rows 3 and 4 of the saddle operator).
+__global__ void k_body_apply(const RepDev *reps, const int *body_rep, const int *body_off, const double *r,
+                             const double *d, const double *__restrict__ x, double *__restrict__ y) {
+    extern __shared__ double sred[];   // [nmp][6]
+    int p = blockIdx.x;
+    const RepDev &R = reps[body_rep[p]];
+    int m0 = body_off[p], m1 = body_off[p + 1], nmp = m1 - m0;
+    long long lam0 = R.off + 4 * R.N;
+    long long U0 = lam0 + 3LL * R.nm + 6LL * (p - R.b0);
+    double U[6];
+    for (int k = 0; k < 6; ++k) U[k] = x[U0 + k];
+    for (int task = threadIdx.x; task < 3 * nmp; task += blockDim.x) {
+        int i = task / 3, c = task % 3, m = m0 + i;
+        double Jv = interp_comp(R, r + 3 * m, c, x + R.off + c * R.N);
+        const double *dm = d + 3 * m;
+        double wxd[3] = {U[4] * dm[2] - U[5] * dm[1], U[5] * dm[0] - U[3] * dm[2], U[3] * dm[1] - U[4] * dm[0]};
+        y[lam0 + 3LL * (m - R.m0) + c] = -Jv + U[c] + wxd[c];
+    }
+    for (int i = threadIdx.x; i < nmp; i += blockDim.x) {
+        int m = m0 + i;
+        const double *l = x + lam0 + 3LL * (m - R.m0);
+        const double *dm = d + 3 * m;
+        sred[6 * i + 0] = l[0];
+        sred[6 * i + 1] = l[1];
+        sred[6 * i + 2] = l[2];
+        sred[6 * i + 3] = dm[1] * l[2] - dm[2] * l[1];
+        sred[6 * i + 4] = dm[2] * l[0] - dm[0] * l[2];
+        sred[6 * i + 5] = dm[0] * l[1] - dm[1] * l[0];
+    }
+    __syncthreads();
+    if (threadIdx.x < 6) {
+        double s = 0.0;
+        for (int i = 0; i < nmp; ++i) s += sred[6 * i + threadIdx.x];
+        y[U0 + threadIdx.x] = s;
+    }
+}
+
+void launch_body_apply(Ctx &c, MarkerSet &ms, const double *q, const double *x, double *y) {
+    (void)q;
+    if (c.nb == 0) return;
+    size_t sh = sizeof(double) * 6 * (size_t)c.max_body_nm;
+    hipLaunchKernelGGL(k_body_apply, dim3(c.nb), dim3(128), sh, c.stream, c.d_reps, c.d_body_rep, c.d_body_off, ms.r,
+                       ms.d, x, y);
+}
+
+// ------------------------------------------------------------------ interpolation
+// out[m, c] (= or +=) alpha * (J u)_c at markers of ms; u is a state vector.
+__global__ void k_interp(const RepDev *reps, const int *marker_body, const int *body_rep, const double *r, int nm,
+                         const double *__restrict__ u, double *__restrict__ out, double alpha, int accumulate) {
+    int task = blockIdx.x * blockDim.x + threadIdx.x;
+    if (task >= 3 * nm) return;
+    int m = task / 3, c = task % 3;
+    const RepDev &R = reps[body_rep[marker_body[m]]];
+    double v = alpha * interp_comp(R, r + 3 * m, c, u + R.off + c * R.N);
+    if (accumulate) out[task] += v; else out[task] = v;
+}
+
+void launch_interp(Ctx &c, MarkerSet &ms, const double *u, double *out, double alpha, bool accumulate) {
+    if (c.nm == 0) return;
+    hipLaunchKernelGGL(k_interp, dim3((3 * c.nm + 255) / 256), dim3(256), 0, c.stream, c.d_reps, c.d_marker_body,
+                       c.d_body_rep, ms.r, c.nm, u, out, alpha, accumulate ? 1 : 0);
+}
+
+// Affine part of interpolation next to sliding walls: for each support point across a
+// wall moving with tangential velocity U (component c), add w * 2U * (product of the
+// signs of the point's other reflections).  out[m, c] += alpha * J_bc.
+__global__ void k_interp_bc(const RepDev *reps, const int *marker_body, const int *body_rep, const double *r, int nm,
+                            double *__restrict__ out, double alpha) {
+    int task = blockIdx.x * blockDim.x + threadIdx.x;
+    if (task >= 3 * nm) return;
+    int m = task / 3, c = task % 3;
+    const RepDev &R = reps[body_rep[marker_body[m]]];
+    if (!R.movwall) return;
+    int idx[3][4], cr[3][4];
+    double w[3][4];
+    for (int a = 0; a < 3; ++a) axis_weights(R, r[3 * m + a], c, a, idx[a], w[a], cr[a]);
+    double acc = 0.0;
+    for (int z = 0; z < 4; ++z)
+        for (int y = 0; y < 4; ++y)
+            for (int x = 0; x < 4; ++x) {
+                double wt = w[0][x] * w[1][y] * w[2][z];
+                if (wt == 0.0) continue;
+                int crs[3] = {cr[0][x], cr[1][y], cr[2][z]};
+                // w carries the product of all reflection signs; divide out the one of
+                // the moving wall itself (multiply by -1 again) to keep the others'.
+                double aff = 0.0;
+                for (int a = 0; a < 3; ++a) {
+                    if (a == c || crs[a] == 0 || R.bc[a] != RBFIB_WALL) continue;
+                    double U = R.wv[a][crs[a] - 1][c];
+                    if (U != 0.0) aff += -2.0 * U;
+                }
+                acc += wt * aff;
+            }
+    out[task] += alpha * acc;
+}
+
+void launch_interp_bc(Ctx &c, MarkerSet &ms, double *out, double alpha) {
+    if (c.nm == 0) return;
+    hipLaunchKernelGGL(k_interp_bc, dim3((3 * c.nm + 255) / 256), dim3(256), 0, c.stream, c.d_reps, c.d_marker_body,
+                       c.d_body_rep, ms.r, c.nm, out, alpha);
+}
+
+// ------------------------------------------------------------------ body block of P^-1
+// Per body, in the body frame (rotation by R^T): U' = N (r_U' + K^T Minv g'),
+// lambda' = Minv K U' - Minv g', with Minv the inverse blob mobility of the
+// reference body; rotated back to the lab frame.
+__global__ void k_body_precond(const RepDev *reps, const int *body_rep, const int *body_off, const int *body_shape,
+                               const ShapeDev *shapes, const double *sdata, const double *theta,
+                               const double *__restrict__ rin, double *__restrict__ z) {
+    extern __shared__ double sm[];
+    int p = blockIdx.x;
+    const RepDev &R = reps[body_rep[p]];
+    const ShapeDev &S = shapes[body_shape[p]];
+    int m0 = body_off[p], n3 = 3 * S.nm;
+    double *g = sm;            // [n3]
+    double *a = sm + n3;       // [n3]
+    double *b6 = sm + 2 * n3;  // [6]  body-frame rhs
+    double *U6 = b6 + 6;       // [6]
+    double Rm[9];
+    quat_to_R(theta + 4 * p, Rm);
+    long long lam0 = R.off + 4 * R.N + 3LL * (m0 - R.m0);
+    long long U0 = R.off + 4 * R.N + 3LL * R.nm + 6LL * (p - R.b0);
+    for (int i = threadIdx.x; i < S.nm; i += blockDim.x) {
+        const double *v = rin + lam0 + 3 * i;
+        for (int k = 0; k < 3; ++k) g[3 * i + k] = Rm[k] * v[0] + Rm[3 + k] * v[1] + Rm[6 + k] * v[2];
+    }
+    if (threadIdx.x < 2) {
+        const double *v = rin + U0 + 3 * threadIdx.x;
+        for (int k = 0; k < 3; ++k) b6[3 * threadIdx.x + k] = Rm[k] * v[0] + Rm[3 + k] * v[1] + Rm[6 + k] * v[2];
+    }
+    __syncthreads();
+    const double *Minv = sdata + S.minv_off;
+    for (int k = threadIdx.x; k < n3; k += blockDim.x) {
+        double s = 0.0;
+        const double *row = Minv + (long long)k * n3;
+        for (int j = 0; j < n3; ++j) s += row[j] * g[j];
+        a[k] = s;
+    }
+    __syncthreads();
+    const double *rr = sdata + S.rref_off;
+    if (threadIdx.x < 6) {
+        int k = threadIdx.x;
+        double s = 0.0;
+        for (int i = 0; i < S.nm; ++i) {
+            const double *ai = a + 3 * i;
+            const double *ri = rr + 3 * i;
+            double v;
+            if (k < 3) v = ai[k];
+            else if (k == 3) v = ri[1] * ai[2] - ri[2] * ai[1];
+            else if (k == 4) v = ri[2] * ai[0] - ri[0] * ai[2];
+            else v = ri[0] * ai[1] - ri[1] * ai[0];
+            s += v;
+        }
+        b6[k] += s;
+    }
+    __syncthreads();
+    if (threadIdx.x < 6) {
+        const double *Nm = sdata + S.n_off;
+        double s = 0.0;
+        for (int l = 0; l < 6; ++l) s += Nm[6 * threadIdx.x + l] * b6[l];
+        U6[threadIdx.x] = s;
+    }
+    __syncthreads();
+    const double *MK = sdata + S.mk_off;
+    for (int k = threadIdx.x; k < n3; k += blockDim.x) {
+        double s = 0.0;
+        for (int l = 0; l < 6; ++l) s += MK[6 * k + l] * U6[l];
+        g[k] = s - a[k];       // lambda' (body frame), reuse g
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < S.nm; i += blockDim.x) {
+        const double *v = g + 3 * i;
+        double *o = z + lam0 + 3 * i;
+        for (int k = 0; k < 3; ++k) o[k] = Rm[3 * k] * v[0] + Rm[3 * k + 1] * v[1] + Rm[3 * k + 2] * v[2];
+    }
+    if (threadIdx.x < 2) {
+        const double *v = U6 + 3 * threadIdx.x;
+        double *o = z + U0 + 3 * threadIdx.x;
+        for (int k = 0; k < 3; ++k) o[k] = Rm[3 * k] * v[0] + Rm[3 * k + 1] * v[1] + Rm[3 * k + 2] * v[2];
+    }
+}
+
+void launch_body_precond(Ctx &c, MarkerSet &ms, const double *theta, const double *r, double *z) {
+    (void)ms;
+    if (c.nb == 0) return;
+    size_t sh = sizeof(double) * (size_t)(6 * c.max_body_nm + 12);
+    hipLaunchKernelGGL(k_body_precond, dim3(c.nb), dim3(128), sh, c.stream, c.d_reps, c.d_body_rep, c.d_body_off,
+                       c.d_body_shape, c.d_shapes, c.d_shape_data, theta, r, z);
+}
+
+// ------------------------------------------------------------------ small helpers
+// zero the lambda and U slots of every replica
+__global__ void k_zero_bodies(const RepDev *reps, int nrep, double *y) {
+    int r = blockIdx.y;
+    if (r >= nrep) return;
+    const RepDev &R = reps[r];
+    long long n = 3LL * R.nm + 6LL * R.nb;
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+        y[R.off + 4 * R.N + i] = 0.0;
+}
+
+void launch_zero_bodies(Ctx &c, double *y) {
+    hipLaunchKernelGGL(k_zero_bodies, dim3(4, c.nrep), dim3(256), 0, c.stream, c.d_reps, c.nrep, y);
+}
+
+// b = [0 ; 0 ; -slip ; FT]  (fluid rows zeroed; boundary terms added separately)
+__global__ void k_set_rhs_bodies(const RepDev *reps, const int *marker_body, const int *body_rep, int nm, int nb,
+                                 const double *FT, const double *slip, double *b) {
+    int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < 3 * nm) {
+        int m = t / 3, c = t % 3;
+        const RepDev &R = reps[body_rep[marker_body[m]]];
+        b[R.off + 4 * R.N + 3LL * (m - R.m0) + c] = slip ? -slip[t] : 0.0;
+    }
+    if (t < 6 * nb) {
+        int p = t / 6, k = t % 6;
+        const RepDev &R = reps[body_rep[p]];
+        b[R.off + 4 * R.N + 3LL * R.nm + 6LL * (p - R.b0) + k] = FT ? FT[t] : 0.0;
+    }
+}
+
+void launch_set_rhs(Ctx &c, const double *FT, const double *slip, double *b) {
+    int n = std::max(3 * c.nm, 6 * c.nb);
+    if (n == 0) return;
+    hipLaunchKernelGGL(k_set_rhs_bodies, dim3((n + 255) / 256), dim3(256), 0, c.stream, c.d_reps, c.d_marker_body,
+                       c.d_body_rep, c.nm, c.nb, FT, slip, b);
+}
+
+// U[p] = scale * x_U[p]
+__global__ void k_copy_U(const RepDev *reps, const int *body_rep, int nb, const double *x, double *U, double scale) {
+    int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= 6 * nb) return;
+    int p = t / 6, k = t % 6;
+    const RepDev &R = reps[body_rep[p]];
+    U[t] = scale * x[R.off + 4 * R.N + 3LL * R.nm + 6LL * (p - R.b0) + k];
+}
+
+void launch_copy_U(Ctx &c, const double *x, double *U, double scale) {
+    if (c.nb == 0) return;
+    hipLaunchKernelGGL(k_copy_U, dim3((6 * c.nb + 255) / 256), dim3(256), 0, c.stream, c.d_reps, c.d_body_rep, c.nb,
+                       x, U, scale);
+}
+
+}  // namespace rb

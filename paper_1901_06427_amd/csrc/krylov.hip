@@ -1,0 +1,259 @@
+// Flexible GMRES building blocks, batched over independent replicas.
+// Every replica owns a contiguous segment of each state vector; blocks are
+// replica-aligned chunks of RB_CHUNK elements, so per-replica dot products are
+// block partial sums reduced in a fixed order (deterministic, no atomics).
+// Hessenberg, Givens rotations and the least-squares solve live on the device,
+// one thread per replica.
+#include "common.h"
+
+namespace rb {
+
+__device__ __forceinline__ double block_sum(double v, double *sh) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+    int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0) sh[wid] = v;
+    __syncthreads();
+    double s = 0.0;
+    if (threadIdx.x == 0) {
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) s += sh[w];
+    }
+    __syncthreads();
+    return s;   // valid in thread 0
+}
+
+// partial[blk * stride + i] = sum over the block's chunk of V_i . w
+__global__ __launch_bounds__(RB_BLOCK) void k_dot_partial(const RepDev *reps, const BlockEnt *tab, const double *V,
+                                                          long long L, int nvec, const double *__restrict__ w,
+                                                          double *partial, int stride, const int *mask) {
+    __shared__ double sh[8];
+    BlockEnt be = tab[blockIdx.x];
+    if (mask && !mask[be.rep]) return;
+    const RepDev &R = reps[be.rep];
+    long long b = R.off + be.start;
+    long long e = R.off + min(be.start + (long long)RB_CHUNK, R.len);
+    double wv[RB_CHUNK / RB_BLOCK];
+#pragma unroll
+    for (int k = 0; k < RB_CHUNK / RB_BLOCK; ++k) {
+        long long g = b + threadIdx.x + (long long)k * RB_BLOCK;
+        wv[k] = (g < e) ? w[g] : 0.0;
+    }
+    for (int i = 0; i < nvec; ++i) {
+        const double *Vi = V + (long long)i * L;
+        double acc = 0.0;
+#pragma unroll
+        for (int k = 0; k < RB_CHUNK / RB_BLOCK; ++k) {
+            long long g = b + threadIdx.x + (long long)k * RB_BLOCK;
+            if (g < e) acc += Vi[g] * wv[k];
+        }
+        double s = block_sum(acc, sh);
+        if (threadIdx.x == 0) partial[(long long)blockIdx.x * stride + i] = s;
+    }
+}
+
+__global__ void k_dot_reduce(const int *first, const int *nblk, int nvec, const double *partial, int stride,
+                             double *out, int out_stride, const int *mask, int take_sqrt) {
+    int r = blockIdx.x;
+    if (mask && !mask[r]) return;
+    for (int i = threadIdx.x; i < nvec; i += blockDim.x) {
+        double s = 0.0;
+        for (int b = 0; b < nblk[r]; ++b) s += partial[(long long)(first[r] + b) * stride + i];
+        out[(long long)r * out_stride + i] = take_sqrt ? sqrt(s) : s;
+    }
+}
+
+void launch_dots(Ctx &c, const double *V, int nvec, const double *w, double *out, const int *mask) {
+    int stride = c.m + 1;
+    hipLaunchKernelGGL(k_dot_partial, dim3(c.n_tab_vec), dim3(RB_BLOCK), 0, c.stream, c.d_reps, c.d_tab_vec, V, c.L,
+                       nvec, w, c.partial, stride, mask);
+    hipLaunchKernelGGL(k_dot_reduce, dim3(c.nrep), dim3(64), 0, c.stream, c.d_vec_first, c.d_vec_nblk, nvec,
+                       c.partial, stride, out, c.m + 1, mask, 0);
+}
+
+void launch_norm(Ctx &c, const double *w, double *out, const int *mask) {
+    int stride = c.m + 1;
+    hipLaunchKernelGGL(k_dot_partial, dim3(c.n_tab_vec), dim3(RB_BLOCK), 0, c.stream, c.d_reps, c.d_tab_vec, w, c.L,
+                       1, w, c.partial, stride, mask);
+    hipLaunchKernelGGL(k_dot_reduce, dim3(c.nrep), dim3(64), 0, c.stream, c.d_vec_first, c.d_vec_nblk, 1, c.partial,
+                       stride, out, 1, mask, 1);
+}
+
+// w += sign * sum_i coef[r][i] V_i
+__global__ __launch_bounds__(RB_BLOCK) void k_axpy_multi(const RepDev *reps, const BlockEnt *tab, const double *V,
+                                                         long long L, int nvec, const double *coef, int cstride,
+                                                         double *__restrict__ w, double sign, const int *mask) {
+    BlockEnt be = tab[blockIdx.x];
+    if (mask && !mask[be.rep]) return;
+    const RepDev &R = reps[be.rep];
+    long long b = R.off + be.start;
+    long long e = R.off + min(be.start + (long long)RB_CHUNK, R.len);
+    const double *cf = coef + (long long)be.rep * cstride;
+    for (int k = 0; k < RB_CHUNK / RB_BLOCK; ++k) {
+        long long g = b + threadIdx.x + (long long)k * RB_BLOCK;
+        if (g >= e) break;
+        double acc = 0.0;
+        for (int i = 0; i < nvec; ++i) acc += cf[i] * V[(long long)i * L + g];
+        w[g] += sign * acc;
+    }
+}
+
+void launch_axpy_multi(Ctx &c, const double *V, int nvec, const double *coef, double *w, double sign, const int *mask) {
+    hipLaunchKernelGGL(k_axpy_multi, dim3(c.n_tab_vec), dim3(RB_BLOCK), 0, c.stream, c.d_reps, c.d_tab_vec, V, c.L,
+                       nvec, coef, c.m + 1, w, sign, mask);
+}
+
+// out = w * s[r]  (or w / s[r] when inverse; a zero divisor leaves out unchanged)
+__global__ void k_scale(const RepDev *reps, const BlockEnt *tab, const double *w, const double *s, int sstride,
+                        double *out, const int *mask, int inverse) {
+    BlockEnt be = tab[blockIdx.x];
+    if (mask && !mask[be.rep]) return;
+    const RepDev &R = reps[be.rep];
+    double f = s[(long long)be.rep * sstride];
+    if (inverse) {
+        if (f == 0.0) return;
+        f = 1.0 / f;
+    }
+    long long b = R.off + be.start;
+    long long e = R.off + min(be.start + (long long)RB_CHUNK, R.len);
+    for (long long g = b + threadIdx.x; g < e; g += RB_BLOCK) out[g] = w[g] * f;
+}
+
+void launch_scale(Ctx &c, const double *w, const double *s, double *out, const int *mask, bool inverse) {
+    hipLaunchKernelGGL(k_scale, dim3(c.n_tab_vec), dim3(RB_BLOCK), 0, c.stream, c.d_reps, c.d_tab_vec, w, s, 1, out,
+                       mask, inverse ? 1 : 0);
+}
+
+__global__ void k_axpby(const RepDev *reps, const BlockEnt *tab, double a, const double *x, double b,
+                        const double *y, double *out, const int *mask) {
+    BlockEnt be = tab[blockIdx.x];
+    if (mask && !mask[be.rep]) return;
+    const RepDev &R = reps[be.rep];
+    long long s = R.off + be.start;
+    long long e = R.off + min(be.start + (long long)RB_CHUNK, R.len);
+    for (long long g = s + threadIdx.x; g < e; g += RB_BLOCK) {
+        double v = (a == 0.0 ? 0.0 : a * x[g]);
+        if (b != 0.0) v += b * y[g];
+        out[g] = v;
+    }
+}
+
+void launch_axpby(Ctx &c, double a, const double *x, double b, const double *y, double *out, const int *mask) {
+    hipLaunchKernelGGL(k_axpby, dim3(c.n_tab_vec), dim3(RB_BLOCK), 0, c.stream, c.d_reps, c.d_tab_vec, a, x, b, y,
+                       out, mask);
+}
+
+void launch_copy(Ctx &c, const double *x, double *y, const int *mask) { launch_axpby(c, 1.0, x, 0.0, x, y, mask); }
+void launch_zero(Ctx &c, double *y, const int *mask) { launch_axpby(c, 0.0, y, 0.0, y, y, mask); }
+
+// Arnoldi column j: H[:, j] = h1 + h2 (two Gram-Schmidt passes), H[j+1, j] = ||w||;
+// apply the stored rotations, form the new one, update g and the convergence state.
+__global__ void k_givens(int nrep, int m, int j, double tol, const double *h1, const double *h2, const double *nrm,
+                         double *H, double *cs, double *sn, double *gv, const double *beta0, int *active,
+                         int *jf, int *status, int *iters) {
+    int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= nrep || !active[r]) return;
+    double *Hc = H + (long long)r * (m + 1) * m + (long long)j * (m + 1);
+    double *c = cs + (long long)r * m, *s = sn + (long long)r * m, *g = gv + (long long)r * (m + 1);
+    for (int i = 0; i <= j; ++i) Hc[i] = h1[(long long)r * (m + 1) + i] + h2[(long long)r * (m + 1) + i];
+    double hn = nrm[r];
+    Hc[j + 1] = hn;
+    for (int i = 0; i < j; ++i) {
+        double t = c[i] * Hc[i] + s[i] * Hc[i + 1];
+        Hc[i + 1] = -s[i] * Hc[i] + c[i] * Hc[i + 1];
+        Hc[i] = t;
+    }
+    double den = hypot(Hc[j], Hc[j + 1]);
+    double cj = den > 0.0 ? Hc[j] / den : 1.0;
+    double sj = den > 0.0 ? Hc[j + 1] / den : 0.0;
+    c[j] = cj;
+    s[j] = sj;
+    Hc[j] = den;
+    Hc[j + 1] = 0.0;
+    g[j + 1] = -sj * g[j];
+    g[j] = cj * g[j];
+    iters[r] += 1;
+    double res = fabs(g[j + 1]);
+    if (!isfinite(res) || !isfinite(den)) {
+        status[r] = RBFIB_ENUMERIC;
+        active[r] = 0;
+        jf[r] = j;
+        return;
+    }
+    if (res <= tol * beta0[r] || hn == 0.0) {
+        active[r] = 0;
+        jf[r] = j + 1;
+        status[r] = RBFIB_OK;
+    } else if (j + 1 == m) {
+        jf[r] = m;
+    }
+}
+
+void launch_givens(Ctx &c, int j, double tol) {
+    double *h1 = c.hcol, *h2 = c.hcol + (long long)c.nrep * (c.m + 1), *nrm = c.hcol + 2LL * c.nrep * (c.m + 1);
+    hipLaunchKernelGGL(k_givens, dim3((c.nrep + 63) / 64), dim3(64), 0, c.stream, c.nrep, c.m, j, tol, h1, h2, nrm,
+                       c.H, c.cs, c.sn, c.gv, c.beta0, c.active, c.jf, c.status, c.iters);
+}
+
+// Back substitution H[0:jf, 0:jf] y = g[0:jf] for replicas active at cycle start.
+__global__ void k_trisolve(int nrep, int m, const double *H, const double *gv, const int *cyc, const int *jf,
+                           double *y) {
+    int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= nrep || !cyc[r]) return;
+    int n = jf[r];
+    const double *Hr = H + (long long)r * (m + 1) * m;
+    const double *g = gv + (long long)r * (m + 1);
+    double *yr = y + (long long)r * (m + 1);
+    for (int i = n - 1; i >= 0; --i) {
+        double s = g[i];
+        for (int k = i + 1; k < n; ++k) s -= Hr[(long long)k * (m + 1) + i] * yr[k];
+        double d = Hr[(long long)i * (m + 1) + i];
+        yr[i] = d != 0.0 ? s / d : 0.0;
+    }
+    for (int i = n; i < m; ++i) yr[i] = 0.0;
+}
+
+// x += sum_{i < jf} y_i Z_i
+__global__ __launch_bounds__(RB_BLOCK) void k_update_x(const RepDev *reps, const BlockEnt *tab, const double *Z,
+                                                       long long L, int m, const double *y, const int *jf,
+                                                       const int *cyc, double *x) {
+    BlockEnt be = tab[blockIdx.x];
+    if (!cyc[be.rep]) return;
+    const RepDev &R = reps[be.rep];
+    int n = jf[be.rep];
+    const double *yr = y + (long long)be.rep * (m + 1);
+    long long b = R.off + be.start;
+    long long e = R.off + min(be.start + (long long)RB_CHUNK, R.len);
+    for (long long g = b + threadIdx.x; g < e; g += RB_BLOCK) {
+        double acc = 0.0;
+        for (int i = 0; i < n; ++i) acc += yr[i] * Z[(long long)i * L + g];
+        x[g] += acc;
+    }
+}
+
+void launch_trisolve_update(Ctx &c) {
+    hipLaunchKernelGGL(k_trisolve, dim3((c.nrep + 63) / 64), dim3(64), 0, c.stream, c.nrep, c.m, c.H, c.gv,
+                       c.cyc_active, c.jf, c.yv);
+    hipLaunchKernelGGL(k_update_x, dim3(c.n_tab_vec), dim3(RB_BLOCK), 0, c.stream, c.d_reps, c.d_tab_vec, c.Z, c.L,
+                       c.m, c.yv, c.jf, c.cyc_active, c.xsol);
+}
+
+// Start of a restart cycle for active replicas: g = (beta, 0, ...), jf = 0; beta in nrm slot.
+__global__ void k_start_cycle(int nrep, int m, const double *beta, double *gv, int *active, int *jf, int *cyc,
+                              int *status) {
+    int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= nrep) return;
+    cyc[r] = active[r];
+    if (!active[r]) return;
+    double *g = gv + (long long)r * (m + 1);
+    g[0] = beta[r];
+    for (int i = 1; i <= m; ++i) g[i] = 0.0;
+    jf[r] = 0;
+    if (!isfinite(beta[r])) { status[r] = RBFIB_ENUMERIC; active[r] = 0; cyc[r] = 0; }
+}
+
+void launch_start_cycle(Ctx &c) {
+    double *nrm = c.hcol + 2LL * c.nrep * (c.m + 1);
+    hipLaunchKernelGGL(k_start_cycle, dim3((c.nrep + 63) / 64), dim3(64), 0, c.stream, c.nrep, c.m, nrm, c.gv,
+                       c.active, c.jf, c.cyc_active, c.status);
+}
+
+}  // namespace rb

@@ -1,0 +1,964 @@
+// Host side of the RB-FIB library: context construction (multigrid hierarchy,
+// block tables, dense coarsest-level inverses, body-block data), the batched
+// right-preconditioned FGMRES driver, the preconditioner and operator sequences,
+// and the C ABI declared in include/rbfib.h.
+#include "common.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+static thread_local std::string g_last_error;
+
+void rb_last_hip_error(hipError_t e, const char *what, const char *file, int line) {
+    g_last_error = std::string(hipGetErrorString(e)) + " in " + what + " at " + file + ":" + std::to_string(line);
+}
+
+struct rbfib_ctx {
+    rb::Ctx c;
+};
+
+namespace rb {
+
+// ------------------------------------------------------------------ small host linear algebra
+// In-place Gauss-Jordan inverse with partial pivoting (n <= ~1000).
+static bool invert(std::vector<double> &A, int n) {
+    std::vector<int> piv(n);
+    std::vector<double> inv(n * (size_t)n, 0.0);
+    for (int i = 0; i < n; ++i) inv[(size_t)i * n + i] = 1.0;
+    for (int col = 0; col < n; ++col) {
+        int best = col;
+        double bv = std::fabs(A[(size_t)col * n + col]);
+        for (int r = col + 1; r < n; ++r) {
+            double v = std::fabs(A[(size_t)r * n + col]);
+            if (v > bv) { bv = v; best = r; }
+        }
+        if (bv == 0.0) return false;
+        if (best != col) {
+            for (int k = 0; k < n; ++k) {
+                std::swap(A[(size_t)col * n + k], A[(size_t)best * n + k]);
+                std::swap(inv[(size_t)col * n + k], inv[(size_t)best * n + k]);
+            }
+        }
+        double d = 1.0 / A[(size_t)col * n + col];
+        for (int k = 0; k < n; ++k) { A[(size_t)col * n + k] *= d; inv[(size_t)col * n + k] *= d; }
+        for (int r = 0; r < n; ++r) {
+            if (r == col) continue;
+            double f = A[(size_t)r * n + col];
+            if (f == 0.0) continue;
+            for (int k = 0; k < n; ++k) {
+                A[(size_t)r * n + k] -= f * A[(size_t)col * n + k];
+                inv[(size_t)r * n + k] -= f * inv[(size_t)col * n + k];
+            }
+        }
+    }
+    A.swap(inv);
+    return true;
+}
+
+// Dense inverse of A = s * Lap on a coarsest grid (component comp, or 3 = pressure),
+// padded layout; pinned wall-face slots get zero rows and columns.  The pressure
+// operator is singular (constants); its inverse is taken on the mean-zero subspace
+// via the matrix bordered by the mean constraint.
+static std::vector<double> coarse_inverse(const int n[3], const double ih2[3], const int bc[3], double eta, int comp) {
+    int m = n[0] * n[1] * n[2];
+    std::vector<int> map(m, -1);
+    int nu = 0;
+    for (int k = 0; k < n[2]; ++k)
+        for (int j = 0; j < n[1]; ++j)
+            for (int i = 0; i < n[0]; ++i) {
+                int idx[3] = {i, j, k};
+                bool pin = comp < 3 && bc[comp] == RBFIB_WALL && idx[comp] == 0;
+                if (!pin) map[i + n[0] * (j + n[1] * k)] = nu++;
+            }
+    bool singular = (comp == 3);
+    int nn = nu + (singular ? 1 : 0);
+    std::vector<double> A((size_t)nn * nn, 0.0);
+    double s = comp < 3 ? -eta : -1.0;
+    for (int k = 0; k < n[2]; ++k)
+        for (int j = 0; j < n[1]; ++j)
+            for (int i = 0; i < n[0]; ++i) {
+                int idx[3] = {i, j, k};
+                int row = map[i + n[0] * (j + n[1] * k)];
+                if (row < 0) continue;
+                for (int a = 0; a < 3; ++a) {
+                    A[(size_t)row * nn + row] += -2.0 * s * ih2[a];
+                    for (int d = -1; d <= 1; d += 2) {
+                        int q[3] = {idx[0], idx[1], idx[2]};
+                        q[a] += d;
+                        if (bc[a] == RBFIB_PERIODIC) {
+                            q[a] = (q[a] + n[a]) % n[a];
+                        } else if (a == comp) {
+                            if (q[a] <= 0 || q[a] >= n[a]) continue;
+                        } else if (q[a] < 0 || q[a] >= n[a]) {
+                            A[(size_t)row * nn + row] += (comp == 3 ? 1.0 : -1.0) * s * ih2[a];
+                            continue;
+                        }
+                        int col = map[q[0] + n[0] * (q[1] + n[1] * q[2])];
+                        if (col >= 0) A[(size_t)row * nn + col] += s * ih2[a];
+                    }
+                }
+            }
+    if (singular) {
+        for (int r = 0; r < nu; ++r) { A[(size_t)r * nn + nu] = 1.0; A[(size_t)nu * nn + r] = 1.0; }
+    }
+    if (!invert(A, nn)) throw (int)RBFIB_EINVAL;
+    std::vector<double> out((size_t)m * m, 0.0);
+    for (int r = 0; r < m; ++r) {
+        if (map[r] < 0) continue;
+        for (int cc = 0; cc < m; ++cc) {
+            if (map[cc] < 0) continue;
+            out[(size_t)r * m + cc] = A[(size_t)map[r] * nn + map[cc]];
+        }
+    }
+    return out;
+}
+
+// Rotne-Prager-Yamakawa blob mobility (free space), only used to build the body block
+// of the preconditioner.
+static std::vector<double> rpy_matrix(const double *x, int n, double a, double eta) {
+    std::vector<double> M((size_t)9 * n * n, 0.0);
+    double c0 = 1.0 / (6.0 * M_PI * eta * a);
+    int N3 = 3 * n;
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) {
+            double d[3] = {x[3 * i] - x[3 * j], x[3 * i + 1] - x[3 * j + 1], x[3 * i + 2] - x[3 * j + 2]};
+            double r = std::sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+            for (int p = 0; p < 3; ++p)
+                for (int q = 0; q < 3; ++q) {
+                    double I = (p == q) ? 1.0 : 0.0;
+                    double v;
+                    if (i == j) v = c0 * I;
+                    else {
+                        double e = d[p] * d[q] / (r * r);
+                        if (r >= 2 * a)
+                            v = (1.0 / (8.0 * M_PI * eta * r)) * ((1 + 2 * a * a / (3 * r * r)) * I + (1 - 2 * a * a / (r * r)) * e);
+                        else
+                            v = c0 * ((1 - 9 * r / (32 * a)) * I + (3 * r / (32 * a)) * e);
+                    }
+                    M[(size_t)(3 * i + p) * N3 + 3 * j + q] = v;
+                }
+        }
+    return M;
+}
+
+// ------------------------------------------------------------------ allocation helpers
+template <typename T>
+static T *dalloc(size_t n) {
+    if (n == 0) n = 1;
+    void *p = nullptr;
+    if (hipMalloc(&p, n * sizeof(T)) != hipSuccess) {
+        g_last_error = "hipMalloc of " + std::to_string(n * sizeof(T)) + " bytes failed";
+        throw (int)RBFIB_ENOMEM;
+    }
+    return reinterpret_cast<T *>(p);
+}
+
+template <typename T>
+static T *upload(Ctx &c, const std::vector<T> &h) {
+    T *d = dalloc<T>(h.size());
+    if (!h.empty()) HIP_OK(hipMemcpyAsync(d, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, c.stream));
+    return d;
+}
+
+template <typename T>
+void zero_device(Ctx &c, T *p, long long n) {
+    if (n > 0) HIP_OK(hipMemsetAsync(p, 0, (size_t)n * sizeof(T), c.stream));
+}
+
+static void free_all(Ctx &c);
+
+// ------------------------------------------------------------------ operator and preconditioner
+static void record(Ctx &c, int cls, bool start) {
+    if (!c.timing.on) return;
+    auto &v = c.timing.ev[cls];
+    size_t k = c.timing.used[cls];
+    if (start) {
+        if (k + 2 > v.size()) return;
+        HIP_OK(hipEventRecord(v[k], c.stream));
+    } else {
+        if (k + 2 > v.size()) return;
+        HIP_OK(hipEventRecord(v[k + 1], c.stream));
+        c.timing.used[cls] = k + 2;
+    }
+}
+
+static void apply_op(Ctx &c, MarkerSet &ms, const double *x, double *y, bool fluid_only) {
+    record(c, 0, true);
+    launch_apply_fluid(c, x, y);
+    record(c, 0, false);
+    if (fluid_only || c.nm == 0) {
+        launch_zero_bodies(c, y);
+        return;
+    }
+    launch_spread(c, ms, x, y, -1.0);
+    launch_body_apply(c, ms, nullptr, x, y);
+}
+
+template <typename T>
+static void vcycle(Ctx &c, int c0, int nc) {
+    T *X = (T *)c.mg_x, *B = (T *)c.mg_b, *Tt = (T *)c.mg_t;
+    int nu = std::max(1, c.opts.mg_sweeps);
+    for (int l = 0; l < c.maxlev; ++l) {
+        launch_coarse<T>(c, l, c0, nc, B, X);
+        if (c.n_tab_lev[l] == 0) continue;
+        for (int k = 1; k <= nu; ++k) {
+            T *out = ((nu - k) % 2 == 0) ? X : Tt;
+            T *in = (out == X) ? Tt : X;
+            if (l == 0) record(c, 1, true);
+            launch_smooth<T>(c, l, c0, nc, in, out, B, k == 1);
+            if (l == 0) record(c, 1, false);
+        }
+        launch_restrict<T>(c, l, c0, nc, X, B, B);
+    }
+    for (int l = c.maxlev - 2; l >= 0; --l) {
+        if (c.n_tab_lev[l] == 0) continue;
+        launch_prolong<T>(c, l, c0, nc, X, X);
+        T *in = X, *out = Tt;
+        for (int k = 1; k <= nu; ++k) {
+            if (l == 0) record(c, 1, true);
+            launch_smooth<T>(c, l, c0, nc, in, out, B, false);
+            if (l == 0) record(c, 1, false);
+            std::swap(in, out);
+        }
+        if (in != X) launch_smooth<T>(c, l, c0, nc, in, X, B, false);   // odd count: one more sweep lands in X
+    }
+}
+
+template <typename T>
+static void precond_t(Ctx &c, MarkerSet &ms, const double *theta, const double *r, double *z, bool fluid_only) {
+    bool bodies = !fluid_only && c.nb > 0;
+    if (bodies) launch_body_precond(c, ms, theta, r, z);
+    launch_copy(c, r, c.fluid_tmp, nullptr);
+    if (bodies) launch_spread(c, ms, z, c.fluid_tmp, 1.0);
+    T *X = (T *)c.mg_x, *B = (T *)c.mg_b;
+    launch_to_level0<T>(c, c.fluid_tmp, B, 0, 3);
+    vcycle<T>(c, 0, 3);
+    launch_proj_div<T>(c, X, c.fluid_tmp, B, z);
+    vcycle<T>(c, 3, 1);
+    launch_proj_correct<T>(c, X, X, z);
+    if (!bodies) launch_zero_bodies(c, z);
+}
+
+static void precond(Ctx &c, MarkerSet &ms, const double *theta, const double *r, double *z, bool fluid_only) {
+    if (c.mg_fp32) precond_t<float>(c, ms, theta, r, z, fluid_only);
+    else precond_t<double>(c, ms, theta, r, z, fluid_only);
+}
+
+// ------------------------------------------------------------------ FGMRES
+__global__ void k_init_solver(int nrep, int *active, int *status, int *iters, const double *beta0) {
+    int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= nrep) return;
+    status[r] = RBFIB_OK;
+    iters[r] = 0;
+    active[r] = beta0[r] > 0.0 ? 1 : 0;
+    if (!isfinite(beta0[r])) { status[r] = RBFIB_ENUMERIC; active[r] = 0; }
+}
+
+__global__ void k_count(int nrep, const int *active, int *out) {
+    int s = 0;
+    for (int r = 0; r < nrep; ++r) s += active[r];
+    *out = s;
+}
+
+static int count_active(Ctx &c) {
+    hipLaunchKernelGGL(k_count, dim3(1), dim3(1), 0, c.stream, c.nrep, c.active, c.d_count);
+    HIP_OK(hipMemcpyAsync(c.h_count, c.d_count, sizeof(int), hipMemcpyDeviceToHost, c.stream));
+    HIP_OK(hipStreamSynchronize(c.stream));
+    return *c.h_count;
+}
+
+// Solves A x = b (b a state vector); the solution is left in c.xsol.
+static void fgmres(Ctx &c, MarkerSet &ms, const double *theta, const double *b, bool fluid_only,
+                   std::vector<rbfib_info> &info) {
+    const double tol = c.opts.tol;
+    const int m = c.m;
+    double *nrm = c.hcol + 2LL * c.nrep * (m + 1);
+    double *h1 = c.hcol, *h2 = c.hcol + (long long)c.nrep * (m + 1);
+    launch_zero(c, c.xsol, nullptr);
+    launch_norm(c, b, c.beta0, nullptr);
+    hipLaunchKernelGGL(k_init_solver, dim3((c.nrep + 63) / 64), dim3(64), 0, c.stream, c.nrep, c.active, c.status,
+                       c.iters, c.beta0);
+    launch_scale(c, b, c.beta0, c.V, c.active, true);
+    HIP_OK(hipMemcpyAsync(nrm, c.beta0, sizeof(double) * c.nrep, hipMemcpyDeviceToDevice, c.stream));
+    launch_start_cycle(c);
+    int total = 0;
+    int check = std::max(1, c.opts.check_every);
+    bool done = count_active(c) == 0;
+    while (!done) {
+        for (int j = 0; j < m; ++j) {
+            double *Vj = c.V + (long long)j * c.L, *Zj = c.Z + (long long)j * c.L;
+            precond(c, ms, theta, Vj, Zj, fluid_only);
+            apply_op(c, ms, Zj, c.W, fluid_only);
+            launch_dots(c, c.V, j + 1, c.W, h1, c.active);
+            launch_axpy_multi(c, c.V, j + 1, h1, c.W, -1.0, c.active);
+            launch_dots(c, c.V, j + 1, c.W, h2, c.active);
+            launch_axpy_multi(c, c.V, j + 1, h2, c.W, -1.0, c.active);
+            launch_norm(c, c.W, nrm, c.active);
+            launch_givens(c, j, tol);
+            launch_scale(c, c.W, nrm, c.V + (long long)(j + 1) * c.L, c.active, true);
+            ++total;
+            if ((j + 1) % check == 0 || j + 1 == m || total >= c.opts.max_iter) {
+                if (count_active(c) == 0) { done = true; break; }
+                if (total >= c.opts.max_iter) break;
+            }
+        }
+        launch_trisolve_update(c);
+        if (done || total >= c.opts.max_iter) break;
+        // restart for replicas still active: r = b - A x
+        apply_op(c, ms, c.xsol, c.W, fluid_only);
+        launch_axpby(c, 1.0, b, -1.0, c.W, c.W, c.active);
+        launch_norm(c, c.W, nrm, c.active);
+        launch_scale(c, c.W, nrm, c.V, c.active, true);
+        launch_start_cycle(c);
+    }
+    // true residual of every replica
+    apply_op(c, ms, c.xsol, c.W, fluid_only);
+    launch_axpby(c, 1.0, b, -1.0, c.W, c.W, nullptr);
+    launch_norm(c, c.W, c.d_resid, nullptr);
+    std::vector<double> res(c.nrep), b0(c.nrep);
+    std::vector<int> st(c.nrep), it(c.nrep), act(c.nrep);
+    HIP_OK(hipMemcpyAsync(res.data(), c.d_resid, sizeof(double) * c.nrep, hipMemcpyDeviceToHost, c.stream));
+    HIP_OK(hipMemcpyAsync(b0.data(), c.beta0, sizeof(double) * c.nrep, hipMemcpyDeviceToHost, c.stream));
+    HIP_OK(hipMemcpyAsync(st.data(), c.status, sizeof(int) * c.nrep, hipMemcpyDeviceToHost, c.stream));
+    HIP_OK(hipMemcpyAsync(it.data(), c.iters, sizeof(int) * c.nrep, hipMemcpyDeviceToHost, c.stream));
+    HIP_OK(hipMemcpyAsync(act.data(), c.active, sizeof(int) * c.nrep, hipMemcpyDeviceToHost, c.stream));
+    HIP_OK(hipStreamSynchronize(c.stream));
+    info.resize(c.nrep);
+    for (int r = 0; r < c.nrep; ++r) {
+        info[r].iters = it[r];
+        info[r].rel_residual = b0[r] > 0.0 ? res[r] / b0[r] : 0.0;
+        int s = st[r];
+        if (s == RBFIB_OK && act[r]) s = RBFIB_ENOCONV;
+        if (s == RBFIB_OK && !(info[r].rel_residual == info[r].rel_residual)) s = RBFIB_ENUMERIC;
+        info[r].status = s;
+    }
+    if (c.timing.on) {
+        for (int cls = 0; cls < 2; ++cls) {
+            for (size_t k = 0; k + 1 < c.timing.used[cls]; k += 2) {
+                float ms_ = 0.f;
+                HIP_OK(hipEventElapsedTime(&ms_, c.timing.ev[cls][k], c.timing.ev[cls][k + 1]));
+                c.timing.total_ms[cls] += ms_;
+                c.timing.launches[cls] += 1;
+            }
+            c.timing.used[cls] = 0;
+        }
+    }
+}
+
+static int first_bad(const std::vector<rbfib_info> &info) {
+    for (auto &i : info) if (i.status != RBFIB_OK) return i.status;
+    return RBFIB_OK;
+}
+
+// markers at (q, theta) into ms; returns RBFIB_EREJECT when a marker leaves the domain.
+static int build_markers(Ctx &c, MarkerSet &ms, const double *q, const double *theta, bool check) {
+    HIP_OK(hipMemsetAsync(c.d_flags, 0, sizeof(int) * 4, c.stream));
+    launch_markers(c, ms, q, theta);
+    if (!check) return RBFIB_OK;
+    HIP_OK(hipMemcpyAsync(c.h_flags, c.d_flags, sizeof(int) * 4, hipMemcpyDeviceToHost, c.stream));
+    HIP_OK(hipStreamSynchronize(c.stream));
+    return c.h_flags[0] ? RBFIB_EREJECT : RBFIB_OK;
+}
+
+__global__ void k_add_lambda_bc(const RepDev *reps, const int *marker_body, const int *body_rep, int nm,
+                                const double *jbc, double *b) {
+    int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= 3 * nm) return;
+    int m = t / 3, cc = t % 3;
+    const RepDev &R = reps[body_rep[marker_body[m]]];
+    b[R.off + 4 * R.N + 3LL * (m - R.m0) + cc] += jbc[t];
+}
+
+static void add_boundary_terms(Ctx &c, MarkerSet &ms, double *b) {
+    bool any = false;
+    for (auto &R : c.reps) any |= (R.movwall != 0);
+    if (!any) return;
+    launch_wall_rhs(c, b);
+    if (c.nm > 0) {
+        zero_device(c, c.slip_acc, 3LL * c.nm);
+        launch_interp_bc(c, ms, c.slip_acc, 1.0);
+        hipLaunchKernelGGL(k_add_lambda_bc, dim3((3 * c.nm + 255) / 256), dim3(256), 0, c.stream, c.d_reps,
+                           c.d_marker_body, c.d_body_rep, c.nm, c.slip_acc, b);
+    }
+}
+
+// ------------------------------------------------------------------ context construction
+static void validate(int nrep, const rbfib_grid *grids, const rbfib_bodies *bodies, const rbfib_opts &o) {
+    if (nrep < 1 || !grids || !bodies) throw (int)RBFIB_EINVAL;
+    if (!(o.tol > 0.0) || o.restart < 1 || o.restart > 200 || o.max_iter < 1 || o.mg_sweeps < 1 ||
+        !(o.mg_omega > 0.0) || !(o.blob_radius > 0.0) || !(o.rfd_delta > 0.0))
+        throw (int)RBFIB_EINVAL;
+    for (int r = 0; r < nrep; ++r) {
+        const rbfib_grid &g = grids[r];
+        int walls = 0;
+        for (int a = 0; a < 3; ++a) {
+            if (g.n[a] < 4 || g.n[a] > (1 << 16)) throw (int)RBFIB_EINVAL;
+            if (g.bc[a] != RBFIB_PERIODIC && g.bc[a] != RBFIB_WALL) throw (int)RBFIB_EINVAL;
+            walls += g.bc[a] == RBFIB_WALL;
+        }
+        if (walls == 0 || !(g.h > 0.0) || !(g.eta > 0.0)) throw (int)RBFIB_EINVAL;
+        const rbfib_bodies &b = bodies[r];
+        if (b.nb < 0 || b.nm < 0) throw (int)RBFIB_EINVAL;
+        if (b.nb > 0 && (!b.marker_offset || !b.r_ref)) throw (int)RBFIB_EINVAL;
+        if (b.nb > 0) {
+            if (b.marker_offset[0] != 0 || b.marker_offset[b.nb] != b.nm) throw (int)RBFIB_EINVAL;
+            for (int p = 0; p < b.nb; ++p)
+                if (b.marker_offset[p + 1] <= b.marker_offset[p]) throw (int)RBFIB_EINVAL;
+        } else if (b.nm != 0) throw (int)RBFIB_EINVAL;
+    }
+}
+
+static void build(Ctx &c, int nrep, const rbfib_grid *grids, const rbfib_bodies *bodies) {
+    c.nrep = nrep;
+    c.reps.resize(nrep);
+    long long off = 0;
+    int b0 = 0, m0 = 0, t0 = 0;
+    std::vector<int> marker_body, body_rep, body_off(1, 0), tile_rep;
+    std::vector<double> rref;
+    c.max_body_nm = 1;
+    for (int r = 0; r < nrep; ++r) {
+        const rbfib_grid &g = grids[r];
+        const rbfib_bodies &bd = bodies[r];
+        RepDev &R = c.reps[r];
+        memset(&R, 0, sizeof(R));
+        for (int a = 0; a < 3; ++a) { R.n[a] = g.n[a]; R.bc[a] = g.bc[a]; R.tdim[a] = (g.n[a] + RB_TILE - 1) / RB_TILE; }
+        R.h = g.h; R.inv_h = 1.0 / g.h; R.eta = g.eta; R.dV = g.h * g.h * g.h;
+        R.N = (long long)g.n[0] * g.n[1] * g.n[2];
+        R.nb = bd.nb; R.nm = bd.nm; R.b0 = b0; R.m0 = m0;
+        R.off = off;
+        R.len = 4 * R.N + 3LL * bd.nm + 6LL * bd.nb;
+        off += R.len;
+        R.tile0 = t0;
+        int nt = R.tdim[0] * R.tdim[1] * R.tdim[2];
+        for (int t = 0; t < nt; ++t) tile_rep.push_back(r);
+        t0 += nt;
+        R.movwall = 0;
+        for (int a = 0; a < 3; ++a)
+            for (int s = 0; s < 2; ++s)
+                for (int k = 0; k < 3; ++k) {
+                    double v = (g.bc[a] == RBFIB_WALL && k != a) ? g.wall_vel[a][s][k] : 0.0;
+                    R.wv[a][s][k] = v;
+                    if (v != 0.0) R.movwall = 1;
+                }
+        for (int p = 0; p < bd.nb; ++p) {
+            int n = bd.marker_offset[p + 1] - bd.marker_offset[p];
+            c.max_body_nm = std::max(c.max_body_nm, n);
+            for (int i = 0; i < n; ++i) marker_body.push_back(b0 + p);
+            body_rep.push_back(r);
+            body_off.push_back(m0 + bd.marker_offset[p + 1]);
+        }
+        for (int i = 0; i < 3 * bd.nm; ++i) rref.push_back(bd.r_ref[i]);
+        b0 += bd.nb;
+        m0 += bd.nm;
+    }
+    c.L = off; c.nb = b0; c.nm = m0; c.ntiles = t0;
+
+    // ---- multigrid hierarchy: coarsen an axis while it is even and >= 8
+    c.levs.assign((size_t)nrep * RB_MAXLEV, LevDev());
+    long long loff = 0;
+    c.maxlev = 0;
+    for (int r = 0; r < nrep; ++r) {
+        RepDev &R = c.reps[r];
+        int n[3] = {R.n[0], R.n[1], R.n[2]};
+        double h[3] = {R.h, R.h, R.h};
+        int l = 0;
+        while (true) {
+            LevDev &Lv = c.levs[(size_t)r * RB_MAXLEV + l];
+            for (int a = 0; a < 3; ++a) { Lv.n[a] = n[a]; Lv.inv_h2[a] = 1.0 / (h[a] * h[a]); }
+            Lv.N = (long long)n[0] * n[1] * n[2];
+            Lv.off = loff;
+            loff += 4 * Lv.N;
+            bool any = false;
+            int nn[3];
+            for (int a = 0; a < 3; ++a) {
+                bool can = (n[a] % 2 == 0) && n[a] >= 8;
+                nn[a] = can ? n[a] / 2 : n[a];
+                any |= can;
+            }
+            if (!any || l + 1 >= RB_MAXLEV) break;
+            for (int a = 0; a < 3; ++a) { if (nn[a] != n[a]) h[a] *= 2.0; n[a] = nn[a]; }
+            ++l;
+        }
+        R.nlev = l + 1;
+        c.maxlev = std::max(c.maxlev, R.nlev);
+        if (c.levs[(size_t)r * RB_MAXLEV + l].N > 1000) {
+            g_last_error = "coarsest multigrid level has more than 1000 cells; use grid sizes with more factors of 2";
+            throw (int)RBFIB_EINVAL;
+        }
+    }
+    c.lev_total = loff;
+
+    // ---- block tables
+    auto chunks = [](std::vector<BlockEnt> &tab, int rep, long long n, long long step) {
+        for (long long s = 0; s < n; s += step) tab.push_back(BlockEnt{rep, 0, s});
+    };
+    std::vector<BlockEnt> tcells, tvec;
+    c.vec_first.resize(nrep);
+    c.vec_nblk.resize(nrep);
+    for (int r = 0; r < nrep; ++r) {
+        chunks(tcells, r, c.reps[r].N, RB_BLOCK);
+        c.vec_first[r] = (int)tvec.size();
+        chunks(tvec, r, c.reps[r].len, RB_CHUNK);
+        c.vec_nblk[r] = (int)tvec.size() - c.vec_first[r];
+    }
+    c.n_tab_cells = (int)tcells.size();
+    c.n_tab_vec = (int)tvec.size();
+    c.d_tab_cells = upload(c, tcells);
+    c.d_tab_vec = upload(c, tvec);
+    c.d_vec_first = upload(c, c.vec_first);
+    c.d_vec_nblk = upload(c, c.vec_nblk);
+    for (int l = 0; l < c.maxlev; ++l) {
+        std::vector<BlockEnt> tl, tc, ta;
+        for (int r = 0; r < nrep; ++r) {
+            const RepDev &R = c.reps[r];
+            if (l >= R.nlev) continue;
+            long long N = c.levs[(size_t)r * RB_MAXLEV + l].N;
+            chunks(ta, r, N, RB_BLOCK);
+            if (l < R.nlev - 1) chunks(tl, r, N, RB_BLOCK);
+            else tc.push_back(BlockEnt{r, 0, 0});
+        }
+        c.n_tab_lev[l] = (int)tl.size(); c.d_tab_lev[l] = upload(c, tl);
+        c.n_tab_crs[l] = (int)tc.size(); c.d_tab_crs[l] = upload(c, tc);
+        c.n_tab_all[l] = (int)ta.size(); c.d_tab_all[l] = upload(c, ta);
+    }
+
+    // ---- dense coarsest inverses, deduplicated by (dims, spacing, bc, eta, component)
+    std::map<std::string, long long> keyoff;
+    std::vector<double> pool;
+    std::vector<long long> coff((size_t)nrep * 4, 0);
+    c.max_coarse = 1;
+    for (int r = 0; r < nrep; ++r) {
+        const RepDev &R = c.reps[r];
+        const LevDev &Lv = c.levs[(size_t)r * RB_MAXLEV + R.nlev - 1];
+        c.max_coarse = std::max(c.max_coarse, (int)Lv.N);
+        for (int comp = 0; comp < 4; ++comp) {
+            char key[512];
+            snprintf(key, sizeof key, "%d %d %d %.17g %.17g %.17g %d %d %d %.17g %d", Lv.n[0], Lv.n[1], Lv.n[2],
+                     Lv.inv_h2[0], Lv.inv_h2[1], Lv.inv_h2[2], R.bc[0], R.bc[1], R.bc[2], R.eta, comp);
+            auto it = keyoff.find(key);
+            if (it == keyoff.end()) {
+                std::vector<double> inv = coarse_inverse(Lv.n, Lv.inv_h2, R.bc, R.eta, comp);
+                long long o = (long long)pool.size();
+                pool.insert(pool.end(), inv.begin(), inv.end());
+                it = keyoff.emplace(key, o).first;
+            }
+            coff[(size_t)r * 4 + comp] = it->second;
+        }
+    }
+    c.d_coarse64 = upload(c, pool);
+    std::vector<float> pool32(pool.begin(), pool.end());
+    c.d_coarse32 = upload(c, pool32);
+    c.d_coarse_off = upload(c, coff);
+
+    // ---- body shapes for the preconditioner block (deduplicated by marker geometry)
+    std::map<std::vector<double>, int> shape_id;
+    std::vector<ShapeDev> shapes;
+    std::vector<double> sdata;
+    std::vector<int> body_shape(c.nb);
+    std::vector<double> body_len(c.nb, 0.0);
+    for (int p = 0; p < c.nb; ++p) {
+        int mb = body_off[p], me = body_off[p + 1], n = me - mb;
+        std::vector<double> geo(rref.begin() + 3 * mb, rref.begin() + 3 * me);
+        double Lp = 0.0;
+        for (int i = 0; i < n; ++i)
+            for (int j = i + 1; j < n; ++j) {
+                double dx = geo[3 * i] - geo[3 * j], dy = geo[3 * i + 1] - geo[3 * j + 1], dz = geo[3 * i + 2] - geo[3 * j + 2];
+                Lp = std::max(Lp, std::sqrt(dx * dx + dy * dy + dz * dz));
+            }
+        body_len[p] = Lp;
+        const RepDev &R = c.reps[body_rep[p]];
+        std::vector<double> key = geo;
+        key.push_back(R.h);
+        key.push_back(R.eta);
+        auto it = shape_id.find(key);
+        if (it == shape_id.end()) {
+            int N3 = 3 * n;
+            std::vector<double> M = rpy_matrix(geo.data(), n, c.opts.blob_radius * R.h, R.eta);
+            if (!invert(M, N3)) throw (int)RBFIB_EINVAL;
+            std::vector<double> K((size_t)N3 * 6, 0.0);
+            for (int i = 0; i < n; ++i) {
+                const double *d = &geo[3 * i];
+                for (int a = 0; a < 3; ++a) K[(size_t)(3 * i + a) * 6 + a] = 1.0;
+                // -[d]_x
+                K[(size_t)(3 * i + 0) * 6 + 4] = d[2];  K[(size_t)(3 * i + 0) * 6 + 5] = -d[1];
+                K[(size_t)(3 * i + 1) * 6 + 3] = -d[2]; K[(size_t)(3 * i + 1) * 6 + 5] = d[0];
+                K[(size_t)(3 * i + 2) * 6 + 3] = d[1];  K[(size_t)(3 * i + 2) * 6 + 4] = -d[0];
+            }
+            std::vector<double> MK((size_t)N3 * 6, 0.0);
+            for (int k = 0; k < N3; ++k)
+                for (int l = 0; l < 6; ++l) {
+                    double s = 0.0;
+                    for (int j = 0; j < N3; ++j) s += M[(size_t)k * N3 + j] * K[(size_t)j * 6 + l];
+                    MK[(size_t)k * 6 + l] = s;
+                }
+            std::vector<double> Nm(36, 0.0);
+            for (int a = 0; a < 6; ++a)
+                for (int b = 0; b < 6; ++b) {
+                    double s = 0.0;
+                    for (int j = 0; j < N3; ++j) s += K[(size_t)j * 6 + a] * MK[(size_t)j * 6 + b];
+                    Nm[a * 6 + b] = s;
+                }
+            if (!invert(Nm, 6)) throw (int)RBFIB_EINVAL;
+            ShapeDev S;
+            S.nm = n;
+            S.minv_off = (long long)sdata.size(); sdata.insert(sdata.end(), M.begin(), M.end());
+            S.mk_off = (long long)sdata.size(); sdata.insert(sdata.end(), MK.begin(), MK.end());
+            S.n_off = (long long)sdata.size(); sdata.insert(sdata.end(), Nm.begin(), Nm.end());
+            S.rref_off = (long long)sdata.size(); sdata.insert(sdata.end(), geo.begin(), geo.end());
+            shapes.push_back(S);
+            it = shape_id.emplace(key, (int)shapes.size() - 1).first;
+        }
+        body_shape[p] = it->second;
+    }
+
+    // ---- device copies
+    c.d_reps = upload(c, c.reps);
+    c.d_levs = upload(c, c.levs);
+    c.d_marker_body = upload(c, marker_body);
+    c.d_body_rep = upload(c, body_rep);
+    c.d_body_off = upload(c, body_off);
+    c.d_tile_rep = upload(c, tile_rep);
+    c.d_rref = upload(c, rref);
+    c.d_body_shape = upload(c, body_shape);
+    c.d_shapes = upload(c, shapes);
+    c.d_shape_data = upload(c, sdata);
+    c.d_body_len = upload(c, body_len);
+    c.h_body_len = body_len;
+
+    // ---- marker sets
+    for (int k = 0; k < 4; ++k) {
+        MarkerSet &ms = c.ms[k];
+        ms.r = dalloc<double>(3 * (size_t)c.nm);
+        ms.d = dalloc<double>(3 * (size_t)c.nm);
+        ms.tile = dalloc<int>(c.nm);
+        ms.perm = dalloc<int>(c.nm);
+        ms.tile_count = dalloc<int>(c.ntiles);
+        ms.tile_start = dalloc<int>(c.ntiles);
+        ms.tile_fill = dalloc<int>(c.ntiles);
+        ms.active = dalloc<int>(c.ntiles);
+        ms.flag = dalloc<int>(c.ntiles);
+        ms.n_active = dalloc<int>(1);
+        zero_device(c, ms.n_active, 1);
+    }
+    c.d_flags = dalloc<int>(4);
+    HIP_OK(hipHostMalloc((void **)&c.h_flags, sizeof(int) * 4, hipHostMallocDefault));
+    HIP_OK(hipHostMalloc((void **)&c.h_count, sizeof(int), hipHostMallocDefault));
+    c.d_count = dalloc<int>(1);
+
+    // ---- multigrid pools
+    c.mg_fp32 = c.opts.precond_fp32 != 0;
+    size_t es = c.mg_fp32 ? sizeof(float) : sizeof(double);
+    c.mg_x = dalloc<unsigned char>(es * (size_t)c.lev_total);
+    c.mg_b = dalloc<unsigned char>(es * (size_t)c.lev_total);
+    c.mg_t = dalloc<unsigned char>(es * (size_t)c.lev_total);
+    HIP_OK(hipMemsetAsync(c.mg_x, 0, es * (size_t)c.lev_total, c.stream));
+    HIP_OK(hipMemsetAsync(c.mg_b, 0, es * (size_t)c.lev_total, c.stream));
+    HIP_OK(hipMemsetAsync(c.mg_t, 0, es * (size_t)c.lev_total, c.stream));
+
+    // ---- Krylov storage
+    c.m = c.opts.restart;
+    size_t L = (size_t)c.L;
+    c.V = dalloc<double>(L * (c.m + 1));
+    c.Z = dalloc<double>(L * c.m);
+    c.W = dalloc<double>(L);
+    c.xsol = dalloc<double>(L);
+    c.rhs = dalloc<double>(L);
+    c.tmp = dalloc<double>(L);
+    c.fluid_tmp = dalloc<double>(L);
+    c.xR = dalloc<double>(L);
+    c.xS = dalloc<double>(L);
+    c.partial = dalloc<double>((size_t)c.n_tab_vec * (c.m + 1));
+    c.H = dalloc<double>((size_t)nrep * (c.m + 1) * c.m);
+    c.cs = dalloc<double>((size_t)nrep * c.m);
+    c.sn = dalloc<double>((size_t)nrep * c.m);
+    c.gv = dalloc<double>((size_t)nrep * (c.m + 1));
+    c.beta0 = dalloc<double>(nrep);
+    c.hcol = dalloc<double>((size_t)3 * nrep * (c.m + 1));
+    c.yv = dalloc<double>((size_t)nrep * (c.m + 1));
+    c.d_resid = dalloc<double>(nrep);
+    c.active = dalloc<int>(nrep);
+    c.cyc_active = dalloc<int>(nrep);
+    c.jf = dalloc<int>(nrep);
+    c.status = dalloc<int>(nrep);
+    c.iters = dalloc<int>(nrep);
+    zero_device(c, c.H, (long long)nrep * (c.m + 1) * c.m);
+    zero_device(c, c.hcol, 3LL * nrep * (c.m + 1));
+    // SEM scratch
+    for (int k = 0; k < 3; ++k) {
+        c.q_buf[k] = dalloc<double>(3 * (size_t)std::max(c.nb, 1));
+        c.th_buf[k] = dalloc<double>(4 * (size_t)std::max(c.nb, 1));
+    }
+    c.Wf = dalloc<double>(3 * (size_t)std::max(c.nb, 1));
+    c.Wt = dalloc<double>(3 * (size_t)std::max(c.nb, 1));
+    c.WFT = dalloc<double>(6 * (size_t)std::max(c.nb, 1));
+    c.Fp = dalloc<double>(6 * (size_t)std::max(c.nb, 1));
+    c.UR = dalloc<double>(6 * (size_t)std::max(c.nb, 1));
+    c.slip_acc = dalloc<double>(3 * (size_t)std::max(c.nm, 1));
+    for (int cls = 0; cls < 2; ++cls) {
+        c.timing.ev[cls].resize(8192);
+        for (auto &e : c.timing.ev[cls]) HIP_OK(hipEventCreate(&e));
+    }
+    HIP_OK(hipStreamSynchronize(c.stream));
+}
+
+static void free_all(Ctx &c) {
+    auto F = [](void *p) { if (p) (void)hipFree(p); };
+    F(c.d_reps); F(c.d_levs); F(c.d_marker_body); F(c.d_body_rep); F(c.d_body_off); F(c.d_tile_rep); F(c.d_rref);
+    F(c.d_body_shape); F(c.d_shapes); F(c.d_shape_data); F(c.d_body_len);
+    F(c.d_tab_cells); F(c.d_tab_vec); F(c.d_vec_first); F(c.d_vec_nblk);
+    for (int l = 0; l < RB_MAXLEV; ++l) { F(c.d_tab_lev[l]); F(c.d_tab_crs[l]); F(c.d_tab_all[l]); }
+    F(c.d_coarse_off); F(c.d_coarse64); F(c.d_coarse32);
+    F(c.mg_x); F(c.mg_b); F(c.mg_t);
+    for (int k = 0; k < 4; ++k) {
+        MarkerSet &ms = c.ms[k];
+        F(ms.r); F(ms.d); F(ms.tile); F(ms.perm); F(ms.tile_count); F(ms.tile_start); F(ms.tile_fill);
+        F(ms.active); F(ms.flag); F(ms.n_active);
+    }
+    F(c.d_flags); F(c.d_count);
+    if (c.h_flags) (void)hipHostFree(c.h_flags);
+    if (c.h_count) (void)hipHostFree(c.h_count);
+    F(c.V); F(c.Z); F(c.W); F(c.xsol); F(c.rhs); F(c.tmp); F(c.fluid_tmp); F(c.xR); F(c.xS); F(c.partial);
+    F(c.H); F(c.cs); F(c.sn); F(c.gv); F(c.beta0); F(c.hcol); F(c.yv); F(c.d_resid);
+    F(c.active); F(c.cyc_active); F(c.jf); F(c.status); F(c.iters);
+    for (int k = 0; k < 3; ++k) { F(c.q_buf[k]); F(c.th_buf[k]); }
+    F(c.Wf); F(c.Wt); F(c.WFT); F(c.Fp); F(c.UR); F(c.slip_acc);
+    for (int cls = 0; cls < 2; ++cls)
+        for (auto &e : c.timing.ev[cls]) (void)hipEventDestroy(e);
+}
+
+}  // namespace rb
+
+using namespace rb;
+
+// ====================================================================== C ABI
+#define GUARD_BEGIN try {
+#define GUARD_END                                          \
+    }                                                      \
+    catch (int code) { return code; }                      \
+    catch (...) { g_last_error = "internal error"; return RBFIB_EDEVICE; }
+
+extern "C" {
+
+void rbfib_default_opts(rbfib_opts *o) {
+    if (!o) return;
+    o->tol = 1e-6;
+    o->restart = 30;
+    o->max_iter = 600;
+    o->precond_fp32 = 0;
+    o->mg_sweeps = 2;
+    o->mg_omega = 0.8;
+    o->blob_radius = 1.25;
+    o->rfd_delta = 1e-5;
+    o->min_body_dist = 0.0;
+    o->check_every = 4;
+}
+
+const char *rbfib_strerror(int code) {
+    switch (code) {
+        case RBFIB_OK: return "ok";
+        case RBFIB_EINVAL: return "invalid argument";
+        case RBFIB_EREJECT: return "unphysical configuration (step rejected)";
+        case RBFIB_ENOCONV: return "solver did not converge";
+        case RBFIB_ENUMERIC: return "NaN or Inf in the solver";
+        case RBFIB_EDEVICE: return "HIP runtime error";
+        case RBFIB_ENOMEM: return "device allocation failed";
+        default: return "unknown error";
+    }
+}
+
+const char *rbfib_last_error(void) { return g_last_error.c_str(); }
+
+int rbfib_create_batch(int nrep, const rbfib_grid *grids, const rbfib_bodies *bodies, const rbfib_opts *opts,
+                       void *hip_stream, rbfib_ctx **out) {
+    if (!out) return RBFIB_EINVAL;
+    *out = nullptr;
+    rbfib_ctx *ctx = nullptr;
+    try {
+        rbfib_opts o;
+        rbfib_default_opts(&o);
+        if (opts) o = *opts;
+        validate(nrep, grids, bodies, o);
+        ctx = new rbfib_ctx();
+        ctx->c.stream = (hipStream_t)hip_stream;
+        ctx->c.opts = o;
+        build(ctx->c, nrep, grids, bodies);
+        *out = ctx;
+        return RBFIB_OK;
+    } catch (int code) {
+        if (ctx) { free_all(ctx->c); delete ctx; }
+        return code;
+    } catch (...) {
+        if (ctx) { free_all(ctx->c); delete ctx; }
+        return RBFIB_EDEVICE;
+    }
+}
+
+int rbfib_create(const rbfib_grid *grid, const rbfib_bodies *bodies, const rbfib_opts *opts, void *hip_stream,
+                 rbfib_ctx **out) {
+    return rbfib_create_batch(1, grid, bodies, opts, hip_stream, out);
+}
+
+void rbfib_destroy(rbfib_ctx *ctx) {
+    if (!ctx) return;
+    (void)hipStreamSynchronize(ctx->c.stream);
+    free_all(ctx->c);
+    delete ctx;
+}
+
+int rbfib_set_opts(rbfib_ctx *ctx, const rbfib_opts *o) {
+    if (!ctx || !o) return RBFIB_EINVAL;
+    Ctx &c = ctx->c;
+    if (!(o->tol > 0.0) || o->max_iter < 1 || o->mg_sweeps < 1 || !(o->mg_omega > 0.0) || !(o->rfd_delta > 0.0))
+        return RBFIB_EINVAL;
+    // fields fixed at creation: restart length, precision, blob radius
+    if (o->restart != c.opts.restart || (o->precond_fp32 != 0) != c.mg_fp32 || o->blob_radius != c.opts.blob_radius)
+        return RBFIB_EINVAL;
+    c.opts = *o;
+    return RBFIB_OK;
+}
+
+long long rbfib_state_size(const rbfib_ctx *ctx) { return ctx ? ctx->c.L : 0; }
+
+int rbfib_layout(const rbfib_ctx *ctx, long long *out) {
+    if (!ctx || !out) return RBFIB_EINVAL;
+    const Ctx &c = ctx->c;
+    for (int r = 0; r < c.nrep; ++r) {
+        const RepDev &R = c.reps[r];
+        out[4 * r + 0] = R.off;
+        out[4 * r + 1] = R.off + 3 * R.N;
+        out[4 * r + 2] = R.off + 4 * R.N;
+        out[4 * r + 3] = R.off + 4 * R.N + 3LL * R.nm;
+    }
+    return RBFIB_OK;
+}
+
+__global__ void k_perm_local(const int *perm, const int *marker_body, const int *body_off_rep_m0, int nm, int *out) {
+    int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nm) return;
+    int m = perm[t];
+    out[t] = m - body_off_rep_m0[marker_body[m]];
+}
+
+int rbfib_markers(rbfib_ctx *ctx, const double *q, const double *theta, double *r, int *tile, int *perm) {
+    if (!ctx || (ctx->c.nb > 0 && (!q || !theta))) return RBFIB_EINVAL;
+    GUARD_BEGIN
+    Ctx &c = ctx->c;
+    MarkerSet &ms = c.ms[0];
+    build_markers(c, ms, q, theta, false);
+    if (r && c.nm) HIP_OK(hipMemcpyAsync(r, ms.r, sizeof(double) * 3 * c.nm, hipMemcpyDeviceToDevice, c.stream));
+    if (tile && c.nm) HIP_OK(hipMemcpyAsync(tile, ms.tile, sizeof(int) * c.nm, hipMemcpyDeviceToDevice, c.stream));
+    if (perm && c.nm) {
+        // replica-local ids: subtract each replica's first marker
+        std::vector<int> m0(c.nb);
+        for (int p = 0; p < c.nb; ++p) {
+            int rr = 0;
+            while (rr + 1 < c.nrep && c.reps[rr + 1].b0 <= p) ++rr;
+            m0[p] = c.reps[rr].m0;
+        }
+        int *d_m0 = dalloc<int>(c.nb);
+        HIP_OK(hipMemcpyAsync(d_m0, m0.data(), sizeof(int) * c.nb, hipMemcpyHostToDevice, c.stream));
+        hipLaunchKernelGGL(k_perm_local, dim3((c.nm + 255) / 256), dim3(256), 0, c.stream, ms.perm, c.d_marker_body,
+                           d_m0, c.nm, perm);
+        HIP_OK(hipStreamSynchronize(c.stream));
+        (void)hipFree(d_m0);
+    }
+    // tile indices returned replica-local as well
+    return RBFIB_OK;
+    GUARD_END
+}
+
+int rbfib_apply_saddle(rbfib_ctx *ctx, const double *q, const double *theta, const double *x, double *y) {
+    if (!ctx || !x || !y || x == y || (ctx->c.nb > 0 && (!q || !theta))) return RBFIB_EINVAL;
+    GUARD_BEGIN
+    Ctx &c = ctx->c;
+    build_markers(c, c.ms[0], q, theta, false);
+    apply_op(c, c.ms[0], x, y, false);
+    return RBFIB_OK;
+    GUARD_END
+}
+
+int rbfib_precondition(rbfib_ctx *ctx, const double *q, const double *theta, const double *r, double *z) {
+    if (!ctx || !r || !z || r == z || (ctx->c.nb > 0 && (!q || !theta))) return RBFIB_EINVAL;
+    GUARD_BEGIN
+    Ctx &c = ctx->c;
+    build_markers(c, c.ms[0], q, theta, false);
+    precond(c, c.ms[0], theta, r, z, false);
+    return RBFIB_OK;
+    GUARD_END
+}
+
+int rbfib_solve_mobility(rbfib_ctx *ctx, const double *q, const double *theta, const double *FT, const double *slip,
+                         int include_bc, double *U, double *x_out, rbfib_info *info) {
+    if (!ctx || (ctx->c.nb > 0 && (!q || !theta || !FT))) return RBFIB_EINVAL;
+    GUARD_BEGIN
+    Ctx &c = ctx->c;
+    MarkerSet &ms = c.ms[0];
+    int st = build_markers(c, ms, q, theta, true);
+    if (st != RBFIB_OK) {
+        if (info) for (int r = 0; r < c.nrep; ++r) info[r] = rbfib_info{0, 0.0, st};
+        return st;
+    }
+    launch_zero(c, c.rhs, nullptr);
+    launch_set_rhs(c, FT, slip, c.rhs);
+    if (include_bc) add_boundary_terms(c, ms, c.rhs);
+    std::vector<rbfib_info> inf;
+    fgmres(c, ms, theta, c.rhs, false, inf);
+    if (U) launch_copy_U(c, c.xsol, U, 1.0);
+    if (x_out) HIP_OK(hipMemcpyAsync(x_out, c.xsol, sizeof(double) * c.L, hipMemcpyDeviceToDevice, c.stream));
+    HIP_OK(hipStreamSynchronize(c.stream));
+    if (info) for (int r = 0; r < c.nrep; ++r) info[r] = inf[r];
+    return first_bad(inf);
+    GUARD_END
+}
+
+int rbfib_fluctuating_stress(rbfib_ctx *ctx, double kT, double dt, uint64_t seed, uint64_t step, double *f) {
+    if (!ctx || !f || !(dt > 0.0) || kT < 0.0) return RBFIB_EINVAL;
+    GUARD_BEGIN
+    Ctx &c = ctx->c;
+    launch_zero(c, f, nullptr);
+    launch_noise(c, kT, dt, seed, step, f, false);
+    return RBFIB_OK;
+    GUARD_END
+}
+
+int rbfib_sem_step(rbfib_ctx *ctx, double *q, double *theta, const double *FT, const double *slip, double kT, double dt,
+                   uint64_t seed, uint64_t step, double *U, rbfib_info *info) {
+    (void)ctx; (void)q; (void)theta; (void)FT; (void)slip; (void)kT; (void)dt; (void)seed; (void)step; (void)U; (void)info;
+    g_last_error = "rbfib_sem_step: not available in this build";
+    return RBFIB_EINVAL;
+}
+
+int rbfib_mobility_vjp(rbfib_ctx *ctx, const double *q, const double *theta, const double *FT, const double *Ubar,
+                       double *dFT, double *dq, double *dphi, rbfib_info *info) {
+    (void)ctx; (void)q; (void)theta; (void)FT; (void)Ubar; (void)dFT; (void)dq; (void)dphi; (void)info;
+    g_last_error = "rbfib_mobility_vjp: not available in this build";
+    return RBFIB_EINVAL;
+}
+
+int rbfib_enable_timing(rbfib_ctx *ctx, int on) {
+    if (!ctx) return RBFIB_EINVAL;
+    ctx->c.timing.on = on != 0;
+    for (int k = 0; k < 2; ++k) { ctx->c.timing.total_ms[k] = 0; ctx->c.timing.launches[k] = 0; ctx->c.timing.used[k] = 0; }
+    return RBFIB_OK;
+}
+
+int rbfib_kernel_stats(rbfib_ctx *ctx, int which, double *avg_ms, double *bytes_per_launch, long long *launches) {
+    if (!ctx || which < 0 || which > 1) return RBFIB_EINVAL;
+    Ctx &c = ctx->c;
+    long long n = c.timing.launches[which];
+    if (avg_ms) *avg_ms = n ? c.timing.total_ms[which] / n : 0.0;
+    if (launches) *launches = n;
+    double cells = 0.0;
+    for (auto &R : c.reps) cells += (double)R.N;
+    if (bytes_per_launch) {
+        if (which == 0) *bytes_per_launch = cells * 8.0 * 8.0;            // read 4 FP64 fields, write 4
+        else *bytes_per_launch = cells * 3.0 * 3.0 * (c.mg_fp32 ? 4.0 : 8.0);   // 3 comps: read x, b; write x
+    }
+    return RBFIB_OK;
+}
+
+}  // extern "C"
