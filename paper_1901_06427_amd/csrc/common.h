@@ -157,6 +157,39 @@ __device__ __forceinline__ double philox_normal(uint64_t seed, uint32_t stream, 
     return (index & 1) ? rho * sin(ang) : rho * cos(ang);
 }
 
+// ------------------------------------------------------------------ kernel weights
+// 1-D folded weights of one marker coordinate for component c along axis a:
+// raw support base..base+3, folded index and signed weight (0 when dropped).
+__device__ __forceinline__ void axis_weights(const RepDev &R, double ra, int c, int a, int idx[4], double w[4],
+                                             int cross[4]) {
+    double s = ra * R.inv_h - (a == c ? 0.0 : 0.5);
+    int b = (int)floor(s) - 1;
+    for (int q = 0; q < 4; ++q) {
+        int p = b + q;
+        double sg;
+        bool ok = fold_index(p, R.n[a], R.bc[a], a == c, idx[q], sg, cross[q]);
+        w[q] = ok ? sg * phi4(s - (double)p) : 0.0;
+    }
+}
+
+// (J u)_c at marker position rm; u points at component c of the replica's fluid block.
+__device__ __forceinline__ double interp_comp(const RepDev &R, const double *rm, int c, const double *u) {
+    int idx[3][4], cr[3][4];
+    double w[3][4];
+    for (int a = 0; a < 3; ++a) axis_weights(R, rm[a], c, a, idx[a], w[a], cr[a]);
+    double acc = 0.0;
+    for (int z = 0; z < 4; ++z) {
+        if (w[2][z] == 0.0) continue;
+        for (int y = 0; y < 4; ++y) {
+            double wzy = w[2][z] * w[1][y];
+            if (wzy == 0.0) continue;
+            long long row = (long long)R.n[0] * ((long long)idx[1][y] + (long long)R.n[1] * idx[2][z]);
+            for (int x = 0; x < 4; ++x) acc += wzy * w[0][x] * u[row + idx[0][x]];
+        }
+    }
+    return acc;
+}
+
 // ---------------------------------------------------------------- host context
 struct MarkerSet {
     double *r = nullptr;      // [nm, 3]
@@ -224,8 +257,8 @@ struct Ctx {
 
     // marker sets: 0 = Q^n, 1 = Q+, 2 = Q-, 3 = new configuration
     MarkerSet ms[4];
-    int *d_flags = nullptr;     // [4]: 0 reject/outside, 1 numeric
-    int *h_flags = nullptr;     // pinned host
+    int *d_flags = nullptr;     // [nrep]: bit 0 marker outside the domain, bit 1 bodies too close
+    int *h_flags = nullptr;     // pinned host copy
 
     // Krylov
     int m = 0;
@@ -242,6 +275,7 @@ struct Ctx {
     double *q_buf[3] = {nullptr, nullptr, nullptr};      // q+, q-, q_new  [nb, 3]
     double *th_buf[3] = {nullptr, nullptr, nullptr};     // [nb, 4]
     double *Wf = nullptr, *Wt = nullptr, *WFT = nullptr, *Fp = nullptr, *slip_acc = nullptr, *UR = nullptr;
+    double *jbc = nullptr;      // [nm, 3] scratch for the sliding-wall interpolation term
     double *xR = nullptr, *xS = nullptr;
 
     Timing timing;
@@ -267,8 +301,12 @@ void launch_body_apply(Ctx &c, MarkerSet &ms, const double *q, const double *x, 
 void launch_body_precond(Ctx &c, MarkerSet &ms, const double *theta, const double *r, double *z);
 void launch_interp(Ctx &c, MarkerSet &ms, const double *x, double *out, double alpha, bool accumulate);
 void launch_interp_bc(Ctx &c, MarkerSet &ms, double *out, double alpha);
-void launch_body_rfd(Ctx &c, double kT, double delta, uint64_t seed, uint64_t step);
-void launch_rfd_terms(Ctx &c, double delta, const double *FT);
+void launch_body_rfd(Ctx &c, double kT, double delta, uint64_t seed, uint64_t step, const double *q,
+                     const double *theta);
+void launch_rfd_terms(Ctx &c, double delta);
+void launch_rfd_forces(Ctx &c, double delta, const double *FT);
+void launch_set_rhs_U(Ctx &c, const double *Fp, double *b);
+void launch_body_distance(Ctx &c, double dmin);
 void launch_sem_rhs_lambda(Ctx &c, const double *slip, double *b);
 void launch_update_positions(Ctx &c, const double *q, const double *theta, const double *U, double dt);
 void launch_commit_positions(Ctx &c, double *q, double *theta);

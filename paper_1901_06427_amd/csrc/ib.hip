@@ -65,7 +65,7 @@ __global__ void k_markers(const RepDev *reps, const int *marker_body, const int 
     for (int a = 0; a < 3; ++a) { r_out[3 * m + a] = r[a]; d_out[3 * m + a] = d[a]; }
     tile[m] = t;
     atomicAdd(&tile_count[t], 1);
-    if (outside) atomicOr(&flags[0], 1 << 0);
+    if (outside) atomicOr(&flags[body_rep[p]], 1);
 }
 
 // exclusive scan of tile counts (one workgroup), zero the fill counters
@@ -172,39 +172,6 @@ void launch_markers(Ctx &c, MarkerSet &ms, const double *q, const double *theta)
     hipLaunchKernelGGL(k_tile_active, dim3((c.ntiles + 255) / 256), dim3(256), 0, c.stream, c.d_reps, c.d_tile_rep,
                        ms.tile_count, ms.flag, c.ntiles);
     hipLaunchKernelGGL(k_compact, dim3(1), dim3(1024), 0, c.stream, ms.flag, ms.active, ms.n_active, c.ntiles);
-}
-
-// ------------------------------------------------------------------ kernel weights
-// 1-D folded weights of one marker coordinate for component c along axis a:
-// raw support base..base+3, folded index and signed weight (0 when dropped).
-__device__ __forceinline__ void axis_weights(const RepDev &R, double ra, int c, int a, int idx[4], double w[4],
-                                             int cross[4]) {
-    double s = ra * R.inv_h - (a == c ? 0.0 : 0.5);
-    int b = (int)floor(s) - 1;
-    for (int q = 0; q < 4; ++q) {
-        int p = b + q;
-        double sg;
-        bool ok = fold_index(p, R.n[a], R.bc[a], a == c, idx[q], sg, cross[q]);
-        w[q] = ok ? sg * phi4(s - (double)p) : 0.0;
-    }
-}
-
-// (J u)_c at marker position rm; u points at component c of the replica's fluid block.
-__device__ double interp_comp(const RepDev &R, const double *rm, int c, const double *u) {
-    int idx[3][4], cr[3][4];
-    double w[3][4];
-    for (int a = 0; a < 3; ++a) axis_weights(R, rm[a], c, a, idx[a], w[a], cr[a]);
-    double acc = 0.0;
-    for (int z = 0; z < 4; ++z) {
-        if (w[2][z] == 0.0) continue;
-        for (int y = 0; y < 4; ++y) {
-            double wzy = w[2][z] * w[1][y];
-            if (wzy == 0.0) continue;
-            long long row = (long long)R.n[0] * ((long long)idx[1][y] + (long long)R.n[1] * idx[2][z]);
-            for (int x = 0; x < 4; ++x) acc += wzy * w[0][x] * u[row + idx[0][x]];
-        }
-    }
-    return acc;
 }
 
 // ------------------------------------------------------------------ spreading (gather)

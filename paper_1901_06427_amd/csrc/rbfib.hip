@@ -354,14 +354,24 @@ static int first_bad(const std::vector<rbfib_info> &info) {
     return RBFIB_OK;
 }
 
+// Per-replica rejection flags (bit 0: a marker outside the open domain along a wall
+// axis, bit 1: two body centres closer than opts.min_body_dist).
+static void clear_flags(Ctx &c) { HIP_OK(hipMemsetAsync(c.d_flags, 0, sizeof(int) * c.nrep, c.stream)); }
+
+static bool read_flags(Ctx &c) {
+    HIP_OK(hipMemcpyAsync(c.h_flags, c.d_flags, sizeof(int) * c.nrep, hipMemcpyDeviceToHost, c.stream));
+    HIP_OK(hipStreamSynchronize(c.stream));
+    bool any = false;
+    for (int r = 0; r < c.nrep; ++r) any |= c.h_flags[r] != 0;
+    return any;
+}
+
 // markers at (q, theta) into ms; returns RBFIB_EREJECT when a marker leaves the domain.
 static int build_markers(Ctx &c, MarkerSet &ms, const double *q, const double *theta, bool check) {
-    HIP_OK(hipMemsetAsync(c.d_flags, 0, sizeof(int) * 4, c.stream));
+    clear_flags(c);
     launch_markers(c, ms, q, theta);
     if (!check) return RBFIB_OK;
-    HIP_OK(hipMemcpyAsync(c.h_flags, c.d_flags, sizeof(int) * 4, hipMemcpyDeviceToHost, c.stream));
-    HIP_OK(hipStreamSynchronize(c.stream));
-    return c.h_flags[0] ? RBFIB_EREJECT : RBFIB_OK;
+    return read_flags(c) ? RBFIB_EREJECT : RBFIB_OK;
 }
 
 __global__ void k_add_lambda_bc(const RepDev *reps, const int *marker_body, const int *body_rep, int nm,
@@ -379,11 +389,82 @@ static void add_boundary_terms(Ctx &c, MarkerSet &ms, double *b) {
     if (!any) return;
     launch_wall_rhs(c, b);
     if (c.nm > 0) {
-        zero_device(c, c.slip_acc, 3LL * c.nm);
-        launch_interp_bc(c, ms, c.slip_acc, 1.0);
+        zero_device(c, c.jbc, 3LL * c.nm);
+        launch_interp_bc(c, ms, c.jbc, 1.0);
         hipLaunchKernelGGL(k_add_lambda_bc, dim3((3 * c.nm + 255) / 256), dim3(256), 0, c.stream, c.d_reps,
-                           c.d_marker_body, c.d_body_rep, c.nm, c.slip_acc, b);
+                           c.d_marker_body, c.d_body_rep, c.nm, c.jbc, b);
     }
+}
+
+// One SEM step for every replica (Algorithm 1); see include/rbfib.h.
+static int sem_step(Ctx &c, double *q, double *theta, const double *FT, const double *slip, double kT, double dt,
+                    uint64_t seed, uint64_t step, double *U, std::vector<rbfib_info> &out) {
+    const double delta = c.opts.rfd_delta;
+    out.assign(c.nrep, rbfib_info{0, 0.0, RBFIB_OK});
+    // configuration Q^n must be valid
+    if (build_markers(c, c.ms[0], q, theta, true) != RBFIB_OK) {
+        for (int r = 0; r < c.nrep; ++r) if (c.h_flags[r]) out[r].status = RBFIB_EREJECT;
+        return RBFIB_EREJECT;
+    }
+    std::vector<rbfib_info> inf;
+    // 1. random forces/torques and displaced configurations
+    launch_body_rfd(c, kT, delta, seed, step, q, theta);
+    // 2. RFD solve: force W^FT, homogeneous data
+    launch_zero(c, c.rhs, nullptr);
+    launch_set_rhs_U(c, c.WFT, c.rhs);
+    fgmres(c, c.ms[0], theta, c.rhs, false, inf);
+    for (int r = 0; r < c.nrep; ++r) { out[r].iters += inf[r].iters; if (inf[r].status) out[r].status = inf[r].status; }
+    HIP_OK(hipMemcpyAsync(c.xR, c.xsol, sizeof(double) * c.L, hipMemcpyDeviceToDevice, c.stream));
+    // 3. markers at Q+ and Q-
+    clear_flags(c);
+    launch_markers(c, c.ms[1], c.q_buf[0], c.th_buf[0]);
+    launch_markers(c, c.ms[2], c.q_buf[1], c.th_buf[1]);
+    // 4. unconstrained Stokes solve with (1/delta)[S(Q+) - S(Q-)] lambda^R
+    launch_zero(c, c.rhs, nullptr);
+    launch_spread(c, c.ms[1], c.xR, c.rhs, 1.0 / delta);
+    launch_spread(c, c.ms[2], c.xR, c.rhs, -1.0 / delta);
+    fgmres(c, c.ms[0], theta, c.rhs, true, inf);
+    for (int r = 0; r < c.nrep; ++r) { out[r].iters += inf[r].iters; if (inf[r].status) out[r].status = inf[r].status; }
+    HIP_OK(hipMemcpyAsync(c.xS, c.xsol, sizeof(double) * c.L, hipMemcpyDeviceToDevice, c.stream));
+    // 5. random finite differences of K, J (markers) and K^T (bodies)
+    launch_rfd_terms(c, delta);
+    launch_rfd_forces(c, delta, FT);
+    // 6. noisy constrained solve with the drift terms
+    launch_zero(c, c.rhs, nullptr);
+    if (kT > 0.0) launch_noise(c, kT, dt, seed, step, c.rhs, false);
+    launch_sem_rhs_lambda(c, slip, c.rhs);
+    launch_set_rhs_U(c, c.Fp, c.rhs);
+    add_boundary_terms(c, c.ms[0], c.rhs);
+    fgmres(c, c.ms[0], theta, c.rhs, false, inf);
+    for (int r = 0; r < c.nrep; ++r) {
+        out[r].iters += inf[r].iters;
+        out[r].rel_residual = inf[r].rel_residual;
+        if (inf[r].status) out[r].status = inf[r].status;
+    }
+    if (U) launch_copy_U(c, c.xsol, U, 1.0);
+    // 7. update and rejection (Q+-, Q^{n+1} outside, or bodies too close)
+    launch_update_positions(c, q, theta, c.xsol, dt);
+    launch_markers(c, c.ms[3], c.q_buf[2], c.th_buf[2]);
+    launch_body_distance(c, c.opts.min_body_dist);
+    // replicas whose solves failed keep their state as well
+    std::vector<int> bad(c.nrep, 0);
+    for (int r = 0; r < c.nrep; ++r) bad[r] = out[r].status != RBFIB_OK ? 4 : 0;
+    bool anybad = false;
+    for (int r = 0; r < c.nrep; ++r) anybad |= bad[r] != 0;
+    if (anybad) {
+        HIP_OK(hipMemcpyAsync(c.h_flags, c.d_flags, sizeof(int) * c.nrep, hipMemcpyDeviceToHost, c.stream));
+        HIP_OK(hipStreamSynchronize(c.stream));
+        for (int r = 0; r < c.nrep; ++r) c.h_flags[r] |= bad[r];
+        HIP_OK(hipMemcpyAsync(c.d_flags, c.h_flags, sizeof(int) * c.nrep, hipMemcpyHostToDevice, c.stream));
+    }
+    launch_commit_positions(c, q, theta);
+    read_flags(c);
+    int ret = RBFIB_OK;
+    for (int r = 0; r < c.nrep; ++r) {
+        if (c.h_flags[r] & 3) out[r].status = RBFIB_EREJECT;
+        if (out[r].status != RBFIB_OK && ret == RBFIB_OK) ret = out[r].status;
+    }
+    return ret;
 }
 
 // ------------------------------------------------------------------ context construction
@@ -644,8 +725,8 @@ static void build(Ctx &c, int nrep, const rbfib_grid *grids, const rbfib_bodies 
         ms.n_active = dalloc<int>(1);
         zero_device(c, ms.n_active, 1);
     }
-    c.d_flags = dalloc<int>(4);
-    HIP_OK(hipHostMalloc((void **)&c.h_flags, sizeof(int) * 4, hipHostMallocDefault));
+    c.d_flags = dalloc<int>(std::max(nrep, 4));
+    HIP_OK(hipHostMalloc((void **)&c.h_flags, sizeof(int) * std::max(nrep, 4), hipHostMallocDefault));
     HIP_OK(hipHostMalloc((void **)&c.h_count, sizeof(int), hipHostMallocDefault));
     c.d_count = dalloc<int>(1);
 
@@ -698,6 +779,7 @@ static void build(Ctx &c, int nrep, const rbfib_grid *grids, const rbfib_bodies 
     c.Fp = dalloc<double>(6 * (size_t)std::max(c.nb, 1));
     c.UR = dalloc<double>(6 * (size_t)std::max(c.nb, 1));
     c.slip_acc = dalloc<double>(3 * (size_t)std::max(c.nm, 1));
+    c.jbc = dalloc<double>(3 * (size_t)std::max(c.nm, 1));
     for (int cls = 0; cls < 2; ++cls) {
         c.timing.ev[cls].resize(8192);
         for (auto &e : c.timing.ev[cls]) HIP_OK(hipEventCreate(&e));
@@ -725,7 +807,7 @@ static void free_all(Ctx &c) {
     F(c.H); F(c.cs); F(c.sn); F(c.gv); F(c.beta0); F(c.hcol); F(c.yv); F(c.d_resid);
     F(c.active); F(c.cyc_active); F(c.jf); F(c.status); F(c.iters);
     for (int k = 0; k < 3; ++k) { F(c.q_buf[k]); F(c.th_buf[k]); }
-    F(c.Wf); F(c.Wt); F(c.WFT); F(c.Fp); F(c.UR); F(c.slip_acc);
+    F(c.Wf); F(c.Wt); F(c.WFT); F(c.Fp); F(c.UR); F(c.slip_acc); F(c.jbc);
     for (int cls = 0; cls < 2; ++cls)
         for (auto &e : c.timing.ev[cls]) (void)hipEventDestroy(e);
 }
@@ -746,7 +828,7 @@ extern "C" {
 void rbfib_default_opts(rbfib_opts *o) {
     if (!o) return;
     o->tol = 1e-6;
-    o->restart = 30;
+    o->restart = 50;
     o->max_iter = 600;
     o->precond_fp32 = 0;
     o->mg_sweeps = 2;
@@ -927,9 +1009,15 @@ int rbfib_fluctuating_stress(rbfib_ctx *ctx, double kT, double dt, uint64_t seed
 
 int rbfib_sem_step(rbfib_ctx *ctx, double *q, double *theta, const double *FT, const double *slip, double kT, double dt,
                    uint64_t seed, uint64_t step, double *U, rbfib_info *info) {
-    (void)ctx; (void)q; (void)theta; (void)FT; (void)slip; (void)kT; (void)dt; (void)seed; (void)step; (void)U; (void)info;
-    g_last_error = "rbfib_sem_step: not available in this build";
-    return RBFIB_EINVAL;
+    if (!ctx || !(dt > 0.0) || !(kT >= 0.0) || (ctx->c.nb > 0 && (!q || !theta))) return RBFIB_EINVAL;
+    GUARD_BEGIN
+    Ctx &c = ctx->c;
+    std::vector<rbfib_info> inf;
+    int code = sem_step(c, q, theta, FT, slip, kT, dt, seed, step, U, inf);
+    HIP_OK(hipStreamSynchronize(c.stream));
+    if (info) for (int r = 0; r < c.nrep; ++r) info[r] = inf[r];
+    return code;
+    GUARD_END
 }
 
 int rbfib_mobility_vjp(rbfib_ctx *ctx, const double *q, const double *theta, const double *FT, const double *Ubar,
