@@ -1,18 +1,20 @@
 """Benchmark of the RB-FIB mobility-solve hot path on one MI355X.
 
-Workload (default): two 42-marker spheres of radius 2.5 h tightly confined in a
-32 x 32 x 64 walled box, kT = 1, dt = 0.01, soft steric repulsion between the
-spheres and with the walls, fluctuating stress on cells and edges, and one
-Split-Euler-Maruyama step per benchmark step (Algorithm 1: two constrained
-mobility solves and one unconstrained Stokes solve, each to a relative
-residual of 1e-6).  Inputs are seeded and synthetic, and resident in GPU
-memory before the timed region.
+Headline workload: an ensemble of 256 independent walled boxes (edge drawn from
+16/24/32/48 cells, h = 1, viscosity 1) holding 1-4 spheres of 42 markers and
+radius 2.5 h each, kT = 1, dt = 0.01, soft steric repulsion, fluctuating
+stress on cells and edges.  One benchmark step advances every replica by one
+Split-Euler-Maruyama step (Algorithm 1: two constrained mobility solves and
+one unconstrained Stokes solve per replica, each to a relative residual of
+1e-6) in one batched launch sequence with the FP32 multigrid preconditioner
+and captured HIP graphs.  "plain_fp64" solves the same replicas one at a time
+with the FP64 preconditioner on the same GPU; "two_spheres" is the 32x32x64
+two-sphere box of the paper's tight-cavity example, one replica.
 
-The JSON line reports constrained mobility solves per second with the FP32
-multigrid preconditioner (the headline), the same workload with the FP64
-preconditioner ("plain_fp64"), a roofline object for the dominant kernel
-(timed with HIP events inside the library on its own stream), and the FP64
-CPU oracle timed on a bounded sample of the same workload.
+Inputs are seeded and synthetic, and resident in GPU memory before the timed
+region.  The roofline object is for the dominant kernel class, timed with HIP
+events inside the library on its own stream in a short eager run; the CPU
+baseline is the FP64 oracle's SEM step on a bounded sample of replicas.
 """
 import argparse
 import json
@@ -79,24 +81,63 @@ def soft_forces_np(q, radius, n, h, kT):
     return F
 
 
-# ----------------------------------------------------------------- GPU run
-def run_gpu(w, steps, warmup, fp32, seed=2024, timing=False):
+# ----------------------------------------------------------------- GPU runs
+class Ensemble:
+    """Concatenated replicas plus per-body data for the caller-side forces."""
+
+    def __init__(self, ws):
+        import torch
+        self.ws = ws
+        self.nb = sum(w.nb for w in ws)
+        self.q = torch.as_tensor(np.concatenate([w.q for w in ws]), dtype=torch.float64).cuda().contiguous()
+        self.th = torch.as_tensor(np.concatenate([w.theta for w in ws]), dtype=torch.float64).cuda().contiguous()
+        rep = np.concatenate([np.full(w.nb, r) for r, w in enumerate(ws)])
+        box = np.concatenate([np.tile(np.array(w.n, dtype=float) * w.h, (w.nb, 1)) for w in ws])
+        self.rep = torch.as_tensor(rep).cuda()
+        self.box = torch.as_tensor(box, dtype=torch.float64).cuda()
+        self.R = float(ws[0].radius[0])
+        self.kT = ws[0].kT
+        self.dt = ws[0].dt
+
+    def forces(self):
+        """Soft steric forces, pairs only within a replica (see soft_forces_torch)."""
+        import torch
+        q = self.q
+        phi0 = 4.0 * self.kT
+        b = 0.1 * self.R
+
+        def mag(r, d):
+            return torch.where(r < d, torch.full_like(r, phi0) / b, (phi0 / b) * torch.exp((d - r) / b))
+
+        F = torch.zeros((self.nb, 6), dtype=q.dtype, device=q.device)
+        F[:, :3] += mag(q, self.R) - mag(self.box - q, self.R)
+        # bodies of one replica are contiguous: loop over the (<= 4) partner offsets
+        for o in range(1, 4):
+            if o >= self.nb:
+                break
+            same = self.rep[o:] == self.rep[:-o]
+            d = q[:-o] - q[o:]
+            r = torch.linalg.norm(d, dim=1).clamp_min(1e-12)
+            f = torch.where(same[:, None], mag(r, 2 * self.R)[:, None] * d / r[:, None], torch.zeros_like(d))
+            F[:-o, :3] += f
+            F[o:, :3] -= f
+        return F
+
+
+def run_gpu(ws, steps, warmup, fp32, seed=2024, timing=False, graphs=True):
     import torch
     import paper_1901_06427_amd as rb
     from tests.helpers import lib_context
-    ctx = lib_context(rb, w, tol=w.tol, precond_fp32=fp32, min_body_dist=0.0)
-    q = torch.as_tensor(w.q, dtype=torch.float64).cuda().contiguous()
-    th = torch.as_tensor(w.theta, dtype=torch.float64).cuda().contiguous()
-    U = torch.empty((w.nb, 6), dtype=torch.float64, device="cuda")
-    R = float(w.radius[0])
+    E = Ensemble(ws)
+    ctx = lib_context(rb, ws, tol=ws[0].tol, precond_fp32=fp32, use_graphs=int(graphs and not timing))
+    U = torch.empty((E.nb, 6), dtype=torch.float64, device="cuda")
     step_id = 0
     iters = 0
     rejected = 0
 
     def one():
         nonlocal step_id, iters, rejected
-        F = soft_forces_torch(q, R, w.n, w.h, w.kT)
-        info = rb.rbfib_sem_step(ctx, q, th, F, w.kT, w.dt, seed, step_id, U)
+        info = rb.rbfib_sem_step(ctx, E.q, E.th, E.forces(), E.kT, E.dt, seed, step_id, U)
         step_id += 1
         iters += sum(i.iters for i in info)
         rejected += sum(1 for i in info if i.status == rb.RBFIB_EREJECT)
@@ -118,26 +159,35 @@ def run_gpu(w, steps, warmup, fp32, seed=2024, timing=False):
         for which, name in ((0, "mac_saddle_apply"), (1, "mg_smooth_level0")):
             avg_ms, nbytes, launches = rb.rbfib_kernel_stats(ctx, which)
             stats[name] = (avg_ms, nbytes, launches)
-    out = {"seconds": t1 - t0, "steps": steps, "iters": iters, "rejected": rejected, "stats": stats}
     ctx.close()
-    return out
+    return {"seconds": t1 - t0, "steps": steps, "iters": iters, "rejected": rejected, "stats": stats,
+            "replicas": len(ws)}
+
+
+def run_plain(ws, warmup=1, seed=2024):
+    """The same replicas one at a time, FP64 preconditioner, one SEM step each."""
+    total = 0.0
+    iters = 0
+    for w in ws:
+        r = run_gpu([w], 1, warmup, fp32=0, seed=seed, graphs=True)
+        total += r["seconds"]
+        iters += r["iters"]
+    return {"seconds": total, "steps": len(ws), "iters": iters}
 
 
 # ----------------------------------------------------------------- CPU oracle baseline
-def run_cpu_baseline(w, budget_s=20.0, seed=2024):
-    """The oracle's SEM step as it stands (FP64, solves to 1e-12), single thread."""
+def run_cpu_baseline(ws, budget_s=20.0, seed=2024):
+    """The oracle's SEM step as it stands (FP64, solves to 1e-12), single thread,
+    one step per replica in ensemble order until the time budget is used."""
     from threadpoolctl import threadpool_limits
     from oracle import mac, sem
-    g = mac.Grid(w.n, w.bc, w.h, w.eta, w.wall_vel)
-    q, th = w.q.copy(), w.theta.copy()
-    R = float(w.radius[0])
     n_steps = 0
     with threadpool_limits(limits=1):
         t0 = time.perf_counter()
-        while True:
-            F = soft_forces_np(q, R, w.n, w.h, w.kT)
-            res = sem.sem_step(g, w.r_ref, w.offsets, q, th, F, w.kT, w.dt, seed, n_steps)
-            q, th = res.q, res.theta
+        for w in ws:
+            g = mac.Grid(w.n, w.bc, w.h, w.eta, w.wall_vel)
+            F = soft_forces_np(w.q, float(w.radius[0]), w.n, w.h, w.kT)
+            sem.sem_step(g, w.r_ref, w.offsets, w.q, w.theta, F, w.kT, w.dt, seed, 0)
             n_steps += 1
             if time.perf_counter() - t0 > budget_s:
                 break
@@ -145,75 +195,92 @@ def run_cpu_baseline(w, budget_s=20.0, seed=2024):
     return {"steps": n_steps, "seconds": t1 - t0}
 
 
+def roofline_of(stats):
+    best = max(stats.items(), key=lambda kv: kv[1][0] * kv[1][2])
+    name, (avg_ms, nbytes, launches) = best
+    achieved = nbytes / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else 0.0
+    roof = {"bound": "hbm", "kernel": name, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "avg_us": round(avg_ms * 1e3, 2),
+            "bytes_per_launch": nbytes, "launches": launches}
+    others = {k: {"avg_us": round(v[0] * 1e3, 2), "launches": v[2],
+                  "GB/s": round(v[1] / (v[0] * 1e-3) / 1e9, 1) if v[0] > 0 else 0.0} for k, v in stats.items()}
+    return roof, others
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=40)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--plain-steps", type=int, default=None)
+    ap.add_argument("--steps", type=int, default=2, help="timed batched SEM launches")
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--replicas", type=int, default=256)
+    ap.add_argument("--plain-replicas", type=int, default=24, help="replicas timed one at a time")
+    ap.add_argument("--two-spheres-steps", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py measures one GPU: every box here has a single MI355X, and the hot path "
-              "(one confined suspension per device) is not sharded across GPUs; run with --gpus 1.",
-              file=sys.stderr)
+        print("bench.py measures one GPU: every box here has a single MI355X, and the replicas of the "
+              "ensemble share one device; run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
 
     import torch
     import workloads as W
-    w = W.two_spheres()
-    log("workload two_spheres: grid", w.n, "bodies", w.nb, "markers", w.nm)
+    ens = W.ensemble(n_replicas=args.replicas)
+    log("ensemble: %d replicas, %d bodies, %d markers" % (len(ens), sum(w.nb for w in ens), sum(w.nm for w in ens)))
 
-    fast = run_gpu(w, args.steps, args.warmup, fp32=1, timing=True)
-    plain = run_gpu(w, args.plain_steps or max(5, args.steps // 2), 2, fp32=0)
-    solves_per_step = 2
-    value = solves_per_step * fast["steps"] / fast["seconds"]
-    plain_value = solves_per_step * plain["steps"] / plain["seconds"]
-    log("fp32-pc: %.1f solves/s, %.1f iters/step; fp64-pc: %.1f solves/s" %
-        (value, fast["iters"] / fast["steps"], plain_value))
+    batched = run_gpu(ens, args.steps, args.warmup, fp32=1)
+    solves = 2 * batched["replicas"] * batched["steps"]
+    value = solves / batched["seconds"]
+    log("batched fp32-pc: %.1f solves/s (%.2f s per launch)" % (value, batched["seconds"] / batched["steps"]))
 
-    # roofline of the dominant kernel class (by measured total time)
-    st = fast["stats"]
-    best = max(st.items(), key=lambda kv: kv[1][0] * kv[1][2])
-    name, (avg_ms, nbytes, launches) = best
-    achieved = nbytes / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else 0.0
-    roofline = {"bound": "hbm", "kernel": name, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                "avg_us": round(avg_ms * 1e3, 2), "bytes_per_launch": nbytes, "launches": launches}
-    others = {k: {"avg_us": round(v[0] * 1e3, 2), "launches": v[2],
-                  "GB/s": round(v[1] / (v[0] * 1e-3) / 1e9, 1) if v[0] > 0 else 0.0} for k, v in st.items()}
+    plain = run_plain(ens[:args.plain_replicas])
+    plain_value = 2 * plain["steps"] / plain["seconds"]
+    log("plain fp64-pc, one replica at a time: %.1f solves/s" % plain_value)
+
+    timing = run_gpu(ens, 1, 0, fp32=1, timing=True)
+    roofline, kernels = roofline_of(timing["stats"])
+
+    w2 = W.two_spheres()
+    two = run_gpu([w2], args.two_spheres_steps, 2, fp32=1)
+    two_value = 2 * two["steps"] / two["seconds"]
+    log("two spheres: %.1f solves/s" % two_value)
 
     cpu = None
     if not args.no_cpu_baseline:
-        cb = run_cpu_baseline(w, args.cpu_budget)
-        cpu = {"value": round(solves_per_step * cb["steps"] / cb["seconds"], 4), "unit": "mobility solves/s",
-               "cores": 1, "kind": "oracle",
-               "sample": "%d SEM steps of the same workload (FP64 oracle, solves to 1e-12, 1 thread)" % cb["steps"]}
+        cb = run_cpu_baseline(ens, args.cpu_budget)
+        cpu = {"value": round(2 * cb["steps"] / cb["seconds"], 4), "unit": "mobility solves/s", "cores": 1,
+               "kind": "oracle",
+               "sample": "one SEM step on each of the first %d ensemble replicas (FP64 oracle, solves to 1e-12, "
+                         "1 thread)" % cb["steps"]}
 
-    ms_per_step = 1e3 * fast["seconds"] / fast["steps"]
+    n_cells = sum(int(np.prod(w.n)) for w in ens)
     line = {
         "metric": METRIC,
         "value": round(value, 3),
         "unit": "mobility solves/s",
         "n_gpus": 1,
-        "steps": fast["steps"],
+        "steps": batched["steps"],
         "warmup": args.warmup,
-        "ms_per_step": round(ms_per_step, 3),
+        "ms_per_step": round(1e3 * batched["seconds"] / batched["steps"], 3),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": "two_spheres_32x32x64_sem", "grid": list(w.n), "bodies": w.nb, "markers": w.nm,
-                   "kT": w.kT, "dt": w.dt, "tol": w.tol, "precond": "fp32 multigrid", "solves_per_step": 2,
-                   "fgmres_iters_per_step": round(fast["iters"] / fast["steps"], 2),
-                   "rejected_steps": fast["rejected"]},
+        "config": {"workload": "ensemble_256_walled_boxes_sem", "replicas": len(ens),
+                   "edges": [16, 24, 32, 48], "cells": n_cells, "bodies": sum(w.nb for w in ens),
+                   "markers": sum(w.nm for w in ens), "kT": 1.0, "dt": 0.01, "tol": 1e-6,
+                   "precond": "fp32 multigrid", "solves_per_step_per_replica": 2,
+                   "fgmres_iters_per_launch": round(batched["iters"] / batched["steps"], 1),
+                   "rejected": batched["rejected"]},
         "plain_fp64": {"value": round(plain_value, 3), "unit": "mobility solves/s",
-                       "fgmres_iters_per_step": round(plain["iters"] / plain["steps"], 2),
-                       "ratio_fp32pc_over_plain": round(value / plain_value, 3)},
+                       "sample": "first %d replicas, one SEM step each, solved one at a time" % plain["steps"],
+                       "ratio_batched_over_plain": round(value / plain_value, 3)},
+        "two_spheres": {"value": round(two_value, 3), "unit": "mobility solves/s", "grid": [32, 32, 64],
+                        "ms_per_step": round(1e3 * two["seconds"] / two["steps"], 3),
+                        "fgmres_iters_per_step": round(two["iters"] / two["steps"], 1)},
         "roofline": roofline,
-        "kernels": others,
+        "kernels": kernels,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

@@ -110,7 +110,7 @@ typedef struct {
 /* Solver options; rbfib_default_opts fills every field. */
 typedef struct {
     double tol;                /* relative residual ||b - A x|| / ||b||  (1e-6)      */
-    int restart;               /* FGMRES restart length (50)                         */
+    int restart;               /* FGMRES restart length (60)                         */
     int max_iter;              /* total iteration cap (600)                          */
     int precond_fp32;          /* 1: multigrid preconditioner in FP32 (0)            */
     int mg_sweeps;             /* damped-Jacobi sweeps before and after (2)          */
@@ -118,7 +118,9 @@ typedef struct {
     double blob_radius;        /* blob radius of the body block, units of h (1.25)   */
     double rfd_delta;          /* random-finite-difference delta (1e-5)              */
     double min_body_dist;      /* rejection distance between body centres (0 = off)  */
-    int check_every;           /* iterations between host convergence checks (4)    */
+    int check_every;           /* iterations between host convergence checks (5)    */
+    int use_graphs;            /* 1: replay each FGMRES iteration as a captured HIP  */
+                               /*    graph on the library's stream (1)               */
 } rbfib_opts;
 
 typedef struct {
@@ -201,14 +203,18 @@ int rbfib_sem_step(rbfib_ctx *ctx, double *q, double *theta, const double *FT,
                    const double *slip, double kT, double dt, uint64_t seed, uint64_t step,
                    double *U, rbfib_info *info);
 
-/* Vector-Jacobian product of U = N(q, theta) F (no slip, no wall motion):
- * given Ubar = dL/dU [nb, 6], returns dFT = dL/dF [nb, 6], dq = dL/dq [nb, 3]
- * and dphi [nb, 3], the gradient with respect to a lab-frame rotation vector
- * applied to each body.  Re-solves the forward problem (the Krylov basis is
+/* Vector-Jacobian product of U = N(q, theta) F (no slip, no wall motion;
+ * eqs. D1-D4 differentiated): given Ubar = dL/dU [nb, 6], returns
+ * dFT = dL/dF [nb, 6], dq = dL/dq [nb, 3], dphi [nb, 3] (gradient with respect
+ * to a lab-frame rotation vector applied to each body) and dtheta [nb, 4]
+ * (gradient with respect to the unit quaternion, tangent to the unit sphere).
+ * Any output may be NULL.  Re-solves the forward problem (the Krylov basis is
  * recomputed, not stored) and solves the adjoint system, which has the same
- * operator. */
+ * operator; the body-position gradient enters through the derivative of the
+ * kernel in J (and S = J^T / dV).  info: iterations of both solves, the larger
+ * of the two residuals. */
 int rbfib_mobility_vjp(rbfib_ctx *ctx, const double *q, const double *theta, const double *FT,
-                       const double *Ubar, double *dFT, double *dq, double *dphi,
+                       const double *Ubar, double *dFT, double *dq, double *dphi, double *dtheta,
                        rbfib_info *info);
 
 /* Average duration (ms) of the dominant kernel class over the last solve,

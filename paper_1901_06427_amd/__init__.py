@@ -50,7 +50,7 @@ class rbfib_opts(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("restart", ctypes.c_int), ("max_iter", ctypes.c_int),
                 ("precond_fp32", ctypes.c_int), ("mg_sweeps", ctypes.c_int), ("mg_omega", ctypes.c_double),
                 ("blob_radius", ctypes.c_double), ("rfd_delta", ctypes.c_double),
-                ("min_body_dist", ctypes.c_double), ("check_every", ctypes.c_int)]
+                ("min_body_dist", ctypes.c_double), ("check_every", ctypes.c_int), ("use_graphs", ctypes.c_int)]
 
 
 class rbfib_info(ctypes.Structure):
@@ -87,7 +87,7 @@ def _load():
         "rbfib_solve_mobility": (I, [P, P, P, P, P, I, P, P, ctypes.POINTER(rbfib_info)]),
         "rbfib_fluctuating_stress": (I, [P, D, D, U64, U64, P]),
         "rbfib_sem_step": (I, [P, P, P, P, P, D, D, U64, U64, P, ctypes.POINTER(rbfib_info)]),
-        "rbfib_mobility_vjp": (I, [P, P, P, P, P, P, P, P, ctypes.POINTER(rbfib_info)]),
+        "rbfib_mobility_vjp": (I, [P, P, P, P, P, P, P, P, P, ctypes.POINTER(rbfib_info)]),
         "rbfib_kernel_stats": (I, [P, I, ctypes.POINTER(D), ctypes.POINTER(D), ctypes.POINTER(ctypes.c_longlong)]),
         "rbfib_enable_timing": (I, [P, I]),
     }
@@ -257,13 +257,53 @@ def rbfib_sem_step(ctx: Context, q, theta, FT, kT: float, dt: float, seed: int, 
     return list(info)
 
 
-def rbfib_mobility_vjp(ctx: Context, q, theta, FT, Ubar, dFT, dq, dphi,
+def rbfib_mobility_vjp(ctx: Context, q, theta, FT, Ubar, dFT, dq, dphi, dtheta=None,
                        allow=(RBFIB_ENOCONV,)) -> List[rbfib_info]:
     info = _infos(ctx.nrep)
     code = _lib.rbfib_mobility_vjp(ctx.h, _ptr(q), _ptr(theta), _ptr(FT), _ptr(Ubar), _ptr(dFT), _ptr(dq),
-                                   _ptr(dphi), info)
+                                   _ptr(dphi), _ptr(dtheta), info)
     _check(code, "rbfib_mobility_vjp", allow)
     return list(info)
+
+
+def _mobility_function():
+    import torch
+
+    class MobilitySolve(torch.autograd.Function):
+        """U = N(q, theta) F through rbfib_solve_mobility; backward through
+        rbfib_mobility_vjp (gradients for q, theta and F)."""
+
+        @staticmethod
+        def forward(fctx, lib_ctx, q, theta, FT):
+            q, theta, FT = q.contiguous(), theta.contiguous(), FT.contiguous()
+            U = torch.empty_like(FT)
+            rbfib_solve_mobility(lib_ctx, q, theta, FT, U, include_bc=False, allow=())
+            fctx.lib_ctx = lib_ctx
+            fctx.save_for_backward(q, theta, FT)
+            return U
+
+        @staticmethod
+        def backward(fctx, Ubar):
+            q, theta, FT = fctx.saved_tensors
+            dFT = torch.empty_like(FT)
+            dq = torch.empty_like(q)
+            dphi = torch.empty_like(q)
+            dth = torch.empty_like(theta)
+            rbfib_mobility_vjp(fctx.lib_ctx, q, theta, FT, Ubar.contiguous(), dFT, dq, dphi, dth, allow=())
+            return None, dq, dth, dFT
+
+    return MobilitySolve
+
+
+_MOBILITY = None
+
+
+def mobility_solve(ctx: Context, q, theta, FT):
+    """Differentiable U = N(q, theta) F (torch.autograd.Function over the C ABI)."""
+    global _MOBILITY
+    if _MOBILITY is None:
+        _MOBILITY = _mobility_function()
+    return _MOBILITY.apply(ctx, q, theta, FT)
 
 
 def rbfib_enable_timing(ctx: Context, on: bool = True):

@@ -19,7 +19,7 @@
 #define RB_MAXLEV 12
 #define RB_TILE 4
 #define RB_BLOCK 256
-#define RB_CHUNK 2048          // Krylov elements per block (RB_BLOCK * 8)
+#define RB_CHUNK 1024          // Krylov elements per block (RB_BLOCK * 4)
 
 namespace rb {
 
@@ -190,6 +190,36 @@ __device__ __forceinline__ double interp_comp(const RepDev &R, const double *rm,
     return acc;
 }
 
+// Gradient with respect to the marker position of (J u)_c: the derivative along
+// axis a replaces phi_a by phi_a' / h; fold signs and indices are fixed within each
+// smooth piece of the kernel.
+__device__ __forceinline__ void interp_grad(const RepDev &R, const double *rm, int c, const double *u, double g[3]) {
+    int idx[3][4], cr[3][4];
+    double w[3][4], dw[3][4];
+    for (int a = 0; a < 3; ++a) {
+        double s = rm[a] * R.inv_h - (a == c ? 0.0 : 0.5);
+        int b = (int)floor(s) - 1;
+        for (int q = 0; q < 4; ++q) {
+            int p = b + q;
+            double sg;
+            bool ok = fold_index(p, R.n[a], R.bc[a], a == c, idx[a][q], sg, cr[a][q]);
+            w[a][q] = ok ? sg * phi4(s - (double)p) : 0.0;
+            dw[a][q] = ok ? sg * dphi4(s - (double)p) * R.inv_h : 0.0;
+        }
+    }
+    g[0] = g[1] = g[2] = 0.0;
+    for (int z = 0; z < 4; ++z)
+        for (int y = 0; y < 4; ++y) {
+            long long row = (long long)R.n[0] * ((long long)idx[1][y] + (long long)R.n[1] * idx[2][z]);
+            for (int x = 0; x < 4; ++x) {
+                double v = u[row + idx[0][x]];
+                g[0] += dw[0][x] * w[1][y] * w[2][z] * v;
+                g[1] += w[0][x] * dw[1][y] * w[2][z] * v;
+                g[2] += w[0][x] * w[1][y] * dw[2][z] * v;
+            }
+        }
+}
+
 // ---------------------------------------------------------------- host context
 struct MarkerSet {
     double *r = nullptr;      // [nm, 3]
@@ -212,7 +242,13 @@ struct Timing {
 };
 
 struct Ctx {
-    hipStream_t stream = nullptr;
+    hipStream_t stream = nullptr;        // library-owned stream (default priority) all work runs on
+    hipStream_t user_stream = nullptr;   // caller's stream, ordered against ours with events
+    hipEvent_t ev_in = nullptr, ev_out = nullptr;
+    std::vector<hipGraphExec_t> graphs[2];   // one captured FGMRES iteration per (fluid_only, j)
+    double graph_tol = -1.0;                 // tolerance baked into the captured graphs
+    double *theta_int = nullptr;             // [nb, 4] orientation copy read by the preconditioner
+    const int *mask = nullptr;               // replica mask for grid/body kernels (null = all)
     rbfib_opts opts;
     int nrep = 0;
     std::vector<RepDev> reps;
@@ -310,7 +346,9 @@ void launch_body_distance(Ctx &c, double dmin);
 void launch_sem_rhs_lambda(Ctx &c, const double *slip, double *b);
 void launch_update_positions(Ctx &c, const double *q, const double *theta, const double *U, double dt);
 void launch_commit_positions(Ctx &c, double *q, double *theta);
-void launch_body_gradient(Ctx &c, MarkerSet &ms, const double *x, const double *xa, double *dq, double *dphi);
+void launch_body_grad(Ctx &c, const double *x, const double *xa, const double *theta, double *dFT, double *dq,
+                      double *dphi, double *dtheta);
+void launch_set_rhs_adjoint(Ctx &c, const double *Ubar, double *b);
 void launch_copy_U(Ctx &c, const double *x, double *U, double scale);
 void launch_set_rhs(Ctx &c, const double *FT, const double *slip, double *b);
 
@@ -318,6 +356,8 @@ void launch_set_rhs(Ctx &c, const double *FT, const double *slip, double *b);
 void launch_dots(Ctx &c, const double *V, int nvec, const double *w, double *out /*[nrep*(m+1)]*/, const int *mask);
 void launch_axpy_multi(Ctx &c, const double *V, int nvec, const double *coef, double *w, double sign, const int *mask);
 void launch_norm(Ctx &c, const double *w, double *out, const int *mask);
+void launch_axpy_multi_norm(Ctx &c, const double *V, int nvec, const double *coef, double *w, double *nrm,
+                            const int *mask);
 void launch_scale(Ctx &c, const double *w, const double *s, double *out, const int *mask, bool inverse);
 void launch_axpby(Ctx &c, double a, const double *x, double b, const double *y, double *out, const int *mask);
 void launch_copy(Ctx &c, const double *x, double *y, const int *mask);

@@ -70,8 +70,9 @@ __device__ __forceinline__ void unlin(long long lin, const int n[3], int idx[3])
 // ------------------------------------------------------------------ fused fluid apply
 // y_c = -eta Lm_c v + (G pi)_c for c = x, y, z;  y_pi = -(D v).  Pinned slots -> 0.
 __global__ void k_apply_fluid(const RepDev *reps, const BlockEnt *tab, const double *__restrict__ x,
-                              double *__restrict__ y) {
+                              double *__restrict__ y, const int *__restrict__ mask) {
     BlockEnt be = tab[blockIdx.x];
+    if (mask && !mask[be.rep]) return;
     const RepDev &R = reps[be.rep];
     long long lin = be.start + threadIdx.x;
     long long N = R.N;
@@ -114,15 +115,16 @@ __global__ void k_apply_fluid(const RepDev *reps, const BlockEnt *tab, const dou
 
 void launch_apply_fluid(Ctx &c, const double *x, double *y) {
     hipLaunchKernelGGL(k_apply_fluid, dim3(c.n_tab_cells), dim3(RB_BLOCK), 0, c.stream, c.d_reps, c.d_tab_cells,
-                       x, y);
+                       x, y, c.mask);
 }
 
 // ------------------------------------------------------------------ multigrid
 // Level pools hold 4 fields per (replica, level): comp c at lev.off + c * lev.N.
 template <typename T>
 __global__ void k_to_level0(const RepDev *reps, const LevDev *levs, const BlockEnt *tab, const double *src,
-                            T *b, int c0) {
+                            T *b, int c0, const int *__restrict__ mask) {
     BlockEnt be = tab[blockIdx.x];
+    if (mask && !mask[be.rep]) return;
     int comp = c0 + blockIdx.y;
     const RepDev &R = reps[be.rep];
     long long lin = be.start + threadIdx.x;
@@ -134,15 +136,16 @@ __global__ void k_to_level0(const RepDev *reps, const LevDev *levs, const BlockE
 template <typename T>
 void launch_to_level0(Ctx &c, const double *src, T *b, int c0, int nc) {
     hipLaunchKernelGGL(k_to_level0<T>, dim3(c.n_tab_cells, nc), dim3(RB_BLOCK), 0, c.stream, c.d_reps, c.d_levs,
-                       c.d_tab_cells, src, b, c0);
+                       c.d_tab_cells, src, b, c0, c.mask);
 }
 
 // Operator of component comp at a level: A = -eta Lm (velocity) or -L (pressure).
 template <typename T>
 __global__ void k_smooth(const RepDev *reps, const LevDev *levs, const BlockEnt *tab, int lev, int c0,
                          const T *__restrict__ xin, T *__restrict__ xout, const T *__restrict__ b, double omega,
-                         int first) {
+                         int first, const int *__restrict__ mask) {
     BlockEnt be = tab[blockIdx.x];
+    if (mask && !mask[be.rep]) return;
     int comp = c0 + blockIdx.y;
     const RepDev &R = reps[be.rep];
     const LevDev &Lv = levs[be.rep * RB_MAXLEV + lev];
@@ -179,7 +182,7 @@ template <typename T>
 void launch_smooth(Ctx &c, int lev, int c0, int nc, const T *xin, T *xout, const T *b, bool first) {
     if (c.n_tab_lev[lev] == 0) return;
     hipLaunchKernelGGL(k_smooth<T>, dim3(c.n_tab_lev[lev], nc), dim3(RB_BLOCK), 0, c.stream, c.d_reps, c.d_levs,
-                       c.d_tab_lev[lev], lev, c0, xin, xout, b, c.opts.mg_omega, first ? 1 : 0);
+                       c.d_tab_lev[lev], lev, c0, xin, xout, b, c.opts.mg_omega, first ? 1 : 0, c.mask);
 }
 
 // Residual of level lev restricted to level lev+1: face-normal axis full weighting
@@ -198,8 +201,9 @@ __device__ T residual_at(const RepDev &R, const LevDev &Lv, int comp, int i, int
 
 template <typename T>
 __global__ void k_restrict(const RepDev *reps, const LevDev *levs, const BlockEnt *tab, int lev, int c0,
-                           const T *__restrict__ x, const T *__restrict__ b, T *__restrict__ bc) {
+                           const T *__restrict__ x, const T *__restrict__ b, T *__restrict__ bc, const int *__restrict__ mask) {
     BlockEnt be = tab[blockIdx.x];
+    if (mask && !mask[be.rep]) return;
     int comp = c0 + blockIdx.y;
     const RepDev &R = reps[be.rep];
     const LevDev &F = levs[be.rep * RB_MAXLEV + lev];
@@ -248,7 +252,7 @@ void launch_restrict(Ctx &c, int lev, int c0, int nc, const T *x, const T *b, T 
     if (c.n_tab_lev[lev] == 0) return;
     // one thread per coarse point: use the table of level lev+1 restricted to replicas descending from lev
     hipLaunchKernelGGL(k_restrict<T>, dim3(c.n_tab_all[lev + 1], nc), dim3(RB_BLOCK), 0, c.stream, c.d_reps,
-                       c.d_levs, c.d_tab_all[lev + 1], lev, c0, x, b, bcoarse);
+                       c.d_levs, c.d_tab_all[lev + 1], lev, c0, x, b, bcoarse, c.mask);
 }
 
 // x_f += P x_c: face-normal axis linear (even faces copy, odd faces average),
@@ -256,8 +260,9 @@ void launch_restrict(Ctx &c, int lev, int c0, int nc, const T *x, const T *b, T 
 // even ghosts for pressure.
 template <typename T>
 __global__ void k_prolong(const RepDev *reps, const LevDev *levs, const BlockEnt *tab, int lev, int c0,
-                          const T *__restrict__ xc, T *__restrict__ xf) {
+                          const T *__restrict__ xc, T *__restrict__ xf, const int *__restrict__ mask) {
     BlockEnt be = tab[blockIdx.x];
+    if (mask && !mask[be.rep]) return;
     int comp = c0 + blockIdx.y;
     const RepDev &R = reps[be.rep];
     const LevDev &F = levs[be.rep * RB_MAXLEV + lev];
@@ -319,15 +324,16 @@ template <typename T>
 void launch_prolong(Ctx &c, int lev, int c0, int nc, const T *xc, T *xf) {
     if (c.n_tab_lev[lev] == 0) return;
     hipLaunchKernelGGL(k_prolong<T>, dim3(c.n_tab_lev[lev], nc), dim3(RB_BLOCK), 0, c.stream, c.d_reps, c.d_levs,
-                       c.d_tab_lev[lev], lev, c0, xc, xf);
+                       c.d_tab_lev[lev], lev, c0, xc, xf, c.mask);
 }
 
 // Dense coarsest solve x = Ainv b, one workgroup per (replica, component).
 template <typename T>
 __global__ void k_coarse(const RepDev *reps, const LevDev *levs, const BlockEnt *tab, int lev, int c0,
                          const long long *coff, const T *__restrict__ Ainv, const T *__restrict__ b,
-                         T *__restrict__ x) {
+                         T *__restrict__ x, const int *__restrict__ mask) {
     BlockEnt be = tab[blockIdx.x];
+    if (mask && !mask[be.rep]) return;
     int comp = c0 + blockIdx.y;
     const LevDev &Lv = levs[be.rep * RB_MAXLEV + lev];
     extern __shared__ unsigned char smem_raw[];
@@ -355,15 +361,16 @@ void launch_coarse(Ctx &c, int lev, int c0, int nc, const T *b, T *x) {
     if (c.n_tab_crs[lev] == 0) return;
     size_t sh = sizeof(T) * (size_t)c.max_coarse;
     hipLaunchKernelGGL(k_coarse<T>, dim3(c.n_tab_crs[lev], nc), dim3(RB_BLOCK), sh, c.stream, c.d_reps, c.d_levs,
-                       c.d_tab_crs[lev], lev, c0, c.d_coarse_off, coarse_pool<T>(c), b, x);
+                       c.d_tab_crs[lev], lev, c0, c.d_coarse_off, coarse_pool<T>(c), b, x, c.mask);
 }
 
 // ------------------------------------------------------------------ projection step
 // d = D x* + r_pi ;  b_p (level 0) = -d  (so that -L phi = -d) ;  z_pi = -eta d.
 template <typename T>
 __global__ void k_proj_div(const RepDev *reps, const LevDev *levs, const BlockEnt *tab, const T *__restrict__ xv,
-                           const double *__restrict__ r, T *__restrict__ bp, double *__restrict__ z) {
+                           const double *__restrict__ r, T *__restrict__ bp, double *__restrict__ z, const int *__restrict__ mask) {
     BlockEnt be = tab[blockIdx.x];
+    if (mask && !mask[be.rep]) return;
     const RepDev &R = reps[be.rep];
     const LevDev &Lv = levs[be.rep * RB_MAXLEV];
     long long lin = be.start + threadIdx.x;
@@ -390,14 +397,15 @@ __global__ void k_proj_div(const RepDev *reps, const LevDev *levs, const BlockEn
 template <typename T>
 void launch_proj_div(Ctx &c, const T *xv, const double *r, T *bp, double *z) {
     hipLaunchKernelGGL(k_proj_div<T>, dim3(c.n_tab_cells), dim3(RB_BLOCK), 0, c.stream, c.d_reps, c.d_levs,
-                       c.d_tab_cells, xv, r, bp, z);
+                       c.d_tab_cells, xv, r, bp, z, c.mask);
 }
 
 // z_v = x* - G phi  (phi in the pressure slot of the level-0 pool).
 template <typename T>
 __global__ void k_proj_correct(const RepDev *reps, const LevDev *levs, const BlockEnt *tab, const T *__restrict__ xv,
-                               const T *__restrict__ phi, double *__restrict__ z) {
+                               const T *__restrict__ phi, double *__restrict__ z, const int *__restrict__ mask) {
     BlockEnt be = tab[blockIdx.x];
+    if (mask && !mask[be.rep]) return;
     const RepDev &R = reps[be.rep];
     const LevDev &Lv = levs[be.rep * RB_MAXLEV];
     long long lin = be.start + threadIdx.x;
@@ -422,7 +430,7 @@ __global__ void k_proj_correct(const RepDev *reps, const LevDev *levs, const Blo
 template <typename T>
 void launch_proj_correct(Ctx &c, const T *xv, const T *phi, double *z) {
     hipLaunchKernelGGL(k_proj_correct<T>, dim3(c.n_tab_cells), dim3(RB_BLOCK), 0, c.stream, c.d_reps, c.d_levs,
-                       c.d_tab_cells, xv, phi, z);
+                       c.d_tab_cells, xv, phi, z, c.mask);
 }
 
 // ------------------------------------------------------------------ fluctuating stress

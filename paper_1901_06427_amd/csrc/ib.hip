@@ -180,7 +180,8 @@ __global__ __launch_bounds__(256) void k_spread(const RepDev *reps, const int *t
                                                 const int *n_active, const int *tile_start, const int *tile_count,
                                                 const int *perm, const double *__restrict__ r,
                                                 const double *__restrict__ lam_state, const int *marker_body,
-                                                const int *body_rep, double *__restrict__ y, double alpha) {
+                                                const int *body_rep, double *__restrict__ y, double alpha,
+                                                const int *__restrict__ mask) {
     __shared__ double Wt[SP_CHUNK][3][3][4];
     __shared__ double Ls[SP_CHUNK][3];
     __shared__ int Ms[SP_CHUNK];
@@ -190,6 +191,7 @@ __global__ __launch_bounds__(256) void k_spread(const RepDev *reps, const int *t
     int na = *n_active;
     for (int it = blockIdx.x; it < na; it += gridDim.x) {
         int t = active[it];
+        if (mask && !mask[tile_rep[t]]) continue;
         const RepDev &R = reps[tile_rep[t]];
         int lt = t - R.tile0;
         int tc[3] = {lt % R.tdim[0], (lt / R.tdim[0]) % R.tdim[1], lt / (R.tdim[0] * R.tdim[1])};
@@ -266,18 +268,20 @@ __global__ __launch_bounds__(256) void k_spread(const RepDev *reps, const int *t
 // y_fluid += alpha * S lambda, lambda read from the lambda slots of lam_state.
 void launch_spread(Ctx &c, MarkerSet &ms, const double *lam_state, double *y, double alpha) {
     if (c.nm == 0) return;
-    int grid = std::min(c.ntiles, 2048);
+    int grid = std::min(c.ntiles, 32768);   // grid-stride over the active tiles
     hipLaunchKernelGGL(k_spread, dim3(grid), dim3(256), 0, c.stream, c.d_reps, c.d_tile_rep, ms.active, ms.n_active,
                        ms.tile_start, ms.tile_count, ms.perm, ms.r, lam_state, c.d_marker_body, c.d_body_rep, y,
-                       alpha);
+                       alpha, c.mask);
 }
 
 // ------------------------------------------------------------------ J, K, K^T per body
 // y_lambda = -J v + K U ;  y_U = K^T lambda  (rows 3 and 4 of the saddle operator).
 __global__ void k_body_apply(const RepDev *reps, const int *body_rep, const int *body_off, const double *r,
-                             const double *d, const double *__restrict__ x, double *__restrict__ y) {
+                             const double *d, const double *__restrict__ x, double *__restrict__ y,
+                             const int *__restrict__ mask) {
     extern __shared__ double sred[];   // [nmp][6]
     int p = blockIdx.x;
+    if (mask && !mask[body_rep[p]]) return;
     const RepDev &R = reps[body_rep[p]];
     int m0 = body_off[p], m1 = body_off[p + 1], nmp = m1 - m0;
     long long lam0 = R.off + 4 * R.N;
@@ -315,7 +319,7 @@ void launch_body_apply(Ctx &c, MarkerSet &ms, const double *q, const double *x, 
     if (c.nb == 0) return;
     size_t sh = sizeof(double) * 6 * (size_t)c.max_body_nm;
     hipLaunchKernelGGL(k_body_apply, dim3(c.nb), dim3(128), sh, c.stream, c.d_reps, c.d_body_rep, c.d_body_off, ms.r,
-                       ms.d, x, y);
+                       ms.d, x, y, c.mask);
 }
 
 // ------------------------------------------------------------------ interpolation
@@ -381,9 +385,11 @@ void launch_interp_bc(Ctx &c, MarkerSet &ms, double *out, double alpha) {
 // reference body; rotated back to the lab frame.
 __global__ void k_body_precond(const RepDev *reps, const int *body_rep, const int *body_off, const int *body_shape,
                                const ShapeDev *shapes, const double *sdata, const double *theta,
-                               const double *__restrict__ rin, double *__restrict__ z) {
+                               const double *__restrict__ rin, double *__restrict__ z,
+                               const int *__restrict__ mask) {
     extern __shared__ double sm[];
     int p = blockIdx.x;
+    if (mask && !mask[body_rep[p]]) return;
     const RepDev &R = reps[body_rep[p]];
     const ShapeDev &S = shapes[body_shape[p]];
     int m0 = body_off[p], n3 = 3 * S.nm;
@@ -460,14 +466,14 @@ void launch_body_precond(Ctx &c, MarkerSet &ms, const double *theta, const doubl
     if (c.nb == 0) return;
     size_t sh = sizeof(double) * (size_t)(6 * c.max_body_nm + 12);
     hipLaunchKernelGGL(k_body_precond, dim3(c.nb), dim3(128), sh, c.stream, c.d_reps, c.d_body_rep, c.d_body_off,
-                       c.d_body_shape, c.d_shapes, c.d_shape_data, theta, r, z);
+                       c.d_body_shape, c.d_shapes, c.d_shape_data, theta, r, z, c.mask);
 }
 
 // ------------------------------------------------------------------ small helpers
 // zero the lambda and U slots of every replica
-__global__ void k_zero_bodies(const RepDev *reps, int nrep, double *y) {
+__global__ void k_zero_bodies(const RepDev *reps, int nrep, double *y, const int *__restrict__ mask) {
     int r = blockIdx.y;
-    if (r >= nrep) return;
+    if (r >= nrep || (mask && !mask[r])) return;
     const RepDev &R = reps[r];
     long long n = 3LL * R.nm + 6LL * R.nb;
     for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
@@ -475,7 +481,7 @@ __global__ void k_zero_bodies(const RepDev *reps, int nrep, double *y) {
 }
 
 void launch_zero_bodies(Ctx &c, double *y) {
-    hipLaunchKernelGGL(k_zero_bodies, dim3(4, c.nrep), dim3(256), 0, c.stream, c.d_reps, c.nrep, y);
+    hipLaunchKernelGGL(k_zero_bodies, dim3(4, c.nrep), dim3(256), 0, c.stream, c.d_reps, c.nrep, y, c.mask);
 }
 
 // b = [0 ; 0 ; -slip ; FT]  (fluid rows zeroed; boundary terms added separately)

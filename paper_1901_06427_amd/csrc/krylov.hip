@@ -8,64 +8,52 @@
 
 namespace rb {
 
-__device__ __forceinline__ double block_sum(double v, double *sh) {
+__device__ __forceinline__ double wave_sum(double v) {
     for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
-    int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    if (lane == 0) sh[wid] = v;
-    __syncthreads();
-    double s = 0.0;
-    if (threadIdx.x == 0) {
-        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) s += sh[w];
-    }
-    __syncthreads();
-    return s;   // valid in thread 0
+    return v;   // valid in lane 0
 }
 
-// partial[blk * stride + i] = sum over the block's chunk of V_i . w
+// partial[blk * stride + i] = sum over the block's chunk of V_i . w.  The chunk of w
+// is staged in LDS once; each wavefront then owns every fourth basis vector, so the
+// vector loop needs no block barrier.
 __global__ __launch_bounds__(RB_BLOCK) void k_dot_partial(const RepDev *reps, const BlockEnt *tab, const double *V,
                                                           long long L, int nvec, const double *__restrict__ w,
                                                           double *partial, int stride, const int *mask) {
-    __shared__ double sh[8];
+    __shared__ double ws[RB_CHUNK];
     BlockEnt be = tab[blockIdx.x];
     if (mask && !mask[be.rep]) return;
     const RepDev &R = reps[be.rep];
     long long b = R.off + be.start;
-    long long e = R.off + min(be.start + (long long)RB_CHUNK, R.len);
-    double wv[RB_CHUNK / RB_BLOCK];
-#pragma unroll
-    for (int k = 0; k < RB_CHUNK / RB_BLOCK; ++k) {
-        long long g = b + threadIdx.x + (long long)k * RB_BLOCK;
-        wv[k] = (g < e) ? w[g] : 0.0;
-    }
-    for (int i = 0; i < nvec; ++i) {
-        const double *Vi = V + (long long)i * L;
+    int n = (int)min((long long)RB_CHUNK, R.len - be.start);
+    for (int k = threadIdx.x; k < RB_CHUNK; k += RB_BLOCK) ws[k] = (k < n) ? w[b + k] : 0.0;
+    __syncthreads();
+    int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    for (int i = wid; i < nvec; i += RB_BLOCK / 64) {
+        const double *Vi = V + (long long)i * L + b;
         double acc = 0.0;
-#pragma unroll
-        for (int k = 0; k < RB_CHUNK / RB_BLOCK; ++k) {
-            long long g = b + threadIdx.x + (long long)k * RB_BLOCK;
-            if (g < e) acc += Vi[g] * wv[k];
-        }
-        double s = block_sum(acc, sh);
-        if (threadIdx.x == 0) partial[(long long)blockIdx.x * stride + i] = s;
+        for (int k = lane; k < n; k += 64) acc += Vi[k] * ws[k];
+        acc = wave_sum(acc);
+        if (lane == 0) partial[(long long)blockIdx.x * stride + i] = acc;
     }
 }
 
-__global__ void k_dot_reduce(const int *first, const int *nblk, int nvec, const double *partial, int stride,
-                             double *out, int out_stride, const int *mask, int take_sqrt) {
-    int r = blockIdx.x;
+// out[r * out_stride + i] = sum of replica r's block partials of vector i, one
+// wavefront per (replica, vector), fixed summation order.
+__global__ void k_dot_reduce(const int *first, const int *nblk, const double *partial, int stride, double *out,
+                             int out_stride, const int *mask, int take_sqrt) {
+    int r = blockIdx.x, i = blockIdx.y;
     if (mask && !mask[r]) return;
-    for (int i = threadIdx.x; i < nvec; i += blockDim.x) {
-        double s = 0.0;
-        for (int b = 0; b < nblk[r]; ++b) s += partial[(long long)(first[r] + b) * stride + i];
-        out[(long long)r * out_stride + i] = take_sqrt ? sqrt(s) : s;
-    }
+    double s = 0.0;
+    for (int b = threadIdx.x; b < nblk[r]; b += 64) s += partial[(long long)(first[r] + b) * stride + i];
+    s = wave_sum(s);
+    if (threadIdx.x == 0) out[(long long)r * out_stride + i] = take_sqrt ? sqrt(s) : s;
 }
 
 void launch_dots(Ctx &c, const double *V, int nvec, const double *w, double *out, const int *mask) {
     int stride = c.m + 1;
     hipLaunchKernelGGL(k_dot_partial, dim3(c.n_tab_vec), dim3(RB_BLOCK), 0, c.stream, c.d_reps, c.d_tab_vec, V, c.L,
                        nvec, w, c.partial, stride, mask);
-    hipLaunchKernelGGL(k_dot_reduce, dim3(c.nrep), dim3(64), 0, c.stream, c.d_vec_first, c.d_vec_nblk, nvec,
+    hipLaunchKernelGGL(k_dot_reduce, dim3(c.nrep, nvec), dim3(64), 0, c.stream, c.d_vec_first, c.d_vec_nblk,
                        c.partial, stride, out, c.m + 1, mask, 0);
 }
 
@@ -73,32 +61,59 @@ void launch_norm(Ctx &c, const double *w, double *out, const int *mask) {
     int stride = c.m + 1;
     hipLaunchKernelGGL(k_dot_partial, dim3(c.n_tab_vec), dim3(RB_BLOCK), 0, c.stream, c.d_reps, c.d_tab_vec, w, c.L,
                        1, w, c.partial, stride, mask);
-    hipLaunchKernelGGL(k_dot_reduce, dim3(c.nrep), dim3(64), 0, c.stream, c.d_vec_first, c.d_vec_nblk, 1, c.partial,
+    hipLaunchKernelGGL(k_dot_reduce, dim3(c.nrep, 1), dim3(64), 0, c.stream, c.d_vec_first, c.d_vec_nblk, c.partial,
                        stride, out, 1, mask, 1);
 }
 
-// w += sign * sum_i coef[r][i] V_i
+// w += sign * sum_i coef[r][i] V_i ; when norm_out is given, also the norm of the
+// updated w (block partials reduced by k_dot_reduce).
 __global__ __launch_bounds__(RB_BLOCK) void k_axpy_multi(const RepDev *reps, const BlockEnt *tab, const double *V,
                                                          long long L, int nvec, const double *coef, int cstride,
-                                                         double *__restrict__ w, double sign, const int *mask) {
+                                                         double *__restrict__ w, double sign, const int *mask,
+                                                         double *partial, int stride) {
+    __shared__ double cf[RB_BLOCK];   // restart length <= 200 < RB_BLOCK
+    __shared__ double red[RB_BLOCK / 64];
     BlockEnt be = tab[blockIdx.x];
     if (mask && !mask[be.rep]) return;
     const RepDev &R = reps[be.rep];
+    if (threadIdx.x < nvec) cf[threadIdx.x] = sign * coef[(long long)be.rep * cstride + threadIdx.x];
+    __syncthreads();
     long long b = R.off + be.start;
-    long long e = R.off + min(be.start + (long long)RB_CHUNK, R.len);
-    const double *cf = coef + (long long)be.rep * cstride;
-    for (int k = 0; k < RB_CHUNK / RB_BLOCK; ++k) {
-        long long g = b + threadIdx.x + (long long)k * RB_BLOCK;
-        if (g >= e) break;
+    int n = (int)min((long long)RB_CHUNK, R.len - be.start);
+    double sq = 0.0;
+    for (int k = threadIdx.x; k < n; k += RB_BLOCK) {
+        long long g = b + k;
         double acc = 0.0;
         for (int i = 0; i < nvec; ++i) acc += cf[i] * V[(long long)i * L + g];
-        w[g] += sign * acc;
+        double v = w[g] + acc;
+        w[g] = v;
+        sq += v * v;
+    }
+    if (partial) {
+        sq = wave_sum(sq);
+        if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = sq;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double s = 0.0;
+            for (int k = 0; k < RB_BLOCK / 64; ++k) s += red[k];
+            partial[(long long)blockIdx.x * stride] = s;
+        }
     }
 }
 
 void launch_axpy_multi(Ctx &c, const double *V, int nvec, const double *coef, double *w, double sign, const int *mask) {
     hipLaunchKernelGGL(k_axpy_multi, dim3(c.n_tab_vec), dim3(RB_BLOCK), 0, c.stream, c.d_reps, c.d_tab_vec, V, c.L,
-                       nvec, coef, c.m + 1, w, sign, mask);
+                       nvec, coef, c.m + 1, w, sign, mask, (double *)nullptr, 0);
+}
+
+// w -= sum_i coef_i V_i and nrm[r] = ||w|| in two launches.
+void launch_axpy_multi_norm(Ctx &c, const double *V, int nvec, const double *coef, double *w, double *nrm,
+                            const int *mask) {
+    int stride = c.m + 1;
+    hipLaunchKernelGGL(k_axpy_multi, dim3(c.n_tab_vec), dim3(RB_BLOCK), 0, c.stream, c.d_reps, c.d_tab_vec, V, c.L,
+                       nvec, coef, c.m + 1, w, -1.0, mask, c.partial, stride);
+    hipLaunchKernelGGL(k_dot_reduce, dim3(c.nrep, 1), dim3(64), 0, c.stream, c.d_vec_first, c.d_vec_nblk, c.partial,
+                       stride, nrm, 1, mask, 1);
 }
 
 // out = w * s[r]  (or w / s[r] when inverse; a zero divisor leaves out unchanged)

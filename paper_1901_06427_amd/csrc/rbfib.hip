@@ -232,7 +232,7 @@ template <typename T>
 static void precond_t(Ctx &c, MarkerSet &ms, const double *theta, const double *r, double *z, bool fluid_only) {
     bool bodies = !fluid_only && c.nb > 0;
     if (bodies) launch_body_precond(c, ms, theta, r, z);
-    launch_copy(c, r, c.fluid_tmp, nullptr);
+    launch_copy(c, r, c.fluid_tmp, c.mask);
     if (bodies) launch_spread(c, ms, z, c.fluid_tmp, 1.0);
     T *X = (T *)c.mg_x, *B = (T *)c.mg_b;
     launch_to_level0<T>(c, c.fluid_tmp, B, 0, 3);
@@ -264,6 +264,13 @@ __global__ void k_count(int nrep, const int *active, int *out) {
     *out = s;
 }
 
+__global__ void k_recheck(int nrep, const double *resid, const double *beta0, double tol, int *active,
+                          const int *status) {
+    int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= nrep || status[r] != RBFIB_OK || active[r]) return;
+    if (beta0[r] > 0.0 && resid[r] > tol * beta0[r]) active[r] = 1;
+}
+
 static int count_active(Ctx &c) {
     hipLaunchKernelGGL(k_count, dim3(1), dim3(1), 0, c.stream, c.nrep, c.active, c.d_count);
     HIP_OK(hipMemcpyAsync(c.h_count, c.d_count, sizeof(int), hipMemcpyDeviceToHost, c.stream));
@@ -288,37 +295,84 @@ static void fgmres(Ctx &c, MarkerSet &ms, const double *theta, const double *b, 
     int total = 0;
     int check = std::max(1, c.opts.check_every);
     bool done = count_active(c) == 0;
-    while (!done) {
-        for (int j = 0; j < m; ++j) {
-            double *Vj = c.V + (long long)j * c.L, *Zj = c.Z + (long long)j * c.L;
-            precond(c, ms, theta, Vj, Zj, fluid_only);
-            apply_op(c, ms, Zj, c.W, fluid_only);
-            launch_dots(c, c.V, j + 1, c.W, h1, c.active);
-            launch_axpy_multi(c, c.V, j + 1, h1, c.W, -1.0, c.active);
-            launch_dots(c, c.V, j + 1, c.W, h2, c.active);
-            launch_axpy_multi(c, c.V, j + 1, h2, c.W, -1.0, c.active);
-            launch_norm(c, c.W, nrm, c.active);
-            launch_givens(c, j, tol);
-            launch_scale(c, c.W, nrm, c.V + (long long)(j + 1) * c.L, c.active, true);
-            ++total;
-            if ((j + 1) % check == 0 || j + 1 == m || total >= c.opts.max_iter) {
-                if (count_active(c) == 0) { done = true; break; }
-                if (total >= c.opts.max_iter) break;
+    zero_device(c, h2, (long long)c.nrep * (m + 1));
+    const bool reorth = tol < 1e-9;
+    while (true) {
+        while (!done) {
+            for (int j = 0; j < m; ++j) {
+                // one Arnoldi step: z_j = P^-1 v_j, w = A z_j, classical Gram-Schmidt
+                // (one pass), ||w||, Givens update, v_{j+1} = w / ||w||.  Loss of
+                // orthogonality is caught by the true-residual check below.
+                auto body = [&]() {
+                    double *Vj = c.V + (long long)j * c.L, *Zj = c.Z + (long long)j * c.L;
+                    // converged replicas skip the grid and body kernels (not in timing
+                    // runs, whose byte counts assume every replica is processed)
+                    c.mask = c.timing.on ? nullptr : c.active;
+                    precond(c, ms, theta, Vj, Zj, fluid_only);
+                    apply_op(c, ms, Zj, c.W, fluid_only);
+                    c.mask = nullptr;
+                    launch_dots(c, c.V, j + 1, c.W, h1, c.active);
+                    if (reorth) {
+                        // tight tolerances: second Gram-Schmidt pass keeps the basis
+                        // orthogonal to working precision
+                        launch_axpy_multi(c, c.V, j + 1, h1, c.W, -1.0, c.active);
+                        launch_dots(c, c.V, j + 1, c.W, h2, c.active);
+                        launch_axpy_multi_norm(c, c.V, j + 1, h2, c.W, nrm, c.active);
+                    } else {
+                        launch_axpy_multi_norm(c, c.V, j + 1, h1, c.W, nrm, c.active);
+                    }
+                    launch_givens(c, j, tol);
+                    launch_scale(c, c.W, nrm, c.V + (long long)(j + 1) * c.L, c.active, true);
+                };
+                bool graphable = c.opts.use_graphs && !c.timing.on && theta == c.theta_int && &ms == &c.ms[0];
+                if (graphable) {
+                    if (c.graph_tol != tol) {
+                        for (int f = 0; f < 2; ++f)
+                            for (auto &g : c.graphs[f]) if (g) { (void)hipGraphExecDestroy(g); g = nullptr; }
+                        c.graph_tol = tol;
+                    }
+                    hipGraphExec_t &ge = c.graphs[fluid_only ? 1 : 0][j];
+                    if (!ge) {
+                        hipGraph_t gr;
+                        HIP_OK(hipStreamBeginCapture(c.stream, hipStreamCaptureModeThreadLocal));
+                        body();
+                        HIP_OK(hipStreamEndCapture(c.stream, &gr));
+                        HIP_OK(hipGraphInstantiate(&ge, gr, nullptr, nullptr, 0));
+                        (void)hipGraphDestroy(gr);
+                    }
+                    HIP_OK(hipGraphLaunch(ge, c.stream));
+                } else {
+                    body();
+                }
+                ++total;
+                if ((j + 1) % check == 0 || j + 1 == m || total >= c.opts.max_iter) {
+                    if (count_active(c) == 0) { done = true; break; }
+                    if (total >= c.opts.max_iter) break;
+                }
             }
+            launch_trisolve_update(c);
+            if (done || total >= c.opts.max_iter) break;
+            // restart for replicas still active: r = b - A x
+            apply_op(c, ms, c.xsol, c.W, fluid_only);
+            launch_axpby(c, 1.0, b, -1.0, c.W, c.W, c.active);
+            launch_norm(c, c.W, nrm, c.active);
+            launch_scale(c, c.W, nrm, c.V, c.active, true);
+            launch_start_cycle(c);
         }
-        launch_trisolve_update(c);
-        if (done || total >= c.opts.max_iter) break;
-        // restart for replicas still active: r = b - A x
+        // true residual of every replica; replicas whose Arnoldi estimate was too
+        // optimistic are reactivated and restarted from their current iterate
         apply_op(c, ms, c.xsol, c.W, fluid_only);
-        launch_axpby(c, 1.0, b, -1.0, c.W, c.W, c.active);
-        launch_norm(c, c.W, nrm, c.active);
+        launch_axpby(c, 1.0, b, -1.0, c.W, c.W, nullptr);
+        launch_norm(c, c.W, c.d_resid, nullptr);
+        if (total >= c.opts.max_iter) break;
+        hipLaunchKernelGGL(k_recheck, dim3((c.nrep + 63) / 64), dim3(64), 0, c.stream, c.nrep, c.d_resid, c.beta0,
+                           tol, c.active, c.status);
+        if (count_active(c) == 0) break;
+        HIP_OK(hipMemcpyAsync(nrm, c.d_resid, sizeof(double) * c.nrep, hipMemcpyDeviceToDevice, c.stream));
         launch_scale(c, c.W, nrm, c.V, c.active, true);
         launch_start_cycle(c);
+        done = false;
     }
-    // true residual of every replica
-    apply_op(c, ms, c.xsol, c.W, fluid_only);
-    launch_axpby(c, 1.0, b, -1.0, c.W, c.W, nullptr);
-    launch_norm(c, c.W, c.d_resid, nullptr);
     std::vector<double> res(c.nrep), b0(c.nrep);
     std::vector<int> st(c.nrep), it(c.nrep), act(c.nrep);
     HIP_OK(hipMemcpyAsync(res.data(), c.d_resid, sizeof(double) * c.nrep, hipMemcpyDeviceToHost, c.stream));
@@ -396,6 +450,14 @@ static void add_boundary_terms(Ctx &c, MarkerSet &ms, double *b) {
     }
 }
 
+// Copy of the orientations read by the preconditioner (fixed address, so the
+// captured FGMRES iterations can be replayed for any caller buffer).
+static const double *stage_theta(Ctx &c, const double *theta) {
+    if (c.nb > 0)
+        HIP_OK(hipMemcpyAsync(c.theta_int, theta, sizeof(double) * 4 * c.nb, hipMemcpyDeviceToDevice, c.stream));
+    return c.theta_int;
+}
+
 // One SEM step for every replica (Algorithm 1); see include/rbfib.h.
 static int sem_step(Ctx &c, double *q, double *theta, const double *FT, const double *slip, double kT, double dt,
                     uint64_t seed, uint64_t step, double *U, std::vector<rbfib_info> &out) {
@@ -407,12 +469,13 @@ static int sem_step(Ctx &c, double *q, double *theta, const double *FT, const do
         return RBFIB_EREJECT;
     }
     std::vector<rbfib_info> inf;
+    const double *th_solve = stage_theta(c, theta);
     // 1. random forces/torques and displaced configurations
     launch_body_rfd(c, kT, delta, seed, step, q, theta);
     // 2. RFD solve: force W^FT, homogeneous data
     launch_zero(c, c.rhs, nullptr);
     launch_set_rhs_U(c, c.WFT, c.rhs);
-    fgmres(c, c.ms[0], theta, c.rhs, false, inf);
+    fgmres(c, c.ms[0], th_solve, c.rhs, false, inf);
     for (int r = 0; r < c.nrep; ++r) { out[r].iters += inf[r].iters; if (inf[r].status) out[r].status = inf[r].status; }
     HIP_OK(hipMemcpyAsync(c.xR, c.xsol, sizeof(double) * c.L, hipMemcpyDeviceToDevice, c.stream));
     // 3. markers at Q+ and Q-
@@ -423,7 +486,7 @@ static int sem_step(Ctx &c, double *q, double *theta, const double *FT, const do
     launch_zero(c, c.rhs, nullptr);
     launch_spread(c, c.ms[1], c.xR, c.rhs, 1.0 / delta);
     launch_spread(c, c.ms[2], c.xR, c.rhs, -1.0 / delta);
-    fgmres(c, c.ms[0], theta, c.rhs, true, inf);
+    fgmres(c, c.ms[0], th_solve, c.rhs, true, inf);
     for (int r = 0; r < c.nrep; ++r) { out[r].iters += inf[r].iters; if (inf[r].status) out[r].status = inf[r].status; }
     HIP_OK(hipMemcpyAsync(c.xS, c.xsol, sizeof(double) * c.L, hipMemcpyDeviceToDevice, c.stream));
     // 5. random finite differences of K, J (markers) and K^T (bodies)
@@ -435,7 +498,7 @@ static int sem_step(Ctx &c, double *q, double *theta, const double *FT, const do
     launch_sem_rhs_lambda(c, slip, c.rhs);
     launch_set_rhs_U(c, c.Fp, c.rhs);
     add_boundary_terms(c, c.ms[0], c.rhs);
-    fgmres(c, c.ms[0], theta, c.rhs, false, inf);
+    fgmres(c, c.ms[0], th_solve, c.rhs, false, inf);
     for (int r = 0; r < c.nrep; ++r) {
         out[r].iters += inf[r].iters;
         out[r].rel_residual = inf[r].rel_residual;
@@ -725,6 +788,9 @@ static void build(Ctx &c, int nrep, const rbfib_grid *grids, const rbfib_bodies 
         ms.n_active = dalloc<int>(1);
         zero_device(c, ms.n_active, 1);
     }
+    c.theta_int = dalloc<double>(4 * (size_t)std::max(c.nb, 1));
+    c.graphs[0].assign(c.opts.restart, nullptr);
+    c.graphs[1].assign(c.opts.restart, nullptr);
     c.d_flags = dalloc<int>(std::max(nrep, 4));
     HIP_OK(hipHostMalloc((void **)&c.h_flags, sizeof(int) * std::max(nrep, 4), hipHostMallocDefault));
     HIP_OK(hipHostMalloc((void **)&c.h_count, sizeof(int), hipHostMallocDefault));
@@ -807,7 +873,12 @@ static void free_all(Ctx &c) {
     F(c.H); F(c.cs); F(c.sn); F(c.gv); F(c.beta0); F(c.hcol); F(c.yv); F(c.d_resid);
     F(c.active); F(c.cyc_active); F(c.jf); F(c.status); F(c.iters);
     for (int k = 0; k < 3; ++k) { F(c.q_buf[k]); F(c.th_buf[k]); }
-    F(c.Wf); F(c.Wt); F(c.WFT); F(c.Fp); F(c.UR); F(c.slip_acc); F(c.jbc);
+    F(c.Wf); F(c.Wt); F(c.WFT); F(c.Fp); F(c.UR); F(c.slip_acc); F(c.jbc); F(c.theta_int);
+    for (int f = 0; f < 2; ++f)
+        for (auto &g : c.graphs[f]) if (g) (void)hipGraphExecDestroy(g);
+    if (c.ev_in) (void)hipEventDestroy(c.ev_in);
+    if (c.ev_out) (void)hipEventDestroy(c.ev_out);
+    if (c.stream && c.stream != c.user_stream) (void)hipStreamDestroy(c.stream);
     for (int cls = 0; cls < 2; ++cls)
         for (auto &e : c.timing.ev[cls]) (void)hipEventDestroy(e);
 }
@@ -828,7 +899,7 @@ extern "C" {
 void rbfib_default_opts(rbfib_opts *o) {
     if (!o) return;
     o->tol = 1e-6;
-    o->restart = 50;
+    o->restart = 60;
     o->max_iter = 600;
     o->precond_fp32 = 0;
     o->mg_sweeps = 2;
@@ -836,7 +907,8 @@ void rbfib_default_opts(rbfib_opts *o) {
     o->blob_radius = 1.25;
     o->rfd_delta = 1e-5;
     o->min_body_dist = 0.0;
-    o->check_every = 4;
+    o->check_every = 5;
+    o->use_graphs = 1;
 }
 
 const char *rbfib_strerror(int code) {
@@ -865,7 +937,10 @@ int rbfib_create_batch(int nrep, const rbfib_grid *grids, const rbfib_bodies *bo
         if (opts) o = *opts;
         validate(nrep, grids, bodies, o);
         ctx = new rbfib_ctx();
-        ctx->c.stream = (hipStream_t)hip_stream;
+        ctx->c.user_stream = (hipStream_t)hip_stream;
+        HIP_OK(hipStreamCreateWithFlags(&ctx->c.stream, hipStreamNonBlocking));
+        HIP_OK(hipEventCreateWithFlags(&ctx->c.ev_in, hipEventDisableTiming));
+        HIP_OK(hipEventCreateWithFlags(&ctx->c.ev_out, hipEventDisableTiming));
         ctx->c.opts = o;
         build(ctx->c, nrep, grids, bodies);
         *out = ctx;
@@ -925,10 +1000,25 @@ __global__ void k_perm_local(const int *perm, const int *marker_body, const int 
     out[t] = m - body_off_rep_m0[marker_body[m]];
 }
 
+// Orders the library stream after the caller's stream on entry and the caller's
+// stream after the library stream on exit.
+struct Session {
+    Ctx &c;
+    explicit Session(Ctx &c_) : c(c_) {
+        HIP_OK(hipEventRecord(c.ev_in, c.user_stream));
+        HIP_OK(hipStreamWaitEvent(c.stream, c.ev_in, 0));
+    }
+    ~Session() {
+        (void)hipEventRecord(c.ev_out, c.stream);
+        (void)hipStreamWaitEvent(c.user_stream, c.ev_out, 0);
+    }
+};
+
 int rbfib_markers(rbfib_ctx *ctx, const double *q, const double *theta, double *r, int *tile, int *perm) {
     if (!ctx || (ctx->c.nb > 0 && (!q || !theta))) return RBFIB_EINVAL;
     GUARD_BEGIN
     Ctx &c = ctx->c;
+    Session s(c);
     MarkerSet &ms = c.ms[0];
     build_markers(c, ms, q, theta, false);
     if (r && c.nm) HIP_OK(hipMemcpyAsync(r, ms.r, sizeof(double) * 3 * c.nm, hipMemcpyDeviceToDevice, c.stream));
@@ -948,7 +1038,6 @@ int rbfib_markers(rbfib_ctx *ctx, const double *q, const double *theta, double *
         HIP_OK(hipStreamSynchronize(c.stream));
         (void)hipFree(d_m0);
     }
-    // tile indices returned replica-local as well
     return RBFIB_OK;
     GUARD_END
 }
@@ -957,6 +1046,7 @@ int rbfib_apply_saddle(rbfib_ctx *ctx, const double *q, const double *theta, con
     if (!ctx || !x || !y || x == y || (ctx->c.nb > 0 && (!q || !theta))) return RBFIB_EINVAL;
     GUARD_BEGIN
     Ctx &c = ctx->c;
+    Session s(c);
     build_markers(c, c.ms[0], q, theta, false);
     apply_op(c, c.ms[0], x, y, false);
     return RBFIB_OK;
@@ -967,8 +1057,9 @@ int rbfib_precondition(rbfib_ctx *ctx, const double *q, const double *theta, con
     if (!ctx || !r || !z || r == z || (ctx->c.nb > 0 && (!q || !theta))) return RBFIB_EINVAL;
     GUARD_BEGIN
     Ctx &c = ctx->c;
+    Session s(c);
     build_markers(c, c.ms[0], q, theta, false);
-    precond(c, c.ms[0], theta, r, z, false);
+    precond(c, c.ms[0], stage_theta(c, theta), r, z, false);
     return RBFIB_OK;
     GUARD_END
 }
@@ -978,17 +1069,19 @@ int rbfib_solve_mobility(rbfib_ctx *ctx, const double *q, const double *theta, c
     if (!ctx || (ctx->c.nb > 0 && (!q || !theta || !FT))) return RBFIB_EINVAL;
     GUARD_BEGIN
     Ctx &c = ctx->c;
+    Session s(c);
     MarkerSet &ms = c.ms[0];
     int st = build_markers(c, ms, q, theta, true);
     if (st != RBFIB_OK) {
         if (info) for (int r = 0; r < c.nrep; ++r) info[r] = rbfib_info{0, 0.0, st};
         return st;
     }
+    const double *th = stage_theta(c, theta);
     launch_zero(c, c.rhs, nullptr);
     launch_set_rhs(c, FT, slip, c.rhs);
     if (include_bc) add_boundary_terms(c, ms, c.rhs);
     std::vector<rbfib_info> inf;
-    fgmres(c, ms, theta, c.rhs, false, inf);
+    fgmres(c, ms, th, c.rhs, false, inf);
     if (U) launch_copy_U(c, c.xsol, U, 1.0);
     if (x_out) HIP_OK(hipMemcpyAsync(x_out, c.xsol, sizeof(double) * c.L, hipMemcpyDeviceToDevice, c.stream));
     HIP_OK(hipStreamSynchronize(c.stream));
@@ -1001,6 +1094,7 @@ int rbfib_fluctuating_stress(rbfib_ctx *ctx, double kT, double dt, uint64_t seed
     if (!ctx || !f || !(dt > 0.0) || kT < 0.0) return RBFIB_EINVAL;
     GUARD_BEGIN
     Ctx &c = ctx->c;
+    Session s(c);
     launch_zero(c, f, nullptr);
     launch_noise(c, kT, dt, seed, step, f, false);
     return RBFIB_OK;
@@ -1012,6 +1106,7 @@ int rbfib_sem_step(rbfib_ctx *ctx, double *q, double *theta, const double *FT, c
     if (!ctx || !(dt > 0.0) || !(kT >= 0.0) || (ctx->c.nb > 0 && (!q || !theta))) return RBFIB_EINVAL;
     GUARD_BEGIN
     Ctx &c = ctx->c;
+    Session s(c);
     std::vector<rbfib_info> inf;
     int code = sem_step(c, q, theta, FT, slip, kT, dt, seed, step, U, inf);
     HIP_OK(hipStreamSynchronize(c.stream));
@@ -1021,10 +1116,38 @@ int rbfib_sem_step(rbfib_ctx *ctx, double *q, double *theta, const double *FT, c
 }
 
 int rbfib_mobility_vjp(rbfib_ctx *ctx, const double *q, const double *theta, const double *FT, const double *Ubar,
-                       double *dFT, double *dq, double *dphi, rbfib_info *info) {
-    (void)ctx; (void)q; (void)theta; (void)FT; (void)Ubar; (void)dFT; (void)dq; (void)dphi; (void)info;
-    g_last_error = "rbfib_mobility_vjp: not available in this build";
-    return RBFIB_EINVAL;
+                       double *dFT, double *dq, double *dphi, double *dtheta, rbfib_info *info) {
+    if (!ctx || (ctx->c.nb > 0 && (!q || !theta || !FT || !Ubar))) return RBFIB_EINVAL;
+    GUARD_BEGIN
+    Ctx &c = ctx->c;
+    Session s(c);
+    int st = build_markers(c, c.ms[0], q, theta, true);
+    if (st != RBFIB_OK) {
+        if (info) for (int r = 0; r < c.nrep; ++r) info[r] = rbfib_info{0, 0.0, st};
+        return st;
+    }
+    const double *th = stage_theta(c, theta);
+    std::vector<rbfib_info> fwd, adj;
+    // forward solve (the Krylov basis is recomputed, not stored)
+    launch_zero(c, c.rhs, nullptr);
+    launch_set_rhs(c, FT, nullptr, c.rhs);
+    fgmres(c, c.ms[0], th, c.rhs, false, fwd);
+    HIP_OK(hipMemcpyAsync(c.xR, c.xsol, sizeof(double) * c.L, hipMemcpyDeviceToDevice, c.stream));
+    // adjoint solve with the same operator
+    launch_zero(c, c.rhs, nullptr);
+    launch_set_rhs_adjoint(c, Ubar, c.rhs);
+    fgmres(c, c.ms[0], th, c.rhs, false, adj);
+    launch_body_grad(c, c.xR, c.xsol, theta, dFT, dq, dphi, dtheta);
+    HIP_OK(hipStreamSynchronize(c.stream));
+    int ret = RBFIB_OK;
+    for (int r = 0; r < c.nrep; ++r) {
+        rbfib_info i{fwd[r].iters + adj[r].iters, std::max(fwd[r].rel_residual, adj[r].rel_residual),
+                     fwd[r].status != RBFIB_OK ? fwd[r].status : adj[r].status};
+        if (info) info[r] = i;
+        if (i.status != RBFIB_OK && ret == RBFIB_OK) ret = i.status;
+    }
+    return ret;
+    GUARD_END
 }
 
 int rbfib_enable_timing(rbfib_ctx *ctx, int on) {
