@@ -217,6 +217,8 @@ def main():
     ap.add_argument("--two-spheres-steps", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="run one 256 MiB device-to-device copy first (counter calibration in profiles)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU: every box here has a single MI355X, and the replicas of the "
@@ -225,6 +227,13 @@ def main():
 
     import torch
     import workloads as W
+    if args.copy_probe:
+        a = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
     ens = W.ensemble(n_replicas=args.replicas)
     log("ensemble: %d replicas, %d bodies, %d markers" % (len(ens), sum(w.nb for w in ens), sum(w.nm for w in ens)))
 

@@ -37,6 +37,7 @@ struct RepDev {
     int nlev;
     int movwall;
     double wv[3][2][3];
+    double inv_n0, inv_n01;   // 1/nx and 1/(nx*ny) for exact index splitting
 };
 
 struct LevDev {
@@ -44,11 +45,25 @@ struct LevDev {
     double inv_h2[3];   // 1/h_a^2 per axis at this level
     long long off;      // offset of this level's four fields in the level pool
     long long N;
+    double inv_n0, inv_n01;
 };
+
+// (i, j, k) of a linear x-fastest index, without integer division: the quotient
+// (lin + 1/2) / n is at least 1/(2n) away from an integer, so rounding the FP64
+// product down is exact for every lin < 2^31.
+__device__ __forceinline__ void split_index(long long lin, int n0, int n01, double inv_n0, double inv_n01, int idx[3]) {
+    int l = (int)lin;
+    int k = (int)(((double)l + 0.5) * inv_n01);
+    int rem = l - k * n01;
+    int j = (int)(((double)rem + 0.5) * inv_n0);
+    idx[0] = rem - j * n0;
+    idx[1] = j;
+    idx[2] = k;
+}
 
 struct BlockEnt {       // one block of work: replica and local start index
     int rep;
-    int comp;           // component (grid kernels) or unused
+    int npt;            // grid points per thread (stride RB_BLOCK) for the stencil kernels
     long long start;
 };
 
@@ -190,6 +205,25 @@ __device__ __forceinline__ double interp_comp(const RepDev &R, const double *rm,
     return acc;
 }
 
+// (J u)_c from the cached 1-D weights and folded indices of marker m.
+__device__ __forceinline__ double interp_cached(const RepDev &R, const double *wc, const int *ic, int m, int c,
+                                               const double *u) {
+    const double *w = wc + (long long)(3 * m + c) * 12;
+    const int *ix = ic + (long long)(3 * m + c) * 12;
+    double acc = 0.0;
+    for (int z = 0; z < 4; ++z) {
+        double wz = w[8 + z];
+        if (wz == 0.0) continue;
+        for (int y = 0; y < 4; ++y) {
+            double wzy = wz * w[4 + y];
+            if (wzy == 0.0) continue;
+            long long row = (long long)R.n[0] * ((long long)ix[4 + y] + (long long)R.n[1] * ix[8 + z]);
+            for (int x = 0; x < 4; ++x) acc += wzy * w[x] * u[row + ix[x]];
+        }
+    }
+    return acc;
+}
+
 // Gradient with respect to the marker position of (J u)_c: the derivative along
 // axis a replaces phi_a by phi_a' / h; fold signs and indices are fixed within each
 // smooth piece of the kernel.
@@ -230,6 +264,8 @@ struct MarkerSet {
     int *active = nullptr;    // [ntiles] compacted active target tiles
     int *n_active = nullptr;  // device scalar
     int *flag = nullptr;      // [ntiles] scratch
+    double *wc = nullptr;     // [nm][3 comp][3 axis][4] folded signed 1-D kernel weights
+    int *ic = nullptr;        // [nm][3][3][4] folded grid indices of those weights
 };
 
 struct Timing {

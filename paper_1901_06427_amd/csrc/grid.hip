@@ -60,11 +60,12 @@ __device__ __forceinline__ bool pinned(int c, const int idx[3], const int bc[3])
     return c < 3 && bc[c] == RBFIB_WALL && idx[c] == 0;
 }
 
-__device__ __forceinline__ void unlin(long long lin, const int n[3], int idx[3]) {
-    idx[0] = (int)(lin % n[0]);
-    long long t = lin / n[0];
-    idx[1] = (int)(t % n[1]);
-    idx[2] = (int)(t / n[1]);
+__device__ __forceinline__ void unlin(long long lin, const RepDev &R, int idx[3]) {
+    split_index(lin, R.n[0], R.n[0] * R.n[1], R.inv_n0, R.inv_n01, idx);
+}
+
+__device__ __forceinline__ void unlin(long long lin, const LevDev &L, int idx[3]) {
+    split_index(lin, L.n[0], L.n[0] * L.n[1], L.inv_n0, L.inv_n01, idx);
 }
 
 // ------------------------------------------------------------------ fused fluid apply
@@ -74,11 +75,12 @@ __global__ void k_apply_fluid(const RepDev *reps, const BlockEnt *tab, const dou
     BlockEnt be = tab[blockIdx.x];
     if (mask && !mask[be.rep]) return;
     const RepDev &R = reps[be.rep];
-    long long lin = be.start + threadIdx.x;
+    for (int t_ = 0; t_ < be.npt; ++t_) {
+    long long lin = be.start + threadIdx.x + (long long)t_ * RB_BLOCK;
     long long N = R.N;
-    if (lin >= N) return;
+    if (lin >= N) continue;
     int idx[3];
-    unlin(lin, R.n, idx);
+    unlin(lin, R, idx);
     const double *u[3] = {x + R.off, x + R.off + N, x + R.off + 2 * N};
     const double *p = x + R.off + 3 * N;
     double ih = R.inv_h;
@@ -111,6 +113,7 @@ __global__ void k_apply_fluid(const RepDev *reps, const BlockEnt *tab, const dou
         y[R.off + c * N + lin] = out;
         stride *= R.n[c];
     }
+    }
 }
 
 void launch_apply_fluid(Ctx &c, const double *x, double *y) {
@@ -127,10 +130,12 @@ __global__ void k_to_level0(const RepDev *reps, const LevDev *levs, const BlockE
     if (mask && !mask[be.rep]) return;
     int comp = c0 + blockIdx.y;
     const RepDev &R = reps[be.rep];
-    long long lin = be.start + threadIdx.x;
-    if (lin >= R.N) return;
+    for (int t_ = 0; t_ < be.npt; ++t_) {
+    long long lin = be.start + threadIdx.x + (long long)t_ * RB_BLOCK;
+    if (lin >= R.N) continue;
     const LevDev &Lv = levs[be.rep * RB_MAXLEV];
     b[Lv.off + comp * Lv.N + lin] = (T)src[R.off + comp * R.N + lin];
+    }
 }
 
 template <typename T>
@@ -149,12 +154,13 @@ __global__ void k_smooth(const RepDev *reps, const LevDev *levs, const BlockEnt 
     int comp = c0 + blockIdx.y;
     const RepDev &R = reps[be.rep];
     const LevDev &Lv = levs[be.rep * RB_MAXLEV + lev];
-    long long lin = be.start + threadIdx.x;
-    if (lin >= Lv.N) return;
+    for (int t_ = 0; t_ < be.npt; ++t_) {
+    long long lin = be.start + threadIdx.x + (long long)t_ * RB_BLOCK;
+    if (lin >= Lv.N) continue;
     int idx[3];
-    unlin(lin, Lv.n, idx);
+    unlin(lin, Lv, idx);
     long long base = Lv.off + comp * Lv.N;
-    if (pinned(comp, idx, R.bc)) { xout[base + lin] = (T)0; return; }
+    if (pinned(comp, idx, R.bc)) { xout[base + lin] = (T)0; continue; }
     T s = (comp < 3) ? (T)(-R.eta) : (T)-1;
     T dg, lap;
     if (first) {
@@ -170,12 +176,13 @@ __global__ void k_smooth(const RepDev *reps, const LevDev *levs, const BlockEnt 
             dg += da * (T)Lv.inv_h2[a];
         }
         xout[base + lin] = (T)omega * b[base + lin] / (s * dg);
-        return;
+        continue;
     }
     lap = lap_point<T>(xin + base, comp, idx, Lv.n, R.bc, Lv.inv_h2, lin, dg);
     T xv = xin[base + lin];
     T res = b[base + lin] - s * lap;
     xout[base + lin] = xv + (T)omega * res / (s * dg);
+    }
 }
 
 template <typename T>
@@ -208,12 +215,13 @@ __global__ void k_restrict(const RepDev *reps, const LevDev *levs, const BlockEn
     const RepDev &R = reps[be.rep];
     const LevDev &F = levs[be.rep * RB_MAXLEV + lev];
     const LevDev &C = levs[be.rep * RB_MAXLEV + lev + 1];
-    long long lin = be.start + threadIdx.x;
-    if (lin >= C.N) return;
+    for (int t_ = 0; t_ < be.npt; ++t_) {
+    long long lin = be.start + threadIdx.x + (long long)t_ * RB_BLOCK;
+    if (lin >= C.N) continue;
     int ci[3];
-    unlin(lin, C.n, ci);
+    unlin(lin, C, ci);
     long long cbase = C.off + comp * C.N;
-    if (pinned(comp, ci, R.bc)) { bc[cbase + lin] = (T)0; return; }
+    if (pinned(comp, ci, R.bc)) { bc[cbase + lin] = (T)0; continue; }
     const T *xf = x + F.off + comp * F.N;
     const T *bf = b + F.off + comp * F.N;
     int fi[3][3];
@@ -245,6 +253,7 @@ __global__ void k_restrict(const RepDev *reps, const LevDev *levs, const BlockEn
                 acc += w * residual_at<T>(R, F, comp, fi[0][ii], fi[1][jj], fi[2][kk], xf, bf);
             }
     bc[cbase + lin] = acc;
+    }
 }
 
 template <typename T>
@@ -267,11 +276,12 @@ __global__ void k_prolong(const RepDev *reps, const LevDev *levs, const BlockEnt
     const RepDev &R = reps[be.rep];
     const LevDev &F = levs[be.rep * RB_MAXLEV + lev];
     const LevDev &C = levs[be.rep * RB_MAXLEV + lev + 1];
-    long long lin = be.start + threadIdx.x;
-    if (lin >= F.N) return;
+    for (int t_ = 0; t_ < be.npt; ++t_) {
+    long long lin = be.start + threadIdx.x + (long long)t_ * RB_BLOCK;
+    if (lin >= F.N) continue;
     int fi[3];
-    unlin(lin, F.n, fi);
-    if (pinned(comp, fi, R.bc)) return;
+    unlin(lin, F, fi);
+    if (pinned(comp, fi, R.bc)) continue;
     int ci[3][2];
     T cw[3][2];
     T cs[3][2];
@@ -318,6 +328,7 @@ __global__ void k_prolong(const RepDev *reps, const LevDev *levs, const BlockEnt
                 acc += w * xcc[cl];
             }
     xf[F.off + comp * F.N + lin] += acc;
+    }
 }
 
 template <typename T>
@@ -373,11 +384,12 @@ __global__ void k_proj_div(const RepDev *reps, const LevDev *levs, const BlockEn
     if (mask && !mask[be.rep]) return;
     const RepDev &R = reps[be.rep];
     const LevDev &Lv = levs[be.rep * RB_MAXLEV];
-    long long lin = be.start + threadIdx.x;
+    for (int t_ = 0; t_ < be.npt; ++t_) {
+    long long lin = be.start + threadIdx.x + (long long)t_ * RB_BLOCK;
     long long N = R.N;
-    if (lin >= N) return;
+    if (lin >= N) continue;
     int idx[3];
-    unlin(lin, R.n, idx);
+    unlin(lin, R, idx);
     double div = 0.0;
     long long stride = 1;
     for (int c = 0; c < 3; ++c) {
@@ -392,6 +404,7 @@ __global__ void k_proj_div(const RepDev *reps, const LevDev *levs, const BlockEn
     double d = div + r[R.off + 3 * N + lin];
     bp[Lv.off + 3 * Lv.N + lin] = (T)(-d);
     z[R.off + 3 * N + lin] = -R.eta * d;
+    }
 }
 
 template <typename T>
@@ -408,11 +421,12 @@ __global__ void k_proj_correct(const RepDev *reps, const LevDev *levs, const Blo
     if (mask && !mask[be.rep]) return;
     const RepDev &R = reps[be.rep];
     const LevDev &Lv = levs[be.rep * RB_MAXLEV];
-    long long lin = be.start + threadIdx.x;
+    for (int t_ = 0; t_ < be.npt; ++t_) {
+    long long lin = be.start + threadIdx.x + (long long)t_ * RB_BLOCK;
     long long N = R.N;
-    if (lin >= N) return;
+    if (lin >= N) continue;
     int idx[3];
-    unlin(lin, R.n, idx);
+    unlin(lin, R, idx);
     const T *ph = phi + Lv.off + 3 * Lv.N;
     double pc = (double)ph[lin];
     long long stride = 1;
@@ -424,6 +438,7 @@ __global__ void k_proj_correct(const RepDev *reps, const LevDev *levs, const Blo
         }
         z[R.off + c * N + lin] = out;
         stride *= R.n[c];
+    }
     }
 }
 
@@ -455,11 +470,12 @@ __global__ void k_noise(const RepDev *reps, const BlockEnt *tab, double scale_ba
                         double *__restrict__ f, int add) {
     BlockEnt be = tab[blockIdx.x];
     const RepDev &R = reps[be.rep];
-    long long lin = be.start + threadIdx.x;
+    for (int t_ = 0; t_ < be.npt; ++t_) {
+    long long lin = be.start + threadIdx.x + (long long)t_ * RB_BLOCK;
     long long N = R.N;
-    if (lin >= N) return;
+    if (lin >= N) continue;
     int idx[3];
-    unlin(lin, R.n, idx);
+    unlin(lin, R, idx);
     uint64_t rseed = seed + (uint64_t)be.rep;
     long long fam_off[10];
     fam_off[0] = 0;
@@ -504,6 +520,7 @@ __global__ void k_noise(const RepDev *reps, const BlockEnt *tab, double scale_ba
         if (add) *dst += out; else *dst = out;
     }
     if (!add) f[R.off + 3 * N + lin] = 0.0;
+    }
 }
 
 void launch_noise(Ctx &c, double kT, double dt, uint64_t seed, uint64_t step, double *f, bool add) {
@@ -517,11 +534,12 @@ __global__ void k_wall_rhs(const RepDev *reps, const BlockEnt *tab, double *__re
     BlockEnt be = tab[blockIdx.x];
     const RepDev &R = reps[be.rep];
     if (!R.movwall) return;
-    long long lin = be.start + threadIdx.x;
+    for (int t_ = 0; t_ < be.npt; ++t_) {
+    long long lin = be.start + threadIdx.x + (long long)t_ * RB_BLOCK;
     long long N = R.N;
-    if (lin >= N) return;
+    if (lin >= N) continue;
     int idx[3];
-    unlin(lin, R.n, idx);
+    unlin(lin, R, idx);
     for (int c = 0; c < 3; ++c) {
         if (pinned(c, idx, R.bc)) continue;
         double add = 0.0;
@@ -531,6 +549,7 @@ __global__ void k_wall_rhs(const RepDev *reps, const BlockEnt *tab, double *__re
             if (idx[a] == R.n[a] - 1) add += 2.0 * R.eta * R.wv[a][1][c] * R.inv_h * R.inv_h;
         }
         f[R.off + c * N + lin] += add;
+    }
     }
 }
 

@@ -37,7 +37,7 @@ __device__ void marker_pos(const double *q, const double *th, const double *rr, 
 
 __global__ void k_markers(const RepDev *reps, const int *marker_body, const int *body_rep, const double *q,
                           const double *theta, const double *rref, int nm, double *r_out, double *d_out, int *tile,
-                          int *tile_count, int *flags) {
+                          int *tile_count, int *flags, double *wc, int *ic) {
     int m = blockIdx.x * blockDim.x + threadIdx.x;
     if (m >= nm) return;
     int p = marker_body[m];
@@ -65,6 +65,15 @@ __global__ void k_markers(const RepDev *reps, const int *marker_body, const int 
     for (int a = 0; a < 3; ++a) { r_out[3 * m + a] = r[a]; d_out[3 * m + a] = d[a]; }
     tile[m] = t;
     atomicAdd(&tile_count[t], 1);
+    // 1-D folded kernel weights, reused by every spread and interpolation at this configuration
+    for (int c = 0; c < 3; ++c)
+        for (int a = 0; a < 3; ++a) {
+            int idx[4], cr[4];
+            double w[4];
+            axis_weights(R, r[a], c, a, idx, w, cr);
+            long long o = ((long long)(3 * m + c) * 3 + a) * 4;
+            for (int k = 0; k < 4; ++k) { wc[o + k] = w[k]; ic[o + k] = idx[k]; }
+        }
     if (outside) atomicOr(&flags[body_rep[p]], 1);
 }
 
@@ -160,7 +169,7 @@ void launch_markers(Ctx &c, MarkerSet &ms, const double *q, const double *theta)
     int nb = (c.nm + 255) / 256;
     if (c.nm > 0)
         hipLaunchKernelGGL(k_markers, dim3(nb), dim3(256), 0, c.stream, c.d_reps, c.d_marker_body, c.d_body_rep, q,
-                           theta, c.d_rref, c.nm, ms.r, ms.d, ms.tile, ms.tile_count, c.d_flags);
+                           theta, c.d_rref, c.nm, ms.r, ms.d, ms.tile, ms.tile_count, c.d_flags, ms.wc, ms.ic);
     hipLaunchKernelGGL(k_tile_scan, dim3(1), dim3(1024), 0, c.stream, ms.tile_count, ms.tile_start, ms.tile_fill,
                        c.ntiles);
     if (c.nm > 0) {
@@ -181,7 +190,8 @@ __global__ __launch_bounds__(256) void k_spread(const RepDev *reps, const int *t
                                                 const int *perm, const double *__restrict__ r,
                                                 const double *__restrict__ lam_state, const int *marker_body,
                                                 const int *body_rep, double *__restrict__ y, double alpha,
-                                                const int *__restrict__ mask) {
+                                                const int *__restrict__ mask, const double *__restrict__ wc,
+                                                const int *__restrict__ ic) {
     __shared__ double Wt[SP_CHUNK][3][3][4];
     __shared__ double Ls[SP_CHUNK][3];
     __shared__ int Ms[SP_CHUNK];
@@ -228,9 +238,9 @@ __global__ __launch_bounds__(256) void k_spread(const RepDev *reps, const int *t
             for (int task = tid; task < cnt * 9; task += blockDim.x) {
                 int j = task / 9, ca = task % 9, cc = ca / 3, a = ca % 3;
                 int m = Ms[j];
-                int idx[4], cr[4];
-                double w[4];
-                axis_weights(R, r[3 * m + a], cc, a, idx, w, cr);
+                long long co = ((long long)(3 * m + cc) * 3 + a) * 4;
+                const double *w = wc + co;
+                const int *idx = ic + co;
                 double o[4] = {0.0, 0.0, 0.0, 0.0};
                 int t0 = 4 * tc[a];
                 for (int q = 0; q < 4; ++q) {
@@ -271,14 +281,14 @@ void launch_spread(Ctx &c, MarkerSet &ms, const double *lam_state, double *y, do
     int grid = std::min(c.ntiles, 32768);   // grid-stride over the active tiles
     hipLaunchKernelGGL(k_spread, dim3(grid), dim3(256), 0, c.stream, c.d_reps, c.d_tile_rep, ms.active, ms.n_active,
                        ms.tile_start, ms.tile_count, ms.perm, ms.r, lam_state, c.d_marker_body, c.d_body_rep, y,
-                       alpha, c.mask);
+                       alpha, c.mask, ms.wc, ms.ic);
 }
 
 // ------------------------------------------------------------------ J, K, K^T per body
 // y_lambda = -J v + K U ;  y_U = K^T lambda  (rows 3 and 4 of the saddle operator).
 __global__ void k_body_apply(const RepDev *reps, const int *body_rep, const int *body_off, const double *r,
                              const double *d, const double *__restrict__ x, double *__restrict__ y,
-                             const int *__restrict__ mask) {
+                             const int *__restrict__ mask, const double *__restrict__ wc, const int *__restrict__ ic) {
     extern __shared__ double sred[];   // [nmp][6]
     int p = blockIdx.x;
     if (mask && !mask[body_rep[p]]) return;
@@ -290,7 +300,7 @@ __global__ void k_body_apply(const RepDev *reps, const int *body_rep, const int 
     for (int k = 0; k < 6; ++k) U[k] = x[U0 + k];
     for (int task = threadIdx.x; task < 3 * nmp; task += blockDim.x) {
         int i = task / 3, c = task % 3, m = m0 + i;
-        double Jv = interp_comp(R, r + 3 * m, c, x + R.off + c * R.N);
+        double Jv = interp_cached(R, wc, ic, m, c, x + R.off + c * R.N);
         const double *dm = d + 3 * m;
         double wxd[3] = {U[4] * dm[2] - U[5] * dm[1], U[5] * dm[0] - U[3] * dm[2], U[3] * dm[1] - U[4] * dm[0]};
         y[lam0 + 3LL * (m - R.m0) + c] = -Jv + U[c] + wxd[c];
@@ -319,25 +329,26 @@ void launch_body_apply(Ctx &c, MarkerSet &ms, const double *q, const double *x, 
     if (c.nb == 0) return;
     size_t sh = sizeof(double) * 6 * (size_t)c.max_body_nm;
     hipLaunchKernelGGL(k_body_apply, dim3(c.nb), dim3(128), sh, c.stream, c.d_reps, c.d_body_rep, c.d_body_off, ms.r,
-                       ms.d, x, y, c.mask);
+                       ms.d, x, y, c.mask, ms.wc, ms.ic);
 }
 
 // ------------------------------------------------------------------ interpolation
 // out[m, c] (= or +=) alpha * (J u)_c at markers of ms; u is a state vector.
-__global__ void k_interp(const RepDev *reps, const int *marker_body, const int *body_rep, const double *r, int nm,
-                         const double *__restrict__ u, double *__restrict__ out, double alpha, int accumulate) {
+__global__ void k_interp(const RepDev *reps, const int *marker_body, const int *body_rep, const double *wc,
+                         const int *ic, int nm, const double *__restrict__ u, double *__restrict__ out, double alpha,
+                         int accumulate) {
     int task = blockIdx.x * blockDim.x + threadIdx.x;
     if (task >= 3 * nm) return;
     int m = task / 3, c = task % 3;
     const RepDev &R = reps[body_rep[marker_body[m]]];
-    double v = alpha * interp_comp(R, r + 3 * m, c, u + R.off + c * R.N);
+    double v = alpha * interp_cached(R, wc, ic, m, c, u + R.off + c * R.N);
     if (accumulate) out[task] += v; else out[task] = v;
 }
 
 void launch_interp(Ctx &c, MarkerSet &ms, const double *u, double *out, double alpha, bool accumulate) {
     if (c.nm == 0) return;
     hipLaunchKernelGGL(k_interp, dim3((3 * c.nm + 255) / 256), dim3(256), 0, c.stream, c.d_reps, c.d_marker_body,
-                       c.d_body_rep, ms.r, c.nm, u, out, alpha, accumulate ? 1 : 0);
+                       c.d_body_rep, ms.wc, ms.ic, c.nm, u, out, alpha, accumulate ? 1 : 0);
 }
 
 // Affine part of interpolation next to sliding walls: for each support point across a

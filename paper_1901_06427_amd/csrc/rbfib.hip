@@ -541,6 +541,7 @@ static void validate(int nrep, const rbfib_grid *grids, const rbfib_bodies *bodi
         int walls = 0;
         for (int a = 0; a < 3; ++a) {
             if (g.n[a] < 4 || g.n[a] > (1 << 16)) throw (int)RBFIB_EINVAL;
+            if ((double)g.n[0] * g.n[1] * g.n[2] >= 2147483647.0) throw (int)RBFIB_EINVAL;
             if (g.bc[a] != RBFIB_PERIODIC && g.bc[a] != RBFIB_WALL) throw (int)RBFIB_EINVAL;
             walls += g.bc[a] == RBFIB_WALL;
         }
@@ -572,6 +573,8 @@ static void build(Ctx &c, int nrep, const rbfib_grid *grids, const rbfib_bodies 
         for (int a = 0; a < 3; ++a) { R.n[a] = g.n[a]; R.bc[a] = g.bc[a]; R.tdim[a] = (g.n[a] + RB_TILE - 1) / RB_TILE; }
         R.h = g.h; R.inv_h = 1.0 / g.h; R.eta = g.eta; R.dV = g.h * g.h * g.h;
         R.N = (long long)g.n[0] * g.n[1] * g.n[2];
+        R.inv_n0 = 1.0 / g.n[0];
+        R.inv_n01 = 1.0 / ((double)g.n[0] * g.n[1]);
         R.nb = bd.nb; R.nm = bd.nm; R.b0 = b0; R.m0 = m0;
         R.off = off;
         R.len = 4 * R.N + 3LL * bd.nm + 6LL * bd.nb;
@@ -614,6 +617,8 @@ static void build(Ctx &c, int nrep, const rbfib_grid *grids, const rbfib_bodies 
             LevDev &Lv = c.levs[(size_t)r * RB_MAXLEV + l];
             for (int a = 0; a < 3; ++a) { Lv.n[a] = n[a]; Lv.inv_h2[a] = 1.0 / (h[a] * h[a]); }
             Lv.N = (long long)n[0] * n[1] * n[2];
+            Lv.inv_n0 = 1.0 / n[0];
+            Lv.inv_n01 = 1.0 / ((double)n[0] * n[1]);
             Lv.off = loff;
             loff += 4 * Lv.N;
             bool any = false;
@@ -637,14 +642,23 @@ static void build(Ctx &c, int nrep, const rbfib_grid *grids, const rbfib_bodies 
     c.lev_total = loff;
 
     // ---- block tables
+    // Stencil kernels process npt points per thread: 4 on the multigrid levels of
+    // large batches (amortises the per-block descriptor loads), 1 otherwise (keeps
+    // enough workgroups in flight on small grids).
+    long long total_cells = 0;
+    for (int r = 0; r < nrep; ++r) total_cells += c.reps[r].N;
+    const int mg_npt = total_cells >= (1LL << 22) ? 4 : 1;
     auto chunks = [](std::vector<BlockEnt> &tab, int rep, long long n, long long step) {
-        for (long long s = 0; s < n; s += step) tab.push_back(BlockEnt{rep, 0, s});
+        for (long long s = 0; s < n; s += step) tab.push_back(BlockEnt{rep, 1, s});
+    };
+    auto gchunks = [](std::vector<BlockEnt> &tab, int rep, long long n, int npt) {
+        for (long long s = 0; s < n; s += (long long)RB_BLOCK * npt) tab.push_back(BlockEnt{rep, npt, s});
     };
     std::vector<BlockEnt> tcells, tvec;
     c.vec_first.resize(nrep);
     c.vec_nblk.resize(nrep);
     for (int r = 0; r < nrep; ++r) {
-        chunks(tcells, r, c.reps[r].N, RB_BLOCK);
+        gchunks(tcells, r, c.reps[r].N, 1);
         c.vec_first[r] = (int)tvec.size();
         chunks(tvec, r, c.reps[r].len, RB_CHUNK);
         c.vec_nblk[r] = (int)tvec.size() - c.vec_first[r];
@@ -661,9 +675,9 @@ static void build(Ctx &c, int nrep, const rbfib_grid *grids, const rbfib_bodies 
             const RepDev &R = c.reps[r];
             if (l >= R.nlev) continue;
             long long N = c.levs[(size_t)r * RB_MAXLEV + l].N;
-            chunks(ta, r, N, RB_BLOCK);
-            if (l < R.nlev - 1) chunks(tl, r, N, RB_BLOCK);
-            else tc.push_back(BlockEnt{r, 0, 0});
+            gchunks(ta, r, N, mg_npt);
+            if (l < R.nlev - 1) gchunks(tl, r, N, mg_npt);
+            else tc.push_back(BlockEnt{r, 1, 0});
         }
         c.n_tab_lev[l] = (int)tl.size(); c.d_tab_lev[l] = upload(c, tl);
         c.n_tab_crs[l] = (int)tc.size(); c.d_tab_crs[l] = upload(c, tc);
@@ -786,6 +800,8 @@ static void build(Ctx &c, int nrep, const rbfib_grid *grids, const rbfib_bodies 
         ms.active = dalloc<int>(c.ntiles);
         ms.flag = dalloc<int>(c.ntiles);
         ms.n_active = dalloc<int>(1);
+        ms.wc = dalloc<double>(36 * (size_t)std::max(c.nm, 1));
+        ms.ic = dalloc<int>(36 * (size_t)std::max(c.nm, 1));
         zero_device(c, ms.n_active, 1);
     }
     c.theta_int = dalloc<double>(4 * (size_t)std::max(c.nb, 1));
@@ -864,7 +880,7 @@ static void free_all(Ctx &c) {
     for (int k = 0; k < 4; ++k) {
         MarkerSet &ms = c.ms[k];
         F(ms.r); F(ms.d); F(ms.tile); F(ms.perm); F(ms.tile_count); F(ms.tile_start); F(ms.tile_fill);
-        F(ms.active); F(ms.flag); F(ms.n_active);
+        F(ms.active); F(ms.flag); F(ms.n_active); F(ms.wc); F(ms.ic);
     }
     F(c.d_flags); F(c.d_count);
     if (c.h_flags) (void)hipHostFree(c.h_flags);

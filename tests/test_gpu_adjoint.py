@@ -76,8 +76,9 @@ def test_vjp_finite_differences_full_size(rb):
     eps = 1e-5
     # The 4-point kernel is only C^1, so central differences carry an O(eps) error
     # wherever a marker crosses a kernel breakpoint; it is compared with the size of
-    # a typical directional derivative (gradient norm times direction norm / sqrt(n)).
-    gnorm = np.sqrt(np.sum(dF ** 2) + np.sum(dq ** 2) + np.sum(dphi ** 2))
+    # a typical directional derivative (the mean magnitude over the random directions).
+    typical = []
+    checks = []
     for k in range(8):
         a = rng.standard_normal((w.nb, 6))
         b = rng.standard_normal((w.nb, 3))
@@ -89,19 +90,21 @@ def test_vjp_finite_differences_full_size(rb):
             vals.append(_loss(rb, ctx, w, q2, th2, w.FT + sgn * eps * a))
         fd = (vals[0] - vals[1]) / (2 * eps)
         an = np.sum(dF * a) + np.sum(dq * b) + np.sum(dphi * c)
-        scale = gnorm * np.sqrt(np.sum(a ** 2) + np.sum(b ** 2) + np.sum(c ** 2)) / np.sqrt(a.size + b.size + c.size)
+        typical.append(abs(an))
+        checks.append((fd, an))
         print("  direction", k, "fd", fd, "adjoint", an, "rel", abs(fd - an) / abs(fd), flush=True)
-        assert abs(fd - an) <= 1e-5 * max(abs(fd), scale)
+    scale = float(np.mean(typical))
+    print("  typical directional derivative", scale, flush=True)
     # quaternion gradient along directions tangent to the unit sphere
-    tnorm = np.sqrt(np.sum(dth ** 2))
     for k in range(2):
         d = rng.standard_normal((w.nb, 4))
         d -= np.sum(d * w.theta, axis=1, keepdims=True) * w.theta
         vals = [_loss(rb, ctx, w, w.q, w.theta + sgn * eps * d, w.FT) for sgn in (1.0, -1.0)]
         fd = (vals[0] - vals[1]) / (2 * eps)
         an = np.sum(dth * d)
-        scale = tnorm * np.sqrt(np.sum(d ** 2)) / np.sqrt(d.size)
         print("  quaternion direction", k, "fd", fd, "adjoint", an, flush=True)
+        checks.append((fd, an))
+    for fd, an in checks:
         assert abs(fd - an) <= 1e-5 * max(abs(fd), scale)
     ctx.close()
 
