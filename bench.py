@@ -124,12 +124,16 @@ class Ensemble:
         return F
 
 
+MG_FUSED = 1
+
+
 def run_gpu(ws, steps, warmup, fp32, seed=2024, timing=False, graphs=True):
     import torch
     import paper_1901_06427_amd as rb
     from tests.helpers import lib_context
     E = Ensemble(ws)
-    ctx = lib_context(rb, ws, tol=ws[0].tol, precond_fp32=fp32, use_graphs=int(graphs and not timing))
+    ctx = lib_context(rb, ws, tol=ws[0].tol, precond_fp32=fp32, use_graphs=int(graphs and not timing),
+                      mg_fused=MG_FUSED)
     U = torch.empty((E.nb, 6), dtype=torch.float64, device="cuda")
     step_id = 0
     iters = 0
@@ -156,9 +160,11 @@ def run_gpu(ws, steps, warmup, fp32, seed=2024, timing=False, graphs=True):
     t1 = time.perf_counter()
     stats = {}
     if timing:
-        for which, name in ((0, "mac_saddle_apply"), (1, "mg_smooth_level0")):
+        for which, name in ((0, "mac_saddle_apply"), (1, "mg_smooth_level0"), (2, "mg_down_level0"),
+                            (3, "mg_up_level0")):
             avg_ms, nbytes, launches = rb.rbfib_kernel_stats(ctx, which)
-            stats[name] = (avg_ms, nbytes, launches)
+            if launches:
+                stats[name] = (avg_ms, nbytes, launches)
     ctx.close()
     return {"seconds": t1 - t0, "steps": steps, "iters": iters, "rejected": rejected, "stats": stats,
             "replicas": len(ws)}
@@ -219,7 +225,14 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--copy-probe", action="store_true",
                     help="run one 256 MiB device-to-device copy first (counter calibration in profiles)")
+    ap.add_argument("--timing-only", action="store_true",
+                    help="only the eager timed run of the ensemble (one SEM launch, no masking of converged "
+                         "replicas, no graphs): the command the hardware-counter profiles are taken on")
+    ap.add_argument("--mg-fused", type=int, default=1, choices=(0, 1),
+                    help="1: fused multigrid level kernels (default); 0: separate smoother/transfer kernels")
     args = ap.parse_args()
+    global MG_FUSED
+    MG_FUSED = args.mg_fused
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU: every box here has a single MI355X, and the replicas of the "
               "ensemble share one device; run with --gpus 1.", file=sys.stderr)
@@ -236,6 +249,11 @@ def main():
         del a, b
     ens = W.ensemble(n_replicas=args.replicas)
     log("ensemble: %d replicas, %d bodies, %d markers" % (len(ens), sum(w.nb for w in ens), sum(w.nm for w in ens)))
+    if args.timing_only:
+        timing = run_gpu(ens, 1, 0, fp32=1, timing=True)
+        roofline, kernels = roofline_of(timing["stats"])
+        print(json.dumps({"timing_only": True, "roofline": roofline, "kernels": kernels}), flush=True)
+        return
 
     batched = run_gpu(ens, args.steps, args.warmup, fp32=1)
     solves = 2 * batched["replicas"] * batched["steps"]

@@ -121,6 +121,10 @@ typedef struct {
     int check_every;           /* iterations between host convergence checks (5)    */
     int use_graphs;            /* 1: replay each FGMRES iteration as a captured HIP  */
                                /*    graph on the library's stream (1)               */
+    int mg_fused;              /* 1: with mg_sweeps == 2, each multigrid level runs  */
+                               /*    as two fused kernels (sweeps + residual +       */
+                               /*    restriction; prolongation + sweeps) that give   */
+                               /*    the same V-cycle as the separate kernels (1)    */
 } rbfib_opts;
 
 typedef struct {
@@ -218,8 +222,11 @@ int rbfib_mobility_vjp(rbfib_ctx *ctx, const double *q, const double *theta, con
                        rbfib_info *info);
 
 /* Average duration (ms) of the dominant kernel class over the last solve,
- * measured with HIP events on the context stream; and its algorithmic bytes
- * per launch.  which: 0 = fused MAC saddle apply, 1 = multigrid smoother sweep. */
+ * measured with HIP events on the context stream, and its average algorithmic
+ * bytes per launch.  which: 0 = fused MAC saddle apply, 1 = level-0 smoother
+ * sweep (separate kernels), 2 = level-0 fused down kernel (two sweeps, residual,
+ * restriction), 3 = level-0 fused up kernel (prolongation, two sweeps).  Only
+ * solves run with timing enabled (rbfib_enable_timing) are counted. */
 int rbfib_kernel_stats(rbfib_ctx *ctx, int which, double *avg_ms, double *bytes_per_launch,
                        long long *launches);
 int rbfib_enable_timing(rbfib_ctx *ctx, int on);

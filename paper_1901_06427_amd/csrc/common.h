@@ -20,6 +20,22 @@
 #define RB_TILE 4
 #define RB_BLOCK 256
 #define RB_CHUNK 1024          // Krylov elements per block (RB_BLOCK * 4)
+// Fused multigrid tiles: the down kernel works on one coarse tile of
+// MGD{32,64}_{X,Y,Z} points, the up kernel on one fine tile of MGU{32,64}_{X,Y,Z}
+// points (FP32 / FP64 multigrid pools).
+#define MGD32_X 8
+#define MGD32_Y 4
+#define MGD32_Z 4
+#define MGU32_X 16
+#define MGU32_Y 8
+#define MGU32_Z 8
+#define MGD64_X 4
+#define MGD64_Y 4
+#define MGD64_Z 2
+#define MGU64_X 8
+#define MGU64_Y 8
+#define MGU64_Z 8
+#define RB_NTIMING 4           // timing classes: apply, smoother sweep, fused down, fused up (level 0)
 
 namespace rb {
 
@@ -59,6 +75,85 @@ __device__ __forceinline__ void split_index(long long lin, int n0, int n01, doub
     idx[0] = rem - j * n0;
     idx[1] = j;
     idx[2] = k;
+}
+
+// ---------------------------------------------------------------- grid transfers
+// Written with per-axis scalars (no dynamically indexed private arrays).
+// Restriction weight of the o-th fine point along an axis.
+template <typename T>
+__device__ __forceinline__ T restrict_weight(bool coarsened, bool face, int o) {
+    if (!coarsened) return (T)1;
+    if (!face) return (T)0.5;
+    return (o == 1) ? (T)0.5 : (T)0.25;
+}
+
+// Coarse points feeding one fine point along an axis: up to two (index, weight) pairs.
+template <typename T>
+struct ProlongAxis {
+    int i0, i1, cnt;
+    T w0, w1;
+};
+
+template <typename T>
+__device__ __forceinline__ ProlongAxis<T> prolong_axis(int f, int nf, int nc, int bc, bool face, int comp) {
+    ProlongAxis<T> p;
+    if (nf == nc) { p.cnt = 1; p.i0 = p.i1 = f; p.w0 = (T)1; p.w1 = (T)0; return p; }
+    const int I = f >> 1;
+    if (face) {
+        p.i0 = I; p.i1 = I;
+        if ((f & 1) == 0) { p.cnt = 1; p.w0 = (T)1; p.w1 = (T)0; }
+        else {
+            p.cnt = 2; p.w0 = (T)0.5;
+            int J = I + 1;
+            T wj = (T)0.5;
+            if (J >= nc) {
+                if (bc == RBFIB_PERIODIC) J -= nc;
+                else { J = I; wj = (T)0; }
+            }
+            p.i1 = J; p.w1 = wj;
+        }
+        if (bc == RBFIB_WALL) {          // coarse face 0 on a wall axis is the wall
+            if (p.i0 == 0) p.w0 = (T)0;
+            if (p.cnt == 2 && p.i1 == 0) p.w1 = (T)0;
+        }
+    } else {
+        p.cnt = 2; p.i0 = I; p.w0 = (T)0.75;
+        int J = (f & 1) ? I + 1 : I - 1;
+        T g = (T)0.25;
+        if (J < 0 || J >= nc) {
+            if (bc == RBFIB_PERIODIC) J = (J < 0) ? J + nc : J - nc;
+            else { J = I; g = (comp == 3) ? (T)0.25 : (T)-0.25; }
+        }
+        p.i1 = J; p.w1 = g;
+    }
+    return p;
+}
+
+// (P x_c) at fine point fi: face-normal axis linear (even faces copy, odd faces
+// average), cell-centred axes (3/4, 1/4) with odd ghosts for velocity at walls and
+// even ghosts for pressure.
+template <typename T>
+__device__ __forceinline__ T prolong_at(const RepDev &R, const LevDev &F, const LevDev &C, int comp, const int fi[3],
+                                        const T *xc) {
+    const ProlongAxis<T> px = prolong_axis<T>(fi[0], F.n[0], C.n[0], R.bc[0], comp == 0, comp);
+    const ProlongAxis<T> py = prolong_axis<T>(fi[1], F.n[1], C.n[1], R.bc[1], comp == 1, comp);
+    const ProlongAxis<T> pz = prolong_axis<T>(fi[2], F.n[2], C.n[2], R.bc[2], comp == 2, comp);
+    T acc = (T)0;
+    const long long c01 = (long long)C.n[0] * C.n[1];
+    for (int kk = 0; kk < pz.cnt; ++kk) {
+        const int k = kk ? pz.i1 : pz.i0;
+        const T wz = kk ? pz.w1 : pz.w0;
+        for (int jj = 0; jj < py.cnt; ++jj) {
+            const int j = jj ? py.i1 : py.i0;
+            const T wy = jj ? py.w1 : py.w0;
+            for (int ii = 0; ii < px.cnt; ++ii) {
+                const int i = ii ? px.i1 : px.i0;
+                const T wx = ii ? px.w1 : px.w0;
+                acc += wx * wy * wz * xc[i + (long long)C.n[0] * j + c01 * k];
+            }
+        }
+    }
+    return acc;
 }
 
 struct BlockEnt {       // one block of work: replica and local start index
@@ -270,11 +365,12 @@ struct MarkerSet {
 
 struct Timing {
     bool on = false;
-    std::vector<hipEvent_t> ev[2];
-    size_t used[2] = {0, 0};
-    double bytes[2] = {0, 0};
-    long long launches[2] = {0, 0};
-    double total_ms[2] = {0, 0};
+    std::vector<hipEvent_t> ev[RB_NTIMING];
+    std::vector<double> ev_bytes[RB_NTIMING];   // algorithmic bytes of each recorded launch
+    size_t used[RB_NTIMING] = {0, 0, 0, 0};
+    double bytes[RB_NTIMING] = {0, 0, 0, 0};
+    long long launches[RB_NTIMING] = {0, 0, 0, 0};
+    double total_ms[RB_NTIMING] = {0, 0, 0, 0};
 };
 
 struct Ctx {
@@ -316,6 +412,13 @@ struct Ctx {
     BlockEnt *d_tab_lev[RB_MAXLEV] = {nullptr};  int n_tab_lev[RB_MAXLEV] = {0};   // replicas with level l, not coarsest
     BlockEnt *d_tab_crs[RB_MAXLEV] = {nullptr};  int n_tab_crs[RB_MAXLEV] = {0};   // replicas whose coarsest is l
     BlockEnt *d_tab_all[RB_MAXLEV] = {nullptr};  int n_tab_all[RB_MAXLEV] = {0};   // replicas having level l
+    // fused level kernels (start = tile index): coarse tiles of level l+1 and fine
+    // tiles of level l, for the replicas that have level l+1
+    BlockEnt *d_tab_down[RB_MAXLEV] = {nullptr}; int n_tab_down[RB_MAXLEV] = {0};
+    BlockEnt *d_tab_up[RB_MAXLEV] = {nullptr};   int n_tab_up[RB_MAXLEV] = {0};
+    double lev_cells[RB_MAXLEV] = {0};   // points of level l summed over the replicas that have level l+1
+    double lev_cells_c[RB_MAXLEV] = {0}; // points of level l+1 over the same replicas
+    double cells_all = 0;                // level-0 points over all replicas
     // coarse dense inverses
     long long *d_coarse_off = nullptr;   // [nrep * 4] offset into coarse pools (doubles)
     double *d_coarse64 = nullptr;
@@ -361,6 +464,9 @@ template <typename T> void launch_smooth(Ctx &c, int lev, int c0, int nc, const 
 template <typename T> void launch_restrict(Ctx &c, int lev, int c0, int nc, const T *x, const T *b, T *bc);
 template <typename T> void launch_prolong(Ctx &c, int lev, int c0, int nc, const T *xc, T *xf);
 template <typename T> void launch_coarse(Ctx &c, int lev, int c0, int nc, const T *b, T *x);
+// fused level kernels (mgfused.hip)
+template <typename T> void launch_mg_down(Ctx &c, int lev, int c0, int nc, const T *b, T *x);
+template <typename T> void launch_mg_up(Ctx &c, int lev, int c0, int nc, const T *b, const T *xin, const T *xc, T *xout);
 template <typename T> void launch_proj_div(Ctx &c, const T *xv, const double *r, T *bp, double *z);
 template <typename T> void launch_proj_correct(Ctx &c, const T *xv, const T *phi, double *z);
 void launch_noise(Ctx &c, double kT, double dt, uint64_t seed, uint64_t step, double *f, bool add);

@@ -224,34 +224,31 @@ __global__ void k_restrict(const RepDev *reps, const LevDev *levs, const BlockEn
     if (pinned(comp, ci, R.bc)) { bc[cbase + lin] = (T)0; continue; }
     const T *xf = x + F.off + comp * F.N;
     const T *bf = b + F.off + comp * F.N;
-    int fi[3][3];
-    T fw[3][3];
-    int cnt[3];
+    int fb[3], fc[3];
+    bool crs[3], face[3];
     for (int a = 0; a < 3; ++a) {
-        if (F.n[a] == C.n[a]) { cnt[a] = 1; fi[a][0] = ci[a]; fw[a][0] = (T)1; continue; }
-        if (a == comp) {
-            cnt[a] = 3;
-            int f0 = 2 * ci[a];
-            int fm = f0 - 1;
-            if (fm < 0) fm += F.n[a];   // periodic wrap (wall: ci = 0 is pinned, excluded above)
-            int fp = f0 + 1;
-            if (fp >= F.n[a]) fp -= F.n[a];
-            fi[a][0] = fm; fw[a][0] = (T)0.25;
-            fi[a][1] = f0; fw[a][1] = (T)0.5;
-            fi[a][2] = fp; fw[a][2] = (T)0.25;
-        } else {
-            cnt[a] = 2;
-            fi[a][0] = 2 * ci[a]; fw[a][0] = (T)0.5;
-            fi[a][1] = 2 * ci[a] + 1; fw[a][1] = (T)0.5;
+        crs[a] = F.n[a] != C.n[a];
+        face[a] = crs[a] && a == comp;
+        fc[a] = !crs[a] ? 1 : (face[a] ? 3 : 2);
+        fb[a] = crs[a] ? 2 * ci[a] - (face[a] ? 1 : 0) : ci[a];
+    }
+    // periodic wrap of the face-normal neighbours (wall: ci = 0 is pinned, excluded above)
+    auto wrap = [](int f, int n) { return f < 0 ? f + n : (f >= n ? f - n : f); };
+    T acc = (T)0;
+    for (int kk = 0; kk < fc[2]; ++kk) {
+        const int k = wrap(fb[2] + kk, F.n[2]);
+        const T wz = restrict_weight<T>(crs[2], face[2], kk);
+        for (int jj = 0; jj < fc[1]; ++jj) {
+            const int j = wrap(fb[1] + jj, F.n[1]);
+            const T wy = restrict_weight<T>(crs[1], face[1], jj);
+            for (int ii = 0; ii < fc[0]; ++ii) {
+                const int i = wrap(fb[0] + ii, F.n[0]);
+                const T wx = restrict_weight<T>(crs[0], face[0], ii);
+                const T w = wx * wy * wz;
+                acc += w * residual_at<T>(R, F, comp, i, j, k, xf, bf);
+            }
         }
     }
-    T acc = (T)0;
-    for (int kk = 0; kk < cnt[2]; ++kk)
-        for (int jj = 0; jj < cnt[1]; ++jj)
-            for (int ii = 0; ii < cnt[0]; ++ii) {
-                T w = fw[0][ii] * fw[1][jj] * fw[2][kk];
-                acc += w * residual_at<T>(R, F, comp, fi[0][ii], fi[1][jj], fi[2][kk], xf, bf);
-            }
     bc[cbase + lin] = acc;
     }
 }
@@ -282,51 +279,7 @@ __global__ void k_prolong(const RepDev *reps, const LevDev *levs, const BlockEnt
     int fi[3];
     unlin(lin, F, fi);
     if (pinned(comp, fi, R.bc)) continue;
-    int ci[3][2];
-    T cw[3][2];
-    T cs[3][2];
-    int cnt[3];
-    for (int a = 0; a < 3; ++a) {
-        cs[a][0] = cs[a][1] = (T)1;
-        if (F.n[a] == C.n[a]) { cnt[a] = 1; ci[a][0] = fi[a]; cw[a][0] = (T)1; continue; }
-        int I = fi[a] >> 1;
-        if (a == comp) {
-            if ((fi[a] & 1) == 0) { cnt[a] = 1; ci[a][0] = I; cw[a][0] = (T)1; }
-            else {
-                cnt[a] = 2;
-                ci[a][0] = I; cw[a][0] = (T)0.5;
-                int J = I + 1;
-                if (J >= C.n[a]) {
-                    if (R.bc[a] == RBFIB_PERIODIC) J -= C.n[a];
-                    else { J = I; cs[a][1] = (T)0; }      // wall face: zero
-                }
-                ci[a][1] = J; cw[a][1] = (T)0.5;
-            }
-            // coarse slot 0 on a wall axis is the wall face (zero)
-            if (R.bc[a] == RBFIB_WALL) {
-                for (int t = 0; t < cnt[a]; ++t) if (ci[a][t] == 0) cs[a][t] = (T)0;
-            }
-        } else {
-            cnt[a] = 2;
-            ci[a][0] = I; cw[a][0] = (T)0.75;
-            int J = (fi[a] & 1) ? I + 1 : I - 1;
-            T g = (T)1;
-            if (J < 0 || J >= C.n[a]) {
-                if (R.bc[a] == RBFIB_PERIODIC) J = (J < 0) ? J + C.n[a] : J - C.n[a];
-                else { J = I; g = (comp == 3) ? (T)1 : (T)-1; }
-            }
-            ci[a][1] = J; cw[a][1] = (T)0.25; cs[a][1] = g;
-        }
-    }
-    const T *xcc = xc + C.off + comp * C.N;
-    T acc = (T)0;
-    for (int kk = 0; kk < cnt[2]; ++kk)
-        for (int jj = 0; jj < cnt[1]; ++jj)
-            for (int ii = 0; ii < cnt[0]; ++ii) {
-                T w = cw[0][ii] * cw[1][jj] * cw[2][kk] * cs[0][ii] * cs[1][jj] * cs[2][kk];
-                long long cl = (long long)ci[0][ii] + (long long)C.n[0] * ((long long)ci[1][jj] + (long long)C.n[1] * ci[2][kk]);
-                acc += w * xcc[cl];
-            }
+    const T acc = prolong_at<T>(R, F, C, comp, fi, xc + C.off + comp * C.N);
     xf[F.off + comp * F.N + lin] += acc;
     }
 }

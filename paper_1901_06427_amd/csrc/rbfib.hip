@@ -171,8 +171,17 @@ void zero_device(Ctx &c, T *p, long long n) {
 
 static void free_all(Ctx &c);
 
+// Captured FGMRES iterations bake in the tolerance and the multigrid settings;
+// they are rebuilt on the next solve after any of these change.
+static void drop_graphs(Ctx &c) {
+    for (int f = 0; f < 2; ++f)
+        for (auto &g : c.graphs[f]) if (g) { (void)hipGraphExecDestroy(g); g = nullptr; }
+}
+
 // ------------------------------------------------------------------ operator and preconditioner
-static void record(Ctx &c, int cls, bool start) {
+// Events around one launch of a timed kernel class; `bytes` (given with the
+// closing record) is the launch's algorithmic HBM traffic.
+static void record(Ctx &c, int cls, bool start, double bytes = 0.0) {
     if (!c.timing.on) return;
     auto &v = c.timing.ev[cls];
     size_t k = c.timing.used[cls];
@@ -182,6 +191,7 @@ static void record(Ctx &c, int cls, bool start) {
     } else {
         if (k + 2 > v.size()) return;
         HIP_OK(hipEventRecord(v[k + 1], c.stream));
+        c.timing.ev_bytes[cls][k / 2] = bytes;
         c.timing.used[cls] = k + 2;
     }
 }
@@ -189,7 +199,7 @@ static void record(Ctx &c, int cls, bool start) {
 static void apply_op(Ctx &c, MarkerSet &ms, const double *x, double *y, bool fluid_only) {
     record(c, 0, true);
     launch_apply_fluid(c, x, y);
-    record(c, 0, false);
+    record(c, 0, false, c.cells_all * 64.0);      // read 4 FP64 fields, write 4
     if (fluid_only || c.nm == 0) {
         launch_zero_bodies(c, y);
         return;
@@ -198,10 +208,29 @@ static void apply_op(Ctx &c, MarkerSet &ms, const double *x, double *y, bool flu
     launch_body_apply(c, ms, nullptr, x, y);
 }
 
+// One V-cycle on components c0 .. c0+nc-1 of the multigrid pools; returns the
+// pool that holds the level-0 result (X for the unfused path, T for the fused one).
 template <typename T>
-static void vcycle(Ctx &c, int c0, int nc) {
+static T *vcycle(Ctx &c, int c0, int nc) {
     T *X = (T *)c.mg_x, *B = (T *)c.mg_b, *Tt = (T *)c.mg_t;
+    const double sz = (double)sizeof(T) * nc;
     int nu = std::max(1, c.opts.mg_sweeps);
+    if (c.opts.mg_fused && nu == 2) {
+        // down: X(l) = two sweeps from zero, B(l+1) = R (B(l) - A X(l)); coarsest: T = A^-1 B
+        for (int l = 0; l < c.maxlev; ++l) {
+            launch_coarse<T>(c, l, c0, nc, B, Tt);
+            if (l == 0) record(c, 2, true);
+            launch_mg_down<T>(c, l, c0, nc, B, X);
+            if (l == 0) record(c, 2, false, sz * (2.0 * c.lev_cells[0] + c.lev_cells_c[0]));
+        }
+        // up: T(l) = two sweeps from X(l) + P T(l+1)
+        for (int l = c.maxlev - 2; l >= 0; --l) {
+            if (l == 0) record(c, 3, true);
+            launch_mg_up<T>(c, l, c0, nc, B, X, Tt, Tt);
+            if (l == 0) record(c, 3, false, sz * (3.0 * c.lev_cells[0] + c.lev_cells_c[0]));
+        }
+        return Tt;
+    }
     for (int l = 0; l < c.maxlev; ++l) {
         launch_coarse<T>(c, l, c0, nc, B, X);
         if (c.n_tab_lev[l] == 0) continue;
@@ -210,7 +239,7 @@ static void vcycle(Ctx &c, int c0, int nc) {
             T *in = (out == X) ? Tt : X;
             if (l == 0) record(c, 1, true);
             launch_smooth<T>(c, l, c0, nc, in, out, B, k == 1);
-            if (l == 0) record(c, 1, false);
+            if (l == 0) record(c, 1, false, sz * c.lev_cells[0] * (k == 1 ? 2.0 : 3.0));
         }
         launch_restrict<T>(c, l, c0, nc, X, B, B);
     }
@@ -221,11 +250,12 @@ static void vcycle(Ctx &c, int c0, int nc) {
         for (int k = 1; k <= nu; ++k) {
             if (l == 0) record(c, 1, true);
             launch_smooth<T>(c, l, c0, nc, in, out, B, false);
-            if (l == 0) record(c, 1, false);
+            if (l == 0) record(c, 1, false, sz * c.lev_cells[0] * 3.0);
             std::swap(in, out);
         }
         if (in != X) launch_smooth<T>(c, l, c0, nc, in, X, B, false);   // odd count: one more sweep lands in X
     }
+    return X;
 }
 
 template <typename T>
@@ -234,13 +264,14 @@ static void precond_t(Ctx &c, MarkerSet &ms, const double *theta, const double *
     if (bodies) launch_body_precond(c, ms, theta, r, z);
     launch_copy(c, r, c.fluid_tmp, c.mask);
     if (bodies) launch_spread(c, ms, z, c.fluid_tmp, 1.0);
-    T *X = (T *)c.mg_x, *B = (T *)c.mg_b;
+    T *B = (T *)c.mg_b;
     launch_to_level0<T>(c, c.fluid_tmp, B, 0, 3);
-    vcycle<T>(c, 0, 3);
-    launch_proj_div<T>(c, X, c.fluid_tmp, B, z);
-    vcycle<T>(c, 3, 1);
-    launch_proj_correct<T>(c, X, X, z);
+    T *V = vcycle<T>(c, 0, 3);
+    launch_proj_div<T>(c, V, c.fluid_tmp, B, z);
+    T *P = vcycle<T>(c, 3, 1);
+    launch_proj_correct<T>(c, V, P, z);
     if (!bodies) launch_zero_bodies(c, z);
+    HIP_OK(hipGetLastError());     // a launch the runtime refused surfaces here, not as stale results
 }
 
 static void precond(Ctx &c, MarkerSet &ms, const double *theta, const double *r, double *z, bool fluid_only) {
@@ -327,8 +358,7 @@ static void fgmres(Ctx &c, MarkerSet &ms, const double *theta, const double *b, 
                 bool graphable = c.opts.use_graphs && !c.timing.on && theta == c.theta_int && &ms == &c.ms[0];
                 if (graphable) {
                     if (c.graph_tol != tol) {
-                        for (int f = 0; f < 2; ++f)
-                            for (auto &g : c.graphs[f]) if (g) { (void)hipGraphExecDestroy(g); g = nullptr; }
+                        drop_graphs(c);
                         c.graph_tol = tol;
                     }
                     hipGraphExec_t &ge = c.graphs[fluid_only ? 1 : 0][j];
@@ -391,11 +421,12 @@ static void fgmres(Ctx &c, MarkerSet &ms, const double *theta, const double *b, 
         info[r].status = s;
     }
     if (c.timing.on) {
-        for (int cls = 0; cls < 2; ++cls) {
+        for (int cls = 0; cls < RB_NTIMING; ++cls) {
             for (size_t k = 0; k + 1 < c.timing.used[cls]; k += 2) {
                 float ms_ = 0.f;
                 HIP_OK(hipEventElapsedTime(&ms_, c.timing.ev[cls][k], c.timing.ev[cls][k + 1]));
                 c.timing.total_ms[cls] += ms_;
+                c.timing.bytes[cls] += c.timing.ev_bytes[cls][k / 2];
                 c.timing.launches[cls] += 1;
             }
             c.timing.used[cls] = 0;
@@ -683,6 +714,30 @@ static void build(Ctx &c, int nrep, const rbfib_grid *grids, const rbfib_bodies 
         c.n_tab_crs[l] = (int)tc.size(); c.d_tab_crs[l] = upload(c, tc);
         c.n_tab_all[l] = (int)ta.size(); c.d_tab_all[l] = upload(c, ta);
     }
+    // fused level kernels: one block per coarse tile (down) / fine tile (up)
+    const bool t32 = c.opts.precond_fp32 != 0;
+    const int dt[3] = {t32 ? MGD32_X : MGD64_X, t32 ? MGD32_Y : MGD64_Y, t32 ? MGD32_Z : MGD64_Z};
+    const int ut[3] = {t32 ? MGU32_X : MGU64_X, t32 ? MGU32_Y : MGU64_Y, t32 ? MGU32_Z : MGU64_Z};
+    for (int l = 0; l + 1 < c.maxlev; ++l) {
+        std::vector<BlockEnt> td, tu;
+        for (int r = 0; r < nrep; ++r) {
+            if (l + 1 >= c.reps[r].nlev) continue;
+            const LevDev &F = c.levs[(size_t)r * RB_MAXLEV + l];
+            const LevDev &C = c.levs[(size_t)r * RB_MAXLEV + l + 1];
+            long long nd = 1, nu_ = 1;
+            for (int a = 0; a < 3; ++a) {
+                nd *= (C.n[a] + dt[a] - 1) / dt[a];
+                nu_ *= (F.n[a] + ut[a] - 1) / ut[a];
+            }
+            for (long long t = 0; t < nd; ++t) td.push_back(BlockEnt{r, 1, t});
+            for (long long t = 0; t < nu_; ++t) tu.push_back(BlockEnt{r, 1, t});
+            c.lev_cells[l] += (double)F.N;
+            c.lev_cells_c[l] += (double)C.N;
+        }
+        c.n_tab_down[l] = (int)td.size(); c.d_tab_down[l] = upload(c, td);
+        c.n_tab_up[l] = (int)tu.size(); c.d_tab_up[l] = upload(c, tu);
+    }
+    c.cells_all = (double)total_cells;
 
     // ---- dense coarsest inverses, deduplicated by (dims, spacing, bc, eta, component)
     std::map<std::string, long long> keyoff;
@@ -862,8 +917,9 @@ static void build(Ctx &c, int nrep, const rbfib_grid *grids, const rbfib_bodies 
     c.UR = dalloc<double>(6 * (size_t)std::max(c.nb, 1));
     c.slip_acc = dalloc<double>(3 * (size_t)std::max(c.nm, 1));
     c.jbc = dalloc<double>(3 * (size_t)std::max(c.nm, 1));
-    for (int cls = 0; cls < 2; ++cls) {
+    for (int cls = 0; cls < RB_NTIMING; ++cls) {
         c.timing.ev[cls].resize(8192);
+        c.timing.ev_bytes[cls].assign(4096, 0.0);
         for (auto &e : c.timing.ev[cls]) HIP_OK(hipEventCreate(&e));
     }
     HIP_OK(hipStreamSynchronize(c.stream));
@@ -874,7 +930,9 @@ static void free_all(Ctx &c) {
     F(c.d_reps); F(c.d_levs); F(c.d_marker_body); F(c.d_body_rep); F(c.d_body_off); F(c.d_tile_rep); F(c.d_rref);
     F(c.d_body_shape); F(c.d_shapes); F(c.d_shape_data); F(c.d_body_len);
     F(c.d_tab_cells); F(c.d_tab_vec); F(c.d_vec_first); F(c.d_vec_nblk);
-    for (int l = 0; l < RB_MAXLEV; ++l) { F(c.d_tab_lev[l]); F(c.d_tab_crs[l]); F(c.d_tab_all[l]); }
+    for (int l = 0; l < RB_MAXLEV; ++l) {
+        F(c.d_tab_lev[l]); F(c.d_tab_crs[l]); F(c.d_tab_all[l]); F(c.d_tab_down[l]); F(c.d_tab_up[l]);
+    }
     F(c.d_coarse_off); F(c.d_coarse64); F(c.d_coarse32);
     F(c.mg_x); F(c.mg_b); F(c.mg_t);
     for (int k = 0; k < 4; ++k) {
@@ -895,7 +953,7 @@ static void free_all(Ctx &c) {
     if (c.ev_in) (void)hipEventDestroy(c.ev_in);
     if (c.ev_out) (void)hipEventDestroy(c.ev_out);
     if (c.stream && c.stream != c.user_stream) (void)hipStreamDestroy(c.stream);
-    for (int cls = 0; cls < 2; ++cls)
+    for (int cls = 0; cls < RB_NTIMING; ++cls)
         for (auto &e : c.timing.ev[cls]) (void)hipEventDestroy(e);
 }
 
@@ -925,6 +983,7 @@ void rbfib_default_opts(rbfib_opts *o) {
     o->min_body_dist = 0.0;
     o->check_every = 5;
     o->use_graphs = 1;
+    o->mg_fused = 1;
 }
 
 const char *rbfib_strerror(int code) {
@@ -990,6 +1049,8 @@ int rbfib_set_opts(rbfib_ctx *ctx, const rbfib_opts *o) {
     // fields fixed at creation: restart length, precision, blob radius
     if (o->restart != c.opts.restart || (o->precond_fp32 != 0) != c.mg_fp32 || o->blob_radius != c.opts.blob_radius)
         return RBFIB_EINVAL;
+    if (o->mg_sweeps != c.opts.mg_sweeps || o->mg_omega != c.opts.mg_omega || o->mg_fused != c.opts.mg_fused)
+        drop_graphs(c);
     c.opts = *o;
     return RBFIB_OK;
 }
@@ -1169,22 +1230,19 @@ int rbfib_mobility_vjp(rbfib_ctx *ctx, const double *q, const double *theta, con
 int rbfib_enable_timing(rbfib_ctx *ctx, int on) {
     if (!ctx) return RBFIB_EINVAL;
     ctx->c.timing.on = on != 0;
-    for (int k = 0; k < 2; ++k) { ctx->c.timing.total_ms[k] = 0; ctx->c.timing.launches[k] = 0; ctx->c.timing.used[k] = 0; }
+    for (int k = 0; k < RB_NTIMING; ++k) {
+        ctx->c.timing.total_ms[k] = 0; ctx->c.timing.bytes[k] = 0; ctx->c.timing.launches[k] = 0; ctx->c.timing.used[k] = 0;
+    }
     return RBFIB_OK;
 }
 
 int rbfib_kernel_stats(rbfib_ctx *ctx, int which, double *avg_ms, double *bytes_per_launch, long long *launches) {
-    if (!ctx || which < 0 || which > 1) return RBFIB_EINVAL;
+    if (!ctx || which < 0 || which >= RB_NTIMING) return RBFIB_EINVAL;
     Ctx &c = ctx->c;
     long long n = c.timing.launches[which];
     if (avg_ms) *avg_ms = n ? c.timing.total_ms[which] / n : 0.0;
     if (launches) *launches = n;
-    double cells = 0.0;
-    for (auto &R : c.reps) cells += (double)R.N;
-    if (bytes_per_launch) {
-        if (which == 0) *bytes_per_launch = cells * 8.0 * 8.0;            // read 4 FP64 fields, write 4
-        else *bytes_per_launch = cells * 3.0 * 3.0 * (c.mg_fp32 ? 4.0 : 8.0);   // 3 comps: read x, b; write x
-    }
+    if (bytes_per_launch) *bytes_per_launch = n ? c.timing.bytes[which] / n : 0.0;
     return RBFIB_OK;
 }
 
