@@ -124,7 +124,7 @@ class Ensemble:
         return F
 
 
-MG_FUSED = 1
+MG_FUSED = 0
 
 
 def run_gpu(ws, steps, warmup, fp32, seed=2024, timing=False, graphs=True):
@@ -224,12 +224,12 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--copy-probe", action="store_true",
-                    help="run one 256 MiB device-to-device copy first (counter calibration in profiles)")
+                    help="run one elementwise kernel reading and writing 256 MiB first (counter calibration)")
     ap.add_argument("--timing-only", action="store_true",
                     help="only the eager timed run of the ensemble (one SEM launch, no masking of converged "
                          "replicas, no graphs): the command the hardware-counter profiles are taken on")
-    ap.add_argument("--mg-fused", type=int, default=1, choices=(0, 1),
-                    help="1: fused multigrid level kernels (default); 0: separate smoother/transfer kernels")
+    ap.add_argument("--mg-fused", type=int, default=0, choices=(0, 1),
+                    help="0: separate smoother/transfer kernels (default); 1: fused multigrid level kernels")
     args = ap.parse_args()
     global MG_FUSED
     MG_FUSED = args.mg_fused
@@ -241,10 +241,12 @@ def main():
     import torch
     import workloads as W
     if args.copy_probe:
+        # one elementwise kernel that reads 256 MiB and writes 256 MiB: the
+        # calibration dispatch for the FETCH_SIZE / WRITE_SIZE counters
         a = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device="cuda")
         b = torch.empty_like(a)
         torch.cuda.synchronize()
-        b.copy_(a)
+        torch.mul(a, 2.0, out=b)
         torch.cuda.synchronize()
         del a, b
     ens = W.ensemble(n_replicas=args.replicas)
