@@ -228,8 +228,9 @@ def main():
     ap.add_argument("--timing-only", action="store_true",
                     help="only the eager timed run of the ensemble (one SEM launch, no masking of converged "
                          "replicas, no graphs): the command the hardware-counter profiles are taken on")
-    ap.add_argument("--mg-fused", type=int, default=0, choices=(0, 1),
-                    help="0: separate smoother/transfer kernels (default); 1: fused multigrid level kernels")
+    ap.add_argument("--mg-fused", type=int, default=0, choices=(0, 1, 2),
+                    help="multigrid level kernels: 0 separate (default), 1 fused where the level fills the "
+                         "device, 2 fused on every level")
     args = ap.parse_args()
     global MG_FUSED
     MG_FUSED = args.mg_fused

@@ -121,10 +121,12 @@ typedef struct {
     int check_every;           /* iterations between host convergence checks (5)    */
     int use_graphs;            /* 1: replay each FGMRES iteration as a captured HIP  */
                                /*    graph on the library's stream (1)               */
-    int mg_fused;              /* 1: with mg_sweeps == 2, each multigrid level runs  */
-                               /*    as two fused kernels (sweeps + residual +       */
-                               /*    restriction; prolongation + sweeps) that give   */
-                               /*    the same V-cycle as the separate kernels (1)    */
+    int mg_fused;              /* multigrid levels as two fused kernels (sweeps +    */
+                               /*    residual + restriction; prolongation + sweeps)  */
+                               /*    with the same values as the separate kernels;   */
+                               /*    needs mg_sweeps == 2.  0 never, 1 on levels     */
+                               /*    with enough workgroups to fill the device,      */
+                               /*    2 on every level (0)                            */
 } rbfib_opts;
 
 typedef struct {

@@ -20,21 +20,14 @@
 #define RB_TILE 4
 #define RB_BLOCK 256
 #define RB_CHUNK 1024          // Krylov elements per block (RB_BLOCK * 4)
-// Fused multigrid tiles: the down kernel works on one coarse tile of
-// MGD{32,64}_{X,Y,Z} points, the up kernel on one fine tile of MGU{32,64}_{X,Y,Z}
-// points (FP32 / FP64 multigrid pools).
-#define MGD32_X 8
-#define MGD32_Y 4
-#define MGD32_Z 4
-#define MGU32_X 16
-#define MGU32_Y 8
-#define MGU32_Z 8
-#define MGD64_X 4
-#define MGD64_Y 4
-#define MGD64_Z 2
-#define MGU64_X 8
-#define MGU64_Y 8
-#define MGU64_Z 8
+// Fused multigrid kernels: a workgroup owns MGF_OX x MGF_OY x MGF_ZC fine points
+// of one component (all even, so that coarse cells never straddle two blocks).
+#define MGF_OX 32
+#define MGF_OY 8
+#define MGF_ZC 16
+// A level runs fused only with at least this many workgroups (each marches
+// through its z planes, so it needs several resident workgroups per CU).
+#define MGF_MIN_BLOCKS 1024
 #define RB_NTIMING 4           // timing classes: apply, smoother sweep, fused down, fused up (level 0)
 
 namespace rb {
@@ -75,6 +68,56 @@ __device__ __forceinline__ void split_index(long long lin, int n0, int n01, doub
     idx[0] = rem - j * n0;
     idx[1] = j;
     idx[2] = k;
+}
+
+// ---------------------------------------------------------------- smoother arithmetic
+// Every multigrid kernel evaluates the Laplacian, the Jacobi update, the residual
+// and the transfer sums through these helpers, with explicit fused multiply-adds,
+// so that the separate and the fused kernels round identically whatever the
+// compiler's contraction choices.
+__device__ __forceinline__ float fmad(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fmad(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
+// acc + (up - 2 self + um) ih2: one axis of the 7-point Laplacian
+template <typename T>
+__device__ __forceinline__ T lap_acc(T up, T self, T um, T ih2, T acc) {
+    return fmad(fmad((T)-2, self, up) + um, ih2, acc);
+}
+// damped-Jacobi weight omega / (s diag)
+template <typename T>
+__device__ __forceinline__ T jacobi_w(T omega, T s, T dg) { return omega / (s * dg); }
+// residual b - s lap
+template <typename T>
+__device__ __forceinline__ T mg_residual(T b, T s, T lap) { return fmad(-s, lap, b); }
+// x + w (b - s lap)
+template <typename T>
+__device__ __forceinline__ T jacobi_step(T x, T b, T s, T lap, T w) { return fmad(mg_residual(b, s, lap), w, x); }
+// diagonal term of axis a: -2, plus one ghost weight per wall the point touches
+// (tangential velocity odd: -1, pressure even: +1; face-normal axes have none)
+template <typename T>
+__device__ __forceinline__ T diag_axis(int comp, int a, int g, int n, int bc) {
+    T da = (T)-2;
+    if (bc == RBFIB_WALL && a != comp) {
+        const T gg = (comp == 3) ? (T)1 : (T)-1;
+        if (g == 0) da += gg;
+        if (g == n - 1) da += gg;
+    }
+    return da;
+}
+
+// neighbour rules along one axis: 0 neighbour value, 1 zero (wall face),
+// 2 even ghost (+self), 3 odd ghost (-self)
+__device__ __forceinline__ int nbr_kind(int g, int d, int n, int bc, int a, int comp) {
+    if (bc == RBFIB_PERIODIC) return 0;
+    const int q = g + d;
+    if (a == comp) return (q <= 0 || q >= n) ? 1 : 0;
+    if (q < 0 || q >= n) return (comp == 3) ? 2 : 3;
+    return 0;
+}
+
+template <typename T>
+__device__ __forceinline__ T pick(int kind, T nb, T self) {
+    return kind == 0 ? nb : (kind == 1 ? (T)0 : (kind == 2 ? self : -self));
 }
 
 // ---------------------------------------------------------------- grid transfers
@@ -149,7 +192,7 @@ __device__ __forceinline__ T prolong_at(const RepDev &R, const LevDev &F, const 
             for (int ii = 0; ii < px.cnt; ++ii) {
                 const int i = ii ? px.i1 : px.i0;
                 const T wx = ii ? px.w1 : px.w0;
-                acc += wx * wy * wz * xc[i + (long long)C.n[0] * j + c01 * k];
+                acc = fmad(wx * wy * wz, xc[i + (long long)C.n[0] * j + c01 * k], acc);
             }
         }
     }
@@ -412,13 +455,12 @@ struct Ctx {
     BlockEnt *d_tab_lev[RB_MAXLEV] = {nullptr};  int n_tab_lev[RB_MAXLEV] = {0};   // replicas with level l, not coarsest
     BlockEnt *d_tab_crs[RB_MAXLEV] = {nullptr};  int n_tab_crs[RB_MAXLEV] = {0};   // replicas whose coarsest is l
     BlockEnt *d_tab_all[RB_MAXLEV] = {nullptr};  int n_tab_all[RB_MAXLEV] = {0};   // replicas having level l
-    // fused level kernels (start = tile index): coarse tiles of level l+1 and fine
-    // tiles of level l, for the replicas that have level l+1
-    BlockEnt *d_tab_down[RB_MAXLEV] = {nullptr}; int n_tab_down[RB_MAXLEV] = {0};
-    BlockEnt *d_tab_up[RB_MAXLEV] = {nullptr};   int n_tab_up[RB_MAXLEV] = {0};
+    // fused level kernels (start = tile index of level l), replicas that have level l+1
+    BlockEnt *d_tab_mg[RB_MAXLEV] = {nullptr};   int n_tab_mg[RB_MAXLEV] = {0};
     double lev_cells[RB_MAXLEV] = {0};   // points of level l summed over the replicas that have level l+1
     double lev_cells_c[RB_MAXLEV] = {0}; // points of level l+1 over the same replicas
     double cells_all = 0;                // level-0 points over all replicas
+    int mg_npt = 1;                      // points per thread of the multigrid block tables
     // coarse dense inverses
     long long *d_coarse_off = nullptr;   // [nrep * 4] offset into coarse pools (doubles)
     double *d_coarse64 = nullptr;

@@ -42,14 +42,8 @@ __device__ __forceinline__ T lap_point(const T *u, int c, int idx[3], const int 
     for (int a = 0; a < 3; ++a) {
         T up = nbr(u, c, a, +1, idx, n, bc, self, lin, stride);
         T um = nbr(u, c, a, -1, idx, n, bc, self, lin, stride);
-        acc += (up - (T)2 * self + um) * (T)ih2[a];
-        T da = (T)-2;
-        if (bc[a] == RBFIB_WALL && a != c) {
-            T g = (c == 3) ? (T)1 : (T)-1;
-            if (idx[a] == 0) da += g;
-            if (idx[a] == n[a] - 1) da += g;
-        }
-        dg += da * (T)ih2[a];
+        acc = lap_acc<T>(up, self, um, (T)ih2[a], acc);
+        dg = fmad(diag_axis<T>(c, a, idx[a], n[a], bc[a]), (T)ih2[a], dg);
         stride *= n[a];
     }
     diag = dg;
@@ -145,51 +139,94 @@ void launch_to_level0(Ctx &c, const double *src, T *b, int c0, int nc) {
 }
 
 // Operator of component comp at a level: A = -eta Lm (velocity) or -L (pressure).
-template <typename T>
-__global__ void k_smooth(const RepDev *reps, const LevDev *levs, const BlockEnt *tab, int lev, int c0,
-                         const T *__restrict__ xin, T *__restrict__ xout, const T *__restrict__ b, double omega,
-                         int first, const int *__restrict__ mask) {
-    BlockEnt be = tab[blockIdx.x];
+// Damped Jacobi sweep x_out = x_in + w (b - A x_in), w = omega / diag (FIRST: x_in = 0).
+// NPT points per thread, all loads of a thread issued before any arithmetic and
+// the boundary rules applied with selects, so that the loads of the NPT points are
+// in flight together.
+template <typename T, int NPT, bool FIRST>
+__global__ __launch_bounds__(RB_BLOCK) void k_smooth(const RepDev *reps, const LevDev *levs, const BlockEnt *tab,
+                                                     int lev, int c0, const T *__restrict__ xin, T *__restrict__ xout,
+                                                     const T *__restrict__ b, double omega,
+                                                     const int *__restrict__ mask) {
+    const BlockEnt be = tab[blockIdx.x];
     if (mask && !mask[be.rep]) return;
-    int comp = c0 + blockIdx.y;
+    const int comp = c0 + blockIdx.y;
     const RepDev &R = reps[be.rep];
     const LevDev &Lv = levs[be.rep * RB_MAXLEV + lev];
-    for (int t_ = 0; t_ < be.npt; ++t_) {
-    long long lin = be.start + threadIdx.x + (long long)t_ * RB_BLOCK;
-    if (lin >= Lv.N) continue;
-    int idx[3];
-    unlin(lin, Lv, idx);
-    long long base = Lv.off + comp * Lv.N;
-    if (pinned(comp, idx, R.bc)) { xout[base + lin] = (T)0; continue; }
-    T s = (comp < 3) ? (T)(-R.eta) : (T)-1;
-    T dg, lap;
-    if (first) {
-        // x_in = 0: diagonal only
-        dg = (T)0;
+    const long long base = Lv.off + comp * Lv.N;
+    const T *xi = xin + base;
+    const T *bb = b + base;
+    T *xo = xout + base;
+    const T s = (comp < 3) ? (T)(-R.eta) : (T)-1;
+    const int st[3] = {1, Lv.n[0], Lv.n[0] * Lv.n[1]};
+    int lin[NPT], kinds[NPT];
+    bool ok[NPT], pin[NPT];
+    T dg[NPT], bv[NPT], xv[NPT], nb[NPT][6];
+#pragma unroll
+    for (int t = 0; t < NPT; ++t) {
+        const long long l = be.start + threadIdx.x + (long long)t * RB_BLOCK;
+        ok[t] = l < Lv.N;
+        lin[t] = ok[t] ? (int)l : 0;
+        int idx[3];
+        unlin(lin[t], Lv, idx);
+        pin[t] = pinned(comp, idx, R.bc);
+        T d = (T)0;
+        int kd = 0;
+        int off[6];
+#pragma unroll
         for (int a = 0; a < 3; ++a) {
-            T da = (T)-2;
-            if (R.bc[a] == RBFIB_WALL && a != comp) {
-                T g = (comp == 3) ? (T)1 : (T)-1;
-                if (idx[a] == 0) da += g;
-                if (idx[a] == Lv.n[a] - 1) da += g;
-            }
-            dg += da * (T)Lv.inv_h2[a];
+            d = fmad(diag_axis<T>(comp, a, idx[a], Lv.n[a], R.bc[a]), (T)Lv.inv_h2[a], d);
+            const int km = nbr_kind(idx[a], -1, Lv.n[a], R.bc[a], a, comp);
+            const int kp = nbr_kind(idx[a], +1, Lv.n[a], R.bc[a], a, comp);
+            kd |= (km | (kp << 2)) << (4 * a);
+            // periodic neighbours wrap; the other rules never read the neighbour
+            off[2 * a] = km ? 0 : (idx[a] == 0 ? (Lv.n[a] - 1) * st[a] : -st[a]);
+            off[2 * a + 1] = kp ? 0 : (idx[a] == Lv.n[a] - 1 ? -(Lv.n[a] - 1) * st[a] : st[a]);
         }
-        xout[base + lin] = (T)omega * b[base + lin] / (s * dg);
-        continue;
+        dg[t] = d;
+        kinds[t] = kd;
+        bv[t] = bb[lin[t]];
+        if (!FIRST) {
+            xv[t] = xi[lin[t]];
+#pragma unroll
+            for (int q = 0; q < 6; ++q) nb[t][q] = xi[lin[t] + off[q]];
+        }
     }
-    lap = lap_point<T>(xin + base, comp, idx, Lv.n, R.bc, Lv.inv_h2, lin, dg);
-    T xv = xin[base + lin];
-    T res = b[base + lin] - s * lap;
-    xout[base + lin] = xv + (T)omega * res / (s * dg);
+#pragma unroll
+    for (int t = 0; t < NPT; ++t) {
+        const T w = jacobi_w<T>((T)omega, s, dg[t]);
+        T y;
+        if (FIRST) {
+            y = bv[t] * w;
+        } else {
+            T acc = (T)0;
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                const int kd = kinds[t] >> (4 * a);
+                acc = lap_acc<T>(pick<T>((kd >> 2) & 3, nb[t][2 * a + 1], xv[t]), xv[t],
+                                 pick<T>(kd & 3, nb[t][2 * a], xv[t]), (T)Lv.inv_h2[a], acc);
+            }
+            y = jacobi_step<T>(xv[t], bv[t], s, acc, w);
+        }
+        if (ok[t]) xo[lin[t]] = pin[t] ? (T)0 : y;
     }
+}
+
+template <typename T, int NPT>
+static void launch_smooth_n(Ctx &c, int lev, int c0, int nc, const T *xin, T *xout, const T *b, bool first) {
+    if (first)
+        hipLaunchKernelGGL((k_smooth<T, NPT, true>), dim3(c.n_tab_lev[lev], nc), dim3(RB_BLOCK), 0, c.stream,
+                           c.d_reps, c.d_levs, c.d_tab_lev[lev], lev, c0, xin, xout, b, c.opts.mg_omega, c.mask);
+    else
+        hipLaunchKernelGGL((k_smooth<T, NPT, false>), dim3(c.n_tab_lev[lev], nc), dim3(RB_BLOCK), 0, c.stream,
+                           c.d_reps, c.d_levs, c.d_tab_lev[lev], lev, c0, xin, xout, b, c.opts.mg_omega, c.mask);
 }
 
 template <typename T>
 void launch_smooth(Ctx &c, int lev, int c0, int nc, const T *xin, T *xout, const T *b, bool first) {
     if (c.n_tab_lev[lev] == 0) return;
-    hipLaunchKernelGGL(k_smooth<T>, dim3(c.n_tab_lev[lev], nc), dim3(RB_BLOCK), 0, c.stream, c.d_reps, c.d_levs,
-                       c.d_tab_lev[lev], lev, c0, xin, xout, b, c.opts.mg_omega, first ? 1 : 0, c.mask);
+    if (c.mg_npt == 4) launch_smooth_n<T, 4>(c, lev, c0, nc, xin, xout, b, first);
+    else launch_smooth_n<T, 1>(c, lev, c0, nc, xin, xout, b, first);
 }
 
 // Residual of level lev restricted to level lev+1: face-normal axis full weighting
@@ -203,7 +240,7 @@ __device__ T residual_at(const RepDev &R, const LevDev &Lv, int comp, int i, int
     T dg;
     T lap = lap_point<T>(x, comp, idx, Lv.n, R.bc, Lv.inv_h2, lin, dg);
     T s = (comp < 3) ? (T)(-R.eta) : (T)-1;
-    return b[lin] - s * lap;
+    return mg_residual<T>(b[lin], s, lap);
 }
 
 template <typename T>
@@ -244,8 +281,7 @@ __global__ void k_restrict(const RepDev *reps, const LevDev *levs, const BlockEn
             for (int ii = 0; ii < fc[0]; ++ii) {
                 const int i = wrap(fb[0] + ii, F.n[0]);
                 const T wx = restrict_weight<T>(crs[0], face[0], ii);
-                const T w = wx * wy * wz;
-                acc += w * residual_at<T>(R, F, comp, i, j, k, xf, bf);
+                acc = fmad(wx * wy * wz, residual_at<T>(R, F, comp, i, j, k, xf, bf), acc);
             }
         }
     }

@@ -14,7 +14,8 @@ __device__ __forceinline__ double wave_sum(double v) {
 }
 
 // partial[blk * stride + i] = sum over the block's chunk of V_i . w.  The chunk of w
-// is staged in LDS once; each wavefront then owns every fourth basis vector, so the
+// is staged in LDS once; each wavefront then owns every fourth basis vector and
+// reads its chunk of V_i with all sixteen loads per lane in flight together, so the
 // vector loop needs no block barrier.
 __global__ __launch_bounds__(RB_BLOCK) void k_dot_partial(const RepDev *reps, const BlockEnt *tab, const double *V,
                                                           long long L, int nvec, const double *__restrict__ w,
@@ -30,8 +31,15 @@ __global__ __launch_bounds__(RB_BLOCK) void k_dot_partial(const RepDev *reps, co
     int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     for (int i = wid; i < nvec; i += RB_BLOCK / 64) {
         const double *Vi = V + (long long)i * L + b;
+        double v[RB_CHUNK / 64];
+#pragma unroll
+        for (int m = 0; m < RB_CHUNK / 64; ++m) {
+            const int k = lane + 64 * m;
+            v[m] = k < n ? Vi[k] : 0.0;
+        }
         double acc = 0.0;
-        for (int k = lane; k < n; k += 64) acc += Vi[k] * ws[k];
+#pragma unroll
+        for (int m = 0; m < RB_CHUNK / 64; ++m) acc = fma(v[m], ws[lane + 64 * m], acc);
         acc = wave_sum(acc);
         if (lane == 0) partial[(long long)blockIdx.x * stride + i] = acc;
     }
@@ -80,12 +88,40 @@ __global__ __launch_bounds__(RB_BLOCK) void k_axpy_multi(const RepDev *reps, con
     __syncthreads();
     long long b = R.off + be.start;
     int n = (int)min((long long)RB_CHUNK, R.len - be.start);
+    // four elements per thread; four basis vectors per step, so that sixteen loads
+    // are in flight; each element sums its terms in increasing i
+    constexpr int E = RB_CHUNK / RB_BLOCK;
+    double acc[E];
+    bool ok[E];
+#pragma unroll
+    for (int m = 0; m < E; ++m) {
+        acc[m] = 0.0;
+        ok[m] = threadIdx.x + RB_BLOCK * m < n;
+    }
+    int i = 0;
+    for (; i + 4 <= nvec; i += 4) {
+        double v[4][E];
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int m = 0; m < E; ++m)
+                v[q][m] = ok[m] ? V[(long long)(i + q) * L + b + threadIdx.x + RB_BLOCK * m] : 0.0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int m = 0; m < E; ++m) acc[m] = fma(cf[i + q], v[q][m], acc[m]);
+    }
+    for (; i < nvec; ++i) {
+#pragma unroll
+        for (int m = 0; m < E; ++m)
+            if (ok[m]) acc[m] = fma(cf[i], V[(long long)i * L + b + threadIdx.x + RB_BLOCK * m], acc[m]);
+    }
     double sq = 0.0;
-    for (int k = threadIdx.x; k < n; k += RB_BLOCK) {
-        long long g = b + k;
-        double acc = 0.0;
-        for (int i = 0; i < nvec; ++i) acc += cf[i] * V[(long long)i * L + g];
-        double v = w[g] + acc;
+#pragma unroll
+    for (int m = 0; m < E; ++m) {
+        if (!ok[m]) continue;
+        const long long g = b + threadIdx.x + RB_BLOCK * m;
+        const double v = w[g] + acc[m];
         w[g] = v;
         sq += v * v;
     }

@@ -1,85 +1,122 @@
-// Fused multigrid level kernels (two damped-Jacobi sweeps per level).
+// Fused multigrid level kernels (V(2,2) damped Jacobi), marching along z.
 //
-// k_mg_down (one workgroup per coarse tile of level l+1): stages b of level l on
-// the tile's fine region plus a two-point halo in LDS, takes the first sweep from
-// zero (x1 = omega D^-1 b), the second sweep, writes the smoothed x of the fine
-// points the tile owns, forms the residual and restricts it to the coarse tile:
-// one read of b, one write of x and of the coarse right-hand side, instead of
-// three launches and four passes.
+// A workgroup owns an MGF_OX x MGF_OY x MGF_ZC block of fine points of one
+// component and walks its z planes in order, keeping a few (x, y) planes with a
+// two-point halo in LDS:
 //
-// k_mg_up (one workgroup per fine tile of level l): x + P x_coarse on the tile
-// plus a two-point halo, then two sweeps in LDS, one write.
+// k_mg_down: plane t   <- b and the first sweep from zero, x1 = w b
+//            plane t-1 <- second sweep x2 from the x1 planes t-2 .. t
+//            plane t-2 <- residual r = b - A x2; x2 of owned points to HBM
+//            then every coarse plane whose fine planes are complete is
+//            restricted (full weighting on the face-normal axis, pairs on the
+//            cell axes) and written.
+// k_mg_up:   plane t   <- x + P x_coarse
+//            plane t-1 <- first sweep; plane t-2 <- second sweep, written.
 //
-// The operator, boundary rules, transfer weights and damping are those of the
-// unfused kernels in grid.hip (face-normal wall faces Dirichlet, odd ghosts for
-// tangential velocity, even ghosts for pressure, periodic wrap), applied in
-// global coordinates so that halo points outside a wall are never read.
+// Per level: b read once and x written once going down, x, b read and x written
+// once going up, instead of six separate passes.  The operator, boundary rules,
+// transfer weights and the rounding of every operation are those of the separate
+// kernels in grid.hip (shared helpers in common.h), so the V-cycle output is
+// bit-identical.
 #include "common.h"
 
 namespace rb {
 
-template <typename T> struct TileShape;
-template <> struct TileShape<float> {
-    static constexpr int CX = MGD32_X, CY = MGD32_Y, CZ = MGD32_Z, FX = MGU32_X, FY = MGU32_Y, FZ = MGU32_Z;
+#define MGF_PLANE ((MGF_OX + 5) * (MGF_OY + 5))
+#define MGF_NS ((MGF_PLANE + 255) / 256)
+
+__device__ __forceinline__ int wrap_axis(int g, int n) {
+    if (g < 0) g += n;
+    if (g < 0) g += n;
+    if (g >= n) g -= n;
+    if (g >= n) g -= n;
+    return g;
+}
+
+// Per-thread description of its (x, y) plane positions.
+template <typename T>
+struct PlaneSlots {
+    int p[MGF_NS];       // plane index, -1 if unused
+    int l0[MGF_NS], l1[MGF_NS];
+    int g0[MGF_NS], g1[MGF_NS];   // wrapped coordinates
+    int gxy[MGF_NS];     // g0 + n0 g1
+    bool in[MGF_NS];     // (x, y) inside the domain
+    bool pin[MGF_NS];    // pinned through the x or y coordinate
+    int kinds[MGF_NS];   // 2 bits each: x-, x+, y-, y+
+    T dxy[MGF_NS];       // diagonal terms of x and y
 };
-template <> struct TileShape<double> {
-    static constexpr int CX = MGD64_X, CY = MGD64_Y, CZ = MGD64_Z, FX = MGU64_X, FY = MGU64_Y, FZ = MGU64_Z;
+
+template <typename T>
+__device__ __forceinline__ void make_slots(PlaneSlots<T> &S, int PX, int PY, int px0, int py0, const LevDev &F,
+                                           const RepDev &R, int comp) {
+#pragma unroll
+    for (int k = 0; k < MGF_NS; ++k) {
+        const int p = threadIdx.x + k * 256;
+        S.p[k] = p < PX * PY ? p : -1;
+        const int l1 = p / PX, l0 = p - l1 * PX;
+        S.l0[k] = l0;
+        S.l1[k] = l1;
+        int g0 = px0 + l0, g1 = py0 + l1;
+        bool in0 = R.bc[0] == RBFIB_PERIODIC || (g0 >= 0 && g0 < F.n[0]);
+        bool in1 = R.bc[1] == RBFIB_PERIODIC || (g1 >= 0 && g1 < F.n[1]);
+        if (R.bc[0] == RBFIB_PERIODIC) g0 = wrap_axis(g0, F.n[0]);
+        if (R.bc[1] == RBFIB_PERIODIC) g1 = wrap_axis(g1, F.n[1]);
+        S.in[k] = in0 && in1;
+        S.g0[k] = g0;
+        S.g1[k] = g1;
+        S.gxy[k] = S.in[k] ? g0 + F.n[0] * g1 : 0;
+        S.pin[k] = (comp == 0 && R.bc[0] == RBFIB_WALL && g0 == 0) || (comp == 1 && R.bc[1] == RBFIB_WALL && g1 == 0);
+        S.kinds[k] = nbr_kind(g0, -1, F.n[0], R.bc[0], 0, comp) | (nbr_kind(g0, +1, F.n[0], R.bc[0], 0, comp) << 2) |
+                     (nbr_kind(g1, -1, F.n[1], R.bc[1], 1, comp) << 4) |
+                     (nbr_kind(g1, +1, F.n[1], R.bc[1], 1, comp) << 6);
+        S.dxy[k] = fmad(diag_axis<T>(comp, 1, g1, F.n[1], R.bc[1]), (T)F.inv_h2[1],
+                        fmad(diag_axis<T>(comp, 0, g0, F.n[0], R.bc[0]), (T)F.inv_h2[0], (T)0));
+    }
+}
+
+// One z plane of a marching block: unwrapped z, wrapped index, membership, rules.
+struct ZPlane {
+    int z, gz;
+    bool in, pin;
+    int km, kp;
 };
 
-__device__ __forceinline__ bool is_pinned(int comp, const int g[3], const int bc[3]) {
-    return comp < 3 && bc[comp] == RBFIB_WALL && g[comp] == 0;
+__device__ __forceinline__ ZPlane zplane(int z, const LevDev &F, const RepDev &R, int comp) {
+    ZPlane P;
+    P.z = z;
+    if (R.bc[2] == RBFIB_PERIODIC) { P.in = true; P.gz = wrap_axis(z, F.n[2]); }
+    else { P.in = z >= 0 && z < F.n[2]; P.gz = P.in ? z : 0; }
+    P.pin = comp == 2 && R.bc[2] == RBFIB_WALL && P.gz == 0;
+    P.km = nbr_kind(P.gz, -1, F.n[2], R.bc[2], 2, comp);
+    P.kp = nbr_kind(P.gz, +1, F.n[2], R.bc[2], 2, comp);
+    return P;
 }
 
-// global coordinate of box position (lo + l) along an axis; false when outside a wall
-__device__ __forceinline__ bool box_coord(int lo, int l, int n, int bc, int &g) {
-    g = lo + l;
-    if (bc == RBFIB_PERIODIC) {
-        g %= n;
-        if (g < 0) g += n;
-        return true;
-    }
-    return g >= 0 && g < n;
-}
-
+// 7-point Laplacian at plane position p of plane slot c (neighbour planes cm, cp),
+// same association as lap_point in grid.hip.
 template <typename T>
-__device__ __forceinline__ T diag_at(int comp, const int g[3], const int n[3], const int bc[3], const double ih2[3]) {
-    T dg = (T)0;
-    for (int a = 0; a < 3; ++a) {
-        T da = (T)-2;
-        if (bc[a] == RBFIB_WALL && a != comp) {
-            T gg = (comp == 3) ? (T)1 : (T)-1;
-            if (g[a] == 0) da += gg;
-            if (g[a] == n[a] - 1) da += gg;
-        }
-        dg += da * (T)ih2[a];
-    }
-    return dg;
-}
-
-// sum_a (u(+a) - 2u + u(-a)) ih2[a] at box point li (interior of the box), with
-// the boundary rule and the association of the unfused stencil.
-template <typename T>
-__device__ __forceinline__ T box_nbr(const T *A, int li, int stride, int d, T self, int q, int n, int bc, int a,
-                                     int comp) {
-    if (bc == RBFIB_PERIODIC) return A[li + d * stride];
-    if (a == comp) return (q <= 0 || q >= n) ? (T)0 : A[li + d * stride];
-    if (q < 0 || q >= n) return (comp == 3) ? self : -self;
-    return A[li + d * stride];
-}
-
-template <typename T>
-__device__ __forceinline__ T lap_box(const T *A, int li, const int S[3], const int g[3], int comp, const int n[3],
-                                     const int bc[3], const double ih2[3]) {
-    T self = A[li];
-    T acc = (T)0;
-    int stride = 1;
-    for (int a = 0; a < 3; ++a) {
-        T up = box_nbr<T>(A, li, stride, +1, self, g[a] + 1, n[a], bc[a], a, comp);
-        T um = box_nbr<T>(A, li, stride, -1, self, g[a] - 1, n[a], bc[a], a, comp);
-        acc += (up - (T)2 * self + um) * (T)ih2[a];
-        stride *= S[a];
-    }
+__device__ __forceinline__ T lap_planes(const T (*A)[MGF_PLANE], int cm, int c, int cp, int p, int PX, int kinds,
+                                        const ZPlane &Z, const LevDev &F) {
+    const T self = A[c][p];
+    T acc = lap_acc<T>(pick<T>((kinds >> 2) & 3, A[c][p + 1], self), self, pick<T>(kinds & 3, A[c][p - 1], self),
+                       (T)F.inv_h2[0], (T)0);
+    acc = lap_acc<T>(pick<T>((kinds >> 6) & 3, A[c][p + PX], self), self,
+                     pick<T>((kinds >> 4) & 3, A[c][p - PX], self), (T)F.inv_h2[1], acc);
+    acc = lap_acc<T>(pick<T>(Z.kp, A[cp][p], self), self, pick<T>(Z.km, A[cm][p], self), (T)F.inv_h2[2], acc);
     return acc;
+}
+
+// Tile of the fused kernels: tile index -> owned fine block [lo, hi) per axis.
+__device__ __forceinline__ void mg_tile(long long t, const LevDev &F, int lo[3], int hi[3]) {
+    const int nt0 = (F.n[0] + MGF_OX - 1) / MGF_OX, nt1 = (F.n[1] + MGF_OY - 1) / MGF_OY;
+    const int t0 = (int)(t % nt0);
+    t /= nt0;
+    const int t1 = (int)(t % nt1);
+    const int t2 = (int)(t / nt1);
+    lo[0] = t0 * MGF_OX; lo[1] = t1 * MGF_OY; lo[2] = t2 * MGF_ZC;
+    hi[0] = min(lo[0] + MGF_OX, F.n[0]);
+    hi[1] = min(lo[1] + MGF_OY, F.n[1]);
+    hi[2] = min(lo[2] + MGF_ZC, F.n[2]);
 }
 
 // ------------------------------------------------------------------ down
@@ -87,130 +124,150 @@ template <typename T>
 __global__ __launch_bounds__(256) void k_mg_down(const RepDev *reps, const LevDev *levs, const BlockEnt *tab,
                                                   int lev, int c0, const T *bpool, T *__restrict__ xpool, T *bcpool,
                                                   double omega, const int *__restrict__ mask) {
-    constexpr int CX = TileShape<T>::CX, CY = TileShape<T>::CY, CZ = TileShape<T>::CZ;
-    // box extent: 2 C + 5 along the face-normal axis of the component, 2 C + 4 along the others
-    constexpr int B0 = (2 * CX + 5) * (2 * CY + 4) * (2 * CZ + 4);
-    constexpr int B1 = (2 * CX + 4) * (2 * CY + 5) * (2 * CZ + 4);
-    constexpr int B2 = (2 * CX + 4) * (2 * CY + 4) * (2 * CZ + 5);
-    constexpr int MAXB = B0 > B1 ? (B0 > B2 ? B0 : B2) : (B1 > B2 ? B1 : B2);
-    __shared__ T B[MAXB];
-    __shared__ T X1[MAXB];
-    __shared__ T X2[MAXB];
-    BlockEnt be = tab[blockIdx.x];
+    __shared__ T sB[3][MGF_PLANE];
+    __shared__ T sW[3][MGF_PLANE];
+    __shared__ T sX1[3][MGF_PLANE];
+    __shared__ T sX2[3][MGF_PLANE];
+    __shared__ T sR[3][MGF_PLANE];
+    const BlockEnt be = tab[blockIdx.x];
     if (mask && !mask[be.rep]) return;
     const int comp = c0 + blockIdx.y;
     const RepDev &R = reps[be.rep];
     const LevDev &F = levs[be.rep * RB_MAXLEV + lev];
     const LevDev &C = levs[be.rep * RB_MAXLEV + lev + 1];
     const T s = (comp < 3) ? (T)(-R.eta) : (T)-1;
-    const int TC[3] = {CX, CY, CZ};
-    int ntc[3], tc[3], cl[3], ce[3], rlo[3], rhi[3], blo[3], S[3];
-    for (int a = 0; a < 3; ++a) ntc[a] = (C.n[a] + TC[a] - 1) / TC[a];
-    long long t = be.start;
-    tc[0] = (int)(t % ntc[0]); t /= ntc[0];
-    tc[1] = (int)(t % ntc[1]); tc[2] = (int)(t / ntc[1]);
+    const T om = (T)omega;
+    int lo[3], hi[3], fr[3];
     bool crs[3];
+    mg_tile(be.start, F, lo, hi);
     for (int a = 0; a < 3; ++a) {
         crs[a] = F.n[a] != C.n[a];
-        cl[a] = tc[a] * TC[a];
-        ce[a] = min(TC[a], C.n[a] - cl[a]);
-        if (crs[a]) {
-            rlo[a] = 2 * cl[a] - (a == comp ? 1 : 0);
-            rhi[a] = 2 * (cl[a] + ce[a]) - 1;
-        } else {
-            rlo[a] = cl[a];
-            rhi[a] = cl[a] + ce[a] - 1;
-        }
-        blo[a] = rlo[a] - 2;
-        S[a] = rhi[a] - rlo[a] + 5;
+        fr[a] = (crs[a] && a == comp) ? 1 : 0;   // the residual also covers face 2I-1 of the first coarse face
     }
-    const int nbox = S[0] * S[1] * S[2];
+    const int PX = hi[0] - lo[0] + fr[0] + 4, PY = hi[1] - lo[1] + fr[1] + 4;
+    const int px0 = lo[0] - fr[0] - 2, py0 = lo[1] - fr[1] - 2;
+    const int Z0 = lo[2] - fr[2] - 2;
+    const int NZ = hi[2] - lo[2] + fr[2];        // residual planes
+    PlaneSlots<T> S;
+    make_slots<T>(S, PX, PY, px0, py0, F, R, comp);
     const T *b = bpool + F.off + comp * F.N;
     T *x = xpool + F.off + comp * F.N;
     T *bc = bcpool + C.off + comp * C.N;
-    const long long n01 = (long long)F.n[0] * F.n[1];
-    // phase 1: b on the box, x1 = omega D^-1 b
-    for (int li = threadIdx.x; li < nbox; li += blockDim.x) {
-        int l[3] = {li % S[0], (li / S[0]) % S[1], li / (S[0] * S[1])};
-        int g[3];
-        bool in = true;
-        for (int a = 0; a < 3; ++a) in &= box_coord(blo[a], l[a], F.n[a], R.bc[a], g[a]);
-        T bv = (T)0, x1 = (T)0;
-        if (in && !is_pinned(comp, g, R.bc)) {
-            bv = b[g[0] + (long long)F.n[0] * g[1] + n01 * g[2]];
-            x1 = (T)omega * bv / (s * diag_at<T>(comp, g, F.n, R.bc, F.inv_h2));
-        }
-        B[li] = bv;
-        X1[li] = x1;
+    const int n01 = F.n[0] * F.n[1];
+    // coarse points owned by this block
+    int clo[3], chi[3];
+    for (int a = 0; a < 3; ++a) {
+        clo[a] = crs[a] ? lo[a] / 2 : lo[a];
+        chi[a] = crs[a] ? hi[a] / 2 : hi[a];
     }
-    __syncthreads();
-    // phase 2: second sweep on the region plus one halo point
-    for (int li = threadIdx.x; li < nbox; li += blockDim.x) {
-        int l[3] = {li % S[0], (li / S[0]) % S[1], li / (S[0] * S[1])};
-        if (l[0] < 1 || l[0] > S[0] - 2 || l[1] < 1 || l[1] > S[1] - 2 || l[2] < 1 || l[2] > S[2] - 2) continue;
-        int g[3];
-        bool in = true;
-        for (int a = 0; a < 3; ++a) in &= box_coord(blo[a], l[a], F.n[a], R.bc[a], g[a]);
-        T x2 = (T)0;
-        if (in && !is_pinned(comp, g, R.bc)) {
-            T dg = diag_at<T>(comp, g, F.n, R.bc, F.inv_h2);
-            T lap = lap_box<T>(X1, li, S, g, comp, F.n, R.bc, F.inv_h2);
-            x2 = X1[li] + (T)omega * (B[li] - s * lap) / (s * dg);
-        }
-        X2[li] = x2;
-    }
-    __syncthreads();
-    // phase 3: write the owned fine points; residual on the restriction region
-    for (int li = threadIdx.x; li < nbox; li += blockDim.x) {
-        int l[3] = {li % S[0], (li / S[0]) % S[1], li / (S[0] * S[1])};
-        if (l[0] < 2 || l[0] > S[0] - 3 || l[1] < 2 || l[1] > S[1] - 3 || l[2] < 2 || l[2] > S[2] - 3) continue;
-        int g[3];
-        bool in = true;
-        for (int a = 0; a < 3; ++a) in &= box_coord(blo[a], l[a], F.n[a], R.bc[a], g[a]);
-        T r = (T)0;
-        if (in) {
-            bool own = true;
-            for (int a = 0; a < 3; ++a) {
-                int gl = blo[a] + l[a];          // unwrapped
-                int olo = crs[a] ? 2 * cl[a] : cl[a];
-                int ohi = crs[a] ? 2 * (cl[a] + ce[a]) - 1 : cl[a] + ce[a] - 1;
-                own &= (gl >= olo && gl <= ohi);
+    const int cex = chi[0] - clo[0], cey = chi[1] - clo[1];
+
+    // b of the next plane is loaded one iteration ahead, so that its latency
+    // overlaps the sweeps of the current planes (the barriers wait on LDS only)
+    T nb[MGF_NS];
+    auto fetch = [&](int t) {
+        const ZPlane Z = zplane(Z0 + t, F, R, comp);
+#pragma unroll
+        for (int k = 0; k < MGF_NS; ++k)
+            nb[k] = (S.p[k] >= 0 && S.in[k] && Z.in && !S.pin[k] && !Z.pin) ? b[S.gxy[k] + n01 * Z.gz] : (T)0;
+    };
+    fetch(0);
+    for (int t = 0; t <= NZ + 3; ++t) {
+        // plane t: b, weight and the first sweep from zero
+        {
+            const ZPlane Z = zplane(Z0 + t, F, R, comp);
+            const int c = t % 3;
+            const T dz = (T)F.inv_h2[2];
+            const T daz = diag_axis<T>(comp, 2, Z.gz, F.n[2], R.bc[2]);
+#pragma unroll
+            for (int k = 0; k < MGF_NS; ++k) {
+                if (S.p[k] < 0) continue;
+                T w = (T)0;
+                if (S.in[k] && Z.in && !S.pin[k] && !Z.pin) w = jacobi_w<T>(om, s, fmad(daz, dz, S.dxy[k]));
+                sB[c][S.p[k]] = nb[k];
+                sW[c][S.p[k]] = w;
+                sX1[c][S.p[k]] = nb[k] * w;
             }
-            long long gi = g[0] + (long long)F.n[0] * g[1] + n01 * g[2];
-            if (own) x[gi] = X2[li];
-            if (!is_pinned(comp, g, R.bc)) r = B[li] - s * lap_box<T>(X2, li, S, g, comp, F.n, R.bc, F.inv_h2);
         }
-        X1[li] = r;      // X1 no longer needed: residual on the region
-    }
-    __syncthreads();
-    // phase 4: restriction to the coarse tile
-    const int nct = ce[0] * ce[1] * ce[2];
-    const long long c01 = (long long)C.n[0] * C.n[1];
-    for (int k = threadIdx.x; k < nct; k += blockDim.x) {
-        int ci[3] = {cl[0] + k % ce[0], cl[1] + (k / ce[0]) % ce[1], cl[2] + k / (ce[0] * ce[1])};
-        long long cgi = ci[0] + (long long)C.n[0] * ci[1] + c01 * ci[2];
-        if (is_pinned(comp, ci, R.bc)) { bc[cgi] = (T)0; continue; }
-        // per axis: first box index of the fine points, their count, and whether
-        // the axis is the face-normal one (weights 1/4, 1/2, 1/4) or a cell axis (1/2, 1/2)
-        int fb[3], fc[3];
-        bool face[3];
-        for (int a = 0; a < 3; ++a) {
-            face[a] = crs[a] && a == comp;
-            fc[a] = !crs[a] ? 1 : (face[a] ? 3 : 2);
-            fb[a] = (crs[a] ? 2 * ci[a] - (face[a] ? 1 : 0) : ci[a]) - blo[a];
+        if (t + 1 <= NZ + 3) fetch(t + 1);
+        __syncthreads();
+        // plane t-1: second sweep
+        if (t >= 2) {
+            const int tb = t - 1;
+            const ZPlane Z = zplane(Z0 + tb, F, R, comp);
+            const int c = tb % 3, cm = (tb + 2) % 3, cp = t % 3;
+#pragma unroll
+            for (int k = 0; k < MGF_NS; ++k) {
+                if (S.p[k] < 0 || S.l0[k] < 1 || S.l0[k] > PX - 2 || S.l1[k] < 1 || S.l1[k] > PY - 2) continue;
+                T x2 = (T)0;
+                if (S.in[k] && Z.in && !S.pin[k] && !Z.pin) {
+                    const T lap = lap_planes<T>(sX1, cm, c, cp, S.p[k], PX, S.kinds[k], Z, F);
+                    x2 = jacobi_step<T>(sX1[c][S.p[k]], sB[c][S.p[k]], s, lap, sW[c][S.p[k]]);
+                }
+                sX2[c][S.p[k]] = x2;
+            }
         }
-        T acc = (T)0;
-        for (int kk = 0; kk < fc[2]; ++kk) {
-            const T wz = restrict_weight<T>(crs[2], face[2], kk);
-            for (int jj = 0; jj < fc[1]; ++jj) {
-                const T wy = restrict_weight<T>(crs[1], face[1], jj);
-                for (int ii = 0; ii < fc[0]; ++ii) {
-                    const T wx = restrict_weight<T>(crs[0], face[0], ii);
-                    acc += wx * wy * wz * X1[fb[0] + ii + S[0] * (fb[1] + jj + S[1] * (fb[2] + kk))];
+        __syncthreads();
+        // plane t-2: residual; owned x written
+        const int tc = t - 2;
+        if (t >= 4) {
+            const ZPlane Z = zplane(Z0 + tc, F, R, comp);
+            const int c = tc % 3, cm = (tc + 2) % 3, cp = (tc + 1) % 3;
+            const bool zown = Z.z >= lo[2] && Z.z < hi[2];
+#pragma unroll
+            for (int k = 0; k < MGF_NS; ++k) {
+                if (S.p[k] < 0 || S.l0[k] < 2 || S.l0[k] > PX - 3 || S.l1[k] < 2 || S.l1[k] > PY - 3) continue;
+                T r = (T)0;
+                if (S.in[k] && Z.in) {
+                    const int ux = px0 + S.l0[k], uy = py0 + S.l1[k];
+                    if (zown && ux >= lo[0] && ux < hi[0] && uy >= lo[1] && uy < hi[1])
+                        x[S.gxy[k] + n01 * Z.gz] = sX2[c][S.p[k]];
+                    if (!S.pin[k] && !Z.pin) {
+                        const T lap = lap_planes<T>(sX2, cm, c, cp, S.p[k], PX, S.kinds[k], Z, F);
+                        r = mg_residual<T>(sB[c][S.p[k]], s, lap);
+                    }
+                }
+                sR[c][S.p[k]] = r;
+            }
+        }
+        __syncthreads();
+        // coarse plane K whose fine residual planes are complete
+        if (t >= 4) {
+            const int z = Z0 + tc;              // unwrapped fine z of the newest residual plane
+            int K = -1, nk = 1, zf = tc;        // zf: relative index of the first fine plane
+            if (!crs[2]) {
+                if (z >= lo[2] && z < hi[2]) K = z;
+            } else if ((z & 1) && z - 1 >= lo[2] && z - 1 < hi[2]) {
+                K = (z - 1) >> 1;
+                nk = fr[2] ? 3 : 2;
+                zf = tc - nk + 1;
+            }
+            if (K >= 0) {
+                const int c01 = C.n[0] * C.n[1];
+                for (int q = threadIdx.x; q < cex * cey; q += blockDim.x) {
+                    const int J = clo[1] + q / cex, I = clo[0] + q % cex;
+                    T *out = bc + I + C.n[0] * J + c01 * K;
+                    const int ci[3] = {I, J, K};
+                    if (comp < 3 && R.bc[comp] == RBFIB_WALL && ci[comp] == 0) { *out = (T)0; continue; }
+                    const int fb0 = (crs[0] ? 2 * I - fr[0] : I) - px0;
+                    const int fb1 = (crs[1] ? 2 * J - fr[1] : J) - py0;
+                    const int nx = !crs[0] ? 1 : (fr[0] ? 3 : 2), ny = !crs[1] ? 1 : (fr[1] ? 3 : 2);
+                    T acc = (T)0;
+                    for (int kk = 0; kk < nk; ++kk) {
+                        const int cz = (zf + kk) % 3;
+                        const T wz = restrict_weight<T>(crs[2], fr[2] != 0, kk);
+                        for (int jj = 0; jj < ny; ++jj) {
+                            const T wy = restrict_weight<T>(crs[1], fr[1] != 0, jj);
+                            for (int ii = 0; ii < nx; ++ii) {
+                                const T wx = restrict_weight<T>(crs[0], fr[0] != 0, ii);
+                                acc = fmad(wx * wy * wz, sR[cz][fb0 + ii + PX * (fb1 + jj)], acc);
+                            }
+                        }
+                    }
+                    *out = acc;
                 }
             }
         }
-        bc[cgi] = acc;
     }
 }
 
@@ -220,95 +277,145 @@ __global__ __launch_bounds__(256) void k_mg_up(const RepDev *reps, const LevDev 
                                                 int c0, const T *__restrict__ bpool, const T *__restrict__ xinpool,
                                                 const T *__restrict__ xcpool, T *__restrict__ xoutpool, double omega,
                                                 const int *__restrict__ mask) {
-    constexpr int FX = TileShape<T>::FX, FY = TileShape<T>::FY, FZ = TileShape<T>::FZ;
-    constexpr int MAXB = (FX + 4) * (FY + 4) * (FZ + 4);
-    __shared__ T XP[MAXB];
-    __shared__ T XS[MAXB];
-    BlockEnt be = tab[blockIdx.x];
+    __shared__ T sB[3][MGF_PLANE];
+    __shared__ T sW[3][MGF_PLANE];
+    __shared__ T sXP[3][MGF_PLANE];
+    __shared__ T sXS[3][MGF_PLANE];
+    const BlockEnt be = tab[blockIdx.x];
     if (mask && !mask[be.rep]) return;
     const int comp = c0 + blockIdx.y;
     const RepDev &R = reps[be.rep];
     const LevDev &F = levs[be.rep * RB_MAXLEV + lev];
     const LevDev &C = levs[be.rep * RB_MAXLEV + lev + 1];
     const T s = (comp < 3) ? (T)(-R.eta) : (T)-1;
-    const int TF[3] = {FX, FY, FZ};
-    int ntf[3], tl[3], te[3], blo[3], S[3];
-    for (int a = 0; a < 3; ++a) ntf[a] = (F.n[a] + TF[a] - 1) / TF[a];
-    long long t = be.start;
-    int tcoord[3];
-    tcoord[0] = (int)(t % ntf[0]); t /= ntf[0];
-    tcoord[1] = (int)(t % ntf[1]); tcoord[2] = (int)(t / ntf[1]);
-    for (int a = 0; a < 3; ++a) {
-        tl[a] = tcoord[a] * TF[a];
-        te[a] = min(TF[a], F.n[a] - tl[a]);
-        blo[a] = tl[a] - 2;
-        S[a] = te[a] + 4;
-    }
-    const int nbox = S[0] * S[1] * S[2];
+    const T om = (T)omega;
+    int lo[3], hi[3];
+    mg_tile(be.start, F, lo, hi);
+    const int PX = hi[0] - lo[0] + 4, PY = hi[1] - lo[1] + 4;
+    const int px0 = lo[0] - 2, py0 = lo[1] - 2;
+    const int Z0 = lo[2] - 2;
+    const int NZ = hi[2] - lo[2];
+    PlaneSlots<T> S;
+    make_slots<T>(S, PX, PY, px0, py0, F, R, comp);
     const T *b = bpool + F.off + comp * F.N;
     const T *xin = xinpool + F.off + comp * F.N;
-    T *x = xoutpool + F.off + comp * F.N;
     const T *xc = xcpool + C.off + comp * C.N;
-    const long long n01 = (long long)F.n[0] * F.n[1];
-    // phase 1: x + P x_c on the box (x read from the down pass, never from the output)
-    for (int li = threadIdx.x; li < nbox; li += blockDim.x) {
-        int l[3] = {li % S[0], (li / S[0]) % S[1], li / (S[0] * S[1])};
-        int g[3];
-        bool in = true;
-        for (int a = 0; a < 3; ++a) in &= box_coord(blo[a], l[a], F.n[a], R.bc[a], g[a]);
-        T v = (T)0;
-        if (in && !is_pinned(comp, g, R.bc))
-            v = xin[g[0] + (long long)F.n[0] * g[1] + n01 * g[2]] + prolong_at<T>(R, F, C, comp, g, xc);
-        XP[li] = v;
-    }
-    __syncthreads();
-    // phase 2: first post-smoothing sweep on the tile plus one halo point
-    for (int li = threadIdx.x; li < nbox; li += blockDim.x) {
-        int l[3] = {li % S[0], (li / S[0]) % S[1], li / (S[0] * S[1])};
-        if (l[0] < 1 || l[0] > S[0] - 2 || l[1] < 1 || l[1] > S[1] - 2 || l[2] < 1 || l[2] > S[2] - 2) continue;
-        int g[3];
-        bool in = true;
-        for (int a = 0; a < 3; ++a) in &= box_coord(blo[a], l[a], F.n[a], R.bc[a], g[a]);
-        T v = (T)0;
-        if (in && !is_pinned(comp, g, R.bc)) {
-            T dg = diag_at<T>(comp, g, F.n, R.bc, F.inv_h2);
-            T lap = lap_box<T>(XP, li, S, g, comp, F.n, R.bc, F.inv_h2);
-            T bv = b[g[0] + (long long)F.n[0] * g[1] + n01 * g[2]];
-            v = XP[li] + (T)omega * (bv - s * lap) / (s * dg);
+    T *xo = xoutpool + F.off + comp * F.N;
+    const int n01 = F.n[0] * F.n[1];
+    const long long c01 = (long long)C.n[0] * C.n[1];
+
+    // b, x and the (up to 8) coarse values of the next plane are loaded one
+    // iteration ahead; P x_c is summed in the order of prolong_at
+    T nb[MGF_NS], nx[MGF_NS], ncv[MGF_NS][8];
+    auto fetch = [&](int t) {
+        const ZPlane Z = zplane(Z0 + t, F, R, comp);
+        const ProlongAxis<T> pz = prolong_axis<T>(Z.gz, F.n[2], C.n[2], R.bc[2], comp == 2, comp);
+#pragma unroll
+        for (int k = 0; k < MGF_NS; ++k) {
+            const bool ok = S.p[k] >= 0 && S.in[k] && Z.in && !S.pin[k] && !Z.pin;
+            const int gi = S.gxy[k] + n01 * Z.gz;
+            nb[k] = ok ? b[gi] : (T)0;
+            nx[k] = ok ? xin[gi] : (T)0;
+            const ProlongAxis<T> px = prolong_axis<T>(S.g0[k], F.n[0], C.n[0], R.bc[0], comp == 0, comp);
+            const ProlongAxis<T> py = prolong_axis<T>(S.g1[k], F.n[1], C.n[1], R.bc[1], comp == 1, comp);
+#pragma unroll
+            for (int kk = 0; kk < 2; ++kk)
+#pragma unroll
+                for (int jj = 0; jj < 2; ++jj)
+#pragma unroll
+                    for (int ii = 0; ii < 2; ++ii) {
+                        const bool use = ok && kk < pz.cnt && jj < py.cnt && ii < px.cnt;
+                        const long long ci = (ii ? px.i1 : px.i0) + (long long)C.n[0] * (jj ? py.i1 : py.i0) +
+                                             c01 * (kk ? pz.i1 : pz.i0);
+                        ncv[k][kk * 4 + jj * 2 + ii] = use ? xc[ci] : (T)0;
+                    }
         }
-        XS[li] = v;
-    }
-    __syncthreads();
-    // phase 3: second sweep on the tile, written back
-    for (int li = threadIdx.x; li < nbox; li += blockDim.x) {
-        int l[3] = {li % S[0], (li / S[0]) % S[1], li / (S[0] * S[1])};
-        if (l[0] < 2 || l[0] > S[0] - 3 || l[1] < 2 || l[1] > S[1] - 3 || l[2] < 2 || l[2] > S[2] - 3) continue;
-        int g[3];
-        bool in = true;
-        for (int a = 0; a < 3; ++a) in &= box_coord(blo[a], l[a], F.n[a], R.bc[a], g[a]);
-        if (!in) continue;
-        long long gi = g[0] + (long long)F.n[0] * g[1] + n01 * g[2];
-        if (is_pinned(comp, g, R.bc)) { x[gi] = (T)0; continue; }
-        T dg = diag_at<T>(comp, g, F.n, R.bc, F.inv_h2);
-        T lap = lap_box<T>(XS, li, S, g, comp, F.n, R.bc, F.inv_h2);
-        x[gi] = XS[li] + (T)omega * (b[gi] - s * lap) / (s * dg);
+    };
+    fetch(0);
+    for (int t = 0; t <= NZ + 3; ++t) {
+        // plane t: x + P x_c, b and weight
+        {
+            const ZPlane Z = zplane(Z0 + t, F, R, comp);
+            const int c = t % 3;
+            const T daz = diag_axis<T>(comp, 2, Z.gz, F.n[2], R.bc[2]);
+            const ProlongAxis<T> pz = prolong_axis<T>(Z.gz, F.n[2], C.n[2], R.bc[2], comp == 2, comp);
+#pragma unroll
+            for (int k = 0; k < MGF_NS; ++k) {
+                if (S.p[k] < 0) continue;
+                T w = (T)0, v = (T)0;
+                if (S.in[k] && Z.in && !S.pin[k] && !Z.pin) {
+                    w = jacobi_w<T>(om, s, fmad(daz, (T)F.inv_h2[2], S.dxy[k]));
+                    const ProlongAxis<T> px = prolong_axis<T>(S.g0[k], F.n[0], C.n[0], R.bc[0], comp == 0, comp);
+                    const ProlongAxis<T> py = prolong_axis<T>(S.g1[k], F.n[1], C.n[1], R.bc[1], comp == 1, comp);
+                    T acc = (T)0;
+#pragma unroll
+                    for (int kk = 0; kk < 2; ++kk)
+#pragma unroll
+                        for (int jj = 0; jj < 2; ++jj)
+#pragma unroll
+                            for (int ii = 0; ii < 2; ++ii)
+                                if (kk < pz.cnt && jj < py.cnt && ii < px.cnt)
+                                    acc = fmad((ii ? px.w1 : px.w0) * (jj ? py.w1 : py.w0) * (kk ? pz.w1 : pz.w0),
+                                               ncv[k][kk * 4 + jj * 2 + ii], acc);
+                    v = nx[k] + acc;
+                }
+                sB[c][S.p[k]] = nb[k];
+                sW[c][S.p[k]] = w;
+                sXP[c][S.p[k]] = v;
+            }
+        }
+        if (t + 1 <= NZ + 3) fetch(t + 1);
+        __syncthreads();
+        // plane t-1: first sweep
+        if (t >= 2) {
+            const int tb = t - 1;
+            const ZPlane Z = zplane(Z0 + tb, F, R, comp);
+            const int c = tb % 3, cm = (tb + 2) % 3, cp = t % 3;
+#pragma unroll
+            for (int k = 0; k < MGF_NS; ++k) {
+                if (S.p[k] < 0 || S.l0[k] < 1 || S.l0[k] > PX - 2 || S.l1[k] < 1 || S.l1[k] > PY - 2) continue;
+                T v = (T)0;
+                if (S.in[k] && Z.in && !S.pin[k] && !Z.pin) {
+                    const T lap = lap_planes<T>(sXP, cm, c, cp, S.p[k], PX, S.kinds[k], Z, F);
+                    v = jacobi_step<T>(sXP[c][S.p[k]], sB[c][S.p[k]], s, lap, sW[c][S.p[k]]);
+                }
+                sXS[c][S.p[k]] = v;
+            }
+        }
+        __syncthreads();
+        // plane t-2: second sweep, written
+        if (t >= 4) {
+            const int tc = t - 2;
+            const ZPlane Z = zplane(Z0 + tc, F, R, comp);
+            const int c = tc % 3, cm = (tc + 2) % 3, cp = (tc + 1) % 3;
+#pragma unroll
+            for (int k = 0; k < MGF_NS; ++k) {
+                if (S.p[k] < 0 || S.l0[k] < 2 || S.l0[k] > PX - 3 || S.l1[k] < 2 || S.l1[k] > PY - 3) continue;
+                if (!S.in[k] || !Z.in) continue;
+                const int gi = S.gxy[k] + n01 * Z.gz;
+                if (S.pin[k] || Z.pin) { xo[gi] = (T)0; continue; }
+                const T lap = lap_planes<T>(sXS, cm, c, cp, S.p[k], PX, S.kinds[k], Z, F);
+                xo[gi] = jacobi_step<T>(sXS[c][S.p[k]], sB[c][S.p[k]], s, lap, sW[c][S.p[k]]);
+            }
+        }
+        __syncthreads();
     }
 }
 
 template <typename T>
 void launch_mg_down(Ctx &c, int lev, int c0, int nc, const T *b, T *x) {
-    int n = c.n_tab_down[lev];
+    int n = c.n_tab_mg[lev];
     if (n == 0) return;
-    hipLaunchKernelGGL(k_mg_down<T>, dim3(n, nc), dim3(256), 0, c.stream, c.d_reps, c.d_levs, c.d_tab_down[lev], lev,
+    hipLaunchKernelGGL(k_mg_down<T>, dim3(n, nc), dim3(256), 0, c.stream, c.d_reps, c.d_levs, c.d_tab_mg[lev], lev,
                        c0, b, x, (T *)b, c.opts.mg_omega, c.mask);
     HIP_OK(hipGetLastError());
 }
 
 template <typename T>
 void launch_mg_up(Ctx &c, int lev, int c0, int nc, const T *b, const T *xin, const T *xc, T *xout) {
-    int n = c.n_tab_up[lev];
+    int n = c.n_tab_mg[lev];
     if (n == 0) return;
-    hipLaunchKernelGGL(k_mg_up<T>, dim3(n, nc), dim3(256), 0, c.stream, c.d_reps, c.d_levs, c.d_tab_up[lev], lev, c0,
+    hipLaunchKernelGGL(k_mg_up<T>, dim3(n, nc), dim3(256), 0, c.stream, c.d_reps, c.d_levs, c.d_tab_mg[lev], lev, c0,
                        b, xin, xc, xout, c.opts.mg_omega, c.mask);
     HIP_OK(hipGetLastError());
 }

@@ -209,31 +209,34 @@ static void apply_op(Ctx &c, MarkerSet &ms, const double *x, double *y, bool flu
 }
 
 // One V-cycle on components c0 .. c0+nc-1 of the multigrid pools; returns the
-// pool that holds the level-0 result (X for the unfused path, T for the fused one).
+// pool that holds the level-0 result.  Each level runs either the fused down/up
+// kernels (two sweeps only, and enough workgroups to fill the device) or the
+// separate smoother / restriction / prolongation kernels; both give the same
+// values.  After the down pass X holds each level's smoothed iterate and B its
+// right-hand side; the corrected result of level l ends in res[l] (T after a
+// fused up pass, X after a separate one), where the coarse solve of the
+// replicas whose coarsest level is l also writes.
 template <typename T>
 static T *vcycle(Ctx &c, int c0, int nc) {
     T *X = (T *)c.mg_x, *B = (T *)c.mg_b, *Tt = (T *)c.mg_t;
     const double sz = (double)sizeof(T) * nc;
-    int nu = std::max(1, c.opts.mg_sweeps);
-    if (c.opts.mg_fused && nu == 2) {
-        // down: X(l) = two sweeps from zero, B(l+1) = R (B(l) - A X(l)); coarsest: T = A^-1 B
-        for (int l = 0; l < c.maxlev; ++l) {
-            launch_coarse<T>(c, l, c0, nc, B, Tt);
+    const int nu = std::max(1, c.opts.mg_sweeps);
+    bool fz[RB_MAXLEV];
+    T *res[RB_MAXLEV];
+    for (int l = 0; l < c.maxlev; ++l) {
+        fz[l] = nu == 2 && l + 1 < c.maxlev &&
+                (c.opts.mg_fused == 2 || (c.opts.mg_fused == 1 && (long long)c.n_tab_mg[l] * nc >= MGF_MIN_BLOCKS));
+        res[l] = fz[l] ? Tt : X;
+    }
+    for (int l = 0; l < c.maxlev; ++l) {
+        launch_coarse<T>(c, l, c0, nc, B, res[l]);
+        if (c.n_tab_lev[l] == 0) continue;
+        if (fz[l]) {
             if (l == 0) record(c, 2, true);
             launch_mg_down<T>(c, l, c0, nc, B, X);
             if (l == 0) record(c, 2, false, sz * (2.0 * c.lev_cells[0] + c.lev_cells_c[0]));
+            continue;
         }
-        // up: T(l) = two sweeps from X(l) + P T(l+1)
-        for (int l = c.maxlev - 2; l >= 0; --l) {
-            if (l == 0) record(c, 3, true);
-            launch_mg_up<T>(c, l, c0, nc, B, X, Tt, Tt);
-            if (l == 0) record(c, 3, false, sz * (3.0 * c.lev_cells[0] + c.lev_cells_c[0]));
-        }
-        return Tt;
-    }
-    for (int l = 0; l < c.maxlev; ++l) {
-        launch_coarse<T>(c, l, c0, nc, B, X);
-        if (c.n_tab_lev[l] == 0) continue;
         for (int k = 1; k <= nu; ++k) {
             T *out = ((nu - k) % 2 == 0) ? X : Tt;
             T *in = (out == X) ? Tt : X;
@@ -245,7 +248,13 @@ static T *vcycle(Ctx &c, int c0, int nc) {
     }
     for (int l = c.maxlev - 2; l >= 0; --l) {
         if (c.n_tab_lev[l] == 0) continue;
-        launch_prolong<T>(c, l, c0, nc, X, X);
+        if (fz[l]) {
+            if (l == 0) record(c, 3, true);
+            launch_mg_up<T>(c, l, c0, nc, B, X, res[l + 1], Tt);
+            if (l == 0) record(c, 3, false, sz * (3.0 * c.lev_cells[0] + c.lev_cells_c[0]));
+            continue;
+        }
+        launch_prolong<T>(c, l, c0, nc, res[l + 1], X);
         T *in = X, *out = Tt;
         for (int k = 1; k <= nu; ++k) {
             if (l == 0) record(c, 1, true);
@@ -255,7 +264,7 @@ static T *vcycle(Ctx &c, int c0, int nc) {
         }
         if (in != X) launch_smooth<T>(c, l, c0, nc, in, X, B, false);   // odd count: one more sweep lands in X
     }
-    return X;
+    return res[0];
 }
 
 template <typename T>
@@ -679,6 +688,7 @@ static void build(Ctx &c, int nrep, const rbfib_grid *grids, const rbfib_bodies 
     long long total_cells = 0;
     for (int r = 0; r < nrep; ++r) total_cells += c.reps[r].N;
     const int mg_npt = total_cells >= (1LL << 22) ? 4 : 1;
+    c.mg_npt = mg_npt;
     auto chunks = [](std::vector<BlockEnt> &tab, int rep, long long n, long long step) {
         for (long long s = 0; s < n; s += step) tab.push_back(BlockEnt{rep, 1, s});
     };
@@ -714,28 +724,20 @@ static void build(Ctx &c, int nrep, const rbfib_grid *grids, const rbfib_bodies 
         c.n_tab_crs[l] = (int)tc.size(); c.d_tab_crs[l] = upload(c, tc);
         c.n_tab_all[l] = (int)ta.size(); c.d_tab_all[l] = upload(c, ta);
     }
-    // fused level kernels: one block per coarse tile (down) / fine tile (up)
-    const bool t32 = c.opts.precond_fp32 != 0;
-    const int dt[3] = {t32 ? MGD32_X : MGD64_X, t32 ? MGD32_Y : MGD64_Y, t32 ? MGD32_Z : MGD64_Z};
-    const int ut[3] = {t32 ? MGU32_X : MGU64_X, t32 ? MGU32_Y : MGU64_Y, t32 ? MGU32_Z : MGU64_Z};
+    // fused level kernels: one block per MGF_OX x MGF_OY x MGF_ZC block of level l
     for (int l = 0; l + 1 < c.maxlev; ++l) {
-        std::vector<BlockEnt> td, tu;
+        std::vector<BlockEnt> tm;
         for (int r = 0; r < nrep; ++r) {
             if (l + 1 >= c.reps[r].nlev) continue;
             const LevDev &F = c.levs[(size_t)r * RB_MAXLEV + l];
             const LevDev &C = c.levs[(size_t)r * RB_MAXLEV + l + 1];
-            long long nd = 1, nu_ = 1;
-            for (int a = 0; a < 3; ++a) {
-                nd *= (C.n[a] + dt[a] - 1) / dt[a];
-                nu_ *= (F.n[a] + ut[a] - 1) / ut[a];
-            }
-            for (long long t = 0; t < nd; ++t) td.push_back(BlockEnt{r, 1, t});
-            for (long long t = 0; t < nu_; ++t) tu.push_back(BlockEnt{r, 1, t});
+            const long long nt = (long long)((F.n[0] + MGF_OX - 1) / MGF_OX) * ((F.n[1] + MGF_OY - 1) / MGF_OY) *
+                                 ((F.n[2] + MGF_ZC - 1) / MGF_ZC);
+            for (long long t = 0; t < nt; ++t) tm.push_back(BlockEnt{r, 1, t});
             c.lev_cells[l] += (double)F.N;
             c.lev_cells_c[l] += (double)C.N;
         }
-        c.n_tab_down[l] = (int)td.size(); c.d_tab_down[l] = upload(c, td);
-        c.n_tab_up[l] = (int)tu.size(); c.d_tab_up[l] = upload(c, tu);
+        c.n_tab_mg[l] = (int)tm.size(); c.d_tab_mg[l] = upload(c, tm);
     }
     c.cells_all = (double)total_cells;
 
@@ -931,7 +933,7 @@ static void free_all(Ctx &c) {
     F(c.d_body_shape); F(c.d_shapes); F(c.d_shape_data); F(c.d_body_len);
     F(c.d_tab_cells); F(c.d_tab_vec); F(c.d_vec_first); F(c.d_vec_nblk);
     for (int l = 0; l < RB_MAXLEV; ++l) {
-        F(c.d_tab_lev[l]); F(c.d_tab_crs[l]); F(c.d_tab_all[l]); F(c.d_tab_down[l]); F(c.d_tab_up[l]);
+        F(c.d_tab_lev[l]); F(c.d_tab_crs[l]); F(c.d_tab_all[l]); F(c.d_tab_mg[l]);
     }
     F(c.d_coarse_off); F(c.d_coarse64); F(c.d_coarse32);
     F(c.mg_x); F(c.mg_b); F(c.mg_t);
@@ -983,7 +985,7 @@ void rbfib_default_opts(rbfib_opts *o) {
     o->min_body_dist = 0.0;
     o->check_every = 5;
     o->use_graphs = 1;
-    o->mg_fused = 1;
+    o->mg_fused = 0;
 }
 
 const char *rbfib_strerror(int code) {

@@ -62,7 +62,7 @@ def test_fused_vcycle_matches_separate_kernels(rb, name, fp32):
     q, th, r = _state(ws, ctx, 11)
     z0 = torch.full((ctx.L,), float("nan"), dtype=torch.float64, device="cuda")
     rb.rbfib_precondition(ctx, q, th, r, z0)
-    rb.rbfib_set_opts(ctx, rb.rbfib_default_opts(precond_fp32=fp32, mg_fused=1))
+    rb.rbfib_set_opts(ctx, rb.rbfib_default_opts(precond_fp32=fp32, mg_fused=2))
     z1 = torch.full_like(z0, float("nan"))
     rb.rbfib_precondition(ctx, q, th, r, z1)
     torch.cuda.synchronize()
@@ -79,7 +79,7 @@ def test_fused_solve_matches_separate_kernels(rb, fp32):
     import torch
     w = W.two_spheres()
     out = []
-    for fused in (0, 1):
+    for fused in (0, 2):
         ctx = lib_context(rb, w, tol=1e-8, precond_fp32=fp32, mg_fused=fused)
         U = torch.empty((w.nb, 6), dtype=torch.float64, device="cuda")
         info = rb.rbfib_solve_mobility(ctx, dev(w.q), dev(w.theta), dev(w.FT), U, include_bc=False)
@@ -91,7 +91,7 @@ def test_fused_solve_matches_separate_kernels(rb, fp32):
     assert np.abs(out[0][1] - out[1][1]).max() <= 1e-6 * np.abs(out[0][1]).max()
 
 
-@pytest.mark.parametrize("fused", [1, 0])
+@pytest.mark.parametrize("fused", [2, 0])
 @pytest.mark.parametrize("name", ["ragged_10x12x14", "periodic_x_16x12x12", "uneven_16x12x20",
                                   "monolayer_64x32x16", "batch_mixed_depths"])
 def test_fp64_cycle_matches_fp32_cycle(rb, name, fused):
@@ -117,3 +117,23 @@ def test_fp64_cycle_matches_fp32_cycle(rb, name, fused):
                 worst = max(worst, float(np.abs(z[1][a:b] - ref).max() / np.abs(ref).max()))
     print(name, "fused", fused, "fp32 vs fp64 worst field rel diff", worst, flush=True)
     assert worst < 2e-5
+
+
+@pytest.mark.parametrize("fp32", [1, 0])
+def test_mixed_levels_match_separate_kernels(rb, fp32):
+    """mg_fused = 1 picks fused or separate kernels per level by workgroup count
+    (the 128^3 grid: fused on the fine levels, separate on the coarse ones)."""
+    import torch
+    ws = CASES["many_spheres_128"]
+    ctx = lib_context(rb, ws, precond_fp32=fp32, mg_fused=0)
+    q, th, r = _state(ws, ctx, 13)
+    z = []
+    for mode in (0, 1):
+        rb.rbfib_set_opts(ctx, rb.rbfib_default_opts(precond_fp32=fp32, mg_fused=mode))
+        out = torch.full((ctx.L,), float("nan"), dtype=torch.float64, device="cuda")
+        rb.rbfib_precondition(ctx, q, th, r, out)
+        torch.cuda.synchronize()
+        z.append(out.cpu().numpy())
+    assert np.all(np.isfinite(z[1]))
+    assert np.array_equal(z[0], z[1])
+    ctx.close()
