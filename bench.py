@@ -201,12 +201,41 @@ def run_cpu_baseline(ws, budget_s=20.0, seed=2024):
     return {"steps": n_steps, "seconds": t1 - t0}
 
 
-def roofline_of(stats):
+COUNTERS = os.path.join(ROOT, "profiles", "ensemble_256_sem_hbm_counters.md")
+KERNEL_SOURCES = ("paper_1901_06427_amd/csrc/grid.hip", "paper_1901_06427_amd/csrc/common.h")
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of a kernel class from the committed counter summary
+    (FETCH_SIZE and WRITE_SIZE, each scaled by the counts of a calibration
+    kernel of known size); None when the kernel sources changed since."""
+    try:
+        with open(COUNTERS) as fh:
+            for line in fh:
+                f = line.split()
+                if len(f) == 6 and f[0] == "traffic:" and f[1] == kernel and f[4] == "sources":
+                    return float(f[2]) if f[5] == kernel_source_hash() else None
+    except OSError:
+        return None
+    return None
+
+
+def roofline_of(stats, ensemble_default=True):
     best = max(stats.items(), key=lambda kv: kv[1][0] * kv[1][2])
     name, (avg_ms, nbytes, launches) = best
     achieved = nbytes / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else 0.0
+    traffic = measured_traffic(name) if ensemble_default else None
     roof = {"bound": "hbm", "kernel": name, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "avg_us": round(avg_ms * 1e3, 2),
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "avg_us": round(avg_ms * 1e3, 2),
             "bytes_per_launch": nbytes, "launches": launches}
     others = {k: {"avg_us": round(v[0] * 1e3, 2), "launches": v[2],
                   "GB/s": round(v[1] / (v[0] * 1e-3) / 1e9, 1) if v[0] > 0 else 0.0} for k, v in stats.items()}
@@ -254,8 +283,9 @@ def main():
     log("ensemble: %d replicas, %d bodies, %d markers" % (len(ens), sum(w.nb for w in ens), sum(w.nm for w in ens)))
     if args.timing_only:
         timing = run_gpu(ens, 1, 0, fp32=1, timing=True)
-        roofline, kernels = roofline_of(timing["stats"])
-        print(json.dumps({"timing_only": True, "roofline": roofline, "kernels": kernels}), flush=True)
+        roofline, kernels = roofline_of(timing["stats"], args.replicas == 256 and MG_FUSED == 0)
+        print(json.dumps({"timing_only": True, "roofline": roofline, "kernels": kernels,
+                          "kernel_sources": kernel_source_hash()}), flush=True)
         return
 
     batched = run_gpu(ens, args.steps, args.warmup, fp32=1)
@@ -268,7 +298,7 @@ def main():
     log("plain fp64-pc, one replica at a time: %.1f solves/s" % plain_value)
 
     timing = run_gpu(ens, 1, 0, fp32=1, timing=True)
-    roofline, kernels = roofline_of(timing["stats"])
+    roofline, kernels = roofline_of(timing["stats"], args.replicas == 256 and MG_FUSED == 0)
 
     w2 = W.two_spheres()
     two = run_gpu([w2], args.two_spheres_steps, 2, fp32=1)

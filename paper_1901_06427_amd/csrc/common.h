@@ -70,6 +70,18 @@ __device__ __forceinline__ void split_index(long long lin, int n0, int n01, doub
     idx[2] = k;
 }
 
+// ---------------------------------------------------------------- XCD-aware block order
+// Workgroups are dispatched to the eight XCDs (each with its own L2) round-robin by
+// blockIdx.x.  Stencil kernels read the neighbouring rows and planes of their
+// chunk, so each XCD is given one contiguous range of table entries: table entry
+// of workgroup b = (b mod 8) * (n / 8) + min(b mod 8, n mod 8) + b / 8, a
+// permutation of [0, n).
+#define RB_NXCD 8
+__device__ __forceinline__ int xcd_block(int b, int n) {
+    const int x = b % RB_NXCD, i = b / RB_NXCD, per = n / RB_NXCD, rem = n % RB_NXCD;
+    return x * per + min(x, rem) + i;
+}
+
 // ---------------------------------------------------------------- smoother arithmetic
 // Every multigrid kernel evaluates the Laplacian, the Jacobi update, the residual
 // and the transfer sums through these helpers, with explicit fused multiply-adds,
@@ -183,19 +195,18 @@ __device__ __forceinline__ T prolong_at(const RepDev &R, const LevDev &F, const 
     const ProlongAxis<T> pz = prolong_axis<T>(fi[2], F.n[2], C.n[2], R.bc[2], comp == 2, comp);
     T acc = (T)0;
     const long long c01 = (long long)C.n[0] * C.n[1];
-    for (int kk = 0; kk < pz.cnt; ++kk) {
-        const int k = kk ? pz.i1 : pz.i0;
-        const T wz = kk ? pz.w1 : pz.w0;
-        for (int jj = 0; jj < py.cnt; ++jj) {
-            const int j = jj ? py.i1 : py.i0;
-            const T wy = jj ? py.w1 : py.w0;
-            for (int ii = 0; ii < px.cnt; ++ii) {
-                const int i = ii ? px.i1 : px.i0;
-                const T wx = ii ? px.w1 : px.w0;
-                acc = fmad(wx * wy * wz, xc[i + (long long)C.n[0] * j + c01 * k], acc);
-            }
-        }
-    }
+    // fixed trip counts with predicates: all loads of the point issue together
+#pragma unroll
+    for (int kk = 0; kk < 2; ++kk)
+#pragma unroll
+        for (int jj = 0; jj < 2; ++jj)
+#pragma unroll
+            for (int ii = 0; ii < 2; ++ii)
+                if (kk < pz.cnt && jj < py.cnt && ii < px.cnt)
+                    acc = fmad((ii ? px.w1 : px.w0) * (jj ? py.w1 : py.w0) * (kk ? pz.w1 : pz.w0),
+                               xc[(ii ? px.i1 : px.i0) + (long long)C.n[0] * (jj ? py.i1 : py.i0) +
+                                  c01 * (kk ? pz.i1 : pz.i0)],
+                               acc);
     return acc;
 }
 

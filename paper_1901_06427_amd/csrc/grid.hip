@@ -66,7 +66,7 @@ __device__ __forceinline__ void unlin(long long lin, const LevDev &L, int idx[3]
 // y_c = -eta Lm_c v + (G pi)_c for c = x, y, z;  y_pi = -(D v).  Pinned slots -> 0.
 __global__ void k_apply_fluid(const RepDev *reps, const BlockEnt *tab, const double *__restrict__ x,
                               double *__restrict__ y, const int *__restrict__ mask) {
-    BlockEnt be = tab[blockIdx.x];
+    BlockEnt be = tab[xcd_block(blockIdx.x, gridDim.x)];
     if (mask && !mask[be.rep]) return;
     const RepDev &R = reps[be.rep];
     for (int t_ = 0; t_ < be.npt; ++t_) {
@@ -120,7 +120,7 @@ void launch_apply_fluid(Ctx &c, const double *x, double *y) {
 template <typename T>
 __global__ void k_to_level0(const RepDev *reps, const LevDev *levs, const BlockEnt *tab, const double *src,
                             T *b, int c0, const int *__restrict__ mask) {
-    BlockEnt be = tab[blockIdx.x];
+    BlockEnt be = tab[xcd_block(blockIdx.x, gridDim.x)];
     if (mask && !mask[be.rep]) return;
     int comp = c0 + blockIdx.y;
     const RepDev &R = reps[be.rep];
@@ -148,7 +148,7 @@ __global__ __launch_bounds__(RB_BLOCK) void k_smooth(const RepDev *reps, const L
                                                      int lev, int c0, const T *__restrict__ xin, T *__restrict__ xout,
                                                      const T *__restrict__ b, double omega,
                                                      const int *__restrict__ mask) {
-    const BlockEnt be = tab[blockIdx.x];
+    const BlockEnt be = tab[xcd_block(blockIdx.x, gridDim.x)];
     if (mask && !mask[be.rep]) return;
     const int comp = c0 + blockIdx.y;
     const RepDev &R = reps[be.rep];
@@ -232,60 +232,86 @@ void launch_smooth(Ctx &c, int lev, int c0, int nc, const T *xin, T *xout, const
 // Residual of level lev restricted to level lev+1: face-normal axis full weighting
 // (1/4, 1/2, 1/4 on faces 2I-1, 2I, 2I+1), cell-centred axes averaging of the two
 // children; an axis that is not coarsened keeps its index.
+// Residual b - A x at fine point (i, j, k), 0 at pinned points; the boundary rules
+// are applied with selects so that its eight loads issue together.
 template <typename T>
-__device__ T residual_at(const RepDev &R, const LevDev &Lv, int comp, int i, int j, int k, const T *x, const T *b) {
-    int idx[3] = {i, j, k};
-    if (pinned(comp, idx, R.bc)) return (T)0;
-    long long lin = (long long)i + (long long)Lv.n[0] * ((long long)j + (long long)Lv.n[1] * k);
-    T dg;
-    T lap = lap_point<T>(x, comp, idx, Lv.n, R.bc, Lv.inv_h2, lin, dg);
-    T s = (comp < 3) ? (T)(-R.eta) : (T)-1;
-    return mg_residual<T>(b[lin], s, lap);
+__device__ __forceinline__ T residual_at(const RepDev &R, const LevDev &Lv, int comp, int i, int j, int k,
+                                         const T *x, const T *b) {
+    const int idx[3] = {i, j, k};
+    const int st[3] = {1, Lv.n[0], Lv.n[0] * Lv.n[1]};
+    const int lin = i + st[1] * j + st[2] * k;
+    int kind[6], off[6];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        kind[2 * a] = nbr_kind(idx[a], -1, Lv.n[a], R.bc[a], a, comp);
+        kind[2 * a + 1] = nbr_kind(idx[a], +1, Lv.n[a], R.bc[a], a, comp);
+        off[2 * a] = kind[2 * a] ? 0 : (idx[a] == 0 ? (Lv.n[a] - 1) * st[a] : -st[a]);
+        off[2 * a + 1] = kind[2 * a + 1] ? 0 : (idx[a] == Lv.n[a] - 1 ? -(Lv.n[a] - 1) * st[a] : st[a]);
+    }
+    const T self = x[lin], bv = b[lin];
+    T nb[6];
+#pragma unroll
+    for (int q = 0; q < 6; ++q) nb[q] = x[lin + off[q]];
+    T acc = (T)0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+        acc = lap_acc<T>(pick<T>(kind[2 * a + 1], nb[2 * a + 1], self), self, pick<T>(kind[2 * a], nb[2 * a], self),
+                         (T)Lv.inv_h2[a], acc);
+    const T s = (comp < 3) ? (T)(-R.eta) : (T)-1;
+    return pinned(comp, idx, R.bc) ? (T)0 : mg_residual<T>(bv, s, acc);
 }
 
-template <typename T>
-__global__ void k_restrict(const RepDev *reps, const LevDev *levs, const BlockEnt *tab, int lev, int c0,
-                           const T *__restrict__ x, const T *__restrict__ b, T *__restrict__ bc, const int *__restrict__ mask) {
-    BlockEnt be = tab[blockIdx.x];
+// Residual of level lev restricted to level lev+1: face-normal axis full weighting
+// (1/4, 1/2, 1/4 on faces 2I-1, 2I, 2I+1), cell-centred axes averaging of the two
+// children; an axis that is not coarsened keeps its index.
+template <typename T, int NPT>
+__global__ __launch_bounds__(RB_BLOCK) void k_restrict(const RepDev *reps, const LevDev *levs, const BlockEnt *tab,
+                                                       int lev, int c0, const T *__restrict__ x,
+                                                       const T *__restrict__ b, T *__restrict__ bc,
+                                                       const int *__restrict__ mask) {
+    BlockEnt be = tab[xcd_block(blockIdx.x, gridDim.x)];
     if (mask && !mask[be.rep]) return;
     int comp = c0 + blockIdx.y;
     const RepDev &R = reps[be.rep];
     const LevDev &F = levs[be.rep * RB_MAXLEV + lev];
     const LevDev &C = levs[be.rep * RB_MAXLEV + lev + 1];
-    for (int t_ = 0; t_ < be.npt; ++t_) {
-    long long lin = be.start + threadIdx.x + (long long)t_ * RB_BLOCK;
-    if (lin >= C.N) continue;
-    int ci[3];
-    unlin(lin, C, ci);
-    long long cbase = C.off + comp * C.N;
-    if (pinned(comp, ci, R.bc)) { bc[cbase + lin] = (T)0; continue; }
     const T *xf = x + F.off + comp * F.N;
     const T *bf = b + F.off + comp * F.N;
-    int fb[3], fc[3];
     bool crs[3], face[3];
+    int fc[3];
+#pragma unroll
     for (int a = 0; a < 3; ++a) {
         crs[a] = F.n[a] != C.n[a];
         face[a] = crs[a] && a == comp;
         fc[a] = !crs[a] ? 1 : (face[a] ? 3 : 2);
-        fb[a] = crs[a] ? 2 * ci[a] - (face[a] ? 1 : 0) : ci[a];
     }
-    // periodic wrap of the face-normal neighbours (wall: ci = 0 is pinned, excluded above)
+    // periodic wrap of the face-normal neighbours (wall: ci = 0 is pinned, excluded below)
     auto wrap = [](int f, int n) { return f < 0 ? f + n : (f >= n ? f - n : f); };
-    T acc = (T)0;
-    for (int kk = 0; kk < fc[2]; ++kk) {
-        const int k = wrap(fb[2] + kk, F.n[2]);
-        const T wz = restrict_weight<T>(crs[2], face[2], kk);
-        for (int jj = 0; jj < fc[1]; ++jj) {
-            const int j = wrap(fb[1] + jj, F.n[1]);
-            const T wy = restrict_weight<T>(crs[1], face[1], jj);
-            for (int ii = 0; ii < fc[0]; ++ii) {
-                const int i = wrap(fb[0] + ii, F.n[0]);
-                const T wx = restrict_weight<T>(crs[0], face[0], ii);
-                acc = fmad(wx * wy * wz, residual_at<T>(R, F, comp, i, j, k, xf, bf), acc);
-            }
-        }
-    }
-    bc[cbase + lin] = acc;
+#pragma unroll
+    for (int t_ = 0; t_ < NPT; ++t_) {
+        long long lin = be.start + threadIdx.x + (long long)t_ * RB_BLOCK;
+        if (lin >= C.N) continue;
+        int ci[3];
+        unlin(lin, C, ci);
+        long long cbase = C.off + comp * C.N;
+        if (pinned(comp, ci, R.bc)) { bc[cbase + lin] = (T)0; continue; }
+        int fb[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) fb[a] = crs[a] ? 2 * ci[a] - (face[a] ? 1 : 0) : ci[a];
+        T acc = (T)0;
+#pragma unroll
+        for (int kk = 0; kk < 3; ++kk)
+#pragma unroll
+            for (int jj = 0; jj < 3; ++jj)
+#pragma unroll
+                for (int ii = 0; ii < 3; ++ii)
+                    if (kk < fc[2] && jj < fc[1] && ii < fc[0])
+                        acc = fmad(restrict_weight<T>(crs[0], face[0], ii) * restrict_weight<T>(crs[1], face[1], jj) *
+                                       restrict_weight<T>(crs[2], face[2], kk),
+                                   residual_at<T>(R, F, comp, wrap(fb[0] + ii, F.n[0]), wrap(fb[1] + jj, F.n[1]),
+                                                  wrap(fb[2] + kk, F.n[2]), xf, bf),
+                                   acc);
+        bc[cbase + lin] = acc;
     }
 }
 
@@ -293,8 +319,12 @@ template <typename T>
 void launch_restrict(Ctx &c, int lev, int c0, int nc, const T *x, const T *b, T *bcoarse) {
     if (c.n_tab_lev[lev] == 0) return;
     // one thread per coarse point: use the table of level lev+1 restricted to replicas descending from lev
-    hipLaunchKernelGGL(k_restrict<T>, dim3(c.n_tab_all[lev + 1], nc), dim3(RB_BLOCK), 0, c.stream, c.d_reps,
-                       c.d_levs, c.d_tab_all[lev + 1], lev, c0, x, b, bcoarse, c.mask);
+    if (c.mg_npt == 4)
+        hipLaunchKernelGGL((k_restrict<T, 4>), dim3(c.n_tab_all[lev + 1], nc), dim3(RB_BLOCK), 0, c.stream,
+                           c.d_reps, c.d_levs, c.d_tab_all[lev + 1], lev, c0, x, b, bcoarse, c.mask);
+    else
+        hipLaunchKernelGGL((k_restrict<T, 1>), dim3(c.n_tab_all[lev + 1], nc), dim3(RB_BLOCK), 0, c.stream,
+                           c.d_reps, c.d_levs, c.d_tab_all[lev + 1], lev, c0, x, b, bcoarse, c.mask);
 }
 
 // x_f += P x_c: face-normal axis linear (even faces copy, odd faces average),
@@ -303,7 +333,7 @@ void launch_restrict(Ctx &c, int lev, int c0, int nc, const T *x, const T *b, T 
 template <typename T>
 __global__ void k_prolong(const RepDev *reps, const LevDev *levs, const BlockEnt *tab, int lev, int c0,
                           const T *__restrict__ xc, T *__restrict__ xf, const int *__restrict__ mask) {
-    BlockEnt be = tab[blockIdx.x];
+    BlockEnt be = tab[xcd_block(blockIdx.x, gridDim.x)];
     if (mask && !mask[be.rep]) return;
     int comp = c0 + blockIdx.y;
     const RepDev &R = reps[be.rep];
@@ -369,7 +399,7 @@ void launch_coarse(Ctx &c, int lev, int c0, int nc, const T *b, T *x) {
 template <typename T>
 __global__ void k_proj_div(const RepDev *reps, const LevDev *levs, const BlockEnt *tab, const T *__restrict__ xv,
                            const double *__restrict__ r, T *__restrict__ bp, double *__restrict__ z, const int *__restrict__ mask) {
-    BlockEnt be = tab[blockIdx.x];
+    BlockEnt be = tab[xcd_block(blockIdx.x, gridDim.x)];
     if (mask && !mask[be.rep]) return;
     const RepDev &R = reps[be.rep];
     const LevDev &Lv = levs[be.rep * RB_MAXLEV];
@@ -406,7 +436,7 @@ void launch_proj_div(Ctx &c, const T *xv, const double *r, T *bp, double *z) {
 template <typename T>
 __global__ void k_proj_correct(const RepDev *reps, const LevDev *levs, const BlockEnt *tab, const T *__restrict__ xv,
                                const T *__restrict__ phi, double *__restrict__ z, const int *__restrict__ mask) {
-    BlockEnt be = tab[blockIdx.x];
+    BlockEnt be = tab[xcd_block(blockIdx.x, gridDim.x)];
     if (mask && !mask[be.rep]) return;
     const RepDev &R = reps[be.rep];
     const LevDev &Lv = levs[be.rep * RB_MAXLEV];
