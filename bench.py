@@ -182,23 +182,65 @@ def run_plain(ws, warmup=1, seed=2024):
 
 
 # ----------------------------------------------------------------- CPU oracle baseline
-def run_cpu_baseline(ws, budget_s=20.0, seed=2024):
-    """The oracle's SEM step as it stands (FP64, solves to 1e-12), single thread,
-    one step per replica in ensemble order until the time budget is used."""
+_CPU_ENS = None
+
+
+def _cpu_init():
     from threadpoolctl import threadpool_limits
+    threadpool_limits(limits=1)
+
+
+def _cpu_step(k, seed=2024):
+    """One oracle SEM step on replica k of the default ensemble (worker process)."""
+    global _CPU_ENS
+    import workloads as W
     from oracle import mac, sem
-    n_steps = 0
-    with threadpool_limits(limits=1):
+    if _CPU_ENS is None:
+        _CPU_ENS = W.ensemble()
+    w = _CPU_ENS[k]
+    g = mac.Grid(w.n, w.bc, w.h, w.eta, w.wall_vel)
+    F = soft_forces_np(w.q, float(w.radius[0]), w.n, w.h, w.kT)
+    sem.sem_step(g, w.r_ref, w.offsets, w.q, w.theta, F, w.kT, w.dt, seed, 0)
+    return k
+
+
+def run_cpu_baseline(n_replicas, budget_s=20.0):
+    """The oracle's SEM step as it stands (FP64, solves to 1e-12), one single-threaded
+    process per host core (at most 16), replicas taken in ensemble order until the
+    time budget is used.  Runs before anything touches the GPU."""
+    import multiprocessing as mp
+    cores = max(1, min(16, os.cpu_count() or 1))
+    ctx = mp.get_context("spawn")
+    with ctx.Pool(cores, initializer=_cpu_init) as pool:
+        pool.map(_cpu_step, [0] * cores, chunksize=1)       # import and build once per worker, untimed
+        done = 0
         t0 = time.perf_counter()
-        for w in ws:
-            g = mac.Grid(w.n, w.bc, w.h, w.eta, w.wall_vel)
-            F = soft_forces_np(w.q, float(w.radius[0]), w.n, w.h, w.kT)
-            sem.sem_step(g, w.r_ref, w.offsets, w.q, w.theta, F, w.kT, w.dt, seed, 0)
-            n_steps += 1
+        for _ in pool.imap_unordered(_cpu_step, range(n_replicas), chunksize=1):
+            done += 1
             if time.perf_counter() - t0 > budget_s:
                 break
         t1 = time.perf_counter()
-    return {"steps": n_steps, "seconds": t1 - t0}
+        pool.terminate()
+    return {"steps": done, "seconds": t1 - t0, "cores": cores}
+
+
+def copy_ceiling():
+    """Achieved device-to-device copy bandwidth (read + write bytes / time) of 1 GiB
+    arrays, timed with events on torch's stream, which the copy runs on."""
+    import torch
+    a = torch.ones(128 * 1024 * 1024, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(10):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / 10
+    del a, b
+    return 2 * 128 * 1024 * 1024 * 8 / (ms * 1e-3) / 1e9
 
 
 COUNTERS = os.path.join(ROOT, "profiles", "ensemble_256_sem_hbm_counters.md")
@@ -268,6 +310,16 @@ def main():
               "ensemble share one device; run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
 
+    cpu = None
+    if not args.no_cpu_baseline and not args.timing_only:
+        cb = run_cpu_baseline(args.replicas, args.cpu_budget)
+        cpu = {"value": round(2 * cb["steps"] / cb["seconds"], 4), "unit": "mobility solves/s",
+               "cores": cb["cores"], "kind": "oracle",
+               "sample": "one SEM step on each of %d ensemble replicas in ensemble order (FP64 oracle, solves "
+                         "to 1e-12), %d single-threaded processes, %.1f s" % (cb["steps"], cb["cores"],
+                                                                             cb["seconds"])}
+        log("cpu oracle: %.3f solves/s on %d processes" % (cpu["value"], cb["cores"]))
+
     import torch
     import workloads as W
     if args.copy_probe:
@@ -299,19 +351,13 @@ def main():
 
     timing = run_gpu(ens, 1, 0, fp32=1, timing=True)
     roofline, kernels = roofline_of(timing["stats"], args.replicas == 256 and MG_FUSED == 0)
+    roofline["copy_ceiling_GBps"] = round(copy_ceiling(), 1)
 
     w2 = W.two_spheres()
     two = run_gpu([w2], args.two_spheres_steps, 2, fp32=1)
     two_value = 2 * two["steps"] / two["seconds"]
     log("two spheres: %.1f solves/s" % two_value)
 
-    cpu = None
-    if not args.no_cpu_baseline:
-        cb = run_cpu_baseline(ens, args.cpu_budget)
-        cpu = {"value": round(2 * cb["steps"] / cb["seconds"], 4), "unit": "mobility solves/s", "cores": 1,
-               "kind": "oracle",
-               "sample": "one SEM step on each of the first %d ensemble replicas (FP64 oracle, solves to 1e-12, "
-                         "1 thread)" % cb["steps"]}
 
     n_cells = sum(int(np.prod(w.n)) for w in ens)
     line = {
