@@ -125,6 +125,7 @@ class Ensemble:
 
 
 MG_FUSED = 0
+RESTART = 0       # 0: the library default
 
 
 def run_gpu(ws, steps, warmup, fp32, seed=2024, timing=False, graphs=True):
@@ -133,7 +134,7 @@ def run_gpu(ws, steps, warmup, fp32, seed=2024, timing=False, graphs=True):
     from tests.helpers import lib_context
     E = Ensemble(ws)
     ctx = lib_context(rb, ws, tol=ws[0].tol, precond_fp32=fp32, use_graphs=int(graphs and not timing),
-                      mg_fused=MG_FUSED)
+                      mg_fused=MG_FUSED, **({"restart": RESTART} if RESTART else {}))
     U = torch.empty((E.nb, 6), dtype=torch.float64, device="cuda")
     step_id = 0
     iters = 0
@@ -299,19 +300,23 @@ def main():
     ap.add_argument("--timing-only", action="store_true",
                     help="only the eager timed run of the ensemble (one SEM launch, no masking of converged "
                          "replicas, no graphs): the command the hardware-counter profiles are taken on")
+    ap.add_argument("--restart", type=int, default=0, help="FGMRES restart length (0: library default)")
+    ap.add_argument("--batched-only", action="store_true",
+                    help="only the batched ensemble launches (the command the graph-mode trace is taken on)")
     ap.add_argument("--mg-fused", type=int, default=0, choices=(0, 1, 2),
                     help="multigrid level kernels: 0 separate (default), 1 fused where the level fills the "
                          "device, 2 fused on every level")
     args = ap.parse_args()
-    global MG_FUSED
+    global MG_FUSED, RESTART
     MG_FUSED = args.mg_fused
+    RESTART = args.restart
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU: every box here has a single MI355X, and the replicas of the "
               "ensemble share one device; run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
 
     cpu = None
-    if not args.no_cpu_baseline and not args.timing_only:
+    if not args.no_cpu_baseline and not args.timing_only and not args.batched_only:
         cb = run_cpu_baseline(args.replicas, args.cpu_budget)
         cpu = {"value": round(2 * cb["steps"] / cb["seconds"], 4), "unit": "mobility solves/s",
                "cores": cb["cores"], "kind": "oracle",
@@ -344,6 +349,10 @@ def main():
     solves = 2 * batched["replicas"] * batched["steps"]
     value = solves / batched["seconds"]
     log("batched fp32-pc: %.1f solves/s (%.2f s per launch)" % (value, batched["seconds"] / batched["steps"]))
+    if args.batched_only:
+        print(json.dumps({"batched_only": True, "value": round(value, 3), "steps": batched["steps"],
+                          "fgmres_iters_per_launch": batched["iters"] / batched["steps"]}), flush=True)
+        return
 
     plain = run_plain(ens[:args.plain_replicas])
     plain_value = 2 * plain["steps"] / plain["seconds"]
