@@ -64,54 +64,67 @@ __device__ __forceinline__ void unlin(long long lin, const LevDev &L, int idx[3]
 
 // ------------------------------------------------------------------ fused fluid apply
 // y_c = -eta Lm_c v + (G pi)_c for c = x, y, z;  y_pi = -(D v).  Pinned slots -> 0.
-__global__ void k_apply_fluid(const RepDev *reps, const BlockEnt *tab, const double *__restrict__ x,
-                              double *__restrict__ y, const int *__restrict__ mask) {
-    BlockEnt be = tab[xcd_block(blockIdx.x, gridDim.x)];
+// One thread per cell (npt cells, RB_BLOCK apart).  Neighbour offsets and boundary rules are computed first and
+// applied with selects, so the loads of all three components are in flight together;
+// the divergence reuses each component's +e_c neighbour.
+__global__ __launch_bounds__(RB_BLOCK) void k_apply_fluid(const RepDev *reps, const BlockEnt *tab,
+                                                          const double *__restrict__ x, double *__restrict__ y,
+                                                          const int *__restrict__ mask) {
+    const BlockEnt be = tab[xcd_block(blockIdx.x, gridDim.x)];
     if (mask && !mask[be.rep]) return;
     const RepDev &R = reps[be.rep];
     for (int t_ = 0; t_ < be.npt; ++t_) {
-    long long lin = be.start + threadIdx.x + (long long)t_ * RB_BLOCK;
-    long long N = R.N;
-    if (lin >= N) continue;
+    const long long l = be.start + threadIdx.x + (long long)t_ * RB_BLOCK;
+    if (l >= R.N) break;
+    const int lin = (int)l, N = (int)R.N;
     int idx[3];
     unlin(lin, R, idx);
-    const double *u[3] = {x + R.off, x + R.off + N, x + R.off + 2 * N};
-    const double *p = x + R.off + 3 * N;
-    double ih = R.inv_h;
-    double ih2[3] = {ih * ih, ih * ih, ih * ih};
-    // pressure: cell lin; divergence uses faces lin and lin + e_c
-    double div = 0.0;
-    long long stride = 1;
+    const int st[3] = {1, R.n[0], R.n[0] * R.n[1]};
+    const double *xr = x + R.off;
+    double *yr = y + R.off;
+    const double ih = R.inv_h, ih2 = R.inv_h * R.inv_h;
+    int kd[3][6], off[3][6], offp[3];
+#pragma unroll
     for (int c = 0; c < 3; ++c) {
-        double lo = pinned(c, idx, R.bc) ? 0.0 : u[c][lin];
-        double hi;
-        int q = idx[c] + 1;
-        if (q < R.n[c]) hi = u[c][lin + stride];
-        else hi = (R.bc[c] == RBFIB_PERIODIC) ? u[c][lin - (long long)(R.n[c] - 1) * stride] : 0.0;
-        div += (hi - lo) * ih;
-        stride *= R.n[c];
-    }
-    y[R.off + 3 * N + lin] = -div;
-    stride = 1;
-    double pc = p[lin];
-    for (int c = 0; c < 3; ++c) {
-        double out = 0.0;
-        if (!pinned(c, idx, R.bc)) {
-            double dg;
-            double lap = lap_point<double>(u[c], c, idx, R.n, R.bc, ih2, lin, dg);
-            // neighbour values at pinned slots must read as zero
-            // (lap_point's face-normal rule already returns 0 for p <= 0)
-            double pm = (idx[c] > 0) ? p[lin - stride] : p[lin + (long long)(R.n[c] - 1) * stride];
-            out = -R.eta * lap + (pc - pm) * ih;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            kd[c][2 * a] = nbr_kind(idx[a], -1, R.n[a], R.bc[a], a, c);
+            kd[c][2 * a + 1] = nbr_kind(idx[a], +1, R.n[a], R.bc[a], a, c);
+            off[c][2 * a] = kd[c][2 * a] ? 0 : (idx[a] == 0 ? (R.n[a] - 1) * st[a] : -st[a]);
+            off[c][2 * a + 1] = kd[c][2 * a + 1] ? 0 : (idx[a] == R.n[a] - 1 ? -(R.n[a] - 1) * st[a] : st[a]);
         }
-        y[R.off + c * N + lin] = out;
-        stride *= R.n[c];
+        offp[c] = idx[c] > 0 ? -st[c] : (R.n[c] - 1) * st[c];   // pressure at -e_c (unused when pinned)
     }
+    double self[3], nb[3][6], pm[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const double *u = xr + (long long)c * N;
+        self[c] = u[lin];
+#pragma unroll
+        for (int q = 0; q < 6; ++q) nb[c][q] = u[lin + off[c][q]];
+        pm[c] = xr[3LL * N + lin + offp[c]];
+    }
+    const double pc = xr[3LL * N + lin];
+    double div = 0.0;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const bool pin = pinned(c, idx, R.bc);
+        double lap = 0.0;
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+            lap = lap_acc<double>(pick<double>(kd[c][2 * a + 1], nb[c][2 * a + 1], self[c]), self[c],
+                                  pick<double>(kd[c][2 * a], nb[c][2 * a], self[c]), ih2, lap);
+        // D v: face +e_c (zero beyond a wall, wrapped when periodic) minus face c of this cell
+        const double hi = pick<double>(kd[c][2 * c + 1], nb[c][2 * c + 1], self[c]);
+        div += (hi - (pin ? 0.0 : self[c])) * ih;
+        yr[(long long)c * N + lin] = pin ? 0.0 : -R.eta * lap + (pc - pm[c]) * ih;
+    }
+    yr[3LL * N + lin] = -div;
     }
 }
 
 void launch_apply_fluid(Ctx &c, const double *x, double *y) {
-    hipLaunchKernelGGL(k_apply_fluid, dim3(c.n_tab_cells), dim3(RB_BLOCK), 0, c.stream, c.d_reps, c.d_tab_cells,
+    hipLaunchKernelGGL(k_apply_fluid, dim3(c.n_tab_cells1), dim3(RB_BLOCK), 0, c.stream, c.d_reps, c.d_tab_cells1,
                        x, y, c.mask);
 }
 

@@ -129,6 +129,19 @@ __device__ __forceinline__ int axis_neighbours(int t, int T, int bc, int out[3])
     return k;
 }
 
+// The o-th entry (o = 0, 1, 2) of axis_neighbours(t, T, bc); false when there is none.
+__device__ __forceinline__ bool tile_neighbour(int t, int T, int bc, int o, int &out) {
+    if (bc == RBFIB_PERIODIC) {
+        if (T >= 3) { out = o == 0 ? (t + T - 1) % T : (o == 1 ? t : (t + 1) % T); return true; }
+        if (T == 2) { out = o == 0 ? t : 1 - t; return o < 2; }
+        out = t;
+        return o == 0;
+    }
+    const int first = t > 0 ? t - 1 : 0, last = t + 1 < T ? t + 1 : T - 1;
+    out = first + o;
+    return out <= last;
+}
+
 __global__ void k_tile_active(const RepDev *reps, const int *tile_rep, const int *count, int *flag, int ntiles) {
     int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= ntiles) return;
@@ -205,21 +218,29 @@ __global__ __launch_bounds__(256) void k_spread(const RepDev *reps, const int *t
         const RepDev &R = reps[tile_rep[t]];
         int lt = t - R.tile0;
         int tc[3] = {lt % R.tdim[0], (lt / R.tdim[0]) % R.tdim[1], lt / (R.tdim[0] * R.tdim[1])};
+        // source tiles: slot x + 3 (y + 3 z) holds the x-th, y-th, z-th neighbour of
+        // axis_neighbours (empty when that axis has fewer), loaded by 27 threads at once;
+        // the non-empty slots keep the order of the axis_neighbours enumeration
+        if (tid < 27) {
+            const int o[3] = {tid % 3, (tid / 3) % 3, tid / 9};
+            bool ok = true;
+            int nbt[3];
+#pragma unroll
+            for (int a = 0; a < 3; ++a) ok = tile_neighbour(tc[a], R.tdim[a], R.bc[a], o[a], nbt[a]) && ok;
+            int st = 0, ct = 0;
+            if (ok) {
+                const int g = R.tile0 + nbt[0] + R.tdim[0] * (nbt[1] + R.tdim[1] * nbt[2]);
+                st = tile_start[g];
+                ct = tile_count[g];
+            }
+            nstart[tid] = st;
+            ncnt[tid] = ct;
+        }
+        __syncthreads();
         if (tid == 0) {
-            int nb[3][3], k[3];
-            for (int a = 0; a < 3; ++a) k[a] = axis_neighbours(tc[a], R.tdim[a], R.bc[a], nb[a]);
-            int cnt = 0;
             npre[0] = 0;
-            for (int z = 0; z < k[2]; ++z)
-                for (int yy = 0; yy < k[1]; ++yy)
-                    for (int x = 0; x < k[0]; ++x) {
-                        int g = R.tile0 + nb[0][x] + R.tdim[0] * (nb[1][yy] + R.tdim[1] * nb[2][z]);
-                        nstart[cnt] = tile_start[g];
-                        ncnt[cnt] = tile_count[g];
-                        npre[cnt + 1] = npre[cnt] + ncnt[cnt];
-                        ++cnt;
-                    }
-            nn = cnt;
+            for (int k = 0; k < 27; ++k) npre[k + 1] = npre[k] + ncnt[k];
+            nn = 27;
         }
         __syncthreads();
         int M = npre[nn];
