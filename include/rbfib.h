@@ -113,8 +113,8 @@ typedef struct {
     int restart;               /* FGMRES restart length (60)                         */
     int max_iter;              /* total iteration cap (600)                          */
     int precond_fp32;          /* 1: multigrid preconditioner in FP32 (0)            */
-    int mg_sweeps;             /* damped-Jacobi sweeps before and after (2)          */
-    double mg_omega;           /* Jacobi damping (0.8)                               */
+    int mg_sweeps;             /* damped-Jacobi sweeps before and after (3)          */
+    double mg_omega;           /* Jacobi damping (0.9)                               */
     double blob_radius;        /* blob radius of the body block, units of h (1.25)   */
     double rfd_delta;          /* random-finite-difference delta (1e-5)              */
     double min_body_dist;      /* rejection distance between body centres (0 = off)  */

@@ -226,7 +226,8 @@ static T *vcycle(Ctx &c, int c0, int nc) {
     for (int l = 0; l < c.maxlev; ++l) {
         fz[l] = nu == 2 && l + 1 < c.maxlev &&
                 (c.opts.mg_fused == 2 || (c.opts.mg_fused == 1 && (long long)c.n_tab_mg[l] * nc >= MGF_MIN_BLOCKS));
-        res[l] = fz[l] ? Tt : X;
+        // separate kernels: the up sweeps alternate X -> T -> X ..., ending in T for odd counts
+        res[l] = (fz[l] || nu % 2 == 1) ? Tt : X;
     }
     for (int l = 0; l < c.maxlev; ++l) {
         launch_coarse<T>(c, l, c0, nc, B, res[l]);
@@ -262,7 +263,7 @@ static T *vcycle(Ctx &c, int c0, int nc) {
             if (l == 0) record(c, 1, false, sz * c.lev_cells[0] * 3.0);
             std::swap(in, out);
         }
-        if (in != X) launch_smooth<T>(c, l, c0, nc, in, X, B, false);   // odd count: one more sweep lands in X
+        // the last sweep wrote `in`, which is res[l] by construction
     }
     return res[0];
 }
@@ -981,8 +982,8 @@ void rbfib_default_opts(rbfib_opts *o) {
     o->restart = 60;
     o->max_iter = 600;
     o->precond_fp32 = 0;
-    o->mg_sweeps = 2;
-    o->mg_omega = 0.8;
+    o->mg_sweeps = 3;
+    o->mg_omega = 0.9;
     o->blob_radius = 1.25;
     o->rfd_delta = 1e-5;
     o->min_body_dist = 0.0;

@@ -1,7 +1,7 @@
 """Fused multigrid level kernels against the separate smoother / restriction /
 prolongation kernels, through rbfib_precondition.
 
-Both run the same V(2,2) cycle (damped Jacobi, full-weighting restriction,
+The fused kernels implement two sweeps per level, so both run a V(2,2) cycle (damped Jacobi, full-weighting restriction,
 linear prolongation, dense coarsest solve) with the same association of every
 floating-point operation, so the preconditioner outputs are identical: grids
 with ragged tiles, a periodic axis, a sliding wall, an axis that stops
@@ -58,11 +58,11 @@ def test_fused_vcycle_matches_separate_kernels(rb, name, fp32):
     import torch
     ws = CASES[name]
     print("mgfused", name, "fp32", fp32, flush=True)
-    ctx = lib_context(rb, ws, precond_fp32=fp32, mg_fused=0)
+    ctx = lib_context(rb, ws, precond_fp32=fp32, mg_fused=0, mg_sweeps=2)
     q, th, r = _state(ws, ctx, 11)
     z0 = torch.full((ctx.L,), float("nan"), dtype=torch.float64, device="cuda")
     rb.rbfib_precondition(ctx, q, th, r, z0)
-    rb.rbfib_set_opts(ctx, rb.rbfib_default_opts(precond_fp32=fp32, mg_fused=2))
+    rb.rbfib_set_opts(ctx, rb.rbfib_default_opts(precond_fp32=fp32, mg_fused=2, mg_sweeps=2))
     z1 = torch.full_like(z0, float("nan"))
     rb.rbfib_precondition(ctx, q, th, r, z1)
     torch.cuda.synchronize()
@@ -80,7 +80,7 @@ def test_fused_solve_matches_separate_kernels(rb, fp32):
     w = W.two_spheres()
     out = []
     for fused in (0, 2):
-        ctx = lib_context(rb, w, tol=1e-8, precond_fp32=fp32, mg_fused=fused)
+        ctx = lib_context(rb, w, tol=1e-8, precond_fp32=fp32, mg_fused=fused, mg_sweeps=2)
         U = torch.empty((w.nb, 6), dtype=torch.float64, device="cuda")
         info = rb.rbfib_solve_mobility(ctx, dev(w.q), dev(w.theta), dev(w.FT), U, include_bc=False)
         print("fused", fused, "fp32", fp32, "iters", info[0].iters, "res", info[0].rel_residual, flush=True)
@@ -99,7 +99,7 @@ def test_fp64_cycle_matches_fp32_cycle(rb, name, fused):
     ws = CASES[name]
     z = {}
     for fp32 in (0, 1):
-        ctx = lib_context(rb, ws, precond_fp32=fp32, mg_fused=fused)
+        ctx = lib_context(rb, ws, precond_fp32=fp32, mg_fused=fused, mg_sweeps=2)
         q, th, r = _state(ws, ctx, 12)
         out = torch.full((ctx.L,), float("nan"), dtype=torch.float64, device="cuda")
         rb.rbfib_precondition(ctx, q, th, r, out)
@@ -125,11 +125,11 @@ def test_mixed_levels_match_separate_kernels(rb, fp32):
     (the 128^3 grid: fused on the fine levels, separate on the coarse ones)."""
     import torch
     ws = CASES["many_spheres_128"]
-    ctx = lib_context(rb, ws, precond_fp32=fp32, mg_fused=0)
+    ctx = lib_context(rb, ws, precond_fp32=fp32, mg_fused=0, mg_sweeps=2)
     q, th, r = _state(ws, ctx, 13)
     z = []
     for mode in (0, 1):
-        rb.rbfib_set_opts(ctx, rb.rbfib_default_opts(precond_fp32=fp32, mg_fused=mode))
+        rb.rbfib_set_opts(ctx, rb.rbfib_default_opts(precond_fp32=fp32, mg_fused=mode, mg_sweeps=2))
         out = torch.full((ctx.L,), float("nan"), dtype=torch.float64, device="cuda")
         rb.rbfib_precondition(ctx, q, th, r, out)
         torch.cuda.synchronize()
