@@ -156,6 +156,82 @@ void launch_to_level0(Ctx &c, const double *src, T *b, int c0, int nc) {
 // NPT points per thread, all loads of a thread issued before any arithmetic and
 // the boundary rules applied with selects, so that the loads of the NPT points are
 // in flight together.
+// FP32 sweep on four consecutive x points per thread (rows whose length is a multiple
+// of 4, blocks of 1024 points): 16-byte loads of the point, its y and z neighbour rows
+// and b, two scalar loads for the x neighbours outside the group; y and z rules are
+// shared by the four points.  Same arithmetic, in the same order, as the scalar path.
+template <bool FIRST>
+__device__ __forceinline__ void smooth_row4(const RepDev &R, const LevDev &Lv, const BlockEnt &be, int comp,
+                                            const float *__restrict__ xi, float *__restrict__ xo,
+                                            const float *__restrict__ bb, float s, float om) {
+    const long long g0 = be.start + 4LL * threadIdx.x;
+    if (g0 >= Lv.N) return;
+    const int lin = (int)g0;
+    int idx[3];
+    unlin(lin, Lv, idx);
+    const int n0 = Lv.n[0], x0 = idx[0];
+    const int st[3] = {1, n0, n0 * Lv.n[1]};
+    int kyz[4], off[4];
+#pragma unroll
+    for (int a = 1; a < 3; ++a) {
+        const int km = nbr_kind(idx[a], -1, Lv.n[a], R.bc[a], a, comp);
+        const int kp = nbr_kind(idx[a], +1, Lv.n[a], R.bc[a], a, comp);
+        kyz[2 * (a - 1)] = km;
+        kyz[2 * (a - 1) + 1] = kp;
+        off[2 * (a - 1)] = km ? 0 : (idx[a] == 0 ? (Lv.n[a] - 1) * st[a] : -st[a]);
+        off[2 * (a - 1) + 1] = kp ? 0 : (idx[a] == Lv.n[a] - 1 ? -(Lv.n[a] - 1) * st[a] : st[a]);
+    }
+    const float4 bv = *reinterpret_cast<const float4 *>(bb + lin);
+    const float b4[4] = {bv.x, bv.y, bv.z, bv.w};
+    float x4[4] = {0.f, 0.f, 0.f, 0.f}, nb[4][4], xl = 0.f, xr = 0.f;
+    int kxm[4], kxp[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        kxm[q] = nbr_kind(x0 + q, -1, n0, R.bc[0], 0, comp);
+        kxp[q] = nbr_kind(x0 + q, +1, n0, R.bc[0], 0, comp);
+    }
+    if (!FIRST) {
+        const float4 v = *reinterpret_cast<const float4 *>(xi + lin);
+        x4[0] = v.x; x4[1] = v.y; x4[2] = v.z; x4[3] = v.w;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const float4 u = *reinterpret_cast<const float4 *>(xi + lin + off[e]);
+            nb[e][0] = u.x; nb[e][1] = u.y; nb[e][2] = u.z; nb[e][3] = u.w;
+        }
+        // x neighbours outside the group (wrapped when periodic, unused otherwise)
+        xl = xi[lin + (kxm[0] ? 0 : (x0 == 0 ? n0 - 1 : -1))];
+        xr = xi[lin + 3 + (kxp[3] ? 0 : (x0 + 3 == n0 - 1 ? -(n0 - 1) : 1))];
+    }
+    const float ihx = (float)Lv.inv_h2[0], ihy = (float)Lv.inv_h2[1], ihz = (float)Lv.inv_h2[2];
+    const float day = diag_axis<float>(comp, 1, idx[1], Lv.n[1], R.bc[1]);
+    const float daz = diag_axis<float>(comp, 2, idx[2], Lv.n[2], R.bc[2]);
+    const bool pin_yz = (comp == 1 && R.bc[1] == RBFIB_WALL && idx[1] == 0) ||
+                        (comp == 2 && R.bc[2] == RBFIB_WALL && idx[2] == 0);
+    float y4[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const float dg = fmad(daz, ihz, fmad(day, ihy, fmad(diag_axis<float>(comp, 0, x0 + q, n0, R.bc[0]), ihx, 0.f)));
+        const float w = jacobi_w<float>(om, s, dg);
+        float y;
+        if (FIRST) {
+            y = b4[q] * w;
+        } else {
+            const float self = x4[q];
+            const float xm = q == 0 ? xl : x4[q > 0 ? q - 1 : 0];
+            const float xp = q == 3 ? xr : x4[q < 3 ? q + 1 : 3];
+            float acc = lap_acc<float>(pick<float>(kxp[q], xp, self), self, pick<float>(kxm[q], xm, self), ihx, 0.f);
+            acc = lap_acc<float>(pick<float>(kyz[1], nb[1][q], self), self, pick<float>(kyz[0], nb[0][q], self), ihy,
+                                 acc);
+            acc = lap_acc<float>(pick<float>(kyz[3], nb[3][q], self), self, pick<float>(kyz[2], nb[2][q], self), ihz,
+                                 acc);
+            y = jacobi_step<float>(self, b4[q], s, acc, w);
+        }
+        const bool pin = pin_yz || (comp == 0 && R.bc[0] == RBFIB_WALL && x0 + q == 0);
+        y4[q] = pin ? 0.f : y;
+    }
+    *reinterpret_cast<float4 *>(xo + lin) = make_float4(y4[0], y4[1], y4[2], y4[3]);
+}
+
 template <typename T, int NPT, bool FIRST>
 __global__ __launch_bounds__(RB_BLOCK) void k_smooth(const RepDev *reps, const LevDev *levs, const BlockEnt *tab,
                                                      int lev, int c0, const T *__restrict__ xin, T *__restrict__ xout,
@@ -171,6 +247,13 @@ __global__ __launch_bounds__(RB_BLOCK) void k_smooth(const RepDev *reps, const L
     const T *bb = b + base;
     T *xo = xout + base;
     const T s = (comp < 3) ? (T)(-R.eta) : (T)-1;
+    if constexpr (sizeof(T) == 4 && NPT == 4) {
+        if (Lv.n[0] % 4 == 0) {    // uniform per block: every row splits into aligned groups of 4
+            smooth_row4<FIRST>(R, Lv, be, comp, (const float *)xi, (float *)xo, (const float *)bb, (float)s,
+                               (float)omega);
+            return;
+        }
+    }
     const int st[3] = {1, Lv.n[0], Lv.n[0] * Lv.n[1]};
     int lin[NPT], kinds[NPT];
     bool ok[NPT], pin[NPT];

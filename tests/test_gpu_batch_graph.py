@@ -109,3 +109,41 @@ def test_graph_replay_matches_eager(rb):
     assert np.array_equal(Ug.cpu().numpy(), Ue2.cpu().numpy())
     cg.close()
     ce.close()
+
+
+@pytest.mark.parametrize("fp32", [1, 0])
+def test_large_batch_paths_equal_single_replica(rb, fp32):
+    """The 256-replica ensemble (10.9M cells) runs the grid kernels with four points
+    per thread (the FP32 smoother on aligned groups of four x points); single
+    replicas run one point per thread.  Preconditioner outputs and full solves agree
+    bit for bit on the replicas' segments."""
+    import torch
+    ens = W.ensemble()
+    picks = [0, 1, 2, 3, 100, 255]
+    ctx = lib_context(rb, ens, tol=1e-6, precond_fp32=fp32)
+    q = dev(_cat([w.q for w in ens]))
+    th = dev(_cat([w.theta for w in ens]))
+    r = torch.as_tensor(np.random.default_rng(31).standard_normal(ctx.L), dtype=torch.float64).cuda()
+    z = torch.full_like(r, float("nan"))
+    rb.rbfib_precondition(ctx, q, th, r, z)
+    U = torch.empty((sum(w.nb for w in ens), 6), dtype=torch.float64, device="cuda")
+    info = rb.rbfib_solve_mobility(ctx, q, th, dev(_cat([w.FT for w in ens])), U, allow=())
+    torch.cuda.synchronize()
+    zb, Ub, lay = z.cpu().numpy(), U.cpu().numpy(), ctx.layout.copy()
+    ctx.close()
+    body0 = np.cumsum([0] + [w.nb for w in ens])
+    for k in picks:
+        w = ens[k]
+        a, e = int(lay[k][0]), int(lay[k][3]) + 6 * w.nb
+        c1 = lib_context(rb, w, tol=1e-6, precond_fp32=fp32)
+        assert c1.L == e - a
+        z1 = torch.full((c1.L,), float("nan"), dtype=torch.float64, device="cuda")
+        rb.rbfib_precondition(c1, dev(w.q), dev(w.theta), r[a:e].contiguous(), z1)
+        U1 = torch.empty((w.nb, 6), dtype=torch.float64, device="cuda")
+        i1 = rb.rbfib_solve_mobility(c1, dev(w.q), dev(w.theta), dev(w.FT), U1, allow=())
+        torch.cuda.synchronize()
+        print("replica", k, w.n, "iters batched", info[k].iters, "alone", i1[0].iters, flush=True)
+        assert np.array_equal(zb[a:e], z1.cpu().numpy())
+        assert info[k].iters == i1[0].iters
+        assert np.array_equal(Ub[body0[k]:body0[k + 1]], U1.cpu().numpy())
+        c1.close()
