@@ -515,7 +515,7 @@ struct Ctx {
 void launch_apply_fluid(Ctx &c, const double *x, double *y);
 template <typename T> void launch_to_level0(Ctx &c, const double *src, T *b, int c0, int nc);
 template <typename T> void launch_smooth(Ctx &c, int lev, int c0, int nc, const T *xin, T *xout, const T *b, bool first);
-template <typename T> void launch_restrict(Ctx &c, int lev, int c0, int nc, const T *x, const T *b, T *bc);
+template <typename T> void launch_restrict(Ctx &c, int lev, int c0, int nc, const T *x, const T *b, T *bc, T *r);
 template <typename T> void launch_prolong(Ctx &c, int lev, int c0, int nc, const T *xc, T *xf);
 template <typename T> void launch_coarse(Ctx &c, int lev, int c0, int nc, const T *b, T *x);
 // fused level kernels (mgfused.hip)

@@ -152,7 +152,9 @@ void launch_to_level0(Ctx &c, const double *src, T *b, int c0, int nc) {
 }
 
 // Operator of component comp at a level: A = -eta Lm (velocity) or -L (pressure).
-// Damped Jacobi sweep x_out = x_in + w (b - A x_in), w = omega / diag (FIRST: x_in = 0).
+// MG_FIRST: damped Jacobi sweep from zero, x_out = w b (w = omega / diag);
+// MG_SWEEP: x_out = x_in + w (b - A x_in); MG_RESID: x_out = b - A x_in.
+// Pinned slots are written as zero.
 // NPT points per thread, all loads of a thread issued before any arithmetic and
 // the boundary rules applied with selects, so that the loads of the NPT points are
 // in flight together.
@@ -160,7 +162,11 @@ void launch_to_level0(Ctx &c, const double *src, T *b, int c0, int nc) {
 // of 4, blocks of 1024 points): 16-byte loads of the point, its y and z neighbour rows
 // and b, two scalar loads for the x neighbours outside the group; y and z rules are
 // shared by the four points.  Same arithmetic, in the same order, as the scalar path.
-template <bool FIRST>
+#define MG_FIRST 0
+#define MG_SWEEP 1
+#define MG_RESID 2
+
+template <int MODE>
 __device__ __forceinline__ void smooth_row4(const RepDev &R, const LevDev &Lv, const BlockEnt &be, int comp,
                                             const float *__restrict__ xi, float *__restrict__ xo,
                                             const float *__restrict__ bb, float s, float om) {
@@ -190,7 +196,7 @@ __device__ __forceinline__ void smooth_row4(const RepDev &R, const LevDev &Lv, c
         kxm[q] = nbr_kind(x0 + q, -1, n0, R.bc[0], 0, comp);
         kxp[q] = nbr_kind(x0 + q, +1, n0, R.bc[0], 0, comp);
     }
-    if (!FIRST) {
+    if (MODE != MG_FIRST) {
         const float4 v = *reinterpret_cast<const float4 *>(xi + lin);
         x4[0] = v.x; x4[1] = v.y; x4[2] = v.z; x4[3] = v.w;
 #pragma unroll
@@ -213,7 +219,7 @@ __device__ __forceinline__ void smooth_row4(const RepDev &R, const LevDev &Lv, c
         const float dg = fmad(daz, ihz, fmad(day, ihy, fmad(diag_axis<float>(comp, 0, x0 + q, n0, R.bc[0]), ihx, 0.f)));
         const float w = jacobi_w<float>(om, s, dg);
         float y;
-        if (FIRST) {
+        if (MODE == MG_FIRST) {
             y = b4[q] * w;
         } else {
             const float self = x4[q];
@@ -224,7 +230,7 @@ __device__ __forceinline__ void smooth_row4(const RepDev &R, const LevDev &Lv, c
                                  acc);
             acc = lap_acc<float>(pick<float>(kyz[3], nb[3][q], self), self, pick<float>(kyz[2], nb[2][q], self), ihz,
                                  acc);
-            y = jacobi_step<float>(self, b4[q], s, acc, w);
+            y = MODE == MG_RESID ? mg_residual<float>(b4[q], s, acc) : jacobi_step<float>(self, b4[q], s, acc, w);
         }
         const bool pin = pin_yz || (comp == 0 && R.bc[0] == RBFIB_WALL && x0 + q == 0);
         y4[q] = pin ? 0.f : y;
@@ -232,7 +238,7 @@ __device__ __forceinline__ void smooth_row4(const RepDev &R, const LevDev &Lv, c
     *reinterpret_cast<float4 *>(xo + lin) = make_float4(y4[0], y4[1], y4[2], y4[3]);
 }
 
-template <typename T, int NPT, bool FIRST>
+template <typename T, int NPT, int MODE>
 __global__ __launch_bounds__(RB_BLOCK) void k_smooth(const RepDev *reps, const LevDev *levs, const BlockEnt *tab,
                                                      int lev, int c0, const T *__restrict__ xin, T *__restrict__ xout,
                                                      const T *__restrict__ b, double omega,
@@ -249,8 +255,8 @@ __global__ __launch_bounds__(RB_BLOCK) void k_smooth(const RepDev *reps, const L
     const T s = (comp < 3) ? (T)(-R.eta) : (T)-1;
     if constexpr (sizeof(T) == 4 && NPT == 4) {
         if (Lv.n[0] % 4 == 0) {    // uniform per block: every row splits into aligned groups of 4
-            smooth_row4<FIRST>(R, Lv, be, comp, (const float *)xi, (float *)xo, (const float *)bb, (float)s,
-                               (float)omega);
+            smooth_row4<MODE>(R, Lv, be, comp, (const float *)xi, (float *)xo, (const float *)bb, (float)s,
+                              (float)omega);
             return;
         }
     }
@@ -282,7 +288,7 @@ __global__ __launch_bounds__(RB_BLOCK) void k_smooth(const RepDev *reps, const L
         dg[t] = d;
         kinds[t] = kd;
         bv[t] = bb[lin[t]];
-        if (!FIRST) {
+        if (MODE != MG_FIRST) {
             xv[t] = xi[lin[t]];
 #pragma unroll
             for (int q = 0; q < 6; ++q) nb[t][q] = xi[lin[t] + off[q]];
@@ -292,7 +298,7 @@ __global__ __launch_bounds__(RB_BLOCK) void k_smooth(const RepDev *reps, const L
     for (int t = 0; t < NPT; ++t) {
         const T w = jacobi_w<T>((T)omega, s, dg[t]);
         T y;
-        if (FIRST) {
+        if (MODE == MG_FIRST) {
             y = bv[t] * w;
         } else {
             T acc = (T)0;
@@ -302,77 +308,46 @@ __global__ __launch_bounds__(RB_BLOCK) void k_smooth(const RepDev *reps, const L
                 acc = lap_acc<T>(pick<T>((kd >> 2) & 3, nb[t][2 * a + 1], xv[t]), xv[t],
                                  pick<T>(kd & 3, nb[t][2 * a], xv[t]), (T)Lv.inv_h2[a], acc);
             }
-            y = jacobi_step<T>(xv[t], bv[t], s, acc, w);
+            y = MODE == MG_RESID ? mg_residual<T>(bv[t], s, acc) : jacobi_step<T>(xv[t], bv[t], s, acc, w);
         }
         if (ok[t]) xo[lin[t]] = pin[t] ? (T)0 : y;
     }
 }
 
-template <typename T, int NPT>
-static void launch_smooth_n(Ctx &c, int lev, int c0, int nc, const T *xin, T *xout, const T *b, bool first) {
-    if (first)
-        hipLaunchKernelGGL((k_smooth<T, NPT, true>), dim3(c.n_tab_lev[lev], nc), dim3(RB_BLOCK), 0, c.stream,
-                           c.d_reps, c.d_levs, c.d_tab_lev[lev], lev, c0, xin, xout, b, c.opts.mg_omega, c.mask);
-    else
-        hipLaunchKernelGGL((k_smooth<T, NPT, false>), dim3(c.n_tab_lev[lev], nc), dim3(RB_BLOCK), 0, c.stream,
-                           c.d_reps, c.d_levs, c.d_tab_lev[lev], lev, c0, xin, xout, b, c.opts.mg_omega, c.mask);
+template <typename T, int NPT, int MODE>
+static void launch_stencil(Ctx &c, int lev, int c0, int nc, const T *xin, T *xout, const T *b) {
+    hipLaunchKernelGGL((k_smooth<T, NPT, MODE>), dim3(c.n_tab_lev[lev], nc), dim3(RB_BLOCK), 0, c.stream, c.d_reps,
+                       c.d_levs, c.d_tab_lev[lev], lev, c0, xin, xout, b, c.opts.mg_omega, c.mask);
+}
+
+template <typename T, int MODE>
+static void launch_stencil_any(Ctx &c, int lev, int c0, int nc, const T *xin, T *xout, const T *b) {
+    if (c.n_tab_lev[lev] == 0) return;
+    if (c.mg_npt == 4) launch_stencil<T, 4, MODE>(c, lev, c0, nc, xin, xout, b);
+    else launch_stencil<T, 1, MODE>(c, lev, c0, nc, xin, xout, b);
 }
 
 template <typename T>
 void launch_smooth(Ctx &c, int lev, int c0, int nc, const T *xin, T *xout, const T *b, bool first) {
-    if (c.n_tab_lev[lev] == 0) return;
-    if (c.mg_npt == 4) launch_smooth_n<T, 4>(c, lev, c0, nc, xin, xout, b, first);
-    else launch_smooth_n<T, 1>(c, lev, c0, nc, xin, xout, b, first);
+    if (first) launch_stencil_any<T, MG_FIRST>(c, lev, c0, nc, xin, xout, b);
+    else launch_stencil_any<T, MG_SWEEP>(c, lev, c0, nc, xin, xout, b);
 }
 
-// Residual of level lev restricted to level lev+1: face-normal axis full weighting
-// (1/4, 1/2, 1/4 on faces 2I-1, 2I, 2I+1), cell-centred axes averaging of the two
-// children; an axis that is not coarsened keeps its index.
-// Residual b - A x at fine point (i, j, k), 0 at pinned points; the boundary rules
-// are applied with selects so that its eight loads issue together.
-template <typename T>
-__device__ __forceinline__ T residual_at(const RepDev &R, const LevDev &Lv, int comp, int i, int j, int k,
-                                         const T *x, const T *b) {
-    const int idx[3] = {i, j, k};
-    const int st[3] = {1, Lv.n[0], Lv.n[0] * Lv.n[1]};
-    const int lin = i + st[1] * j + st[2] * k;
-    int kind[6], off[6];
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        kind[2 * a] = nbr_kind(idx[a], -1, Lv.n[a], R.bc[a], a, comp);
-        kind[2 * a + 1] = nbr_kind(idx[a], +1, Lv.n[a], R.bc[a], a, comp);
-        off[2 * a] = kind[2 * a] ? 0 : (idx[a] == 0 ? (Lv.n[a] - 1) * st[a] : -st[a]);
-        off[2 * a + 1] = kind[2 * a + 1] ? 0 : (idx[a] == Lv.n[a] - 1 ? -(Lv.n[a] - 1) * st[a] : st[a]);
-    }
-    const T self = x[lin], bv = b[lin];
-    T nb[6];
-#pragma unroll
-    for (int q = 0; q < 6; ++q) nb[q] = x[lin + off[q]];
-    T acc = (T)0;
-#pragma unroll
-    for (int a = 0; a < 3; ++a)
-        acc = lap_acc<T>(pick<T>(kind[2 * a + 1], nb[2 * a + 1], self), self, pick<T>(kind[2 * a], nb[2 * a], self),
-                         (T)Lv.inv_h2[a], acc);
-    const T s = (comp < 3) ? (T)(-R.eta) : (T)-1;
-    return pinned(comp, idx, R.bc) ? (T)0 : mg_residual<T>(bv, s, acc);
-}
-
-// Residual of level lev restricted to level lev+1: face-normal axis full weighting
-// (1/4, 1/2, 1/4 on faces 2I-1, 2I, 2I+1), cell-centred axes averaging of the two
-// children; an axis that is not coarsened keeps its index.
+// Restriction of the residual r of level lev (written by a MG_RESID pass, zero at
+// pinned points) to the right-hand side of level lev+1: face-normal axis full
+// weighting (1/4, 1/2, 1/4 on faces 2I-1, 2I, 2I+1), cell-centred axes averaging of
+// the two children; an axis that is not coarsened keeps its index.
 template <typename T, int NPT>
 __global__ __launch_bounds__(RB_BLOCK) void k_restrict(const RepDev *reps, const LevDev *levs, const BlockEnt *tab,
-                                                       int lev, int c0, const T *__restrict__ x,
-                                                       const T *__restrict__ b, T *__restrict__ bc,
-                                                       const int *__restrict__ mask) {
+                                                       int lev, int c0, const T *__restrict__ rpool,
+                                                       T *__restrict__ bcpool, const int *__restrict__ mask) {
     BlockEnt be = tab[xcd_block(blockIdx.x, gridDim.x)];
     if (mask && !mask[be.rep]) return;
     int comp = c0 + blockIdx.y;
     const RepDev &R = reps[be.rep];
     const LevDev &F = levs[be.rep * RB_MAXLEV + lev];
     const LevDev &C = levs[be.rep * RB_MAXLEV + lev + 1];
-    const T *xf = x + F.off + comp * F.N;
-    const T *bf = b + F.off + comp * F.N;
+    const T *rf = rpool + F.off + comp * F.N;
     bool crs[3], face[3];
     int fc[3];
 #pragma unroll
@@ -381,6 +356,7 @@ __global__ __launch_bounds__(RB_BLOCK) void k_restrict(const RepDev *reps, const
         face[a] = crs[a] && a == comp;
         fc[a] = !crs[a] ? 1 : (face[a] ? 3 : 2);
     }
+    const int f01 = F.n[0] * F.n[1];
     // periodic wrap of the face-normal neighbours (wall: ci = 0 is pinned, excluded below)
     auto wrap = [](int f, int n) { return f < 0 ? f + n : (f >= n ? f - n : f); };
 #pragma unroll
@@ -390,7 +366,7 @@ __global__ __launch_bounds__(RB_BLOCK) void k_restrict(const RepDev *reps, const
         int ci[3];
         unlin(lin, C, ci);
         long long cbase = C.off + comp * C.N;
-        if (pinned(comp, ci, R.bc)) { bc[cbase + lin] = (T)0; continue; }
+        if (pinned(comp, ci, R.bc)) { bcpool[cbase + lin] = (T)0; continue; }
         int fb[3];
 #pragma unroll
         for (int a = 0; a < 3; ++a) fb[a] = crs[a] ? 2 * ci[a] - (face[a] ? 1 : 0) : ci[a];
@@ -404,23 +380,25 @@ __global__ __launch_bounds__(RB_BLOCK) void k_restrict(const RepDev *reps, const
                     if (kk < fc[2] && jj < fc[1] && ii < fc[0])
                         acc = fmad(restrict_weight<T>(crs[0], face[0], ii) * restrict_weight<T>(crs[1], face[1], jj) *
                                        restrict_weight<T>(crs[2], face[2], kk),
-                                   residual_at<T>(R, F, comp, wrap(fb[0] + ii, F.n[0]), wrap(fb[1] + jj, F.n[1]),
-                                                  wrap(fb[2] + kk, F.n[2]), xf, bf),
+                                   rf[wrap(fb[0] + ii, F.n[0]) + F.n[0] * wrap(fb[1] + jj, F.n[1]) +
+                                      f01 * wrap(fb[2] + kk, F.n[2])],
                                    acc);
-        bc[cbase + lin] = acc;
+        bcpool[cbase + lin] = acc;
     }
 }
 
+// B(lev+1) = R (B(lev) - A X(lev)); the residual passes through r (same pool layout).
 template <typename T>
-void launch_restrict(Ctx &c, int lev, int c0, int nc, const T *x, const T *b, T *bcoarse) {
+void launch_restrict(Ctx &c, int lev, int c0, int nc, const T *x, const T *b, T *bcoarse, T *r) {
     if (c.n_tab_lev[lev] == 0) return;
-    // one thread per coarse point: use the table of level lev+1 restricted to replicas descending from lev
+    launch_stencil_any<T, MG_RESID>(c, lev, c0, nc, x, r, b);
+    // one thread per coarse point: the table of level lev+1 restricted to replicas descending from lev
     if (c.mg_npt == 4)
         hipLaunchKernelGGL((k_restrict<T, 4>), dim3(c.n_tab_all[lev + 1], nc), dim3(RB_BLOCK), 0, c.stream,
-                           c.d_reps, c.d_levs, c.d_tab_all[lev + 1], lev, c0, x, b, bcoarse, c.mask);
+                           c.d_reps, c.d_levs, c.d_tab_all[lev + 1], lev, c0, r, bcoarse, c.mask);
     else
         hipLaunchKernelGGL((k_restrict<T, 1>), dim3(c.n_tab_all[lev + 1], nc), dim3(RB_BLOCK), 0, c.stream,
-                           c.d_reps, c.d_levs, c.d_tab_all[lev + 1], lev, c0, x, b, bcoarse, c.mask);
+                           c.d_reps, c.d_levs, c.d_tab_all[lev + 1], lev, c0, r, bcoarse, c.mask);
 }
 
 // x_f += P x_c: face-normal axis linear (even faces copy, odd faces average),
@@ -677,8 +655,8 @@ template void launch_to_level0<float>(Ctx &, const double *, float *, int, int);
 template void launch_to_level0<double>(Ctx &, const double *, double *, int, int);
 template void launch_smooth<float>(Ctx &, int, int, int, const float *, float *, const float *, bool);
 template void launch_smooth<double>(Ctx &, int, int, int, const double *, double *, const double *, bool);
-template void launch_restrict<float>(Ctx &, int, int, int, const float *, const float *, float *);
-template void launch_restrict<double>(Ctx &, int, int, int, const double *, const double *, double *);
+template void launch_restrict<float>(Ctx &, int, int, int, const float *, const float *, float *, float *);
+template void launch_restrict<double>(Ctx &, int, int, int, const double *, const double *, double *, double *);
 template void launch_prolong<float>(Ctx &, int, int, int, const float *, float *);
 template void launch_prolong<double>(Ctx &, int, int, int, const double *, double *);
 template void launch_coarse<float>(Ctx &, int, int, int, const float *, float *);

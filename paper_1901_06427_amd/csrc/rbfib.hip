@@ -245,7 +245,7 @@ static T *vcycle(Ctx &c, int c0, int nc) {
             launch_smooth<T>(c, l, c0, nc, in, out, B, k == 1);
             if (l == 0) record(c, 1, false, sz * c.lev_cells[0] * (k == 1 ? 2.0 : 3.0));
         }
-        launch_restrict<T>(c, l, c0, nc, X, B, B);
+        launch_restrict<T>(c, l, c0, nc, X, B, B, Tt);   // T(l) is free after the down sweeps
     }
     for (int l = c.maxlev - 2; l >= 0; --l) {
         if (c.n_tab_lev[l] == 0) continue;
