@@ -165,7 +165,7 @@ def run_gpu(ws, steps, warmup, fp32, seed=2024, timing=False, graphs=True):
     stats = {}
     if timing:
         for which, name in ((0, "mac_saddle_apply"), (1, "mg_smooth_level0"), (2, "mg_down_level0"),
-                            (3, "mg_up_level0")):
+                            (3, "mg_up_level0"), (4, "krylov_dots"), (5, "krylov_update")):
             avg_ms, nbytes, launches = rb.rbfib_kernel_stats(ctx, which)
             if launches:
                 stats[name] = (avg_ms, nbytes, launches)
@@ -248,7 +248,8 @@ def copy_ceiling():
 
 
 COUNTERS = os.path.join(ROOT, "profiles", "ensemble_256_sem_hbm_counters.md")
-KERNEL_SOURCES = ("paper_1901_06427_amd/csrc/grid.hip", "paper_1901_06427_amd/csrc/common.h")
+KERNEL_SOURCES = ("paper_1901_06427_amd/csrc/grid.hip", "paper_1901_06427_amd/csrc/krylov.hip",
+                  "paper_1901_06427_amd/csrc/common.h")
 
 
 def kernel_source_hash():

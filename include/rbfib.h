@@ -227,8 +227,10 @@ int rbfib_mobility_vjp(rbfib_ctx *ctx, const double *q, const double *theta, con
  * measured with HIP events on the context stream, and its average algorithmic
  * bytes per launch.  which: 0 = fused MAC saddle apply, 1 = level-0 smoother
  * sweep (separate kernels), 2 = level-0 fused down kernel (two sweeps, residual,
- * restriction), 3 = level-0 fused up kernel (prolongation, two sweeps).  Only
- * solves run with timing enabled (rbfib_enable_timing) are counted. */
+ * restriction), 3 = level-0 fused up kernel (prolongation, two sweeps),
+ * 4 = FGMRES dot products of the basis with w (the dot kernel and its reduction),
+ * 5 = FGMRES basis update of w with its norm.  Only solves run with timing enabled
+ * (rbfib_enable_timing) are counted. */
 int rbfib_kernel_stats(rbfib_ctx *ctx, int which, double *avg_ms, double *bytes_per_launch,
                        long long *launches);
 int rbfib_enable_timing(rbfib_ctx *ctx, int on);

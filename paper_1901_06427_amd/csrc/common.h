@@ -28,7 +28,8 @@
 // A level runs fused only with at least this many workgroups (each marches
 // through its z planes, so it needs several resident workgroups per CU).
 #define MGF_MIN_BLOCKS 1024
-#define RB_NTIMING 4           // timing classes: apply, smoother sweep, fused down, fused up (level 0)
+#define RB_NTIMING 6           // timing classes: apply, smoother sweep, fused down, fused up (level 0),
+                               // Krylov dots, Krylov update
 
 namespace rb {
 
@@ -421,10 +422,10 @@ struct Timing {
     bool on = false;
     std::vector<hipEvent_t> ev[RB_NTIMING];
     std::vector<double> ev_bytes[RB_NTIMING];   // algorithmic bytes of each recorded launch
-    size_t used[RB_NTIMING] = {0, 0, 0, 0};
-    double bytes[RB_NTIMING] = {0, 0, 0, 0};
-    long long launches[RB_NTIMING] = {0, 0, 0, 0};
-    double total_ms[RB_NTIMING] = {0, 0, 0, 0};
+    size_t used[RB_NTIMING] = {};
+    double bytes[RB_NTIMING] = {};
+    long long launches[RB_NTIMING] = {};
+    double total_ms[RB_NTIMING] = {};
 };
 
 struct Ctx {
@@ -499,6 +500,7 @@ struct Ctx {
     int *h_count = nullptr;     // pinned
     double *d_resid = nullptr;  // [nrep]
     int *d_count = nullptr;
+    long long *d_active_len = nullptr;   // timing runs: state length of the active replicas
 
     // SEM scratch
     double *q_buf[3] = {nullptr, nullptr, nullptr};      // q+, q-, q_new  [nb, 3]

@@ -290,6 +290,29 @@ static void precond(Ctx &c, MarkerSet &ms, const double *theta, const double *r,
 }
 
 // ------------------------------------------------------------------ FGMRES
+// Total state length of the active replicas (timing runs: algorithmic bytes of the
+// masked Krylov kernels).  One workgroup; fixed summation order.
+__global__ void k_active_len(int nrep, const RepDev *reps, const int *active, long long *out) {
+    __shared__ long long part[256];
+    long long s = 0;
+    for (int r = threadIdx.x; r < nrep; r += blockDim.x) s += active[r] ? reps[r].len : 0;
+    part[threadIdx.x] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        long long t = 0;
+        for (int k = 0; k < (int)blockDim.x; ++k) t += part[k];
+        *out = t;
+    }
+}
+
+static double active_len(Ctx &c) {
+    hipLaunchKernelGGL(k_active_len, dim3(1), dim3(256), 0, c.stream, c.nrep, c.d_reps, c.active, c.d_active_len);
+    long long h = 0;
+    HIP_OK(hipMemcpyAsync(&h, c.d_active_len, sizeof(long long), hipMemcpyDeviceToHost, c.stream));
+    HIP_OK(hipStreamSynchronize(c.stream));
+    return (double)h;
+}
+
 __global__ void k_init_solver(int nrep, int *active, int *status, int *iters, const double *beta0) {
     int r = blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= nrep) return;
@@ -352,7 +375,11 @@ static void fgmres(Ctx &c, MarkerSet &ms, const double *theta, const double *b, 
                     precond(c, ms, theta, Vj, Zj, fluid_only);
                     apply_op(c, ms, Zj, c.W, fluid_only);
                     c.mask = nullptr;
+                    // algorithmic bytes of the masked Krylov kernels: FP64 vectors of the active replicas
+                    const double vb = c.timing.on ? 8.0 * active_len(c) : 0.0;
+                    record(c, 4, true);
                     launch_dots(c, c.V, j + 1, c.W, h1, c.active);
+                    record(c, 4, false, vb * (j + 2));    // read j+1 basis vectors and w
                     if (reorth) {
                         // tight tolerances: second Gram-Schmidt pass keeps the basis
                         // orthogonal to working precision
@@ -360,7 +387,9 @@ static void fgmres(Ctx &c, MarkerSet &ms, const double *theta, const double *b, 
                         launch_dots(c, c.V, j + 1, c.W, h2, c.active);
                         launch_axpy_multi_norm(c, c.V, j + 1, h2, c.W, nrm, c.active);
                     } else {
+                        record(c, 5, true);
                         launch_axpy_multi_norm(c, c.V, j + 1, h1, c.W, nrm, c.active);
+                        record(c, 5, false, vb * (j + 3));    // read j+1 vectors and w, write w
                     }
                     launch_givens(c, j, tol);
                     launch_scale(c, c.W, nrm, c.V + (long long)(j + 1) * c.L, c.active, true);
@@ -872,6 +901,7 @@ static void build(Ctx &c, int nrep, const rbfib_grid *grids, const rbfib_bodies 
     HIP_OK(hipHostMalloc((void **)&c.h_flags, sizeof(int) * std::max(nrep, 4), hipHostMallocDefault));
     HIP_OK(hipHostMalloc((void **)&c.h_count, sizeof(int), hipHostMallocDefault));
     c.d_count = dalloc<int>(1);
+    c.d_active_len = dalloc<long long>(1);
 
     // ---- multigrid pools
     c.mg_fp32 = c.opts.precond_fp32 != 0;
@@ -946,7 +976,7 @@ static void free_all(Ctx &c) {
         F(ms.r); F(ms.d); F(ms.tile); F(ms.perm); F(ms.tile_count); F(ms.tile_start); F(ms.tile_fill);
         F(ms.active); F(ms.flag); F(ms.n_active); F(ms.wc); F(ms.ic);
     }
-    F(c.d_flags); F(c.d_count);
+    F(c.d_flags); F(c.d_count); F(c.d_active_len);
     if (c.h_flags) (void)hipHostFree(c.h_flags);
     if (c.h_count) (void)hipHostFree(c.h_count);
     F(c.V); F(c.Z); F(c.W); F(c.xsol); F(c.rhs); F(c.tmp); F(c.fluid_tmp); F(c.xR); F(c.xS); F(c.partial);
