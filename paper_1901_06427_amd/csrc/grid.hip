@@ -404,16 +404,86 @@ void launch_restrict(Ctx &c, int lev, int c0, int nc, const T *x, const T *b, T 
 // x_f += P x_c: face-normal axis linear (even faces copy, odd faces average),
 // cell-centred axes linear (3/4, 1/4) with odd ghosts for velocity at walls and
 // even ghosts for pressure.
-template <typename T>
-__global__ void k_prolong(const RepDev *reps, const LevDev *levs, const BlockEnt *tab, int lev, int c0,
-                          const T *__restrict__ xc, T *__restrict__ xf, const int *__restrict__ mask) {
+//
+// FP32 path on four consecutive fine x points (rows a multiple of four long, blocks
+// of 1024 points): x_f moves as one float4; the y/z weights are shared; per coarse
+// (y, z) row the four coarse x values the group can use (indices base .. base+3,
+// wrapped or clamped like prolong_axis) are loaded once and picked by index.  The
+// sums run in prolong_at's order, so the values are identical.
+__device__ __forceinline__ void prolong_row4(const RepDev &R, const LevDev &F, const LevDev &C, const BlockEnt &be,
+                                             int comp, const float *__restrict__ xc, float *__restrict__ xf) {
+    const long long g0 = be.start + 4LL * threadIdx.x;
+    if (g0 >= F.N) return;
+    const int lin = (int)g0;
+    int fi[3];
+    unlin(lin, F, fi);
+    const int x0 = fi[0];
+    const bool crsx = F.n[0] != C.n[0];
+    const int base = crsx ? (x0 >> 1) - 1 : x0;
+    int cx[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        int i = base + t;
+        if (R.bc[0] == RBFIB_PERIODIC) i = i < 0 ? i + C.n[0] : (i >= C.n[0] ? i - C.n[0] : i);
+        else i = i < 0 ? 0 : (i >= C.n[0] ? C.n[0] - 1 : i);
+        cx[t] = i;
+    }
+    const ProlongAxis<float> py = prolong_axis<float>(fi[1], F.n[1], C.n[1], R.bc[1], comp == 1, comp);
+    const ProlongAxis<float> pz = prolong_axis<float>(fi[2], F.n[2], C.n[2], R.bc[2], comp == 2, comp);
+    const long long c01 = (long long)C.n[0] * C.n[1];
+    float rowv[2][2][4];
+#pragma unroll
+    for (int kk = 0; kk < 2; ++kk)
+#pragma unroll
+        for (int jj = 0; jj < 2; ++jj) {
+            const bool use = kk < pz.cnt && jj < py.cnt;
+            const long long ro = (long long)C.n[0] * (jj ? py.i1 : py.i0) + c01 * (kk ? pz.i1 : pz.i0);
+#pragma unroll
+            for (int t = 0; t < 4; ++t) rowv[kk][jj][t] = use ? xc[ro + cx[t]] : 0.f;
+        }
+    const float4 v = *reinterpret_cast<const float4 *>(xf + lin);
+    float x4[4] = {v.x, v.y, v.z, v.w};
+    const bool pin_yz = (comp == 1 && R.bc[1] == RBFIB_WALL && fi[1] == 0) ||
+                        (comp == 2 && R.bc[2] == RBFIB_WALL && fi[2] == 0);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        if (pin_yz || (comp == 0 && R.bc[0] == RBFIB_WALL && x0 + q == 0)) continue;
+        const ProlongAxis<float> px = prolong_axis<float>(x0 + q, F.n[0], C.n[0], R.bc[0], comp == 0, comp);
+        float acc = 0.f;
+#pragma unroll
+        for (int kk = 0; kk < 2; ++kk)
+#pragma unroll
+            for (int jj = 0; jj < 2; ++jj)
+#pragma unroll
+                for (int ii = 0; ii < 2; ++ii)
+                    if (kk < pz.cnt && jj < py.cnt && ii < px.cnt) {
+                        const int i = ii ? px.i1 : px.i0;
+                        const float *rv = rowv[kk][jj];
+                        const float cv = i == cx[0] ? rv[0] : (i == cx[1] ? rv[1] : (i == cx[2] ? rv[2] : rv[3]));
+                        acc = fmad((ii ? px.w1 : px.w0) * (jj ? py.w1 : py.w0) * (kk ? pz.w1 : pz.w0), cv, acc);
+                    }
+        x4[q] += acc;
+    }
+    *reinterpret_cast<float4 *>(xf + lin) = make_float4(x4[0], x4[1], x4[2], x4[3]);
+}
+
+template <typename T, int NPT>
+__global__ __launch_bounds__(RB_BLOCK) void k_prolong(const RepDev *reps, const LevDev *levs, const BlockEnt *tab,
+                                                      int lev, int c0, const T *__restrict__ xc, T *__restrict__ xf,
+                                                      const int *__restrict__ mask) {
     BlockEnt be = tab[xcd_block(blockIdx.x, gridDim.x)];
     if (mask && !mask[be.rep]) return;
     int comp = c0 + blockIdx.y;
     const RepDev &R = reps[be.rep];
     const LevDev &F = levs[be.rep * RB_MAXLEV + lev];
     const LevDev &C = levs[be.rep * RB_MAXLEV + lev + 1];
-    for (int t_ = 0; t_ < be.npt; ++t_) {
+    if constexpr (sizeof(T) == 4 && NPT == 4) {
+        if (F.n[0] % 4 == 0) {    // uniform per block
+            prolong_row4(R, F, C, be, comp, (const float *)(xc + C.off + comp * C.N), (float *)(xf + F.off + comp * F.N));
+            return;
+        }
+    }
+    for (int t_ = 0; t_ < NPT; ++t_) {
     long long lin = be.start + threadIdx.x + (long long)t_ * RB_BLOCK;
     if (lin >= F.N) continue;
     int fi[3];
@@ -427,8 +497,12 @@ __global__ void k_prolong(const RepDev *reps, const LevDev *levs, const BlockEnt
 template <typename T>
 void launch_prolong(Ctx &c, int lev, int c0, int nc, const T *xc, T *xf) {
     if (c.n_tab_lev[lev] == 0) return;
-    hipLaunchKernelGGL(k_prolong<T>, dim3(c.n_tab_lev[lev], nc), dim3(RB_BLOCK), 0, c.stream, c.d_reps, c.d_levs,
-                       c.d_tab_lev[lev], lev, c0, xc, xf, c.mask);
+    if (c.mg_npt == 4)
+        hipLaunchKernelGGL((k_prolong<T, 4>), dim3(c.n_tab_lev[lev], nc), dim3(RB_BLOCK), 0, c.stream, c.d_reps,
+                           c.d_levs, c.d_tab_lev[lev], lev, c0, xc, xf, c.mask);
+    else
+        hipLaunchKernelGGL((k_prolong<T, 1>), dim3(c.n_tab_lev[lev], nc), dim3(RB_BLOCK), 0, c.stream, c.d_reps,
+                           c.d_levs, c.d_tab_lev[lev], lev, c0, xc, xf, c.mask);
 }
 
 // Dense coarsest solve x = Ainv b, one workgroup per (replica, component).
