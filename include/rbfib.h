@@ -114,6 +114,7 @@ typedef struct {
     int max_iter;              /* total iteration cap (600)                          */
     int precond_fp32;          /* 1: multigrid preconditioner in FP32 (0)            */
     int mg_sweeps;             /* damped-Jacobi sweeps before and after (3)          */
+    int mg_sweeps_p;           /* the same for the pressure cycle; 0: mg_sweeps (4)  */
     double mg_omega;           /* Jacobi damping (0.9)                               */
     double blob_radius;        /* blob radius of the body block, units of h (1.25)   */
     double rfd_delta;          /* random-finite-difference delta (1e-5)              */

@@ -48,7 +48,8 @@ class rbfib_bodies(ctypes.Structure):
 
 class rbfib_opts(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("restart", ctypes.c_int), ("max_iter", ctypes.c_int),
-                ("precond_fp32", ctypes.c_int), ("mg_sweeps", ctypes.c_int), ("mg_omega", ctypes.c_double),
+                ("precond_fp32", ctypes.c_int), ("mg_sweeps", ctypes.c_int), ("mg_sweeps_p", ctypes.c_int),
+                ("mg_omega", ctypes.c_double),
                 ("blob_radius", ctypes.c_double), ("rfd_delta", ctypes.c_double),
                 ("min_body_dist", ctypes.c_double), ("check_every", ctypes.c_int), ("use_graphs", ctypes.c_int),
                 ("mg_fused", ctypes.c_int)]

@@ -220,7 +220,8 @@ template <typename T>
 static T *vcycle(Ctx &c, int c0, int nc) {
     T *X = (T *)c.mg_x, *B = (T *)c.mg_b, *Tt = (T *)c.mg_t;
     const double sz = (double)sizeof(T) * nc;
-    const int nu = std::max(1, c.opts.mg_sweeps);
+    // pressure cycles (c0 == 3) may use their own sweep count
+    const int nu = std::max(1, (c0 == 3 && c.opts.mg_sweeps_p > 0) ? c.opts.mg_sweeps_p : c.opts.mg_sweeps);
     bool fz[RB_MAXLEV];
     T *res[RB_MAXLEV];
     for (int l = 0; l < c.maxlev; ++l) {
@@ -1013,6 +1014,7 @@ void rbfib_default_opts(rbfib_opts *o) {
     o->max_iter = 600;
     o->precond_fp32 = 0;
     o->mg_sweeps = 3;
+    o->mg_sweeps_p = 4;
     o->mg_omega = 0.9;
     o->blob_radius = 1.25;
     o->rfd_delta = 1e-5;
@@ -1085,7 +1087,8 @@ int rbfib_set_opts(rbfib_ctx *ctx, const rbfib_opts *o) {
     // fields fixed at creation: restart length, precision, blob radius
     if (o->restart != c.opts.restart || (o->precond_fp32 != 0) != c.mg_fp32 || o->blob_radius != c.opts.blob_radius)
         return RBFIB_EINVAL;
-    if (o->mg_sweeps != c.opts.mg_sweeps || o->mg_omega != c.opts.mg_omega || o->mg_fused != c.opts.mg_fused)
+    if (o->mg_sweeps != c.opts.mg_sweeps || o->mg_sweeps_p != c.opts.mg_sweeps_p || o->mg_omega != c.opts.mg_omega ||
+        o->mg_fused != c.opts.mg_fused)
         drop_graphs(c);
     c.opts = *o;
     return RBFIB_OK;
