@@ -129,6 +129,7 @@ RESTART = 0       # 0: the library default
 SWEEPS = 0        # 0: the library default
 OMEGA = 0.0       # 0: the library default
 PSWEEPS = 0       # 0: the library default
+BLOB = 0.0        # 0: the library default
 
 
 def run_gpu(ws, steps, warmup, fp32, seed=2024, timing=False, graphs=True):
@@ -139,7 +140,7 @@ def run_gpu(ws, steps, warmup, fp32, seed=2024, timing=False, graphs=True):
     ctx = lib_context(rb, ws, tol=ws[0].tol, precond_fp32=fp32, use_graphs=int(graphs and not timing),
                       mg_fused=MG_FUSED, **({"restart": RESTART} if RESTART else {}),
                       **({"mg_sweeps": SWEEPS} if SWEEPS else {}), **({"mg_omega": OMEGA} if OMEGA else {}),
-                      **({"mg_sweeps_p": PSWEEPS} if PSWEEPS else {}))
+                      **({"mg_sweeps_p": PSWEEPS} if PSWEEPS else {}), **({"blob_radius": BLOB} if BLOB else {}))
     U = torch.empty((E.nb, 6), dtype=torch.float64, device="cuda")
     step_id = 0
     iters = 0
@@ -310,18 +311,21 @@ def main():
     ap.add_argument("--mg-sweeps", type=int, default=0, help="damped-Jacobi sweeps per level (0: library default)")
     ap.add_argument("--mg-omega", type=float, default=0.0, help="Jacobi damping (0: library default)")
     ap.add_argument("--mg-sweeps-p", type=int, default=0, help="pressure-cycle sweeps (0: library default)")
+    ap.add_argument("--blob-radius", type=float, default=0.0,
+                    help="blob radius of the body-block preconditioner, units of h (0: library default)")
     ap.add_argument("--batched-only", action="store_true",
                     help="only the batched ensemble launches (the command the graph-mode trace is taken on)")
     ap.add_argument("--mg-fused", type=int, default=0, choices=(0, 1, 2),
                     help="multigrid level kernels: 0 separate (default), 1 fused where the level fills the "
                          "device, 2 fused on every level")
     args = ap.parse_args()
-    global MG_FUSED, RESTART, SWEEPS, OMEGA, PSWEEPS
+    global MG_FUSED, RESTART, SWEEPS, OMEGA, PSWEEPS, BLOB
     MG_FUSED = args.mg_fused
     RESTART = args.restart
     SWEEPS = args.mg_sweeps
     OMEGA = args.mg_omega
     PSWEEPS = args.mg_sweeps_p
+    BLOB = args.blob_radius
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU: every box here has a single MI355X, and the replicas of the "
               "ensemble share one device; run with --gpus 1.", file=sys.stderr)

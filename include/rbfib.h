@@ -116,7 +116,7 @@ typedef struct {
     int mg_sweeps;             /* damped-Jacobi sweeps before and after (3)          */
     int mg_sweeps_p;           /* the same for the pressure cycle; 0: mg_sweeps (4)  */
     double mg_omega;           /* Jacobi damping (0.9)                               */
-    double blob_radius;        /* blob radius of the body block, units of h (1.25)   */
+    double blob_radius;        /* blob radius of the body block, units of h (1.2)    */
     double rfd_delta;          /* random-finite-difference delta (1e-5)              */
     double min_body_dist;      /* rejection distance between body centres (0 = off)  */
     int check_every;           /* iterations between host convergence checks (5)    */

@@ -1016,7 +1016,7 @@ void rbfib_default_opts(rbfib_opts *o) {
     o->mg_sweeps = 3;
     o->mg_sweeps_p = 4;
     o->mg_omega = 0.9;
-    o->blob_radius = 1.25;
+    o->blob_radius = 1.2;
     o->rfd_delta = 1e-5;
     o->min_body_dist = 0.0;
     o->check_every = 5;
