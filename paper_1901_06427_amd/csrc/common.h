@@ -493,7 +493,7 @@ struct Ctx {
     // Krylov
     int m = 0;
     double *V = nullptr, *Z = nullptr, *W = nullptr;
-    double *xsol = nullptr, *rhs = nullptr, *tmp = nullptr, *fluid_tmp = nullptr;
+    double *xsol = nullptr, *rhs = nullptr, *tmp = nullptr;
     double *partial = nullptr;  // [n_tab_vec * (m+1)]
     double *H = nullptr, *cs = nullptr, *sn = nullptr, *gv = nullptr, *beta0 = nullptr, *hcol = nullptr, *yv = nullptr;
     int *active = nullptr, *cyc_active = nullptr, *jf = nullptr, *status = nullptr, *iters = nullptr;
@@ -531,6 +531,7 @@ void launch_wall_rhs(Ctx &c, double *f);
 // immersed boundary and bodies (ib.hip)
 void launch_markers(Ctx &c, MarkerSet &ms, const double *q, const double *theta);
 void launch_spread(Ctx &c, MarkerSet &ms, const double *lam, double *y, double alpha);
+template <typename T> void launch_spread_level0(Ctx &c, MarkerSet &ms, const double *lam, T *pool, double alpha);
 void launch_body_apply(Ctx &c, MarkerSet &ms, const double *q, const double *x, double *y);
 void launch_body_precond(Ctx &c, MarkerSet &ms, const double *theta, const double *r, double *z);
 void launch_interp(Ctx &c, MarkerSet &ms, const double *x, double *out, double alpha, bool accumulate);

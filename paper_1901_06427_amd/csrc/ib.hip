@@ -198,13 +198,16 @@ void launch_markers(Ctx &c, MarkerSet &ms, const double *q, const double *theta)
 
 // ------------------------------------------------------------------ spreading (gather)
 #define SP_CHUNK 64
+// TO = double: y is a state vector (velocity of replica r at R.off + c N);
+// TO = float / double with levs given: y is a multigrid pool, level 0 of each replica.
+template <typename TO>
 __global__ __launch_bounds__(256) void k_spread(const RepDev *reps, const int *tile_rep, const int *active,
                                                 const int *n_active, const int *tile_start, const int *tile_count,
                                                 const int *perm, const double *__restrict__ r,
                                                 const double *__restrict__ lam_state, const int *marker_body,
-                                                const int *body_rep, double *__restrict__ y, double alpha,
+                                                const int *body_rep, TO *__restrict__ y, double alpha,
                                                 const int *__restrict__ mask, const double *__restrict__ wc,
-                                                const int *__restrict__ ic) {
+                                                const int *__restrict__ ic, const LevDev *__restrict__ levs) {
     __shared__ double Wt[SP_CHUNK][3][3][4];
     __shared__ double Ls[SP_CHUNK][3];
     __shared__ int Ms[SP_CHUNK];
@@ -289,7 +292,8 @@ __global__ __launch_bounds__(256) void k_spread(const RepDev *reps, const int *t
             bool pin = R.bc[c] == RBFIB_WALL && g[c] == 0;
             if (in && !pin) {
                 long long lin = (long long)g[0] + (long long)R.n[0] * ((long long)g[1] + (long long)R.n[1] * g[2]);
-                y[R.off + c * R.N + lin] += alpha * acc / R.dV;
+                const long long o = levs ? levs[tile_rep[t] * RB_MAXLEV].off : R.off;
+                y[o + c * R.N + lin] += (TO)(alpha * acc / R.dV);
             }
         }
         __syncthreads();
@@ -300,10 +304,22 @@ __global__ __launch_bounds__(256) void k_spread(const RepDev *reps, const int *t
 void launch_spread(Ctx &c, MarkerSet &ms, const double *lam_state, double *y, double alpha) {
     if (c.nm == 0) return;
     int grid = std::min(c.ntiles, 32768);   // grid-stride over the active tiles
-    hipLaunchKernelGGL(k_spread, dim3(grid), dim3(256), 0, c.stream, c.d_reps, c.d_tile_rep, ms.active, ms.n_active,
-                       ms.tile_start, ms.tile_count, ms.perm, ms.r, lam_state, c.d_marker_body, c.d_body_rep, y,
-                       alpha, c.mask, ms.wc, ms.ic);
+    hipLaunchKernelGGL(k_spread<double>, dim3(grid), dim3(256), 0, c.stream, c.d_reps, c.d_tile_rep, ms.active,
+                       ms.n_active, ms.tile_start, ms.tile_count, ms.perm, ms.r, lam_state, c.d_marker_body,
+                       c.d_body_rep, y, alpha, c.mask, ms.wc, ms.ic, (const LevDev *)nullptr);
 }
+
+// Level 0 of the multigrid pool (velocity components) += alpha * S lambda.
+template <typename T>
+void launch_spread_level0(Ctx &c, MarkerSet &ms, const double *lam_state, T *pool, double alpha) {
+    if (c.nm == 0) return;
+    int grid = std::min(c.ntiles, 32768);
+    hipLaunchKernelGGL(k_spread<T>, dim3(grid), dim3(256), 0, c.stream, c.d_reps, c.d_tile_rep, ms.active,
+                       ms.n_active, ms.tile_start, ms.tile_count, ms.perm, ms.r, lam_state, c.d_marker_body,
+                       c.d_body_rep, pool, alpha, c.mask, ms.wc, ms.ic, (const LevDev *)c.d_levs);
+}
+template void launch_spread_level0<float>(Ctx &, MarkerSet &, const double *, float *, double);
+template void launch_spread_level0<double>(Ctx &, MarkerSet &, const double *, double *, double);
 
 // ------------------------------------------------------------------ J, K, K^T per body
 // y_lambda = -J v + K U ;  y_U = K^T lambda  (rows 3 and 4 of the saddle operator).

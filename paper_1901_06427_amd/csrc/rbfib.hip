@@ -273,12 +273,13 @@ template <typename T>
 static void precond_t(Ctx &c, MarkerSet &ms, const double *theta, const double *r, double *z, bool fluid_only) {
     bool bodies = !fluid_only && c.nb > 0;
     if (bodies) launch_body_precond(c, ms, theta, r, z);
-    launch_copy(c, r, c.fluid_tmp, c.mask);
-    if (bodies) launch_spread(c, ms, z, c.fluid_tmp, 1.0);
+    // Velocity right-hand side r_v + S lambda built straight in level 0 of the pool;
+    // the divergence step reads only the pressure part of r, which spreading leaves alone.
     T *B = (T *)c.mg_b;
-    launch_to_level0<T>(c, c.fluid_tmp, B, 0, 3);
+    launch_to_level0<T>(c, r, B, 0, 3);
+    if (bodies) launch_spread_level0<T>(c, ms, z, B, 1.0);
     T *V = vcycle<T>(c, 0, 3);
-    launch_proj_div<T>(c, V, c.fluid_tmp, B, z);
+    launch_proj_div<T>(c, V, r, B, z);
     T *P = vcycle<T>(c, 3, 1);
     launch_proj_correct<T>(c, V, P, z);
     if (!bodies) launch_zero_bodies(c, z);
@@ -923,7 +924,6 @@ static void build(Ctx &c, int nrep, const rbfib_grid *grids, const rbfib_bodies 
     c.xsol = dalloc<double>(L);
     c.rhs = dalloc<double>(L);
     c.tmp = dalloc<double>(L);
-    c.fluid_tmp = dalloc<double>(L);
     c.xR = dalloc<double>(L);
     c.xS = dalloc<double>(L);
     c.partial = dalloc<double>((size_t)c.n_tab_vec * (c.m + 1));
@@ -980,7 +980,7 @@ static void free_all(Ctx &c) {
     F(c.d_flags); F(c.d_count); F(c.d_active_len);
     if (c.h_flags) (void)hipHostFree(c.h_flags);
     if (c.h_count) (void)hipHostFree(c.h_count);
-    F(c.V); F(c.Z); F(c.W); F(c.xsol); F(c.rhs); F(c.tmp); F(c.fluid_tmp); F(c.xR); F(c.xS); F(c.partial);
+    F(c.V); F(c.Z); F(c.W); F(c.xsol); F(c.rhs); F(c.tmp); F(c.xR); F(c.xS); F(c.partial);
     F(c.H); F(c.cs); F(c.sn); F(c.gv); F(c.beta0); F(c.hcol); F(c.yv); F(c.d_resid);
     F(c.active); F(c.cyc_active); F(c.jf); F(c.status); F(c.iters);
     for (int k = 0; k < 3; ++k) { F(c.q_buf[k]); F(c.th_buf[k]); }
