@@ -411,8 +411,14 @@ struct MarkerSet {
     int *tile = nullptr;      // [nm] global tile
     int *perm = nullptr;      // [nm] global marker ids sorted by tile
     int *tile_count = nullptr, *tile_start = nullptr, *tile_fill = nullptr;
-    int *active = nullptr;    // [ntiles] compacted active target tiles
+    int *active = nullptr;    // [ntiles] compacted tiles that have spreading pairs
     int *n_active = nullptr;  // device scalar
+    // spreading pairs (target tile, marker), by tile then marker id; capacity pair_cap
+    int *pair_count = nullptr, *pair_start = nullptr, *pair_fill = nullptr;   // [ntiles]
+    int *pair_m = nullptr, *pair_tile = nullptr;                              // [pair_cap]
+    double *pair_w = nullptr;      // [pair_cap][3 comp][3 axis][4] weights on the tile's window
+    long long *pair_lam = nullptr; // [pair_cap] offset of the marker's lambda in a state vector
+    long long pair_cap = 0;
     int *flag = nullptr;      // [ntiles] scratch
     double *wc = nullptr;     // [nm][3 comp][3 axis][4] folded signed 1-D kernel weights
     int *ic = nullptr;        // [nm][3][3][4] folded grid indices of those weights

@@ -1,9 +1,9 @@
 // Immersed-boundary and rigid-body kernels (paper Sec. III.B, III.C):
 //   * marker geometry r_i = q_p + R(theta_p) r_i^ref and binning into 4^3-cell tiles;
-//   * spreading S as a deterministic GATHER: one workgroup per target tile pulls the
-//     markers of the (up to) 27 neighbouring tiles into LDS, folds their 4-point
-//     kernel weights onto the tile's 4-wide window per axis, and each thread owns
-//     one target face -- no atomics, fixed summation order;
+//   * spreading S as a deterministic GATHER: per marker configuration, a list of
+//     (tile, marker) pairs with the marker's 4-point weights folded onto the tile's
+//     4-cell window per axis; per application one workgroup per tile sums its pairs
+//     in marker order, one thread per target face -- no atomics;
 //   * interpolation J fused with K U and K^T lambda, one workgroup per body;
 //   * the per-body block of the preconditioner (dense body-frame blob mobility).
 // Walls fold the kernel support by odd reflection so that J = dV S^* holds exactly.
@@ -103,11 +103,13 @@ __global__ void k_tile_place(const int *tile, const int *start, int *fill, int *
     perm[slot] = m;
 }
 
-// insertion sort of each tile's markers by id: a stable (tile, id) order
-__global__ void k_tile_sort(const int *start, const int *count, int *perm, int ntiles) {
+// insertion sort of each tile's entries by id: a stable (tile, id) order; entries at
+// or beyond cap (never written) are left out
+__global__ void k_tile_sort(const int *start, const int *count, int *perm, int ntiles, long long cap) {
     int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= ntiles) return;
-    int b = start[t], n = count[t];
+    int b = start[t];
+    int n = (int)min((long long)count[t], cap - b);
     for (int i = 1; i < n; ++i) {
         int v = perm[b + i];
         int j = i - 1;
@@ -116,46 +118,114 @@ __global__ void k_tile_sort(const int *start, const int *count, int *perm, int n
     }
 }
 
-// neighbour tile offsets along one axis (deduplicated for short periodic axes)
-__device__ __forceinline__ int axis_neighbours(int t, int T, int bc, int out[3]) {
-    int k = 0;
-    if (bc == RBFIB_PERIODIC) {
-        if (T >= 3) { out[k++] = (t + T - 1) % T; out[k++] = t; out[k++] = (t + 1) % T; }
-        else if (T == 2) { out[k++] = t; out[k++] = 1 - t; }
-        else out[k++] = t;
-    } else {
-        for (int o = -1; o <= 1; ++o) if (t + o >= 0 && t + o < T) out[k++] = t + o;
-    }
-    return k;
+// ------------------------------------------------------------------ spreading pairs
+// Spreading is built once per marker configuration as a list of (target tile,
+// marker) pairs, sorted by tile and, within a tile, by marker id.  A marker pairs
+// with every tile that holds, on each axis, a nonzero folded weight of one of its
+// three staggered components.  The union of the three 4-point supports along an
+// axis covers at most five consecutive cells (wrapped on periodic axes, folded into
+// the domain at walls), so it meets at most two 4-cell tiles, three where a periodic
+// axis ends in a partial tile.  Each pair carries the marker's 1-D weights folded
+// onto the tile's 4-cell window per component and axis.
+struct AxisTiles {
+    int k = 0, t0 = 0, t1 = 0, t2 = 0;
+};
+
+__device__ __forceinline__ void add_tile(AxisTiles &s, int t, bool &over) {
+    if ((s.k > 0 && s.t0 == t) || (s.k > 1 && s.t1 == t) || (s.k > 2 && s.t2 == t)) return;
+    if (s.k == 0) s.t0 = t;
+    else if (s.k == 1) s.t1 = t;
+    else if (s.k == 2) s.t2 = t;
+    else { over = true; return; }
+    ++s.k;
 }
 
-// The o-th entry (o = 0, 1, 2) of axis_neighbours(t, T, bc); false when there is none.
-__device__ __forceinline__ bool tile_neighbour(int t, int T, int bc, int o, int &out) {
-    if (bc == RBFIB_PERIODIC) {
-        if (T >= 3) { out = o == 0 ? (t + T - 1) % T : (o == 1 ? t : (t + 1) % T); return true; }
-        if (T == 2) { out = o == 0 ? t : 1 - t; return o < 2; }
-        out = t;
-        return o == 0;
-    }
-    const int first = t > 0 ? t - 1 : 0, last = t + 1 < T ? t + 1 : T - 1;
-    out = first + o;
-    return out <= last;
+__device__ __forceinline__ int tile_at(const AxisTiles &s, int i) { return i == 0 ? s.t0 : (i == 1 ? s.t1 : s.t2); }
+
+__device__ __forceinline__ AxisTiles marker_axis_tiles(const double *wc, const int *ic, int m, int a, bool &over) {
+    AxisTiles s;
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const long long o = ((long long)(3 * m + c) * 3 + a) * 4 + q;
+            if (wc[o] != 0.0) add_tile(s, ic[o] / RB_TILE, over);
+        }
+    return s;
 }
 
-__global__ void k_tile_active(const RepDev *reps, const int *tile_rep, const int *count, int *flag, int ntiles) {
-    int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= ntiles) return;
+// place = 0: count the pairs of each tile; place = 1: write them into the slots
+// given by the exclusive scan of the counts (unordered within a tile).  A marker
+// whose supports break the bound above (non-finite position) or a slot beyond the
+// capacity flags its replica.
+__global__ void k_pair_tiles(const RepDev *reps, const int *marker_body, const int *body_rep, const double *wc,
+                             const int *ic, int nm, int place, int *pair_count, const int *pair_start, int *pair_fill,
+                             int *pair_m, int *pair_tile, long long cap, int *flags) {
+    int m = blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= nm) return;
+    const int rep = body_rep[marker_body[m]];
+    const RepDev &R = reps[rep];
+    bool over = false;
+    const AxisTiles X = marker_axis_tiles(wc, ic, m, 0, over);
+    const AxisTiles Y = marker_axis_tiles(wc, ic, m, 1, over);
+    const AxisTiles Z = marker_axis_tiles(wc, ic, m, 2, over);
+    for (int z = 0; z < Z.k; ++z)
+        for (int y = 0; y < Y.k; ++y)
+            for (int x = 0; x < X.k; ++x) {
+                const int t = R.tile0 + tile_at(X, x) + R.tdim[0] * (tile_at(Y, y) + R.tdim[1] * tile_at(Z, z));
+                if (!place) {
+                    atomicAdd(&pair_count[t], 1);
+                } else {
+                    const long long s = (long long)pair_start[t] + atomicAdd(&pair_fill[t], 1);
+                    if (s < cap) { pair_m[s] = m; pair_tile[s] = t; }
+                    else over = true;
+                }
+            }
+    if (over) atomicOr(&flags[rep], 1);
+}
+
+// Folded weights of each pair on its tile's window, [pair][component][axis][4], and
+// the offset of the marker's lambda in a state vector.
+__global__ void k_pair_weights(const RepDev *reps, const int *tile_rep, const double *wc, const int *ic,
+                               const int *pair_start, const int *pair_count, int ntiles, const int *pair_m,
+                               const int *pair_tile, long long cap, double *pair_w, long long *pair_lam) {
+    const long long s = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    const long long total = (long long)pair_start[ntiles - 1] + pair_count[ntiles - 1];
+    if (s >= total || s >= cap) return;
+    const int t = pair_tile[s], m = pair_m[s];
     const RepDev &R = reps[tile_rep[t]];
-    int lt = t - R.tile0;
-    int tc[3] = {lt % R.tdim[0], (lt / R.tdim[0]) % R.tdim[1], lt / (R.tdim[0] * R.tdim[1])};
-    int nb[3][3], k[3];
-    for (int a = 0; a < 3; ++a) k[a] = axis_neighbours(tc[a], R.tdim[a], R.bc[a], nb[a]);
-    int f = 0;
-    for (int z = 0; z < k[2] && !f; ++z)
-        for (int y = 0; y < k[1] && !f; ++y)
-            for (int x = 0; x < k[0] && !f; ++x)
-                if (count[R.tile0 + nb[0][x] + R.tdim[0] * (nb[1][y] + R.tdim[1] * nb[2][z])] > 0) f = 1;
-    flag[t] = f;
+    const int lt = t - R.tile0;
+    const int tc0 = lt % R.tdim[0], tc1 = (lt / R.tdim[0]) % R.tdim[1], tc2 = lt / (R.tdim[0] * R.tdim[1]);
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const int w0 = RB_TILE * (a == 0 ? tc0 : (a == 1 ? tc1 : tc2));
+            const long long o = ((long long)(3 * m + c) * 3 + a) * 4;
+            double o0 = 0.0, o1 = 0.0, o2 = 0.0, o3 = 0.0;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const double w = wc[o + q];
+                const int loc = ic[o + q] - w0;
+                if (w != 0.0) {
+                    if (loc == 0) o0 += w;
+                    else if (loc == 1) o1 += w;
+                    else if (loc == 2) o2 += w;
+                    else if (loc == 3) o3 += w;
+                }
+            }
+            double *dst = pair_w + s * 36 + (c * 3 + a) * 4;
+            dst[0] = o0;
+            dst[1] = o1;
+            dst[2] = o2;
+            dst[3] = o3;
+        }
+    pair_lam[s] = R.off + 4 * R.N + 3LL * (m - R.m0);
+}
+
+__global__ void k_tile_flag(const int *count, int *flag, int ntiles) {
+    int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < ntiles) flag[t] = count[t] > 0;
 }
 
 // stable compaction of flagged tiles (one workgroup)
@@ -179,6 +249,7 @@ __global__ void k_compact(const int *flag, int *list, int *n_out, int ntiles) {
 
 void launch_markers(Ctx &c, MarkerSet &ms, const double *q, const double *theta) {
     HIP_OK(hipMemsetAsync(ms.tile_count, 0, sizeof(int) * c.ntiles, c.stream));
+    HIP_OK(hipMemsetAsync(ms.pair_count, 0, sizeof(int) * c.ntiles, c.stream));
     int nb = (c.nm + 255) / 256;
     if (c.nm > 0)
         hipLaunchKernelGGL(k_markers, dim3(nb), dim3(256), 0, c.stream, c.d_reps, c.d_marker_body, c.d_body_rep, q,
@@ -189,134 +260,91 @@ void launch_markers(Ctx &c, MarkerSet &ms, const double *q, const double *theta)
         hipLaunchKernelGGL(k_tile_place, dim3(nb), dim3(256), 0, c.stream, ms.tile, ms.tile_start, ms.tile_fill,
                            ms.perm, c.nm);
         hipLaunchKernelGGL(k_tile_sort, dim3((c.ntiles + 255) / 256), dim3(256), 0, c.stream, ms.tile_start,
-                           ms.tile_count, ms.perm, c.ntiles);
+                           ms.tile_count, ms.perm, c.ntiles, (long long)c.nm);
+        hipLaunchKernelGGL(k_pair_tiles, dim3(nb), dim3(256), 0, c.stream, c.d_reps, c.d_marker_body, c.d_body_rep,
+                           ms.wc, ms.ic, c.nm, 0, ms.pair_count, ms.pair_start, ms.pair_fill, ms.pair_m,
+                           ms.pair_tile, ms.pair_cap, c.d_flags);
     }
-    hipLaunchKernelGGL(k_tile_active, dim3((c.ntiles + 255) / 256), dim3(256), 0, c.stream, c.d_reps, c.d_tile_rep,
-                       ms.tile_count, ms.flag, c.ntiles);
+    hipLaunchKernelGGL(k_tile_scan, dim3(1), dim3(1024), 0, c.stream, ms.pair_count, ms.pair_start, ms.pair_fill,
+                       c.ntiles);
+    if (c.nm > 0) {
+        hipLaunchKernelGGL(k_pair_tiles, dim3(nb), dim3(256), 0, c.stream, c.d_reps, c.d_marker_body, c.d_body_rep,
+                           ms.wc, ms.ic, c.nm, 1, ms.pair_count, ms.pair_start, ms.pair_fill, ms.pair_m,
+                           ms.pair_tile, ms.pair_cap, c.d_flags);
+        hipLaunchKernelGGL(k_tile_sort, dim3((c.ntiles + 255) / 256), dim3(256), 0, c.stream, ms.pair_start,
+                           ms.pair_count, ms.pair_m, c.ntiles, ms.pair_cap);
+        hipLaunchKernelGGL(k_pair_weights, dim3((unsigned)((ms.pair_cap + 255) / 256)), dim3(256), 0, c.stream,
+                           c.d_reps, c.d_tile_rep, ms.wc, ms.ic, ms.pair_start, ms.pair_count, c.ntiles, ms.pair_m,
+                           ms.pair_tile, ms.pair_cap, ms.pair_w, ms.pair_lam);
+    }
+    hipLaunchKernelGGL(k_tile_flag, dim3((c.ntiles + 255) / 256), dim3(256), 0, c.stream, ms.pair_count, ms.flag,
+                       c.ntiles);
     hipLaunchKernelGGL(k_compact, dim3(1), dim3(1024), 0, c.stream, ms.flag, ms.active, ms.n_active, c.ntiles);
 }
 
 // ------------------------------------------------------------------ spreading (gather)
-#define SP_CHUNK 64
+// One workgroup per tile that has pairs, one wave per velocity component, one lane
+// per face of the tile: the face sums the tensor-product weights times lambda over
+// the tile's pairs in marker order (no atomics, fixed summation order).
 // TO = double: y is a state vector (velocity of replica r at R.off + c N);
-// TO = float / double with levs given: y is a multigrid pool, level 0 of each replica.
+// with levs given: y is a multigrid pool, level 0 of each replica.
 template <typename TO>
-__global__ __launch_bounds__(256) void k_spread(const RepDev *reps, const int *tile_rep, const int *active,
-                                                const int *n_active, const int *tile_start, const int *tile_count,
-                                                const int *perm, const double *__restrict__ r,
-                                                const double *__restrict__ lam_state, const int *marker_body,
-                                                const int *body_rep, TO *__restrict__ y, double alpha,
-                                                const int *__restrict__ mask, const double *__restrict__ wc,
-                                                const int *__restrict__ ic, const LevDev *__restrict__ levs) {
-    __shared__ double Wt[SP_CHUNK][3][3][4];
-    __shared__ double Ls[SP_CHUNK][3];
-    __shared__ int Ms[SP_CHUNK];
-    __shared__ int nstart[27], ncnt[27], npre[28];
-    __shared__ int nn;
-    int tid = threadIdx.x;
-    int na = *n_active;
+__global__ __launch_bounds__(192) void k_spread(const RepDev *reps, const int *tile_rep, const int *active,
+                                                const int *n_active, const int *pair_start, const int *pair_count,
+                                                long long cap, const double *__restrict__ pair_w,
+                                                const long long *__restrict__ pair_lam,
+                                                const double *__restrict__ lam_state, TO *__restrict__ y,
+                                                double alpha, const int *__restrict__ mask,
+                                                const LevDev *__restrict__ levs) {
+    const int tid = threadIdx.x;
+    const int c = tid >> 6, lx = tid & 3, ly = (tid >> 2) & 3, lz = (tid >> 4) & 3;
+    const int na = *n_active;
     for (int it = blockIdx.x; it < na; it += gridDim.x) {
-        int t = active[it];
-        if (mask && !mask[tile_rep[t]]) continue;
-        const RepDev &R = reps[tile_rep[t]];
-        int lt = t - R.tile0;
-        int tc[3] = {lt % R.tdim[0], (lt / R.tdim[0]) % R.tdim[1], lt / (R.tdim[0] * R.tdim[1])};
-        // source tiles: slot x + 3 (y + 3 z) holds the x-th, y-th, z-th neighbour of
-        // axis_neighbours (empty when that axis has fewer), loaded by 27 threads at once;
-        // the non-empty slots keep the order of the axis_neighbours enumeration
-        if (tid < 27) {
-            const int o[3] = {tid % 3, (tid / 3) % 3, tid / 9};
-            bool ok = true;
-            int nbt[3];
-#pragma unroll
-            for (int a = 0; a < 3; ++a) ok = tile_neighbour(tc[a], R.tdim[a], R.bc[a], o[a], nbt[a]) && ok;
-            int st = 0, ct = 0;
-            if (ok) {
-                const int g = R.tile0 + nbt[0] + R.tdim[0] * (nbt[1] + R.tdim[1] * nbt[2]);
-                st = tile_start[g];
-                ct = tile_count[g];
-            }
-            nstart[tid] = st;
-            ncnt[tid] = ct;
-        }
-        __syncthreads();
-        if (tid == 0) {
-            npre[0] = 0;
-            for (int k = 0; k < 27; ++k) npre[k + 1] = npre[k] + ncnt[k];
-            nn = 27;
-        }
-        __syncthreads();
-        int M = npre[nn];
-        int c = tid >> 6, lx = tid & 3, ly = (tid >> 2) & 3, lz = (tid >> 4) & 3;
+        const int t = active[it];
+        const int rep = tile_rep[t];
+        if (mask && !mask[rep]) continue;
+        const RepDev &R = reps[rep];
+        const long long s0 = pair_start[t];
+        const long long s1 = min(s0 + (long long)pair_count[t], cap);
         double acc = 0.0;
-        for (int base = 0; base < M; base += SP_CHUNK) {
-            int cnt = min(SP_CHUNK, M - base);
-            if (tid < cnt) {
-                int pos = base + tid;
-                int k = 0;
-                while (npre[k + 1] <= pos) ++k;
-                int m = perm[nstart[k] + pos - npre[k]];
-                Ms[tid] = m;
-            }
-            __syncthreads();
-            for (int task = tid; task < cnt * 9; task += blockDim.x) {
-                int j = task / 9, ca = task % 9, cc = ca / 3, a = ca % 3;
-                int m = Ms[j];
-                long long co = ((long long)(3 * m + cc) * 3 + a) * 4;
-                const double *w = wc + co;
-                const int *idx = ic + co;
-                double o[4] = {0.0, 0.0, 0.0, 0.0};
-                int t0 = 4 * tc[a];
-                for (int q = 0; q < 4; ++q) {
-                    int loc = idx[q] - t0;
-                    if (w[q] != 0.0 && loc >= 0 && loc < 4) o[loc] += w[q];
-                }
-                for (int q = 0; q < 4; ++q) Wt[j][cc][a][q] = o[q];
-            }
-            for (int task = tid; task < cnt * 3; task += blockDim.x) {
-                int j = task / 3, cc = task % 3;
-                int m = Ms[j];
-                const RepDev &Rm = reps[body_rep[marker_body[m]]];
-                Ls[j][cc] = lam_state[Rm.off + 4 * Rm.N + 3LL * (m - Rm.m0) + cc];
-            }
-            __syncthreads();
-            if (tid < 192) {
-                for (int j = 0; j < cnt; ++j)
-                    acc += Wt[j][c][0][lx] * Wt[j][c][1][ly] * Wt[j][c][2][lz] * Ls[j][c];
-            }
-            __syncthreads();
+#pragma unroll 4
+        for (long long s = s0; s < s1; ++s) {
+            const double *w = pair_w + s * 36 + c * 12;
+            acc += w[lx] * w[4 + ly] * w[8 + lz] * lam_state[pair_lam[s] + c];
         }
-        if (tid < 192 && M > 0) {
-            int g[3] = {4 * tc[0] + lx, 4 * tc[1] + ly, 4 * tc[2] + lz};
-            bool in = g[0] < R.n[0] && g[1] < R.n[1] && g[2] < R.n[2];
-            bool pin = R.bc[c] == RBFIB_WALL && g[c] == 0;
-            if (in && !pin) {
-                long long lin = (long long)g[0] + (long long)R.n[0] * ((long long)g[1] + (long long)R.n[1] * g[2]);
-                const long long o = levs ? levs[tile_rep[t] * RB_MAXLEV].off : R.off;
-                y[o + c * R.N + lin] += (TO)(alpha * acc / R.dV);
-            }
+        const int lt = t - R.tile0;
+        const int g0 = RB_TILE * (lt % R.tdim[0]) + lx;
+        const int g1 = RB_TILE * ((lt / R.tdim[0]) % R.tdim[1]) + ly;
+        const int g2 = RB_TILE * (lt / (R.tdim[0] * R.tdim[1])) + lz;
+        const bool in = g0 < R.n[0] && g1 < R.n[1] && g2 < R.n[2];
+        const int gc = c == 0 ? g0 : (c == 1 ? g1 : g2);
+        const bool pin = R.bc[c] == RBFIB_WALL && gc == 0;
+        if (in && !pin) {
+            const long long lin = (long long)g0 + (long long)R.n[0] * ((long long)g1 + (long long)R.n[1] * g2);
+            const long long o = levs ? levs[rep * RB_MAXLEV].off : R.off;
+            y[o + c * R.N + lin] += (TO)(alpha * acc / R.dV);
         }
-        __syncthreads();
     }
+}
+
+template <typename TO>
+static void spread_into(Ctx &c, MarkerSet &ms, const double *lam_state, TO *y, double alpha, const LevDev *levs) {
+    if (c.nm == 0) return;
+    int grid = std::min(c.ntiles, 32768);   // grid-stride over the tiles that have pairs
+    hipLaunchKernelGGL(k_spread<TO>, dim3(grid), dim3(192), 0, c.stream, c.d_reps, c.d_tile_rep, ms.active,
+                       ms.n_active, ms.pair_start, ms.pair_count, ms.pair_cap, ms.pair_w, ms.pair_lam, lam_state, y,
+                       alpha, c.mask, levs);
 }
 
 // y_fluid += alpha * S lambda, lambda read from the lambda slots of lam_state.
 void launch_spread(Ctx &c, MarkerSet &ms, const double *lam_state, double *y, double alpha) {
-    if (c.nm == 0) return;
-    int grid = std::min(c.ntiles, 32768);   // grid-stride over the active tiles
-    hipLaunchKernelGGL(k_spread<double>, dim3(grid), dim3(256), 0, c.stream, c.d_reps, c.d_tile_rep, ms.active,
-                       ms.n_active, ms.tile_start, ms.tile_count, ms.perm, ms.r, lam_state, c.d_marker_body,
-                       c.d_body_rep, y, alpha, c.mask, ms.wc, ms.ic, (const LevDev *)nullptr);
+    spread_into<double>(c, ms, lam_state, y, alpha, nullptr);
 }
 
 // Level 0 of the multigrid pool (velocity components) += alpha * S lambda.
 template <typename T>
 void launch_spread_level0(Ctx &c, MarkerSet &ms, const double *lam_state, T *pool, double alpha) {
-    if (c.nm == 0) return;
-    int grid = std::min(c.ntiles, 32768);
-    hipLaunchKernelGGL(k_spread<T>, dim3(grid), dim3(256), 0, c.stream, c.d_reps, c.d_tile_rep, ms.active,
-                       ms.n_active, ms.tile_start, ms.tile_count, ms.perm, ms.r, lam_state, c.d_marker_body,
-                       c.d_body_rep, pool, alpha, c.mask, ms.wc, ms.ic, (const LevDev *)c.d_levs);
+    spread_into<T>(c, ms, lam_state, pool, alpha, c.d_levs);
 }
 template void launch_spread_level0<float>(Ctx &, MarkerSet &, const double *, float *, double);
 template void launch_spread_level0<double>(Ctx &, MarkerSet &, const double *, double *, double);

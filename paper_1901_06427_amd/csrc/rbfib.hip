@@ -880,6 +880,20 @@ static void build(Ctx &c, int nrep, const rbfib_grid *grids, const rbfib_bodies 
     c.h_body_len = body_len;
 
     // ---- marker sets
+    // spreading pairs: at most two tiles per axis per marker, three on a periodic
+    // axis whose last tile is partial, never more than the axis has
+    long long pair_cap = 0;
+    for (const RepDev &R : c.reps) {
+        long long per = 1;
+        for (int a = 0; a < 3; ++a) {
+            int b = (R.bc[a] == RBFIB_PERIODIC && R.n[a] % RB_TILE != 0) ? 3 : 2;
+            per *= std::min(b, R.tdim[a]);
+        }
+        pair_cap += per * R.nm;
+    }
+    pair_cap = std::max(pair_cap, 1LL);
+    // tile-start offsets are int: even 27 pairs per marker must fit
+    if (27LL * c.nm > 2147483647LL) throw (int)RBFIB_EINVAL;
     for (int k = 0; k < 4; ++k) {
         MarkerSet &ms = c.ms[k];
         ms.r = dalloc<double>(3 * (size_t)c.nm);
@@ -894,6 +908,14 @@ static void build(Ctx &c, int nrep, const rbfib_grid *grids, const rbfib_bodies 
         ms.n_active = dalloc<int>(1);
         ms.wc = dalloc<double>(36 * (size_t)std::max(c.nm, 1));
         ms.ic = dalloc<int>(36 * (size_t)std::max(c.nm, 1));
+        ms.pair_cap = pair_cap;
+        ms.pair_count = dalloc<int>(c.ntiles);
+        ms.pair_start = dalloc<int>(c.ntiles);
+        ms.pair_fill = dalloc<int>(c.ntiles);
+        ms.pair_m = dalloc<int>(pair_cap);
+        ms.pair_tile = dalloc<int>(pair_cap);
+        ms.pair_w = dalloc<double>(36 * (size_t)pair_cap);
+        ms.pair_lam = dalloc<long long>(pair_cap);
         zero_device(c, ms.n_active, 1);
     }
     c.theta_int = dalloc<double>(4 * (size_t)std::max(c.nb, 1));
@@ -976,6 +998,8 @@ static void free_all(Ctx &c) {
         MarkerSet &ms = c.ms[k];
         F(ms.r); F(ms.d); F(ms.tile); F(ms.perm); F(ms.tile_count); F(ms.tile_start); F(ms.tile_fill);
         F(ms.active); F(ms.flag); F(ms.n_active); F(ms.wc); F(ms.ic);
+        F(ms.pair_count); F(ms.pair_start); F(ms.pair_fill); F(ms.pair_m); F(ms.pair_tile); F(ms.pair_w);
+        F(ms.pair_lam);
     }
     F(c.d_flags); F(c.d_count); F(c.d_active_len);
     if (c.h_flags) (void)hipHostFree(c.h_flags);

@@ -2,8 +2,9 @@
 
 * marker positions, tile indices and the tile-sorted permutation: bit-exact;
 * the homogeneous saddle operator y = A x: within 1e-10 relative (max-norm)
-  on random state vectors, on walled, periodic, ragged (partial tiles) and
-  sliding-wall grids, up to the full monolayer size;
+  on random state vectors, on walled, periodic, ragged (partial tiles),
+  periodic-with-a-one-cell-last-tile and sliding-wall grids, up to the full
+  monolayer size;
 * the fluctuating-stress forcing DT W with the same Philox normals: 1e-12;
 * mobility solves: the GPU solution's true residual, measured with the
   oracle's assembled operator, meets the requested tolerance, and U agrees
@@ -36,6 +37,12 @@ def _configs():
     w = W.small_box(22, n=(16, 12, 12), n_bodies=3, R=1.5, shape="ico12")
     w.bc = (0, 1, 1)
     out["periodic_x_16x12x12"] = w
+    # periodic x of 17 cells: the last tile holds one cell, and markers of the body
+    # at x = 0.15 h in cell 0 reach cell 15 (tile 3) through the wrap
+    w = W.small_box(23, n=(17, 12, 12), n_bodies=2, R=1.5, shape="ico12")
+    w.bc = (W.PERIODIC, W.WALL, W.WALL)
+    w.q[0, 0] = 0.15 * w.h
+    out["periodic_wrap_17x12x12"] = w
     m = W.monolayer(n=(64, 32, 16), rows=4, cols=16)
     out["monolayer_64x32x16"] = m
     return out
