@@ -110,7 +110,7 @@ typedef struct {
 /* Solver options; rbfib_default_opts fills every field. */
 typedef struct {
     double tol;                /* relative residual ||b - A x|| / ||b||  (1e-6)      */
-    int restart;               /* FGMRES restart length (60)                         */
+    int restart;               /* FGMRES restart length (100)                        */
     int max_iter;              /* total iteration cap (600)                          */
     int precond_fp32;          /* 1: multigrid preconditioner in FP32 (0)            */
     int mg_sweeps;             /* damped-Jacobi sweeps before and after (3)          */

@@ -1034,7 +1034,7 @@ extern "C" {
 void rbfib_default_opts(rbfib_opts *o) {
     if (!o) return;
     o->tol = 1e-6;
-    o->restart = 60;
+    o->restart = 100;
     o->max_iter = 600;
     o->precond_fp32 = 0;
     o->mg_sweeps = 3;

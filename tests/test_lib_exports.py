@@ -27,5 +27,5 @@ def test_binding_lists_every_symbol():
     import paper_1901_06427_amd as rb
     assert sorted(rb.EXPORTS) == _declared()
     o = rb.rbfib_default_opts()
-    assert o.tol == 1e-6 and o.restart == 60 and o.use_graphs == 1
+    assert o.tol == 1e-6 and o.restart == 100 and o.use_graphs == 1
     assert rb._lib.rbfib_strerror(-2).decode().startswith("unphysical")
