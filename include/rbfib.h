@@ -128,6 +128,12 @@ typedef struct {
                                /*    needs mg_sweeps == 2.  0 never, 1 on levels     */
                                /*    with enough workgroups to fill the device,      */
                                /*    2 on every level (0)                            */
+    int mg_bottom;             /* > 0: each replica's coarse levels, from the first  */
+                               /*    whose grids fit mg_bottom KB (at most 64), run  */
+                               /*    in one workgroup per (replica, component) with  */
+                               /*    every grid in LDS and the same values as the    */
+                               /*    separate kernels; 0: separate kernels on every  */
+                               /*    level; fixed at creation (0)                    */
 } rbfib_opts;
 
 typedef struct {

@@ -30,6 +30,10 @@
 #define MGF_MIN_BLOCKS 1024
 #define RB_NTIMING 6           // timing classes: apply, smoother sweep, fused down, fused up (level 0),
                                // Krylov dots, Krylov update
+// LDS-resident bottom of the V-cycle: workgroup size and the largest LDS budget
+// per workgroup an option may ask for
+#define MGB_THREADS 256
+#define MGB_LDS (64 * 1024)
 
 namespace rb {
 
@@ -45,6 +49,7 @@ struct RepDev {
     int tdim[3];        // tile grid dims
     int tile0;          // first global tile index
     int nlev;
+    int lb;             // first multigrid level run by the LDS bottom kernel (nlev - 1: coarsest only)
     int movwall;
     double wv[3][2][3];
     double inv_n0, inv_n01;   // 1/nx and 1/(nx*ny) for exact index splitting
@@ -476,6 +481,9 @@ struct Ctx {
     BlockEnt *d_tab_all[RB_MAXLEV] = {nullptr};  int n_tab_all[RB_MAXLEV] = {0};   // replicas having level l
     // fused level kernels (start = tile index of level l), replicas that have level l+1
     BlockEnt *d_tab_mg[RB_MAXLEV] = {nullptr};   int n_tab_mg[RB_MAXLEV] = {0};
+    // LDS bottom kernel: one entry per replica, dynamic LDS bytes in each precision
+    BlockEnt *d_tab_bot = nullptr; int n_tab_bot = 0;
+    size_t bot_lds32 = 0, bot_lds64 = 0;
     double lev_cells[RB_MAXLEV] = {0};   // points of level l summed over the replicas that have level l+1
     double lev_cells_c[RB_MAXLEV] = {0}; // points of level l+1 over the same replicas
     double cells_all = 0;                // level-0 points over all replicas
@@ -524,6 +532,7 @@ void launch_apply_fluid(Ctx &c, const double *x, double *y);
 template <typename T> void launch_to_level0(Ctx &c, const double *src, T *b, int c0, int nc);
 template <typename T> void launch_smooth(Ctx &c, int lev, int c0, int nc, const T *xin, T *xout, const T *b, bool first);
 template <typename T> void launch_restrict(Ctx &c, int lev, int c0, int nc, const T *x, const T *b, T *bc, T *r);
+template <typename T> void launch_mg_bottom(Ctx &c, int c0, int nc, int nu, const T *b, T *x, T *t, unsigned res_t_mask);
 template <typename T> void launch_prolong(Ctx &c, int lev, int c0, int nc, const T *xc, T *xf);
 template <typename T> void launch_coarse(Ctx &c, int lev, int c0, int nc, const T *b, T *x);
 // fused level kernels (mgfused.hip)

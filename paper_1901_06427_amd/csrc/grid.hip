@@ -525,7 +525,7 @@ __global__ void k_coarse(const RepDev *reps, const LevDev *levs, const BlockEnt 
     for (int i = threadIdx.x; i < m; i += blockDim.x) {
         T acc = (T)0;
         const T *row = A + (long long)i * m;
-        for (int j = 0; j < m; ++j) acc += row[j] * bs[j];
+        for (int j = 0; j < m; ++j) acc = fmad(row[j], bs[j], acc);
         xx[i] = acc;
     }
 }
@@ -541,6 +541,199 @@ void launch_coarse(Ctx &c, int lev, int c0, int nc, const T *b, T *x) {
     hipLaunchKernelGGL(k_coarse<T>, dim3(c.n_tab_crs[lev], nc), dim3(RB_BLOCK), sh, c.stream, c.d_reps, c.d_levs,
                        c.d_tab_crs[lev], lev, c0, c.d_coarse_off, coarse_pool<T>(c), b, x, c.mask);
 }
+
+// ------------------------------------------------------------------ bottom of the V-cycle in LDS
+// One workgroup per (replica, component) runs the levels lb .. nlev-1 of its replica
+// (lb = RepDev::lb, the first level whose grids fit MGB_LDS bytes) with every grid
+// in LDS: the down sweeps, residual and restriction of each level, the dense
+// coarsest solve, and the prolongation and up sweeps, separated by workgroup
+// barriers instead of kernel launches.  Every point is computed by the helpers
+// and in the operation order of the separate kernels, so the result is the same
+// to the bit.  LDS: x_l and b_l for l = lb .. nlev-1, then one level-lb scratch
+// grid t for the Jacobi ping-pong and the residual.
+// Threads own (i, j) columns and march along k: the x and y boundary rules, the
+// x and y terms of the diagonal and the pinning in x and y are evaluated once per
+// column; consecutive lanes touch consecutive LDS words.
+template <typename T, int MODE>
+__device__ __forceinline__ void bot_sweep(const RepDev &R, const LevDev &Lv, int comp, T s, T om,
+                                          const T *xi, T *xo, const T *bb) {
+    const int n0 = Lv.n[0], n1 = Lv.n[1], n2 = Lv.n[2], n01 = n0 * n1;
+    const T ih0 = (T)Lv.inv_h2[0], ih1 = (T)Lv.inv_h2[1], ih2 = (T)Lv.inv_h2[2];
+    for (int col = threadIdx.x; col < n01; col += blockDim.x) {
+        const int j = col / n0, i = col - j * n0;
+        const int kxm = nbr_kind(i, -1, n0, R.bc[0], 0, comp), kxp = nbr_kind(i, +1, n0, R.bc[0], 0, comp);
+        const int kym = nbr_kind(j, -1, n1, R.bc[1], 1, comp), kyp = nbr_kind(j, +1, n1, R.bc[1], 1, comp);
+        const int oxm = kxm ? 0 : (i == 0 ? n0 - 1 : -1);
+        const int oxp = kxp ? 0 : (i == n0 - 1 ? -(n0 - 1) : 1);
+        const int oym = kym ? 0 : (j == 0 ? (n1 - 1) * n0 : -n0);
+        const int oyp = kyp ? 0 : (j == n1 - 1 ? -(n1 - 1) * n0 : n0);
+        const T dxy = fmad(diag_axis<T>(comp, 1, j, n1, R.bc[1]), ih1,
+                           fmad(diag_axis<T>(comp, 0, i, n0, R.bc[0]), ih0, (T)0));
+        const bool pin_xy = (comp == 0 && R.bc[0] == RBFIB_WALL && i == 0) ||
+                            (comp == 1 && R.bc[1] == RBFIB_WALL && j == 0);
+        for (int k = 0; k < n2; ++k) {
+            const int lin = col + k * n01;
+            const T d = fmad(diag_axis<T>(comp, 2, k, n2, R.bc[2]), ih2, dxy);
+            const T w = jacobi_w<T>(om, s, d);
+            T y;
+            if (MODE == MG_FIRST) {
+                y = bb[lin] * w;
+            } else {
+                const int kzm = nbr_kind(k, -1, n2, R.bc[2], 2, comp), kzp = nbr_kind(k, +1, n2, R.bc[2], 2, comp);
+                const int ozm = kzm ? 0 : (k == 0 ? (n2 - 1) * n01 : -n01);
+                const int ozp = kzp ? 0 : (k == n2 - 1 ? -(n2 - 1) * n01 : n01);
+                const T xv = xi[lin];
+                T acc = lap_acc<T>(pick<T>(kxp, xi[lin + oxp], xv), xv, pick<T>(kxm, xi[lin + oxm], xv), ih0, (T)0);
+                acc = lap_acc<T>(pick<T>(kyp, xi[lin + oyp], xv), xv, pick<T>(kym, xi[lin + oym], xv), ih1, acc);
+                acc = lap_acc<T>(pick<T>(kzp, xi[lin + ozp], xv), xv, pick<T>(kzm, xi[lin + ozm], xv), ih2, acc);
+                y = MODE == MG_RESID ? mg_residual<T>(bb[lin], s, acc) : jacobi_step<T>(xv, bb[lin], s, acc, w);
+            }
+            const bool pin = pin_xy || (comp == 2 && R.bc[2] == RBFIB_WALL && k == 0);
+            xo[lin] = pin ? (T)0 : y;
+        }
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ void bot_restrict(const RepDev &R, const LevDev &F, const LevDev &C, int comp,
+                                             const T *rf, T *bc) {
+    bool crs[3], face[3];
+    int fc[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        crs[a] = F.n[a] != C.n[a];
+        face[a] = crs[a] && a == comp;
+        fc[a] = !crs[a] ? 1 : (face[a] ? 3 : 2);
+    }
+    const int f01 = F.n[0] * F.n[1], c01 = C.n[0] * C.n[1];
+    auto wrap = [](int f, int n) { return f < 0 ? f + n : (f >= n ? f - n : f); };
+    for (int col = threadIdx.x; col < c01; col += blockDim.x) {
+        const int cj = col / C.n[0], cix = col - cj * C.n[0];
+        for (int ck = 0; ck < C.n[2]; ++ck) {
+            const int lin = col + ck * c01;
+            const int ci[3] = {cix, cj, ck};
+            if (pinned(comp, ci, R.bc)) { bc[lin] = (T)0; continue; }
+            int fb[3];
+#pragma unroll
+            for (int a = 0; a < 3; ++a) fb[a] = crs[a] ? 2 * ci[a] - (face[a] ? 1 : 0) : ci[a];
+            T acc = (T)0;
+#pragma unroll
+            for (int kk = 0; kk < 3; ++kk)
+#pragma unroll
+                for (int jj = 0; jj < 3; ++jj)
+#pragma unroll
+                    for (int ii = 0; ii < 3; ++ii)
+                        if (kk < fc[2] && jj < fc[1] && ii < fc[0])
+                            acc = fmad(restrict_weight<T>(crs[0], face[0], ii) *
+                                           restrict_weight<T>(crs[1], face[1], jj) *
+                                           restrict_weight<T>(crs[2], face[2], kk),
+                                       rf[wrap(fb[0] + ii, F.n[0]) + F.n[0] * wrap(fb[1] + jj, F.n[1]) +
+                                          f01 * wrap(fb[2] + kk, F.n[2])],
+                                       acc);
+            bc[lin] = acc;
+        }
+    }
+}
+
+// x_f += P x_c over the fine level, by columns
+template <typename T>
+__device__ __forceinline__ void bot_prolong(const RepDev &R, const LevDev &F, const LevDev &C, int comp,
+                                            const T *xc, T *xf) {
+    const int f01 = F.n[0] * F.n[1];
+    for (int col = threadIdx.x; col < f01; col += blockDim.x) {
+        const int fj = col / F.n[0], fix = col - fj * F.n[0];
+        for (int fk = 0; fk < F.n[2]; ++fk) {
+            const int fi[3] = {fix, fj, fk};
+            if (pinned(comp, fi, R.bc)) continue;
+            xf[col + fk * f01] += prolong_at<T>(R, F, C, comp, fi, xc);
+        }
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(MGB_THREADS) void k_mg_bottom(const RepDev *reps, const LevDev *levs, const BlockEnt *tab,
+                                                           int c0, int nu, double omega, const T *__restrict__ bpool,
+                                                           T *xpool, T *tpool, unsigned res_t_mask,
+                                                           const long long *coff, const T *__restrict__ Ainv,
+                                                           const int *__restrict__ mask) {
+    const BlockEnt be = tab[blockIdx.x];
+    if (mask && !mask[be.rep]) return;
+    const int comp = c0 + blockIdx.y;
+    const RepDev &R = reps[be.rep];
+    const LevDev *lv = levs + be.rep * RB_MAXLEV;
+    const int lb = R.lb, lc = R.nlev - 1;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    T *sm = reinterpret_cast<T *>(smem_raw);
+    auto xl = [&](int l) {
+        long long o = 0;
+        for (int k = lb; k < l; ++k) o += 2 * lv[k].N;
+        return sm + o;
+    };
+    auto bl = [&](int l) { return xl(l) + lv[l].N; };
+    T *t = xl(lc + 1);
+    const T s = (comp < 3) ? (T)(-R.eta) : (T)-1;
+    const T om = (T)omega;
+    {
+        const T *src = bpool + lv[lb].off + comp * lv[lb].N;
+        T *b = bl(lb);
+        for (int i = threadIdx.x; i < (int)lv[lb].N; i += blockDim.x) b[i] = src[i];
+    }
+    __syncthreads();
+    for (int l = lb; l < lc; ++l) {
+        T *x = xl(l), *b = bl(l);
+        for (int k = 1; k <= nu; ++k) {
+            T *out = ((nu - k) % 2 == 0) ? x : t;
+            T *in = (out == x) ? t : x;
+            if (k == 1) bot_sweep<T, MG_FIRST>(R, lv[l], comp, s, om, in, out, b);
+            else bot_sweep<T, MG_SWEEP>(R, lv[l], comp, s, om, in, out, b);
+            __syncthreads();
+        }
+        bot_sweep<T, MG_RESID>(R, lv[l], comp, s, om, x, t, b);
+        __syncthreads();
+        bot_restrict<T>(R, lv[l], lv[l + 1], comp, t, bl(l + 1));
+        __syncthreads();
+    }
+    {
+        const int m = (int)lv[lc].N;
+        const T *A = Ainv + coff[be.rep * 4 + comp];
+        const T *b = bl(lc);
+        T *x = xl(lc);
+        for (int i = threadIdx.x; i < m; i += blockDim.x) {
+            T acc = (T)0;
+            const T *row = A + (long long)i * m;
+            for (int j = 0; j < m; ++j) acc = fmad(row[j], b[j], acc);
+            x[i] = acc;
+        }
+        __syncthreads();
+    }
+    const T *res = xl(lc);
+    for (int l = lc - 1; l >= lb; --l) {
+        T *x = xl(l);
+        const LevDev &F = lv[l], &C = lv[l + 1];
+        bot_prolong<T>(R, F, C, comp, res, x);
+        __syncthreads();
+        T *in = x, *out = t;
+        for (int k = 1; k <= nu; ++k) {
+            bot_sweep<T, MG_SWEEP>(R, F, comp, s, om, in, out, bl(l));
+            __syncthreads();
+            T *tmp = in; in = out; out = tmp;
+        }
+        res = in;
+    }
+    T *dst = (((res_t_mask >> lb) & 1u) ? tpool : xpool) + lv[lb].off + comp * lv[lb].N;
+    for (int i = threadIdx.x; i < (int)lv[lb].N; i += blockDim.x) dst[i] = res[i];
+}
+
+template <typename T>
+void launch_mg_bottom(Ctx &c, int c0, int nc, int nu, const T *b, T *x, T *t, unsigned res_t_mask) {
+    if (c.n_tab_bot == 0) return;
+    const size_t sh = sizeof(T) == 4 ? c.bot_lds32 : c.bot_lds64;
+    hipLaunchKernelGGL(k_mg_bottom<T>, dim3(c.n_tab_bot, nc), dim3(MGB_THREADS), sh, c.stream, c.d_reps, c.d_levs,
+                       c.d_tab_bot, c0, nu, c.opts.mg_omega, b, x, t, res_t_mask, c.d_coarse_off, coarse_pool<T>(c),
+                       c.mask);
+}
+template void launch_mg_bottom<float>(Ctx &, int, int, int, const float *, float *, float *, unsigned);
+template void launch_mg_bottom<double>(Ctx &, int, int, int, const double *, double *, double *, unsigned);
 
 // ------------------------------------------------------------------ projection step
 // d = D x* + r_pi ;  b_p (level 0) = -d  (so that -L phi = -d) ;  z_pi = -eta d.

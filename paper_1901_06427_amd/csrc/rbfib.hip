@@ -248,6 +248,10 @@ static T *vcycle(Ctx &c, int c0, int nc) {
         }
         launch_restrict<T>(c, l, c0, nc, X, B, B, Tt);   // T(l) is free after the down sweeps
     }
+    // levels lb .. nlev-1 of every replica in one launch; its result lands in res[lb]
+    unsigned res_t = 0;
+    for (int l = 0; l < c.maxlev; ++l) res_t |= (res[l] == Tt ? 1u : 0u) << l;
+    launch_mg_bottom<T>(c, c0, nc, nu, B, X, Tt, res_t);
     for (int l = c.maxlev - 2; l >= 0; --l) {
         if (c.n_tab_lev[l] == 0) continue;
         if (fz[l]) {
@@ -606,7 +610,7 @@ static int sem_step(Ctx &c, double *q, double *theta, const double *FT, const do
 static void validate(int nrep, const rbfib_grid *grids, const rbfib_bodies *bodies, const rbfib_opts &o) {
     if (nrep < 1 || !grids || !bodies) throw (int)RBFIB_EINVAL;
     if (!(o.tol > 0.0) || o.restart < 1 || o.restart > 200 || o.max_iter < 1 || o.mg_sweeps < 1 ||
-        !(o.mg_omega > 0.0) || !(o.blob_radius > 0.0) || !(o.rfd_delta > 0.0))
+        !(o.mg_omega > 0.0) || !(o.blob_radius > 0.0) || !(o.rfd_delta > 0.0) || o.mg_bottom < 0 || o.mg_bottom > MGB_LDS / 1024)
         throw (int)RBFIB_EINVAL;
     for (int r = 0; r < nrep; ++r) {
         const rbfib_grid &g = grids[r];
@@ -713,6 +717,29 @@ static void build(Ctx &c, int nrep, const rbfib_grid *grids, const rbfib_bodies 
     }
     c.lev_total = loff;
 
+    // ---- bottom level of each replica: the first level whose grids (x and b of it
+    // and every coarser level, plus one scratch grid of its size) fit the LDS budget
+    // (mg_bottom KB) of one workgroup; without the bottom kernel only the coarsest
+    // level is solved apart
+    c.bot_lds32 = c.bot_lds64 = 0;
+    for (int r = 0; r < nrep; ++r) {
+        RepDev &R = c.reps[r];
+        const int lc = R.nlev - 1;
+        auto cells = [&](int l) {
+            long long n = (l < lc) ? c.levs[(size_t)r * RB_MAXLEV + l].N : 0;
+            for (int k = l; k <= lc; ++k) n += 2 * c.levs[(size_t)r * RB_MAXLEV + k].N;
+            return n;
+        };
+        R.lb = lc;
+        if (c.opts.mg_bottom) {
+            const size_t es = c.opts.precond_fp32 ? sizeof(float) : sizeof(double);
+            const size_t budget = (size_t)c.opts.mg_bottom * 1024;
+            while (R.lb > 0 && (size_t)cells(R.lb - 1) * es <= budget) --R.lb;
+            c.bot_lds32 = std::max(c.bot_lds32, (size_t)cells(R.lb) * sizeof(float));
+            c.bot_lds64 = std::max(c.bot_lds64, (size_t)cells(R.lb) * sizeof(double));
+        }
+    }
+
     // ---- block tables
     // Grid kernels (level-0 cell kernels and every multigrid level) process npt points
     // per thread: 4 for large batches (amortises the per-block descriptor loads), 1
@@ -745,15 +772,18 @@ static void build(Ctx &c, int nrep, const rbfib_grid *grids, const rbfib_bodies 
     c.d_tab_vec = upload(c, tvec);
     c.d_vec_first = upload(c, c.vec_first);
     c.d_vec_nblk = upload(c, c.vec_nblk);
+    // level l of replica r runs in the separate (or fused) kernels for l < lb; the
+    // restriction into level l for l <= lb; the coarsest-level kernel only for
+    // replicas the bottom kernel does not take
     for (int l = 0; l < c.maxlev; ++l) {
         std::vector<BlockEnt> tl, tc, ta;
         for (int r = 0; r < nrep; ++r) {
             const RepDev &R = c.reps[r];
-            if (l >= R.nlev) continue;
+            if (l >= R.nlev || l > R.lb) continue;
             long long N = c.levs[(size_t)r * RB_MAXLEV + l].N;
             gchunks(ta, r, N, mg_npt);
-            if (l < R.nlev - 1) gchunks(tl, r, N, mg_npt);
-            else tc.push_back(BlockEnt{r, 1, 0});
+            if (l < R.lb) gchunks(tl, r, N, mg_npt);
+            else if (!c.opts.mg_bottom) tc.push_back(BlockEnt{r, 1, 0});
         }
         c.n_tab_lev[l] = (int)tl.size(); c.d_tab_lev[l] = upload(c, tl);
         c.n_tab_crs[l] = (int)tc.size(); c.d_tab_crs[l] = upload(c, tc);
@@ -763,7 +793,7 @@ static void build(Ctx &c, int nrep, const rbfib_grid *grids, const rbfib_bodies 
     for (int l = 0; l + 1 < c.maxlev; ++l) {
         std::vector<BlockEnt> tm;
         for (int r = 0; r < nrep; ++r) {
-            if (l + 1 >= c.reps[r].nlev) continue;
+            if (l >= c.reps[r].lb) continue;
             const LevDev &F = c.levs[(size_t)r * RB_MAXLEV + l];
             const LevDev &C = c.levs[(size_t)r * RB_MAXLEV + l + 1];
             const long long nt = (long long)((F.n[0] + MGF_OX - 1) / MGF_OX) * ((F.n[1] + MGF_OY - 1) / MGF_OY) *
@@ -775,6 +805,12 @@ static void build(Ctx &c, int nrep, const rbfib_grid *grids, const rbfib_bodies 
         c.n_tab_mg[l] = (int)tm.size(); c.d_tab_mg[l] = upload(c, tm);
     }
     c.cells_all = (double)total_cells;
+    if (c.opts.mg_bottom) {
+        std::vector<BlockEnt> tb;
+        for (int r = 0; r < nrep; ++r) tb.push_back(BlockEnt{r, 1, 0});
+        c.n_tab_bot = (int)tb.size();
+        c.d_tab_bot = upload(c, tb);
+    }
 
     // ---- dense coarsest inverses, deduplicated by (dims, spacing, bc, eta, component)
     std::map<std::string, long long> keyoff;
@@ -988,7 +1024,7 @@ static void free_all(Ctx &c) {
     auto F = [](void *p) { if (p) (void)hipFree(p); };
     F(c.d_reps); F(c.d_levs); F(c.d_marker_body); F(c.d_body_rep); F(c.d_body_off); F(c.d_tile_rep); F(c.d_rref);
     F(c.d_body_shape); F(c.d_shapes); F(c.d_shape_data); F(c.d_body_len);
-    F(c.d_tab_cells); F(c.d_tab_cells1); F(c.d_tab_vec); F(c.d_vec_first); F(c.d_vec_nblk);
+    F(c.d_tab_cells); F(c.d_tab_cells1); F(c.d_tab_vec); F(c.d_vec_first); F(c.d_vec_nblk); F(c.d_tab_bot);
     for (int l = 0; l < RB_MAXLEV; ++l) {
         F(c.d_tab_lev[l]); F(c.d_tab_crs[l]); F(c.d_tab_all[l]); F(c.d_tab_mg[l]);
     }
@@ -1046,6 +1082,7 @@ void rbfib_default_opts(rbfib_opts *o) {
     o->check_every = 5;
     o->use_graphs = 1;
     o->mg_fused = 0;
+    o->mg_bottom = 0;
 }
 
 const char *rbfib_strerror(int code) {
@@ -1108,8 +1145,9 @@ int rbfib_set_opts(rbfib_ctx *ctx, const rbfib_opts *o) {
     Ctx &c = ctx->c;
     if (!(o->tol > 0.0) || o->max_iter < 1 || o->mg_sweeps < 1 || !(o->mg_omega > 0.0) || !(o->rfd_delta > 0.0))
         return RBFIB_EINVAL;
-    // fields fixed at creation: restart length, precision, blob radius
-    if (o->restart != c.opts.restart || (o->precond_fp32 != 0) != c.mg_fp32 || o->blob_radius != c.opts.blob_radius)
+    // fields fixed at creation: restart length, precision, blob radius, bottom kernel
+    if (o->restart != c.opts.restart || (o->precond_fp32 != 0) != c.mg_fp32 || o->blob_radius != c.opts.blob_radius ||
+        o->mg_bottom != c.opts.mg_bottom)
         return RBFIB_EINVAL;
     if (o->mg_sweeps != c.opts.mg_sweeps || o->mg_sweeps_p != c.opts.mg_sweeps_p || o->mg_omega != c.opts.mg_omega ||
         o->mg_fused != c.opts.mg_fused)
