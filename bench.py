@@ -131,6 +131,7 @@ OMEGA = 0.0       # 0: the library default
 PSWEEPS = 0       # 0: the library default
 BLOB = 0.0        # 0: the library default
 BOTTOM = -1       # -1: the library default
+CHEBY = -1.0      # < 0: the library default
 
 
 def run_gpu(ws, steps, warmup, fp32, seed=2024, timing=False, graphs=True):
@@ -142,7 +143,8 @@ def run_gpu(ws, steps, warmup, fp32, seed=2024, timing=False, graphs=True):
                       mg_fused=MG_FUSED, **({"restart": RESTART} if RESTART else {}),
                       **({"mg_sweeps": SWEEPS} if SWEEPS else {}), **({"mg_omega": OMEGA} if OMEGA else {}),
                       **({"mg_sweeps_p": PSWEEPS} if PSWEEPS else {}), **({"blob_radius": BLOB} if BLOB else {}),
-                      **({"mg_bottom": BOTTOM} if BOTTOM >= 0 else {}))
+                      **({"mg_bottom": BOTTOM} if BOTTOM >= 0 else {}),
+                      **({"mg_cheby": CHEBY} if CHEBY >= 0 else {}))
     U = torch.empty((E.nb, 6), dtype=torch.float64, device="cuda")
     step_id = 0
     iters = 0
@@ -311,6 +313,8 @@ def main():
                          "replicas, no graphs): the command the hardware-counter profiles are taken on")
     ap.add_argument("--mg-bottom", type=int, default=-1,
                     help="LDS budget in KB of the bottom multigrid kernel, 0 off (-1: library default)")
+    ap.add_argument("--mg-cheby", type=float, default=-1.0,
+                    help="lower end of the Chebyshev smoothing interval, 0 constant weights (-1: library default)")
     ap.add_argument("--restart", type=int, default=0, help="FGMRES restart length (0: library default)")
     ap.add_argument("--mg-sweeps", type=int, default=0, help="damped-Jacobi sweeps per level (0: library default)")
     ap.add_argument("--mg-omega", type=float, default=0.0, help="Jacobi damping (0: library default)")
@@ -323,10 +327,11 @@ def main():
                     help="multigrid level kernels: 0 separate (default), 1 fused where the level fills the "
                          "device, 2 fused on every level")
     args = ap.parse_args()
-    global MG_FUSED, RESTART, SWEEPS, OMEGA, PSWEEPS, BLOB, BOTTOM
+    global MG_FUSED, RESTART, SWEEPS, OMEGA, PSWEEPS, BLOB, BOTTOM, CHEBY
     MG_FUSED = args.mg_fused
     RESTART = args.restart
     BOTTOM = args.mg_bottom
+    CHEBY = args.mg_cheby
     SWEEPS = args.mg_sweeps
     OMEGA = args.mg_omega
     PSWEEPS = args.mg_sweeps_p

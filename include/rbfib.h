@@ -113,8 +113,8 @@ typedef struct {
     int restart;               /* FGMRES restart length (100)                        */
     int max_iter;              /* total iteration cap (600)                          */
     int precond_fp32;          /* 1: multigrid preconditioner in FP32 (0)            */
-    int mg_sweeps;             /* damped-Jacobi sweeps before and after (3)          */
-    int mg_sweeps_p;           /* the same for the pressure cycle; 0: mg_sweeps (4)  */
+    int mg_sweeps;             /* damped-Jacobi sweeps before and after, 1..16 (2)   */
+    int mg_sweeps_p;           /* the same for the pressure cycle; 0: mg_sweeps (3)  */
     double mg_omega;           /* Jacobi damping (0.9)                               */
     double blob_radius;        /* blob radius of the body block, units of h (1.2)    */
     double rfd_delta;          /* random-finite-difference delta (1e-5)              */
@@ -134,6 +134,9 @@ typedef struct {
                                /*    every grid in LDS and the same values as the    */
                                /*    separate kernels; 0: separate kernels on every  */
                                /*    level; fixed at creation (0)                    */
+    double mg_cheby;           /* > 0: sweep k of nu has weight 1 / lambda_k, the    */
+                               /*    roots of the degree-nu Chebyshev polynomial on  */
+                               /*    [mg_cheby, 2]; 0: every sweep mg_omega (0.27)   */
 } rbfib_opts;
 
 typedef struct {

@@ -34,6 +34,8 @@
 // per workgroup an option may ask for
 #define MGB_THREADS 256
 #define MGB_LDS (64 * 1024)
+// most damped-Jacobi sweeps per level and direction
+#define RB_MAXSWEEP 16
 
 namespace rb {
 
@@ -215,6 +217,10 @@ __device__ __forceinline__ T prolong_at(const RepDev &R, const LevDev &F, const 
                                acc);
     return acc;
 }
+
+struct SweepW {         // weight of each smoothing sweep of a V-cycle (sweep k in w[k - 1])
+    double w[RB_MAXSWEEP];
+};
 
 struct BlockEnt {       // one block of work: replica and local start index
     int rep;
@@ -530,14 +536,17 @@ struct Ctx {
 // grid / multigrid (grid.hip)
 void launch_apply_fluid(Ctx &c, const double *x, double *y);
 template <typename T> void launch_to_level0(Ctx &c, const double *src, T *b, int c0, int nc);
-template <typename T> void launch_smooth(Ctx &c, int lev, int c0, int nc, const T *xin, T *xout, const T *b, bool first);
+template <typename T> void launch_smooth(Ctx &c, int lev, int c0, int nc, const T *xin, T *xout, const T *b, bool first,
+                                          double omega);
 template <typename T> void launch_restrict(Ctx &c, int lev, int c0, int nc, const T *x, const T *b, T *bc, T *r);
-template <typename T> void launch_mg_bottom(Ctx &c, int c0, int nc, int nu, const T *b, T *x, T *t, unsigned res_t_mask);
+template <typename T> void launch_mg_bottom(Ctx &c, int c0, int nc, int nu, const SweepW &w, const T *b, T *x, T *t,
+                                           unsigned res_t_mask);
 template <typename T> void launch_prolong(Ctx &c, int lev, int c0, int nc, const T *xc, T *xf);
 template <typename T> void launch_coarse(Ctx &c, int lev, int c0, int nc, const T *b, T *x);
 // fused level kernels (mgfused.hip)
-template <typename T> void launch_mg_down(Ctx &c, int lev, int c0, int nc, const T *b, T *x);
-template <typename T> void launch_mg_up(Ctx &c, int lev, int c0, int nc, const T *b, const T *xin, const T *xc, T *xout);
+template <typename T> void launch_mg_down(Ctx &c, int lev, int c0, int nc, const T *b, T *x, double omega1, double omega2);
+template <typename T> void launch_mg_up(Ctx &c, int lev, int c0, int nc, const T *b, const T *xin, const T *xc, T *xout,
+                                       double omega1, double omega2);
 template <typename T> void launch_proj_div(Ctx &c, const T *xv, const double *r, T *bp, double *z);
 template <typename T> void launch_proj_correct(Ctx &c, const T *xv, const T *phi, double *z);
 void launch_noise(Ctx &c, double kT, double dt, uint64_t seed, uint64_t step, double *f, bool add);

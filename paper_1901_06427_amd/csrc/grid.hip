@@ -315,22 +315,23 @@ __global__ __launch_bounds__(RB_BLOCK) void k_smooth(const RepDev *reps, const L
 }
 
 template <typename T, int NPT, int MODE>
-static void launch_stencil(Ctx &c, int lev, int c0, int nc, const T *xin, T *xout, const T *b) {
+static void launch_stencil(Ctx &c, int lev, int c0, int nc, const T *xin, T *xout, const T *b, double omega) {
     hipLaunchKernelGGL((k_smooth<T, NPT, MODE>), dim3(c.n_tab_lev[lev], nc), dim3(RB_BLOCK), 0, c.stream, c.d_reps,
-                       c.d_levs, c.d_tab_lev[lev], lev, c0, xin, xout, b, c.opts.mg_omega, c.mask);
+                       c.d_levs, c.d_tab_lev[lev], lev, c0, xin, xout, b, omega, c.mask);
 }
 
 template <typename T, int MODE>
-static void launch_stencil_any(Ctx &c, int lev, int c0, int nc, const T *xin, T *xout, const T *b) {
+static void launch_stencil_any(Ctx &c, int lev, int c0, int nc, const T *xin, T *xout, const T *b, double omega) {
     if (c.n_tab_lev[lev] == 0) return;
-    if (c.mg_npt == 4) launch_stencil<T, 4, MODE>(c, lev, c0, nc, xin, xout, b);
-    else launch_stencil<T, 1, MODE>(c, lev, c0, nc, xin, xout, b);
+    if (c.mg_npt == 4) launch_stencil<T, 4, MODE>(c, lev, c0, nc, xin, xout, b, omega);
+    else launch_stencil<T, 1, MODE>(c, lev, c0, nc, xin, xout, b, omega);
 }
 
+// one damped-Jacobi sweep with weight omega (first: from a zero iterate)
 template <typename T>
-void launch_smooth(Ctx &c, int lev, int c0, int nc, const T *xin, T *xout, const T *b, bool first) {
-    if (first) launch_stencil_any<T, MG_FIRST>(c, lev, c0, nc, xin, xout, b);
-    else launch_stencil_any<T, MG_SWEEP>(c, lev, c0, nc, xin, xout, b);
+void launch_smooth(Ctx &c, int lev, int c0, int nc, const T *xin, T *xout, const T *b, bool first, double omega) {
+    if (first) launch_stencil_any<T, MG_FIRST>(c, lev, c0, nc, xin, xout, b, omega);
+    else launch_stencil_any<T, MG_SWEEP>(c, lev, c0, nc, xin, xout, b, omega);
 }
 
 // Restriction of the residual r of level lev (written by a MG_RESID pass, zero at
@@ -391,7 +392,7 @@ __global__ __launch_bounds__(RB_BLOCK) void k_restrict(const RepDev *reps, const
 template <typename T>
 void launch_restrict(Ctx &c, int lev, int c0, int nc, const T *x, const T *b, T *bcoarse, T *r) {
     if (c.n_tab_lev[lev] == 0) return;
-    launch_stencil_any<T, MG_RESID>(c, lev, c0, nc, x, r, b);
+    launch_stencil_any<T, MG_RESID>(c, lev, c0, nc, x, r, b, c.opts.mg_omega);   // the residual ignores omega
     // one thread per coarse point: the table of level lev+1 restricted to replicas descending from lev
     if (c.mg_npt == 4)
         hipLaunchKernelGGL((k_restrict<T, 4>), dim3(c.n_tab_all[lev + 1], nc), dim3(RB_BLOCK), 0, c.stream,
@@ -652,7 +653,7 @@ __device__ __forceinline__ void bot_prolong(const RepDev &R, const LevDev &F, co
 
 template <typename T>
 __global__ __launch_bounds__(MGB_THREADS) void k_mg_bottom(const RepDev *reps, const LevDev *levs, const BlockEnt *tab,
-                                                           int c0, int nu, double omega, const T *__restrict__ bpool,
+                                                           int c0, int nu, SweepW sw, const T *__restrict__ bpool,
                                                            T *xpool, T *tpool, unsigned res_t_mask,
                                                            const long long *coff, const T *__restrict__ Ainv,
                                                            const int *__restrict__ mask) {
@@ -672,7 +673,6 @@ __global__ __launch_bounds__(MGB_THREADS) void k_mg_bottom(const RepDev *reps, c
     auto bl = [&](int l) { return xl(l) + lv[l].N; };
     T *t = xl(lc + 1);
     const T s = (comp < 3) ? (T)(-R.eta) : (T)-1;
-    const T om = (T)omega;
     {
         const T *src = bpool + lv[lb].off + comp * lv[lb].N;
         T *b = bl(lb);
@@ -684,11 +684,11 @@ __global__ __launch_bounds__(MGB_THREADS) void k_mg_bottom(const RepDev *reps, c
         for (int k = 1; k <= nu; ++k) {
             T *out = ((nu - k) % 2 == 0) ? x : t;
             T *in = (out == x) ? t : x;
-            if (k == 1) bot_sweep<T, MG_FIRST>(R, lv[l], comp, s, om, in, out, b);
-            else bot_sweep<T, MG_SWEEP>(R, lv[l], comp, s, om, in, out, b);
+            if (k == 1) bot_sweep<T, MG_FIRST>(R, lv[l], comp, s, (T)sw.w[k - 1], in, out, b);
+            else bot_sweep<T, MG_SWEEP>(R, lv[l], comp, s, (T)sw.w[k - 1], in, out, b);
             __syncthreads();
         }
-        bot_sweep<T, MG_RESID>(R, lv[l], comp, s, om, x, t, b);
+        bot_sweep<T, MG_RESID>(R, lv[l], comp, s, (T)0, x, t, b);
         __syncthreads();
         bot_restrict<T>(R, lv[l], lv[l + 1], comp, t, bl(l + 1));
         __syncthreads();
@@ -714,7 +714,7 @@ __global__ __launch_bounds__(MGB_THREADS) void k_mg_bottom(const RepDev *reps, c
         __syncthreads();
         T *in = x, *out = t;
         for (int k = 1; k <= nu; ++k) {
-            bot_sweep<T, MG_SWEEP>(R, F, comp, s, om, in, out, bl(l));
+            bot_sweep<T, MG_SWEEP>(R, F, comp, s, (T)sw.w[k - 1], in, out, bl(l));
             __syncthreads();
             T *tmp = in; in = out; out = tmp;
         }
@@ -725,15 +725,15 @@ __global__ __launch_bounds__(MGB_THREADS) void k_mg_bottom(const RepDev *reps, c
 }
 
 template <typename T>
-void launch_mg_bottom(Ctx &c, int c0, int nc, int nu, const T *b, T *x, T *t, unsigned res_t_mask) {
+void launch_mg_bottom(Ctx &c, int c0, int nc, int nu, const SweepW &w, const T *b, T *x, T *t, unsigned res_t_mask) {
     if (c.n_tab_bot == 0) return;
     const size_t sh = sizeof(T) == 4 ? c.bot_lds32 : c.bot_lds64;
     hipLaunchKernelGGL(k_mg_bottom<T>, dim3(c.n_tab_bot, nc), dim3(MGB_THREADS), sh, c.stream, c.d_reps, c.d_levs,
-                       c.d_tab_bot, c0, nu, c.opts.mg_omega, b, x, t, res_t_mask, c.d_coarse_off, coarse_pool<T>(c),
-                       c.mask);
+                       c.d_tab_bot, c0, nu, w, b, x, t, res_t_mask, c.d_coarse_off, coarse_pool<T>(c), c.mask);
 }
-template void launch_mg_bottom<float>(Ctx &, int, int, int, const float *, float *, float *, unsigned);
-template void launch_mg_bottom<double>(Ctx &, int, int, int, const double *, double *, double *, unsigned);
+template void launch_mg_bottom<float>(Ctx &, int, int, int, const SweepW &, const float *, float *, float *, unsigned);
+template void launch_mg_bottom<double>(Ctx &, int, int, int, const SweepW &, const double *, double *, double *,
+                                       unsigned);
 
 // ------------------------------------------------------------------ projection step
 // d = D x* + r_pi ;  b_p (level 0) = -d  (so that -L phi = -d) ;  z_pi = -eta d.
@@ -920,8 +920,8 @@ void launch_wall_rhs(Ctx &c, double *f) {
 // explicit instantiations
 template void launch_to_level0<float>(Ctx &, const double *, float *, int, int);
 template void launch_to_level0<double>(Ctx &, const double *, double *, int, int);
-template void launch_smooth<float>(Ctx &, int, int, int, const float *, float *, const float *, bool);
-template void launch_smooth<double>(Ctx &, int, int, int, const double *, double *, const double *, bool);
+template void launch_smooth<float>(Ctx &, int, int, int, const float *, float *, const float *, bool, double);
+template void launch_smooth<double>(Ctx &, int, int, int, const double *, double *, const double *, bool, double);
 template void launch_restrict<float>(Ctx &, int, int, int, const float *, const float *, float *, float *);
 template void launch_restrict<double>(Ctx &, int, int, int, const double *, const double *, double *, double *);
 template void launch_prolong<float>(Ctx &, int, int, int, const float *, float *);

@@ -123,7 +123,7 @@ __device__ __forceinline__ void mg_tile(long long t, const LevDev &F, int lo[3],
 template <typename T>
 __global__ __launch_bounds__(256) void k_mg_down(const RepDev *reps, const LevDev *levs, const BlockEnt *tab,
                                                   int lev, int c0, const T *bpool, T *__restrict__ xpool, T *bcpool,
-                                                  double omega, const int *__restrict__ mask) {
+                                                  double omega1, double omega2, const int *__restrict__ mask) {
     __shared__ T sB[3][MGF_PLANE];
     __shared__ T sW[3][MGF_PLANE];
     __shared__ T sX1[3][MGF_PLANE];
@@ -136,7 +136,7 @@ __global__ __launch_bounds__(256) void k_mg_down(const RepDev *reps, const LevDe
     const LevDev &F = levs[be.rep * RB_MAXLEV + lev];
     const LevDev &C = levs[be.rep * RB_MAXLEV + lev + 1];
     const T s = (comp < 3) ? (T)(-R.eta) : (T)-1;
-    const T om = (T)omega;
+    const T om1 = (T)omega1, om2 = (T)omega2;
     int lo[3], hi[3], fr[3];
     bool crs[3];
     mg_tile(be.start, F, lo, hi);
@@ -182,11 +182,14 @@ __global__ __launch_bounds__(256) void k_mg_down(const RepDev *reps, const LevDe
 #pragma unroll
             for (int k = 0; k < MGF_NS; ++k) {
                 if (S.p[k] < 0) continue;
-                T w = (T)0;
-                if (S.in[k] && Z.in && !S.pin[k] && !Z.pin) w = jacobi_w<T>(om, s, fmad(daz, dz, S.dxy[k]));
+                T d = (T)0, x1 = (T)0;
+                if (S.in[k] && Z.in && !S.pin[k] && !Z.pin) {
+                    d = fmad(daz, dz, S.dxy[k]);
+                    x1 = nb[k] * jacobi_w<T>(om1, s, d);
+                }
                 sB[c][S.p[k]] = nb[k];
-                sW[c][S.p[k]] = w;
-                sX1[c][S.p[k]] = nb[k] * w;
+                sW[c][S.p[k]] = d;
+                sX1[c][S.p[k]] = x1;
             }
         }
         if (t + 1 <= NZ + 3) fetch(t + 1);
@@ -202,7 +205,7 @@ __global__ __launch_bounds__(256) void k_mg_down(const RepDev *reps, const LevDe
                 T x2 = (T)0;
                 if (S.in[k] && Z.in && !S.pin[k] && !Z.pin) {
                     const T lap = lap_planes<T>(sX1, cm, c, cp, S.p[k], PX, S.kinds[k], Z, F);
-                    x2 = jacobi_step<T>(sX1[c][S.p[k]], sB[c][S.p[k]], s, lap, sW[c][S.p[k]]);
+                    x2 = jacobi_step<T>(sX1[c][S.p[k]], sB[c][S.p[k]], s, lap, jacobi_w<T>(om2, s, sW[c][S.p[k]]));
                 }
                 sX2[c][S.p[k]] = x2;
             }
@@ -275,8 +278,8 @@ __global__ __launch_bounds__(256) void k_mg_down(const RepDev *reps, const LevDe
 template <typename T>
 __global__ __launch_bounds__(256) void k_mg_up(const RepDev *reps, const LevDev *levs, const BlockEnt *tab, int lev,
                                                 int c0, const T *__restrict__ bpool, const T *__restrict__ xinpool,
-                                                const T *__restrict__ xcpool, T *__restrict__ xoutpool, double omega,
-                                                const int *__restrict__ mask) {
+                                                const T *__restrict__ xcpool, T *__restrict__ xoutpool, double omega1,
+                                                double omega2, const int *__restrict__ mask) {
     __shared__ T sB[3][MGF_PLANE];
     __shared__ T sW[3][MGF_PLANE];
     __shared__ T sXP[3][MGF_PLANE];
@@ -288,7 +291,7 @@ __global__ __launch_bounds__(256) void k_mg_up(const RepDev *reps, const LevDev 
     const LevDev &F = levs[be.rep * RB_MAXLEV + lev];
     const LevDev &C = levs[be.rep * RB_MAXLEV + lev + 1];
     const T s = (comp < 3) ? (T)(-R.eta) : (T)-1;
-    const T om = (T)omega;
+    const T om1 = (T)omega1, om2 = (T)omega2;
     int lo[3], hi[3];
     mg_tile(be.start, F, lo, hi);
     const int PX = hi[0] - lo[0] + 4, PY = hi[1] - lo[1] + 4;
@@ -342,9 +345,9 @@ __global__ __launch_bounds__(256) void k_mg_up(const RepDev *reps, const LevDev 
 #pragma unroll
             for (int k = 0; k < MGF_NS; ++k) {
                 if (S.p[k] < 0) continue;
-                T w = (T)0, v = (T)0;
+                T d = (T)0, v = (T)0;
                 if (S.in[k] && Z.in && !S.pin[k] && !Z.pin) {
-                    w = jacobi_w<T>(om, s, fmad(daz, (T)F.inv_h2[2], S.dxy[k]));
+                    d = fmad(daz, (T)F.inv_h2[2], S.dxy[k]);
                     const ProlongAxis<T> px = prolong_axis<T>(S.g0[k], F.n[0], C.n[0], R.bc[0], comp == 0, comp);
                     const ProlongAxis<T> py = prolong_axis<T>(S.g1[k], F.n[1], C.n[1], R.bc[1], comp == 1, comp);
                     T acc = (T)0;
@@ -360,7 +363,7 @@ __global__ __launch_bounds__(256) void k_mg_up(const RepDev *reps, const LevDev 
                     v = nx[k] + acc;
                 }
                 sB[c][S.p[k]] = nb[k];
-                sW[c][S.p[k]] = w;
+                sW[c][S.p[k]] = d;
                 sXP[c][S.p[k]] = v;
             }
         }
@@ -377,7 +380,7 @@ __global__ __launch_bounds__(256) void k_mg_up(const RepDev *reps, const LevDev 
                 T v = (T)0;
                 if (S.in[k] && Z.in && !S.pin[k] && !Z.pin) {
                     const T lap = lap_planes<T>(sXP, cm, c, cp, S.p[k], PX, S.kinds[k], Z, F);
-                    v = jacobi_step<T>(sXP[c][S.p[k]], sB[c][S.p[k]], s, lap, sW[c][S.p[k]]);
+                    v = jacobi_step<T>(sXP[c][S.p[k]], sB[c][S.p[k]], s, lap, jacobi_w<T>(om1, s, sW[c][S.p[k]]));
                 }
                 sXS[c][S.p[k]] = v;
             }
@@ -395,7 +398,7 @@ __global__ __launch_bounds__(256) void k_mg_up(const RepDev *reps, const LevDev 
                 const int gi = S.gxy[k] + n01 * Z.gz;
                 if (S.pin[k] || Z.pin) { xo[gi] = (T)0; continue; }
                 const T lap = lap_planes<T>(sXS, cm, c, cp, S.p[k], PX, S.kinds[k], Z, F);
-                xo[gi] = jacobi_step<T>(sXS[c][S.p[k]], sB[c][S.p[k]], s, lap, sW[c][S.p[k]]);
+                xo[gi] = jacobi_step<T>(sXS[c][S.p[k]], sB[c][S.p[k]], s, lap, jacobi_w<T>(om2, s, sW[c][S.p[k]]));
             }
         }
         __syncthreads();
@@ -403,26 +406,29 @@ __global__ __launch_bounds__(256) void k_mg_up(const RepDev *reps, const LevDev 
 }
 
 template <typename T>
-void launch_mg_down(Ctx &c, int lev, int c0, int nc, const T *b, T *x) {
+void launch_mg_down(Ctx &c, int lev, int c0, int nc, const T *b, T *x, double omega1, double omega2) {
     int n = c.n_tab_mg[lev];
     if (n == 0) return;
     hipLaunchKernelGGL(k_mg_down<T>, dim3(n, nc), dim3(256), 0, c.stream, c.d_reps, c.d_levs, c.d_tab_mg[lev], lev,
-                       c0, b, x, (T *)b, c.opts.mg_omega, c.mask);
+                       c0, b, x, (T *)b, omega1, omega2, c.mask);
     HIP_OK(hipGetLastError());
 }
 
 template <typename T>
-void launch_mg_up(Ctx &c, int lev, int c0, int nc, const T *b, const T *xin, const T *xc, T *xout) {
+void launch_mg_up(Ctx &c, int lev, int c0, int nc, const T *b, const T *xin, const T *xc, T *xout, double omega1,
+                  double omega2) {
     int n = c.n_tab_mg[lev];
     if (n == 0) return;
     hipLaunchKernelGGL(k_mg_up<T>, dim3(n, nc), dim3(256), 0, c.stream, c.d_reps, c.d_levs, c.d_tab_mg[lev], lev, c0,
-                       b, xin, xc, xout, c.opts.mg_omega, c.mask);
+                       b, xin, xc, xout, omega1, omega2, c.mask);
     HIP_OK(hipGetLastError());
 }
 
-template void launch_mg_down<float>(Ctx &, int, int, int, const float *, float *);
-template void launch_mg_down<double>(Ctx &, int, int, int, const double *, double *);
-template void launch_mg_up<float>(Ctx &, int, int, int, const float *, const float *, const float *, float *);
-template void launch_mg_up<double>(Ctx &, int, int, int, const double *, const double *, const double *, double *);
+template void launch_mg_down<float>(Ctx &, int, int, int, const float *, float *, double, double);
+template void launch_mg_down<double>(Ctx &, int, int, int, const double *, double *, double, double);
+template void launch_mg_up<float>(Ctx &, int, int, int, const float *, const float *, const float *, float *, double,
+                                  double);
+template void launch_mg_up<double>(Ctx &, int, int, int, const double *, const double *, const double *, double *,
+                                   double, double);
 
 }  // namespace rb

@@ -222,6 +222,19 @@ static T *vcycle(Ctx &c, int c0, int nc) {
     const double sz = (double)sizeof(T) * nc;
     // pressure cycles (c0 == 3) may use their own sweep count
     const int nu = std::max(1, (c0 == 3 && c.opts.mg_sweeps_p > 0) ? c.opts.mg_sweeps_p : c.opts.mg_sweeps);
+    // weight of sweep k = 1 .. nu: mg_omega, or with mg_cheby = a > 0 the reciprocals
+    // of the roots of the degree-nu Chebyshev polynomial on [a, 2], the interval of
+    // the high-frequency eigenvalues of D^-1 A that the sweeps must damp
+    SweepW sw;
+    for (int k = 1; k <= RB_MAXSWEEP; ++k) {
+        double w = c.opts.mg_omega;
+        if (c.opts.mg_cheby > 0.0 && k <= nu) {
+            const double a = c.opts.mg_cheby, b = 2.0;
+            w = 1.0 / (0.5 * (b + a) + 0.5 * (b - a) * std::cos((2.0 * k - 1.0) * M_PI / (2.0 * nu)));
+        }
+        sw.w[k - 1] = w;
+    }
+    auto omega = [&](int k) { return sw.w[k - 1]; };
     bool fz[RB_MAXLEV];
     T *res[RB_MAXLEV];
     for (int l = 0; l < c.maxlev; ++l) {
@@ -235,7 +248,7 @@ static T *vcycle(Ctx &c, int c0, int nc) {
         if (c.n_tab_lev[l] == 0) continue;
         if (fz[l]) {
             if (l == 0) record(c, 2, true);
-            launch_mg_down<T>(c, l, c0, nc, B, X);
+            launch_mg_down<T>(c, l, c0, nc, B, X, omega(1), omega(2));
             if (l == 0) record(c, 2, false, sz * (2.0 * c.lev_cells[0] + c.lev_cells_c[0]));
             continue;
         }
@@ -243,7 +256,7 @@ static T *vcycle(Ctx &c, int c0, int nc) {
             T *out = ((nu - k) % 2 == 0) ? X : Tt;
             T *in = (out == X) ? Tt : X;
             if (l == 0) record(c, 1, true);
-            launch_smooth<T>(c, l, c0, nc, in, out, B, k == 1);
+            launch_smooth<T>(c, l, c0, nc, in, out, B, k == 1, omega(k));
             if (l == 0) record(c, 1, false, sz * c.lev_cells[0] * (k == 1 ? 2.0 : 3.0));
         }
         launch_restrict<T>(c, l, c0, nc, X, B, B, Tt);   // T(l) is free after the down sweeps
@@ -251,12 +264,12 @@ static T *vcycle(Ctx &c, int c0, int nc) {
     // levels lb .. nlev-1 of every replica in one launch; its result lands in res[lb]
     unsigned res_t = 0;
     for (int l = 0; l < c.maxlev; ++l) res_t |= (res[l] == Tt ? 1u : 0u) << l;
-    launch_mg_bottom<T>(c, c0, nc, nu, B, X, Tt, res_t);
+    launch_mg_bottom<T>(c, c0, nc, nu, sw, B, X, Tt, res_t);
     for (int l = c.maxlev - 2; l >= 0; --l) {
         if (c.n_tab_lev[l] == 0) continue;
         if (fz[l]) {
             if (l == 0) record(c, 3, true);
-            launch_mg_up<T>(c, l, c0, nc, B, X, res[l + 1], Tt);
+            launch_mg_up<T>(c, l, c0, nc, B, X, res[l + 1], Tt, omega(1), omega(2));
             if (l == 0) record(c, 3, false, sz * (3.0 * c.lev_cells[0] + c.lev_cells_c[0]));
             continue;
         }
@@ -264,7 +277,7 @@ static T *vcycle(Ctx &c, int c0, int nc) {
         T *in = X, *out = Tt;
         for (int k = 1; k <= nu; ++k) {
             if (l == 0) record(c, 1, true);
-            launch_smooth<T>(c, l, c0, nc, in, out, B, false);
+            launch_smooth<T>(c, l, c0, nc, in, out, B, false, omega(k));
             if (l == 0) record(c, 1, false, sz * c.lev_cells[0] * 3.0);
             std::swap(in, out);
         }
@@ -610,7 +623,9 @@ static int sem_step(Ctx &c, double *q, double *theta, const double *FT, const do
 static void validate(int nrep, const rbfib_grid *grids, const rbfib_bodies *bodies, const rbfib_opts &o) {
     if (nrep < 1 || !grids || !bodies) throw (int)RBFIB_EINVAL;
     if (!(o.tol > 0.0) || o.restart < 1 || o.restart > 200 || o.max_iter < 1 || o.mg_sweeps < 1 ||
-        !(o.mg_omega > 0.0) || !(o.blob_radius > 0.0) || !(o.rfd_delta > 0.0) || o.mg_bottom < 0 || o.mg_bottom > MGB_LDS / 1024)
+        !(o.mg_omega > 0.0) || !(o.blob_radius > 0.0) || !(o.rfd_delta > 0.0) || o.mg_bottom < 0 || o.mg_bottom > MGB_LDS / 1024 ||
+        !(o.mg_cheby >= 0.0 && o.mg_cheby < 2.0) || o.mg_sweeps > RB_MAXSWEEP || o.mg_sweeps_p < 0 ||
+        o.mg_sweeps_p > RB_MAXSWEEP)
         throw (int)RBFIB_EINVAL;
     for (int r = 0; r < nrep; ++r) {
         const rbfib_grid &g = grids[r];
@@ -1073,8 +1088,8 @@ void rbfib_default_opts(rbfib_opts *o) {
     o->restart = 100;
     o->max_iter = 600;
     o->precond_fp32 = 0;
-    o->mg_sweeps = 3;
-    o->mg_sweeps_p = 4;
+    o->mg_sweeps = 2;
+    o->mg_sweeps_p = 3;
     o->mg_omega = 0.9;
     o->blob_radius = 1.2;
     o->rfd_delta = 1e-5;
@@ -1083,6 +1098,7 @@ void rbfib_default_opts(rbfib_opts *o) {
     o->use_graphs = 1;
     o->mg_fused = 0;
     o->mg_bottom = 0;
+    o->mg_cheby = 0.27;
 }
 
 const char *rbfib_strerror(int code) {
@@ -1143,13 +1159,16 @@ void rbfib_destroy(rbfib_ctx *ctx) {
 int rbfib_set_opts(rbfib_ctx *ctx, const rbfib_opts *o) {
     if (!ctx || !o) return RBFIB_EINVAL;
     Ctx &c = ctx->c;
-    if (!(o->tol > 0.0) || o->max_iter < 1 || o->mg_sweeps < 1 || !(o->mg_omega > 0.0) || !(o->rfd_delta > 0.0))
+    if (!(o->tol > 0.0) || o->max_iter < 1 || o->mg_sweeps < 1 || !(o->mg_omega > 0.0) || !(o->rfd_delta > 0.0) ||
+        !(o->mg_cheby >= 0.0 && o->mg_cheby < 2.0) || o->mg_sweeps > RB_MAXSWEEP || o->mg_sweeps_p < 0 ||
+        o->mg_sweeps_p > RB_MAXSWEEP)
         return RBFIB_EINVAL;
     // fields fixed at creation: restart length, precision, blob radius, bottom kernel
     if (o->restart != c.opts.restart || (o->precond_fp32 != 0) != c.mg_fp32 || o->blob_radius != c.opts.blob_radius ||
         o->mg_bottom != c.opts.mg_bottom)
         return RBFIB_EINVAL;
     if (o->mg_sweeps != c.opts.mg_sweeps || o->mg_sweeps_p != c.opts.mg_sweeps_p || o->mg_omega != c.opts.mg_omega ||
+        o->mg_cheby != c.opts.mg_cheby ||
         o->mg_fused != c.opts.mg_fused)
         drop_graphs(c);
     c.opts = *o;

@@ -75,12 +75,15 @@ def test_bottom_vcycle_matches_separate_kernels(rb, name, fp32, budget):
     assert np.array_equal(a, b), float(np.abs(a - b).max() / np.abs(b).max())
 
 
+@pytest.mark.parametrize("cheby", [0.27, 0.0])
 @pytest.mark.parametrize("fp32", [1, 0])
-def test_bottom_with_fused_levels(rb, fp32):
+def test_bottom_with_fused_levels(rb, fp32, cheby):
+    """Fused level kernels above the bottom kernel, with per-sweep (Chebyshev) or
+    constant weights."""
     ws = CASES["batch_mixed_depths"]
-    print("mgbottom fused levels fp32", fp32, flush=True)
-    a = _precondition(rb, ws, fp32, 24, mg_sweeps=2, mg_sweeps_p=2, mg_fused=2)
-    b = _precondition(rb, ws, fp32, 0, mg_sweeps=2, mg_sweeps_p=2, mg_fused=0)
+    print("mgbottom fused levels fp32", fp32, "cheby", cheby, flush=True)
+    a = _precondition(rb, ws, fp32, 24, mg_sweeps=2, mg_sweeps_p=2, mg_fused=2, mg_cheby=cheby)
+    b = _precondition(rb, ws, fp32, 0, mg_sweeps=2, mg_sweeps_p=2, mg_fused=0, mg_cheby=cheby)
     assert np.array_equal(a, b)
 
 
