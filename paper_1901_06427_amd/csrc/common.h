@@ -430,7 +430,6 @@ struct MarkerSet {
     double *pair_w = nullptr;      // [pair_cap][3 comp][3 axis][4] weights on the tile's window
     long long *pair_lam = nullptr; // [pair_cap] offset of the marker's lambda in a state vector
     long long pair_cap = 0;
-    int *flag = nullptr;      // [ntiles] scratch
     double *wc = nullptr;     // [nm][3 comp][3 axis][4] folded signed 1-D kernel weights
     int *ic = nullptr;        // [nm][3][3][4] folded grid indices of those weights
 };
@@ -507,6 +506,7 @@ struct Ctx {
 
     // marker sets: 0 = Q^n, 1 = Q+, 2 = Q-, 3 = new configuration
     MarkerSet ms[4];
+    int *d_scan = nullptr;      // block sums of the tile scans
     int *d_flags = nullptr;     // [nrep]: bit 0 marker outside the domain, bit 1 bodies too close
     int *h_flags = nullptr;     // pinned host copy
 

@@ -77,22 +77,100 @@ __global__ void k_markers(const RepDev *reps, const int *marker_body, const int 
     if (outside) atomicOr(&flags[body_rep[p]], 1);
 }
 
-// exclusive scan of tile counts (one workgroup), zero the fill counters
-__global__ void k_tile_scan(const int *count, int *start, int *fill, int ntiles) {
-    __shared__ int part[1024];
-    int per = (ntiles + blockDim.x - 1) / blockDim.x;
-    int b = threadIdx.x * per, e = min(ntiles, b + per);
-    int s = 0;
-    for (int i = b; i < e; ++i) s += count[i];
-    part[threadIdx.x] = s;
+// ------------------------------------------------------------------ scans over tiles
+// Exclusive scan of n ints in three launches: sums of SCAN_B-entry blocks, one
+// workgroup scanning the block sums, and each block's own scan plus its offset.
+// pred = 1 scans (v > 0) instead of v and writes the indices with v > 0 to list
+// (a stable compaction); otherwise out = the exclusive prefix and fill = 0.
+#define SCAN_T 256
+#define SCAN_B (4 * SCAN_T)
+
+__device__ __forceinline__ int scan_val(const int *in, int i, int n, int pred) {
+    if (i >= n) return 0;
+    const int v = in[i];
+    return pred ? (v > 0 ? 1 : 0) : v;
+}
+
+// exclusive scan of one value per thread across the workgroup (SCAN_T threads)
+__device__ __forceinline__ int block_exscan(int v, int *sh, int &total) {
+    const int t = threadIdx.x;
+    sh[t] = v;
     __syncthreads();
-    if (threadIdx.x == 0) {
-        int acc = 0;
-        for (int i = 0; i < (int)blockDim.x; ++i) { int v = part[i]; part[i] = acc; acc += v; }
+    for (int o = 1; o < SCAN_T; o <<= 1) {
+        const int a = t >= o ? sh[t - o] : 0;
+        __syncthreads();
+        sh[t] += a;
+        __syncthreads();
     }
+    total = sh[SCAN_T - 1];
+    const int ex = sh[t] - v;
     __syncthreads();
-    int acc = part[threadIdx.x];
-    for (int i = b; i < e; ++i) { start[i] = acc; acc += count[i]; fill[i] = 0; }
+    return ex;
+}
+
+__global__ __launch_bounds__(SCAN_T) void k_scan_sums(const int *in, int n, int pred, int *bsum) {
+    __shared__ int sh[SCAN_T];
+    const int base = blockIdx.x * SCAN_B + 4 * threadIdx.x;
+    int v = 0;
+    for (int k = 0; k < 4; ++k) v += scan_val(in, base + k, n, pred);
+    int total;
+    block_exscan(v, sh, total);
+    if (threadIdx.x == 0) bsum[blockIdx.x] = total;
+}
+
+// one workgroup: exclusive scan of the nb block sums in place; the grand total to *total
+__global__ __launch_bounds__(SCAN_T) void k_scan_blocks(int *bsum, int nb, int *total) {
+    __shared__ int sh[SCAN_T];
+    int carry = 0;
+    for (int b0 = 0; b0 < nb; b0 += SCAN_T) {
+        const int i = b0 + threadIdx.x;
+        const int v = i < nb ? bsum[i] : 0;
+        int tot;
+        const int ex = block_exscan(v, sh, tot);
+        if (i < nb) bsum[i] = carry + ex;
+        carry += tot;
+    }
+    if (threadIdx.x == 0 && total) *total = carry;
+}
+
+__global__ __launch_bounds__(SCAN_T) void k_scan_local(const int *in, int n, int pred, const int *boff, int *out,
+                                                       int *fill, int *list) {
+    __shared__ int sh[SCAN_T];
+    const int base = blockIdx.x * SCAN_B + 4 * threadIdx.x;
+    int v[4], s = 0;
+    for (int k = 0; k < 4; ++k) { v[k] = scan_val(in, base + k, n, pred); s += v[k]; }
+    int total;
+    int ex = boff[blockIdx.x] + block_exscan(s, sh, total);
+    for (int k = 0; k < 4; ++k) {
+        const int i = base + k;
+        if (i < n) {
+            if (pred) {
+                if (v[k]) list[ex] = i;
+            } else {
+                out[i] = ex;
+                if (fill) fill[i] = 0;
+            }
+        }
+        ex += v[k];
+    }
+}
+
+// start = exclusive scan of count, fill = 0
+static void scan_tiles(Ctx &c, const int *count, int *start, int *fill) {
+    const int nb = (c.ntiles + SCAN_B - 1) / SCAN_B;
+    hipLaunchKernelGGL(k_scan_sums, dim3(nb), dim3(SCAN_T), 0, c.stream, count, c.ntiles, 0, c.d_scan);
+    hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(SCAN_T), 0, c.stream, c.d_scan, nb, (int *)nullptr);
+    hipLaunchKernelGGL(k_scan_local, dim3(nb), dim3(SCAN_T), 0, c.stream, count, c.ntiles, 0, c.d_scan, start, fill,
+                       (int *)nullptr);
+}
+
+// list = the tiles with count > 0 in order, *n_out = how many
+static void compact_tiles(Ctx &c, const int *count, int *list, int *n_out) {
+    const int nb = (c.ntiles + SCAN_B - 1) / SCAN_B;
+    hipLaunchKernelGGL(k_scan_sums, dim3(nb), dim3(SCAN_T), 0, c.stream, count, c.ntiles, 1, c.d_scan);
+    hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(SCAN_T), 0, c.stream, c.d_scan, nb, n_out);
+    hipLaunchKernelGGL(k_scan_local, dim3(nb), dim3(SCAN_T), 0, c.stream, count, c.ntiles, 1, c.d_scan,
+                       (int *)nullptr, (int *)nullptr, list);
 }
 
 __global__ void k_tile_place(const int *tile, const int *start, int *fill, int *perm, int nm) {
@@ -223,30 +301,6 @@ __global__ void k_pair_weights(const RepDev *reps, const int *tile_rep, const do
     pair_lam[s] = R.off + 4 * R.N + 3LL * (m - R.m0);
 }
 
-__global__ void k_tile_flag(const int *count, int *flag, int ntiles) {
-    int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t < ntiles) flag[t] = count[t] > 0;
-}
-
-// stable compaction of flagged tiles (one workgroup)
-__global__ void k_compact(const int *flag, int *list, int *n_out, int ntiles) {
-    __shared__ int part[1024];
-    int per = (ntiles + blockDim.x - 1) / blockDim.x;
-    int b = threadIdx.x * per, e = min(ntiles, b + per);
-    int s = 0;
-    for (int i = b; i < e; ++i) s += flag[i];
-    part[threadIdx.x] = s;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        int acc = 0;
-        for (int i = 0; i < (int)blockDim.x; ++i) { int v = part[i]; part[i] = acc; acc += v; }
-        *n_out = acc;
-    }
-    __syncthreads();
-    int acc = part[threadIdx.x];
-    for (int i = b; i < e; ++i) if (flag[i]) list[acc++] = i;
-}
-
 void launch_markers(Ctx &c, MarkerSet &ms, const double *q, const double *theta) {
     HIP_OK(hipMemsetAsync(ms.tile_count, 0, sizeof(int) * c.ntiles, c.stream));
     HIP_OK(hipMemsetAsync(ms.pair_count, 0, sizeof(int) * c.ntiles, c.stream));
@@ -254,8 +308,7 @@ void launch_markers(Ctx &c, MarkerSet &ms, const double *q, const double *theta)
     if (c.nm > 0)
         hipLaunchKernelGGL(k_markers, dim3(nb), dim3(256), 0, c.stream, c.d_reps, c.d_marker_body, c.d_body_rep, q,
                            theta, c.d_rref, c.nm, ms.r, ms.d, ms.tile, ms.tile_count, c.d_flags, ms.wc, ms.ic);
-    hipLaunchKernelGGL(k_tile_scan, dim3(1), dim3(1024), 0, c.stream, ms.tile_count, ms.tile_start, ms.tile_fill,
-                       c.ntiles);
+    scan_tiles(c, ms.tile_count, ms.tile_start, ms.tile_fill);
     if (c.nm > 0) {
         hipLaunchKernelGGL(k_tile_place, dim3(nb), dim3(256), 0, c.stream, ms.tile, ms.tile_start, ms.tile_fill,
                            ms.perm, c.nm);
@@ -265,8 +318,7 @@ void launch_markers(Ctx &c, MarkerSet &ms, const double *q, const double *theta)
                            ms.wc, ms.ic, c.nm, 0, ms.pair_count, ms.pair_start, ms.pair_fill, ms.pair_m,
                            ms.pair_tile, ms.pair_cap, c.d_flags);
     }
-    hipLaunchKernelGGL(k_tile_scan, dim3(1), dim3(1024), 0, c.stream, ms.pair_count, ms.pair_start, ms.pair_fill,
-                       c.ntiles);
+    scan_tiles(c, ms.pair_count, ms.pair_start, ms.pair_fill);
     if (c.nm > 0) {
         hipLaunchKernelGGL(k_pair_tiles, dim3(nb), dim3(256), 0, c.stream, c.d_reps, c.d_marker_body, c.d_body_rep,
                            ms.wc, ms.ic, c.nm, 1, ms.pair_count, ms.pair_start, ms.pair_fill, ms.pair_m,
@@ -277,9 +329,7 @@ void launch_markers(Ctx &c, MarkerSet &ms, const double *q, const double *theta)
                            c.d_reps, c.d_tile_rep, ms.wc, ms.ic, ms.pair_start, ms.pair_count, c.ntiles, ms.pair_m,
                            ms.pair_tile, ms.pair_cap, ms.pair_w, ms.pair_lam);
     }
-    hipLaunchKernelGGL(k_tile_flag, dim3((c.ntiles + 255) / 256), dim3(256), 0, c.stream, ms.pair_count, ms.flag,
-                       c.ntiles);
-    hipLaunchKernelGGL(k_compact, dim3(1), dim3(1024), 0, c.stream, ms.flag, ms.active, ms.n_active, c.ntiles);
+    compact_tiles(c, ms.pair_count, ms.active, ms.n_active);
 }
 
 // ------------------------------------------------------------------ spreading (gather)

@@ -59,8 +59,8 @@ __global__ void k_dot_reduce(const int *first, const int *nblk, const double *pa
 
 void launch_dots(Ctx &c, const double *V, int nvec, const double *w, double *out, const int *mask) {
     int stride = c.m + 1;
-    hipLaunchKernelGGL(k_dot_partial, dim3(c.n_tab_vec), dim3(RB_BLOCK), 0, c.stream, c.d_reps, c.d_tab_vec, V, c.L,
-                       nvec, w, c.partial, stride, mask);
+    hipLaunchKernelGGL(k_dot_partial, dim3(c.n_tab_vec), dim3(RB_BLOCK), 0, c.stream, c.d_reps, c.d_tab_vec, V,
+                       c.L, nvec, w, c.partial, stride, mask);
     hipLaunchKernelGGL(k_dot_reduce, dim3(c.nrep, nvec), dim3(64), 0, c.stream, c.d_vec_first, c.d_vec_nblk,
                        c.partial, stride, out, c.m + 1, mask, 0);
 }
@@ -263,9 +263,12 @@ __global__ void k_trisolve(int nrep, int m, const double *H, const double *gv, c
 }
 
 // x += sum_{i < jf} y_i Z_i
-__global__ __launch_bounds__(RB_BLOCK) void k_update_x(const RepDev *reps, const BlockEnt *tab, const double *Z,
-                                                       long long L, int m, const double *y, const int *jf,
-                                                       const int *cyc, double *x) {
+// (the column loop is unrolled so that eight loads, one basis vector apart, are in
+// flight together; the sum keeps its order)
+__global__ __launch_bounds__(RB_BLOCK) void k_update_x(const RepDev *reps, const BlockEnt *tab,
+                                                       const double *__restrict__ Z, long long L, int m,
+                                                       const double *__restrict__ y, const int *jf, const int *cyc,
+                                                       double *__restrict__ x) {
     BlockEnt be = tab[blockIdx.x];
     if (!cyc[be.rep]) return;
     const RepDev &R = reps[be.rep];
@@ -275,6 +278,7 @@ __global__ __launch_bounds__(RB_BLOCK) void k_update_x(const RepDev *reps, const
     long long e = R.off + min(be.start + (long long)RB_CHUNK, R.len);
     for (long long g = b + threadIdx.x; g < e; g += RB_BLOCK) {
         double acc = 0.0;
+#pragma unroll 8
         for (int i = 0; i < n; ++i) acc += yr[i] * Z[(long long)i * L + g];
         x[g] += acc;
     }

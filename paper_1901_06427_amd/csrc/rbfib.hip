@@ -955,7 +955,6 @@ static void build(Ctx &c, int nrep, const rbfib_grid *grids, const rbfib_bodies 
         ms.tile_start = dalloc<int>(c.ntiles);
         ms.tile_fill = dalloc<int>(c.ntiles);
         ms.active = dalloc<int>(c.ntiles);
-        ms.flag = dalloc<int>(c.ntiles);
         ms.n_active = dalloc<int>(1);
         ms.wc = dalloc<double>(36 * (size_t)std::max(c.nm, 1));
         ms.ic = dalloc<int>(36 * (size_t)std::max(c.nm, 1));
@@ -973,6 +972,7 @@ static void build(Ctx &c, int nrep, const rbfib_grid *grids, const rbfib_bodies 
     c.graphs[0].assign(c.opts.restart, nullptr);
     c.graphs[1].assign(c.opts.restart, nullptr);
     c.d_flags = dalloc<int>(std::max(nrep, 4));
+    c.d_scan = dalloc<int>((c.ntiles + 1023) / 1024 + 1);
     HIP_OK(hipHostMalloc((void **)&c.h_flags, sizeof(int) * std::max(nrep, 4), hipHostMallocDefault));
     HIP_OK(hipHostMalloc((void **)&c.h_count, sizeof(int), hipHostMallocDefault));
     c.d_count = dalloc<int>(1);
@@ -1048,11 +1048,11 @@ static void free_all(Ctx &c) {
     for (int k = 0; k < 4; ++k) {
         MarkerSet &ms = c.ms[k];
         F(ms.r); F(ms.d); F(ms.tile); F(ms.perm); F(ms.tile_count); F(ms.tile_start); F(ms.tile_fill);
-        F(ms.active); F(ms.flag); F(ms.n_active); F(ms.wc); F(ms.ic);
+        F(ms.active); F(ms.n_active); F(ms.wc); F(ms.ic);
         F(ms.pair_count); F(ms.pair_start); F(ms.pair_fill); F(ms.pair_m); F(ms.pair_tile); F(ms.pair_w);
         F(ms.pair_lam);
     }
-    F(c.d_flags); F(c.d_count); F(c.d_active_len);
+    F(c.d_flags); F(c.d_scan); F(c.d_count); F(c.d_active_len);
     if (c.h_flags) (void)hipHostFree(c.h_flags);
     if (c.h_count) (void)hipHostFree(c.h_count);
     F(c.V); F(c.Z); F(c.W); F(c.xsol); F(c.rhs); F(c.tmp); F(c.xR); F(c.xS); F(c.partial);
