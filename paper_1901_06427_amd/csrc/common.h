@@ -477,7 +477,7 @@ struct Ctx {
 
     // block tables
     BlockEnt *d_tab_cells = nullptr; int n_tab_cells = 0;         // level 0, all replicas, per cell chunk
-    BlockEnt *d_tab_cells1 = nullptr; int n_tab_cells1 = 0;       // the same with one cell per thread (apply)
+    BlockEnt *d_tab_cells2 = nullptr; int n_tab_cells2 = 0;       // two cells per thread (apply)
     BlockEnt *d_tab_vec = nullptr; int n_tab_vec = 0;             // state chunks
     std::vector<int> vec_first, vec_nblk;                         // per replica block range
     int *d_vec_first = nullptr, *d_vec_nblk = nullptr;

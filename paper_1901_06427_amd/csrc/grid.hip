@@ -64,15 +64,116 @@ __device__ __forceinline__ void unlin(long long lin, const LevDev &L, int idx[3]
 
 // ------------------------------------------------------------------ fused fluid apply
 // y_c = -eta Lm_c v + (G pi)_c for c = x, y, z;  y_pi = -(D v).  Pinned slots -> 0.
-// One thread per cell (npt cells, RB_BLOCK apart).  Neighbour offsets and boundary rules are computed first and
-// applied with selects, so the loads of all three components are in flight together;
-// the divergence reuses each component's +e_c neighbour.
+// The three momentum rows and the divergence of one cell from its gathered values:
+// self[c] = v_c of the cell, nb[c][2a] / nb[c][2a+1] its -e_a / +e_a neighbours (rule
+// kd), pm[c] the pressure at -e_c, pc the cell's.  Explicit fused multiply-adds, so
+// both gather paths below round identically.
+__device__ __forceinline__ void apply_cell(const RepDev &R, const double self[3], const double nb[3][6],
+                                           const double pm[3], double pc, const int kd[3][6], const bool pin[3],
+                                           double out[4]) {
+    const double ih = R.inv_h, ih2 = R.inv_h * R.inv_h;
+    double div = 0.0;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        double lap = 0.0;
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+            lap = lap_acc<double>(pick<double>(kd[c][2 * a + 1], nb[c][2 * a + 1], self[c]), self[c],
+                                  pick<double>(kd[c][2 * a], nb[c][2 * a], self[c]), ih2, lap);
+        // D v: face +e_c (zero beyond a wall, wrapped when periodic) minus face c of this cell
+        const double hi = pick<double>(kd[c][2 * c + 1], nb[c][2 * c + 1], self[c]);
+        div = fmad(hi - (pin[c] ? 0.0 : self[c]), ih, div);
+        out[c] = pin[c] ? 0.0 : fmad(-R.eta, lap, (pc - pm[c]) * ih);
+    }
+    out[3] = -div;
+}
+
+// Two consecutive x cells per thread (rows of even length, blocks of 512 cells,
+// 16-byte aligned fields): the pair, its y and z neighbour pairs and the pressure
+// pairs move as 16-byte loads and stores, the x neighbours outside the pair as
+// scalars; the y and z rules are shared by the pair.
+__device__ __forceinline__ void apply_row2(const RepDev &R, const BlockEnt &be, const double *__restrict__ xr,
+                                           double *__restrict__ yr) {
+    const long long g0 = be.start + 2LL * threadIdx.x;
+    if (g0 >= R.N) return;
+    const int lin = (int)g0, N = (int)R.N, n0 = R.n[0];
+    int idx[3];
+    unlin(lin, R, idx);
+    const int st[3] = {1, R.n[0], R.n[0] * R.n[1]};
+    const double *p = xr + 3LL * N;
+    auto ld2 = [](const double *q) { return *reinterpret_cast<const double2 *>(q); };
+    double self[2][3], nb[2][3][6], pm[2][3];
+    int kd[2][3][6];
+    bool pin[2][3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const double *u = xr + (long long)c * N;
+        const double2 sp = ld2(u + lin);
+        self[0][c] = sp.x;
+        self[1][c] = sp.y;
+#pragma unroll
+        for (int a = 1; a < 3; ++a) {
+            const int km = nbr_kind(idx[a], -1, R.n[a], R.bc[a], a, c);
+            const int kp = nbr_kind(idx[a], +1, R.n[a], R.bc[a], a, c);
+            const int om = km ? 0 : (idx[a] == 0 ? (R.n[a] - 1) * st[a] : -st[a]);
+            const int op = kp ? 0 : (idx[a] == R.n[a] - 1 ? -(R.n[a] - 1) * st[a] : st[a]);
+            const double2 vm = ld2(u + lin + om), vp = ld2(u + lin + op);
+            kd[0][c][2 * a] = kd[1][c][2 * a] = km;
+            kd[0][c][2 * a + 1] = kd[1][c][2 * a + 1] = kp;
+            nb[0][c][2 * a] = vm.x;
+            nb[1][c][2 * a] = vm.y;
+            nb[0][c][2 * a + 1] = vp.x;
+            nb[1][c][2 * a + 1] = vp.y;
+        }
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            kd[q][c][0] = nbr_kind(idx[0] + q, -1, n0, R.bc[0], 0, c);
+            kd[q][c][1] = nbr_kind(idx[0] + q, +1, n0, R.bc[0], 0, c);
+        }
+        // x neighbours: inside the pair, or one cell beyond it (wrapped when periodic)
+        nb[0][c][0] = kd[0][c][0] ? sp.x : u[lin + (idx[0] == 0 ? n0 - 1 : -1)];
+        nb[0][c][1] = sp.y;
+        nb[1][c][0] = sp.x;
+        nb[1][c][1] = kd[1][c][1] ? sp.y : u[lin + 1 + (idx[0] + 1 == n0 - 1 ? -(n0 - 1) : 1)];
+        // pressure at -e_c
+        if (c == 0) {
+            pm[0][0] = p[lin + (idx[0] > 0 ? -1 : n0 - 1)];
+            pm[1][0] = p[lin];
+        } else {
+            const double2 pp = ld2(p + lin + (idx[c] > 0 ? -st[c] : (R.n[c] - 1) * st[c]));
+            pm[0][c] = pp.x;
+            pm[1][c] = pp.y;
+        }
+        pin[0][c] = R.bc[c] == RBFIB_WALL && (c == 0 ? idx[0] : idx[c]) == 0;
+        pin[1][c] = R.bc[c] == RBFIB_WALL && (c == 0 ? idx[0] + 1 : idx[c]) == 0;
+    }
+    const double2 pcv = ld2(p + lin);
+    double o0[4], o1[4];
+    apply_cell(R, self[0], nb[0], pm[0], pcv.x, kd[0], pin[0], o0);
+    apply_cell(R, self[1], nb[1], pm[1], pcv.y, kd[1], pin[1], o1);
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+        *reinterpret_cast<double2 *>(yr + (long long)c * N + lin) = make_double2(o0[c], o1[c]);
+}
+
+// One thread per cell (npt cells, RB_BLOCK apart), or apply_row2 where it applies.
+// Neighbour offsets and boundary rules are computed first and applied with selects,
+// so the loads of all three components are in flight together; the divergence
+// reuses each component's +e_c neighbour.
 __global__ __launch_bounds__(RB_BLOCK) void k_apply_fluid(const RepDev *reps, const BlockEnt *tab,
                                                           const double *__restrict__ x, double *__restrict__ y,
                                                           const int *__restrict__ mask) {
     const BlockEnt be = tab[xcd_block(blockIdx.x, gridDim.x)];
     if (mask && !mask[be.rep]) return;
     const RepDev &R = reps[be.rep];
+    const double *xr = x + R.off;
+    double *yr = y + R.off;
+    // uniform per block: even rows, even field length, 16-byte aligned fields
+    if (be.npt == 2 && R.n[0] % 2 == 0 && R.N % 2 == 0 && ((reinterpret_cast<unsigned long long>(xr) & 15) == 0) &&
+        ((reinterpret_cast<unsigned long long>(yr) & 15) == 0)) {
+        apply_row2(R, be, xr, yr);
+        return;
+    }
     for (int t_ = 0; t_ < be.npt; ++t_) {
     const long long l = be.start + threadIdx.x + (long long)t_ * RB_BLOCK;
     if (l >= R.N) break;
@@ -80,9 +181,6 @@ __global__ __launch_bounds__(RB_BLOCK) void k_apply_fluid(const RepDev *reps, co
     int idx[3];
     unlin(lin, R, idx);
     const int st[3] = {1, R.n[0], R.n[0] * R.n[1]};
-    const double *xr = x + R.off;
-    double *yr = y + R.off;
-    const double ih = R.inv_h, ih2 = R.inv_h * R.inv_h;
     int kd[3][6], off[3][6], offp[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
@@ -96,6 +194,7 @@ __global__ __launch_bounds__(RB_BLOCK) void k_apply_fluid(const RepDev *reps, co
         offp[c] = idx[c] > 0 ? -st[c] : (R.n[c] - 1) * st[c];   // pressure at -e_c (unused when pinned)
     }
     double self[3], nb[3][6], pm[3];
+    bool pin[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
         const double *u = xr + (long long)c * N;
@@ -103,28 +202,17 @@ __global__ __launch_bounds__(RB_BLOCK) void k_apply_fluid(const RepDev *reps, co
 #pragma unroll
         for (int q = 0; q < 6; ++q) nb[c][q] = u[lin + off[c][q]];
         pm[c] = xr[3LL * N + lin + offp[c]];
+        pin[c] = pinned(c, idx, R.bc);
     }
-    const double pc = xr[3LL * N + lin];
-    double div = 0.0;
+    double out[4];
+    apply_cell(R, self, nb, pm, xr[3LL * N + lin], kd, pin, out);
 #pragma unroll
-    for (int c = 0; c < 3; ++c) {
-        const bool pin = pinned(c, idx, R.bc);
-        double lap = 0.0;
-#pragma unroll
-        for (int a = 0; a < 3; ++a)
-            lap = lap_acc<double>(pick<double>(kd[c][2 * a + 1], nb[c][2 * a + 1], self[c]), self[c],
-                                  pick<double>(kd[c][2 * a], nb[c][2 * a], self[c]), ih2, lap);
-        // D v: face +e_c (zero beyond a wall, wrapped when periodic) minus face c of this cell
-        const double hi = pick<double>(kd[c][2 * c + 1], nb[c][2 * c + 1], self[c]);
-        div += (hi - (pin ? 0.0 : self[c])) * ih;
-        yr[(long long)c * N + lin] = pin ? 0.0 : -R.eta * lap + (pc - pm[c]) * ih;
-    }
-    yr[3LL * N + lin] = -div;
+    for (int c = 0; c < 4; ++c) yr[(long long)c * N + lin] = out[c];
     }
 }
 
 void launch_apply_fluid(Ctx &c, const double *x, double *y) {
-    hipLaunchKernelGGL(k_apply_fluid, dim3(c.n_tab_cells1), dim3(RB_BLOCK), 0, c.stream, c.d_reps, c.d_tab_cells1,
+    hipLaunchKernelGGL(k_apply_fluid, dim3(c.n_tab_cells2), dim3(RB_BLOCK), 0, c.stream, c.d_reps, c.d_tab_cells2,
                        x, y, c.mask);
 }
 

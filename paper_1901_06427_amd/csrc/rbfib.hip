@@ -769,12 +769,12 @@ static void build(Ctx &c, int nrep, const rbfib_grid *grids, const rbfib_bodies 
     auto gchunks = [](std::vector<BlockEnt> &tab, int rep, long long n, int npt) {
         for (long long s = 0; s < n; s += (long long)RB_BLOCK * npt) tab.push_back(BlockEnt{rep, npt, s});
     };
-    std::vector<BlockEnt> tcells, tcells1, tvec;
+    std::vector<BlockEnt> tcells, tcells2, tvec;
     c.vec_first.resize(nrep);
     c.vec_nblk.resize(nrep);
     for (int r = 0; r < nrep; ++r) {
         gchunks(tcells, r, c.reps[r].N, mg_npt);
-        gchunks(tcells1, r, c.reps[r].N, 1);
+        gchunks(tcells2, r, c.reps[r].N, 2);
         c.vec_first[r] = (int)tvec.size();
         chunks(tvec, r, c.reps[r].len, RB_CHUNK);
         c.vec_nblk[r] = (int)tvec.size() - c.vec_first[r];
@@ -782,8 +782,8 @@ static void build(Ctx &c, int nrep, const rbfib_grid *grids, const rbfib_bodies 
     c.n_tab_cells = (int)tcells.size();
     c.n_tab_vec = (int)tvec.size();
     c.d_tab_cells = upload(c, tcells);
-    c.n_tab_cells1 = (int)tcells1.size();
-    c.d_tab_cells1 = upload(c, tcells1);
+    c.n_tab_cells2 = (int)tcells2.size();
+    c.d_tab_cells2 = upload(c, tcells2);
     c.d_tab_vec = upload(c, tvec);
     c.d_vec_first = upload(c, c.vec_first);
     c.d_vec_nblk = upload(c, c.vec_nblk);
@@ -1039,7 +1039,7 @@ static void free_all(Ctx &c) {
     auto F = [](void *p) { if (p) (void)hipFree(p); };
     F(c.d_reps); F(c.d_levs); F(c.d_marker_body); F(c.d_body_rep); F(c.d_body_off); F(c.d_tile_rep); F(c.d_rref);
     F(c.d_body_shape); F(c.d_shapes); F(c.d_shape_data); F(c.d_body_len);
-    F(c.d_tab_cells); F(c.d_tab_cells1); F(c.d_tab_vec); F(c.d_vec_first); F(c.d_vec_nblk); F(c.d_tab_bot);
+    F(c.d_tab_cells); F(c.d_tab_cells2); F(c.d_tab_vec); F(c.d_vec_first); F(c.d_vec_nblk); F(c.d_tab_bot);
     for (int l = 0; l < RB_MAXLEV; ++l) {
         F(c.d_tab_lev[l]); F(c.d_tab_crs[l]); F(c.d_tab_all[l]); F(c.d_tab_mg[l]);
     }
