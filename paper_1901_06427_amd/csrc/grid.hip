@@ -218,17 +218,38 @@ void launch_apply_fluid(Ctx &c, const double *x, double *y) {
 
 // ------------------------------------------------------------------ multigrid
 // Level pools hold 4 fields per (replica, level): comp c at lev.off + c * lev.N.
+// FP32 cell kernels on four consecutive x cells per thread: blocks of 1024 cells
+// (four per thread), rows a multiple of four long, and the replica's FP64 state
+// 16-byte aligned (the level pools always are for such rows).  Uniform per block.
+__device__ __forceinline__ bool cells_row4(const BlockEnt &be, const RepDev &R, const double *state) {
+    return be.npt == 4 && R.n[0] % 4 == 0 && ((reinterpret_cast<unsigned long long>(state + R.off) & 15) == 0);
+}
+
+__device__ __forceinline__ double2 ld_d2(const double *q) { return *reinterpret_cast<const double2 *>(q); }
+__device__ __forceinline__ float4 ld_f4(const float *q) { return *reinterpret_cast<const float4 *>(q); }
+
 template <typename T>
-__global__ void k_to_level0(const RepDev *reps, const LevDev *levs, const BlockEnt *tab, const double *src,
-                            T *b, int c0, const int *__restrict__ mask) {
+__global__ void k_to_level0(const RepDev *reps, const LevDev *levs, const BlockEnt *tab,
+                            const double *__restrict__ src, T *__restrict__ b, int c0, const int *__restrict__ mask) {
     BlockEnt be = tab[xcd_block(blockIdx.x, gridDim.x)];
     if (mask && !mask[be.rep]) return;
     int comp = c0 + blockIdx.y;
     const RepDev &R = reps[be.rep];
+    const LevDev &Lv = levs[be.rep * RB_MAXLEV];
+    if constexpr (sizeof(T) == 4) {
+        if (cells_row4(be, R, src)) {
+            const long long lin = be.start + 4LL * threadIdx.x;
+            if (lin >= R.N) return;
+            const double *s = src + R.off + comp * R.N + lin;
+            const double2 a = ld_d2(s), c = ld_d2(s + 2);
+            *reinterpret_cast<float4 *>(b + Lv.off + comp * Lv.N + lin) =
+                make_float4((float)a.x, (float)a.y, (float)c.x, (float)c.y);
+            return;
+        }
+    }
     for (int t_ = 0; t_ < be.npt; ++t_) {
     long long lin = be.start + threadIdx.x + (long long)t_ * RB_BLOCK;
     if (lin >= R.N) continue;
-    const LevDev &Lv = levs[be.rep * RB_MAXLEV];
     b[Lv.off + comp * Lv.N + lin] = (T)src[R.off + comp * R.N + lin];
     }
 }
@@ -825,6 +846,13 @@ template void launch_mg_bottom<double>(Ctx &, int, int, int, const SweepW &, con
 
 // ------------------------------------------------------------------ projection step
 // d = D x* + r_pi ;  b_p (level 0) = -d  (so that -L phi = -d) ;  z_pi = -eta d.
+// div sums the three axes in order with fused multiply-adds in both paths.
+__device__ __forceinline__ void proj_div_out(double div, double rp, double eta, float &bp, double &zp) {
+    const double d = div + rp;
+    bp = (float)(-d);
+    zp = -eta * d;
+}
+
 template <typename T>
 __global__ void k_proj_div(const RepDev *reps, const LevDev *levs, const BlockEnt *tab, const T *__restrict__ xv,
                            const double *__restrict__ r, T *__restrict__ bp, double *__restrict__ z, const int *__restrict__ mask) {
@@ -832,9 +860,54 @@ __global__ void k_proj_div(const RepDev *reps, const LevDev *levs, const BlockEn
     if (mask && !mask[be.rep]) return;
     const RepDev &R = reps[be.rep];
     const LevDev &Lv = levs[be.rep * RB_MAXLEV];
+    const long long N = R.N;
+    if constexpr (sizeof(T) == 4) {
+        if (cells_row4(be, R, r) && cells_row4(be, R, z)) {
+            const long long g0 = be.start + 4LL * threadIdx.x;
+            if (g0 >= N) return;
+            const int lin = (int)g0, n0 = R.n[0], n01 = R.n[0] * R.n[1];
+            int idx[3];
+            unlin(lin, R, idx);
+            const float *u0 = (const float *)xv + Lv.off, *u1 = u0 + Lv.N, *u2 = u1 + Lv.N;
+            // x: the four faces and the one after them
+            const float4 a0 = ld_f4(u0 + lin);
+            float after;
+            if (idx[0] + 4 < n0) after = u0[lin + 4];
+            else after = (R.bc[0] == RBFIB_PERIODIC) ? u0[lin + 4 - n0] : 0.f;
+            // y and z: this row and the next (wrapped, or zero beyond a wall)
+            const float4 a1 = ld_f4(u1 + lin), a2 = ld_f4(u2 + lin);
+            float4 h1 = make_float4(0.f, 0.f, 0.f, 0.f), h2 = h1;
+            if (idx[1] + 1 < R.n[1]) h1 = ld_f4(u1 + lin + n0);
+            else if (R.bc[1] == RBFIB_PERIODIC) h1 = ld_f4(u1 + lin - (R.n[1] - 1) * n0);
+            if (idx[2] + 1 < R.n[2]) h2 = ld_f4(u2 + lin + n01);
+            else if (R.bc[2] == RBFIB_PERIODIC) h2 = ld_f4(u2 + lin - (R.n[2] - 1) * n01);
+            const double *rp = r + R.off + 3 * N + lin;
+            const double2 r01 = ld_d2(rp), r23 = ld_d2(rp + 2);
+            const float x0[5] = {a0.x, a0.y, a0.z, a0.w, after};
+            const float ys[4] = {a1.x, a1.y, a1.z, a1.w}, yh[4] = {h1.x, h1.y, h1.z, h1.w};
+            const float zs[4] = {a2.x, a2.y, a2.z, a2.w}, zh[4] = {h2.x, h2.y, h2.z, h2.w};
+            const double rr[4] = {r01.x, r01.y, r23.x, r23.y};
+            const bool piny = R.bc[1] == RBFIB_WALL && idx[1] == 0, pinz = R.bc[2] == RBFIB_WALL && idx[2] == 0;
+            float bo[4];
+            double zo[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const bool pinx = R.bc[0] == RBFIB_WALL && idx[0] + q == 0;
+                double div = 0.0;
+                div = fmad((double)x0[q + 1] - (pinx ? 0.0 : (double)x0[q]), R.inv_h, div);
+                div = fmad((double)yh[q] - (piny ? 0.0 : (double)ys[q]), R.inv_h, div);
+                div = fmad((double)zh[q] - (pinz ? 0.0 : (double)zs[q]), R.inv_h, div);
+                proj_div_out(div, rr[q], R.eta, bo[q], zo[q]);
+            }
+            *reinterpret_cast<float4 *>((float *)bp + Lv.off + 3 * Lv.N + lin) = make_float4(bo[0], bo[1], bo[2], bo[3]);
+            double *zp = z + R.off + 3 * N + lin;
+            *reinterpret_cast<double2 *>(zp) = make_double2(zo[0], zo[1]);
+            *reinterpret_cast<double2 *>(zp + 2) = make_double2(zo[2], zo[3]);
+            return;
+        }
+    }
     for (int t_ = 0; t_ < be.npt; ++t_) {
     long long lin = be.start + threadIdx.x + (long long)t_ * RB_BLOCK;
-    long long N = R.N;
     if (lin >= N) continue;
     int idx[3];
     unlin(lin, R, idx);
@@ -846,10 +919,10 @@ __global__ void k_proj_div(const RepDev *reps, const LevDev *levs, const BlockEn
         double hi;
         if (idx[c] + 1 < R.n[c]) hi = (double)u[lin + stride];
         else hi = (R.bc[c] == RBFIB_PERIODIC) ? (double)u[lin - (long long)(R.n[c] - 1) * stride] : 0.0;
-        div += (hi - lo) * R.inv_h;
+        div = fmad(hi - lo, R.inv_h, div);
         stride *= R.n[c];
     }
-    double d = div + r[R.off + 3 * N + lin];
+    const double d = div + r[R.off + 3 * N + lin];
     bp[Lv.off + 3 * Lv.N + lin] = (T)(-d);
     z[R.off + 3 * N + lin] = -R.eta * d;
     }
@@ -869,9 +942,43 @@ __global__ void k_proj_correct(const RepDev *reps, const LevDev *levs, const Blo
     if (mask && !mask[be.rep]) return;
     const RepDev &R = reps[be.rep];
     const LevDev &Lv = levs[be.rep * RB_MAXLEV];
+    const long long N = R.N;
+    if constexpr (sizeof(T) == 4) {
+        if (cells_row4(be, R, z)) {
+            const long long g0 = be.start + 4LL * threadIdx.x;
+            if (g0 >= N) return;
+            const int lin = (int)g0, n0 = R.n[0], n01 = R.n[0] * R.n[1];
+            int idx[3];
+            unlin(lin, R, idx);
+            const float *ph = (const float *)phi + Lv.off + 3 * Lv.N;
+            const float4 p4 = ld_f4(ph + lin);
+            const float before = ph[lin + (idx[0] > 0 ? -1 : n0 - 1)];
+            const float4 py = ld_f4(ph + lin + (idx[1] > 0 ? -n0 : (R.n[1] - 1) * n0));
+            const float4 pz = ld_f4(ph + lin + (idx[2] > 0 ? -n01 : (R.n[2] - 1) * n01));
+            const float pc[4] = {p4.x, p4.y, p4.z, p4.w};
+            const float pmx[4] = {before, p4.x, p4.y, p4.z};
+            const float pmy[4] = {py.x, py.y, py.z, py.w}, pmz[4] = {pz.x, pz.y, pz.z, pz.w};
+            const bool piny = R.bc[1] == RBFIB_WALL && idx[1] == 0, pinz = R.bc[2] == RBFIB_WALL && idx[2] == 0;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                const float4 x4 = ld_f4((const float *)xv + Lv.off + c * Lv.N + lin);
+                const float xs[4] = {x4.x, x4.y, x4.z, x4.w};
+                double o[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const bool pin = c == 0 ? (R.bc[0] == RBFIB_WALL && idx[0] + q == 0) : (c == 1 ? piny : pinz);
+                    const float pm = c == 0 ? pmx[q] : (c == 1 ? pmy[q] : pmz[q]);
+                    o[q] = pin ? 0.0 : fmad(-((double)pc[q] - (double)pm), R.inv_h, (double)xs[q]);
+                }
+                double *zp = z + R.off + c * N + lin;
+                *reinterpret_cast<double2 *>(zp) = make_double2(o[0], o[1]);
+                *reinterpret_cast<double2 *>(zp + 2) = make_double2(o[2], o[3]);
+            }
+            return;
+        }
+    }
     for (int t_ = 0; t_ < be.npt; ++t_) {
     long long lin = be.start + threadIdx.x + (long long)t_ * RB_BLOCK;
-    long long N = R.N;
     if (lin >= N) continue;
     int idx[3];
     unlin(lin, R, idx);
@@ -882,7 +989,7 @@ __global__ void k_proj_correct(const RepDev *reps, const LevDev *levs, const Blo
         double out = 0.0;
         if (!pinned(c, idx, R.bc)) {
             double pm = (idx[c] > 0) ? (double)ph[lin - stride] : (double)ph[lin + (long long)(R.n[c] - 1) * stride];
-            out = (double)xv[Lv.off + c * Lv.N + lin] - (pc - pm) * R.inv_h;
+            out = fmad(-(pc - pm), R.inv_h, (double)xv[Lv.off + c * Lv.N + lin]);
         }
         z[R.off + c * N + lin] = out;
         stride *= R.n[c];
