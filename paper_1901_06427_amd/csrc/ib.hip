@@ -333,21 +333,23 @@ void launch_markers(Ctx &c, MarkerSet &ms, const double *q, const double *theta)
 }
 
 // ------------------------------------------------------------------ spreading (gather)
-// One workgroup per tile that has pairs, one wave per velocity component, one lane
-// per face of the tile: the face sums the tensor-product weights times lambda over
-// the tile's pairs in marker order (no atomics, fixed summation order).
+// One wavefront per tile that has pairs, one lane per (x, y, z) position of the
+// tile: the lane sums, for the three velocity components at once, the tensor-product
+// weights times lambda over the tile's pairs in marker order (no atomics, fixed
+// summation order).  A wave per tile keeps many tiles in flight: the work per tile
+// is small and its chain of dependent loads sets the time.
 // TO = double: y is a state vector (velocity of replica r at R.off + c N);
 // with levs given: y is a multigrid pool, level 0 of each replica.
 template <typename TO>
-__global__ __launch_bounds__(192) void k_spread(const RepDev *reps, const int *tile_rep, const int *active,
-                                                const int *n_active, const int *pair_start, const int *pair_count,
-                                                long long cap, const double *__restrict__ pair_w,
-                                                const long long *__restrict__ pair_lam,
-                                                const double *__restrict__ lam_state, TO *__restrict__ y,
-                                                double alpha, const int *__restrict__ mask,
-                                                const LevDev *__restrict__ levs) {
-    const int tid = threadIdx.x;
-    const int c = tid >> 6, lx = tid & 3, ly = (tid >> 2) & 3, lz = (tid >> 4) & 3;
+__global__ __launch_bounds__(64) void k_spread(const RepDev *reps, const int *tile_rep, const int *active,
+                                               const int *n_active, const int *pair_start, const int *pair_count,
+                                               long long cap, const double *__restrict__ pair_w,
+                                               const long long *__restrict__ pair_lam,
+                                               const double *__restrict__ lam_state, TO *__restrict__ y,
+                                               double alpha, const int *__restrict__ mask,
+                                               const LevDev *__restrict__ levs) {
+    const int lane = threadIdx.x;
+    const int lx = lane & 3, ly = (lane >> 2) & 3, lz = lane >> 4;
     const int na = *n_active;
     for (int it = blockIdx.x; it < na; it += gridDim.x) {
         const int t = active[it];
@@ -356,23 +358,26 @@ __global__ __launch_bounds__(192) void k_spread(const RepDev *reps, const int *t
         const RepDev &R = reps[rep];
         const long long s0 = pair_start[t];
         const long long s1 = min(s0 + (long long)pair_count[t], cap);
-        double acc = 0.0;
-#pragma unroll 4
+        double acc[3] = {0.0, 0.0, 0.0};
+#pragma unroll 2
         for (long long s = s0; s < s1; ++s) {
-            const double *w = pair_w + s * 36 + c * 12;
-            acc += w[lx] * w[4 + ly] * w[8 + lz] * lam_state[pair_lam[s] + c];
+            const double *w = pair_w + s * 36;
+            const double *lam = lam_state + pair_lam[s];
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+                acc[c] += w[12 * c + lx] * w[12 * c + 4 + ly] * w[12 * c + 8 + lz] * lam[c];
         }
         const int lt = t - R.tile0;
         const int g0 = RB_TILE * (lt % R.tdim[0]) + lx;
         const int g1 = RB_TILE * ((lt / R.tdim[0]) % R.tdim[1]) + ly;
         const int g2 = RB_TILE * (lt / (R.tdim[0] * R.tdim[1])) + lz;
-        const bool in = g0 < R.n[0] && g1 < R.n[1] && g2 < R.n[2];
-        const int gc = c == 0 ? g0 : (c == 1 ? g1 : g2);
-        const bool pin = R.bc[c] == RBFIB_WALL && gc == 0;
-        if (in && !pin) {
+        if (g0 < R.n[0] && g1 < R.n[1] && g2 < R.n[2]) {
             const long long lin = (long long)g0 + (long long)R.n[0] * ((long long)g1 + (long long)R.n[1] * g2);
             const long long o = levs ? levs[rep * RB_MAXLEV].off : R.off;
-            y[o + c * R.N + lin] += (TO)(alpha * acc / R.dV);
+            const int gc[3] = {g0, g1, g2};
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+                if (!(R.bc[c] == RBFIB_WALL && gc[c] == 0)) y[o + c * R.N + lin] += (TO)(alpha * acc[c] / R.dV);
         }
     }
 }
@@ -380,8 +385,8 @@ __global__ __launch_bounds__(192) void k_spread(const RepDev *reps, const int *t
 template <typename TO>
 static void spread_into(Ctx &c, MarkerSet &ms, const double *lam_state, TO *y, double alpha, const LevDev *levs) {
     if (c.nm == 0) return;
-    int grid = std::min(c.ntiles, 32768);   // grid-stride over the tiles that have pairs
-    hipLaunchKernelGGL(k_spread<TO>, dim3(grid), dim3(192), 0, c.stream, c.d_reps, c.d_tile_rep, ms.active,
+    int grid = std::min(c.ntiles, 65536);   // grid-stride over the tiles that have pairs
+    hipLaunchKernelGGL(k_spread<TO>, dim3(grid), dim3(64), 0, c.stream, c.d_reps, c.d_tile_rep, ms.active,
                        ms.n_active, ms.pair_start, ms.pair_count, ms.pair_cap, ms.pair_w, ms.pair_lam, lam_state, y,
                        alpha, c.mask, levs);
 }
