@@ -132,6 +132,7 @@ PSWEEPS = 0       # 0: the library default
 BLOB = 0.0        # 0: the library default
 BOTTOM = -1       # -1: the library default
 CHEBY = -1.0      # < 0: the library default
+EXTRA_OPTS = {}   # further rbfib_opts fields (--opt name=value)
 
 
 def run_gpu(ws, steps, warmup, fp32, seed=2024, timing=False, graphs=True):
@@ -144,7 +145,7 @@ def run_gpu(ws, steps, warmup, fp32, seed=2024, timing=False, graphs=True):
                       **({"mg_sweeps": SWEEPS} if SWEEPS else {}), **({"mg_omega": OMEGA} if OMEGA else {}),
                       **({"mg_sweeps_p": PSWEEPS} if PSWEEPS else {}), **({"blob_radius": BLOB} if BLOB else {}),
                       **({"mg_bottom": BOTTOM} if BOTTOM >= 0 else {}),
-                      **({"mg_cheby": CHEBY} if CHEBY >= 0 else {}))
+                      **({"mg_cheby": CHEBY} if CHEBY >= 0 else {}), **EXTRA_OPTS)
     U = torch.empty((E.nb, 6), dtype=torch.float64, device="cuda")
     step_id = 0
     iters = 0
@@ -315,6 +316,8 @@ def main():
                     help="LDS budget in KB of the bottom multigrid kernel, 0 off (-1: library default)")
     ap.add_argument("--mg-cheby", type=float, default=-1.0,
                     help="lower end of the Chebyshev smoothing interval, 0 constant weights (-1: library default)")
+    ap.add_argument("--opt", action="append", default=[], metavar="NAME=VALUE",
+                    help="set any other solver option field (repeatable)")
     ap.add_argument("--restart", type=int, default=0, help="FGMRES restart length (0: library default)")
     ap.add_argument("--mg-sweeps", type=int, default=0, help="damped-Jacobi sweeps per level (0: library default)")
     ap.add_argument("--mg-omega", type=float, default=0.0, help="Jacobi damping (0: library default)")
@@ -327,11 +330,14 @@ def main():
                     help="multigrid level kernels: 0 separate (default), 1 fused where the level fills the "
                          "device, 2 fused on every level")
     args = ap.parse_args()
-    global MG_FUSED, RESTART, SWEEPS, OMEGA, PSWEEPS, BLOB, BOTTOM, CHEBY
+    global MG_FUSED, RESTART, SWEEPS, OMEGA, PSWEEPS, BLOB, BOTTOM, CHEBY, EXTRA_OPTS
     MG_FUSED = args.mg_fused
     RESTART = args.restart
     BOTTOM = args.mg_bottom
     CHEBY = args.mg_cheby
+    for kv in args.opt:
+        k, v = kv.split("=", 1)
+        EXTRA_OPTS[k] = float(v) if any(ch in v for ch in ".eE") else int(v)
     SWEEPS = args.mg_sweeps
     OMEGA = args.mg_omega
     PSWEEPS = args.mg_sweeps_p
