@@ -516,6 +516,7 @@ struct Ctx {
     double *xsol = nullptr, *rhs = nullptr, *tmp = nullptr;
     double *partial = nullptr;  // [n_tab_vec * (m+1)]
     double *H = nullptr, *cs = nullptr, *sn = nullptr, *gv = nullptr, *beta0 = nullptr, *hcol = nullptr, *yv = nullptr;
+    double *inv_nu = nullptr;   // [nrep][m+1]: basis vector i is stored as u_i, with v_i = inv_nu[i] u_i
     int *active = nullptr, *cyc_active = nullptr, *jf = nullptr, *status = nullptr, *iters = nullptr;
     int *h_count = nullptr;     // pinned
     double *d_resid = nullptr;  // [nrep]
@@ -535,7 +536,7 @@ struct Ctx {
 // ---------------------------------------------------------------- launchers
 // grid / multigrid (grid.hip)
 void launch_apply_fluid(Ctx &c, const double *x, double *y);
-template <typename T> void launch_to_level0(Ctx &c, const double *src, T *b, int c0, int nc);
+template <typename T> void launch_to_level0(Ctx &c, const double *src, T *b, int c0, int nc, const double *rs = nullptr);
 template <typename T> void launch_smooth(Ctx &c, int lev, int c0, int nc, const T *xin, T *xout, const T *b, bool first,
                                           double omega);
 template <typename T> void launch_restrict(Ctx &c, int lev, int c0, int nc, const T *x, const T *b, T *bc, T *r);
@@ -547,7 +548,8 @@ template <typename T> void launch_coarse(Ctx &c, int lev, int c0, int nc, const 
 template <typename T> void launch_mg_down(Ctx &c, int lev, int c0, int nc, const T *b, T *x, double omega1, double omega2);
 template <typename T> void launch_mg_up(Ctx &c, int lev, int c0, int nc, const T *b, const T *xin, const T *xc, T *xout,
                                        double omega1, double omega2);
-template <typename T> void launch_proj_div(Ctx &c, const T *xv, const double *r, T *bp, double *z);
+template <typename T> void launch_proj_div(Ctx &c, const T *xv, const double *r, T *bp, double *z,
+                                          const double *rs = nullptr);
 template <typename T> void launch_proj_correct(Ctx &c, const T *xv, const T *phi, double *z);
 void launch_noise(Ctx &c, double kT, double dt, uint64_t seed, uint64_t step, double *f, bool add);
 void launch_wall_rhs(Ctx &c, double *f);
@@ -557,7 +559,8 @@ void launch_markers(Ctx &c, MarkerSet &ms, const double *q, const double *theta)
 void launch_spread(Ctx &c, MarkerSet &ms, const double *lam, double *y, double alpha);
 template <typename T> void launch_spread_level0(Ctx &c, MarkerSet &ms, const double *lam, T *pool, double alpha);
 void launch_body_apply(Ctx &c, MarkerSet &ms, const double *q, const double *x, double *y);
-void launch_body_precond(Ctx &c, MarkerSet &ms, const double *theta, const double *r, double *z);
+void launch_body_precond(Ctx &c, MarkerSet &ms, const double *theta, const double *r, double *z,
+                         const double *rs = nullptr);
 void launch_interp(Ctx &c, MarkerSet &ms, const double *x, double *out, double alpha, bool accumulate);
 void launch_interp_bc(Ctx &c, MarkerSet &ms, double *out, double alpha);
 void launch_body_rfd(Ctx &c, double kT, double delta, uint64_t seed, uint64_t step, const double *q,
@@ -576,11 +579,13 @@ void launch_copy_U(Ctx &c, const double *x, double *U, double scale);
 void launch_set_rhs(Ctx &c, const double *FT, const double *slip, double *b);
 
 // Krylov (krylov.hip)
-void launch_dots(Ctx &c, const double *V, int nvec, const double *w, double *out /*[nrep*(m+1)]*/, const int *mask);
-void launch_axpy_multi(Ctx &c, const double *V, int nvec, const double *coef, double *w, double sign, const int *mask);
+void launch_dots(Ctx &c, const double *V, int nvec, const double *w, double *out /*[nrep*(m+1)]*/, const int *mask,
+                 const double *scale = nullptr);
+void launch_axpy_multi(Ctx &c, const double *V, int nvec, const double *coef, double *w, double sign, const int *mask,
+                       const double *scale = nullptr);
 void launch_norm(Ctx &c, const double *w, double *out, const int *mask);
 void launch_axpy_multi_norm(Ctx &c, const double *V, int nvec, const double *coef, double *w, double *nrm,
-                            const int *mask);
+                            const int *mask, const double *scale = nullptr);
 void launch_scale(Ctx &c, const double *w, const double *s, double *out, const int *mask, bool inverse);
 void launch_axpby(Ctx &c, double a, const double *x, double b, const double *y, double *out, const int *mask);
 void launch_copy(Ctx &c, const double *x, double *y, const int *mask);

@@ -228,14 +228,17 @@ __device__ __forceinline__ bool cells_row4(const BlockEnt &be, const RepDev &R, 
 __device__ __forceinline__ double2 ld_d2(const double *q) { return *reinterpret_cast<const double2 *>(q); }
 __device__ __forceinline__ float4 ld_f4(const float *q) { return *reinterpret_cast<const float4 *>(q); }
 
+// b (level 0) = src * f, f = rs[rep * rstride] (1 without rs)
 template <typename T>
 __global__ void k_to_level0(const RepDev *reps, const LevDev *levs, const BlockEnt *tab,
-                            const double *__restrict__ src, T *__restrict__ b, int c0, const int *__restrict__ mask) {
+                            const double *__restrict__ src, T *__restrict__ b, int c0, const int *__restrict__ mask,
+                            const double *__restrict__ rs, int rstride) {
     BlockEnt be = tab[xcd_block(blockIdx.x, gridDim.x)];
     if (mask && !mask[be.rep]) return;
     int comp = c0 + blockIdx.y;
     const RepDev &R = reps[be.rep];
     const LevDev &Lv = levs[be.rep * RB_MAXLEV];
+    const double f = rs ? rs[(long long)be.rep * rstride] : 1.0;
     if constexpr (sizeof(T) == 4) {
         if (cells_row4(be, R, src)) {
             const long long lin = be.start + 4LL * threadIdx.x;
@@ -243,21 +246,21 @@ __global__ void k_to_level0(const RepDev *reps, const LevDev *levs, const BlockE
             const double *s = src + R.off + comp * R.N + lin;
             const double2 a = ld_d2(s), c = ld_d2(s + 2);
             *reinterpret_cast<float4 *>(b + Lv.off + comp * Lv.N + lin) =
-                make_float4((float)a.x, (float)a.y, (float)c.x, (float)c.y);
+                make_float4((float)(a.x * f), (float)(a.y * f), (float)(c.x * f), (float)(c.y * f));
             return;
         }
     }
     for (int t_ = 0; t_ < be.npt; ++t_) {
     long long lin = be.start + threadIdx.x + (long long)t_ * RB_BLOCK;
     if (lin >= R.N) continue;
-    b[Lv.off + comp * Lv.N + lin] = (T)src[R.off + comp * R.N + lin];
+    b[Lv.off + comp * Lv.N + lin] = (T)(src[R.off + comp * R.N + lin] * f);
     }
 }
 
 template <typename T>
-void launch_to_level0(Ctx &c, const double *src, T *b, int c0, int nc) {
+void launch_to_level0(Ctx &c, const double *src, T *b, int c0, int nc, const double *rs) {
     hipLaunchKernelGGL(k_to_level0<T>, dim3(c.n_tab_cells, nc), dim3(RB_BLOCK), 0, c.stream, c.d_reps, c.d_levs,
-                       c.d_tab_cells, src, b, c0, c.mask);
+                       c.d_tab_cells, src, b, c0, c.mask, rs, c.m + 1);
 }
 
 // Operator of component comp at a level: A = -eta Lm (velocity) or -L (pressure).
@@ -847,20 +850,23 @@ template void launch_mg_bottom<double>(Ctx &, int, int, int, const SweepW &, con
 // ------------------------------------------------------------------ projection step
 // d = D x* + r_pi ;  b_p (level 0) = -d  (so that -L phi = -d) ;  z_pi = -eta d.
 // div sums the three axes in order with fused multiply-adds in both paths.
-__device__ __forceinline__ void proj_div_out(double div, double rp, double eta, float &bp, double &zp) {
-    const double d = div + rp;
+__device__ __forceinline__ void proj_div_out(double div, double rp, double f, double eta, float &bp, double &zp) {
+    const double d = fmad(rp, f, div);
     bp = (float)(-d);
     zp = -eta * d;
 }
 
+// (r_pi is read as r * f, f = rs[rep * rstride], 1 without rs)
 template <typename T>
 __global__ void k_proj_div(const RepDev *reps, const LevDev *levs, const BlockEnt *tab, const T *__restrict__ xv,
-                           const double *__restrict__ r, T *__restrict__ bp, double *__restrict__ z, const int *__restrict__ mask) {
+                           const double *__restrict__ r, T *__restrict__ bp, double *__restrict__ z, const int *__restrict__ mask,
+                           const double *__restrict__ rs, int rstride) {
     BlockEnt be = tab[xcd_block(blockIdx.x, gridDim.x)];
     if (mask && !mask[be.rep]) return;
     const RepDev &R = reps[be.rep];
     const LevDev &Lv = levs[be.rep * RB_MAXLEV];
     const long long N = R.N;
+    const double f = rs ? rs[(long long)be.rep * rstride] : 1.0;
     if constexpr (sizeof(T) == 4) {
         if (cells_row4(be, R, r) && cells_row4(be, R, z)) {
             const long long g0 = be.start + 4LL * threadIdx.x;
@@ -897,7 +903,7 @@ __global__ void k_proj_div(const RepDev *reps, const LevDev *levs, const BlockEn
                 div = fmad((double)x0[q + 1] - (pinx ? 0.0 : (double)x0[q]), R.inv_h, div);
                 div = fmad((double)yh[q] - (piny ? 0.0 : (double)ys[q]), R.inv_h, div);
                 div = fmad((double)zh[q] - (pinz ? 0.0 : (double)zs[q]), R.inv_h, div);
-                proj_div_out(div, rr[q], R.eta, bo[q], zo[q]);
+                proj_div_out(div, rr[q], f, R.eta, bo[q], zo[q]);
             }
             *reinterpret_cast<float4 *>((float *)bp + Lv.off + 3 * Lv.N + lin) = make_float4(bo[0], bo[1], bo[2], bo[3]);
             double *zp = z + R.off + 3 * N + lin;
@@ -922,16 +928,16 @@ __global__ void k_proj_div(const RepDev *reps, const LevDev *levs, const BlockEn
         div = fmad(hi - lo, R.inv_h, div);
         stride *= R.n[c];
     }
-    const double d = div + r[R.off + 3 * N + lin];
+    const double d = fmad(r[R.off + 3 * N + lin], f, div);
     bp[Lv.off + 3 * Lv.N + lin] = (T)(-d);
     z[R.off + 3 * N + lin] = -R.eta * d;
     }
 }
 
 template <typename T>
-void launch_proj_div(Ctx &c, const T *xv, const double *r, T *bp, double *z) {
+void launch_proj_div(Ctx &c, const T *xv, const double *r, T *bp, double *z, const double *rs) {
     hipLaunchKernelGGL(k_proj_div<T>, dim3(c.n_tab_cells), dim3(RB_BLOCK), 0, c.stream, c.d_reps, c.d_levs,
-                       c.d_tab_cells, xv, r, bp, z, c.mask);
+                       c.d_tab_cells, xv, r, bp, z, c.mask, rs, c.m + 1);
 }
 
 // z_v = x* - G phi  (phi in the pressure slot of the level-0 pool).
@@ -1113,8 +1119,8 @@ void launch_wall_rhs(Ctx &c, double *f) {
 }
 
 // explicit instantiations
-template void launch_to_level0<float>(Ctx &, const double *, float *, int, int);
-template void launch_to_level0<double>(Ctx &, const double *, double *, int, int);
+template void launch_to_level0<float>(Ctx &, const double *, float *, int, int, const double *);
+template void launch_to_level0<double>(Ctx &, const double *, double *, int, int, const double *);
 template void launch_smooth<float>(Ctx &, int, int, int, const float *, float *, const float *, bool, double);
 template void launch_smooth<double>(Ctx &, int, int, int, const double *, double *, const double *, bool, double);
 template void launch_restrict<float>(Ctx &, int, int, int, const float *, const float *, float *, float *);
@@ -1123,8 +1129,8 @@ template void launch_prolong<float>(Ctx &, int, int, int, const float *, float *
 template void launch_prolong<double>(Ctx &, int, int, int, const double *, double *);
 template void launch_coarse<float>(Ctx &, int, int, int, const float *, float *);
 template void launch_coarse<double>(Ctx &, int, int, int, const double *, double *);
-template void launch_proj_div<float>(Ctx &, const float *, const double *, float *, double *);
-template void launch_proj_div<double>(Ctx &, const double *, const double *, double *, double *);
+template void launch_proj_div<float>(Ctx &, const float *, const double *, float *, double *, const double *);
+template void launch_proj_div<double>(Ctx &, const double *, const double *, double *, double *, const double *);
 template void launch_proj_correct<float>(Ctx &, const float *, const float *, double *);
 template void launch_proj_correct<double>(Ctx &, const double *, const double *, double *);
 

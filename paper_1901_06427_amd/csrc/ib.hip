@@ -517,10 +517,12 @@ void launch_interp_bc(Ctx &c, MarkerSet &ms, double *out, double alpha) {
 __global__ void k_body_precond(const RepDev *reps, const int *body_rep, const int *body_off, const int *body_shape,
                                const ShapeDev *shapes, const double *sdata, const double *theta,
                                const double *__restrict__ rin, double *__restrict__ z,
-                               const int *__restrict__ mask) {
+                               const int *__restrict__ mask, const double *__restrict__ rs, int rstride) {
     extern __shared__ double sm[];
     int p = blockIdx.x;
     if (mask && !mask[body_rep[p]]) return;
+    // rin is read as rin * f (f = rs[rep * rstride], 1 without rs)
+    const double f = rs ? rs[(long long)body_rep[p] * rstride] : 1.0;
     const RepDev &R = reps[body_rep[p]];
     const ShapeDev &S = shapes[body_shape[p]];
     int m0 = body_off[p], n3 = 3 * S.nm;
@@ -533,11 +535,13 @@ __global__ void k_body_precond(const RepDev *reps, const int *body_rep, const in
     long long lam0 = R.off + 4 * R.N + 3LL * (m0 - R.m0);
     long long U0 = R.off + 4 * R.N + 3LL * R.nm + 6LL * (p - R.b0);
     for (int i = threadIdx.x; i < S.nm; i += blockDim.x) {
-        const double *v = rin + lam0 + 3 * i;
+        const double *vi = rin + lam0 + 3 * i;
+        const double v[3] = {vi[0] * f, vi[1] * f, vi[2] * f};
         for (int k = 0; k < 3; ++k) g[3 * i + k] = Rm[k] * v[0] + Rm[3 + k] * v[1] + Rm[6 + k] * v[2];
     }
     if (threadIdx.x < 2) {
-        const double *v = rin + U0 + 3 * threadIdx.x;
+        const double *vi = rin + U0 + 3 * threadIdx.x;
+        const double v[3] = {vi[0] * f, vi[1] * f, vi[2] * f};
         for (int k = 0; k < 3; ++k) b6[3 * threadIdx.x + k] = Rm[k] * v[0] + Rm[3 + k] * v[1] + Rm[6 + k] * v[2];
     }
     __syncthreads();
@@ -592,12 +596,12 @@ __global__ void k_body_precond(const RepDev *reps, const int *body_rep, const in
     }
 }
 
-void launch_body_precond(Ctx &c, MarkerSet &ms, const double *theta, const double *r, double *z) {
+void launch_body_precond(Ctx &c, MarkerSet &ms, const double *theta, const double *r, double *z, const double *rs) {
     (void)ms;
     if (c.nb == 0) return;
     size_t sh = sizeof(double) * (size_t)(6 * c.max_body_nm + 12);
     hipLaunchKernelGGL(k_body_precond, dim3(c.nb), dim3(128), sh, c.stream, c.d_reps, c.d_body_rep, c.d_body_off,
-                       c.d_body_shape, c.d_shapes, c.d_shape_data, theta, r, z, c.mask);
+                       c.d_body_shape, c.d_shapes, c.d_shape_data, theta, r, z, c.mask, rs, c.m + 1);
 }
 
 // ------------------------------------------------------------------ small helpers

@@ -49,23 +49,26 @@ __global__ __launch_bounds__(RB_BLOCK) void k_dot_partial(const RepDev *reps, co
 }
 
 // out[r * out_stride + i] = sum of replica r's block partials of vector i, one
-// wavefront per (replica, vector), fixed summation order.
+// wavefront per (replica, vector), fixed summation order; times scale[r * out_stride
+// + i] when a scale is given.
 __global__ void k_dot_reduce(const int *first, const int *nblk, const double *partial, int stride, double *out,
-                             int out_stride, const int *mask, int take_sqrt) {
+                             int out_stride, const int *mask, int take_sqrt, const double *scale) {
     int r = blockIdx.x, i = blockIdx.y;
     if (mask && !mask[r]) return;
     double s = 0.0;
     for (int b = threadIdx.x; b < nblk[r]; b += 64) s += partial[(long long)(first[r] + b) * stride + i];
     s = wave_sum(s);
+    if (scale) s *= scale[(long long)r * out_stride + i];
     if (threadIdx.x == 0) out[(long long)r * out_stride + i] = take_sqrt ? sqrt(s) : s;
 }
 
-void launch_dots(Ctx &c, const double *V, int nvec, const double *w, double *out, const int *mask) {
+void launch_dots(Ctx &c, const double *V, int nvec, const double *w, double *out, const int *mask,
+                 const double *scale) {
     int stride = c.m + 1;
     hipLaunchKernelGGL(k_dot_partial, dim3(c.n_tab_vec), dim3(RB_BLOCK), 0, c.stream, c.d_reps, c.d_tab_vec, V,
                        c.L, nvec, w, c.partial, stride, mask);
     hipLaunchKernelGGL(k_dot_reduce, dim3(c.nrep, nvec), dim3(64), 0, c.stream, c.d_vec_first, c.d_vec_nblk,
-                       c.partial, stride, out, c.m + 1, mask, 0);
+                       c.partial, stride, out, c.m + 1, mask, 0, scale);
 }
 
 void launch_norm(Ctx &c, const double *w, double *out, const int *mask) {
@@ -73,21 +76,24 @@ void launch_norm(Ctx &c, const double *w, double *out, const int *mask) {
     hipLaunchKernelGGL(k_dot_partial, dim3(c.n_tab_vec), dim3(RB_BLOCK), 0, c.stream, c.d_reps, c.d_tab_vec, w, c.L,
                        1, w, c.partial, stride, mask);
     hipLaunchKernelGGL(k_dot_reduce, dim3(c.nrep, 1), dim3(64), 0, c.stream, c.d_vec_first, c.d_vec_nblk, c.partial,
-                       stride, out, 1, mask, 1);
+                       stride, out, 1, mask, 1, (const double *)nullptr);
 }
 
-// w += sign * sum_i coef[r][i] V_i ; when norm_out is given, also the norm of the
-// updated w (block partials reduced by k_dot_reduce).
+// w += sign * sum_i coef[r][i] scale[r][i] V_i (scale 1 when not given); when
+// partial is given, also the block partials of the updated w's squared norm.
 __global__ __launch_bounds__(RB_BLOCK) void k_axpy_multi(const RepDev *reps, const BlockEnt *tab, const double *V,
                                                          long long L, int nvec, const double *coef, int cstride,
-                                                         double *__restrict__ w, double sign, const int *mask,
-                                                         double *partial, int stride) {
+                                                         const double *scale, double *__restrict__ w, double sign,
+                                                         const int *mask, double *partial, int stride) {
     __shared__ double cf[RB_BLOCK];   // restart length <= 200 < RB_BLOCK
     __shared__ double red[RB_BLOCK / 64];
     BlockEnt be = tab[blockIdx.x];
     if (mask && !mask[be.rep]) return;
     const RepDev &R = reps[be.rep];
-    if (threadIdx.x < nvec) cf[threadIdx.x] = sign * coef[(long long)be.rep * cstride + threadIdx.x];
+    if (threadIdx.x < nvec) {
+        const long long ci = (long long)be.rep * cstride + threadIdx.x;
+        cf[threadIdx.x] = sign * coef[ci] * (scale ? scale[ci] : 1.0);
+    }
     __syncthreads();
     long long b = R.off + be.start;
     int n = (int)min((long long)RB_CHUNK, R.len - be.start);
@@ -140,19 +146,20 @@ __global__ __launch_bounds__(RB_BLOCK) void k_axpy_multi(const RepDev *reps, con
     }
 }
 
-void launch_axpy_multi(Ctx &c, const double *V, int nvec, const double *coef, double *w, double sign, const int *mask) {
+void launch_axpy_multi(Ctx &c, const double *V, int nvec, const double *coef, double *w, double sign, const int *mask,
+                       const double *scale) {
     hipLaunchKernelGGL(k_axpy_multi, dim3(c.n_tab_vec), dim3(RB_BLOCK), 0, c.stream, c.d_reps, c.d_tab_vec, V, c.L,
-                       nvec, coef, c.m + 1, w, sign, mask, (double *)nullptr, 0);
+                       nvec, coef, c.m + 1, scale, w, sign, mask, (double *)nullptr, 0);
 }
 
-// w -= sum_i coef_i V_i and nrm[r] = ||w|| in two launches.
+// w -= sum_i coef_i scale_i V_i and nrm[r] = ||w|| in two launches.
 void launch_axpy_multi_norm(Ctx &c, const double *V, int nvec, const double *coef, double *w, double *nrm,
-                            const int *mask) {
+                            const int *mask, const double *scale) {
     int stride = c.m + 1;
     hipLaunchKernelGGL(k_axpy_multi, dim3(c.n_tab_vec), dim3(RB_BLOCK), 0, c.stream, c.d_reps, c.d_tab_vec, V, c.L,
-                       nvec, coef, c.m + 1, w, -1.0, mask, c.partial, stride);
+                       nvec, coef, c.m + 1, scale, w, -1.0, mask, c.partial, stride);
     hipLaunchKernelGGL(k_dot_reduce, dim3(c.nrep, 1), dim3(64), 0, c.stream, c.d_vec_first, c.d_vec_nblk, c.partial,
-                       stride, nrm, 1, mask, 1);
+                       stride, nrm, 1, mask, 1, (const double *)nullptr);
 }
 
 // out = w * s[r]  (or w / s[r] when inverse; a zero divisor leaves out unchanged)
@@ -202,7 +209,7 @@ void launch_zero(Ctx &c, double *y, const int *mask) { launch_axpby(c, 0.0, y, 0
 // apply the stored rotations, form the new one, update g and the convergence state.
 __global__ void k_givens(int nrep, int m, int j, double tol, const double *h1, const double *h2, const double *nrm,
                          double *H, double *cs, double *sn, double *gv, const double *beta0, int *active,
-                         int *jf, int *status, int *iters) {
+                         int *jf, int *status, int *iters, double *inv_nu) {
     int r = blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= nrep || !active[r]) return;
     double *Hc = H + (long long)r * (m + 1) * m + (long long)j * (m + 1);
@@ -210,6 +217,8 @@ __global__ void k_givens(int nrep, int m, int j, double tol, const double *h1, c
     for (int i = 0; i <= j; ++i) Hc[i] = h1[(long long)r * (m + 1) + i] + h2[(long long)r * (m + 1) + i];
     double hn = nrm[r];
     Hc[j + 1] = hn;
+    // basis vector j+1 is kept unnormalised: v_{j+1} = u_{j+1} / hn
+    inv_nu[(long long)r * (m + 1) + j + 1] = hn > 0.0 ? 1.0 / hn : 0.0;
     for (int i = 0; i < j; ++i) {
         double t = c[i] * Hc[i] + s[i] * Hc[i + 1];
         Hc[i + 1] = -s[i] * Hc[i] + c[i] * Hc[i + 1];
@@ -244,7 +253,7 @@ __global__ void k_givens(int nrep, int m, int j, double tol, const double *h1, c
 void launch_givens(Ctx &c, int j, double tol) {
     double *h1 = c.hcol, *h2 = c.hcol + (long long)c.nrep * (c.m + 1), *nrm = c.hcol + 2LL * c.nrep * (c.m + 1);
     hipLaunchKernelGGL(k_givens, dim3((c.nrep + 63) / 64), dim3(64), 0, c.stream, c.nrep, c.m, j, tol, h1, h2, nrm,
-                       c.H, c.cs, c.sn, c.gv, c.beta0, c.active, c.jf, c.status, c.iters);
+                       c.H, c.cs, c.sn, c.gv, c.beta0, c.active, c.jf, c.status, c.iters, c.inv_nu);
 }
 
 // Back substitution H[0:jf, 0:jf] y = g[0:jf] for replicas active at cycle start.
@@ -296,11 +305,12 @@ void launch_trisolve_update(Ctx &c) {
 
 // Start of a restart cycle for active replicas: g = (beta, 0, ...), jf = 0; beta in nrm slot.
 __global__ void k_start_cycle(int nrep, int m, const double *beta, double *gv, int *active, int *jf, int *cyc,
-                              int *status) {
+                              int *status, double *inv_nu) {
     int r = blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= nrep) return;
     cyc[r] = active[r];
     if (!active[r]) return;
+    inv_nu[(long long)r * (m + 1)] = 1.0;   // the cycle's first basis vector is stored normalised
     double *g = gv + (long long)r * (m + 1);
     g[0] = beta[r];
     for (int i = 1; i <= m; ++i) g[i] = 0.0;
@@ -311,7 +321,7 @@ __global__ void k_start_cycle(int nrep, int m, const double *beta, double *gv, i
 void launch_start_cycle(Ctx &c) {
     double *nrm = c.hcol + 2LL * c.nrep * (c.m + 1);
     hipLaunchKernelGGL(k_start_cycle, dim3((c.nrep + 63) / 64), dim3(64), 0, c.stream, c.nrep, c.m, nrm, c.gv,
-                       c.active, c.jf, c.cyc_active, c.status);
+                       c.active, c.jf, c.cyc_active, c.status, c.inv_nu);
 }
 
 }  // namespace rb

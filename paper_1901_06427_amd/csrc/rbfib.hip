@@ -286,26 +286,30 @@ static T *vcycle(Ctx &c, int c0, int nc) {
     return res[0];
 }
 
+// z = P^-1 (f r), f = rs[rep * (m + 1)] per replica (1 without rs): the readers of r
+// apply the factor, so that an unnormalised Krylov vector needs no scaling pass.
 template <typename T>
-static void precond_t(Ctx &c, MarkerSet &ms, const double *theta, const double *r, double *z, bool fluid_only) {
+static void precond_t(Ctx &c, MarkerSet &ms, const double *theta, const double *r, double *z, bool fluid_only,
+                      const double *rs) {
     bool bodies = !fluid_only && c.nb > 0;
-    if (bodies) launch_body_precond(c, ms, theta, r, z);
+    if (bodies) launch_body_precond(c, ms, theta, r, z, rs);
     // Velocity right-hand side r_v + S lambda built straight in level 0 of the pool;
     // the divergence step reads only the pressure part of r, which spreading leaves alone.
     T *B = (T *)c.mg_b;
-    launch_to_level0<T>(c, r, B, 0, 3);
+    launch_to_level0<T>(c, r, B, 0, 3, rs);
     if (bodies) launch_spread_level0<T>(c, ms, z, B, 1.0);
     T *V = vcycle<T>(c, 0, 3);
-    launch_proj_div<T>(c, V, r, B, z);
+    launch_proj_div<T>(c, V, r, B, z, rs);
     T *P = vcycle<T>(c, 3, 1);
     launch_proj_correct<T>(c, V, P, z);
     if (!bodies) launch_zero_bodies(c, z);
     HIP_OK(hipGetLastError());     // a launch the runtime refused surfaces here, not as stale results
 }
 
-static void precond(Ctx &c, MarkerSet &ms, const double *theta, const double *r, double *z, bool fluid_only) {
-    if (c.mg_fp32) precond_t<float>(c, ms, theta, r, z, fluid_only);
-    else precond_t<double>(c, ms, theta, r, z, fluid_only);
+static void precond(Ctx &c, MarkerSet &ms, const double *theta, const double *r, double *z, bool fluid_only,
+                    const double *rs = nullptr) {
+    if (c.mg_fp32) precond_t<float>(c, ms, theta, r, z, fluid_only, rs);
+    else precond_t<double>(c, ms, theta, r, z, fluid_only, rs);
 }
 
 // ------------------------------------------------------------------ FGMRES
@@ -384,34 +388,38 @@ static void fgmres(Ctx &c, MarkerSet &ms, const double *theta, const double *b, 
         while (!done) {
             for (int j = 0; j < m; ++j) {
                 // one Arnoldi step: z_j = P^-1 v_j, w = A z_j, classical Gram-Schmidt
-                // (one pass), ||w||, Givens update, v_{j+1} = w / ||w||.  Loss of
+                // (one pass), ||w||, Givens update.  The basis is kept unnormalised:
+                // slot i holds u_i with v_i = inv_nu[i] u_i, so w is formed in slot j+1,
+                // orthogonalised there, and its norm only enters inv_nu (set by the
+                // Givens kernel); the projections, the update coefficients and the
+                // preconditioner's reads of v_j apply the factors.  Loss of
                 // orthogonality is caught by the true-residual check below.
                 auto body = [&]() {
                     double *Vj = c.V + (long long)j * c.L, *Zj = c.Z + (long long)j * c.L;
+                    double *W = c.V + (long long)(j + 1) * c.L;
                     // converged replicas skip the grid and body kernels (not in timing
                     // runs, whose byte counts assume every replica is processed)
                     c.mask = c.timing.on ? nullptr : c.active;
-                    precond(c, ms, theta, Vj, Zj, fluid_only);
-                    apply_op(c, ms, Zj, c.W, fluid_only);
+                    precond(c, ms, theta, Vj, Zj, fluid_only, c.inv_nu + j);
+                    apply_op(c, ms, Zj, W, fluid_only);
                     c.mask = nullptr;
                     // algorithmic bytes of the masked Krylov kernels: FP64 vectors of the active replicas
                     const double vb = c.timing.on ? 8.0 * active_len(c) : 0.0;
                     record(c, 4, true);
-                    launch_dots(c, c.V, j + 1, c.W, h1, c.active);
+                    launch_dots(c, c.V, j + 1, W, h1, c.active, c.inv_nu);
                     record(c, 4, false, vb * (j + 2));    // read j+1 basis vectors and w
                     if (reorth) {
                         // tight tolerances: second Gram-Schmidt pass keeps the basis
                         // orthogonal to working precision
-                        launch_axpy_multi(c, c.V, j + 1, h1, c.W, -1.0, c.active);
-                        launch_dots(c, c.V, j + 1, c.W, h2, c.active);
-                        launch_axpy_multi_norm(c, c.V, j + 1, h2, c.W, nrm, c.active);
+                        launch_axpy_multi(c, c.V, j + 1, h1, W, -1.0, c.active, c.inv_nu);
+                        launch_dots(c, c.V, j + 1, W, h2, c.active, c.inv_nu);
+                        launch_axpy_multi_norm(c, c.V, j + 1, h2, W, nrm, c.active, c.inv_nu);
                     } else {
                         record(c, 5, true);
-                        launch_axpy_multi_norm(c, c.V, j + 1, h1, c.W, nrm, c.active);
+                        launch_axpy_multi_norm(c, c.V, j + 1, h1, W, nrm, c.active, c.inv_nu);
                         record(c, 5, false, vb * (j + 3));    // read j+1 vectors and w, write w
                     }
                     launch_givens(c, j, tol);
-                    launch_scale(c, c.W, nrm, c.V + (long long)(j + 1) * c.L, c.active, true);
                 };
                 bool graphable = c.opts.use_graphs && !c.timing.on && theta == c.theta_int && &ms == &c.ms[0];
                 if (graphable) {
@@ -1006,6 +1014,8 @@ static void build(Ctx &c, int nrep, const rbfib_grid *grids, const rbfib_bodies 
     c.gv = dalloc<double>((size_t)nrep * (c.m + 1));
     c.beta0 = dalloc<double>(nrep);
     c.hcol = dalloc<double>((size_t)3 * nrep * (c.m + 1));
+    c.inv_nu = dalloc<double>((size_t)nrep * (c.m + 1));
+    zero_device(c, c.inv_nu, (long long)nrep * (c.m + 1));
     c.yv = dalloc<double>((size_t)nrep * (c.m + 1));
     c.d_resid = dalloc<double>(nrep);
     c.active = dalloc<int>(nrep);
@@ -1056,7 +1066,7 @@ static void free_all(Ctx &c) {
     if (c.h_flags) (void)hipHostFree(c.h_flags);
     if (c.h_count) (void)hipHostFree(c.h_count);
     F(c.V); F(c.Z); F(c.W); F(c.xsol); F(c.rhs); F(c.tmp); F(c.xR); F(c.xS); F(c.partial);
-    F(c.H); F(c.cs); F(c.sn); F(c.gv); F(c.beta0); F(c.hcol); F(c.yv); F(c.d_resid);
+    F(c.H); F(c.cs); F(c.sn); F(c.gv); F(c.beta0); F(c.hcol); F(c.inv_nu); F(c.yv); F(c.d_resid);
     F(c.active); F(c.cyc_active); F(c.jf); F(c.status); F(c.iters);
     for (int k = 0; k < 3; ++k) { F(c.q_buf[k]); F(c.th_buf[k]); }
     F(c.Wf); F(c.Wt); F(c.WFT); F(c.Fp); F(c.UR); F(c.slip_acc); F(c.jbc); F(c.theta_int);
