@@ -207,26 +207,31 @@ void launch_zero(Ctx &c, double *y, const int *mask) { launch_axpby(c, 0.0, y, 0
 
 // Arnoldi column j: H[:, j] = h1 + h2 (two Gram-Schmidt passes), H[j+1, j] = ||w||;
 // apply the stored rotations, form the new one, update g and the convergence state.
-__global__ void k_givens(int nrep, int m, int j, double tol, const double *h1, const double *h2, const double *nrm,
-                         double *H, double *cs, double *sn, double *gv, const double *beta0, int *active,
-                         int *jf, int *status, int *iters, double *inv_nu) {
+// The earlier rotations act on the new column h (= h1 + h2, then ||w||) in order; the
+// entry each rotation passes on is carried in a register, so only its fused
+// multiply-adds are serial (the loads of h, c and s are independent of them).
+__global__ void k_givens(int nrep, int m, int j, double tol, const double *__restrict__ h1,
+                         const double *__restrict__ h2, const double *__restrict__ nrm, double *__restrict__ H,
+                         double *__restrict__ cs, double *__restrict__ sn, double *__restrict__ gv,
+                         const double *__restrict__ beta0, int *active, int *jf, int *status, int *iters,
+                         double *__restrict__ inv_nu) {
     int r = blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= nrep || !active[r]) return;
     double *Hc = H + (long long)r * (m + 1) * m + (long long)j * (m + 1);
     double *c = cs + (long long)r * m, *s = sn + (long long)r * m, *g = gv + (long long)r * (m + 1);
-    for (int i = 0; i <= j; ++i) Hc[i] = h1[(long long)r * (m + 1) + i] + h2[(long long)r * (m + 1) + i];
+    const double *a1 = h1 + (long long)r * (m + 1), *a2 = h2 + (long long)r * (m + 1);
     double hn = nrm[r];
-    Hc[j + 1] = hn;
     // basis vector j+1 is kept unnormalised: v_{j+1} = u_{j+1} / hn
     inv_nu[(long long)r * (m + 1) + j + 1] = hn > 0.0 ? 1.0 / hn : 0.0;
+    double x = a1[0] + a2[0];
     for (int i = 0; i < j; ++i) {
-        double t = c[i] * Hc[i] + s[i] * Hc[i + 1];
-        Hc[i + 1] = -s[i] * Hc[i] + c[i] * Hc[i + 1];
-        Hc[i] = t;
+        const double y = a1[i + 1] + a2[i + 1];
+        Hc[i] = fma(c[i], x, s[i] * y);
+        x = fma(-s[i], x, c[i] * y);
     }
-    double den = hypot(Hc[j], Hc[j + 1]);
-    double cj = den > 0.0 ? Hc[j] / den : 1.0;
-    double sj = den > 0.0 ? Hc[j + 1] / den : 0.0;
+    double den = hypot(x, hn);
+    double cj = den > 0.0 ? x / den : 1.0;
+    double sj = den > 0.0 ? hn / den : 0.0;
     c[j] = cj;
     s[j] = sj;
     Hc[j] = den;
