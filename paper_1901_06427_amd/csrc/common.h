@@ -513,7 +513,7 @@ struct Ctx {
     // Krylov
     int m = 0;
     double *V = nullptr, *Z = nullptr, *W = nullptr;
-    double *xsol = nullptr, *rhs = nullptr, *tmp = nullptr;
+    double *xsol = nullptr, *rhs = nullptr;
     double *partial = nullptr;  // [n_tab_vec * (m+1)]
     double *H = nullptr, *cs = nullptr, *sn = nullptr, *gv = nullptr, *beta0 = nullptr, *hcol = nullptr, *yv = nullptr;
     double *inv_nu = nullptr;   // [nrep][m+1]: basis vector i is stored as u_i, with v_i = inv_nu[i] u_i

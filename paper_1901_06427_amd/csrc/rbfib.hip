@@ -1004,7 +1004,6 @@ static void build(Ctx &c, int nrep, const rbfib_grid *grids, const rbfib_bodies 
     c.W = dalloc<double>(L);
     c.xsol = dalloc<double>(L);
     c.rhs = dalloc<double>(L);
-    c.tmp = dalloc<double>(L);
     c.xR = dalloc<double>(L);
     c.xS = dalloc<double>(L);
     c.partial = dalloc<double>((size_t)c.n_tab_vec * (c.m + 1));
@@ -1065,7 +1064,7 @@ static void free_all(Ctx &c) {
     F(c.d_flags); F(c.d_scan); F(c.d_count); F(c.d_active_len);
     if (c.h_flags) (void)hipHostFree(c.h_flags);
     if (c.h_count) (void)hipHostFree(c.h_count);
-    F(c.V); F(c.Z); F(c.W); F(c.xsol); F(c.rhs); F(c.tmp); F(c.xR); F(c.xS); F(c.partial);
+    F(c.V); F(c.Z); F(c.W); F(c.xsol); F(c.rhs); F(c.xR); F(c.xS); F(c.partial);
     F(c.H); F(c.cs); F(c.sn); F(c.gv); F(c.beta0); F(c.hcol); F(c.inv_nu); F(c.yv); F(c.d_resid);
     F(c.active); F(c.cyc_active); F(c.jf); F(c.status); F(c.iters);
     for (int k = 0; k < 3; ++k) { F(c.q_buf[k]); F(c.th_buf[k]); }
