@@ -51,15 +51,19 @@ __global__ __launch_bounds__(RB_BLOCK) void k_dot_partial(const RepDev *reps, co
 // out[r * out_stride + i] = sum of replica r's block partials of vector i, one
 // wavefront per (replica, vector), fixed summation order; times scale[r * out_stride
 // + i] when a scale is given.
+// blockIdx.z = t selects the t-th of several sets: partial entries at + t * zin, outputs at
+// + t * zout.
 __global__ void k_dot_reduce(const int *first, const int *nblk, const double *partial, int stride, double *out,
-                             int out_stride, const int *mask, int take_sqrt, const double *scale) {
+                             int out_stride, const int *mask, int take_sqrt, const double *scale, int zin = 0,
+                             long long zout = 0) {
     int r = blockIdx.x, i = blockIdx.y;
     if (mask && !mask[r]) return;
+    const double *pp = partial + (long long)blockIdx.z * zin;
     double s = 0.0;
-    for (int b = threadIdx.x; b < nblk[r]; b += 64) s += partial[(long long)(first[r] + b) * stride + i];
+    for (int b = threadIdx.x; b < nblk[r]; b += 64) s += pp[(long long)(first[r] + b) * stride + i];
     s = wave_sum(s);
     if (scale) s *= scale[(long long)r * out_stride + i];
-    if (threadIdx.x == 0) out[(long long)r * out_stride + i] = take_sqrt ? sqrt(s) : s;
+    if (threadIdx.x == 0) out[(long long)blockIdx.z * zout + (long long)r * out_stride + i] = take_sqrt ? sqrt(s) : s;
 }
 
 void launch_dots(Ctx &c, const double *V, int nvec, const double *w, double *out, const int *mask,
@@ -207,6 +211,31 @@ void launch_zero(Ctx &c, double *y, const int *mask) { launch_axpby(c, 0.0, y, 0
 
 // Arnoldi column j: H[:, j] = h1 + h2 (two Gram-Schmidt passes), H[j+1, j] = ||w||;
 // apply the stored rotations, form the new one, update g and the convergence state.
+// New Hessenberg column k (entries e(i) for rows i <= k, hlast in row k+1): the earlier
+// rotations 0..k-1 act on it in order, the entry each rotation passes on carried in a
+// register (only the fused multiply-adds are serial), then rotation k is formed and
+// applied to g.  Returns |g[k+1]|, the residual estimate, and den (row k of R).
+template <class Entry>
+__device__ __forceinline__ double givens_column(double *Hc, double *c, double *s, double *g, int k, Entry e,
+                                                double hlast, double &den) {
+    double x = e(0);
+    for (int i = 0; i < k; ++i) {
+        const double y = e(i + 1);
+        Hc[i] = fma(c[i], x, s[i] * y);
+        x = fma(-s[i], x, c[i] * y);
+    }
+    den = hypot(x, hlast);
+    const double ck = den > 0.0 ? x / den : 1.0;
+    const double sk = den > 0.0 ? hlast / den : 0.0;
+    c[k] = ck;
+    s[k] = sk;
+    Hc[k] = den;
+    Hc[k + 1] = 0.0;
+    g[k + 1] = -sk * g[k];
+    g[k] = ck * g[k];
+    return fabs(g[k + 1]);
+}
+
 // The earlier rotations act on the new column h (= h1 + h2, then ||w||) in order; the
 // entry each rotation passes on is carried in a register, so only its fused
 // multiply-adds are serial (the loads of h, c and s are independent of them).
@@ -223,23 +252,9 @@ __global__ void k_givens(int nrep, int m, int j, double tol, const double *__res
     double hn = nrm[r];
     // basis vector j+1 is kept unnormalised: v_{j+1} = u_{j+1} / hn
     inv_nu[(long long)r * (m + 1) + j + 1] = hn > 0.0 ? 1.0 / hn : 0.0;
-    double x = a1[0] + a2[0];
-    for (int i = 0; i < j; ++i) {
-        const double y = a1[i + 1] + a2[i + 1];
-        Hc[i] = fma(c[i], x, s[i] * y);
-        x = fma(-s[i], x, c[i] * y);
-    }
-    double den = hypot(x, hn);
-    double cj = den > 0.0 ? x / den : 1.0;
-    double sj = den > 0.0 ? hn / den : 0.0;
-    c[j] = cj;
-    s[j] = sj;
-    Hc[j] = den;
-    Hc[j + 1] = 0.0;
-    g[j + 1] = -sj * g[j];
-    g[j] = cj * g[j];
+    double den;
+    const double res = givens_column(Hc, c, s, g, j, [&](int i) { return a1[i] + a2[i]; }, hn, den);
     iters[r] += 1;
-    double res = fabs(g[j + 1]);
     if (!isfinite(res) || !isfinite(den)) {
         status[r] = RBFIB_ENUMERIC;
         active[r] = 0;
@@ -259,6 +274,234 @@ void launch_givens(Ctx &c, int j, double tol) {
     double *h1 = c.hcol, *h2 = c.hcol + (long long)c.nrep * (c.m + 1), *nrm = c.hcol + 2LL * c.nrep * (c.m + 1);
     hipLaunchKernelGGL(k_givens, dim3((c.nrep + 63) / 64), dim3(64), 0, c.stream, c.nrep, c.m, j, tol, h1, h2, nrm,
                        c.H, c.cs, c.sn, c.gv, c.beta0, c.active, c.jf, c.status, c.iters, c.inv_nu);
+}
+
+// ------------------------------------------------------------------ two-step blocks
+// A block of two Arnoldi steps forms u_1 = A P^-1 v_j and u_2 = A P^-1 u_1 first, then
+// orthogonalises both against v_0 .. v_j in one pass over the basis for the projections
+// and one for the update, and against each other by a 2 x 2 Cholesky QR of their Gram
+// matrix.  With z_j = P^-1 v_j and z_{j+1} = P^-1 u_1, A Z = V H holds with the
+// projection coefficients and the Cholesky factors as the two new Hessenberg columns.
+
+// partial[blk * stride + t * half + i] = the block's part of V_i . w_t (t = 0, 1)
+__global__ __launch_bounds__(RB_BLOCK) void k_dot_partial2(const RepDev *reps, const BlockEnt *tab, const double *V,
+                                                           long long L, int nvec, const double *__restrict__ w1,
+                                                           const double *__restrict__ w2, double *partial, int stride,
+                                                           int half, const int *mask) {
+    __shared__ double ws1[RB_CHUNK], ws2[RB_CHUNK];
+    BlockEnt be = tab[blockIdx.x];
+    if (mask && !mask[be.rep]) return;
+    const RepDev &R = reps[be.rep];
+    long long b = R.off + be.start;
+    int n = (int)min((long long)RB_CHUNK, R.len - be.start);
+    for (int k = threadIdx.x; k < RB_CHUNK; k += RB_BLOCK) {
+        ws1[k] = (k < n) ? w1[b + k] : 0.0;
+        ws2[k] = (k < n) ? w2[b + k] : 0.0;
+    }
+    __syncthreads();
+    int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    for (int i = wid; i < nvec; i += RB_BLOCK / 64) {
+        const double *Vi = V + (long long)i * L + b;
+        double v[RB_CHUNK / 64];
+#pragma unroll
+        for (int m = 0; m < RB_CHUNK / 64; ++m) {
+            const int k = lane + 64 * m;
+            v[m] = k < n ? __builtin_nontemporal_load(Vi + k) : 0.0;
+        }
+        double a1 = 0.0, a2 = 0.0;
+#pragma unroll
+        for (int m = 0; m < RB_CHUNK / 64; ++m) {
+            a1 = fma(v[m], ws1[lane + 64 * m], a1);
+            a2 = fma(v[m], ws2[lane + 64 * m], a2);
+        }
+        a1 = wave_sum(a1);
+        a2 = wave_sum(a2);
+        if (lane == 0) {
+            partial[(long long)blockIdx.x * stride + i] = a1;
+            partial[(long long)blockIdx.x * stride + half + i] = a2;
+        }
+    }
+}
+
+// out1 / out2 [r][i] = scale[r][i] * (V_i . w1 / w2), out2 = out1 + nrep * (m + 1)
+void launch_dots2(Ctx &c, const double *V, int nvec, const double *w1, const double *w2, double *out1,
+                  const int *mask, const double *scale) {
+    const int half = c.m + 1, stride = 2 * half;
+    hipLaunchKernelGGL(k_dot_partial2, dim3(c.n_tab_vec), dim3(RB_BLOCK), 0, c.stream, c.d_reps, c.d_tab_vec, V,
+                       c.L, nvec, w1, w2, c.partial, stride, half, mask);
+    hipLaunchKernelGGL(k_dot_reduce, dim3(c.nrep, nvec, 2), dim3(64), 0, c.stream, c.d_vec_first, c.d_vec_nblk,
+                       c.partial, stride, out1, c.m + 1, mask, 0, scale, half, (long long)c.nrep * (c.m + 1));
+}
+
+// u_t -= sum_i coef_t[r][i] scale[r][i] V_i (t = 1, 2), and the block partials of
+// (u_1.u_1, u_1.u_2, u_2.u_2) after the update at partial[blk * stride + 0..2]
+__global__ __launch_bounds__(RB_BLOCK) void k_axpy_multi2(const RepDev *reps, const BlockEnt *tab, const double *V,
+                                                          long long L, int nvec, const double *coef1,
+                                                          const double *coef2, int cstride, const double *scale,
+                                                          double *__restrict__ u1, double *__restrict__ u2,
+                                                          const int *mask, double *partial, int stride) {
+    __shared__ double cf1[RB_BLOCK], cf2[RB_BLOCK];   // restart length <= 200 < RB_BLOCK
+    __shared__ double red[3][RB_BLOCK / 64];
+    BlockEnt be = tab[blockIdx.x];
+    if (mask && !mask[be.rep]) return;
+    const RepDev &R = reps[be.rep];
+    if (threadIdx.x < nvec) {
+        const long long ci = (long long)be.rep * cstride + threadIdx.x;
+        const double sc = scale ? scale[ci] : 1.0;
+        cf1[threadIdx.x] = -coef1[ci] * sc;
+        cf2[threadIdx.x] = -coef2[ci] * sc;
+    }
+    __syncthreads();
+    long long b = R.off + be.start;
+    int n = (int)min((long long)RB_CHUNK, R.len - be.start);
+    constexpr int E = RB_CHUNK / RB_BLOCK;
+    double a1[E], a2[E];
+    bool ok[E];
+#pragma unroll
+    for (int m = 0; m < E; ++m) {
+        a1[m] = 0.0;
+        a2[m] = 0.0;
+        ok[m] = threadIdx.x + RB_BLOCK * m < n;
+    }
+    int i = 0;
+    for (; i + 4 <= nvec; i += 4) {
+        double v[4][E];
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int m = 0; m < E; ++m)
+                v[q][m] = ok[m] ? V[(long long)(i + q) * L + b + threadIdx.x + RB_BLOCK * m] : 0.0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int m = 0; m < E; ++m) {
+                a1[m] = fma(cf1[i + q], v[q][m], a1[m]);
+                a2[m] = fma(cf2[i + q], v[q][m], a2[m]);
+            }
+    }
+    for (; i < nvec; ++i) {
+#pragma unroll
+        for (int m = 0; m < E; ++m)
+            if (ok[m]) {
+                const double vv = V[(long long)i * L + b + threadIdx.x + RB_BLOCK * m];
+                a1[m] = fma(cf1[i], vv, a1[m]);
+                a2[m] = fma(cf2[i], vv, a2[m]);
+            }
+    }
+    double s11 = 0.0, s12 = 0.0, s22 = 0.0;
+#pragma unroll
+    for (int m = 0; m < E; ++m) {
+        if (!ok[m]) continue;
+        const long long g = b + threadIdx.x + RB_BLOCK * m;
+        const double x1 = u1[g] + a1[m], x2 = u2[g] + a2[m];
+        u1[g] = x1;
+        u2[g] = x2;
+        s11 = fma(x1, x1, s11);
+        s12 = fma(x1, x2, s12);
+        s22 = fma(x2, x2, s22);
+    }
+    s11 = wave_sum(s11);
+    s12 = wave_sum(s12);
+    s22 = wave_sum(s22);
+    if ((threadIdx.x & 63) == 0) {
+        red[0][threadIdx.x >> 6] = s11;
+        red[1][threadIdx.x >> 6] = s12;
+        red[2][threadIdx.x >> 6] = s22;
+    }
+    __syncthreads();
+    if (threadIdx.x < 3) {
+        double t = 0.0;
+        for (int k = 0; k < RB_BLOCK / 64; ++k) t += red[threadIdx.x][k];
+        partial[(long long)blockIdx.x * stride + threadIdx.x] = t;
+    }
+}
+
+// gram[r][0..2] = (u_1.u_1, u_1.u_2, u_2.u_2) after the update
+void launch_axpy2_gram(Ctx &c, const double *V, int nvec, const double *coef1, const double *coef2, double *u1,
+                       double *u2, double *gram, const int *mask, const double *scale) {
+    const int stride = 2 * (c.m + 1);
+    hipLaunchKernelGGL(k_axpy_multi2, dim3(c.n_tab_vec), dim3(RB_BLOCK), 0, c.stream, c.d_reps, c.d_tab_vec, V, c.L,
+                       nvec, coef1, coef2, c.m + 1, scale, u1, u2, mask, c.partial, stride);
+    hipLaunchKernelGGL(k_dot_reduce, dim3(c.nrep, 3), dim3(64), 0, c.stream, c.d_vec_first, c.d_vec_nblk, c.partial,
+                       stride, gram, 3, mask, 0, (const double *)nullptr, 0, 0LL);
+}
+
+// Columns j and j+1: R = chol(Gram) gives v_{j+1} = u_1 / r11 and, after the combine
+// pass, v_{j+2} = (u_2 - (r12 / r11) u_1) / r22; column j holds the projections of u_1
+// and r11, column j+1 those of u_2, r12 and r22.  A replica that converges at column j
+// leaves column j+1 unused.
+__global__ void k_givens2(int nrep, int m, int j, double tol, const double *__restrict__ h1,
+                          const double *__restrict__ h2, const double *__restrict__ gram, double *__restrict__ H,
+                          double *__restrict__ cs, double *__restrict__ sn, double *__restrict__ gv,
+                          const double *__restrict__ beta0, int *active, int *jf, int *status, int *iters,
+                          double *__restrict__ inv_nu, double *__restrict__ tco) {
+    int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= nrep || !active[r]) return;
+    const double *a1 = h1 + (long long)r * (m + 1), *a2 = h2 + (long long)r * (m + 1);
+    const double g11 = gram[3 * r], g12 = gram[3 * r + 1], g22 = gram[3 * r + 2];
+    const double r11 = sqrt(g11);
+    const double r12 = r11 > 0.0 ? g12 / r11 : 0.0;
+    const double d22 = g22 - r12 * r12;
+    const double r22 = d22 > 0.0 ? sqrt(d22) : 0.0;
+    double *nu = inv_nu + (long long)r * (m + 1);
+    nu[j + 1] = r11 > 0.0 ? 1.0 / r11 : 0.0;
+    nu[j + 2] = r22 > 0.0 ? 1.0 / r22 : 0.0;
+    tco[r] = r11 > 0.0 ? r12 / r11 : 0.0;
+    double *c = cs + (long long)r * m, *s = sn + (long long)r * m, *g = gv + (long long)r * (m + 1);
+    double *H0 = H + (long long)r * (m + 1) * m + (long long)j * (m + 1);
+    double den;
+    double res = givens_column(H0, c, s, g, j, [&](int i) { return a1[i]; }, r11, den);
+    iters[r] += 1;
+    if (!isfinite(res) || !isfinite(den)) {
+        status[r] = RBFIB_ENUMERIC;
+        active[r] = 0;
+        jf[r] = j;
+        return;
+    }
+    if (res <= tol * beta0[r] || r11 == 0.0) {
+        active[r] = 0;
+        jf[r] = j + 1;
+        status[r] = RBFIB_OK;
+        return;
+    }
+    res = givens_column(H0 + (m + 1), c, s, g, j + 1, [&](int i) { return i <= j ? a2[i] : r12; }, r22, den);
+    iters[r] += 1;
+    if (!isfinite(res) || !isfinite(den)) {
+        status[r] = RBFIB_ENUMERIC;
+        active[r] = 0;
+        jf[r] = j + 1;
+        return;
+    }
+    if (res <= tol * beta0[r] || r22 == 0.0) {
+        active[r] = 0;
+        jf[r] = j + 2;
+        status[r] = RBFIB_OK;
+    } else if (j + 2 == m) {
+        jf[r] = m;
+    }
+}
+
+void launch_givens2(Ctx &c, int j, double tol) {
+    double *h1 = c.hcol, *h2 = c.hcol + (long long)c.nrep * (c.m + 1);
+    hipLaunchKernelGGL(k_givens2, dim3((c.nrep + 63) / 64), dim3(64), 0, c.stream, c.nrep, c.m, j, tol, h1, h2,
+                       c.gram, c.H, c.cs, c.sn, c.gv, c.beta0, c.active, c.jf, c.status, c.iters, c.inv_nu, c.tco);
+}
+
+// u_2 -= tco[r] u_1 (replicas still active)
+__global__ void k_combine(const RepDev *reps, const BlockEnt *tab, const double *__restrict__ u1,
+                          double *__restrict__ u2, const double *__restrict__ tco, const int *mask) {
+    BlockEnt be = tab[blockIdx.x];
+    if (mask && !mask[be.rep]) return;
+    const RepDev &R = reps[be.rep];
+    const double f = tco[be.rep];
+    long long b = R.off + be.start;
+    long long e = R.off + min(be.start + (long long)RB_CHUNK, R.len);
+    for (long long g = b + threadIdx.x; g < e; g += RB_BLOCK) u2[g] = fma(-f, u1[g], u2[g]);
+}
+
+void launch_combine(Ctx &c, const double *u1, double *u2, const int *mask) {
+    hipLaunchKernelGGL(k_combine, dim3(c.n_tab_vec), dim3(RB_BLOCK), 0, c.stream, c.d_reps, c.d_tab_vec, u1, u2,
+                       c.tco, mask);
 }
 
 // Back substitution H[0:jf, 0:jf] y = g[0:jf] for replicas active at cycle start.
