@@ -137,9 +137,10 @@ typedef struct {
     double mg_cheby;           /* > 0: sweep k of nu has weight 1 / lambda_k, the    */
                                /*    roots of the degree-nu Chebyshev polynomial on  */
                                /*    [mg_cheby, 2]; 0: every sweep mg_omega (0.27)   */
-    int krylov_s;              /* Arnoldi steps per block: 1, or 2 (two new vectors  */
-                               /*    orthogonalised in one pass over the basis;      */
-                               /*    even restart; tol >= 1e-9) (2)                  */
+    int krylov_s;              /* Arnoldi steps per block, 1..4: the block's new     */
+                               /*    vectors are orthogonalised in one pass over the */
+                               /*    basis (tol >= 1e-9; a shorter last block runs   */
+                               /*    single steps) (2)                               */
 } rbfib_opts;
 
 typedef struct {

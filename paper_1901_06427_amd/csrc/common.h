@@ -36,6 +36,9 @@
 #define MGB_LDS (64 * 1024)
 // most damped-Jacobi sweeps per level and direction
 #define RB_MAXSWEEP 16
+// largest s-step Arnoldi block, and the packed upper triangle of its Gram matrix
+#define RB_MAXS 4
+#define RB_MAXG (RB_MAXS * (RB_MAXS + 1) / 2)
 
 namespace rb {
 
@@ -517,8 +520,9 @@ struct Ctx {
     double *partial = nullptr;  // [n_tab_vec * (m+1)]
     double *H = nullptr, *cs = nullptr, *sn = nullptr, *gv = nullptr, *beta0 = nullptr, *hcol = nullptr, *yv = nullptr;
     double *inv_nu = nullptr;   // [nrep][m+1]: basis vector i is stored as u_i, with v_i = inv_nu[i] u_i
-    double *gram = nullptr;     // [nrep][3]: Gram matrix of the two new vectors of a two-step block
-    double *tco = nullptr;      // [nrep]: r12 / r11 of that block
+    double *hblk = nullptr;     // [RB_MAXS][nrep][m+1]: projections of an s-step block's new vectors
+    double *gram = nullptr;     // [nrep][RB_MAXG]: upper triangle of their Gram matrix
+    double *tco = nullptr;      // [nrep][RB_MAXS][RB_MAXS]: combine coefficients R_lk / R_ll
     int *active = nullptr, *cyc_active = nullptr, *jf = nullptr, *status = nullptr, *iters = nullptr;
     int *h_count = nullptr;     // pinned
     double *d_resid = nullptr;  // [nrep]
@@ -592,12 +596,11 @@ void launch_scale(Ctx &c, const double *w, const double *s, double *out, const i
 void launch_axpby(Ctx &c, double a, const double *x, double b, const double *y, double *out, const int *mask);
 void launch_copy(Ctx &c, const double *x, double *y, const int *mask);
 void launch_zero(Ctx &c, double *y, const int *mask);
-void launch_dots2(Ctx &c, const double *V, int nvec, const double *w1, const double *w2, double *out1, const int *mask,
-                  const double *scale);
-void launch_axpy2_gram(Ctx &c, const double *V, int nvec, const double *coef1, const double *coef2, double *u1,
-                       double *u2, double *gram, const int *mask, const double *scale);
-void launch_givens2(Ctx &c, int j, double tol);
-void launch_combine(Ctx &c, const double *u1, double *u2, const int *mask);
+void launch_block_dots(Ctx &c, int S, const double *V, int nvec, const double *W, const int *mask,
+                       const double *scale);
+void launch_block_update(Ctx &c, int S, const double *V, int nvec, double *W, const int *mask, const double *scale);
+void launch_givens_s(Ctx &c, int j, int S, double tol);
+void launch_combine_s(Ctx &c, int S, double *W, const int *mask);
 void launch_givens(Ctx &c, int j, double tol);
 void launch_start_cycle(Ctx &c);
 void launch_trisolve_update(Ctx &c);

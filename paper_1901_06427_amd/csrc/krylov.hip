@@ -276,28 +276,29 @@ void launch_givens(Ctx &c, int j, double tol) {
                        c.H, c.cs, c.sn, c.gv, c.beta0, c.active, c.jf, c.status, c.iters, c.inv_nu);
 }
 
-// ------------------------------------------------------------------ two-step blocks
-// A block of two Arnoldi steps forms u_1 = A P^-1 v_j and u_2 = A P^-1 u_1 first, then
-// orthogonalises both against v_0 .. v_j in one pass over the basis for the projections
-// and one for the update, and against each other by a 2 x 2 Cholesky QR of their Gram
-// matrix.  With z_j = P^-1 v_j and z_{j+1} = P^-1 u_1, A Z = V H holds with the
-// projection coefficients and the Cholesky factors as the two new Hessenberg columns.
+// ------------------------------------------------------------------ s-step blocks
+// A block of S Arnoldi steps (S = 2..4) forms u_1 = A P^-1 v_j and u_{k+1} = A P^-1 u_k
+// first (in basis slots j+1 .. j+S), then orthogonalises all S against v_0 .. v_j with
+// one projection pass and one update pass over the basis, and among themselves by a
+// Cholesky QR of their S x S Gram matrix (accumulated by the update pass).  With
+// z_j = P^-1 v_j and z_{j+k} = P^-1 u_k, A Z = V H holds with the projection
+// coefficients and the Cholesky factor R as the S new Hessenberg columns, so flexible
+// GMRES applies unchanged.  The basis is streamed once per S steps.
 
-// partial[blk * stride + t * half + i] = the block's part of V_i . w_t (t = 0, 1)
-__global__ __launch_bounds__(RB_BLOCK) void k_dot_partial2(const RepDev *reps, const BlockEnt *tab, const double *V,
-                                                           long long L, int nvec, const double *__restrict__ w1,
-                                                           const double *__restrict__ w2, double *partial, int stride,
-                                                           int half, const int *mask) {
-    __shared__ double ws1[RB_CHUNK], ws2[RB_CHUNK];
+// partial[blk * stride + t * half + i] = the block's part of V_i . w_t, w_t = W + t L
+template <int S>
+__global__ __launch_bounds__(RB_BLOCK) void k_dot_partial_s(const RepDev *reps, const BlockEnt *tab, const double *V,
+                                                            long long L, int nvec, const double *W, double *partial,
+                                                            int stride, int half, const int *mask) {
+    __shared__ double ws[S][RB_CHUNK];
     BlockEnt be = tab[blockIdx.x];
     if (mask && !mask[be.rep]) return;
     const RepDev &R = reps[be.rep];
     long long b = R.off + be.start;
     int n = (int)min((long long)RB_CHUNK, R.len - be.start);
-    for (int k = threadIdx.x; k < RB_CHUNK; k += RB_BLOCK) {
-        ws1[k] = (k < n) ? w1[b + k] : 0.0;
-        ws2[k] = (k < n) ? w2[b + k] : 0.0;
-    }
+    for (int k = threadIdx.x; k < RB_CHUNK; k += RB_BLOCK)
+#pragma unroll
+        for (int t = 0; t < S; ++t) ws[t][k] = (k < n) ? W[(long long)t * L + b + k] : 0.0;
     __syncthreads();
     int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     for (int i = wid; i < nvec; i += RB_BLOCK / 64) {
@@ -308,60 +309,52 @@ __global__ __launch_bounds__(RB_BLOCK) void k_dot_partial2(const RepDev *reps, c
             const int k = lane + 64 * m;
             v[m] = k < n ? __builtin_nontemporal_load(Vi + k) : 0.0;
         }
-        double a1 = 0.0, a2 = 0.0;
+        double a[S];
 #pragma unroll
-        for (int m = 0; m < RB_CHUNK / 64; ++m) {
-            a1 = fma(v[m], ws1[lane + 64 * m], a1);
-            a2 = fma(v[m], ws2[lane + 64 * m], a2);
-        }
-        a1 = wave_sum(a1);
-        a2 = wave_sum(a2);
-        if (lane == 0) {
-            partial[(long long)blockIdx.x * stride + i] = a1;
-            partial[(long long)blockIdx.x * stride + half + i] = a2;
+        for (int t = 0; t < S; ++t) a[t] = 0.0;
+#pragma unroll
+        for (int m = 0; m < RB_CHUNK / 64; ++m)
+#pragma unroll
+            for (int t = 0; t < S; ++t) a[t] = fma(v[m], ws[t][lane + 64 * m], a[t]);
+#pragma unroll
+        for (int t = 0; t < S; ++t) {
+            const double st = wave_sum(a[t]);
+            if (lane == 0) partial[(long long)blockIdx.x * stride + t * half + i] = st;
         }
     }
 }
 
-// out1 / out2 [r][i] = scale[r][i] * (V_i . w1 / w2), out2 = out1 + nrep * (m + 1)
-void launch_dots2(Ctx &c, const double *V, int nvec, const double *w1, const double *w2, double *out1,
-                  const int *mask, const double *scale) {
-    const int half = c.m + 1, stride = 2 * half;
-    hipLaunchKernelGGL(k_dot_partial2, dim3(c.n_tab_vec), dim3(RB_BLOCK), 0, c.stream, c.d_reps, c.d_tab_vec, V,
-                       c.L, nvec, w1, w2, c.partial, stride, half, mask);
-    hipLaunchKernelGGL(k_dot_reduce, dim3(c.nrep, nvec, 2), dim3(64), 0, c.stream, c.d_vec_first, c.d_vec_nblk,
-                       c.partial, stride, out1, c.m + 1, mask, 0, scale, half, (long long)c.nrep * (c.m + 1));
-}
-
-// u_t -= sum_i coef_t[r][i] scale[r][i] V_i (t = 1, 2), and the block partials of
-// (u_1.u_1, u_1.u_2, u_2.u_2) after the update at partial[blk * stride + 0..2]
-__global__ __launch_bounds__(RB_BLOCK) void k_axpy_multi2(const RepDev *reps, const BlockEnt *tab, const double *V,
-                                                          long long L, int nvec, const double *coef1,
-                                                          const double *coef2, int cstride, const double *scale,
-                                                          double *__restrict__ u1, double *__restrict__ u2,
-                                                          const int *mask, double *partial, int stride) {
-    __shared__ double cf1[RB_BLOCK], cf2[RB_BLOCK];   // restart length <= 200 < RB_BLOCK
-    __shared__ double red[3][RB_BLOCK / 64];
+// u_t -= sum_i coef[t][r][i] scale[r][i] V_i (t < S, u_t = W + t L, coef sets nrep (m+1)
+// apart), and the block partials of the upper triangle of the Gram matrix of the
+// updated u (row-major, S (S + 1) / 2 entries) at partial[blk * stride + q]
+template <int S>
+__global__ __launch_bounds__(RB_BLOCK) void k_axpy_multi_s(const RepDev *reps, const BlockEnt *tab, const double *V,
+                                                           long long L, int nvec, const double *coef,
+                                                           long long cset, int cstride, const double *scale,
+                                                           double *W, const int *mask, double *partial, int stride) {
+    constexpr int NG = S * (S + 1) / 2;
+    __shared__ double cf[S][RB_BLOCK];   // restart length <= 200 < RB_BLOCK
+    __shared__ double red[NG][RB_BLOCK / 64];
     BlockEnt be = tab[blockIdx.x];
     if (mask && !mask[be.rep]) return;
     const RepDev &R = reps[be.rep];
     if (threadIdx.x < nvec) {
         const long long ci = (long long)be.rep * cstride + threadIdx.x;
         const double sc = scale ? scale[ci] : 1.0;
-        cf1[threadIdx.x] = -coef1[ci] * sc;
-        cf2[threadIdx.x] = -coef2[ci] * sc;
+#pragma unroll
+        for (int t = 0; t < S; ++t) cf[t][threadIdx.x] = -coef[t * cset + ci] * sc;
     }
     __syncthreads();
     long long b = R.off + be.start;
     int n = (int)min((long long)RB_CHUNK, R.len - be.start);
     constexpr int E = RB_CHUNK / RB_BLOCK;
-    double a1[E], a2[E];
+    double a[S][E];
     bool ok[E];
 #pragma unroll
     for (int m = 0; m < E; ++m) {
-        a1[m] = 0.0;
-        a2[m] = 0.0;
         ok[m] = threadIdx.x + RB_BLOCK * m < n;
+#pragma unroll
+        for (int t = 0; t < S; ++t) a[t][m] = 0.0;
     }
     int i = 0;
     for (; i + 4 <= nvec; i += 4) {
@@ -374,134 +367,219 @@ __global__ __launch_bounds__(RB_BLOCK) void k_axpy_multi2(const RepDev *reps, co
 #pragma unroll
         for (int q = 0; q < 4; ++q)
 #pragma unroll
-            for (int m = 0; m < E; ++m) {
-                a1[m] = fma(cf1[i + q], v[q][m], a1[m]);
-                a2[m] = fma(cf2[i + q], v[q][m], a2[m]);
-            }
+            for (int m = 0; m < E; ++m)
+#pragma unroll
+                for (int t = 0; t < S; ++t) a[t][m] = fma(cf[t][i + q], v[q][m], a[t][m]);
     }
     for (; i < nvec; ++i) {
 #pragma unroll
         for (int m = 0; m < E; ++m)
             if (ok[m]) {
                 const double vv = V[(long long)i * L + b + threadIdx.x + RB_BLOCK * m];
-                a1[m] = fma(cf1[i], vv, a1[m]);
-                a2[m] = fma(cf2[i], vv, a2[m]);
+#pragma unroll
+                for (int t = 0; t < S; ++t) a[t][m] = fma(cf[t][i], vv, a[t][m]);
             }
     }
-    double s11 = 0.0, s12 = 0.0, s22 = 0.0;
+    double gs[NG];
+#pragma unroll
+    for (int q = 0; q < NG; ++q) gs[q] = 0.0;
 #pragma unroll
     for (int m = 0; m < E; ++m) {
         if (!ok[m]) continue;
         const long long g = b + threadIdx.x + RB_BLOCK * m;
-        const double x1 = u1[g] + a1[m], x2 = u2[g] + a2[m];
-        u1[g] = x1;
-        u2[g] = x2;
-        s11 = fma(x1, x1, s11);
-        s12 = fma(x1, x2, s12);
-        s22 = fma(x2, x2, s22);
+        double x[S];
+#pragma unroll
+        for (int t = 0; t < S; ++t) {
+            x[t] = W[(long long)t * L + g] + a[t][m];
+            W[(long long)t * L + g] = x[t];
+        }
+        int q = 0;
+#pragma unroll
+        for (int p = 0; p < S; ++p)
+#pragma unroll
+            for (int t = p; t < S; ++t) gs[q] = fma(x[p], x[t], gs[q]), ++q;
     }
-    s11 = wave_sum(s11);
-    s12 = wave_sum(s12);
-    s22 = wave_sum(s22);
-    if ((threadIdx.x & 63) == 0) {
-        red[0][threadIdx.x >> 6] = s11;
-        red[1][threadIdx.x >> 6] = s12;
-        red[2][threadIdx.x >> 6] = s22;
+#pragma unroll
+    for (int q = 0; q < NG; ++q) {
+        const double w = wave_sum(gs[q]);
+        if ((threadIdx.x & 63) == 0) red[q][threadIdx.x >> 6] = w;
     }
     __syncthreads();
-    if (threadIdx.x < 3) {
+    if (threadIdx.x < NG) {
         double t = 0.0;
         for (int k = 0; k < RB_BLOCK / 64; ++k) t += red[threadIdx.x][k];
         partial[(long long)blockIdx.x * stride + threadIdx.x] = t;
     }
 }
 
-// gram[r][0..2] = (u_1.u_1, u_1.u_2, u_2.u_2) after the update
-void launch_axpy2_gram(Ctx &c, const double *V, int nvec, const double *coef1, const double *coef2, double *u1,
-                       double *u2, double *gram, const int *mask, const double *scale) {
-    const int stride = 2 * (c.m + 1);
-    hipLaunchKernelGGL(k_axpy_multi2, dim3(c.n_tab_vec), dim3(RB_BLOCK), 0, c.stream, c.d_reps, c.d_tab_vec, V, c.L,
-                       nvec, coef1, coef2, c.m + 1, scale, u1, u2, mask, c.partial, stride);
-    hipLaunchKernelGGL(k_dot_reduce, dim3(c.nrep, 3), dim3(64), 0, c.stream, c.d_vec_first, c.d_vec_nblk, c.partial,
-                       stride, gram, 3, mask, 0, (const double *)nullptr, 0, 0LL);
+// hblk[t][r][i] = scale[r][i] (V_i . u_t), u_t = W + t L
+void launch_block_dots(Ctx &c, int S, const double *V, int nvec, const double *W, const int *mask,
+                       const double *scale) {
+    const int half = c.m + 1, stride = RB_MAXS * half;
+    const long long cset = (long long)c.nrep * (c.m + 1);
+#define RB_DOTS(SS)                                                                                                  \
+    hipLaunchKernelGGL(k_dot_partial_s<SS>, dim3(c.n_tab_vec), dim3(RB_BLOCK), 0, c.stream, c.d_reps, c.d_tab_vec, V, \
+                       c.L, nvec, W, c.partial, stride, half, mask)
+    if (S == 2) RB_DOTS(2);
+    else if (S == 3) RB_DOTS(3);
+    else RB_DOTS(4);
+#undef RB_DOTS
+    hipLaunchKernelGGL(k_dot_reduce, dim3(c.nrep, nvec, S), dim3(64), 0, c.stream, c.d_vec_first, c.d_vec_nblk,
+                       c.partial, stride, c.hblk, c.m + 1, mask, 0, scale, half, cset);
 }
 
-// Columns j and j+1: R = chol(Gram) gives v_{j+1} = u_1 / r11 and, after the combine
-// pass, v_{j+2} = (u_2 - (r12 / r11) u_1) / r22; column j holds the projections of u_1
-// and r11, column j+1 those of u_2, r12 and r22.  A replica that converges at column j
-// leaves column j+1 unused.
-__global__ void k_givens2(int nrep, int m, int j, double tol, const double *__restrict__ h1,
-                          const double *__restrict__ h2, const double *__restrict__ gram, double *__restrict__ H,
-                          double *__restrict__ cs, double *__restrict__ sn, double *__restrict__ gv,
-                          const double *__restrict__ beta0, int *active, int *jf, int *status, int *iters,
-                          double *__restrict__ inv_nu, double *__restrict__ tco) {
+// u_t -= sum_i hblk[t][r][i] scale[r][i] V_i; gram[r][q] = upper triangle of U^T U after it
+void launch_block_update(Ctx &c, int S, const double *V, int nvec, double *W, const int *mask, const double *scale) {
+    const int stride = RB_MAXS * (c.m + 1);
+    const long long cset = (long long)c.nrep * (c.m + 1);
+#define RB_UPD(SS)                                                                                                   \
+    hipLaunchKernelGGL(k_axpy_multi_s<SS>, dim3(c.n_tab_vec), dim3(RB_BLOCK), 0, c.stream, c.d_reps, c.d_tab_vec, V,  \
+                       c.L, nvec, c.hblk, cset, c.m + 1, scale, W, mask, c.partial, stride)
+    if (S == 2) RB_UPD(2);
+    else if (S == 3) RB_UPD(3);
+    else RB_UPD(4);
+#undef RB_UPD
+    const int ng = S * (S + 1) / 2;
+    hipLaunchKernelGGL(k_dot_reduce, dim3(c.nrep, ng), dim3(64), 0, c.stream, c.d_vec_first, c.d_vec_nblk, c.partial,
+                       stride, c.gram, RB_MAXG, mask, 0, (const double *)nullptr, 0, 0LL);
+}
+
+// Columns j .. j+S-1: the Cholesky factor R of the Gram matrix gives v_{j+k} = w_k / R_kk
+// with w_1 = u_1, w_k = u_k - sum_{l<k} (R_lk / R_ll) w_l (the combine pass);
+// column j+k-1 holds the projections of u_k and R_1k .. R_kk.  A replica that
+// converges (or whose Gram matrix loses rank) at a column leaves the later ones unused.
+template <int S>
+__global__ void k_givens_s(int nrep, int m, int j, double tol, const double *__restrict__ hblk,
+                           const double *__restrict__ gram, double *__restrict__ H, double *__restrict__ cs,
+                           double *__restrict__ sn, double *__restrict__ gv, const double *__restrict__ beta0,
+                           int *active, int *jf, int *status, int *iters, double *__restrict__ inv_nu,
+                           double *__restrict__ tco) {
     int r = blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= nrep || !active[r]) return;
-    const double *a1 = h1 + (long long)r * (m + 1), *a2 = h2 + (long long)r * (m + 1);
-    const double g11 = gram[3 * r], g12 = gram[3 * r + 1], g22 = gram[3 * r + 2];
-    const double r11 = sqrt(g11);
-    const double r12 = r11 > 0.0 ? g12 / r11 : 0.0;
-    const double d22 = g22 - r12 * r12;
-    const double r22 = d22 > 0.0 ? sqrt(d22) : 0.0;
+    const long long cset = (long long)nrep * (m + 1);
+    // Cholesky factor of the packed upper triangle (all loops unrolled: constant indices)
+    const double *gr = gram + (long long)r * RB_MAXG;
+    double G[S][S], Rm[S][S];
+    {
+        int q = 0;
+#pragma unroll
+        for (int p = 0; p < S; ++p)
+#pragma unroll
+            for (int t = 0; t < S; ++t) {
+                Rm[p][t] = 0.0;
+                if (t >= p) G[p][t] = gr[q++];
+                else G[p][t] = 0.0;
+            }
+    }
+    int rank = S;   // leading columns with a positive pivot
+#pragma unroll
+    for (int t = 0; t < S; ++t) {
+        double d = G[t][t];
+#pragma unroll
+        for (int p = 0; p < t; ++p) d -= Rm[p][t] * Rm[p][t];
+        const bool ok = rank == S && d > 0.0;
+        if (!ok && rank == S) rank = t;
+        Rm[t][t] = ok ? sqrt(d) : 0.0;
+#pragma unroll
+        for (int u = t + 1; u < S; ++u) {
+            double e = G[t][u];
+#pragma unroll
+            for (int p = 0; p < t; ++p) e -= Rm[p][t] * Rm[p][u];
+            Rm[t][u] = ok ? e / Rm[t][t] : 0.0;
+        }
+    }
     double *nu = inv_nu + (long long)r * (m + 1);
-    nu[j + 1] = r11 > 0.0 ? 1.0 / r11 : 0.0;
-    nu[j + 2] = r22 > 0.0 ? 1.0 / r22 : 0.0;
-    tco[r] = r11 > 0.0 ? r12 / r11 : 0.0;
+    double *T = tco + (long long)r * RB_MAXS * RB_MAXS;
+#pragma unroll
+    for (int k = 0; k < S; ++k) nu[j + 1 + k] = Rm[k][k] > 0.0 ? 1.0 / Rm[k][k] : 0.0;
+#pragma unroll
+    for (int l = 0; l < S; ++l)
+#pragma unroll
+        for (int k = 0; k < S; ++k) T[l * RB_MAXS + k] = (l < k && Rm[l][l] > 0.0) ? Rm[l][k] / Rm[l][l] : 0.0;
     double *c = cs + (long long)r * m, *s = sn + (long long)r * m, *g = gv + (long long)r * (m + 1);
     double *H0 = H + (long long)r * (m + 1) * m + (long long)j * (m + 1);
-    double den;
-    double res = givens_column(H0, c, s, g, j, [&](int i) { return a1[i]; }, r11, den);
-    iters[r] += 1;
-    if (!isfinite(res) || !isfinite(den)) {
-        status[r] = RBFIB_ENUMERIC;
-        active[r] = 0;
-        jf[r] = j;
-        return;
+#pragma unroll
+    for (int k = 0; k < S; ++k) {
+        const double *a = hblk + k * cset + (long long)r * (m + 1);
+        // column j+k: rows 0..j the projections of u_{k+1}, rows j+1 .. j+k+1 R[0..k][k]
+        double rc[S];
+#pragma unroll
+        for (int p = 0; p < S; ++p) rc[p] = Rm[p][k];
+        auto entry = [&](int i) {
+            if (i <= j) return a[i];
+            const int d = i - j - 1;
+            double v = 0.0;
+#pragma unroll
+            for (int p = 0; p < S; ++p) v = (d == p) ? rc[p] : v;
+            return v;
+        };
+        const double last = rc[k];
+        double den;
+        const double res = givens_column(H0 + (long long)k * (m + 1), c, s, g, j + k, entry, last, den);
+        iters[r] += 1;
+        if (!isfinite(res) || !isfinite(den)) {
+            status[r] = RBFIB_ENUMERIC;
+            active[r] = 0;
+            jf[r] = j + k;
+            return;
+        }
+        if (res <= tol * beta0[r] || !(last > 0.0)) {
+            active[r] = 0;
+            jf[r] = j + k + 1;
+            status[r] = RBFIB_OK;
+            return;
+        }
     }
-    if (res <= tol * beta0[r] || r11 == 0.0) {
-        active[r] = 0;
-        jf[r] = j + 1;
-        status[r] = RBFIB_OK;
-        return;
-    }
-    res = givens_column(H0 + (m + 1), c, s, g, j + 1, [&](int i) { return i <= j ? a2[i] : r12; }, r22, den);
-    iters[r] += 1;
-    if (!isfinite(res) || !isfinite(den)) {
-        status[r] = RBFIB_ENUMERIC;
-        active[r] = 0;
-        jf[r] = j + 1;
-        return;
-    }
-    if (res <= tol * beta0[r] || r22 == 0.0) {
-        active[r] = 0;
-        jf[r] = j + 2;
-        status[r] = RBFIB_OK;
-    } else if (j + 2 == m) {
-        jf[r] = m;
-    }
+    (void)rank;
+    if (j + S == m) jf[r] = m;
 }
 
-void launch_givens2(Ctx &c, int j, double tol) {
-    double *h1 = c.hcol, *h2 = c.hcol + (long long)c.nrep * (c.m + 1);
-    hipLaunchKernelGGL(k_givens2, dim3((c.nrep + 63) / 64), dim3(64), 0, c.stream, c.nrep, c.m, j, tol, h1, h2,
-                       c.gram, c.H, c.cs, c.sn, c.gv, c.beta0, c.active, c.jf, c.status, c.iters, c.inv_nu, c.tco);
+void launch_givens_s(Ctx &c, int j, int S, double tol) {
+#define RB_GIV(SS)                                                                                                   \
+    hipLaunchKernelGGL(k_givens_s<SS>, dim3((c.nrep + 63) / 64), dim3(64), 0, c.stream, c.nrep, c.m, j, tol, c.hblk, \
+                       c.gram, c.H, c.cs, c.sn, c.gv, c.beta0, c.active, c.jf, c.status, c.iters, c.inv_nu, c.tco)
+    if (S == 2) RB_GIV(2);
+    else if (S == 3) RB_GIV(3);
+    else RB_GIV(4);
+#undef RB_GIV
 }
 
-// u_2 -= tco[r] u_1 (replicas still active)
-__global__ void k_combine(const RepDev *reps, const BlockEnt *tab, const double *__restrict__ u1,
-                          double *__restrict__ u2, const double *__restrict__ tco, const int *mask) {
+// w_1 = u_1, w_k = u_k - sum_{l<k} T[l][k] w_l in place (slots W + t L), active replicas
+template <int S>
+__global__ void k_combine_s(const RepDev *reps, const BlockEnt *tab, long long L, double *W,
+                            const double *__restrict__ tco, const int *mask) {
     BlockEnt be = tab[blockIdx.x];
     if (mask && !mask[be.rep]) return;
     const RepDev &R = reps[be.rep];
-    const double f = tco[be.rep];
+    const double *T = tco + (long long)be.rep * RB_MAXS * RB_MAXS;
+    double f[S][S];
+#pragma unroll
+    for (int l = 0; l < S; ++l)
+#pragma unroll
+        for (int k = 0; k < S; ++k) f[l][k] = T[l * RB_MAXS + k];
     long long b = R.off + be.start;
     long long e = R.off + min(be.start + (long long)RB_CHUNK, R.len);
-    for (long long g = b + threadIdx.x; g < e; g += RB_BLOCK) u2[g] = fma(-f, u1[g], u2[g]);
+    for (long long g = b + threadIdx.x; g < e; g += RB_BLOCK) {
+        double w[S];
+#pragma unroll
+        for (int k = 0; k < S; ++k) w[k] = W[(long long)k * L + g];
+#pragma unroll
+        for (int k = 1; k < S; ++k) {
+#pragma unroll
+            for (int l = 0; l < k; ++l) w[k] = fma(-f[l][k], w[l], w[k]);
+            W[(long long)k * L + g] = w[k];
+        }
+    }
 }
 
-void launch_combine(Ctx &c, const double *u1, double *u2, const int *mask) {
-    hipLaunchKernelGGL(k_combine, dim3(c.n_tab_vec), dim3(RB_BLOCK), 0, c.stream, c.d_reps, c.d_tab_vec, u1, u2,
-                       c.tco, mask);
+void launch_combine_s(Ctx &c, int S, double *W, const int *mask) {
+#define RB_CMB(SS)                                                                                                   \
+    hipLaunchKernelGGL(k_combine_s<SS>, dim3(c.n_tab_vec), dim3(RB_BLOCK), 0, c.stream, c.d_reps, c.d_tab_vec, c.L, W, \
+                       c.tco, mask)
+    if (S == 2) RB_CMB(2);
+    else if (S == 3) RB_CMB(3);
+    else RB_CMB(4);
+#undef RB_CMB
 }
 
 // Back substitution H[0:jf, 0:jf] y = g[0:jf] for replicas active at cycle start.

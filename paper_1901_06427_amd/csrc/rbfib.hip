@@ -384,13 +384,14 @@ static void fgmres(Ctx &c, MarkerSet &ms, const double *theta, const double *b, 
     bool done = count_active(c) == 0;
     zero_device(c, h2, (long long)c.nrep * (m + 1));
     const bool reorth = tol < 1e-9;
-    // Arnoldi steps per block: two-step blocks (krylov_s = 2) need an even restart and
-    // are not used with the second Gram-Schmidt pass of tight tolerances
-    const int sb = (c.opts.krylov_s == 2 && !reorth && m % 2 == 0) ? 2 : 1;
+    // Arnoldi steps per block (krylov_s; single steps with the second Gram-Schmidt pass
+    // of tight tolerances); a last block shorter than that runs single steps
+    const int sb = reorth ? 1 : std::max(1, std::min(c.opts.krylov_s, RB_MAXS));
     const int check_blocks = std::max(1, check / sb);
     while (true) {
         while (!done) {
-            for (int j = 0; j < m; j += sb) {
+            for (int j = 0; j < m; j += (j + sb <= m ? sb : 1)) {
+                const int sj = j + sb <= m ? sb : 1;   // steps in this block
                 // one Arnoldi step: z_j = P^-1 v_j, w = A z_j, classical Gram-Schmidt
                 // (one pass), ||w||, Givens update.  The basis is kept unnormalised:
                 // slot i holds u_i with v_i = inv_nu[i] u_i, so w is formed in slot j+1,
@@ -398,31 +399,32 @@ static void fgmres(Ctx &c, MarkerSet &ms, const double *theta, const double *b, 
                 // Givens kernel); the projections, the update coefficients and the
                 // preconditioner's reads of v_j apply the factors.  Loss of
                 // orthogonality is caught by the true-residual check below.
-                auto body2 = [&]() {
-                    // two-step block: u_1 = A P^-1 v_j in slot j+1, u_2 = A P^-1 u_1 in
-                    // slot j+2, one projection pass and one update pass for both, the
-                    // 2 x 2 Cholesky QR in the Givens kernel, then u_2 -= (r12 / r11) u_1
-                    double *Vj = c.V + (long long)j * c.L, *Zj = c.Z + (long long)j * c.L;
-                    double *U1 = c.V + (long long)(j + 1) * c.L, *U2 = c.V + (long long)(j + 2) * c.L;
-                    double *Zj1 = c.Z + (long long)(j + 1) * c.L;
+                auto body_s = [&]() {
+                    // s-step block: u_1 = A P^-1 v_j, u_{k+1} = A P^-1 u_k in slots j+1 ..
+                    // j+sj, one projection pass and one update pass for all of them, the
+                    // Cholesky QR of their Gram matrix in the Givens kernel, then the
+                    // combine pass that makes slot j+k the k-th new direction
+                    double *W = c.V + (long long)(j + 1) * c.L;
                     c.mask = c.timing.on ? nullptr : c.active;
-                    precond(c, ms, theta, Vj, Zj, fluid_only, c.inv_nu + j);
-                    apply_op(c, ms, Zj, U1, fluid_only);
-                    precond(c, ms, theta, U1, Zj1, fluid_only);
-                    apply_op(c, ms, Zj1, U2, fluid_only);
+                    for (int k = 0; k < sj; ++k) {
+                        const double *src = c.V + (long long)(j + k) * c.L;
+                        double *zk = c.Z + (long long)(j + k) * c.L;
+                        precond(c, ms, theta, src, zk, fluid_only, k == 0 ? c.inv_nu + j : nullptr);
+                        apply_op(c, ms, zk, c.V + (long long)(j + k + 1) * c.L, fluid_only);
+                    }
                     c.mask = nullptr;
                     const double vb = c.timing.on ? 8.0 * active_len(c) : 0.0;
                     record(c, 4, true);
-                    launch_dots2(c, c.V, j + 1, U1, U2, h1, c.active, c.inv_nu);
-                    record(c, 4, false, vb * (j + 3));    // read j+1 basis vectors and two new ones
+                    launch_block_dots(c, sj, c.V, j + 1, W, c.active, c.inv_nu);
+                    record(c, 4, false, vb * (j + 1 + sj));      // read j+1 basis vectors and sj new ones
                     record(c, 5, true);
-                    launch_axpy2_gram(c, c.V, j + 1, h1, h2, U1, U2, c.gram, c.active, c.inv_nu);
-                    record(c, 5, false, vb * (j + 5));    // read j+1 vectors and two, write two
-                    launch_givens2(c, j, tol);
-                    launch_combine(c, U1, U2, c.active);
+                    launch_block_update(c, sj, c.V, j + 1, W, c.active, c.inv_nu);
+                    record(c, 5, false, vb * (j + 1 + 2 * sj));  // read j+1 vectors and sj, write sj
+                    launch_givens_s(c, j, sj, tol);
+                    launch_combine_s(c, sj, W, c.active);
                 };
                 auto body = [&]() {
-                    if (sb == 2) { body2(); return; }
+                    if (sj > 1) { body_s(); return; }
                     double *Vj = c.V + (long long)j * c.L, *Zj = c.Z + (long long)j * c.L;
                     double *W = c.V + (long long)(j + 1) * c.L;
                     // converged replicas skip the grid and body kernels (not in timing
@@ -468,8 +470,8 @@ static void fgmres(Ctx &c, MarkerSet &ms, const double *theta, const double *b, 
                 } else {
                     body();
                 }
-                total += sb;
-                if ((j / sb + 1) % check_blocks == 0 || j + sb == m || total >= c.opts.max_iter) {
+                total += sj;
+                if ((j / sb + 1) % check_blocks == 0 || j + sj == m || total >= c.opts.max_iter) {
                     if (count_active(c) == 0) { done = true; break; }
                     if (total >= c.opts.max_iter) break;
                 }
@@ -661,7 +663,7 @@ static void validate(int nrep, const rbfib_grid *grids, const rbfib_bodies *bodi
     if (!(o.tol > 0.0) || o.restart < 1 || o.restart > 200 || o.max_iter < 1 || o.mg_sweeps < 1 ||
         !(o.mg_omega > 0.0) || !(o.blob_radius > 0.0) || !(o.rfd_delta > 0.0) || o.mg_bottom < 0 || o.mg_bottom > MGB_LDS / 1024 ||
         !(o.mg_cheby >= 0.0 && o.mg_cheby < 2.0) || o.mg_sweeps > RB_MAXSWEEP || o.mg_sweeps_p < 0 ||
-        o.mg_sweeps_p > RB_MAXSWEEP || (o.krylov_s != 1 && o.krylov_s != 2))
+        o.mg_sweeps_p > RB_MAXSWEEP || o.krylov_s < 1 || o.krylov_s > RB_MAXS)
         throw (int)RBFIB_EINVAL;
     for (int r = 0; r < nrep; ++r) {
         const rbfib_grid &g = grids[r];
@@ -1034,7 +1036,7 @@ static void build(Ctx &c, int nrep, const rbfib_grid *grids, const rbfib_bodies 
     c.rhs = dalloc<double>(L);
     c.xR = dalloc<double>(L);
     c.xS = dalloc<double>(L);
-    c.partial = dalloc<double>((size_t)c.n_tab_vec * 2 * (c.m + 1));   // two-step blocks use 2 (m + 1) per block
+    c.partial = dalloc<double>((size_t)c.n_tab_vec * RB_MAXS * (c.m + 1));   // s-step blocks: s (m + 1) per block
     c.H = dalloc<double>((size_t)nrep * (c.m + 1) * c.m);
     c.cs = dalloc<double>((size_t)nrep * c.m);
     c.sn = dalloc<double>((size_t)nrep * c.m);
@@ -1042,8 +1044,9 @@ static void build(Ctx &c, int nrep, const rbfib_grid *grids, const rbfib_bodies 
     c.beta0 = dalloc<double>(nrep);
     c.hcol = dalloc<double>((size_t)3 * nrep * (c.m + 1));
     c.inv_nu = dalloc<double>((size_t)nrep * (c.m + 1));
-    c.gram = dalloc<double>((size_t)nrep * 3);
-    c.tco = dalloc<double>((size_t)nrep);
+    c.hblk = dalloc<double>((size_t)RB_MAXS * nrep * (c.m + 1));
+    c.gram = dalloc<double>((size_t)nrep * RB_MAXG);
+    c.tco = dalloc<double>((size_t)nrep * RB_MAXS * RB_MAXS);
     zero_device(c, c.inv_nu, (long long)nrep * (c.m + 1));
     c.yv = dalloc<double>((size_t)nrep * (c.m + 1));
     c.d_resid = dalloc<double>(nrep);
@@ -1095,7 +1098,7 @@ static void free_all(Ctx &c) {
     if (c.h_flags) (void)hipHostFree(c.h_flags);
     if (c.h_count) (void)hipHostFree(c.h_count);
     F(c.V); F(c.Z); F(c.W); F(c.xsol); F(c.rhs); F(c.xR); F(c.xS); F(c.partial);
-    F(c.H); F(c.cs); F(c.sn); F(c.gv); F(c.beta0); F(c.hcol); F(c.inv_nu); F(c.gram); F(c.tco); F(c.yv); F(c.d_resid);
+    F(c.H); F(c.cs); F(c.sn); F(c.gv); F(c.beta0); F(c.hcol); F(c.inv_nu); F(c.hblk); F(c.gram); F(c.tco); F(c.yv); F(c.d_resid);
     F(c.active); F(c.cyc_active); F(c.jf); F(c.status); F(c.iters);
     for (int k = 0; k < 3; ++k) { F(c.q_buf[k]); F(c.th_buf[k]); }
     F(c.Wf); F(c.Wt); F(c.WFT); F(c.Fp); F(c.UR); F(c.slip_acc); F(c.jbc); F(c.theta_int);
@@ -1201,7 +1204,7 @@ int rbfib_set_opts(rbfib_ctx *ctx, const rbfib_opts *o) {
     Ctx &c = ctx->c;
     if (!(o->tol > 0.0) || o->max_iter < 1 || o->mg_sweeps < 1 || !(o->mg_omega > 0.0) || !(o->rfd_delta > 0.0) ||
         !(o->mg_cheby >= 0.0 && o->mg_cheby < 2.0) || o->mg_sweeps > RB_MAXSWEEP || o->mg_sweeps_p < 0 ||
-        o->mg_sweeps_p > RB_MAXSWEEP || (o->krylov_s != 1 && o->krylov_s != 2))
+        o->mg_sweeps_p > RB_MAXSWEEP || o->krylov_s < 1 || o->krylov_s > RB_MAXS)
         return RBFIB_EINVAL;
     // fields fixed at creation: restart length, precision, blob radius, bottom kernel
     if (o->restart != c.opts.restart || (o->precond_fp32 != 0) != c.mg_fp32 || o->blob_radius != c.opts.blob_radius ||

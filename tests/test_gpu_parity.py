@@ -150,29 +150,32 @@ def test_solve_mobility(rb, name, tol, fp32, ks):
     ctx.close()
 
 
-def test_two_step_blocks_match_single_steps(rb):
-    """Two-step Arnoldi blocks (one pass over the basis for two new vectors, 2 x 2
-    Cholesky QR) against one step at a time on a batch of replicas of different sizes
-    and body counts: every replica converges, the iteration counts stay within a few
-    steps (a block can run one step past convergence), and the body velocities agree to
-    the accuracy the tolerance allows."""
+@pytest.mark.parametrize("ks", [2, 3, 4])
+def test_block_steps_match_single_steps(rb, ks):
+    """s-step Arnoldi blocks (one pass over the basis for s new vectors, Cholesky QR of
+    their Gram matrix) against one step at a time on a batch of replicas of different
+    sizes and body counts: every replica converges to the tolerance and the body
+    velocities agree to the accuracy it allows.  With two steps per block the iteration
+    counts stay within a few steps (a block can run one step past convergence); longer
+    blocks lose orthogonality in their power basis and may need more."""
     import torch
     ws = W.ensemble(5, n_replicas=6, sizes=(16, 24, 32), max_bodies=3)
     tol = 1e-6
-    print("two-step blocks", flush=True)
+    print("block steps", ks, flush=True)
     q = dev(np.concatenate([w.q for w in ws]))
     th = dev(np.concatenate([w.theta for w in ws]))
     nb = sum(w.nb for w in ws)
     FT = torch.as_tensor(np.random.default_rng(3).standard_normal((nb, 6)), dtype=torch.float64).cuda()
     out = {}
-    for ks in (1, 2):
-        ctx = lib_context(rb, ws, tol=tol, krylov_s=ks)
+    for ks_ in (1, ks):
+        ctx = lib_context(rb, ws, tol=tol, krylov_s=ks_)
         U = torch.empty((nb, 6), dtype=torch.float64, device="cuda")
         info = rb.rbfib_solve_mobility(ctx, q, th, FT, U, include_bc=False, allow=())
         torch.cuda.synchronize()
-        out[ks] = (U.cpu().numpy(), [i.iters for i in info], [i.rel_residual for i in info])
+        out[ks_] = (U.cpu().numpy(), [i.iters for i in info], [i.rel_residual for i in info])
         ctx.close()
-    print("  iters s=1", out[1][1], "s=2", out[2][1], flush=True)
-    assert all(r <= tol * 1.05 for r in out[2][2])
-    assert all(abs(a - b) <= 4 for a, b in zip(out[1][1], out[2][1]))
-    assert _rel(out[2][0], out[1][0]) < 2e3 * tol
+    print("  iters s=1", out[1][1], "s=%d" % ks, out[ks][1], flush=True)
+    assert all(r <= tol * 1.05 for r in out[ks][2])
+    if ks == 2:
+        assert all(abs(a - b) <= 4 for a, b in zip(out[1][1], out[2][1]))
+    assert _rel(out[ks][0], out[1][0]) < 2e3 * tol
