@@ -496,6 +496,7 @@ struct Ctx {
     double lev_cells_c[RB_MAXLEV] = {0}; // points of level l+1 over the same replicas
     double cells_all = 0;                // level-0 points over all replicas
     int mg_npt = 1;                      // points per thread of the multigrid block tables
+    bool lev_row4[RB_MAXLEV] = {false};  // every replica smoothed at level l has rows a multiple of 4 long
     // coarse dense inverses
     long long *d_coarse_off = nullptr;   // [nrep * 4] offset into coarse pools (doubles)
     double *d_coarse64 = nullptr;

@@ -426,8 +426,34 @@ __global__ __launch_bounds__(RB_BLOCK) void k_smooth(const RepDev *reps, const L
     }
 }
 
+// The four-point path alone, for levels whose rows are all a multiple of four long:
+// without the one-point fallback in the same kernel it needs far fewer registers, so
+// more waves are resident to cover the stencil's load latency.
+template <int MODE>
+__global__ __launch_bounds__(RB_BLOCK) void k_smooth_row4(const RepDev *reps, const LevDev *levs, const BlockEnt *tab,
+                                                          int lev, int c0, const float *__restrict__ xin,
+                                                          float *__restrict__ xout, const float *__restrict__ b,
+                                                          double omega, const int *__restrict__ mask) {
+    const BlockEnt be = tab[xcd_block(blockIdx.x, gridDim.x)];
+    if (mask && !mask[be.rep]) return;
+    const int comp = c0 + blockIdx.y;
+    const RepDev &R = reps[be.rep];
+    const LevDev &Lv = levs[be.rep * RB_MAXLEV + lev];
+    const long long base = Lv.off + comp * Lv.N;
+    const float s = (comp < 3) ? (float)(-R.eta) : -1.f;
+    smooth_row4<MODE>(R, Lv, be, comp, xin + base, xout + base, b + base, s, (float)omega);
+}
+
 template <typename T, int NPT, int MODE>
 static void launch_stencil(Ctx &c, int lev, int c0, int nc, const T *xin, T *xout, const T *b, double omega) {
+    if constexpr (sizeof(T) == 4 && NPT == 4) {
+        if (c.lev_row4[lev]) {
+            hipLaunchKernelGGL(k_smooth_row4<MODE>, dim3(c.n_tab_lev[lev], nc), dim3(RB_BLOCK), 0, c.stream, c.d_reps,
+                               c.d_levs, c.d_tab_lev[lev], lev, c0, (const float *)xin, (float *)xout,
+                               (const float *)b, omega, c.mask);
+            return;
+        }
+    }
     hipLaunchKernelGGL((k_smooth<T, NPT, MODE>), dim3(c.n_tab_lev[lev], nc), dim3(RB_BLOCK), 0, c.stream, c.d_reps,
                        c.d_levs, c.d_tab_lev[lev], lev, c0, xin, xout, b, omega, c.mask);
 }

@@ -839,6 +839,9 @@ static void build(Ctx &c, int nrep, const rbfib_grid *grids, const rbfib_bodies 
             else if (!c.opts.mg_bottom) tc.push_back(BlockEnt{r, 1, 0});
         }
         c.n_tab_lev[l] = (int)tl.size(); c.d_tab_lev[l] = upload(c, tl);
+        bool row4 = true;
+        for (const BlockEnt &e : tl) row4 = row4 && c.levs[(size_t)e.rep * RB_MAXLEV + l].n[0] % 4 == 0;
+        c.lev_row4[l] = row4;
         c.n_tab_crs[l] = (int)tc.size(); c.d_tab_crs[l] = upload(c, tc);
         c.n_tab_all[l] = (int)ta.size(); c.d_tab_all[l] = upload(c, ta);
     }
