@@ -141,6 +141,10 @@ typedef struct {
                                /*    vectors are orthogonalised in one pass over the */
                                /*    basis (tol >= 1e-9; a shorter last block runs   */
                                /*    single steps) (2)                               */
+    int mg_first2;             /* 1: the first two sweeps of each down pass as one   */
+                               /*    kernel on FP32 levels whose rows are a multiple */
+                               /*    of 4 (b read once, the first iterate never      */
+                               /*    stored; same values as two sweeps); 0: two (1)  */
 } rbfib_opts;
 
 typedef struct {

@@ -546,6 +546,8 @@ void launch_apply_fluid(Ctx &c, const double *x, double *y);
 template <typename T> void launch_to_level0(Ctx &c, const double *src, T *b, int c0, int nc, const double *rs = nullptr);
 template <typename T> void launch_smooth(Ctx &c, int lev, int c0, int nc, const T *xin, T *xout, const T *b, bool first,
                                           double omega);
+template <typename T> bool launch_smooth_first2(Ctx &c, int lev, int c0, int nc, T *xout, const T *b, double omega1,
+                                                 double omega2);
 template <typename T> void launch_restrict(Ctx &c, int lev, int c0, int nc, const T *x, const T *b, T *bc, T *r);
 template <typename T> void launch_mg_bottom(Ctx &c, int c0, int nc, int nu, const SweepW &w, const T *b, T *x, T *t,
                                            unsigned res_t_mask);

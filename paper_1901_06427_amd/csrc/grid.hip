@@ -274,14 +274,20 @@ void launch_to_level0(Ctx &c, const double *src, T *b, int c0, int nc, const dou
 // of 4, blocks of 1024 points): 16-byte loads of the point, its y and z neighbour rows
 // and b, two scalar loads for the x neighbours outside the group; y and z rules are
 // shared by the four points.  Same arithmetic, in the same order, as the scalar path.
+// MG_FIRST2 (four-point path only): the first two sweeps of a down pass in one.  The
+// first sweep from zero leaves w1 b at every point it does not pin, so the second
+// sweep rebuilds each value it reads from b (the neighbours it reads are never pinned
+// ones) and x1 is never stored: b is read and x written once instead of 2 + 3 passes,
+// with the values of the two separate sweeps.
 #define MG_FIRST 0
 #define MG_SWEEP 1
 #define MG_RESID 2
+#define MG_FIRST2 3
 
 template <int MODE>
 __device__ __forceinline__ void smooth_row4(const RepDev &R, const LevDev &Lv, const BlockEnt &be, int comp,
                                             const float *__restrict__ xi, float *__restrict__ xo,
-                                            const float *__restrict__ bb, float s, float om) {
+                                            const float *__restrict__ bb, float s, float om, float om1) {
     const long long g0 = be.start + 4LL * threadIdx.x;
     if (g0 >= Lv.N) return;
     const int lin = (int)g0;
@@ -308,21 +314,62 @@ __device__ __forceinline__ void smooth_row4(const RepDev &R, const LevDev &Lv, c
         kxm[q] = nbr_kind(x0 + q, -1, n0, R.bc[0], 0, comp);
         kxp[q] = nbr_kind(x0 + q, +1, n0, R.bc[0], 0, comp);
     }
+    // MG_FIRST2 reads these from b and scales them below
+    const float *xs = MODE == MG_FIRST2 ? bb : xi;
     if (MODE != MG_FIRST) {
-        const float4 v = *reinterpret_cast<const float4 *>(xi + lin);
+        const float4 v = *reinterpret_cast<const float4 *>(xs + lin);
         x4[0] = v.x; x4[1] = v.y; x4[2] = v.z; x4[3] = v.w;
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
-            const float4 u = *reinterpret_cast<const float4 *>(xi + lin + off[e]);
+            const float4 u = *reinterpret_cast<const float4 *>(xs + lin + off[e]);
             nb[e][0] = u.x; nb[e][1] = u.y; nb[e][2] = u.z; nb[e][3] = u.w;
         }
         // x neighbours outside the group (wrapped when periodic, unused otherwise)
-        xl = xi[lin + (kxm[0] ? 0 : (x0 == 0 ? n0 - 1 : -1))];
-        xr = xi[lin + 3 + (kxp[3] ? 0 : (x0 + 3 == n0 - 1 ? -(n0 - 1) : 1))];
+        xl = xs[lin + (kxm[0] ? 0 : (x0 == 0 ? n0 - 1 : -1))];
+        xr = xs[lin + 3 + (kxp[3] ? 0 : (x0 + 3 == n0 - 1 ? -(n0 - 1) : 1))];
     }
     const float ihx = (float)Lv.inv_h2[0], ihy = (float)Lv.inv_h2[1], ihz = (float)Lv.inv_h2[2];
     const float day = diag_axis<float>(comp, 1, idx[1], Lv.n[1], R.bc[1]);
     const float daz = diag_axis<float>(comp, 2, idx[2], Lv.n[2], R.bc[2]);
+    if (MODE == MG_FIRST2) {
+        // x1 = w1 b, with w1 from the diagonal of the point read.  The diagonal's x term
+        // is the interior one except at x = 0 and x = n0 - 1, which only the group's
+        // first and last points can be (rows are a multiple of 4 long); the points
+        // outside the group are interior or periodic, whose term is the interior one.
+        // The y and z neighbours differ from the point in one term.
+        const float xti = fmad(diag_axis<float>(comp, 0, x0 + 1, n0, R.bc[0]), ihx, 0.f);
+        const float xte = fmad(diag_axis<float>(comp, 0, 0, n0, R.bc[0]), ihx, 0.f);
+        const float dym = diag_axis<float>(comp, 1, idx[1] - 1, Lv.n[1], R.bc[1]);
+        const float dyp = diag_axis<float>(comp, 1, idx[1] + 1, Lv.n[1], R.bc[1]);
+        const float dzm = diag_axis<float>(comp, 2, idx[2] - 1, Lv.n[2], R.bc[2]);
+        const float dzp = diag_axis<float>(comp, 2, idx[2] + 1, Lv.n[2], R.bc[2]);
+        // weights of the point and of its four y / z neighbours, for an interior x term
+        // and for the wall one
+        auto w5 = [&](float xt, float w[5]) {
+            w[0] = jacobi_w<float>(om1, s, fmad(daz, ihz, fmad(day, ihy, xt)));
+            w[1] = jacobi_w<float>(om1, s, fmad(daz, ihz, fmad(dym, ihy, xt)));
+            w[2] = jacobi_w<float>(om1, s, fmad(daz, ihz, fmad(dyp, ihy, xt)));
+            w[3] = jacobi_w<float>(om1, s, fmad(dzm, ihz, fmad(day, ihy, xt)));
+            w[4] = jacobi_w<float>(om1, s, fmad(dzp, ihz, fmad(day, ihy, xt)));
+        };
+        float wi[5], we[5];
+        w5(xti, wi);
+        if (R.bc[0] == RBFIB_WALL && comp != 0) w5(xte, we);   // uniform per block
+        else {
+#pragma unroll
+            for (int k = 0; k < 5; ++k) we[k] = wi[k];
+        }
+        const bool e0 = x0 == 0, e3 = x0 + 3 == n0 - 1;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const bool eq = (q == 0 && e0) || (q == 3 && e3);
+            x4[q] = x4[q] * (eq ? we[0] : wi[0]);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) nb[e][q] = nb[e][q] * (eq ? we[e + 1] : wi[e + 1]);
+        }
+        xl = xl * wi[0];
+        xr = xr * wi[0];
+    }
     const bool pin_yz = (comp == 1 && R.bc[1] == RBFIB_WALL && idx[1] == 0) ||
                         (comp == 2 && R.bc[2] == RBFIB_WALL && idx[2] == 0);
     float y4[4];
@@ -368,7 +415,7 @@ __global__ __launch_bounds__(RB_BLOCK) void k_smooth(const RepDev *reps, const L
     if constexpr (sizeof(T) == 4 && NPT == 4) {
         if (Lv.n[0] % 4 == 0) {    // uniform per block: every row splits into aligned groups of 4
             smooth_row4<MODE>(R, Lv, be, comp, (const float *)xi, (float *)xo, (const float *)bb, (float)s,
-                              (float)omega);
+                              (float)omega, (float)omega);
             return;
         }
     }
@@ -433,7 +480,8 @@ template <int MODE>
 __global__ __launch_bounds__(RB_BLOCK) void k_smooth_row4(const RepDev *reps, const LevDev *levs, const BlockEnt *tab,
                                                           int lev, int c0, const float *__restrict__ xin,
                                                           float *__restrict__ xout, const float *__restrict__ b,
-                                                          double omega, const int *__restrict__ mask) {
+                                                          double omega, const int *__restrict__ mask,
+                                                          double omega1) {
     const BlockEnt be = tab[xcd_block(blockIdx.x, gridDim.x)];
     if (mask && !mask[be.rep]) return;
     const int comp = c0 + blockIdx.y;
@@ -441,7 +489,7 @@ __global__ __launch_bounds__(RB_BLOCK) void k_smooth_row4(const RepDev *reps, co
     const LevDev &Lv = levs[be.rep * RB_MAXLEV + lev];
     const long long base = Lv.off + comp * Lv.N;
     const float s = (comp < 3) ? (float)(-R.eta) : -1.f;
-    smooth_row4<MODE>(R, Lv, be, comp, xin + base, xout + base, b + base, s, (float)omega);
+    smooth_row4<MODE>(R, Lv, be, comp, xin + base, xout + base, b + base, s, (float)omega, (float)omega1);
 }
 
 template <typename T, int NPT, int MODE>
@@ -450,7 +498,7 @@ static void launch_stencil(Ctx &c, int lev, int c0, int nc, const T *xin, T *xou
         if (c.lev_row4[lev]) {
             hipLaunchKernelGGL(k_smooth_row4<MODE>, dim3(c.n_tab_lev[lev], nc), dim3(RB_BLOCK), 0, c.stream, c.d_reps,
                                c.d_levs, c.d_tab_lev[lev], lev, c0, (const float *)xin, (float *)xout,
-                               (const float *)b, omega, c.mask);
+                               (const float *)b, omega, c.mask, omega);
             return;
         }
     }
@@ -470,6 +518,21 @@ template <typename T>
 void launch_smooth(Ctx &c, int lev, int c0, int nc, const T *xin, T *xout, const T *b, bool first, double omega) {
     if (first) launch_stencil_any<T, MG_FIRST>(c, lev, c0, nc, xin, xout, b, omega);
     else launch_stencil_any<T, MG_SWEEP>(c, lev, c0, nc, xin, xout, b, omega);
+}
+
+// The first two sweeps of a down pass (weights omega1, omega2) as one launch, on FP32
+// levels whose rows are a multiple of 4; returns false (nothing launched) elsewhere.
+template <typename T>
+bool launch_smooth_first2(Ctx &c, int lev, int c0, int nc, T *xout, const T *b, double omega1, double omega2) {
+    if constexpr (sizeof(T) == 4) {
+        if (c.mg_npt != 4 || !c.lev_row4[lev]) return false;
+        if (c.n_tab_lev[lev] == 0) return true;
+        hipLaunchKernelGGL(k_smooth_row4<MG_FIRST2>, dim3(c.n_tab_lev[lev], nc), dim3(RB_BLOCK), 0, c.stream,
+                           c.d_reps, c.d_levs, c.d_tab_lev[lev], lev, c0, (const float *)b, (float *)xout,
+                           (const float *)b, omega2, c.mask, omega1);
+        return true;
+    }
+    return false;
 }
 
 // Restriction of the residual r of level lev (written by a MG_RESID pass, zero at
@@ -1149,6 +1212,8 @@ template void launch_to_level0<float>(Ctx &, const double *, float *, int, int, 
 template void launch_to_level0<double>(Ctx &, const double *, double *, int, int, const double *);
 template void launch_smooth<float>(Ctx &, int, int, int, const float *, float *, const float *, bool, double);
 template void launch_smooth<double>(Ctx &, int, int, int, const double *, double *, const double *, bool, double);
+template bool launch_smooth_first2<float>(Ctx &, int, int, int, float *, const float *, double, double);
+template bool launch_smooth_first2<double>(Ctx &, int, int, int, double *, const double *, double, double);
 template void launch_restrict<float>(Ctx &, int, int, int, const float *, const float *, float *, float *);
 template void launch_restrict<double>(Ctx &, int, int, int, const double *, const double *, double *, double *);
 template void launch_prolong<float>(Ctx &, int, int, int, const float *, float *);

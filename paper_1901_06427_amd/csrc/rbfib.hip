@@ -256,6 +256,12 @@ static T *vcycle(Ctx &c, int c0, int nc) {
             T *out = ((nu - k) % 2 == 0) ? X : Tt;
             T *in = (out == X) ? Tt : X;
             if (l == 0) record(c, 1, true);
+            if (k == 1 && nu >= 2 && c.opts.mg_first2 &&
+                launch_smooth_first2<T>(c, l, c0, nc, ((nu - 2) % 2 == 0) ? X : Tt, B, omega(1), omega(2))) {
+                if (l == 0) record(c, 1, false, sz * c.lev_cells[0] * 2.0);
+                ++k;   // sweeps 1 and 2 done
+                continue;
+            }
             launch_smooth<T>(c, l, c0, nc, in, out, B, k == 1, omega(k));
             if (l == 0) record(c, 1, false, sz * c.lev_cells[0] * (k == 1 ? 2.0 : 3.0));
         }
@@ -663,7 +669,7 @@ static void validate(int nrep, const rbfib_grid *grids, const rbfib_bodies *bodi
     if (!(o.tol > 0.0) || o.restart < 1 || o.restart > 200 || o.max_iter < 1 || o.mg_sweeps < 1 ||
         !(o.mg_omega > 0.0) || !(o.blob_radius > 0.0) || !(o.rfd_delta > 0.0) || o.mg_bottom < 0 || o.mg_bottom > MGB_LDS / 1024 ||
         !(o.mg_cheby >= 0.0 && o.mg_cheby < 2.0) || o.mg_sweeps > RB_MAXSWEEP || o.mg_sweeps_p < 0 ||
-        o.mg_sweeps_p > RB_MAXSWEEP || o.krylov_s < 1 || o.krylov_s > RB_MAXS)
+        o.mg_sweeps_p > RB_MAXSWEEP || o.krylov_s < 1 || o.krylov_s > RB_MAXS || (o.mg_first2 != 0 && o.mg_first2 != 1))
         throw (int)RBFIB_EINVAL;
     for (int r = 0; r < nrep; ++r) {
         const rbfib_grid &g = grids[r];
@@ -1145,6 +1151,7 @@ void rbfib_default_opts(rbfib_opts *o) {
     o->mg_bottom = 0;
     o->mg_cheby = 0.27;
     o->krylov_s = 2;
+    o->mg_first2 = 1;
 }
 
 const char *rbfib_strerror(int code) {
@@ -1207,7 +1214,8 @@ int rbfib_set_opts(rbfib_ctx *ctx, const rbfib_opts *o) {
     Ctx &c = ctx->c;
     if (!(o->tol > 0.0) || o->max_iter < 1 || o->mg_sweeps < 1 || !(o->mg_omega > 0.0) || !(o->rfd_delta > 0.0) ||
         !(o->mg_cheby >= 0.0 && o->mg_cheby < 2.0) || o->mg_sweeps > RB_MAXSWEEP || o->mg_sweeps_p < 0 ||
-        o->mg_sweeps_p > RB_MAXSWEEP || o->krylov_s < 1 || o->krylov_s > RB_MAXS)
+        o->mg_sweeps_p > RB_MAXSWEEP || o->krylov_s < 1 || o->krylov_s > RB_MAXS ||
+        (o->mg_first2 != 0 && o->mg_first2 != 1))
         return RBFIB_EINVAL;
     // fields fixed at creation: restart length, precision, blob radius, bottom kernel
     if (o->restart != c.opts.restart || (o->precond_fp32 != 0) != c.mg_fp32 || o->blob_radius != c.opts.blob_radius ||
@@ -1215,7 +1223,7 @@ int rbfib_set_opts(rbfib_ctx *ctx, const rbfib_opts *o) {
         return RBFIB_EINVAL;
     if (o->mg_sweeps != c.opts.mg_sweeps || o->mg_sweeps_p != c.opts.mg_sweeps_p || o->mg_omega != c.opts.mg_omega ||
         o->mg_cheby != c.opts.mg_cheby || o->krylov_s != c.opts.krylov_s ||
-        o->mg_fused != c.opts.mg_fused)
+        o->mg_fused != c.opts.mg_fused || o->mg_first2 != c.opts.mg_first2)
         drop_graphs(c);
     c.opts = *o;
     return RBFIB_OK;

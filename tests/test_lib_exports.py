@@ -28,4 +28,6 @@ def test_binding_lists_every_symbol():
     assert sorted(rb.EXPORTS) == _declared()
     o = rb.rbfib_default_opts()
     assert o.tol == 1e-6 and o.restart == 100 and o.use_graphs == 1
+    # the last fields land where the C struct has them
+    assert o.mg_cheby == 0.27 and o.krylov_s == 2 and o.mg_first2 == 1
     assert rb._lib.rbfib_strerror(-2).decode().startswith("unphysical")
