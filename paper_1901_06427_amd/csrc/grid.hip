@@ -331,52 +331,59 @@ __device__ __forceinline__ void smooth_row4(const RepDev &R, const LevDev &Lv, c
     const float ihx = (float)Lv.inv_h2[0], ihy = (float)Lv.inv_h2[1], ihz = (float)Lv.inv_h2[2];
     const float day = diag_axis<float>(comp, 1, idx[1], Lv.n[1], R.bc[1]);
     const float daz = diag_axis<float>(comp, 2, idx[2], Lv.n[2], R.bc[2]);
+    // The diagonal's x term is the interior one except at x = 0 and x = n0 - 1 of a
+    // tangential component on an x wall, which only the group's first and last points
+    // can be (rows are a multiple of 4 long), so each weight is formed once per distinct
+    // diagonal: interior, and at the row ends of the threads that hold them.
+    const bool e0 = R.bc[0] == RBFIB_WALL && comp != 0 && x0 == 0;
+    const bool e3 = R.bc[0] == RBFIB_WALL && comp != 0 && x0 + 3 == n0 - 1;
+    const float xti = fmad(diag_axis<float>(comp, 0, x0 + 1, n0, R.bc[0]), ihx, 0.f);
+    const float xte = fmad(diag_axis<float>(comp, 0, 0, n0, R.bc[0]), ihx, 0.f);
+    const float wi = jacobi_w<float>(om, s, fmad(daz, ihz, fmad(day, ihy, xti)));
+    float we = wi;
+    if (e0 || e3) we = jacobi_w<float>(om, s, fmad(daz, ihz, fmad(day, ihy, xte)));
     if (MODE == MG_FIRST2) {
-        // x1 = w1 b, with w1 from the diagonal of the point read.  The diagonal's x term
-        // is the interior one except at x = 0 and x = n0 - 1, which only the group's
-        // first and last points can be (rows are a multiple of 4 long); the points
-        // outside the group are interior or periodic, whose term is the interior one.
-        // The y and z neighbours differ from the point in one term.
-        const float xti = fmad(diag_axis<float>(comp, 0, x0 + 1, n0, R.bc[0]), ihx, 0.f);
-        const float xte = fmad(diag_axis<float>(comp, 0, 0, n0, R.bc[0]), ihx, 0.f);
+        // x1 = w1 b, with w1 from the diagonal of the point read.  The points outside the
+        // group are interior or periodic, whose x term is the interior one; the y and z
+        // neighbours differ from the point in one term, and only next to a y or z wall.
         const float dym = diag_axis<float>(comp, 1, idx[1] - 1, Lv.n[1], R.bc[1]);
         const float dyp = diag_axis<float>(comp, 1, idx[1] + 1, Lv.n[1], R.bc[1]);
         const float dzm = diag_axis<float>(comp, 2, idx[2] - 1, Lv.n[2], R.bc[2]);
         const float dzp = diag_axis<float>(comp, 2, idx[2] + 1, Lv.n[2], R.bc[2]);
-        // weights of the point and of its four y / z neighbours, for an interior x term
-        // and for the wall one
-        auto w5 = [&](float xt, float w[5]) {
-            w[0] = jacobi_w<float>(om1, s, fmad(daz, ihz, fmad(day, ihy, xt)));
-            w[1] = jacobi_w<float>(om1, s, fmad(daz, ihz, fmad(dym, ihy, xt)));
-            w[2] = jacobi_w<float>(om1, s, fmad(daz, ihz, fmad(dyp, ihy, xt)));
-            w[3] = jacobi_w<float>(om1, s, fmad(dzm, ihz, fmad(day, ihy, xt)));
-            w[4] = jacobi_w<float>(om1, s, fmad(dzp, ihz, fmad(day, ihy, xt)));
-        };
-        float wi[5], we[5];
-        w5(xti, wi);
-        if (R.bc[0] == RBFIB_WALL && comp != 0) w5(xte, we);   // uniform per block
-        else {
+        // weights of the point and of its four y / z neighbours, interior x term (v) and
+        // wall x term (u)
+        float v[5], u[5];
+        v[0] = jacobi_w<float>(om1, s, fmad(daz, ihz, fmad(day, ihy, xti)));
+        u[0] = v[0];
+        if (e0 || e3) u[0] = jacobi_w<float>(om1, s, fmad(daz, ihz, fmad(day, ihy, xte)));
 #pragma unroll
-            for (int k = 0; k < 5; ++k) we[k] = wi[k];
+        for (int k = 1; k < 5; ++k) { v[k] = v[0]; u[k] = u[0]; }
+        if (dym != day || dyp != day || dzm != daz || dzp != daz) {
+            auto w4 = [&](float xt, float w[5]) {
+                w[1] = jacobi_w<float>(om1, s, fmad(daz, ihz, fmad(dym, ihy, xt)));
+                w[2] = jacobi_w<float>(om1, s, fmad(daz, ihz, fmad(dyp, ihy, xt)));
+                w[3] = jacobi_w<float>(om1, s, fmad(dzm, ihz, fmad(day, ihy, xt)));
+                w[4] = jacobi_w<float>(om1, s, fmad(dzp, ihz, fmad(day, ihy, xt)));
+            };
+            w4(xti, v);
+            if (e0 || e3) w4(xte, u);
         }
-        const bool e0 = x0 == 0, e3 = x0 + 3 == n0 - 1;
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const bool eq = (q == 0 && e0) || (q == 3 && e3);
-            x4[q] = x4[q] * (eq ? we[0] : wi[0]);
+            x4[q] = x4[q] * (eq ? u[0] : v[0]);
 #pragma unroll
-            for (int e = 0; e < 4; ++e) nb[e][q] = nb[e][q] * (eq ? we[e + 1] : wi[e + 1]);
+            for (int e = 0; e < 4; ++e) nb[e][q] = nb[e][q] * (eq ? u[e + 1] : v[e + 1]);
         }
-        xl = xl * wi[0];
-        xr = xr * wi[0];
+        xl = xl * v[0];
+        xr = xr * v[0];
     }
     const bool pin_yz = (comp == 1 && R.bc[1] == RBFIB_WALL && idx[1] == 0) ||
                         (comp == 2 && R.bc[2] == RBFIB_WALL && idx[2] == 0);
     float y4[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-        const float dg = fmad(daz, ihz, fmad(day, ihy, fmad(diag_axis<float>(comp, 0, x0 + q, n0, R.bc[0]), ihx, 0.f)));
-        const float w = jacobi_w<float>(om, s, dg);
+        const float w = ((q == 0 && e0) || (q == 3 && e3)) ? we : wi;
         float y;
         if (MODE == MG_FIRST) {
             y = b4[q] * w;
