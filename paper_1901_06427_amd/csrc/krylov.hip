@@ -583,21 +583,29 @@ void launch_combine_s(Ctx &c, int S, double *W, const int *mask) {
 }
 
 // Back substitution H[0:jf, 0:jf] y = g[0:jf] for replicas active at cycle start.
-__global__ void k_trisolve(int nrep, int m, const double *H, const double *gv, const int *cyc, const int *jf,
-                           double *y) {
-    int r = blockIdx.x * blockDim.x + threadIdx.x;
+// Back substitution by columns, one wavefront per replica: once y_i is known every
+// row above it drops its term, read from column i of H (contiguous); the right-hand
+// side lives in LDS.
+__global__ __launch_bounds__(64) void k_trisolve(int nrep, int m, const double *H, const double *gv, const int *cyc,
+                                                 const int *jf, double *y) {
+    const int r = blockIdx.x;
     if (r >= nrep || !cyc[r]) return;
-    int n = jf[r];
+    extern __shared__ double s_rhs[];   // m + 1 entries
+    const int n = jf[r], lane = threadIdx.x;
     const double *Hr = H + (long long)r * (m + 1) * m;
     const double *g = gv + (long long)r * (m + 1);
     double *yr = y + (long long)r * (m + 1);
+    for (int k = lane; k < n; k += 64) s_rhs[k] = g[k];
+    __syncthreads();
     for (int i = n - 1; i >= 0; --i) {
-        double s = g[i];
-        for (int k = i + 1; k < n; ++k) s -= Hr[(long long)k * (m + 1) + i] * yr[k];
-        double d = Hr[(long long)i * (m + 1) + i];
-        yr[i] = d != 0.0 ? s / d : 0.0;
+        const double *col = Hr + (long long)i * (m + 1);
+        const double d = col[i];
+        const double yi = d != 0.0 ? s_rhs[i] / d : 0.0;
+        for (int k = lane; k < i; k += 64) s_rhs[k] -= col[k] * yi;   // rows above i only
+        if (lane == 0) yr[i] = yi;
+        __syncthreads();   // row i - 1 is final before the next step reads it
     }
-    for (int i = n; i < m; ++i) yr[i] = 0.0;
+    for (int i = n + lane; i < m; i += 64) yr[i] = 0.0;
 }
 
 // x += sum_{i < jf} y_i Z_i
@@ -623,8 +631,8 @@ __global__ __launch_bounds__(RB_BLOCK) void k_update_x(const RepDev *reps, const
 }
 
 void launch_trisolve_update(Ctx &c) {
-    hipLaunchKernelGGL(k_trisolve, dim3((c.nrep + 63) / 64), dim3(64), 0, c.stream, c.nrep, c.m, c.H, c.gv,
-                       c.cyc_active, c.jf, c.yv);
+    hipLaunchKernelGGL(k_trisolve, dim3(c.nrep), dim3(64), (size_t)(c.m + 1) * sizeof(double), c.stream, c.nrep,
+                       c.m, c.H, c.gv, c.cyc_active, c.jf, c.yv);
     hipLaunchKernelGGL(k_update_x, dim3(c.n_tab_vec), dim3(RB_BLOCK), 0, c.stream, c.d_reps, c.d_tab_vec, c.Z, c.L,
                        c.m, c.yv, c.jf, c.cyc_active, c.xsol);
 }
