@@ -149,6 +149,34 @@ def test_manufactured_stokes(bc):
     assert np.abs(xf[s.sl_v] - v).max() < 1e-9
 
 
+@pytest.mark.parametrize("nz", [8, 16])
+def test_plane_poiseuille_closed_form(nz):
+    """Uniform force F along x between no-slip walls at z = 0 and z = L, periodic x, y.
+
+    Every interior row of the discrete momentum equation holds for the parabola
+    F z (L - z) / (2 eta) (the second difference of a quadratic is exact); at the first
+    and last cell the odd reflection about the wall places the ghost at -u_0, which
+    misses the parabola's value by F h^2 / (4 eta), and the error that this drives is
+    the constant F h^2 / (8 eta).  So the discrete solution is the parabola plus that
+    constant at every x face, with no flow across and a uniform pressure: second-order
+    accuracy of the wall treatment, with its exact error constant."""
+    h, eta, F = 0.5, 1.3, 0.7
+    g = mac.Grid((4, 3, nz), (0, 0, 1), h=h, eta=eta)
+    f = np.zeros((3, nz, 3, 4))
+    f[0] = F
+    s = saddle.Saddle(g, np.zeros((0, 3)), np.zeros((0, 4)), np.zeros((0, 3)), np.zeros(1, dtype=int),
+                      fluid_only=True)
+    x = s.solve_direct(s.rhs(fluid=g.padded_to_compact(f), include_bc=False))
+    v = g.compact_to_padded(x[s.sl_v]).reshape(3, nz, 3, 4)
+    L = nz * h
+    z = (np.arange(nz) + 0.5) * h
+    expect = F * z * (L - z) / (2 * eta) + F * h * h / (8 * eta)
+    assert np.abs(v[0] - expect[:, None, None]).max() < 1e-10 * expect.max()
+    assert np.abs(v[1:]).max() < 1e-12
+    p = x[s.sl_p]
+    assert np.abs(p - p.mean()).max() < 1e-10
+
+
 def test_noise_index_space_counts():
     g = mac.Grid((4, 5, 6), (0, 1, 1))
     dims = [g.family_dims(f) for f in range(9)]
