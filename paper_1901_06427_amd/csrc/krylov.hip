@@ -582,10 +582,9 @@ void launch_combine_s(Ctx &c, int S, double *W, const int *mask) {
 #undef RB_CMB
 }
 
-// Back substitution H[0:jf, 0:jf] y = g[0:jf] for replicas active at cycle start.
-// Back substitution by columns, one wavefront per replica: once y_i is known every
-// row above it drops its term, read from column i of H (contiguous); the right-hand
-// side lives in LDS.
+// Back substitution H[0:jf, 0:jf] y = g[0:jf] for replicas active at cycle start, by
+// columns with one wavefront per replica: once y_i is known every row above it drops
+// its term, read from column i of H (contiguous); the right-hand side lives in LDS.
 __global__ __launch_bounds__(64) void k_trisolve(int nrep, int m, const double *H, const double *gv, const int *cyc,
                                                  const int *jf, double *y) {
     const int r = blockIdx.x;
