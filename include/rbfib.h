@@ -112,7 +112,9 @@ typedef struct {
     double tol;                /* relative residual ||b - A x|| / ||b||  (1e-6)      */
     int restart;               /* FGMRES restart length (100)                        */
     int max_iter;              /* total iteration cap (600)                          */
-    int precond_fp32;          /* 1: multigrid preconditioner in FP32 (0)            */
+    int precond_fp32;          /* 1: multigrid preconditioner in FP32, and FGMRES    */
+                               /*    keeps the preconditioned vectors in FP32 (A is  */
+                               /*    applied to the stored values) (0)               */
     int mg_sweeps;             /* damped-Jacobi sweeps before and after, 1..16 (2)   */
     int mg_sweeps_p;           /* the same for the pressure cycle; 0: mg_sweeps (3)  */
     double mg_omega;           /* Jacobi damping (0.9)                               */

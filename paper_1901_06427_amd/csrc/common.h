@@ -370,8 +370,9 @@ __device__ __forceinline__ double interp_comp(const RepDev &R, const double *rm,
 }
 
 // (J u)_c from the cached 1-D weights and folded indices of marker m.
+template <typename TU>
 __device__ __forceinline__ double interp_cached(const RepDev &R, const double *wc, const int *ic, int m, int c,
-                                               const double *u) {
+                                               const TU *u) {
     const double *w = wc + (long long)(3 * m + c) * 12;
     const int *ix = ic + (long long)(3 * m + c) * 12;
     double acc = 0.0;
@@ -382,7 +383,7 @@ __device__ __forceinline__ double interp_cached(const RepDev &R, const double *w
             double wzy = wz * w[4 + y];
             if (wzy == 0.0) continue;
             long long row = (long long)R.n[0] * ((long long)ix[4 + y] + (long long)R.n[1] * ix[8 + z]);
-            for (int x = 0; x < 4; ++x) acc += wzy * w[x] * u[row + ix[x]];
+            for (int x = 0; x < 4; ++x) acc += wzy * w[x] * (double)u[row + ix[x]];
         }
     }
     return acc;
@@ -517,6 +518,7 @@ struct Ctx {
     // Krylov
     int m = 0;
     double *V = nullptr, *Z = nullptr, *W = nullptr;
+    float *Zf = nullptr;        // the preconditioned vectors in FP32 when the multigrid is FP32 (Z unused)
     double *xsol = nullptr, *rhs = nullptr;
     double *partial = nullptr;  // [n_tab_vec * (m+1)]
     double *H = nullptr, *cs = nullptr, *sn = nullptr, *gv = nullptr, *beta0 = nullptr, *hcol = nullptr, *yv = nullptr;
@@ -542,7 +544,7 @@ struct Ctx {
 
 // ---------------------------------------------------------------- launchers
 // grid / multigrid (grid.hip)
-void launch_apply_fluid(Ctx &c, const double *x, double *y);
+template <typename TX> void launch_apply_fluid(Ctx &c, const TX *x, double *y);
 template <typename T> void launch_to_level0(Ctx &c, const double *src, T *b, int c0, int nc, const double *rs = nullptr);
 template <typename T> void launch_smooth(Ctx &c, int lev, int c0, int nc, const T *xin, T *xout, const T *b, bool first,
                                           double omega);
@@ -557,18 +559,20 @@ template <typename T> void launch_coarse(Ctx &c, int lev, int c0, int nc, const 
 template <typename T> void launch_mg_down(Ctx &c, int lev, int c0, int nc, const T *b, T *x, double omega1, double omega2);
 template <typename T> void launch_mg_up(Ctx &c, int lev, int c0, int nc, const T *b, const T *xin, const T *xc, T *xout,
                                        double omega1, double omega2);
-template <typename T> void launch_proj_div(Ctx &c, const T *xv, const double *r, T *bp, double *z,
-                                          const double *rs = nullptr);
-template <typename T> void launch_proj_correct(Ctx &c, const T *xv, const T *phi, double *z);
+template <typename T, typename TZ> void launch_proj_div(Ctx &c, const T *xv, const double *r, T *bp, TZ *z,
+                                                       const double *rs = nullptr);
+template <typename T, typename TZ> void launch_proj_correct(Ctx &c, const T *xv, const T *phi, TZ *z);
 void launch_noise(Ctx &c, double kT, double dt, uint64_t seed, uint64_t step, double *f, bool add);
 void launch_wall_rhs(Ctx &c, double *f);
 
 // immersed boundary and bodies (ib.hip)
 void launch_markers(Ctx &c, MarkerSet &ms, const double *q, const double *theta);
-void launch_spread(Ctx &c, MarkerSet &ms, const double *lam, double *y, double alpha);
-template <typename T> void launch_spread_level0(Ctx &c, MarkerSet &ms, const double *lam, T *pool, double alpha);
-void launch_body_apply(Ctx &c, MarkerSet &ms, const double *q, const double *x, double *y);
-void launch_body_precond(Ctx &c, MarkerSet &ms, const double *theta, const double *r, double *z,
+template <typename TL> void launch_spread(Ctx &c, MarkerSet &ms, const TL *lam, double *y, double alpha);
+template <typename T, typename TL>
+void launch_spread_level0(Ctx &c, MarkerSet &ms, const TL *lam, T *pool, double alpha);
+template <typename TX> void launch_body_apply(Ctx &c, MarkerSet &ms, const double *q, const TX *x, double *y);
+template <typename TZ>
+void launch_body_precond(Ctx &c, MarkerSet &ms, const double *theta, const double *r, TZ *z,
                          const double *rs = nullptr);
 void launch_interp(Ctx &c, MarkerSet &ms, const double *x, double *out, double alpha, bool accumulate);
 void launch_interp_bc(Ctx &c, MarkerSet &ms, double *out, double alpha);
@@ -607,7 +611,7 @@ void launch_combine_s(Ctx &c, int S, double *W, const int *mask);
 void launch_givens(Ctx &c, int j, double tol);
 void launch_start_cycle(Ctx &c);
 void launch_trisolve_update(Ctx &c);
-void launch_zero_bodies(Ctx &c, double *y);   // zero the lambda and U slots
+template <typename TY> void launch_zero_bodies(Ctx &c, TY *y);   // zero the lambda and U slots
 
 template <typename T> void zero_device(Ctx &c, T *p, long long n);
 

@@ -88,11 +88,25 @@ __device__ __forceinline__ void apply_cell(const RepDev &R, const double self[3]
     out[3] = -div;
 }
 
+// Two consecutive values of x as FP64 (one load of two).
+__device__ __forceinline__ void ld_pair(const double *q, double &a, double &b) {
+    const double2 v = *reinterpret_cast<const double2 *>(q);
+    a = v.x;
+    b = v.y;
+}
+__device__ __forceinline__ void ld_pair(const float *q, double &a, double &b) {
+    const float2 v = *reinterpret_cast<const float2 *>(q);
+    a = (double)v.x;
+    b = (double)v.y;
+}
+
 // Two consecutive x cells per thread (rows of even length, blocks of 512 cells,
-// 16-byte aligned fields): the pair, its y and z neighbour pairs and the pressure
-// pairs move as 16-byte loads and stores, the x neighbours outside the pair as
-// scalars; the y and z rules are shared by the pair.
-__device__ __forceinline__ void apply_row2(const RepDev &R, const BlockEnt &be, const double *__restrict__ xr,
+// fields aligned to two values): the pair, its y and z neighbour pairs and the
+// pressure pairs move as one load each (x in FP64 or FP32, the preconditioned
+// vectors of an FP32 preconditioner), the x neighbours outside the pair as scalars;
+// the y and z rules are shared by the pair.  The output is FP64, 16-byte stores.
+template <typename TX>
+__device__ __forceinline__ void apply_row2(const RepDev &R, const BlockEnt &be, const TX *__restrict__ xr,
                                            double *__restrict__ yr) {
     const long long g0 = be.start + 2LL * threadIdx.x;
     if (g0 >= R.N) return;
@@ -100,30 +114,32 @@ __device__ __forceinline__ void apply_row2(const RepDev &R, const BlockEnt &be, 
     int idx[3];
     unlin(lin, R, idx);
     const int st[3] = {1, R.n[0], R.n[0] * R.n[1]};
-    const double *p = xr + 3LL * N;
-    auto ld2 = [](const double *q) { return *reinterpret_cast<const double2 *>(q); };
+    const TX *p = xr + 3LL * N;
     double self[2][3], nb[2][3][6], pm[2][3];
     int kd[2][3][6];
     bool pin[2][3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-        const double *u = xr + (long long)c * N;
-        const double2 sp = ld2(u + lin);
-        self[0][c] = sp.x;
-        self[1][c] = sp.y;
+        const TX *u = xr + (long long)c * N;
+        double spx, spy;
+        ld_pair(u + lin, spx, spy);
+        self[0][c] = spx;
+        self[1][c] = spy;
 #pragma unroll
         for (int a = 1; a < 3; ++a) {
             const int km = nbr_kind(idx[a], -1, R.n[a], R.bc[a], a, c);
             const int kp = nbr_kind(idx[a], +1, R.n[a], R.bc[a], a, c);
             const int om = km ? 0 : (idx[a] == 0 ? (R.n[a] - 1) * st[a] : -st[a]);
             const int op = kp ? 0 : (idx[a] == R.n[a] - 1 ? -(R.n[a] - 1) * st[a] : st[a]);
-            const double2 vm = ld2(u + lin + om), vp = ld2(u + lin + op);
+            double vmx, vmy, vpx, vpy;
+            ld_pair(u + lin + om, vmx, vmy);
+            ld_pair(u + lin + op, vpx, vpy);
             kd[0][c][2 * a] = kd[1][c][2 * a] = km;
             kd[0][c][2 * a + 1] = kd[1][c][2 * a + 1] = kp;
-            nb[0][c][2 * a] = vm.x;
-            nb[1][c][2 * a] = vm.y;
-            nb[0][c][2 * a + 1] = vp.x;
-            nb[1][c][2 * a + 1] = vp.y;
+            nb[0][c][2 * a] = vmx;
+            nb[1][c][2 * a] = vmy;
+            nb[0][c][2 * a + 1] = vpx;
+            nb[1][c][2 * a + 1] = vpy;
         }
 #pragma unroll
         for (int q = 0; q < 2; ++q) {
@@ -131,26 +147,25 @@ __device__ __forceinline__ void apply_row2(const RepDev &R, const BlockEnt &be, 
             kd[q][c][1] = nbr_kind(idx[0] + q, +1, n0, R.bc[0], 0, c);
         }
         // x neighbours: inside the pair, or one cell beyond it (wrapped when periodic)
-        nb[0][c][0] = kd[0][c][0] ? sp.x : u[lin + (idx[0] == 0 ? n0 - 1 : -1)];
-        nb[0][c][1] = sp.y;
-        nb[1][c][0] = sp.x;
-        nb[1][c][1] = kd[1][c][1] ? sp.y : u[lin + 1 + (idx[0] + 1 == n0 - 1 ? -(n0 - 1) : 1)];
+        nb[0][c][0] = kd[0][c][0] ? spx : (double)u[lin + (idx[0] == 0 ? n0 - 1 : -1)];
+        nb[0][c][1] = spy;
+        nb[1][c][0] = spx;
+        nb[1][c][1] = kd[1][c][1] ? spy : (double)u[lin + 1 + (idx[0] + 1 == n0 - 1 ? -(n0 - 1) : 1)];
         // pressure at -e_c
         if (c == 0) {
-            pm[0][0] = p[lin + (idx[0] > 0 ? -1 : n0 - 1)];
-            pm[1][0] = p[lin];
+            pm[0][0] = (double)p[lin + (idx[0] > 0 ? -1 : n0 - 1)];
+            pm[1][0] = (double)p[lin];
         } else {
-            const double2 pp = ld2(p + lin + (idx[c] > 0 ? -st[c] : (R.n[c] - 1) * st[c]));
-            pm[0][c] = pp.x;
-            pm[1][c] = pp.y;
+            ld_pair(p + lin + (idx[c] > 0 ? -st[c] : (R.n[c] - 1) * st[c]), pm[0][c], pm[1][c]);
         }
         pin[0][c] = R.bc[c] == RBFIB_WALL && (c == 0 ? idx[0] : idx[c]) == 0;
         pin[1][c] = R.bc[c] == RBFIB_WALL && (c == 0 ? idx[0] + 1 : idx[c]) == 0;
     }
-    const double2 pcv = ld2(p + lin);
+    double pc0, pc1;
+    ld_pair(p + lin, pc0, pc1);
     double o0[4], o1[4];
-    apply_cell(R, self[0], nb[0], pm[0], pcv.x, kd[0], pin[0], o0);
-    apply_cell(R, self[1], nb[1], pm[1], pcv.y, kd[1], pin[1], o1);
+    apply_cell(R, self[0], nb[0], pm[0], pc0, kd[0], pin[0], o0);
+    apply_cell(R, self[1], nb[1], pm[1], pc1, kd[1], pin[1], o1);
 #pragma unroll
     for (int c = 0; c < 4; ++c)
         *reinterpret_cast<double2 *>(yr + (long long)c * N + lin) = make_double2(o0[c], o1[c]);
@@ -160,16 +175,18 @@ __device__ __forceinline__ void apply_row2(const RepDev &R, const BlockEnt &be, 
 // Neighbour offsets and boundary rules are computed first and applied with selects,
 // so the loads of all three components are in flight together; the divergence
 // reuses each component's +e_c neighbour.
+template <typename TX>
 __global__ __launch_bounds__(RB_BLOCK) void k_apply_fluid(const RepDev *reps, const BlockEnt *tab,
-                                                          const double *__restrict__ x, double *__restrict__ y,
+                                                          const TX *__restrict__ x, double *__restrict__ y,
                                                           const int *__restrict__ mask) {
     const BlockEnt be = tab[xcd_block(blockIdx.x, gridDim.x)];
     if (mask && !mask[be.rep]) return;
     const RepDev &R = reps[be.rep];
-    const double *xr = x + R.off;
+    const TX *xr = x + R.off;
     double *yr = y + R.off;
-    // uniform per block: even rows, even field length, 16-byte aligned fields
-    if (be.npt == 2 && R.n[0] % 2 == 0 && R.N % 2 == 0 && ((reinterpret_cast<unsigned long long>(xr) & 15) == 0) &&
+    // uniform per block: even rows, even field length, fields aligned to two values
+    if (be.npt == 2 && R.n[0] % 2 == 0 && R.N % 2 == 0 &&
+        ((reinterpret_cast<unsigned long long>(xr) & (2 * sizeof(TX) - 1)) == 0) &&
         ((reinterpret_cast<unsigned long long>(yr) & 15) == 0)) {
         apply_row2(R, be, xr, yr);
         return;
@@ -197,35 +214,47 @@ __global__ __launch_bounds__(RB_BLOCK) void k_apply_fluid(const RepDev *reps, co
     bool pin[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-        const double *u = xr + (long long)c * N;
-        self[c] = u[lin];
+        const TX *u = xr + (long long)c * N;
+        self[c] = (double)u[lin];
 #pragma unroll
-        for (int q = 0; q < 6; ++q) nb[c][q] = u[lin + off[c][q]];
-        pm[c] = xr[3LL * N + lin + offp[c]];
+        for (int q = 0; q < 6; ++q) nb[c][q] = (double)u[lin + off[c][q]];
+        pm[c] = (double)xr[3LL * N + lin + offp[c]];
         pin[c] = pinned(c, idx, R.bc);
     }
     double out[4];
-    apply_cell(R, self, nb, pm, xr[3LL * N + lin], kd, pin, out);
+    apply_cell(R, self, nb, pm, (double)xr[3LL * N + lin], kd, pin, out);
 #pragma unroll
     for (int c = 0; c < 4; ++c) yr[(long long)c * N + lin] = out[c];
     }
 }
 
-void launch_apply_fluid(Ctx &c, const double *x, double *y) {
-    hipLaunchKernelGGL(k_apply_fluid, dim3(c.n_tab_cells2), dim3(RB_BLOCK), 0, c.stream, c.d_reps, c.d_tab_cells2,
-                       x, y, c.mask);
+template <typename TX>
+void launch_apply_fluid(Ctx &c, const TX *x, double *y) {
+    hipLaunchKernelGGL(k_apply_fluid<TX>, dim3(c.n_tab_cells2), dim3(RB_BLOCK), 0, c.stream, c.d_reps,
+                       c.d_tab_cells2, x, y, c.mask);
 }
+template void launch_apply_fluid<double>(Ctx &, const double *, double *);
+template void launch_apply_fluid<float>(Ctx &, const float *, double *);
 
 // ------------------------------------------------------------------ multigrid
 // Level pools hold 4 fields per (replica, level): comp c at lev.off + c * lev.N.
 // FP32 cell kernels on four consecutive x cells per thread: blocks of 1024 cells
 // (four per thread), rows a multiple of four long, and the replica's FP64 state
 // 16-byte aligned (the level pools always are for such rows).  Uniform per block.
-__device__ __forceinline__ bool cells_row4(const BlockEnt &be, const RepDev &R, const double *state) {
+template <typename P>
+__device__ __forceinline__ bool cells_row4(const BlockEnt &be, const RepDev &R, const P *state) {
     return be.npt == 4 && R.n[0] % 4 == 0 && ((reinterpret_cast<unsigned long long>(state + R.off) & 15) == 0);
 }
 
 __device__ __forceinline__ double2 ld_d2(const double *q) { return *reinterpret_cast<const double2 *>(q); }
+// four consecutive z values (16-byte aligned): FP64 as two 16-byte stores, FP32 as one
+__device__ __forceinline__ void st_four(double *q, const double o[4]) {
+    *reinterpret_cast<double2 *>(q) = make_double2(o[0], o[1]);
+    *reinterpret_cast<double2 *>(q + 2) = make_double2(o[2], o[3]);
+}
+__device__ __forceinline__ void st_four(float *q, const double o[4]) {
+    *reinterpret_cast<float4 *>(q) = make_float4((float)o[0], (float)o[1], (float)o[2], (float)o[3]);
+}
 __device__ __forceinline__ float4 ld_f4(const float *q) { return *reinterpret_cast<const float4 *>(q); }
 
 // b (level 0) = src * f, f = rs[rep * rstride] (1 without rs)
@@ -953,9 +982,9 @@ __device__ __forceinline__ void proj_div_out(double div, double rp, double f, do
 }
 
 // (r_pi is read as r * f, f = rs[rep * rstride], 1 without rs)
-template <typename T>
+template <typename T, typename TZ>
 __global__ void k_proj_div(const RepDev *reps, const LevDev *levs, const BlockEnt *tab, const T *__restrict__ xv,
-                           const double *__restrict__ r, T *__restrict__ bp, double *__restrict__ z, const int *__restrict__ mask,
+                           const double *__restrict__ r, T *__restrict__ bp, TZ *__restrict__ z, const int *__restrict__ mask,
                            const double *__restrict__ rs, int rstride) {
     BlockEnt be = tab[xcd_block(blockIdx.x, gridDim.x)];
     if (mask && !mask[be.rep]) return;
@@ -1002,9 +1031,7 @@ __global__ void k_proj_div(const RepDev *reps, const LevDev *levs, const BlockEn
                 proj_div_out(div, rr[q], f, R.eta, bo[q], zo[q]);
             }
             *reinterpret_cast<float4 *>((float *)bp + Lv.off + 3 * Lv.N + lin) = make_float4(bo[0], bo[1], bo[2], bo[3]);
-            double *zp = z + R.off + 3 * N + lin;
-            *reinterpret_cast<double2 *>(zp) = make_double2(zo[0], zo[1]);
-            *reinterpret_cast<double2 *>(zp + 2) = make_double2(zo[2], zo[3]);
+            st_four(z + R.off + 3 * N + lin, zo);
             return;
         }
     }
@@ -1026,20 +1053,20 @@ __global__ void k_proj_div(const RepDev *reps, const LevDev *levs, const BlockEn
     }
     const double d = fmad(r[R.off + 3 * N + lin], f, div);
     bp[Lv.off + 3 * Lv.N + lin] = (T)(-d);
-    z[R.off + 3 * N + lin] = -R.eta * d;
+    z[R.off + 3 * N + lin] = (TZ)(-R.eta * d);
     }
 }
 
-template <typename T>
-void launch_proj_div(Ctx &c, const T *xv, const double *r, T *bp, double *z, const double *rs) {
-    hipLaunchKernelGGL(k_proj_div<T>, dim3(c.n_tab_cells), dim3(RB_BLOCK), 0, c.stream, c.d_reps, c.d_levs,
+template <typename T, typename TZ>
+void launch_proj_div(Ctx &c, const T *xv, const double *r, T *bp, TZ *z, const double *rs) {
+    hipLaunchKernelGGL((k_proj_div<T, TZ>), dim3(c.n_tab_cells), dim3(RB_BLOCK), 0, c.stream, c.d_reps, c.d_levs,
                        c.d_tab_cells, xv, r, bp, z, c.mask, rs, c.m + 1);
 }
 
 // z_v = x* - G phi  (phi in the pressure slot of the level-0 pool).
-template <typename T>
+template <typename T, typename TZ>
 __global__ void k_proj_correct(const RepDev *reps, const LevDev *levs, const BlockEnt *tab, const T *__restrict__ xv,
-                               const T *__restrict__ phi, double *__restrict__ z, const int *__restrict__ mask) {
+                               const T *__restrict__ phi, TZ *__restrict__ z, const int *__restrict__ mask) {
     BlockEnt be = tab[xcd_block(blockIdx.x, gridDim.x)];
     if (mask && !mask[be.rep]) return;
     const RepDev &R = reps[be.rep];
@@ -1072,9 +1099,7 @@ __global__ void k_proj_correct(const RepDev *reps, const LevDev *levs, const Blo
                     const float pm = c == 0 ? pmx[q] : (c == 1 ? pmy[q] : pmz[q]);
                     o[q] = pin ? 0.0 : fmad(-((double)pc[q] - (double)pm), R.inv_h, (double)xs[q]);
                 }
-                double *zp = z + R.off + c * N + lin;
-                *reinterpret_cast<double2 *>(zp) = make_double2(o[0], o[1]);
-                *reinterpret_cast<double2 *>(zp + 2) = make_double2(o[2], o[3]);
+                st_four(z + R.off + c * N + lin, o);
             }
             return;
         }
@@ -1093,15 +1118,15 @@ __global__ void k_proj_correct(const RepDev *reps, const LevDev *levs, const Blo
             double pm = (idx[c] > 0) ? (double)ph[lin - stride] : (double)ph[lin + (long long)(R.n[c] - 1) * stride];
             out = fmad(-(pc - pm), R.inv_h, (double)xv[Lv.off + c * Lv.N + lin]);
         }
-        z[R.off + c * N + lin] = out;
+        z[R.off + c * N + lin] = (TZ)out;
         stride *= R.n[c];
     }
     }
 }
 
-template <typename T>
-void launch_proj_correct(Ctx &c, const T *xv, const T *phi, double *z) {
-    hipLaunchKernelGGL(k_proj_correct<T>, dim3(c.n_tab_cells), dim3(RB_BLOCK), 0, c.stream, c.d_reps, c.d_levs,
+template <typename T, typename TZ>
+void launch_proj_correct(Ctx &c, const T *xv, const T *phi, TZ *z) {
+    hipLaunchKernelGGL((k_proj_correct<T, TZ>), dim3(c.n_tab_cells), dim3(RB_BLOCK), 0, c.stream, c.d_reps, c.d_levs,
                        c.d_tab_cells, xv, phi, z, c.mask);
 }
 
@@ -1227,9 +1252,12 @@ template void launch_prolong<float>(Ctx &, int, int, int, const float *, float *
 template void launch_prolong<double>(Ctx &, int, int, int, const double *, double *);
 template void launch_coarse<float>(Ctx &, int, int, int, const float *, float *);
 template void launch_coarse<double>(Ctx &, int, int, int, const double *, double *);
-template void launch_proj_div<float>(Ctx &, const float *, const double *, float *, double *, const double *);
-template void launch_proj_div<double>(Ctx &, const double *, const double *, double *, double *, const double *);
-template void launch_proj_correct<float>(Ctx &, const float *, const float *, double *);
-template void launch_proj_correct<double>(Ctx &, const double *, const double *, double *);
+template void launch_proj_div<float, double>(Ctx &, const float *, const double *, float *, double *, const double *);
+template void launch_proj_div<float, float>(Ctx &, const float *, const double *, float *, float *, const double *);
+template void launch_proj_div<double, double>(Ctx &, const double *, const double *, double *, double *,
+                                              const double *);
+template void launch_proj_correct<float, double>(Ctx &, const float *, const float *, double *);
+template void launch_proj_correct<float, float>(Ctx &, const float *, const float *, float *);
+template void launch_proj_correct<double, double>(Ctx &, const double *, const double *, double *);
 
 }  // namespace rb

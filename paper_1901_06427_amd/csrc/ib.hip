@@ -340,12 +340,12 @@ void launch_markers(Ctx &c, MarkerSet &ms, const double *q, const double *theta)
 // is small and its chain of dependent loads sets the time.
 // TO = double: y is a state vector (velocity of replica r at R.off + c N);
 // with levs given: y is a multigrid pool, level 0 of each replica.
-template <typename TO>
+template <typename TO, typename TL>
 __global__ __launch_bounds__(64) void k_spread(const RepDev *reps, const int *tile_rep, const int *active,
                                                const int *n_active, const int *pair_start, const int *pair_count,
                                                long long cap, const double *__restrict__ pair_w,
                                                const long long *__restrict__ pair_lam,
-                                               const double *__restrict__ lam_state, TO *__restrict__ y,
+                                               const TL *__restrict__ lam_state, TO *__restrict__ y,
                                                double alpha, const int *__restrict__ mask,
                                                const LevDev *__restrict__ levs) {
     const int lane = threadIdx.x;
@@ -362,10 +362,10 @@ __global__ __launch_bounds__(64) void k_spread(const RepDev *reps, const int *ti
 #pragma unroll 2
         for (long long s = s0; s < s1; ++s) {
             const double *w = pair_w + s * 36;
-            const double *lam = lam_state + pair_lam[s];
+            const TL *lam = lam_state + pair_lam[s];
 #pragma unroll
             for (int c = 0; c < 3; ++c)
-                acc[c] += w[12 * c + lx] * w[12 * c + 4 + ly] * w[12 * c + 8 + lz] * lam[c];
+                acc[c] += w[12 * c + lx] * w[12 * c + 4 + ly] * w[12 * c + 8 + lz] * (double)lam[c];
         }
         const int lt = t - R.tile0;
         const int g0 = RB_TILE * (lt % R.tdim[0]) + lx;
@@ -382,32 +382,37 @@ __global__ __launch_bounds__(64) void k_spread(const RepDev *reps, const int *ti
     }
 }
 
-template <typename TO>
-static void spread_into(Ctx &c, MarkerSet &ms, const double *lam_state, TO *y, double alpha, const LevDev *levs) {
+template <typename TO, typename TL>
+static void spread_into(Ctx &c, MarkerSet &ms, const TL *lam_state, TO *y, double alpha, const LevDev *levs) {
     if (c.nm == 0) return;
     int grid = std::min(c.ntiles, 65536);   // grid-stride over the tiles that have pairs
-    hipLaunchKernelGGL(k_spread<TO>, dim3(grid), dim3(64), 0, c.stream, c.d_reps, c.d_tile_rep, ms.active,
+    hipLaunchKernelGGL((k_spread<TO, TL>), dim3(grid), dim3(64), 0, c.stream, c.d_reps, c.d_tile_rep, ms.active,
                        ms.n_active, ms.pair_start, ms.pair_count, ms.pair_cap, ms.pair_w, ms.pair_lam, lam_state, y,
                        alpha, c.mask, levs);
 }
 
 // y_fluid += alpha * S lambda, lambda read from the lambda slots of lam_state.
-void launch_spread(Ctx &c, MarkerSet &ms, const double *lam_state, double *y, double alpha) {
-    spread_into<double>(c, ms, lam_state, y, alpha, nullptr);
+template <typename TL>
+void launch_spread(Ctx &c, MarkerSet &ms, const TL *lam_state, double *y, double alpha) {
+    spread_into<double, TL>(c, ms, lam_state, y, alpha, nullptr);
 }
+template void launch_spread<double>(Ctx &, MarkerSet &, const double *, double *, double);
+template void launch_spread<float>(Ctx &, MarkerSet &, const float *, double *, double);
 
 // Level 0 of the multigrid pool (velocity components) += alpha * S lambda.
-template <typename T>
-void launch_spread_level0(Ctx &c, MarkerSet &ms, const double *lam_state, T *pool, double alpha) {
-    spread_into<T>(c, ms, lam_state, pool, alpha, c.d_levs);
+template <typename T, typename TL>
+void launch_spread_level0(Ctx &c, MarkerSet &ms, const TL *lam_state, T *pool, double alpha) {
+    spread_into<T, TL>(c, ms, lam_state, pool, alpha, c.d_levs);
 }
-template void launch_spread_level0<float>(Ctx &, MarkerSet &, const double *, float *, double);
-template void launch_spread_level0<double>(Ctx &, MarkerSet &, const double *, double *, double);
+template void launch_spread_level0<float, double>(Ctx &, MarkerSet &, const double *, float *, double);
+template void launch_spread_level0<float, float>(Ctx &, MarkerSet &, const float *, float *, double);
+template void launch_spread_level0<double, double>(Ctx &, MarkerSet &, const double *, double *, double);
 
 // ------------------------------------------------------------------ J, K, K^T per body
 // y_lambda = -J v + K U ;  y_U = K^T lambda  (rows 3 and 4 of the saddle operator).
+template <typename TX>
 __global__ void k_body_apply(const RepDev *reps, const int *body_rep, const int *body_off, const double *r,
-                             const double *d, const double *__restrict__ x, double *__restrict__ y,
+                             const double *d, const TX *__restrict__ x, double *__restrict__ y,
                              const int *__restrict__ mask, const double *__restrict__ wc, const int *__restrict__ ic) {
     extern __shared__ double sred[];   // [nmp][6]
     int p = blockIdx.x;
@@ -417,7 +422,7 @@ __global__ void k_body_apply(const RepDev *reps, const int *body_rep, const int 
     long long lam0 = R.off + 4 * R.N;
     long long U0 = lam0 + 3LL * R.nm + 6LL * (p - R.b0);
     double U[6];
-    for (int k = 0; k < 6; ++k) U[k] = x[U0 + k];
+    for (int k = 0; k < 6; ++k) U[k] = (double)x[U0 + k];
     for (int task = threadIdx.x; task < 3 * nmp; task += blockDim.x) {
         int i = task / 3, c = task % 3, m = m0 + i;
         double Jv = interp_cached(R, wc, ic, m, c, x + R.off + c * R.N);
@@ -427,7 +432,8 @@ __global__ void k_body_apply(const RepDev *reps, const int *body_rep, const int 
     }
     for (int i = threadIdx.x; i < nmp; i += blockDim.x) {
         int m = m0 + i;
-        const double *l = x + lam0 + 3LL * (m - R.m0);
+        const TX *lx = x + lam0 + 3LL * (m - R.m0);
+        const double l[3] = {(double)lx[0], (double)lx[1], (double)lx[2]};
         const double *dm = d + 3 * m;
         sred[6 * i + 0] = l[0];
         sred[6 * i + 1] = l[1];
@@ -444,13 +450,16 @@ __global__ void k_body_apply(const RepDev *reps, const int *body_rep, const int 
     }
 }
 
-void launch_body_apply(Ctx &c, MarkerSet &ms, const double *q, const double *x, double *y) {
+template <typename TX>
+void launch_body_apply(Ctx &c, MarkerSet &ms, const double *q, const TX *x, double *y) {
     (void)q;
     if (c.nb == 0) return;
     size_t sh = sizeof(double) * 6 * (size_t)c.max_body_nm;
-    hipLaunchKernelGGL(k_body_apply, dim3(c.nb), dim3(128), sh, c.stream, c.d_reps, c.d_body_rep, c.d_body_off, ms.r,
+    hipLaunchKernelGGL(k_body_apply<TX>, dim3(c.nb), dim3(128), sh, c.stream, c.d_reps, c.d_body_rep, c.d_body_off, ms.r,
                        ms.d, x, y, c.mask, ms.wc, ms.ic);
 }
+template void launch_body_apply<double>(Ctx &, MarkerSet &, const double *, const double *, double *);
+template void launch_body_apply<float>(Ctx &, MarkerSet &, const double *, const float *, double *);
 
 // ------------------------------------------------------------------ interpolation
 // out[m, c] (= or +=) alpha * (J u)_c at markers of ms; u is a state vector.
@@ -514,9 +523,10 @@ void launch_interp_bc(Ctx &c, MarkerSet &ms, double *out, double alpha) {
 // Per body, in the body frame (rotation by R^T): U' = N (r_U' + K^T Minv g'),
 // lambda' = Minv K U' - Minv g', with Minv the inverse blob mobility of the
 // reference body; rotated back to the lab frame.
+template <typename TZ>
 __global__ void k_body_precond(const RepDev *reps, const int *body_rep, const int *body_off, const int *body_shape,
                                const ShapeDev *shapes, const double *sdata, const double *theta,
-                               const double *__restrict__ rin, double *__restrict__ z,
+                               const double *__restrict__ rin, TZ *__restrict__ z,
                                const int *__restrict__ mask, const double *__restrict__ rs, int rstride) {
     extern __shared__ double sm[];
     int p = blockIdx.x;
@@ -586,38 +596,47 @@ __global__ void k_body_precond(const RepDev *reps, const int *body_rep, const in
     __syncthreads();
     for (int i = threadIdx.x; i < S.nm; i += blockDim.x) {
         const double *v = g + 3 * i;
-        double *o = z + lam0 + 3 * i;
-        for (int k = 0; k < 3; ++k) o[k] = Rm[3 * k] * v[0] + Rm[3 * k + 1] * v[1] + Rm[3 * k + 2] * v[2];
+        TZ *o = z + lam0 + 3 * i;
+        for (int k = 0; k < 3; ++k) o[k] = (TZ)(Rm[3 * k] * v[0] + Rm[3 * k + 1] * v[1] + Rm[3 * k + 2] * v[2]);
     }
     if (threadIdx.x < 2) {
         const double *v = U6 + 3 * threadIdx.x;
-        double *o = z + U0 + 3 * threadIdx.x;
-        for (int k = 0; k < 3; ++k) o[k] = Rm[3 * k] * v[0] + Rm[3 * k + 1] * v[1] + Rm[3 * k + 2] * v[2];
+        TZ *o = z + U0 + 3 * threadIdx.x;
+        for (int k = 0; k < 3; ++k) o[k] = (TZ)(Rm[3 * k] * v[0] + Rm[3 * k + 1] * v[1] + Rm[3 * k + 2] * v[2]);
     }
 }
 
-void launch_body_precond(Ctx &c, MarkerSet &ms, const double *theta, const double *r, double *z, const double *rs) {
+template <typename TZ>
+void launch_body_precond(Ctx &c, MarkerSet &ms, const double *theta, const double *r, TZ *z, const double *rs) {
     (void)ms;
     if (c.nb == 0) return;
     size_t sh = sizeof(double) * (size_t)(6 * c.max_body_nm + 12);
-    hipLaunchKernelGGL(k_body_precond, dim3(c.nb), dim3(128), sh, c.stream, c.d_reps, c.d_body_rep, c.d_body_off,
+    hipLaunchKernelGGL(k_body_precond<TZ>, dim3(c.nb), dim3(128), sh, c.stream, c.d_reps, c.d_body_rep, c.d_body_off,
                        c.d_body_shape, c.d_shapes, c.d_shape_data, theta, r, z, c.mask, rs, c.m + 1);
 }
+template void launch_body_precond<double>(Ctx &, MarkerSet &, const double *, const double *, double *,
+                                          const double *);
+template void launch_body_precond<float>(Ctx &, MarkerSet &, const double *, const double *, float *,
+                                         const double *);
 
 // ------------------------------------------------------------------ small helpers
 // zero the lambda and U slots of every replica
-__global__ void k_zero_bodies(const RepDev *reps, int nrep, double *y, const int *__restrict__ mask) {
+template <typename TY>
+__global__ void k_zero_bodies(const RepDev *reps, int nrep, TY *y, const int *__restrict__ mask) {
     int r = blockIdx.y;
     if (r >= nrep || (mask && !mask[r])) return;
     const RepDev &R = reps[r];
     long long n = 3LL * R.nm + 6LL * R.nb;
     for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
-        y[R.off + 4 * R.N + i] = 0.0;
+        y[R.off + 4 * R.N + i] = (TY)0;
 }
 
-void launch_zero_bodies(Ctx &c, double *y) {
-    hipLaunchKernelGGL(k_zero_bodies, dim3(4, c.nrep), dim3(256), 0, c.stream, c.d_reps, c.nrep, y, c.mask);
+template <typename TY>
+void launch_zero_bodies(Ctx &c, TY *y) {
+    hipLaunchKernelGGL(k_zero_bodies<TY>, dim3(4, c.nrep), dim3(256), 0, c.stream, c.d_reps, c.nrep, y, c.mask);
 }
+template void launch_zero_bodies<double>(Ctx &, double *);
+template void launch_zero_bodies<float>(Ctx &, float *);
 
 // b = [0 ; 0 ; -slip ; FT]  (fluid rows zeroed; boundary terms added separately)
 __global__ void k_set_rhs_bodies(const RepDev *reps, const int *marker_body, const int *body_rep, int nm, int nb,

@@ -609,9 +609,10 @@ __global__ __launch_bounds__(64) void k_trisolve(int nrep, int m, const double *
 
 // x += sum_{i < jf} y_i Z_i
 // (the column loop is unrolled so that eight loads, one basis vector apart, are in
-// flight together; the sum keeps its order)
+// flight together; the sum keeps its order); Z is FP64, or FP32 with an FP32 preconditioner
+template <typename TZ>
 __global__ __launch_bounds__(RB_BLOCK) void k_update_x(const RepDev *reps, const BlockEnt *tab,
-                                                       const double *__restrict__ Z, long long L, int m,
+                                                       const TZ *__restrict__ Z, long long L, int m,
                                                        const double *__restrict__ y, const int *jf, const int *cyc,
                                                        double *__restrict__ x) {
     BlockEnt be = tab[blockIdx.x];
@@ -624,7 +625,7 @@ __global__ __launch_bounds__(RB_BLOCK) void k_update_x(const RepDev *reps, const
     for (long long g = b + threadIdx.x; g < e; g += RB_BLOCK) {
         double acc = 0.0;
 #pragma unroll 8
-        for (int i = 0; i < n; ++i) acc += yr[i] * Z[(long long)i * L + g];
+        for (int i = 0; i < n; ++i) acc += yr[i] * (double)Z[(long long)i * L + g];
         x[g] += acc;
     }
 }
@@ -632,8 +633,12 @@ __global__ __launch_bounds__(RB_BLOCK) void k_update_x(const RepDev *reps, const
 void launch_trisolve_update(Ctx &c) {
     hipLaunchKernelGGL(k_trisolve, dim3(c.nrep), dim3(64), (size_t)(c.m + 1) * sizeof(double), c.stream, c.nrep,
                        c.m, c.H, c.gv, c.cyc_active, c.jf, c.yv);
-    hipLaunchKernelGGL(k_update_x, dim3(c.n_tab_vec), dim3(RB_BLOCK), 0, c.stream, c.d_reps, c.d_tab_vec, c.Z, c.L,
-                       c.m, c.yv, c.jf, c.cyc_active, c.xsol);
+    if (c.Zf)
+        hipLaunchKernelGGL(k_update_x<float>, dim3(c.n_tab_vec), dim3(RB_BLOCK), 0, c.stream, c.d_reps, c.d_tab_vec,
+                           c.Zf, c.L, c.m, c.yv, c.jf, c.cyc_active, c.xsol);
+    else
+        hipLaunchKernelGGL(k_update_x<double>, dim3(c.n_tab_vec), dim3(RB_BLOCK), 0, c.stream, c.d_reps,
+                           c.d_tab_vec, c.Z, c.L, c.m, c.yv, c.jf, c.cyc_active, c.xsol);
 }
 
 // Start of a restart cycle for active replicas: g = (beta, 0, ...), jf = 0; beta in nrm slot.

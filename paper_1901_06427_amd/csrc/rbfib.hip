@@ -196,10 +196,12 @@ static void record(Ctx &c, int cls, bool start, double bytes = 0.0) {
     }
 }
 
-static void apply_op(Ctx &c, MarkerSet &ms, const double *x, double *y, bool fluid_only) {
+// y = A x; x is FP64, or FP32 for the preconditioned vectors of an FP32 preconditioner
+template <typename TX>
+static void apply_op(Ctx &c, MarkerSet &ms, const TX *x, double *y, bool fluid_only) {
     record(c, 0, true);
     launch_apply_fluid(c, x, y);
-    record(c, 0, false, c.cells_all * 64.0);      // read 4 FP64 fields, write 4
+    record(c, 0, false, c.cells_all * (4.0 * sizeof(TX) + 32.0));   // read 4 fields of x, write 4 FP64
     if (fluid_only || c.nm == 0) {
         launch_zero_bodies(c, y);
         return;
@@ -293,9 +295,11 @@ static T *vcycle(Ctx &c, int c0, int nc) {
 }
 
 // z = P^-1 (f r), f = rs[rep * (m + 1)] per replica (1 without rs): the readers of r
-// apply the factor, so that an unnormalised Krylov vector needs no scaling pass.
-template <typename T>
-static void precond_t(Ctx &c, MarkerSet &ms, const double *theta, const double *r, double *z, bool fluid_only,
+// apply the factor, so that an unnormalised Krylov vector needs no scaling pass.  z is
+// FP64, or FP32 (the FGMRES basis Z of an FP32 preconditioner: A is applied to the
+// stored values, so the Arnoldi relation holds for them exactly).
+template <typename T, typename TZ>
+static void precond_t(Ctx &c, MarkerSet &ms, const double *theta, const double *r, TZ *z, bool fluid_only,
                       const double *rs) {
     bool bodies = !fluid_only && c.nb > 0;
     if (bodies) launch_body_precond(c, ms, theta, r, z, rs);
@@ -312,10 +316,12 @@ static void precond_t(Ctx &c, MarkerSet &ms, const double *theta, const double *
     HIP_OK(hipGetLastError());     // a launch the runtime refused surfaces here, not as stale results
 }
 
-static void precond(Ctx &c, MarkerSet &ms, const double *theta, const double *r, double *z, bool fluid_only,
+template <typename TZ>
+static void precond(Ctx &c, MarkerSet &ms, const double *theta, const double *r, TZ *z, bool fluid_only,
                     const double *rs = nullptr) {
-    if (c.mg_fp32) precond_t<float>(c, ms, theta, r, z, fluid_only, rs);
-    else precond_t<double>(c, ms, theta, r, z, fluid_only, rs);
+    if (c.mg_fp32) precond_t<float, TZ>(c, ms, theta, r, z, fluid_only, rs);
+    else if constexpr (sizeof(TZ) == 8) precond_t<double, TZ>(c, ms, theta, r, z, fluid_only, rs);
+    else throw (int)RBFIB_EINVAL;   // FP32 z only with the FP32 preconditioner
 }
 
 // ------------------------------------------------------------------ FGMRES
@@ -414,9 +420,17 @@ static void fgmres(Ctx &c, MarkerSet &ms, const double *theta, const double *b, 
                     c.mask = c.timing.on ? nullptr : c.active;
                     for (int k = 0; k < sj; ++k) {
                         const double *src = c.V + (long long)(j + k) * c.L;
-                        double *zk = c.Z + (long long)(j + k) * c.L;
-                        precond(c, ms, theta, src, zk, fluid_only, k == 0 ? c.inv_nu + j : nullptr);
-                        apply_op(c, ms, zk, c.V + (long long)(j + k + 1) * c.L, fluid_only);
+                        double *dst = c.V + (long long)(j + k + 1) * c.L;
+                        const double *rs = k == 0 ? c.inv_nu + j : nullptr;
+                        if (c.Zf) {
+                            float *zk = c.Zf + (long long)(j + k) * c.L;
+                            precond(c, ms, theta, src, zk, fluid_only, rs);
+                            apply_op(c, ms, zk, dst, fluid_only);
+                        } else {
+                            double *zk = c.Z + (long long)(j + k) * c.L;
+                            precond(c, ms, theta, src, zk, fluid_only, rs);
+                            apply_op(c, ms, zk, dst, fluid_only);
+                        }
                     }
                     c.mask = nullptr;
                     const double vb = c.timing.on ? 8.0 * active_len(c) : 0.0;
@@ -431,13 +445,20 @@ static void fgmres(Ctx &c, MarkerSet &ms, const double *theta, const double *b, 
                 };
                 auto body = [&]() {
                     if (sj > 1) { body_s(); return; }
-                    double *Vj = c.V + (long long)j * c.L, *Zj = c.Z + (long long)j * c.L;
+                    double *Vj = c.V + (long long)j * c.L;
                     double *W = c.V + (long long)(j + 1) * c.L;
                     // converged replicas skip the grid and body kernels (not in timing
                     // runs, whose byte counts assume every replica is processed)
                     c.mask = c.timing.on ? nullptr : c.active;
-                    precond(c, ms, theta, Vj, Zj, fluid_only, c.inv_nu + j);
-                    apply_op(c, ms, Zj, W, fluid_only);
+                    if (c.Zf) {
+                        float *Zj = c.Zf + (long long)j * c.L;
+                        precond(c, ms, theta, Vj, Zj, fluid_only, c.inv_nu + j);
+                        apply_op(c, ms, Zj, W, fluid_only);
+                    } else {
+                        double *Zj = c.Z + (long long)j * c.L;
+                        precond(c, ms, theta, Vj, Zj, fluid_only, c.inv_nu + j);
+                        apply_op(c, ms, Zj, W, fluid_only);
+                    }
                     c.mask = nullptr;
                     // algorithmic bytes of the masked Krylov kernels: FP64 vectors of the active replicas
                     const double vb = c.timing.on ? 8.0 * active_len(c) : 0.0;
@@ -1039,7 +1060,10 @@ static void build(Ctx &c, int nrep, const rbfib_grid *grids, const rbfib_bodies 
     c.m = c.opts.restart;
     size_t L = (size_t)c.L;
     c.V = dalloc<double>(L * (c.m + 1));
-    c.Z = dalloc<double>(L * c.m);
+    // preconditioned vectors: FP32 with the FP32 preconditioner (half the traffic of the
+    // apply's input, of the projection outputs and of the solution update)
+    if (c.mg_fp32) c.Zf = dalloc<float>(L * c.m);
+    else c.Z = dalloc<double>(L * c.m);
     c.W = dalloc<double>(L);
     c.xsol = dalloc<double>(L);
     c.rhs = dalloc<double>(L);
@@ -1106,7 +1130,7 @@ static void free_all(Ctx &c) {
     F(c.d_flags); F(c.d_scan); F(c.d_count); F(c.d_active_len);
     if (c.h_flags) (void)hipHostFree(c.h_flags);
     if (c.h_count) (void)hipHostFree(c.h_count);
-    F(c.V); F(c.Z); F(c.W); F(c.xsol); F(c.rhs); F(c.xR); F(c.xS); F(c.partial);
+    F(c.V); F(c.Z); F(c.Zf); F(c.W); F(c.xsol); F(c.rhs); F(c.xR); F(c.xS); F(c.partial);
     F(c.H); F(c.cs); F(c.sn); F(c.gv); F(c.beta0); F(c.hcol); F(c.inv_nu); F(c.hblk); F(c.gram); F(c.tco); F(c.yv); F(c.d_resid);
     F(c.active); F(c.cyc_active); F(c.jf); F(c.status); F(c.iters);
     for (int k = 0; k < 3; ++k) { F(c.q_buf[k]); F(c.th_buf[k]); }
