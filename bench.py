@@ -261,9 +261,15 @@ KERNEL_SOURCES = ("paper_1901_06427_amd/csrc/grid.hip", "paper_1901_06427_amd/cs
 
 
 def _code_tokens(text):
-    """Source text without comments, whitespace runs collapsed: what the compiler
-    sees, so that editing a comment does not mark the counters stale."""
+    """Source text without comments, whitespace runs outside literals collapsed to one
+    space: what the compiler sees, so that editing a comment does not mark the
+    counters stale."""
     out, i, n = [], 0, len(text)
+
+    def space():
+        if out and out[-1] != " ":
+            out.append(" ")
+
     while i < n:
         c = text[i]
         if text.startswith("//", i):
@@ -272,17 +278,20 @@ def _code_tokens(text):
         elif text.startswith("/*", i):
             j = text.find("*/", i + 2)
             i = n if j < 0 else j + 2
-            out.append(" ")
+            space()
         elif c in "\"'":
             j = i + 1
             while j < n and text[j] != c:
                 j += 2 if text[j] == "\\" else 1
             out.append(text[i:j + 1])
             i = j + 1
+        elif c.isspace():
+            space()
+            i += 1
         else:
             out.append(c)
             i += 1
-    return " ".join("".join(out).split())
+    return "".join(out).strip()
 
 
 def kernel_source_hash():

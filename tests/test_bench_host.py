@@ -1,0 +1,32 @@
+"""Host logic of bench.py that needs no GPU.
+
+The measured HBM traffic in the committed counter summary is reported only while
+the kernel sources hash to the ones the counters were taken with; the hash is over
+the code with comments and blank space removed, so editing a comment keeps it and
+changing code (a string literal included) does not.
+"""
+import bench
+
+
+def test_code_tokens_drop_comments_only():
+    src = 'int a = 1;  // note\n/* block\n comment */ const char *s = "// kept /* too */";\nchar c = \'"\';\n'
+    assert bench._code_tokens(src) == 'int a = 1; const char *s = "// kept /* too */"; char c = \'"\';'
+
+
+def test_comment_edit_keeps_hash_code_edit_changes_it():
+    base = "__global__ void k(float *x) {\n    x[0] = 1.0f;   // first\n}\n"
+    comment = "__global__ void k(float *x) {\n    // a new remark\n    x[0] = 1.0f;   /* first */\n}\n"
+    code = "__global__ void k(float *x) {\n    x[0] = 2.0f;   // first\n}\n"
+    assert bench._code_tokens(base) == bench._code_tokens(comment)
+    assert bench._code_tokens(base) != bench._code_tokens(code)
+    assert bench._code_tokens('s = "a  b";') != bench._code_tokens('s = "a b";')  # inside a literal: code
+
+
+def test_committed_traffic_matches_current_sources():
+    # the counter summary names the hash of the sources it was taken with; the
+    # roofline object reports its traffic only while they match
+    h = bench.kernel_source_hash()
+    with open(bench.COUNTERS) as fh:
+        lines = [l.split() for l in fh if l.startswith("traffic:")]
+    assert lines and all(l[5] == h for l in lines), (h, lines)
+    assert bench.measured_traffic("mg_smooth_level0") is not None
