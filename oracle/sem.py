@@ -16,9 +16,16 @@ dN = -N (dK^T) M^-1 K N + N K^T M^-1 (dM) M^-1 K N - N K^T M^-1 (dK) N):
   6. Constrained solve with force F - D^KT, slip  slip + D^K - D^J - D^S, and
      fluid forcing sqrt(2 kT eta / (dV dt)) DT W plus the moving-wall terms.
   7. q <- q + dt u ; theta <- Rotate(theta, dt omega).
-A step whose new markers leave the open domain along a wall axis (or whose
-body centres come closer than ``min_body_dist``) is rejected and the state is
-left unchanged; the caller repeats it with fresh random numbers.
+A step is rejected, and the state left unchanged, when a marker of the new
+configuration Q^{n+1} or of one of the displaced configurations Q+- leaves the
+open domain along a wall axis (S and J are not defined for a marker outside
+the fluid), or when body centres come closer than ``min_body_dist``; the
+caller repeats it with fresh random numbers.  A rejected step still returns
+the velocities its solves produced.
+
+The random forces and torques of step 1 come from the Philox stream of
+(seed, step); ``normals = (W^f, W^tau)`` replaces them with given values (used
+to evaluate the drift at chosen directions).
 """
 from __future__ import annotations
 
@@ -48,11 +55,12 @@ class SEMResult:
     DJ: np.ndarray
     DS: np.ndarray
     x_final: np.ndarray
+    rhs_norms: tuple = ()      # ||b|| of the RFD, unconstrained and final solves
 
 
 def sem_step(g: mac.Grid, r_ref, offsets, q, theta, FT, kT: float, dt: float, seed: int, step: int,
              delta: float = 1e-5, slip: Optional[np.ndarray] = None, min_body_dist: float = 0.0,
-             tol: float = 1e-12, noise: bool = True) -> SEMResult:
+             tol: float = 1e-12, noise: bool = True, normals=None) -> SEMResult:
     q = np.asarray(q, dtype=np.float64).reshape(-1, 3)
     theta = np.asarray(theta, dtype=np.float64).reshape(-1, 4)
     nb = q.shape[0]
@@ -60,12 +68,17 @@ def sem_step(g: mac.Grid, r_ref, offsets, q, theta, FT, kT: float, dt: float, se
     Lp = B.body_length(r_ref, offsets)
 
     # 1. random forces and torques
-    Wf, Wt = rng.body_normals(seed, step, nb)
+    if normals is None:
+        Wf, Wt = rng.body_normals(seed, step, nb)
+    else:
+        Wf = np.asarray(normals[0], dtype=np.float64).reshape(nb, 3)
+        Wt = np.asarray(normals[1], dtype=np.float64).reshape(nb, 3)
     WFT = np.concatenate([kT * Wf / Lp[:, None], kT * Wt], axis=1)
 
     # 2. RFD solve at Q^n (homogeneous data)
     s0 = Saddle(g, q, theta, r_ref, offsets)
-    xR = s0.solve(s0.rhs(FT=WFT, include_bc=False), tol=tol)
+    b1 = s0.rhs(FT=WFT, include_bc=False)
+    xR = s0.solve(b1, tol=tol)
     vR, _, lamR, UR = s0.split(xR)
 
     # 3. displaced configurations
@@ -75,13 +88,15 @@ def sem_step(g: mac.Grid, r_ref, offsets, q, theta, FT, kT: float, dt: float, se
     thm = B.rotate(theta, -0.5 * delta * Wt)
     rp = B.marker_positions(qp, thp, r_ref, offsets)
     rm = B.marker_positions(qm, thm, r_ref, offsets)
+    displaced_inside = B.inside_open_domain(g, rp) and B.inside_open_domain(g, rm)
 
     # 4. unconstrained Stokes solve with the spread difference
     Jp = ib.interpolation(g, rp)
     Jm = ib.interpolation(g, rm)
     fsharp = ((Jp.T @ lamR.ravel()) - (Jm.T @ lamR.ravel())) / (g.dV * delta)
     sf = Saddle(g, q, theta, r_ref, offsets, fluid_only=True)
-    xs = sf.solve(sf.rhs(fluid=fsharp, include_bc=False), tol=tol)
+    b2 = sf.rhs(fluid=fsharp, include_bc=False)
+    xs = sf.solve(b2, tol=tol)
     vsharp = xs[sf.sl_v]
 
     # 5. random finite differences
@@ -98,20 +113,22 @@ def sem_step(g: mac.Grid, r_ref, offsets, q, theta, FT, kT: float, dt: float, se
     slip2 = DK - DJ - DS
     if slip is not None:
         slip2 = slip2 + np.asarray(slip).reshape(-1, 3)
-    x = s0.solve(s0.rhs(FT=FT - DKT, slip=slip2, fluid=fluid, include_bc=True), tol=tol)
+    b3 = s0.rhs(FT=FT - DKT, slip=slip2, fluid=fluid, include_bc=True)
+    x = s0.solve(b3, tol=tol)
     U = s0.split(x)[3].copy()
 
     # 7. update and rejection test
     qn = q + dt * U[:, :3]
     thn = B.rotate(theta, dt * U[:, 3:])
     rn = B.marker_positions(qn, thn, r_ref, offsets)
-    ok = B.inside_open_domain(g, rn)
+    ok = displaced_inside and B.inside_open_domain(g, rn)
     if ok and min_body_dist > 0.0 and nb > 1:
         d = np.linalg.norm(qn[:, None, :] - qn[None, :, :], axis=2) + np.eye(nb) * 1e300
         ok = bool(d.min() >= min_body_dist)
     if not ok:
         qn, thn = q.copy(), theta.copy()
-    return SEMResult(ok, qn, thn, U, WFT, UR.copy(), lamR.copy(), DKT, DK, DJ, DS, x)
+    norms = tuple(float(np.linalg.norm(b)) for b in (b1, b2, b3))
+    return SEMResult(ok, qn, thn, U, WFT, UR.copy(), lamR.copy(), DKT, DK, DJ, DS, x, norms)
 
 
 def drift_pointwise(g: mac.Grid, r_ref, offsets, q, theta, kT: float, seed: int, step: int,

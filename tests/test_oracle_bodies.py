@@ -96,3 +96,30 @@ def test_tiles_stable_sort():
         assert tile[i] == t
     ref = sorted(range(300), key=lambda i: (tile[i], i))
     assert perm.tolist() == ref
+
+
+def test_K_rotation_sense_matches_marker_motion():
+    """(K U)_i must be the velocity with which marker i actually moves when body p
+    turns with angular velocity omega (Sec. II; K of Sec. III.B): the central
+    difference of r_i(q, Rotate(theta, +eps omega)) and r_i(q, Rotate(theta, -eps
+    omega)) over 2 eps equals K [0, omega] to O(eps^2).  Adjointness holds for either
+    sign of the cross product, and the K^T K closed form on a body with sum d = 0 does
+    not see it, so this is what fixes the rotation sense.  Bodies whose marker offsets
+    do not sum to zero (the sphere shifted off its tracking point) are included."""
+    rng = np.random.default_rng(7)
+    shapes = [W.icosphere42(2.5) + np.array([0.4, -0.2, 0.9]), W.icosahedron(1.5), W.icosahedron(1.0) * 0.7]
+    r_ref = np.vstack(shapes)
+    offs = np.array([0, 42, 54, 66])
+    q = rng.standard_normal((3, 3)) * 3.0
+    th = W.random_unit_quaternions(rng, 3)
+    omega = rng.standard_normal((3, 3))
+    eps = 1e-5
+    rp = B.marker_positions(q, B.rotate(th, eps * omega), r_ref, offs)
+    rm = B.marker_positions(q, B.rotate(th, -eps * omega), r_ref, offs)
+    vel = (rp - rm) / (2 * eps)
+    U = np.concatenate([np.zeros((3, 3)), omega], axis=1)
+    KU = B.apply_K(th, r_ref, offs, U)
+    assert np.abs(vel - KU).max() < 1e-8 * np.abs(KU).max()
+    # a translation moves every marker of its body rigidly
+    U = np.concatenate([rng.standard_normal((3, 3)), np.zeros((3, 3))], axis=1)
+    assert np.abs(B.apply_K(th, r_ref, offs, U) - U[B.body_of_marker(offs), :3]).max() == 0.0

@@ -195,3 +195,52 @@ def test_moving_wall_rhs():
     assert np.allclose(ux[0], 2 * 2.0 * 0.5)
     assert np.allclose(ux[1:], 0.0)
     assert np.allclose(g.compact_to_padded(r)[1:], 0.0)
+
+
+@pytest.mark.parametrize("wall_axis,comp", [(2, 0), (1, 2), (0, 1)])
+def test_plane_couette_closed_form(wall_axis, comp):
+    """Plane Couette flow: walls normal to `wall_axis` sliding with tangential
+    velocities U_lo and U_hi along `comp`, the other two axes periodic, no body.  With
+    the tangential ghost u_g = 2 U_w - u (Sec. III.A; the sliding wall of the monolayer,
+    Sec. VI) the linear profile U_lo + (U_hi - U_lo) x / L at the face centres is the
+    exact discrete solution: its second differences vanish inside, and its value at the
+    mirror point of the first cell is exactly 2 U_w minus its value in that cell.  So
+    the affine right-hand side from the sliding walls must reproduce it to round-off,
+    with no cross flow and a uniform pressure; and interpolation with the sliding-wall
+    term J_bc (Sec. III.B) returns the same line at every marker, wall neighbours
+    included, because the 4-point kernel reproduces linear functions."""
+    from oracle import ib
+    n = [4, 4, 4]
+    n[wall_axis] = 12
+    bc = [mac.PERIODIC] * 3
+    bc[wall_axis] = mac.WALL
+    h, eta = 0.5, 1.7
+    Ulo, Uhi = 0.8, -0.3
+    wv = np.zeros((3, 2, 3))
+    wv[wall_axis, 0, comp] = Ulo
+    wv[wall_axis, 1, comp] = Uhi
+    g = mac.Grid(tuple(n), tuple(bc), h=h, eta=eta, wall_vel=wv)
+    s = saddle.Saddle(g, np.zeros((0, 3)), np.zeros((0, 4)), np.zeros((0, 3)), np.zeros(1, dtype=int),
+                      fluid_only=True)
+    x = s.solve_direct(s.rhs(include_bc=True))
+    v = g.compact_to_padded(x[s.sl_v]).reshape(3, n[2], n[1], n[0])
+    L = n[wall_axis] * h
+    coord = (np.arange(n[wall_axis]) + 0.5) * h
+    line = Ulo + (Uhi - Ulo) * coord / L
+    shape = [1, 1, 1]
+    shape[2 - wall_axis] = n[wall_axis]
+    assert np.abs(v[comp] - line.reshape(shape)).max() < 1e-12
+    for c in range(3):
+        if c != comp:
+            assert np.abs(v[c]).max() < 1e-12
+    p = x[s.sl_p]
+    assert np.abs(p - p.mean()).max() < 1e-11
+    # interpolation with the affine wall term reproduces the line at markers anywhere
+    rng = np.random.default_rng(4)
+    r = rng.uniform(0.02, 0.98, size=(40, 3)) * np.array(n) * h
+    r[:5, wall_axis] = rng.uniform(0.01, 0.3, 5) * h          # next to the lower wall
+    r[5:10, wall_axis] = L - rng.uniform(0.01, 0.3, 5) * h    # next to the upper wall
+    Jv = (ib.interpolation(g, r) @ x[s.sl_v]).reshape(-1, 3) + ib.interpolation_bc(g, r)
+    expect = Ulo + (Uhi - Ulo) * r[:, wall_axis] / L
+    assert np.abs(Jv[:, comp] - expect).max() < 1e-12
+    assert np.abs(np.delete(Jv, comp, axis=1)).max() < 1e-12

@@ -15,7 +15,7 @@ import numpy as np
 
 import workloads as W
 from oracle import bodies as B
-from oracle import mac, sem
+from oracle import mac, rng, sem
 from oracle.saddle import Saddle
 
 
@@ -70,3 +70,95 @@ def test_rejection_leaves_state():
     res = sem.sem_step(g, w.r_ref, w.offsets, q, w.theta, F * 0, kT=1.0, dt=1e-3, seed=1, step=0)
     assert res.accepted
     assert not np.array_equal(res.q, q)
+
+
+def _kT_div_N(g, w, kT, eps=1e-4):
+    """kT times the divergence of the body mobility with respect to the configuration,
+    sum_k d N_{:,k} / d Q_k, by central differences of single columns of the dense N
+    (translations of q_p, and lab-frame rotation vectors of theta_p)."""
+    nb = w.nb
+    div = np.zeros(6 * nb)
+    for k in range(6 * nb):
+        p, a = divmod(k, 6)
+        cols = []
+        for sgn in (1.0, -1.0):
+            dq = np.zeros((nb, 3))
+            dphi = np.zeros((nb, 3))
+            if a < 3:
+                dq[p, a] = sgn * eps
+            else:
+                dphi[p, a - 3] = sgn * eps
+            s = Saddle(g, w.q + dq, B.rotate(w.theta, dphi), w.r_ref, w.offsets)
+            e = np.zeros(6 * nb)
+            e[k] = 1.0
+            x = s.solve(s.rhs(FT=e.reshape(nb, 6), include_bc=False))
+            cols.append(s.split(x)[3].ravel())
+        div += (cols[0] - cols[1]) / (2 * eps)
+    return kT * div
+
+
+def test_mean_drift_equals_kT_div_N():
+    """The mean of the random-finite-difference drift is kT div_Q N (Sec. IV, eqs. RFD
+    and DriDef), independent of how the random force W^FT and the displacement of
+    Q+- are scaled individually -- only their product is fixed.  With no deterministic
+    force and no fluid noise, the velocity a step returns is the drift alone, a
+    quadratic form in the 6 N_b body normals up to O(delta^2); the mean of a quadratic
+    form in standard normals is its trace, which the cubature sum over the unit
+    vectors W = e_k evaluates exactly.  Two bodies near walls and each other, kT != 1,
+    so that a wrong kT, L_p or delta/2 factor, or a dropped cross-body term, fails."""
+    w = W.small_box(7, n=(6, 8, 10), n_bodies=2, R=1.0, shape="ico12", gap=0.7)
+    g = mac.Grid(w.n, w.bc, w.h, w.eta)
+    kT = 2.5
+    ref = _kT_div_N(g, w, kT)
+    zero = np.zeros((w.nb, 6))
+    mean = np.zeros(6 * w.nb)
+    for k in range(6 * w.nb):
+        e = np.zeros(6 * w.nb)
+        e[k] = 1.0
+        e = e.reshape(w.nb, 6)
+        res = sem.sem_step(g, w.r_ref, w.offsets, w.q, w.theta, zero, kT=kT, dt=0.01, seed=5, step=0,
+                           delta=1e-4, noise=False, normals=(e[:, :3], e[:, 3:]))
+        mean += res.U.ravel()
+    assert np.abs(mean - ref).max() < 1e-5 * np.abs(ref).max()
+    # the drift is not small against its own derivative scale: every body moves
+    assert np.all(np.abs(ref.reshape(2, 6)[:, :3]).max(axis=1) > 1e-4)
+
+
+def test_mean_drift_statistical():
+    """The same mean over the step's own Philox draws (W^f, W^tau independent
+    standard normals): the sample mean of the drift lies within 3 standard errors of
+    kT div_Q N in every component.  This exercises the random-number path that the
+    cubature check bypasses."""
+    w = W.small_box(7, n=(6, 6, 8), n_bodies=1, R=1.0, shape="ico12", gap=0.7)
+    g = mac.Grid(w.n, w.bc, w.h, w.eta)
+    kT = 2.5
+    ref = _kT_div_N(g, w, kT)
+    zero = np.zeros((1, 6))
+    n = 120
+    S = np.array([sem.sem_step(g, w.r_ref, w.offsets, w.q, w.theta, zero, kT=kT, dt=0.01, seed=5, step=k,
+                               delta=1e-4, noise=False).U.ravel() for k in range(n)])
+    z = (S.mean(axis=0) - ref) / (S.std(axis=0, ddof=1) / np.sqrt(n))
+    assert np.all(np.abs(z) < 3.0), z
+
+
+def test_rejection_on_displaced_configurations():
+    """A step whose displaced configuration Q+ or Q- (the random finite difference
+    around Q^n) puts a marker outside the fluid is rejected, even when Q^n and Q^{n+1}
+    are inside: S and J are not defined there.  A lowest marker 1e-3 h above the wall
+    with delta = 0.1 moves by about 0.15 |W^f_z| h, so one of Q+- leaves the domain."""
+    w = W.small_box(2, n=(8, 8, 8), n_bodies=1, R=1.5, shape="ico12")
+    g = mac.Grid(w.n, w.bc, w.h, w.eta)
+    r0 = B.marker_positions(w.q, w.theta, w.r_ref, w.offsets)
+    q = w.q.copy()
+    q[0, 2] += 1e-3 - r0[:, 2].min()
+    zero = np.zeros((1, 6))
+    res = sem.sem_step(g, w.r_ref, w.offsets, q, w.theta, zero, kT=1.0, dt=1e-6, seed=3, step=0, delta=0.1,
+                       noise=False)
+    Wf, _ = rng.body_normals(3, 0, 1)
+    assert abs(Wf[0, 2]) > 0.05                  # the draw does push one side through the wall
+    assert not res.accepted
+    assert np.array_equal(res.q, q) and np.array_equal(res.theta, w.theta)
+    # the same configuration with a small delta keeps Q+- inside and is accepted
+    res = sem.sem_step(g, w.r_ref, w.offsets, q, w.theta, zero, kT=1.0, dt=1e-6, seed=3, step=0, delta=1e-6,
+                       noise=False)
+    assert res.accepted
