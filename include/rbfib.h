@@ -31,10 +31,11 @@
  *  * All array arguments are DEVICE pointers owned by the caller, FP64,
  *    contiguous, row-major, unless a comment says "host".  The library never
  *    frees caller memory.  A context owns all workspace it allocates.
- *  * Work is enqueued on the HIP stream given at creation.  Entry points that
- *    return convergence or rejection information synchronise that stream
- *    before returning; rbfib_apply_saddle, rbfib_markers and
- *    rbfib_fluctuating_stress are asynchronous.
+ *  * Work is enqueued on the HIP stream given at creation.  Every entry point
+ *    that takes orientations checks them on the device and reads the result
+ *    back, and those that return convergence or rejection information wait
+ *    for their results, so all of these synchronise that stream before
+ *    returning; rbfib_fluctuating_stress is asynchronous.
  *  * Quaternions are scalar first (w, x, y, z).  Body arrays are [nb, 3]
  *    (q), [nb, 4] (theta), [nb, 6] (forces/torques or velocities [u, omega]).
  *    Marker arrays are [nm, 3].
@@ -54,7 +55,9 @@
  * ------
  * Every int-returning call returns RBFIB_OK (0) or a negative code:
  *   RBFIB_EINVAL   bad argument (sizes, no wall axis, periodic axis not a
- *                  multiple of 4, too few cells, NULL pointer, bad options);
+ *                  multiple of 4, too few cells, NULL pointer, bad options,
+ *                  an orientation theta_p with | |theta_p| - 1 | > 1e-12 or
+ *                  not finite -- Sec. II requires unit quaternions);
  *   RBFIB_EREJECT  unphysical configuration: a marker outside the open domain
  *                  along a wall axis, or body centres closer than
  *                  opts.min_body_dist (the paper rejects and repeats such
@@ -249,8 +252,11 @@ int rbfib_mobility_vjp(rbfib_ctx *ctx, const double *q, const double *theta, con
  * sweep (separate kernels), 2 = level-0 fused down kernel (two sweeps, residual,
  * restriction), 3 = level-0 fused up kernel (prolongation, two sweeps),
  * 4 = FGMRES dot products of the basis with w (the dot kernel and its reduction),
- * 5 = FGMRES basis update of w with its norm.  Only solves run with timing enabled
- * (rbfib_enable_timing) are counted. */
+ * 5 = FGMRES basis update of w with its norm, 6 = spreading -S lambda of the
+ * apply (bytes: read-modify-write of the three FP64 velocity components on every
+ * cell of every target tile, plus each marker's position and lambda).  Only solves
+ * run with timing enabled (rbfib_enable_timing) are counted; a timing run reads
+ * the active-tile count back before each timed spreading launch. */
 int rbfib_kernel_stats(rbfib_ctx *ctx, int which, double *avg_ms, double *bytes_per_launch,
                        long long *launches);
 int rbfib_enable_timing(rbfib_ctx *ctx, int on);

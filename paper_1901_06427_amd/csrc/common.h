@@ -28,8 +28,8 @@
 // A level runs fused only with at least this many workgroups (each marches
 // through its z planes, so it needs several resident workgroups per CU).
 #define MGF_MIN_BLOCKS 1024
-#define RB_NTIMING 6           // timing classes: apply, smoother sweep, fused down, fused up (level 0),
-                               // Krylov dots, Krylov update
+#define RB_NTIMING 7           // timing classes: apply, smoother sweep, fused down, fused up (level 0),
+                               // Krylov dots, Krylov update, spreading of the apply
 // LDS-resident bottom of the V-cycle: workgroup size and the largest LDS budget
 // per workgroup an option may ask for
 #define MGB_THREADS 256
@@ -59,6 +59,29 @@ struct RepDev {
     double wv[3][2][3];
     double inv_n0, inv_n01;   // 1/nx and 1/(nx*ny) for exact index splitting
 };
+
+// Descriptor of one replica with grid g and nb bodies of nm markers, its state at
+// offset off, its first body, marker and tile b0, m0, tile0 (multigrid fields unset).
+inline void rep_from_grid(RepDev &R, const rbfib_grid &g, int nb, int nm, long long off, int b0, int m0, int tile0) {
+    R = RepDev();
+    for (int a = 0; a < 3; ++a) { R.n[a] = g.n[a]; R.bc[a] = g.bc[a]; R.tdim[a] = (g.n[a] + RB_TILE - 1) / RB_TILE; }
+    R.h = g.h; R.inv_h = 1.0 / g.h; R.eta = g.eta; R.dV = g.h * g.h * g.h;
+    R.N = (long long)g.n[0] * g.n[1] * g.n[2];
+    R.inv_n0 = 1.0 / g.n[0];
+    R.inv_n01 = 1.0 / ((double)g.n[0] * g.n[1]);
+    R.nb = nb; R.nm = nm; R.b0 = b0; R.m0 = m0;
+    R.off = off;
+    R.len = 4 * R.N + 3LL * nm + 6LL * nb;
+    R.tile0 = tile0;
+    R.movwall = 0;
+    for (int a = 0; a < 3; ++a)
+        for (int s = 0; s < 2; ++s)
+            for (int k = 0; k < 3; ++k) {
+                const double v = (g.bc[a] == RBFIB_WALL && k != a) ? g.wall_vel[a][s][k] : 0.0;
+                R.wv[a][s][k] = v;
+                if (v != 0.0) R.movwall = 1;
+            }
+}
 
 struct LevDev {
     int n[3];
@@ -431,8 +454,6 @@ struct MarkerSet {
     // spreading pairs (target tile, marker), by tile then marker id; capacity pair_cap
     int *pair_count = nullptr, *pair_start = nullptr, *pair_fill = nullptr;   // [ntiles]
     int *pair_m = nullptr, *pair_tile = nullptr;                              // [pair_cap]
-    double *pair_w = nullptr;      // [pair_cap][3 comp][3 axis][4] weights on the tile's window
-    long long *pair_lam = nullptr; // [pair_cap] offset of the marker's lambda in a state vector
     long long pair_cap = 0;
     double *wc = nullptr;     // [nm][3 comp][3 axis][4] folded signed 1-D kernel weights
     int *ic = nullptr;        // [nm][3][3][4] folded grid indices of those weights
@@ -566,7 +587,7 @@ void launch_noise(Ctx &c, double kT, double dt, uint64_t seed, uint64_t step, do
 void launch_wall_rhs(Ctx &c, double *f);
 
 // immersed boundary and bodies (ib.hip)
-void launch_markers(Ctx &c, MarkerSet &ms, const double *q, const double *theta);
+void launch_markers(Ctx &c, MarkerSet &ms, const double *q, const double *theta, bool counts_zeroed = false);
 template <typename TL> void launch_spread(Ctx &c, MarkerSet &ms, const TL *lam, double *y, double alpha);
 template <typename T, typename TL>
 void launch_spread_level0(Ctx &c, MarkerSet &ms, const TL *lam, T *pool, double alpha);

@@ -44,6 +44,10 @@ __global__ void k_markers(const RepDev *reps, const int *marker_body, const int 
     const RepDev &R = reps[body_rep[p]];
     double d[3], r[3];
     marker_pos(q + 3 * p, theta + 4 * p, rref + 3 * m, d, r);
+    // orientations must be unit quaternions to 1e-12 (bit 3 of the replica's flags)
+    const double *th = theta + 4 * p;
+    const double qn = sqrt(th[0] * th[0] + th[1] * th[1] + th[2] * th[2] + th[3] * th[3]);
+    if (!(fabs(qn - 1.0) <= 1e-12)) atomicOr(&flags[body_rep[p]], 8);
     int cell[3];
     bool outside = false;
     for (int a = 0; a < 3; ++a) {
@@ -262,48 +266,13 @@ __global__ void k_pair_tiles(const RepDev *reps, const int *marker_body, const i
     if (over) atomicOr(&flags[rep], 1);
 }
 
-// Folded weights of each pair on its tile's window, [pair][component][axis][4], and
-// the offset of the marker's lambda in a state vector.
-__global__ void k_pair_weights(const RepDev *reps, const int *tile_rep, const double *wc, const int *ic,
-                               const int *pair_start, const int *pair_count, int ntiles, const int *pair_m,
-                               const int *pair_tile, long long cap, double *pair_w, long long *pair_lam) {
-    const long long s = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-    const long long total = (long long)pair_start[ntiles - 1] + pair_count[ntiles - 1];
-    if (s >= total || s >= cap) return;
-    const int t = pair_tile[s], m = pair_m[s];
-    const RepDev &R = reps[tile_rep[t]];
-    const int lt = t - R.tile0;
-    const int tc0 = lt % R.tdim[0], tc1 = (lt / R.tdim[0]) % R.tdim[1], tc2 = lt / (R.tdim[0] * R.tdim[1]);
-#pragma unroll
-    for (int c = 0; c < 3; ++c)
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            const int w0 = RB_TILE * (a == 0 ? tc0 : (a == 1 ? tc1 : tc2));
-            const long long o = ((long long)(3 * m + c) * 3 + a) * 4;
-            double o0 = 0.0, o1 = 0.0, o2 = 0.0, o3 = 0.0;
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const double w = wc[o + q];
-                const int loc = ic[o + q] - w0;
-                if (w != 0.0) {
-                    if (loc == 0) o0 += w;
-                    else if (loc == 1) o1 += w;
-                    else if (loc == 2) o2 += w;
-                    else if (loc == 3) o3 += w;
-                }
-            }
-            double *dst = pair_w + s * 36 + (c * 3 + a) * 4;
-            dst[0] = o0;
-            dst[1] = o1;
-            dst[2] = o2;
-            dst[3] = o3;
-        }
-    pair_lam[s] = R.off + 4 * R.N + 3LL * (m - R.m0);
-}
-
-void launch_markers(Ctx &c, MarkerSet &ms, const double *q, const double *theta) {
-    HIP_OK(hipMemsetAsync(ms.tile_count, 0, sizeof(int) * c.ntiles, c.stream));
-    HIP_OK(hipMemsetAsync(ms.pair_count, 0, sizeof(int) * c.ntiles, c.stream));
+// counts_zeroed: the caller has already cleared tile_count and pair_count (the
+// allocation-free entry point does it in its set-up kernel instead of a memset).
+void launch_markers(Ctx &c, MarkerSet &ms, const double *q, const double *theta, bool counts_zeroed) {
+    if (!counts_zeroed) {
+        HIP_OK(hipMemsetAsync(ms.tile_count, 0, sizeof(int) * c.ntiles, c.stream));
+        HIP_OK(hipMemsetAsync(ms.pair_count, 0, sizeof(int) * c.ntiles, c.stream));
+    }
     int nb = (c.nm + 255) / 256;
     if (c.nm > 0)
         hipLaunchKernelGGL(k_markers, dim3(nb), dim3(256), 0, c.stream, c.d_reps, c.d_marker_body, c.d_body_rep, q,
@@ -325,29 +294,33 @@ void launch_markers(Ctx &c, MarkerSet &ms, const double *q, const double *theta)
                            ms.pair_tile, ms.pair_cap, c.d_flags);
         hipLaunchKernelGGL(k_tile_sort, dim3((c.ntiles + 255) / 256), dim3(256), 0, c.stream, ms.pair_start,
                            ms.pair_count, ms.pair_m, c.ntiles, ms.pair_cap);
-        hipLaunchKernelGGL(k_pair_weights, dim3((unsigned)((ms.pair_cap + 255) / 256)), dim3(256), 0, c.stream,
-                           c.d_reps, c.d_tile_rep, ms.wc, ms.ic, ms.pair_start, ms.pair_count, c.ntiles, ms.pair_m,
-                           ms.pair_tile, ms.pair_cap, ms.pair_w, ms.pair_lam);
     }
     compact_tiles(c, ms.pair_count, ms.active, ms.n_active);
 }
 
 // ------------------------------------------------------------------ spreading (gather)
-// One wavefront per tile that has pairs, one lane per (x, y, z) position of the
-// tile: the lane sums, for the three velocity components at once, the tensor-product
-// weights times lambda over the tile's pairs in marker order (no atomics, fixed
-// summation order).  A wave per tile keeps many tiles in flight: the work per tile
-// is small and its chain of dependent loads sets the time.
+// One wavefront per tile that has pairs, one lane per (x, y, z) cell of the tile.  The
+// tile's pairs are taken SPREAD_P at a time: lane i loads the cached folded 1-D
+// weights of pair i's marker (3 components x 3 axes x 4 points, with their folded
+// indices) and its lambda, projects them onto the tile's 4-cell window on each axis
+// (several support points can fold onto one cell next to a wall), folds lambda_c into
+// the z factor, and leaves the 36 window weights in LDS; then every lane sums, for the
+// three velocity components at once, the tensor-product weights of its cell over the
+// staged pairs in marker order.  All loads of a round are independent, so a tile costs
+// one round of latency per SPREAD_P pairs; the sum order is fixed (no atomics), so the
+// result is deterministic.
 // TO = double: y is a state vector (velocity of replica r at R.off + c N);
 // with levs given: y is a multigrid pool, level 0 of each replica.
+#define SPREAD_P 32
 template <typename TO, typename TL>
 __global__ __launch_bounds__(64) void k_spread(const RepDev *reps, const int *tile_rep, const int *active,
                                                const int *n_active, const int *pair_start, const int *pair_count,
-                                               long long cap, const double *__restrict__ pair_w,
-                                               const long long *__restrict__ pair_lam,
+                                               long long cap, const int *__restrict__ pair_m,
+                                               const double *__restrict__ wc, const int *__restrict__ ic,
                                                const TL *__restrict__ lam_state, TO *__restrict__ y,
                                                double alpha, const int *__restrict__ mask,
                                                const LevDev *__restrict__ levs) {
+    __shared__ double sw[SPREAD_P * 36];
     const int lane = threadIdx.x;
     const int lx = lane & 3, ly = (lane >> 2) & 3, lz = lane >> 4;
     const int na = *n_active;
@@ -356,28 +329,56 @@ __global__ __launch_bounds__(64) void k_spread(const RepDev *reps, const int *ti
         const int rep = tile_rep[t];
         if (mask && !mask[rep]) continue;
         const RepDev &R = reps[rep];
+        const int lt = t - R.tile0;
+        const int org[3] = {RB_TILE * (lt % R.tdim[0]), RB_TILE * ((lt / R.tdim[0]) % R.tdim[1]),
+                            RB_TILE * (lt / (R.tdim[0] * R.tdim[1]))};
         const long long s0 = pair_start[t];
         const long long s1 = min(s0 + (long long)pair_count[t], cap);
-        double acc[3] = {0.0, 0.0, 0.0};
-#pragma unroll 2
-        for (long long s = s0; s < s1; ++s) {
-            const double *w = pair_w + s * 36;
-            const TL *lam = lam_state + pair_lam[s];
+        double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0;
+        for (long long base = s0; base < s1; base += SPREAD_P) {
+            const int cnt = (int)min((long long)SPREAD_P, s1 - base);
+            if (lane < cnt) {
+                const int m = pair_m[base + lane];
+                const TL *lam = lam_state + R.off + 4 * R.N + 3LL * (m - R.m0);
+                double *dst = sw + lane * 36;
 #pragma unroll
-            for (int c = 0; c < 3; ++c)
-                acc[c] += w[12 * c + lx] * w[12 * c + 4 + ly] * w[12 * c + 8 + lz] * (double)lam[c];
+                for (int c = 0; c < 3; ++c) {
+                    const double lc = (double)lam[c];
+#pragma unroll
+                    for (int a = 0; a < 3; ++a) {
+                        const long long o = ((long long)(3 * m + c) * 3 + a) * 4;
+                        const double2 w01 = *reinterpret_cast<const double2 *>(wc + o);
+                        const double2 w23 = *reinterpret_cast<const double2 *>(wc + o + 2);
+                        const int4 ix = *reinterpret_cast<const int4 *>(ic + o);
+                        const double w[4] = {w01.x, w01.y, w23.x, w23.y};
+                        const int loc[4] = {ix.x - org[a], ix.y - org[a], ix.z - org[a], ix.w - org[a]};
+#pragma unroll
+                        for (int k = 0; k < 4; ++k) {
+                            double v = 0.0;
+#pragma unroll
+                            for (int q = 0; q < 4; ++q) v += (loc[q] == k) ? w[q] : 0.0;
+                            dst[(c * 3 + a) * 4 + k] = (a == 2) ? v * lc : v;
+                        }
+                    }
+                }
+            }
+            __syncthreads();
+            for (int p = 0; p < cnt; ++p) {
+                const double *w = sw + p * 36;
+                acc0 += w[lx] * w[4 + ly] * w[8 + lz];
+                acc1 += w[12 + lx] * w[16 + ly] * w[20 + lz];
+                acc2 += w[24 + lx] * w[28 + ly] * w[32 + lz];
+            }
+            __syncthreads();
         }
-        const int lt = t - R.tile0;
-        const int g0 = RB_TILE * (lt % R.tdim[0]) + lx;
-        const int g1 = RB_TILE * ((lt / R.tdim[0]) % R.tdim[1]) + ly;
-        const int g2 = RB_TILE * (lt / (R.tdim[0] * R.tdim[1])) + lz;
+        const int g0 = org[0] + lx, g1 = org[1] + ly, g2 = org[2] + lz;
         if (g0 < R.n[0] && g1 < R.n[1] && g2 < R.n[2]) {
             const long long lin = (long long)g0 + (long long)R.n[0] * ((long long)g1 + (long long)R.n[1] * g2);
             const long long o = levs ? levs[rep * RB_MAXLEV].off : R.off;
-            const int gc[3] = {g0, g1, g2};
-#pragma unroll
-            for (int c = 0; c < 3; ++c)
-                if (!(R.bc[c] == RBFIB_WALL && gc[c] == 0)) y[o + c * R.N + lin] += (TO)(alpha * acc[c] / R.dV);
+            const double sc = alpha / R.dV;
+            if (!(R.bc[0] == RBFIB_WALL && g0 == 0)) y[o + lin] += (TO)(sc * acc0);
+            if (!(R.bc[1] == RBFIB_WALL && g1 == 0)) y[o + R.N + lin] += (TO)(sc * acc1);
+            if (!(R.bc[2] == RBFIB_WALL && g2 == 0)) y[o + 2 * R.N + lin] += (TO)(sc * acc2);
         }
     }
 }
@@ -387,8 +388,8 @@ static void spread_into(Ctx &c, MarkerSet &ms, const TL *lam_state, TO *y, doubl
     if (c.nm == 0) return;
     int grid = std::min(c.ntiles, 65536);   // grid-stride over the tiles that have pairs
     hipLaunchKernelGGL((k_spread<TO, TL>), dim3(grid), dim3(64), 0, c.stream, c.d_reps, c.d_tile_rep, ms.active,
-                       ms.n_active, ms.pair_start, ms.pair_count, ms.pair_cap, ms.pair_w, ms.pair_lam, lam_state, y,
-                       alpha, c.mask, levs);
+                       ms.n_active, ms.pair_start, ms.pair_count, ms.pair_cap, ms.pair_m, ms.wc, ms.ic, lam_state,
+                       y, alpha, c.mask, levs);
 }
 
 // y_fluid += alpha * S lambda, lambda read from the lambda slots of lam_state.

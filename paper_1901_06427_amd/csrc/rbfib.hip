@@ -196,6 +196,17 @@ static void record(Ctx &c, int cls, bool start, double bytes = 0.0) {
     }
 }
 
+// Algorithmic bytes of one spreading pass into a state vector (timing runs only; reads
+// the active-tile count back): the read-modify-write of the three FP64 velocity
+// components on every cell of every target tile, plus each marker's position and
+// lambda (lam_size bytes per value).
+static double spread_bytes(Ctx &c, MarkerSet &ms, size_t lam_size) {
+    int na = 0;
+    HIP_OK(hipMemcpyAsync(&na, ms.n_active, sizeof(int), hipMemcpyDeviceToHost, c.stream));
+    HIP_OK(hipStreamSynchronize(c.stream));
+    return (double)na * 64.0 * 3.0 * 16.0 + (double)c.nm * (24.0 + 3.0 * lam_size);
+}
+
 // y = A x; x is FP64, or FP32 for the preconditioned vectors of an FP32 preconditioner
 template <typename TX>
 static void apply_op(Ctx &c, MarkerSet &ms, const TX *x, double *y, bool fluid_only) {
@@ -206,7 +217,10 @@ static void apply_op(Ctx &c, MarkerSet &ms, const TX *x, double *y, bool fluid_o
         launch_zero_bodies(c, y);
         return;
     }
+    const double sb = c.timing.on ? spread_bytes(c, ms, sizeof(TX)) : 0.0;   // before the events
+    record(c, 6, true);
     launch_spread(c, ms, x, y, -1.0);
+    record(c, 6, false, sb);
     launch_body_apply(c, ms, nullptr, x, y);
 }
 
@@ -562,8 +576,9 @@ static int first_bad(const std::vector<rbfib_info> &info) {
     return RBFIB_OK;
 }
 
-// Per-replica rejection flags (bit 0: a marker outside the open domain along a wall
-// axis, bit 1: two body centres closer than opts.min_body_dist).
+// Per-replica flags (bit 0: a marker outside the open domain along a wall axis,
+// bit 1: two body centres closer than opts.min_body_dist, bit 2: a solve of the step
+// failed, bit 3: an orientation that is not a unit quaternion to 1e-12).
 static void clear_flags(Ctx &c) { HIP_OK(hipMemsetAsync(c.d_flags, 0, sizeof(int) * c.nrep, c.stream)); }
 
 static bool read_flags(Ctx &c) {
@@ -574,12 +589,24 @@ static bool read_flags(Ctx &c) {
     return any;
 }
 
-// markers at (q, theta) into ms; returns RBFIB_EREJECT when a marker leaves the domain.
-static int build_markers(Ctx &c, MarkerSet &ms, const double *q, const double *theta, bool check) {
+// Markers at (q, theta) into ms.  Caller-supplied configurations are validated:
+// RBFIB_EINVAL when an orientation is not a unit quaternion to 1e-12, and with
+// check_domain RBFIB_EREJECT when a marker lies outside the open domain along a wall
+// axis.  Both read the flags back, so they synchronise the stream.
+static int build_markers(Ctx &c, MarkerSet &ms, const double *q, const double *theta, bool check_domain) {
     clear_flags(c);
     launch_markers(c, ms, q, theta);
-    if (!check) return RBFIB_OK;
-    return read_flags(c) ? RBFIB_EREJECT : RBFIB_OK;
+    if (c.nb == 0 || !read_flags(c)) return RBFIB_OK;
+    bool inval = false, outside = false;
+    for (int r = 0; r < c.nrep; ++r) {
+        inval |= (c.h_flags[r] & 8) != 0;
+        outside |= (c.h_flags[r] & 1) != 0;
+    }
+    if (inval) {
+        g_last_error = "an orientation is not a unit quaternion to 1e-12";
+        return RBFIB_EINVAL;
+    }
+    return (check_domain && outside) ? RBFIB_EREJECT : RBFIB_OK;
 }
 
 __global__ void k_add_lambda_bc(const RepDev *reps, const int *marker_body, const int *body_rep, int nm,
@@ -618,9 +645,11 @@ static int sem_step(Ctx &c, double *q, double *theta, const double *FT, const do
     const double delta = c.opts.rfd_delta;
     out.assign(c.nrep, rbfib_info{0, 0.0, RBFIB_OK});
     // configuration Q^n must be valid
-    if (build_markers(c, c.ms[0], q, theta, true) != RBFIB_OK) {
-        for (int r = 0; r < c.nrep; ++r) if (c.h_flags[r]) out[r].status = RBFIB_EREJECT;
-        return RBFIB_EREJECT;
+    const int st0 = build_markers(c, c.ms[0], q, theta, true);
+    if (st0 != RBFIB_OK) {
+        for (int r = 0; r < c.nrep; ++r)
+            if (c.h_flags[r]) out[r].status = (c.h_flags[r] & 8) ? RBFIB_EINVAL : RBFIB_EREJECT;
+        return st0;
     }
     std::vector<rbfib_info> inf;
     const double *th_solve = stage_theta(c, theta);
@@ -726,27 +755,11 @@ static void build(Ctx &c, int nrep, const rbfib_grid *grids, const rbfib_bodies 
         const rbfib_bodies &bd = bodies[r];
         RepDev &R = c.reps[r];
         memset(&R, 0, sizeof(R));
-        for (int a = 0; a < 3; ++a) { R.n[a] = g.n[a]; R.bc[a] = g.bc[a]; R.tdim[a] = (g.n[a] + RB_TILE - 1) / RB_TILE; }
-        R.h = g.h; R.inv_h = 1.0 / g.h; R.eta = g.eta; R.dV = g.h * g.h * g.h;
-        R.N = (long long)g.n[0] * g.n[1] * g.n[2];
-        R.inv_n0 = 1.0 / g.n[0];
-        R.inv_n01 = 1.0 / ((double)g.n[0] * g.n[1]);
-        R.nb = bd.nb; R.nm = bd.nm; R.b0 = b0; R.m0 = m0;
-        R.off = off;
-        R.len = 4 * R.N + 3LL * bd.nm + 6LL * bd.nb;
+        rep_from_grid(R, g, bd.nb, bd.nm, off, b0, m0, t0);
         off += R.len;
-        R.tile0 = t0;
         int nt = R.tdim[0] * R.tdim[1] * R.tdim[2];
         for (int t = 0; t < nt; ++t) tile_rep.push_back(r);
         t0 += nt;
-        R.movwall = 0;
-        for (int a = 0; a < 3; ++a)
-            for (int s = 0; s < 2; ++s)
-                for (int k = 0; k < 3; ++k) {
-                    double v = (g.bc[a] == RBFIB_WALL && k != a) ? g.wall_vel[a][s][k] : 0.0;
-                    R.wv[a][s][k] = v;
-                    if (v != 0.0) R.movwall = 1;
-                }
         for (int p = 0; p < bd.nb; ++p) {
             int n = bd.marker_offset[p + 1] - bd.marker_offset[p];
             c.max_body_nm = std::max(c.max_body_nm, n);
@@ -1032,8 +1045,6 @@ static void build(Ctx &c, int nrep, const rbfib_grid *grids, const rbfib_bodies 
         ms.pair_fill = dalloc<int>(c.ntiles);
         ms.pair_m = dalloc<int>(pair_cap);
         ms.pair_tile = dalloc<int>(pair_cap);
-        ms.pair_w = dalloc<double>(36 * (size_t)pair_cap);
-        ms.pair_lam = dalloc<long long>(pair_cap);
         zero_device(c, ms.n_active, 1);
     }
     c.theta_int = dalloc<double>(4 * (size_t)std::max(c.nb, 1));
@@ -1124,8 +1135,7 @@ static void free_all(Ctx &c) {
         MarkerSet &ms = c.ms[k];
         F(ms.r); F(ms.d); F(ms.tile); F(ms.perm); F(ms.tile_count); F(ms.tile_start); F(ms.tile_fill);
         F(ms.active); F(ms.n_active); F(ms.wc); F(ms.ic);
-        F(ms.pair_count); F(ms.pair_start); F(ms.pair_fill); F(ms.pair_m); F(ms.pair_tile); F(ms.pair_w);
-        F(ms.pair_lam);
+        F(ms.pair_count); F(ms.pair_start); F(ms.pair_fill); F(ms.pair_m); F(ms.pair_tile);
     }
     F(c.d_flags); F(c.d_scan); F(c.d_count); F(c.d_active_len);
     if (c.h_flags) (void)hipHostFree(c.h_flags);
@@ -1295,7 +1305,8 @@ int rbfib_markers(rbfib_ctx *ctx, const double *q, const double *theta, double *
     Ctx &c = ctx->c;
     Session s(c);
     MarkerSet &ms = c.ms[0];
-    build_markers(c, ms, q, theta, false);
+    const int st = build_markers(c, ms, q, theta, false);
+    if (st != RBFIB_OK) return st;
     if (r && c.nm) HIP_OK(hipMemcpyAsync(r, ms.r, sizeof(double) * 3 * c.nm, hipMemcpyDeviceToDevice, c.stream));
     if (tile && c.nm) HIP_OK(hipMemcpyAsync(tile, ms.tile, sizeof(int) * c.nm, hipMemcpyDeviceToDevice, c.stream));
     if (perm && c.nm) {
@@ -1322,7 +1333,8 @@ int rbfib_apply_saddle(rbfib_ctx *ctx, const double *q, const double *theta, con
     GUARD_BEGIN
     Ctx &c = ctx->c;
     Session s(c);
-    build_markers(c, c.ms[0], q, theta, false);
+    const int st = build_markers(c, c.ms[0], q, theta, false);
+    if (st != RBFIB_OK) return st;
     apply_op(c, c.ms[0], x, y, false);
     return RBFIB_OK;
     GUARD_END
@@ -1333,7 +1345,8 @@ int rbfib_precondition(rbfib_ctx *ctx, const double *q, const double *theta, con
     GUARD_BEGIN
     Ctx &c = ctx->c;
     Session s(c);
-    build_markers(c, c.ms[0], q, theta, false);
+    const int st = build_markers(c, c.ms[0], q, theta, false);
+    if (st != RBFIB_OK) return st;
     precond(c, c.ms[0], stage_theta(c, theta), r, z, false);
     return RBFIB_OK;
     GUARD_END
