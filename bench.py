@@ -135,12 +135,24 @@ CHEBY = -1.0      # < 0: the library default
 EXTRA_OPTS = {}   # further rbfib_opts fields (--opt name=value)
 
 
-def run_gpu(ws, steps, warmup, fp32, seed=2024, timing=False, graphs=True):
+def lib_context(rb, ws, **opt_kw):
+    """A batched library context for workloads ws (the GPU leg builds its contexts
+    through the binding alone; nothing under oracle/ is imported here)."""
+    grids = [rb.make_grid(w.n, w.bc, w.h, w.eta, w.wall_vel) for w in ws]
+    opts = rb.rbfib_default_opts(**opt_kw)
+    return rb.rbfib_create_batch(grids, [w.r_ref for w in ws], [w.offsets for w in ws], opts)
+
+
+def run_gpu(ws, steps, warmup, fp32, seed=2024, timing=False, graphs=True, tol=None, keep_first_U=False):
+    """`steps` timed SEM launches after `warmup` untimed ones.  Replica r draws from
+    seed + r; launch k uses step counter k.  keep_first_U: the velocities of launch 0
+    (a warm-up launch from the initial configuration) are copied to the host after
+    it, outside the timed region."""
     import torch
     import paper_1901_06427_amd as rb
-    from tests.helpers import lib_context
     E = Ensemble(ws)
-    ctx = lib_context(rb, ws, tol=ws[0].tol, precond_fp32=fp32, use_graphs=int(graphs and not timing),
+    ctx = lib_context(rb, ws, tol=ws[0].tol if tol is None else tol, precond_fp32=fp32,
+                      use_graphs=int(graphs and not timing),
                       mg_fused=MG_FUSED, **({"restart": RESTART} if RESTART else {}),
                       **({"mg_sweeps": SWEEPS} if SWEEPS else {}), **({"mg_omega": OMEGA} if OMEGA else {}),
                       **({"mg_sweeps_p": PSWEEPS} if PSWEEPS else {}), **({"blob_radius": BLOB} if BLOB else {}),
@@ -158,8 +170,11 @@ def run_gpu(ws, steps, warmup, fp32, seed=2024, timing=False, graphs=True):
         iters += sum(i.iters for i in info)
         rejected += sum(1 for i in info if i.status == rb.RBFIB_EREJECT)
 
-    for _ in range(warmup):
+    first_U = None
+    for k in range(warmup):
         one()
+        if k == 0 and keep_first_U:
+            first_U = U.cpu().numpy().copy()
     iters = 0
     rejected = 0
     if timing:
@@ -173,21 +188,23 @@ def run_gpu(ws, steps, warmup, fp32, seed=2024, timing=False, graphs=True):
     stats = {}
     if timing:
         for which, name in ((0, "mac_saddle_apply"), (1, "mg_smooth_level0"), (2, "mg_down_level0"),
-                            (3, "mg_up_level0"), (4, "krylov_dots"), (5, "krylov_update")):
+                            (3, "mg_up_level0"), (4, "krylov_dots"), (5, "krylov_update"),
+                            (6, "spread")):
             avg_ms, nbytes, launches = rb.rbfib_kernel_stats(ctx, which)
             if launches:
                 stats[name] = (avg_ms, nbytes, launches)
     ctx.close()
     return {"seconds": t1 - t0, "steps": steps, "iters": iters, "rejected": rejected, "stats": stats,
-            "replicas": len(ws)}
+            "replicas": len(ws), "first_U": first_U}
 
 
-def run_plain(ws, warmup=1, seed=2024):
-    """The same replicas one at a time, FP64 preconditioner, one SEM step each."""
+def run_plain(ws, warmup=1, seed=2024, tol=None):
+    """The same replicas one at a time, FP64 preconditioner, one SEM step each (replica
+    k of the ensemble draws from seed + k, as in the batched launches)."""
     total = 0.0
     iters = 0
-    for w in ws:
-        r = run_gpu([w], 1, warmup, fp32=0, seed=seed, graphs=True)
+    for k, w in enumerate(ws):
+        r = run_gpu([w], 1, warmup, fp32=0, seed=seed + k, graphs=True, tol=tol)
         total += r["seconds"]
         iters += r["iters"]
     return {"seconds": total, "steps": len(ws), "iters": iters}
@@ -203,7 +220,9 @@ def _cpu_init():
 
 
 def _cpu_step(k, seed=2024):
-    """One oracle SEM step on replica k of the default ensemble (worker process)."""
+    """One oracle SEM step on replica k of the default ensemble (worker process), with
+    the random numbers the GPU's first launch draws for that replica (seed + k, step
+    counter 0) and the same forces; returns (k, U)."""
     global _CPU_ENS
     import workloads as W
     from oracle import mac, sem
@@ -212,28 +231,44 @@ def _cpu_step(k, seed=2024):
     w = _CPU_ENS[k]
     g = mac.Grid(w.n, w.bc, w.h, w.eta, w.wall_vel)
     F = soft_forces_np(w.q, float(w.radius[0]), w.n, w.h, w.kT)
-    sem.sem_step(g, w.r_ref, w.offsets, w.q, w.theta, F, w.kT, w.dt, seed, 0)
-    return k
+    res = sem.sem_step(g, w.r_ref, w.offsets, w.q, w.theta, F, w.kT, w.dt, seed + k, 0)
+    return k, res.U
 
 
 def run_cpu_baseline(n_replicas, budget_s=20.0):
     """The oracle's SEM step as it stands (FP64, solves to 1e-12), one single-threaded
     process per host core (at most 16), replicas taken in ensemble order until the
-    time budget is used.  Runs before anything touches the GPU."""
+    time budget is used.  Runs before anything touches the GPU.  Returns the oracle's
+    velocities of the replicas it finished (the reference for the GPU's error)."""
     import multiprocessing as mp
     cores = max(1, min(16, os.cpu_count() or 1))
     ctx = mp.get_context("spawn")
+    U = {}
     with ctx.Pool(cores, initializer=_cpu_init) as pool:
         pool.map(_cpu_step, [0] * cores, chunksize=1)       # import and build once per worker, untimed
         done = 0
         t0 = time.perf_counter()
-        for _ in pool.imap_unordered(_cpu_step, range(n_replicas), chunksize=1):
+        for k, Uk in pool.imap_unordered(_cpu_step, range(n_replicas), chunksize=1):
             done += 1
+            U[k] = Uk
             if time.perf_counter() - t0 > budget_s:
                 break
         t1 = time.perf_counter()
         pool.terminate()
-    return {"steps": done, "seconds": t1 - t0, "cores": cores}
+    return {"steps": done, "seconds": t1 - t0, "cores": cores, "U": U}
+
+
+def oracle_error(U_gpu, U_ref, ws):
+    """Largest and median over the replicas of max |U_gpu - U_oracle| / max |U_oracle|
+    (one SEM step, every velocity component of the replica's bodies)."""
+    if U_gpu is None or not U_ref:
+        return None
+    b0 = np.cumsum([0] + [w.nb for w in ws])
+    errs = []
+    for k, Ur in sorted(U_ref.items()):
+        Ug = U_gpu[b0[k]:b0[k + 1]]
+        errs.append(float(np.abs(Ug - Ur).max() / max(np.abs(Ur).max(), 1e-300)))
+    return {"max": float(max(errs)), "median": float(np.median(errs)), "replicas": len(errs)}
 
 
 def copy_ceiling():
@@ -340,6 +375,9 @@ def main():
     ap.add_argument("--plain-replicas", type=int, default=24, help="replicas timed one at a time")
     ap.add_argument("--two-spheres-steps", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--tight-tol", type=float, default=1e-9,
+                    help="second batched-vs-plain comparison at this tolerance (0: skip)")
+    ap.add_argument("--tight-steps", type=int, default=3, help="timed batched launches at the tight tolerance")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--copy-probe", action="store_true",
                     help="run one elementwise kernel reading and writing 256 MiB first (counter calibration)")
@@ -382,13 +420,14 @@ def main():
         sys.exit(2)
 
     cpu = None
+    cb = None
     if not args.no_cpu_baseline and not args.timing_only and not args.batched_only:
         cb = run_cpu_baseline(args.replicas, args.cpu_budget)
         cpu = {"value": round(2 * cb["steps"] / cb["seconds"], 4), "unit": "mobility solves/s",
                "cores": cb["cores"], "kind": "oracle",
                "sample": "one SEM step on each of %d ensemble replicas in ensemble order (FP64 oracle, solves "
-                         "to 1e-12), %d single-threaded processes, %.1f s" % (cb["steps"], cb["cores"],
-                                                                             cb["seconds"])}
+                         "to 1e-12, the random numbers of the GPU's first launch), %d single-threaded "
+                         "processes, %.1f s" % (cb["steps"], cb["cores"], cb["seconds"])}
         log("cpu oracle: %.3f solves/s on %d processes" % (cpu["value"], cb["cores"]))
 
     import torch
@@ -411,7 +450,7 @@ def main():
                           "kernel_sources": kernel_source_hash()}), flush=True)
         return
 
-    batched = run_gpu(ens, args.steps, args.warmup, fp32=1)
+    batched = run_gpu(ens, args.steps, args.warmup, fp32=1, keep_first_U=args.warmup > 0)
     solves = 2 * batched["replicas"] * batched["steps"]
     value = solves / batched["seconds"]
     log("batched fp32-pc: %.1f solves/s (%.2f s per launch)" % (value, batched["seconds"] / batched["steps"]))
@@ -419,10 +458,31 @@ def main():
         print(json.dumps({"batched_only": True, "value": round(value, 3), "steps": batched["steps"],
                           "fgmres_iters_per_launch": batched["iters"] / batched["steps"]}), flush=True)
         return
+    U_oracle = cb["U"] if cpu is not None else None
+    err = oracle_error(batched["first_U"], U_oracle, ens)
+    if err:
+        log("batched at tol %.0e: U error vs oracle max %.2e median %.2e over %d replicas"
+            % (ens[0].tol, err["max"], err["median"], err["replicas"]))
 
     plain = run_plain(ens[:args.plain_replicas])
     plain_value = 2 * plain["steps"] / plain["seconds"]
     log("plain fp64-pc, one replica at a time: %.1f solves/s" % plain_value)
+
+    # the same comparison at a tolerance tight enough for the velocities to agree with
+    # the oracle to ~1e-6 (the relative residual is dominated by the fluctuating
+    # forcing, so 1e-6 of it leaves U with a larger relative error)
+    tight = None
+    if args.tight_tol > 0:
+        bt = run_gpu(ens, max(1, min(args.steps, args.tight_steps)), 1, fp32=1, tol=args.tight_tol,
+                     keep_first_U=True)
+        vt = 2 * bt["replicas"] * bt["steps"] / bt["seconds"]
+        pt = run_plain(ens[:args.plain_replicas], tol=args.tight_tol)
+        pvt = 2 * pt["steps"] / pt["seconds"]
+        et = oracle_error(bt["first_U"], U_oracle, ens)
+        tight = {"tol": args.tight_tol, "batched": round(vt, 3), "plain_fp64": round(pvt, 3),
+                 "ratio_batched_over_plain": round(vt / pvt, 3), "steps": bt["steps"],
+                 "fgmres_iters_per_launch": round(bt["iters"] / bt["steps"], 1), "oracle_err": et}
+        log("tol %.0e: batched %.1f, plain %.1f solves/s; U error vs oracle %s" % (args.tight_tol, vt, pvt, et))
 
     timing = run_gpu(ens, 1, 0, fp32=1, timing=True)
     roofline, kernels = roofline_of(timing["stats"], args.replicas == 256 and MG_FUSED == 0)
@@ -454,9 +514,11 @@ def main():
                    "precond": "fp32 multigrid", "solves_per_step_per_replica": 2,
                    "fgmres_iters_per_launch": round(batched["iters"] / batched["steps"], 1),
                    "rejected": batched["rejected"]},
+        "oracle_err": err,
         "plain_fp64": {"value": round(plain_value, 3), "unit": "mobility solves/s",
                        "sample": "first %d replicas, one SEM step each, solved one at a time" % plain["steps"],
                        "ratio_batched_over_plain": round(value / plain_value, 3)},
+        "tight_tolerance": tight,
         "two_spheres": {"value": round(two_value, 3), "unit": "mobility solves/s", "grid": [32, 32, 64],
                         "ms_per_step": round(1e3 * two["seconds"] / two["steps"], 3),
                         "fgmres_iters_per_step": round(two["iters"] / two["steps"], 1)},

@@ -33,3 +33,28 @@ def test_traffic_reported_only_for_matching_sources(tmp_path, monkeypatch):
     assert bench.measured_traffic("mg_smooth_level0") == 1234.0
     assert bench.measured_traffic("krylov_update") is None
     assert bench.measured_traffic("mac_saddle_apply") is None
+
+
+def test_gpu_leg_loads_nothing_from_the_oracle():
+    """Only the CPU-baseline leg (_cpu_step, run in worker processes) may import the
+    oracle: the functions that build contexts and time the GPU reach the library
+    through the binding alone, and no module-level import of bench reaches oracle/
+    or the test helpers (which import the oracle)."""
+    import ast
+    import inspect
+    tree = ast.parse(inspect.getsource(bench))
+    users = set()
+    for fn in [n for n in ast.walk(tree) if isinstance(n, (ast.FunctionDef, ast.ClassDef))]:
+        for n in ast.walk(fn):
+            mods = []
+            if isinstance(n, ast.Import):
+                mods = [a.name for a in n.names]
+            elif isinstance(n, ast.ImportFrom):
+                mods = [n.module or ""]
+            if any(m.split(".")[0] in ("oracle", "tests") for m in mods):
+                users.add(fn.name)
+    assert users == {"_cpu_step"}, users
+    top = [n for n in tree.body if isinstance(n, (ast.Import, ast.ImportFrom))]
+    for n in top:
+        names = [a.name for a in n.names] if isinstance(n, ast.Import) else [n.module or ""]
+        assert not any(m.split(".")[0] in ("oracle", "tests") for m in names)
