@@ -49,3 +49,39 @@ def lib_context(rb, ws, **opt_kw):
 def dev(t):
     import torch
     return torch.as_tensor(np.ascontiguousarray(t), dtype=torch.float64).cuda()
+
+
+# ------------------------------------------------------------------ error bounds
+_GAINS = None
+
+
+def error_gains(name: str) -> np.ndarray:
+    """gain_k = ||A^+ e_{U,k}||_2 for configuration `name`, written by the oracle
+    (tests/golden/make_error_gains.py): a solve whose residual has 2-norm rho has
+    |U_k - U*_k| <= gain_k rho."""
+    global _GAINS
+    if _GAINS is None:
+        import json
+        import os
+        with open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "error_gains.json")) as fh:
+            _GAINS = json.load(fh)
+    return np.asarray(_GAINS[name]["gain"], dtype=np.float64)
+
+
+# Largest gain from the residuals of the two solves that feed the drift of a SEM step
+# (the random-finite-difference solve and the unconstrained Stokes solve) to the
+# final velocities, relative to the gain of the final solve's own residual: their
+# errors reach U through differences of K, K^T, J and S over Q+- divided by delta,
+# which are O(1) multiples of the solution error (at most the largest marker offset
+# times |W|, a few units), and for the unconstrained solve through the inverse
+# Laplacian (up to ~L^2 / (3 pi^2) h^2 for an L-cell box, ~35 at L = 32).
+SEM_DRIFT_GAIN = 100.0
+
+
+def sem_error_bound(name: str, norms, tol: float, final_rel_residual: float) -> np.ndarray:
+    """Per-component bound on |U_gpu - U_oracle| for one SEM step: the final solve's
+    residual (final_rel_residual ||b_3||) times its gain, plus the drift solves'
+    residuals (at most tol ||b_1||, tol ||b_2||) times SEM_DRIFT_GAIN times it."""
+    b1, b2, b3 = norms
+    rho = final_rel_residual * b3 + SEM_DRIFT_GAIN * tol * (b1 + b2)
+    return error_gains(name).reshape(-1, 6) * rho

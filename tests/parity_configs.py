@@ -1,0 +1,71 @@
+"""Named synthetic configurations shared by the GPU parity tests and the script
+that stores the oracle's error gains for them (tests/golden/make_error_gains.py).
+Inputs only: seeded geometry, positions, forces and slip; no arithmetic of the
+method."""
+from __future__ import annotations
+
+import numpy as np
+
+import workloads as W
+
+
+def solve_configs():
+    """Operator-apply and mobility-solve cases: walled, periodic, ragged (partial tiles),
+    a one-cell last tile on a periodic axis, the sliding-wall monolayer, and two
+    replicas of the benchmark ensemble (the crowded 16^3 box with four spheres that
+    sets the length of the batched iteration loop, and a 48^3 box)."""
+    out = {
+        "single_sphere_32": W.single_sphere(),
+        "two_spheres_32x32x64": W.two_spheres(),
+        "ragged_10x12x14": W.small_box(21, n=(10, 12, 14), n_bodies=3, R=1.5, shape="ico12"),
+    }
+    w = W.small_box(22, n=(16, 12, 12), n_bodies=3, R=1.5, shape="ico12")
+    w.bc = (W.PERIODIC, W.WALL, W.WALL)
+    out["periodic_x_16x12x12"] = w
+    # periodic x of 17 cells: the last tile holds one cell, and markers of the body
+    # at x = 0.15 h in cell 0 reach cell 15 (tile 3) through the wrap
+    w = W.small_box(23, n=(17, 12, 12), n_bodies=2, R=1.5, shape="ico12")
+    w.bc = (W.PERIODIC, W.WALL, W.WALL)
+    w.q[0, 0] = 0.15 * w.h
+    out["periodic_wrap_17x12x12"] = w
+    out["monolayer_64x32x16"] = W.monolayer(n=(64, 32, 16), rows=4, cols=16)
+    out.update(ensemble_replicas())
+    return out
+
+
+def ensemble_replicas():
+    """The first 16^3 replica with four spheres and the first 48^3 replica of the
+    256-replica benchmark ensemble, with their ensemble index."""
+    ens = W.ensemble()
+    k16 = next(k for k, w in enumerate(ens) if w.n[0] == 16 and w.nb == 4)
+    k48 = next(k for k, w in enumerate(ens) if w.n[0] == 48)
+    a, b = ens[k16], ens[k48]
+    a.name, b.name = "ensemble_%d" % k16, "ensemble_%d" % k48
+    return {"ensemble16_4spheres": a, "ensemble48": b}
+
+
+def sem_configs():
+    return {
+        "two_spheres_16x16x32": W.spheres_in_box(31, (16, 16, 32), 2, name="two_small"),
+        "two_spheres_32x32x64": W.two_spheres(),
+        "monolayer_32x16x12_sliding": W.monolayer(n=(32, 16, 12), rows=2, cols=8),
+    }
+
+
+def marker_slip(w, seed=17, scale=0.05):
+    """A nonzero prescribed slip on every marker (Sec. II eq. rigidBC): a seeded random
+    field plus a swirl about a fixed axis through each body's tracking point (the
+    surface velocity of an active particle), both of size `scale`, lab frame."""
+    rng = np.random.default_rng(seed)
+    axis = np.array([0.3, -0.5, 0.8])
+    d = w.r_ref / np.maximum(np.linalg.norm(w.r_ref, axis=1, keepdims=True), 1e-12)
+    return scale * (rng.standard_normal((w.nm, 3)) + np.cross(axis, d))
+
+
+def gain_configs():
+    """Every configuration whose solves the GPU tests bound through the stored gains."""
+    out = dict(solve_configs())
+    out.pop("periodic_wrap_17x12x12")          # apply only
+    for k, w in sem_configs().items():
+        out.setdefault(k, w)
+    return out

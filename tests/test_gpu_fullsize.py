@@ -8,8 +8,8 @@
   size), for the FP32 and the FP64 preconditioner.
 * Fluctuation-dissipation balance: over a batch of identical replicas with
   different seeds, dt * Cov(U^n) of the SEM velocity with zero deterministic
-  force matches 2 kT N (N assembled from deterministic solves) within sampling
-  error; the Brownian part dominates U^n at small dt.
+  force matches 2 kT N (N assembled by the oracle's exact solves) within
+  sampling error; the Brownian part dominates U^n at small dt.
 """
 import numpy as np
 import pytest
@@ -78,16 +78,13 @@ def test_fluctuation_dissipation_statistics(rb):
         samples.append(U.cpu().numpy().copy())
     S = np.concatenate(samples)              # (nrep * nstep, 6)
     ctx.close()
-    # N from six deterministic solves
-    c1 = lib_context(rb, base, tol=1e-10)
+    # N from six exact oracle solves (unit forces and torques)
+    s = Saddle(oracle_grid(base), base.q, base.theta, base.r_ref, base.offsets)
     N = np.zeros((6, 6))
     for j in range(6):
         F = np.zeros((1, 6))
         F[0, j] = 1.0
-        Uj = torch.empty((1, 6), dtype=torch.float64, device="cuda")
-        rb.rbfib_solve_mobility(c1, dev(base.q), dev(base.theta), dev(F), Uj, include_bc=False, allow=())
-        N[:, j] = Uj.cpu().numpy()[0]
-    c1.close()
+        N[:, j] = s.split(s.solve(s.rhs(FT=F, include_bc=False)))[3][0]
     n = S.shape[0]
     C = dt * np.cov(S.T)
     target = 2 * kT * N
