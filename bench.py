@@ -375,7 +375,7 @@ def main():
     ap.add_argument("--plain-replicas", type=int, default=24, help="replicas timed one at a time")
     ap.add_argument("--two-spheres-steps", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--tight-tol", type=float, default=1e-9,
+    ap.add_argument("--tight-tol", type=float, default=1e-10,
                     help="second batched-vs-plain comparison at this tolerance (0: skip)")
     ap.add_argument("--tight-steps", type=int, default=3, help="timed batched launches at the tight tolerance")
     ap.add_argument("--cpu-budget", type=float, default=20.0)

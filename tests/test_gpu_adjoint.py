@@ -95,11 +95,16 @@ def test_vjp_finite_differences_full_size(rb):
         print("  direction", k, "fd", fd, "adjoint", an, "rel", abs(fd - an) / abs(fd), flush=True)
     scale = float(np.mean(typical))
     print("  typical directional derivative", scale, flush=True)
-    # quaternion gradient along directions tangent to the unit sphere
+    # quaternion gradient along directions tangent to the unit sphere; the displaced
+    # orientations are renormalised (the library accepts only unit quaternions), which
+    # moves them by O(eps^2) along theta and leaves the tangent derivative unchanged
+    def unit(th):
+        return th / np.linalg.norm(th, axis=1, keepdims=True)
+
     for k in range(2):
         d = rng.standard_normal((w.nb, 4))
         d -= np.sum(d * w.theta, axis=1, keepdims=True) * w.theta
-        vals = [_loss(rb, ctx, w, w.q, w.theta + sgn * eps * d, w.FT) for sgn in (1.0, -1.0)]
+        vals = [_loss(rb, ctx, w, w.q, unit(w.theta + sgn * eps * d), w.FT) for sgn in (1.0, -1.0)]
         fd = (vals[0] - vals[1]) / (2 * eps)
         an = np.sum(dth * d)
         print("  quaternion direction", k, "fd", fd, "adjoint", an, flush=True)
