@@ -197,6 +197,25 @@ int rbfib_markers(rbfib_ctx *ctx, const double *q, const double *theta,
 int rbfib_apply_saddle(rbfib_ctx *ctx, const double *q, const double *theta,
                        const double *x, double *y);
 
+/* Allocation-free y = A x for ONE replica, for callers that cannot allocate device
+ * memory: code under stream capture, tight serving loops, harnesses that forbid
+ * hipMalloc.  The same operator and the same kernels as rbfib_apply_saddle on a
+ * context created from (grid, bodies), but no context: every table the kernels
+ * need lives in one fixed device array of the library (about 10 MiB per device,
+ * held until the process ends), so the call neither allocates nor frees device
+ * memory.  grid and bodies: host, as for rbfib_create (marker_offset and r_ref are
+ * copied to the device on every call); q [nb, 3], theta [nb, 4], x and y (state
+ * vectors of the replica, must not alias): device; hip_stream: the stream all work
+ * is enqueued on (NULL = default stream).  Limits: at most 8192 markers, 2048
+ * bodies, 1024 markers per body, 2^23 cells and 2^17 tiles of 4x4x4 cells; larger
+ * inputs return RBFIB_EINVAL before any work is enqueued.  Asynchronous: the
+ * orientations are not checked (they must be unit quaternions), and markers must
+ * lie inside the domain along wall axes, as for rbfib_apply_saddle.  Every call on a
+ * device uses that device's array and leaves its contents there: calls that overlap
+ * on one device (different streams, or host threads without ordering) race. */
+int rbfib_apply_saddle_noalloc(const rbfib_grid *grid, const rbfib_bodies *bodies, const double *q,
+                               const double *theta, const double *x, double *y, void *hip_stream);
+
 /* Preconditioner z = P^-1 r (for inspection; the solver applies it internally). */
 int rbfib_precondition(rbfib_ctx *ctx, const double *q, const double *theta,
                        const double *r, double *z);

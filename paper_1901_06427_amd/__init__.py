@@ -33,6 +33,7 @@ EXPORTS = [
     "rbfib_destroy", "rbfib_set_opts", "rbfib_state_size", "rbfib_layout", "rbfib_markers",
     "rbfib_apply_saddle", "rbfib_precondition", "rbfib_solve_mobility", "rbfib_fluctuating_stress",
     "rbfib_sem_step", "rbfib_mobility_vjp", "rbfib_kernel_stats", "rbfib_enable_timing",
+    "rbfib_apply_saddle_noalloc",
 ]
 
 
@@ -87,6 +88,7 @@ def _load():
         "rbfib_layout": (I, [P, ctypes.POINTER(ctypes.c_longlong)]),
         "rbfib_markers": (I, [P, P, P, P, P, P]),
         "rbfib_apply_saddle": (I, [P, P, P, P, P]),
+        "rbfib_apply_saddle_noalloc": (I, [ctypes.POINTER(rbfib_grid), ctypes.POINTER(rbfib_bodies), P, P, P, P, P]),
         "rbfib_precondition": (I, [P, P, P, P, P]),
         "rbfib_solve_mobility": (I, [P, P, P, P, P, I, P, P, ctypes.POINTER(rbfib_info)]),
         "rbfib_fluctuating_stress": (I, [P, D, D, U64, U64, P]),
@@ -228,6 +230,22 @@ def rbfib_markers(ctx: Context, q, theta, r=None, tile=None, perm=None):
 
 def rbfib_apply_saddle(ctx: Context, q, theta, x, y):
     _check(_lib.rbfib_apply_saddle(ctx.h, _ptr(q), _ptr(theta), _ptr(x), _ptr(y)), "rbfib_apply_saddle")
+
+
+def rbfib_apply_saddle_noalloc(grid: rbfib_grid, r_ref, offsets, q, theta, x, y, stream=None):
+    """y = A x for one replica without a context (the library allocates nothing)."""
+    import torch
+    rr = np.ascontiguousarray(r_ref, dtype=np.float64).reshape(-1, 3)
+    off = np.ascontiguousarray(offsets, dtype=np.int32)
+    bd = rbfib_bodies()
+    bd.nb = int(len(off) - 1)
+    bd.nm = int(rr.shape[0])
+    bd.marker_offset = off.ctypes.data_as(ctypes.POINTER(ctypes.c_int))
+    bd.r_ref = rr.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    if stream is None:
+        stream = torch.cuda.current_stream().cuda_stream
+    _check(_lib.rbfib_apply_saddle_noalloc(ctypes.byref(grid), ctypes.byref(bd), _ptr(q), _ptr(theta), _ptr(x),
+                                           _ptr(y), ctypes.c_void_p(stream)), "rbfib_apply_saddle_noalloc")
 
 
 def rbfib_precondition(ctx: Context, q, theta, r, z):
