@@ -1,15 +1,24 @@
-"""Immersed-boundary interpolation J and spreading S with the Peskin 4-point kernel.
+"""Immersed-boundary interpolation J and spreading S with a regularised delta kernel.
 
 Follows Sec. III.B of the paper: (J v)_i = sum_alpha delta_h(x_alpha - r_i) v(x_alpha)
 and (S lambda)_alpha = (1/dV) sum_i delta_h(x_alpha - r_i) lambda_i, with the
 adjoint relation J = dV S^*.  delta_h(x) = phi(x/h) phi(y/h) phi(z/h) are
 dimensionless weights.
 
-Kernel (the configurations here use Peskin's standard 4-point function; the
-paper's own runs use a 6-point kernel):
-    phi(r) = (3 - 2|r| + sqrt(1 + 4|r| - 4 r^2)) / 8      |r| <= 1
-           = (5 - 2|r| - sqrt(-7 + 12|r| - 4 r^2)) / 8     1 <= |r| <= 2
-           = 0                                              otherwise
+Kernels (the grid's `kernel` width selects one):
+  * 4: Peskin's standard 4-point function
+        phi(r) = (3 - 2|r| + sqrt(1 + 4|r| - 4 r^2)) / 8      |r| <= 1
+               = (5 - 2|r| - sqrt(-7 + 12|r| - 4 r^2)) / 8     1 <= |r| <= 2
+               = 0                                              otherwise
+  * 6: the 6-point function of the paper's runs (Sec. III.B; Bao, Kaiser & Peskin,
+    J. Comput. Phys. 2016), supported on |r| < 3 and defined, for every shift x,
+    by conditions on its six values at x - k: even and odd sums 1/2 each, first
+    and third moments 0, second moment K = 59/60 - sqrt(29)/20 (the value that
+    makes the function three times continuously differentiable), and sum of
+    squares C, the value those conditions give at x = 0 (where phi(+-3) = 0).
+    Five conditions are linear in the six values; the quadratic one fixes the
+    last free value, on the branch that is continuous with phi(-3) = 0.  The
+    values are computed here by solving exactly that system (no closed form).
 
 Walls (the paper defers to ghost points across the boundary that keep J and
 S adjoint; reading used here -- odd reflection):
@@ -24,7 +33,7 @@ S adjoint; reading used here -- odd reflection):
     signs of the other reflections of that point).
 
 Marker indexing: s = r * (1/h) - o (o = 0 along the face-normal axis, 1/2
-otherwise), base = floor(s) - 1, the four support points base .. base + 3.
+otherwise), base = floor(s) - (W/2 - 1), the W support points base .. base + W - 1.
 """
 from __future__ import annotations
 
@@ -62,17 +71,86 @@ def dphi4(r):
     return out * s
 
 
+K6 = 59.0 / 60.0 - np.sqrt(29.0) / 20.0
+
+
+def _phi6_values(x, K=K6):
+    """For shifts x in [0, 1) (real or complex, for complex-step derivatives), the six
+    kernel values phi(x - k), k = -2 .. 3, as an array (len(x), 6).  K is the second
+    moment (K6 for the kernel; other values only to show what the smoothness needs)."""
+    x = np.asarray(x)
+    n = x.shape[0]
+    ks = np.arange(-2, 4)
+    d = x[:, None] - ks[None, :]                       # distances x - k
+    A = np.zeros((n, 5, 6), dtype=x.dtype)
+    A[:, 0, [0, 2, 4]] = 1.0                           # even sum (k = -2, 0, 2)
+    A[:, 1, [1, 3, 5]] = 1.0                           # odd sum (k = -1, 1, 3)
+    A[:, 2] = d                                        # first moment
+    A[:, 3] = d ** 2                                   # second moment
+    A[:, 4] = d ** 3                                   # third moment
+    b = np.zeros((n, 5), dtype=x.dtype)
+    b[:, 0] = b[:, 1] = 0.5
+    b[:, 3] = K
+    # the last value t = phi(x - 3) is free: values = p + t q
+    M = A[:, :, :5]
+    p = np.linalg.solve(M, b[:, :, None])[:, :, 0]
+    q = np.linalg.solve(M, -A[:, :, 5:6])[:, :, 0]
+    p = np.concatenate([p, np.zeros((n, 1), dtype=x.dtype)], axis=1)
+    q = np.concatenate([q, np.ones((n, 1), dtype=x.dtype)], axis=1)
+    # sum of squares: C from x = 0, where phi(+-3) = 0 and the linear conditions
+    # fix the other five values (phi(+-1) = 1/4, phi(+-2) = (K - 1/2)/8)
+    f2 = (K - 0.5) / 8.0
+    C = (0.5 - 2.0 * f2) ** 2 + 2.0 * 0.25 ** 2 + 2.0 * f2 ** 2
+    qa = np.sum(q * q, axis=1)
+    qb = 2.0 * np.sum(p * q, axis=1)
+    qc = np.sum(p * p, axis=1) - C
+    t = (-qb + np.sqrt(qb * qb - 4.0 * qa * qc)) / (2.0 * qa)   # the root with t = 0 at x = 0
+    return p + t[:, None] * q
+
+
+def phi6(r):
+    """The 6-point kernel (vectorised)."""
+    a = np.abs(np.asarray(r, dtype=np.float64)).ravel()
+    out = np.zeros(a.shape)
+    m = a < 3.0
+    k = np.floor(a[m]).astype(np.int64)
+    vals = _phi6_values(a[m] - k)
+    out[m] = vals[np.arange(k.size), 2 - k]            # phi(x + k) is the value at -k
+    return out.reshape(np.shape(r))
+
+
+def dphi6(r):
+    """d phi / d r of the 6-point kernel, by a complex-step derivative of the same
+    construction (exact to rounding: the values are analytic in the shift)."""
+    r = np.asarray(r, dtype=np.float64)
+    a = np.abs(r).ravel()
+    out = np.zeros(a.shape)
+    m = a < 3.0
+    k = np.floor(a[m]).astype(np.int64)
+    h = 1e-30
+    vals = _phi6_values((a[m] - k) + 1j * h)
+    out[m] = vals[np.arange(k.size), 2 - k].imag / h
+    return (out * np.sign(r.ravel())).reshape(r.shape)
+
+
+def kernel_of(g: Grid):
+    """(width, phi, dphi) of the grid's delta kernel."""
+    return (6, phi6, dphi6) if getattr(g, "kernel", 4) == 6 else (4, phi4, dphi4)
+
+
 def axis_offset(c: int, a: int) -> float:
     return 0.0 if a == c else 0.5
 
 
 def base_index(g: Grid, r: np.ndarray, c: int) -> np.ndarray:
-    """(nm, 3) int: floor(r * (1/h) - o) - 1 per axis for component c."""
+    """(nm, 3) int: floor(r * (1/h) - o) - (W/2 - 1) per axis for component c (W the
+    kernel width: the support is the W points base .. base + W - 1)."""
+    W = kernel_of(g)[0]
     inv_h = 1.0 / g.h
     out = np.empty(r.shape, dtype=np.int64)
     for a in range(3):
         s = r[:, a] * inv_h - axis_offset(c, a)
-        out[:, a] = np.floor(s).astype(np.int64) - 1
+        out[:, a] = np.floor(s).astype(np.int64) - (W // 2 - 1)
     return out
 
 
@@ -108,33 +186,36 @@ def fold(g: Grid, c: int, a: int, p: np.ndarray):
 
 
 def _support(g: Grid, r: np.ndarray, c: int):
-    """Per marker, the 64 support points of component c: (columns, signed weights, valid, crossed, raw phis)."""
+    """Per marker, the W^3 support points of component c: (columns, signed weights, valid, crossed, raw phis)."""
+    W, phi, _ = kernel_of(g)
+    W3 = W ** 3
     nm = r.shape[0]
     b = base_index(g, r, c)
     inv_h = 1.0 / g.h
     per_axis = []
     for a in range(3):
         s = r[:, a] * inv_h - axis_offset(c, a)
-        p = b[:, a][:, None] + np.arange(4)[None, :]
-        w = phi4(s[:, None] - p)
+        p = b[:, a][:, None] + np.arange(W)[None, :]
+        w = phi(s[:, None] - p)
         idx, sign, valid, crossed = fold(g, c, a, p)
         per_axis.append((idx, sign, valid, crossed, w))
     ix, sx, vx, cx, wx = per_axis[0]
     iy, sy, vy, cy, wy = per_axis[1]
     iz, sz, vz, cz, wz = per_axis[2]
-    # broadcast to (nm, 4, 4, 4) in (z, y, x) order -> flatten to 64
-    I = np.broadcast_to(ix[:, None, None, :], (nm, 4, 4, 4)).reshape(nm, 64)
-    J = np.broadcast_to(iy[:, None, :, None], (nm, 4, 4, 4)).reshape(nm, 64)
-    K = np.broadcast_to(iz[:, :, None, None], (nm, 4, 4, 4)).reshape(nm, 64)
-    sgn = (sz[:, :, None, None] * sy[:, None, :, None] * sx[:, None, None, :]).reshape(nm, 64)
-    w = (wz[:, :, None, None] * wy[:, None, :, None] * wx[:, None, None, :]).reshape(nm, 64)
-    valid = (vz[:, :, None, None] & vy[:, None, :, None] & vx[:, None, None, :]).reshape(nm, 64)
-    cross = [np.broadcast_to(cx[:, None, None, :], (nm, 4, 4, 4)).reshape(nm, 64),
-             np.broadcast_to(cy[:, None, :, None], (nm, 4, 4, 4)).reshape(nm, 64),
-             np.broadcast_to(cz[:, :, None, None], (nm, 4, 4, 4)).reshape(nm, 64)]
-    signs = [np.broadcast_to(sx[:, None, None, :], (nm, 4, 4, 4)).reshape(nm, 64),
-             np.broadcast_to(sy[:, None, :, None], (nm, 4, 4, 4)).reshape(nm, 64),
-             np.broadcast_to(sz[:, :, None, None], (nm, 4, 4, 4)).reshape(nm, 64)]
+    # broadcast to (nm, W, W, W) in (z, y, x) order -> flatten to W^3
+    sh = (nm, W, W, W)
+    I = np.broadcast_to(ix[:, None, None, :], sh).reshape(nm, W3)
+    J = np.broadcast_to(iy[:, None, :, None], sh).reshape(nm, W3)
+    K = np.broadcast_to(iz[:, :, None, None], sh).reshape(nm, W3)
+    sgn = (sz[:, :, None, None] * sy[:, None, :, None] * sx[:, None, None, :]).reshape(nm, W3)
+    w = (wz[:, :, None, None] * wy[:, None, :, None] * wx[:, None, None, :]).reshape(nm, W3)
+    valid = (vz[:, :, None, None] & vy[:, None, :, None] & vx[:, None, None, :]).reshape(nm, W3)
+    cross = [np.broadcast_to(cx[:, None, None, :], sh).reshape(nm, W3),
+             np.broadcast_to(cy[:, None, :, None], sh).reshape(nm, W3),
+             np.broadcast_to(cz[:, :, None, None], sh).reshape(nm, W3)]
+    signs = [np.broadcast_to(sx[:, None, None, :], sh).reshape(nm, W3),
+             np.broadcast_to(sy[:, None, :, None], sh).reshape(nm, W3),
+             np.broadcast_to(sz[:, :, None, None], sh).reshape(nm, W3)]
     Ic = np.where(valid, I, 0)
     Jc = np.where(valid, J, 0)
     Kc = np.where(valid, K, 0)
@@ -194,6 +275,7 @@ def interpolation_gradient(g: Grid, r: np.ndarray, v: np.ndarray, mu: np.ndarray
     a replaces phi_a by phi_a' / h.  Folding signs and indices are constant
     within each smooth piece.
     """
+    W, phi, dphi = kernel_of(g)
     nm = r.shape[0]
     out = np.zeros((nm, 3))
     inv_h = 1.0 / g.h
@@ -202,13 +284,13 @@ def interpolation_gradient(g: Grid, r: np.ndarray, v: np.ndarray, mu: np.ndarray
         ax = []
         for a in range(3):
             s = r[:, a] * inv_h - axis_offset(c, a)
-            p = b[:, a][:, None] + np.arange(4)[None, :]
+            p = b[:, a][:, None] + np.arange(W)[None, :]
             idx, sign, valid, _ = fold(g, c, a, p)
-            ax.append((idx, sign, valid, phi4(s[:, None] - p), dphi4(s[:, None] - p) * inv_h))
+            ax.append((idx, sign, valid, phi(s[:, None] - p), dphi(s[:, None] - p) * inv_h))
         (ix, sx, vx, wx, dx), (iy, sy, vy, wy, dy), (iz, sz, vz, wz, dz) = ax
-        I = np.broadcast_to(ix[:, None, None, :], (nm, 4, 4, 4))
-        J = np.broadcast_to(iy[:, None, :, None], (nm, 4, 4, 4))
-        K = np.broadcast_to(iz[:, :, None, None], (nm, 4, 4, 4))
+        I = np.broadcast_to(ix[:, None, None, :], (nm, W, W, W))
+        J = np.broadcast_to(iy[:, None, :, None], (nm, W, W, W))
+        K = np.broadcast_to(iz[:, :, None, None], (nm, W, W, W))
         valid = vz[:, :, None, None] & vy[:, None, :, None] & vx[:, None, None, :]
         col = _face_col(g, c, (np.where(valid, I, 0), np.where(valid, J, 0), np.where(valid, K, 0)))
         valid = valid & (col >= 0)

@@ -43,8 +43,13 @@ FAMILIES: List[Tuple[int, int]] = [(0, 0), (1, 1), (2, 2), (0, 1), (0, 2), (1, 0
 class Grid:
     """A box of Nx x Ny x Nz cells of width h, with a BC per axis and wall velocities."""
 
-    def __init__(self, n, bc, h: float = 1.0, eta: float = 1.0, wall_vel=None):
+    def __init__(self, n, bc, h: float = 1.0, eta: float = 1.0, wall_vel=None, kernel: int = 4):
         self.n = tuple(int(v) for v in n)
+        # width of the immersed-boundary delta kernel used with this grid (ib.py): 4
+        # (Peskin's 4-point function) or 6 (the 6-point function of the paper's runs)
+        if kernel not in (4, 6):
+            raise ValueError("kernel width must be 4 or 6")
+        self.kernel = int(kernel)
         self.bc = tuple(int(v) for v in bc)
         self.h = float(h)
         self.eta = float(eta)

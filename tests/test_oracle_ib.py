@@ -1,7 +1,12 @@
 """Pins of the oracle's delta kernel, interpolation J and spreading S (paper Sec. III.B).
 
-* The 4-point kernel's defining moment conditions hold for every shift.
-* J reproduces linear fields exactly away from walls and, with the odd
+* The 4-point kernel's defining moment conditions hold for every shift; so do
+  the 6-point kernel's (Bao, Kaiser & Peskin), whose values at the integers,
+  evenness, support and three continuous derivatives (the property that fixes
+  its second moment K) are checked separately, and whose blob has the
+  hydrodynamic radius 1.47 h the paper states (Sec. III.B), from the mobility
+  of one blob in triply periodic boxes against Hasimoto's expansion.
+* For both kernels: J reproduces linear fields exactly away from walls and, with the odd
   reflection, linear fields that vanish on a wall (or equal the wall speed
   on a moving wall) right up to the wall.
 * A brute-force coordinate-space J (ghost values from mirror coordinates,
@@ -36,6 +41,99 @@ def test_kernel_derivative():
     assert np.abs(fd - ib.dphi4(x)).max() < 1e-6
 
 
+def test_kernel6_conditions():
+    rng = np.random.default_rng(0)
+    C = None
+    for r in rng.uniform(-4, 4, 200):
+        j = np.arange(math.floor(r) - 4, math.floor(r) + 5)
+        w = ib.phi6(r - j)
+        d = r - j
+        assert abs(w.sum() - 1.0) < 1e-13
+        assert abs(np.sum(d * w)) < 1e-13
+        assert abs(np.sum(d * d * w) - ib.K6) < 1e-13
+        assert abs(np.sum(d ** 3 * w)) < 1e-12
+        assert abs(np.sum(w[j % 2 == 0]) - 0.5) < 1e-13
+        C = np.sum(w * w) if C is None else C
+        assert abs(np.sum(w * w) - C) < 1e-13
+        assert np.count_nonzero(w) <= 6
+    assert abs(ib.K6 - 0.7140750929766081) < 1e-15
+
+
+def test_kernel6_values_evenness_support():
+    """At the integers the linear conditions alone fix the values: phi(+-1) = 1/4,
+    phi(+-2) = (K - 1/2)/8, phi(0) = 1/2 - 2 phi(2), phi(+-3) = 0."""
+    f2 = (ib.K6 - 0.5) / 8
+    got = ib.phi6(np.array([0.0, 1.0, -1.0, 2.0, -2.0, 3.0, -3.0, 3.5]))
+    ref = [0.5 - 2 * f2, 0.25, 0.25, f2, f2, 0.0, 0.0, 0.0]
+    assert np.abs(got - ref).max() < 1e-14
+    x = np.random.default_rng(1).uniform(-3, 3, 500)
+    assert np.abs(ib.phi6(x) - ib.phi6(-x)).max() < 1e-14
+    assert np.all(ib.phi6(np.linspace(2.999, 3.0, 5)) < 1e-9)
+
+
+def test_kernel6_three_continuous_derivatives():
+    """One-sided difference quotients of orders 1 to 3 agree across r = 1, 2, 3 (and
+    vanish at the edge of the support); with the second moment moved off K the
+    third derivative jumps at r = 3, so the smoothness is what singles K out."""
+    h = 1e-3
+
+    def one_sided(f, x0):
+        l = np.array([f(x0 - i * h) for i in range(5)])
+        r = np.array([f(x0 + i * h) for i in range(5)])
+        d1 = ((3 * l[0] - 4 * l[1] + l[2]) / (2 * h), (-3 * r[0] + 4 * r[1] - r[2]) / (2 * h))
+        d2 = ((2 * l[0] - 5 * l[1] + 4 * l[2] - l[3]) / h ** 2, (2 * r[0] - 5 * r[1] + 4 * r[2] - r[3]) / h ** 2)
+        c3 = np.array([5.0, -18.0, 24.0, -14.0, 3.0]) / (2 * h ** 3)
+        d3 = (float(c3 @ l), -float(c3 @ r))
+        return d1, d2, d3
+
+    f = lambda x: float(ib.phi6(np.array([x]))[0])
+    for x0 in (1.0, 2.0, 3.0):
+        for k, (a, b) in enumerate(one_sided(f, x0)):
+            assert abs(a - b) < (2e-6, 2e-4, 2e-3)[k], (x0, k, a, b)
+    # the same construction with K moved by 0.01: a jump in the third derivative at 3
+    for dK in (0.01, -0.01):
+        g = lambda x, dK=dK: float(ib._phi6_values(np.array([x - 2.0]), K=ib.K6 + dK)[0, 0]) if x < 3 else 0.0
+        d3 = one_sided(g, 3.0)[2]
+        assert abs(d3[0] - d3[1]) > 0.01, (dK, d3)
+
+
+def _periodic_blob_mobility(n, r0, kernel):
+    """x-velocity of one blob pushed along x in a triply periodic box of n^3 cells
+    (h = eta = 1): the net force is balanced by a uniform pressure gradient (the
+    mean of the spread force is removed) and the mean flow is removed, as in
+    Hasimoto's periodic array of spheres."""
+    from oracle import saddle
+    g = mac.Grid((n, n, n), (mac.PERIODIC,) * 3, kernel=kernel)
+    s = saddle.Saddle(g, np.zeros((0, 3)), np.zeros((0, 4)), np.zeros((0, 3)), np.zeros(1, dtype=int),
+                      fluid_only=True)
+    J = ib.interpolation(g, np.asarray(r0, dtype=float)[None, :])
+    f = (J.T / g.dV) @ np.array([1.0, 0.0, 0.0])
+    for c in range(3):
+        sl = slice(g.face_offset[c], g.face_offset[c] + g.nface[c])
+        f[sl] -= f[sl].mean()
+    x, info = s.solve_fgmres(s.rhs(fluid=f, include_bc=False), tol=1e-12)
+    u = x[s.sl_v].copy()
+    for c in range(3):
+        sl = slice(g.face_offset[c], g.face_offset[c] + g.nface[c])
+        u[sl] -= u[sl].mean()
+    return float((J @ u)[0])
+
+
+def test_kernel6_hydrodynamic_radius():
+    """The paper gives the 6-point blob an effective hydrodynamic radius a = 1.47 h
+    (Sec. III.B).  Hasimoto's expansion of the mobility of a periodic array,
+    6 pi eta a mu(L) = 1 - 2.837297 a/L + (4 pi / 3) (a/L)^3 - 27.4 (a/L)^6, inverted
+    for a from the oracle's mobility in boxes of 16, 24 and 32 cells gives 1.47 h at
+    every size."""
+    from scipy.optimize import brentq
+    for n in (16, 24, 32):
+        mu = _periodic_blob_mobility(n, [n / 2 + 0.31, n / 2 - 0.17, n / 2 + 0.42], 6)
+        L = float(n)
+        a = brentq(lambda a: (1 - 2.837297 * a / L + 4 * math.pi / 3 * (a / L) ** 3 - 27.4 * (a / L) ** 6)
+                   / (6 * math.pi * a) - mu, 0.5, 3.0)
+        assert abs(a - 1.47) < 0.005, (n, a)
+
+
 def _field_from_function(g, fn):
     """Compact velocity whose component c at each unknown face equals fn(c, x, y, z)."""
     v = np.zeros(g.nv)
@@ -51,10 +149,11 @@ def _field_from_function(g, fn):
     return v
 
 
-def test_interp_linear_field_interior():
-    g = mac.Grid((12, 10, 14), (1, 1, 0), h=0.8)
+@pytest.mark.parametrize("kernel", [4, 6])
+def test_interp_linear_field_interior(kernel):
+    g = mac.Grid((12, 10, 14), (1, 1, 0), h=0.8, kernel=kernel)
     rng = np.random.default_rng(1)
-    r = np.column_stack([rng.uniform(2.5 * g.h, (g.n[a] - 2.5) * g.h, 30) for a in range(3)])
+    r = np.column_stack([rng.uniform(3.5 * g.h, (g.n[a] - 3.5) * g.h, 30) for a in range(3)])
     A = rng.standard_normal((3, 3))
     b0 = rng.standard_normal(3)
     # periodic z: use a field linear in x, y only
@@ -65,14 +164,15 @@ def test_interp_linear_field_interior():
     assert np.abs(Jv - exact).max() < 1e-12
 
 
+@pytest.mark.parametrize("kernel", [4, 6])
 @pytest.mark.parametrize("axis", [0, 1, 2])
-def test_interp_reflection_at_wall(axis):
+def test_interp_reflection_at_wall(axis, kernel):
     """A field linear in the wall-normal coordinate that vanishes on the wall is its
     own odd reflection, so J is exact even when the support crosses the wall."""
-    g = mac.Grid((10, 10, 10), (1, 1, 1), h=1.0)
+    g = mac.Grid((10, 10, 10), (1, 1, 1), h=1.0, kernel=kernel)
     rng = np.random.default_rng(2 + axis)
     r = rng.uniform(4.0, 6.0, size=(25, 3))
-    r[:, axis] = rng.uniform(0.05, 1.9, 25)          # within the kernel width of the lower wall
+    r[:, axis] = rng.uniform(0.05, kernel / 2 - 0.1, 25)   # within the kernel width of the lower wall
     slope = np.array([0.7, -1.3, 2.1])
     v = _field_from_function(g, lambda c, x, y, z: slope[c] * (x, y, z)[axis])
     Jv = (ib.interpolation(g, r) @ v).reshape(-1, 3)
@@ -87,15 +187,16 @@ def test_interp_reflection_at_wall(axis):
     assert np.abs(Jv - exact).max() < 1e-12
 
 
-def test_interp_moving_wall_affine_term():
+@pytest.mark.parametrize("kernel", [4, 6])
+def test_interp_moving_wall_affine_term(kernel):
     """u_x = U_w + s*z near a bottom wall sliding at U_w: J_0 v + J_bc is exact."""
     Uw = 0.5
     wv = np.zeros((3, 2, 3))
     wv[2, 0, 0] = Uw
-    g = mac.Grid((8, 8, 8), (0, 1, 1), wall_vel=wv)
+    g = mac.Grid((8, 8, 8), (0, 1, 1), wall_vel=wv, kernel=kernel)
     rng = np.random.default_rng(9)
     r = rng.uniform(3.0, 5.0, size=(20, 3))
-    r[:, 2] = rng.uniform(0.1, 1.9, 20)
+    r[:, 2] = rng.uniform(0.1, kernel / 2 - 0.1, 20)
     s = 0.37
     v = _field_from_function(g, lambda c, x, y, z: (Uw + s * z) if c == 0 else 0.0 * z)
     Jv = (ib.interpolation(g, r) @ v).reshape(-1, 3) + ib.interpolation_bc(g, r)
@@ -110,6 +211,7 @@ def _brute_force_J(g, r, v):
     for corners) and a point on a wall face of the normal component is zero."""
     vp = g.compact_to_padded(v).reshape(3, g.n[2], g.n[1], g.n[0])
     L = [g.n[a] * g.h for a in range(3)]
+    phi = ib.phi6 if g.kernel == 6 else ib.phi4
 
     def value(c, X):
         X = list(X)
@@ -134,26 +236,27 @@ def _brute_force_J(g, r, v):
     out = np.zeros((r.shape[0], 3))
     for m in range(r.shape[0]):
         for c in range(3):
-            lo = [math.floor(r[m, a] / g.h - (0.0 if a == c else 0.5)) - 2 for a in range(3)]
+            lo = [math.floor(r[m, a] / g.h - (0.0 if a == c else 0.5)) - 3 for a in range(3)]
             acc = 0.0
-            for i in range(lo[0], lo[0] + 6):
-                for j in range(lo[1], lo[1] + 6):
-                    for k in range(lo[2], lo[2] + 6):
+            for i in range(lo[0], lo[0] + 8):
+                for j in range(lo[1], lo[1] + 8):
+                    for k in range(lo[2], lo[2] + 8):
                         X = [(i + (0.0 if c == 0 else 0.5)) * g.h,
                              (j + (0.0 if c == 1 else 0.5)) * g.h,
                              (k + (0.0 if c == 2 else 0.5)) * g.h]
                         w = 1.0
                         for a in range(3):
-                            w *= ib.phi4((r[m, a] - X[a]) / g.h)
+                            w *= phi((r[m, a] - X[a]) / g.h)
                         if w != 0.0:
                             acc += w * value(c, X)
             out[m, c] = acc
     return out
 
 
+@pytest.mark.parametrize("kernel", [4, 6])
 @pytest.mark.parametrize("bc", [(1, 1, 1), (0, 1, 1), (1, 0, 0)])
-def test_interp_brute_force(bc):
-    g = mac.Grid((6, 7, 6), bc, h=1.1)
+def test_interp_brute_force(bc, kernel):
+    g = mac.Grid((6, 7, 6), bc, h=1.1, kernel=kernel)
     rng = np.random.default_rng(11)
     L = np.array(g.n) * g.h
     # markers near corners and walls, and one in the middle
@@ -164,10 +267,11 @@ def test_interp_brute_force(bc):
     assert np.abs(Jv - _brute_force_J(g, r, v)).max() < 1e-12
 
 
-def test_spread_conserves_force_and_adjointness():
-    g = mac.Grid((12, 12, 12), (1, 1, 1), h=0.5)
+@pytest.mark.parametrize("kernel", [4, 6])
+def test_spread_conserves_force_and_adjointness(kernel):
+    g = mac.Grid((12, 12, 12), (1, 1, 1), h=0.5, kernel=kernel)
     rng = np.random.default_rng(4)
-    r = rng.uniform(2.2 * g.h, 9.8 * g.h, size=(40, 3))
+    r = rng.uniform(3.2 * g.h, 8.8 * g.h, size=(40, 3))
     lam = rng.standard_normal((40, 3))
     S = ib.spreading(g, r)
     J = ib.interpolation(g, r)
@@ -185,3 +289,5 @@ def test_base_index_matches_floor():
     b0 = ib.base_index(g, r, 0)
     # x: s = r/h (normal axis); y, z: s = r/h - 1/2
     assert b0.tolist() == [[0, -1, 0], [6, -2, 3]]
+    g6 = mac.Grid((8, 8, 8), (1, 1, 1), h=0.5, kernel=6)
+    assert ib.base_index(g6, r, 0).tolist() == [[-1, -2, -1], [5, -3, 2]]
