@@ -18,7 +18,7 @@
  *     [    0      0   K^T  0 ] [ U      ]   [ F                            ]
  *
  * (Sec. III: MAC operators Lm = DT GT, G = -D^*; interpolation J and spreading
- * S through the Peskin 4-point kernel, J = dV S^*; (K U)_i = u_p + omega_p x
+ * S through a 4- or 6-point delta kernel, J = dV S^*; (K U)_i = u_p + omega_p x
  * (r_i - q_p), (K^T lambda)_p = [sum lambda_i; sum (r_i - q_p) x lambda_i]),
  * and advances the bodies by the Split-Euler-Maruyama scheme of Algorithm 1
  * with the random-finite-difference drift (Sec. IV).  Walls enter S and J by
@@ -150,6 +150,11 @@ typedef struct {
                                /*    kernel on FP32 levels whose rows are a multiple */
                                /*    of 4 (b read once, the first iterate never      */
                                /*    stored; same values as two sweeps); 0: two (1)  */
+    int kernel;                /* width of the delta kernel of S and J (Sec. III.B), */
+                               /*    fixed at creation: 4 = Peskin's 4-point         */
+                               /*    function, 6 = the 6-point function of Bao,      */
+                               /*    Kaiser & Peskin the paper uses (blob radius     */
+                               /*    1.47 h; set blob_radius to match) (4)           */
 } rbfib_opts;
 
 typedef struct {

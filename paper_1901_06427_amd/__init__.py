@@ -55,7 +55,7 @@ class rbfib_opts(ctypes.Structure):
                 ("min_body_dist", ctypes.c_double), ("check_every", ctypes.c_int), ("use_graphs", ctypes.c_int),
                 ("mg_fused", ctypes.c_int), ("mg_bottom", ctypes.c_int),
                 ("mg_cheby", ctypes.c_double), ("krylov_s", ctypes.c_int),
-                ("mg_first2", ctypes.c_int)]
+                ("mg_first2", ctypes.c_int), ("kernel", ctypes.c_int)]
 
 
 class rbfib_info(ctypes.Structure):

@@ -15,6 +15,7 @@
 
 namespace rb {
 
+template <int W>
 __global__ void k_body_grad(const RepDev *reps, const int *body_rep, const int *body_off, const double *r,
                             const double *d, const double *__restrict__ x, const double *__restrict__ xa,
                             const double *theta, double *dFT, double *dq, double *dphi, double *dtheta) {
@@ -36,8 +37,8 @@ __global__ void k_body_grad(const RepDev *reps, const int *body_rep, const int *
         double G[3] = {0.0, 0.0, 0.0};
         for (int c = 0; c < 3; ++c) {
             double g1[3], g2[3];
-            interp_grad(R, rm, c, x + R.off + c * R.N, g1);
-            interp_grad(R, rm, c, xa + R.off + c * R.N, g2);
+            interp_grad<W>(R, rm, c, x + R.off + c * R.N, g1);
+            interp_grad<W>(R, rm, c, xa + R.off + c * R.N, g2);
             for (int a = 0; a < 3; ++a) G[a] += lb[c] * g1[a] + inv_dV * lam[c] * g2[a];
         }
         double E[3] = {-(lb[1] * om[2] - lb[2] * om[1]) - (lam[1] * omh[2] - lam[2] * omh[1]),
@@ -79,8 +80,8 @@ void launch_body_grad(Ctx &c, const double *x, const double *xa, const double *t
                       double *dphi, double *dtheta) {
     if (c.nb == 0) return;
     size_t sh = sizeof(double) * 6 * (size_t)c.max_body_nm;
-    hipLaunchKernelGGL(k_body_grad, dim3(c.nb), dim3(64), sh, c.stream, c.d_reps, c.d_body_rep, c.d_body_off,
-                       c.ms[0].r, c.ms[0].d, x, xa, theta, dFT, dq, dphi, dtheta);
+    hipLaunchKernelGGL(c.kw == 6 ? k_body_grad<6> : k_body_grad<4>, dim3(c.nb), dim3(64), sh, c.stream, c.d_reps,
+                       c.d_body_rep, c.d_body_off, c.ms[0].r, c.ms[0].d, x, xa, theta, dFT, dq, dphi, dtheta);
 }
 
 // b_U[p] = dV * Ubar[p] (right side of the adjoint solve)

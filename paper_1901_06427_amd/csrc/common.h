@@ -360,53 +360,115 @@ __device__ __forceinline__ double philox_normal(uint64_t seed, uint32_t stream, 
 }
 
 // ------------------------------------------------------------------ kernel weights
+// Kernel of width W (4: Peskin's 4-point function; 6: the 6-point function of
+// Bao, Kaiser & Peskin that the paper's runs use).  For a scaled coordinate s the W
+// support points are base .. base + W - 1, base = floor(s) - (W/2 - 1), with weights
+// phi(s - p).
+//
+// 6-point function: with x = s - floor(s) in [0, 1), its six values a_q = phi(x + 2 - q)
+// satisfy five linear conditions (even and odd sums 1/2, moments 1 and 3 zero, moment 2
+// K = 59/60 - sqrt(29)/20) and a quadratic one (sum of squares); solved in closed form
+// they are polynomials in x plus multiples of t = a_5, the root of
+// 28 t^2 + B(x) t + Cq(x) = 0 that vanishes at x = 0, taken as -2 Cq / (B + sqrt(disc))
+// (no cancellation), disc = B^2 - 112 Cq.
+#define RB_SQRT29 5.385164807134504
+__device__ __forceinline__ void phi6_values(double x, double a[6]) {
+    const double x2 = x * x, x3 = x2 * x, x4 = x2 * x2, x6 = x3 * x3;
+    const double B = -7.0 / 3.0 * x3 - 1.5 * x2 + (0.45 + 0.35 * RB_SQRT29) * x + 0.075 * RB_SQRT29 + 0.775;
+    const double Cq = 5.0 / 72.0 * x6 + (1.0 / 32.0 - RB_SQRT29 / 48.0) * x4;
+    const double disc = B * B - 112.0 * Cq;
+    const double t = -2.0 * Cq / (B + sqrt(disc));
+    const double c0 = -RB_SQRT29 / 160.0 + 29.0 / 480.0;
+    a[0] = t - x3 / 12.0 + x2 / 8.0 + (RB_SQRT29 - 13.0) / 80.0 * x + c0;
+    a[1] = -3.0 * t + x3 / 6.0 - (7.0 + RB_SQRT29) / 40.0 * x + 0.25;
+    a[2] = 2.0 * t - 0.25 * x2 + RB_SQRT29 / 80.0 + 91.0 / 240.0;
+    a[3] = 2.0 * t - x3 / 6.0 + (7.0 + RB_SQRT29) / 40.0 * x + 0.25;
+    a[4] = -3.0 * t + x3 / 12.0 + x2 / 8.0 + (13.0 - RB_SQRT29) / 80.0 * x + c0;
+    a[5] = t;
+}
+
+// d a_q / dx, with t' from the quadratic: (56 t + B) t' = -(B' t + Cq'), 56 t + B = sqrt(disc)
+__device__ __forceinline__ void dphi6_values(double x, double da[6]) {
+    const double x2 = x * x, x3 = x2 * x, x4 = x2 * x2, x5 = x4 * x, x6 = x3 * x3;
+    const double B = -7.0 / 3.0 * x3 - 1.5 * x2 + (0.45 + 0.35 * RB_SQRT29) * x + 0.075 * RB_SQRT29 + 0.775;
+    const double Cq = 5.0 / 72.0 * x6 + (1.0 / 32.0 - RB_SQRT29 / 48.0) * x4;
+    const double sq = sqrt(B * B - 112.0 * Cq);
+    const double t = -2.0 * Cq / (B + sq);
+    const double dB = -7.0 * x2 - 3.0 * x + 0.45 + 0.35 * RB_SQRT29;
+    const double dCq = 5.0 / 12.0 * x5 + (1.0 / 8.0 - RB_SQRT29 / 12.0) * x3;
+    const double dt = -(dB * t + dCq) / sq;
+    da[0] = dt - 0.25 * x2 + 0.25 * x + (RB_SQRT29 - 13.0) / 80.0;
+    da[1] = -3.0 * dt + 0.5 * x2 - (7.0 + RB_SQRT29) / 40.0;
+    da[2] = 2.0 * dt - 0.5 * x;
+    da[3] = 2.0 * dt - 0.5 * x2 + (7.0 + RB_SQRT29) / 40.0;
+    da[4] = -3.0 * dt + 0.25 * x2 + 0.25 * x + (13.0 - RB_SQRT29) / 80.0;
+    da[5] = dt;
+}
+
+// support base and the W weights phi(s - p), p = base + q
+template <int W>
+__device__ __forceinline__ int kernel_weights(double s, double w[W]);
+template <>
+__device__ __forceinline__ int kernel_weights<4>(double s, double w[4]) {
+    const int b = (int)floor(s) - 1;
+    for (int q = 0; q < 4; ++q) w[q] = phi4(s - (double)(b + q));
+    return b;
+}
+template <>
+__device__ __forceinline__ int kernel_weights<6>(double s, double w[6]) {
+    const double f = floor(s);
+    phi6_values(s - f, w);
+    return (int)f - 2;
+}
+// the same with the derivatives d phi(s - p) / ds
+template <int W>
+__device__ __forceinline__ int kernel_weights_d(double s, double w[W], double dw[W]);
+template <>
+__device__ __forceinline__ int kernel_weights_d<4>(double s, double w[4], double dw[4]) {
+    const int b = (int)floor(s) - 1;
+    for (int q = 0; q < 4; ++q) { w[q] = phi4(s - (double)(b + q)); dw[q] = dphi4(s - (double)(b + q)); }
+    return b;
+}
+template <>
+__device__ __forceinline__ int kernel_weights_d<6>(double s, double w[6], double dw[6]) {
+    const double f = floor(s);
+    phi6_values(s - f, w);
+    dphi6_values(s - f, dw);
+    return (int)f - 2;
+}
+
 // 1-D folded weights of one marker coordinate for component c along axis a:
-// raw support base..base+3, folded index and signed weight (0 when dropped).
-__device__ __forceinline__ void axis_weights(const RepDev &R, double ra, int c, int a, int idx[4], double w[4],
-                                             int cross[4]) {
-    double s = ra * R.inv_h - (a == c ? 0.0 : 0.5);
-    int b = (int)floor(s) - 1;
-    for (int q = 0; q < 4; ++q) {
+// raw support base..base+W-1, folded index and signed weight (0 when dropped).
+template <int W>
+__device__ __forceinline__ void axis_weights(const RepDev &R, double ra, int c, int a, int idx[W], double w[W],
+                                             int cross[W]) {
+    const double s = ra * R.inv_h - (a == c ? 0.0 : 0.5);
+    double ph[W];
+    const int b = kernel_weights<W>(s, ph);
+    for (int q = 0; q < W; ++q) {
         int p = b + q;
         double sg;
         bool ok = fold_index(p, R.n[a], R.bc[a], a == c, idx[q], sg, cross[q]);
-        w[q] = ok ? sg * phi4(s - (double)p) : 0.0;
+        w[q] = ok ? sg * ph[q] : 0.0;
     }
 }
 
-// (J u)_c at marker position rm; u points at component c of the replica's fluid block.
-__device__ __forceinline__ double interp_comp(const RepDev &R, const double *rm, int c, const double *u) {
-    int idx[3][4], cr[3][4];
-    double w[3][4];
-    for (int a = 0; a < 3; ++a) axis_weights(R, rm[a], c, a, idx[a], w[a], cr[a]);
-    double acc = 0.0;
-    for (int z = 0; z < 4; ++z) {
-        if (w[2][z] == 0.0) continue;
-        for (int y = 0; y < 4; ++y) {
-            double wzy = w[2][z] * w[1][y];
-            if (wzy == 0.0) continue;
-            long long row = (long long)R.n[0] * ((long long)idx[1][y] + (long long)R.n[1] * idx[2][z]);
-            for (int x = 0; x < 4; ++x) acc += wzy * w[0][x] * u[row + idx[0][x]];
-        }
-    }
-    return acc;
-}
-
-// (J u)_c from the cached 1-D weights and folded indices of marker m.
-template <typename TU>
+// (J u)_c from the cached 1-D weights and folded indices of marker m (layout
+// [marker][component][axis][W]).
+template <int W, typename TU>
 __device__ __forceinline__ double interp_cached(const RepDev &R, const double *wc, const int *ic, int m, int c,
                                                const TU *u) {
-    const double *w = wc + (long long)(3 * m + c) * 12;
-    const int *ix = ic + (long long)(3 * m + c) * 12;
+    const double *w = wc + (long long)(3 * m + c) * 3 * W;
+    const int *ix = ic + (long long)(3 * m + c) * 3 * W;
     double acc = 0.0;
-    for (int z = 0; z < 4; ++z) {
-        double wz = w[8 + z];
+    for (int z = 0; z < W; ++z) {
+        double wz = w[2 * W + z];
         if (wz == 0.0) continue;
-        for (int y = 0; y < 4; ++y) {
-            double wzy = wz * w[4 + y];
+        for (int y = 0; y < W; ++y) {
+            double wzy = wz * w[W + y];
             if (wzy == 0.0) continue;
-            long long row = (long long)R.n[0] * ((long long)ix[4 + y] + (long long)R.n[1] * ix[8 + z]);
-            for (int x = 0; x < 4; ++x) acc += wzy * w[x] * (double)u[row + ix[x]];
+            long long row = (long long)R.n[0] * ((long long)ix[W + y] + (long long)R.n[1] * ix[2 * W + z]);
+            for (int x = 0; x < W; ++x) acc += wzy * w[x] * (double)u[row + ix[x]];
         }
     }
     return acc;
@@ -415,25 +477,27 @@ __device__ __forceinline__ double interp_cached(const RepDev &R, const double *w
 // Gradient with respect to the marker position of (J u)_c: the derivative along
 // axis a replaces phi_a by phi_a' / h; fold signs and indices are fixed within each
 // smooth piece of the kernel.
+template <int W>
 __device__ __forceinline__ void interp_grad(const RepDev &R, const double *rm, int c, const double *u, double g[3]) {
-    int idx[3][4], cr[3][4];
-    double w[3][4], dw[3][4];
+    int idx[3][W], cr[3][W];
+    double w[3][W], dw[3][W];
     for (int a = 0; a < 3; ++a) {
         double s = rm[a] * R.inv_h - (a == c ? 0.0 : 0.5);
-        int b = (int)floor(s) - 1;
-        for (int q = 0; q < 4; ++q) {
+        double ph[W], dph[W];
+        const int b = kernel_weights_d<W>(s, ph, dph);
+        for (int q = 0; q < W; ++q) {
             int p = b + q;
             double sg;
             bool ok = fold_index(p, R.n[a], R.bc[a], a == c, idx[a][q], sg, cr[a][q]);
-            w[a][q] = ok ? sg * phi4(s - (double)p) : 0.0;
-            dw[a][q] = ok ? sg * dphi4(s - (double)p) * R.inv_h : 0.0;
+            w[a][q] = ok ? sg * ph[q] : 0.0;
+            dw[a][q] = ok ? sg * dph[q] * R.inv_h : 0.0;
         }
     }
     g[0] = g[1] = g[2] = 0.0;
-    for (int z = 0; z < 4; ++z)
-        for (int y = 0; y < 4; ++y) {
+    for (int z = 0; z < W; ++z)
+        for (int y = 0; y < W; ++y) {
             long long row = (long long)R.n[0] * ((long long)idx[1][y] + (long long)R.n[1] * idx[2][z]);
-            for (int x = 0; x < 4; ++x) {
+            for (int x = 0; x < W; ++x) {
                 double v = u[row + idx[0][x]];
                 g[0] += dw[0][x] * w[1][y] * w[2][z] * v;
                 g[1] += w[0][x] * dw[1][y] * w[2][z] * v;
@@ -455,8 +519,8 @@ struct MarkerSet {
     int *pair_count = nullptr, *pair_start = nullptr, *pair_fill = nullptr;   // [ntiles]
     int *pair_m = nullptr, *pair_tile = nullptr;                              // [pair_cap]
     long long pair_cap = 0;
-    double *wc = nullptr;     // [nm][3 comp][3 axis][4] folded signed 1-D kernel weights
-    int *ic = nullptr;        // [nm][3][3][4] folded grid indices of those weights
+    double *wc = nullptr;     // [nm][3 comp][3 axis][W] folded signed 1-D kernel weights
+    int *ic = nullptr;        // [nm][3][3][W] folded grid indices of those weights
 };
 
 struct Timing {
@@ -479,6 +543,7 @@ struct Ctx {
     const int *mask = nullptr;               // replica mask for grid/body kernels (null = all)
     rbfib_opts opts;
     int nrep = 0;
+    int kw = 4;               // delta-kernel width (4 or 6), fixed at creation
     std::vector<RepDev> reps;
     long long L = 0;          // state length
     int nb = 0, nm = 0;

@@ -1,9 +1,9 @@
 // Immersed-boundary and rigid-body kernels (paper Sec. III.B, III.C):
 //   * marker geometry r_i = q_p + R(theta_p) r_i^ref and binning into 4^3-cell tiles;
 //   * spreading S as a deterministic GATHER: per marker configuration, a list of
-//     (tile, marker) pairs with the marker's 4-point weights folded onto the tile's
-//     4-cell window per axis; per application one workgroup per tile sums its pairs
-//     in marker order, one thread per target face -- no atomics;
+//     (tile, marker) pairs; per application one wavefront per tile projects its pairs'
+//     cached kernel weights (4- or 6-point) onto the tile's 4-cell window per axis in
+//     LDS and sums them in marker order, one lane per target cell -- no atomics;
 //   * interpolation J fused with K U and K^T lambda, one workgroup per body;
 //   * the per-body block of the preconditioner (dense body-frame blob mobility).
 // Walls fold the kernel support by odd reflection so that J = dV S^* holds exactly.
@@ -35,6 +35,7 @@ __device__ void marker_pos(const double *q, const double *th, const double *rr, 
     r[2] = q[2] + d[2];
 }
 
+template <int W>
 __global__ void k_markers(const RepDev *reps, const int *marker_body, const int *body_rep, const double *q,
                           const double *theta, const double *rref, int nm, double *r_out, double *d_out, int *tile,
                           int *tile_count, int *flags, double *wc, int *ic) {
@@ -72,11 +73,11 @@ __global__ void k_markers(const RepDev *reps, const int *marker_body, const int 
     // 1-D folded kernel weights, reused by every spread and interpolation at this configuration
     for (int c = 0; c < 3; ++c)
         for (int a = 0; a < 3; ++a) {
-            int idx[4], cr[4];
-            double w[4];
-            axis_weights(R, r[a], c, a, idx, w, cr);
-            long long o = ((long long)(3 * m + c) * 3 + a) * 4;
-            for (int k = 0; k < 4; ++k) { wc[o + k] = w[k]; ic[o + k] = idx[k]; }
+            int idx[W], cr[W];
+            double w[W];
+            axis_weights<W>(R, r[a], c, a, idx, w, cr);
+            long long o = ((long long)(3 * m + c) * 3 + a) * W;
+            for (int k = 0; k < W; ++k) { wc[o + k] = w[k]; ic[o + k] = idx[k]; }
         }
     if (outside) atomicOr(&flags[body_rep[p]], 1);
 }
@@ -204,33 +205,37 @@ __global__ void k_tile_sort(const int *start, const int *count, int *perm, int n
 // Spreading is built once per marker configuration as a list of (target tile,
 // marker) pairs, sorted by tile and, within a tile, by marker id.  A marker pairs
 // with every tile that holds, on each axis, a nonzero folded weight of one of its
-// three staggered components.  The union of the three 4-point supports along an
-// axis covers at most five consecutive cells (wrapped on periodic axes, folded into
-// the domain at walls), so it meets at most two 4-cell tiles, three where a periodic
-// axis ends in a partial tile.  Each pair carries the marker's 1-D weights folded
-// onto the tile's 4-cell window per component and axis.
+// three staggered components.  The union of the three W-point supports along an
+// axis covers at most W + 1 consecutive cells (wrapped on periodic axes, folded into
+// the domain at walls), so it meets at most W/2 4-cell tiles, one more where a
+// periodic axis ends in a partial tile.  The spreading kernel projects each pair's
+// cached 1-D weights onto the tile's 4-cell window.
 struct AxisTiles {
-    int k = 0, t0 = 0, t1 = 0, t2 = 0;
+    int k = 0, t0 = 0, t1 = 0, t2 = 0, t3 = 0;   // scalars, not an array: no private memory
 };
 
 __device__ __forceinline__ void add_tile(AxisTiles &s, int t, bool &over) {
-    if ((s.k > 0 && s.t0 == t) || (s.k > 1 && s.t1 == t) || (s.k > 2 && s.t2 == t)) return;
+    if ((s.k > 0 && s.t0 == t) || (s.k > 1 && s.t1 == t) || (s.k > 2 && s.t2 == t) || (s.k > 3 && s.t3 == t)) return;
     if (s.k == 0) s.t0 = t;
     else if (s.k == 1) s.t1 = t;
     else if (s.k == 2) s.t2 = t;
+    else if (s.k == 3) s.t3 = t;
     else { over = true; return; }
     ++s.k;
 }
 
-__device__ __forceinline__ int tile_at(const AxisTiles &s, int i) { return i == 0 ? s.t0 : (i == 1 ? s.t1 : s.t2); }
+__device__ __forceinline__ int tile_at(const AxisTiles &s, int i) {
+    return i == 0 ? s.t0 : (i == 1 ? s.t1 : (i == 2 ? s.t2 : s.t3));
+}
 
+template <int W>
 __device__ __forceinline__ AxisTiles marker_axis_tiles(const double *wc, const int *ic, int m, int a, bool &over) {
     AxisTiles s;
 #pragma unroll
     for (int c = 0; c < 3; ++c)
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const long long o = ((long long)(3 * m + c) * 3 + a) * 4 + q;
+        for (int q = 0; q < W; ++q) {
+            const long long o = ((long long)(3 * m + c) * 3 + a) * W + q;
             if (wc[o] != 0.0) add_tile(s, ic[o] / RB_TILE, over);
         }
     return s;
@@ -240,6 +245,7 @@ __device__ __forceinline__ AxisTiles marker_axis_tiles(const double *wc, const i
 // given by the exclusive scan of the counts (unordered within a tile).  A marker
 // whose supports break the bound above (non-finite position) or a slot beyond the
 // capacity flags its replica.
+template <int W>
 __global__ void k_pair_tiles(const RepDev *reps, const int *marker_body, const int *body_rep, const double *wc,
                              const int *ic, int nm, int place, int *pair_count, const int *pair_start, int *pair_fill,
                              int *pair_m, int *pair_tile, long long cap, int *flags) {
@@ -248,9 +254,9 @@ __global__ void k_pair_tiles(const RepDev *reps, const int *marker_body, const i
     const int rep = body_rep[marker_body[m]];
     const RepDev &R = reps[rep];
     bool over = false;
-    const AxisTiles X = marker_axis_tiles(wc, ic, m, 0, over);
-    const AxisTiles Y = marker_axis_tiles(wc, ic, m, 1, over);
-    const AxisTiles Z = marker_axis_tiles(wc, ic, m, 2, over);
+    const AxisTiles X = marker_axis_tiles<W>(wc, ic, m, 0, over);
+    const AxisTiles Y = marker_axis_tiles<W>(wc, ic, m, 1, over);
+    const AxisTiles Z = marker_axis_tiles<W>(wc, ic, m, 2, over);
     for (int z = 0; z < Z.k; ++z)
         for (int y = 0; y < Y.k; ++y)
             for (int x = 0; x < X.k; ++x) {
@@ -266,16 +272,15 @@ __global__ void k_pair_tiles(const RepDev *reps, const int *marker_body, const i
     if (over) atomicOr(&flags[rep], 1);
 }
 
-// counts_zeroed: the caller has already cleared tile_count and pair_count (the
-// allocation-free entry point does it in its set-up kernel instead of a memset).
-void launch_markers(Ctx &c, MarkerSet &ms, const double *q, const double *theta, bool counts_zeroed) {
+template <int W>
+static void markers_w(Ctx &c, MarkerSet &ms, const double *q, const double *theta, bool counts_zeroed) {
     if (!counts_zeroed) {
         HIP_OK(hipMemsetAsync(ms.tile_count, 0, sizeof(int) * c.ntiles, c.stream));
         HIP_OK(hipMemsetAsync(ms.pair_count, 0, sizeof(int) * c.ntiles, c.stream));
     }
     int nb = (c.nm + 255) / 256;
     if (c.nm > 0)
-        hipLaunchKernelGGL(k_markers, dim3(nb), dim3(256), 0, c.stream, c.d_reps, c.d_marker_body, c.d_body_rep, q,
+        hipLaunchKernelGGL(k_markers<W>, dim3(nb), dim3(256), 0, c.stream, c.d_reps, c.d_marker_body, c.d_body_rep, q,
                            theta, c.d_rref, c.nm, ms.r, ms.d, ms.tile, ms.tile_count, c.d_flags, ms.wc, ms.ic);
     scan_tiles(c, ms.tile_count, ms.tile_start, ms.tile_fill);
     if (c.nm > 0) {
@@ -283,13 +288,13 @@ void launch_markers(Ctx &c, MarkerSet &ms, const double *q, const double *theta,
                            ms.perm, c.nm);
         hipLaunchKernelGGL(k_tile_sort, dim3((c.ntiles + 255) / 256), dim3(256), 0, c.stream, ms.tile_start,
                            ms.tile_count, ms.perm, c.ntiles, (long long)c.nm);
-        hipLaunchKernelGGL(k_pair_tiles, dim3(nb), dim3(256), 0, c.stream, c.d_reps, c.d_marker_body, c.d_body_rep,
+        hipLaunchKernelGGL(k_pair_tiles<W>, dim3(nb), dim3(256), 0, c.stream, c.d_reps, c.d_marker_body, c.d_body_rep,
                            ms.wc, ms.ic, c.nm, 0, ms.pair_count, ms.pair_start, ms.pair_fill, ms.pair_m,
                            ms.pair_tile, ms.pair_cap, c.d_flags);
     }
     scan_tiles(c, ms.pair_count, ms.pair_start, ms.pair_fill);
     if (c.nm > 0) {
-        hipLaunchKernelGGL(k_pair_tiles, dim3(nb), dim3(256), 0, c.stream, c.d_reps, c.d_marker_body, c.d_body_rep,
+        hipLaunchKernelGGL(k_pair_tiles<W>, dim3(nb), dim3(256), 0, c.stream, c.d_reps, c.d_marker_body, c.d_body_rep,
                            ms.wc, ms.ic, c.nm, 1, ms.pair_count, ms.pair_start, ms.pair_fill, ms.pair_m,
                            ms.pair_tile, ms.pair_cap, c.d_flags);
         hipLaunchKernelGGL(k_tile_sort, dim3((c.ntiles + 255) / 256), dim3(256), 0, c.stream, ms.pair_start,
@@ -298,10 +303,17 @@ void launch_markers(Ctx &c, MarkerSet &ms, const double *q, const double *theta,
     compact_tiles(c, ms.pair_count, ms.active, ms.n_active);
 }
 
+// counts_zeroed: the caller has already cleared tile_count and pair_count (the
+// allocation-free entry point does it in its set-up kernel instead of a memset).
+void launch_markers(Ctx &c, MarkerSet &ms, const double *q, const double *theta, bool counts_zeroed) {
+    if (c.kw == 6) markers_w<6>(c, ms, q, theta, counts_zeroed);
+    else markers_w<4>(c, ms, q, theta, counts_zeroed);
+}
+
 // ------------------------------------------------------------------ spreading (gather)
 // One wavefront per tile that has pairs, one lane per (x, y, z) cell of the tile.  The
 // tile's pairs are taken SPREAD_P at a time: lane i loads the cached folded 1-D
-// weights of pair i's marker (3 components x 3 axes x 4 points, with their folded
+// weights of pair i's marker (3 components x 3 axes x W points, with their folded
 // indices) and its lambda, projects them onto the tile's 4-cell window on each axis
 // (several support points can fold onto one cell next to a wall), folds lambda_c into
 // the z factor, and leaves the 36 window weights in LDS; then every lane sums, for the
@@ -312,7 +324,32 @@ void launch_markers(Ctx &c, MarkerSet &ms, const double *q, const double *theta,
 // TO = double: y is a state vector (velocity of replica r at R.off + c N);
 // with levs given: y is a multigrid pool, level 0 of each replica.
 #define SPREAD_P 32
-template <typename TO, typename TL>
+// the cached folded weights and indices of (marker m, component c, axis a)
+template <int W>
+__device__ __forceinline__ void load_axis(const double *__restrict__ wc, const int *__restrict__ ic, long long o,
+                                          double w[W], int ix[W]);
+template <>
+__device__ __forceinline__ void load_axis<4>(const double *__restrict__ wc, const int *__restrict__ ic, long long o,
+                                             double w[4], int ix[4]) {
+    const double2 w01 = *reinterpret_cast<const double2 *>(wc + o);
+    const double2 w23 = *reinterpret_cast<const double2 *>(wc + o + 2);
+    const int4 i4 = *reinterpret_cast<const int4 *>(ic + o);
+    w[0] = w01.x; w[1] = w01.y; w[2] = w23.x; w[3] = w23.y;
+    ix[0] = i4.x; ix[1] = i4.y; ix[2] = i4.z; ix[3] = i4.w;
+}
+template <>
+__device__ __forceinline__ void load_axis<6>(const double *__restrict__ wc, const int *__restrict__ ic, long long o,
+                                             double w[6], int ix[6]) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const double2 wk = *reinterpret_cast<const double2 *>(wc + o + 2 * k);
+        const int2 ik = *reinterpret_cast<const int2 *>(ic + o + 2 * k);
+        w[2 * k] = wk.x; w[2 * k + 1] = wk.y;
+        ix[2 * k] = ik.x; ix[2 * k + 1] = ik.y;
+    }
+}
+
+template <typename TO, typename TL, int W>
 __global__ __launch_bounds__(64) void k_spread(const RepDev *reps, const int *tile_rep, const int *active,
                                                const int *n_active, const int *pair_start, const int *pair_count,
                                                long long cap, const int *__restrict__ pair_m,
@@ -346,17 +383,14 @@ __global__ __launch_bounds__(64) void k_spread(const RepDev *reps, const int *ti
                     const double lc = (double)lam[c];
 #pragma unroll
                     for (int a = 0; a < 3; ++a) {
-                        const long long o = ((long long)(3 * m + c) * 3 + a) * 4;
-                        const double2 w01 = *reinterpret_cast<const double2 *>(wc + o);
-                        const double2 w23 = *reinterpret_cast<const double2 *>(wc + o + 2);
-                        const int4 ix = *reinterpret_cast<const int4 *>(ic + o);
-                        const double w[4] = {w01.x, w01.y, w23.x, w23.y};
-                        const int loc[4] = {ix.x - org[a], ix.y - org[a], ix.z - org[a], ix.w - org[a]};
+                        double w[W];
+                        int ix[W];
+                        load_axis<W>(wc, ic, ((long long)(3 * m + c) * 3 + a) * W, w, ix);
 #pragma unroll
                         for (int k = 0; k < 4; ++k) {
                             double v = 0.0;
 #pragma unroll
-                            for (int q = 0; q < 4; ++q) v += (loc[q] == k) ? w[q] : 0.0;
+                            for (int q = 0; q < W; ++q) v += (ix[q] - org[a] == k) ? w[q] : 0.0;
                             dst[(c * 3 + a) * 4 + k] = (a == 2) ? v * lc : v;
                         }
                     }
@@ -387,9 +421,14 @@ template <typename TO, typename TL>
 static void spread_into(Ctx &c, MarkerSet &ms, const TL *lam_state, TO *y, double alpha, const LevDev *levs) {
     if (c.nm == 0) return;
     int grid = std::min(c.ntiles, 65536);   // grid-stride over the tiles that have pairs
-    hipLaunchKernelGGL((k_spread<TO, TL>), dim3(grid), dim3(64), 0, c.stream, c.d_reps, c.d_tile_rep, ms.active,
-                       ms.n_active, ms.pair_start, ms.pair_count, ms.pair_cap, ms.pair_m, ms.wc, ms.ic, lam_state,
-                       y, alpha, c.mask, levs);
+    if (c.kw == 6)
+        hipLaunchKernelGGL((k_spread<TO, TL, 6>), dim3(grid), dim3(64), 0, c.stream, c.d_reps, c.d_tile_rep, ms.active,
+                           ms.n_active, ms.pair_start, ms.pair_count, ms.pair_cap, ms.pair_m, ms.wc, ms.ic,
+                           lam_state, y, alpha, c.mask, levs);
+    else
+        hipLaunchKernelGGL((k_spread<TO, TL, 4>), dim3(grid), dim3(64), 0, c.stream, c.d_reps, c.d_tile_rep, ms.active,
+                           ms.n_active, ms.pair_start, ms.pair_count, ms.pair_cap, ms.pair_m, ms.wc, ms.ic,
+                           lam_state, y, alpha, c.mask, levs);
 }
 
 // y_fluid += alpha * S lambda, lambda read from the lambda slots of lam_state.
@@ -411,7 +450,7 @@ template void launch_spread_level0<double, double>(Ctx &, MarkerSet &, const dou
 
 // ------------------------------------------------------------------ J, K, K^T per body
 // y_lambda = -J v + K U ;  y_U = K^T lambda  (rows 3 and 4 of the saddle operator).
-template <typename TX>
+template <typename TX, int W>
 __global__ void k_body_apply(const RepDev *reps, const int *body_rep, const int *body_off, const double *r,
                              const double *d, const TX *__restrict__ x, double *__restrict__ y,
                              const int *__restrict__ mask, const double *__restrict__ wc, const int *__restrict__ ic) {
@@ -426,7 +465,7 @@ __global__ void k_body_apply(const RepDev *reps, const int *body_rep, const int 
     for (int k = 0; k < 6; ++k) U[k] = (double)x[U0 + k];
     for (int task = threadIdx.x; task < 3 * nmp; task += blockDim.x) {
         int i = task / 3, c = task % 3, m = m0 + i;
-        double Jv = interp_cached(R, wc, ic, m, c, x + R.off + c * R.N);
+        double Jv = interp_cached<W>(R, wc, ic, m, c, x + R.off + c * R.N);
         const double *dm = d + 3 * m;
         double wxd[3] = {U[4] * dm[2] - U[5] * dm[1], U[5] * dm[0] - U[3] * dm[2], U[3] * dm[1] - U[4] * dm[0]};
         y[lam0 + 3LL * (m - R.m0) + c] = -Jv + U[c] + wxd[c];
@@ -456,14 +495,19 @@ void launch_body_apply(Ctx &c, MarkerSet &ms, const double *q, const TX *x, doub
     (void)q;
     if (c.nb == 0) return;
     size_t sh = sizeof(double) * 6 * (size_t)c.max_body_nm;
-    hipLaunchKernelGGL(k_body_apply<TX>, dim3(c.nb), dim3(128), sh, c.stream, c.d_reps, c.d_body_rep, c.d_body_off, ms.r,
-                       ms.d, x, y, c.mask, ms.wc, ms.ic);
+    if (c.kw == 6)
+        hipLaunchKernelGGL((k_body_apply<TX, 6>), dim3(c.nb), dim3(128), sh, c.stream, c.d_reps, c.d_body_rep,
+                           c.d_body_off, ms.r, ms.d, x, y, c.mask, ms.wc, ms.ic);
+    else
+        hipLaunchKernelGGL((k_body_apply<TX, 4>), dim3(c.nb), dim3(128), sh, c.stream, c.d_reps, c.d_body_rep,
+                           c.d_body_off, ms.r, ms.d, x, y, c.mask, ms.wc, ms.ic);
 }
 template void launch_body_apply<double>(Ctx &, MarkerSet &, const double *, const double *, double *);
 template void launch_body_apply<float>(Ctx &, MarkerSet &, const double *, const float *, double *);
 
 // ------------------------------------------------------------------ interpolation
 // out[m, c] (= or +=) alpha * (J u)_c at markers of ms; u is a state vector.
+template <int W>
 __global__ void k_interp(const RepDev *reps, const int *marker_body, const int *body_rep, const double *wc,
                          const int *ic, int nm, const double *__restrict__ u, double *__restrict__ out, double alpha,
                          int accumulate) {
@@ -471,19 +515,20 @@ __global__ void k_interp(const RepDev *reps, const int *marker_body, const int *
     if (task >= 3 * nm) return;
     int m = task / 3, c = task % 3;
     const RepDev &R = reps[body_rep[marker_body[m]]];
-    double v = alpha * interp_cached(R, wc, ic, m, c, u + R.off + c * R.N);
+    double v = alpha * interp_cached<W>(R, wc, ic, m, c, u + R.off + c * R.N);
     if (accumulate) out[task] += v; else out[task] = v;
 }
 
 void launch_interp(Ctx &c, MarkerSet &ms, const double *u, double *out, double alpha, bool accumulate) {
     if (c.nm == 0) return;
-    hipLaunchKernelGGL(k_interp, dim3((3 * c.nm + 255) / 256), dim3(256), 0, c.stream, c.d_reps, c.d_marker_body,
-                       c.d_body_rep, ms.wc, ms.ic, c.nm, u, out, alpha, accumulate ? 1 : 0);
+    hipLaunchKernelGGL(c.kw == 6 ? k_interp<6> : k_interp<4>, dim3((3 * c.nm + 255) / 256), dim3(256), 0, c.stream,
+                       c.d_reps, c.d_marker_body, c.d_body_rep, ms.wc, ms.ic, c.nm, u, out, alpha, accumulate ? 1 : 0);
 }
 
 // Affine part of interpolation next to sliding walls: for each support point across a
 // wall moving with tangential velocity U (component c), add w * 2U * (product of the
 // signs of the point's other reflections).  out[m, c] += alpha * J_bc.
+template <int W>
 __global__ void k_interp_bc(const RepDev *reps, const int *marker_body, const int *body_rep, const double *r, int nm,
                             double *__restrict__ out, double alpha) {
     int task = blockIdx.x * blockDim.x + threadIdx.x;
@@ -491,13 +536,13 @@ __global__ void k_interp_bc(const RepDev *reps, const int *marker_body, const in
     int m = task / 3, c = task % 3;
     const RepDev &R = reps[body_rep[marker_body[m]]];
     if (!R.movwall) return;
-    int idx[3][4], cr[3][4];
-    double w[3][4];
-    for (int a = 0; a < 3; ++a) axis_weights(R, r[3 * m + a], c, a, idx[a], w[a], cr[a]);
+    int idx[3][W], cr[3][W];
+    double w[3][W];
+    for (int a = 0; a < 3; ++a) axis_weights<W>(R, r[3 * m + a], c, a, idx[a], w[a], cr[a]);
     double acc = 0.0;
-    for (int z = 0; z < 4; ++z)
-        for (int y = 0; y < 4; ++y)
-            for (int x = 0; x < 4; ++x) {
+    for (int z = 0; z < W; ++z)
+        for (int y = 0; y < W; ++y)
+            for (int x = 0; x < W; ++x) {
                 double wt = w[0][x] * w[1][y] * w[2][z];
                 if (wt == 0.0) continue;
                 int crs[3] = {cr[0][x], cr[1][y], cr[2][z]};
@@ -516,8 +561,8 @@ __global__ void k_interp_bc(const RepDev *reps, const int *marker_body, const in
 
 void launch_interp_bc(Ctx &c, MarkerSet &ms, double *out, double alpha) {
     if (c.nm == 0) return;
-    hipLaunchKernelGGL(k_interp_bc, dim3((3 * c.nm + 255) / 256), dim3(256), 0, c.stream, c.d_reps, c.d_marker_body,
-                       c.d_body_rep, ms.r, c.nm, out, alpha);
+    hipLaunchKernelGGL(c.kw == 6 ? k_interp_bc<6> : k_interp_bc<4>, dim3((3 * c.nm + 255) / 256), dim3(256), 0,
+                       c.stream, c.d_reps, c.d_marker_body, c.d_body_rep, ms.r, c.nm, out, alpha);
 }
 
 // ------------------------------------------------------------------ body block of P^-1

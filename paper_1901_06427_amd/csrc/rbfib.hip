@@ -719,7 +719,8 @@ static void validate(int nrep, const rbfib_grid *grids, const rbfib_bodies *bodi
     if (!(o.tol > 0.0) || o.restart < 1 || o.restart > 200 || o.max_iter < 1 || o.mg_sweeps < 1 ||
         !(o.mg_omega > 0.0) || !(o.blob_radius > 0.0) || !(o.rfd_delta > 0.0) || o.mg_bottom < 0 || o.mg_bottom > MGB_LDS / 1024 ||
         !(o.mg_cheby >= 0.0 && o.mg_cheby < 2.0) || o.mg_sweeps > RB_MAXSWEEP || o.mg_sweeps_p < 0 ||
-        o.mg_sweeps_p > RB_MAXSWEEP || o.krylov_s < 1 || o.krylov_s > RB_MAXS || (o.mg_first2 != 0 && o.mg_first2 != 1))
+        o.mg_sweeps_p > RB_MAXSWEEP || o.krylov_s < 1 || o.krylov_s > RB_MAXS || (o.mg_first2 != 0 && o.mg_first2 != 1) ||
+        (o.kernel != 4 && o.kernel != 6))
         throw (int)RBFIB_EINVAL;
     for (int r = 0; r < nrep; ++r) {
         const rbfib_grid &g = grids[r];
@@ -1012,20 +1013,21 @@ static void build(Ctx &c, int nrep, const rbfib_grid *grids, const rbfib_bodies 
     c.h_body_len = body_len;
 
     // ---- marker sets
-    // spreading pairs: at most two tiles per axis per marker, three on a periodic
-    // axis whose last tile is partial, never more than the axis has
+    // spreading pairs: at most W/2 tiles per axis per marker (the union of the
+    // components' W-point supports spans W + 1 cells), one more on a periodic axis
+    // whose last tile is partial, never more than the axis has
     long long pair_cap = 0;
     for (const RepDev &R : c.reps) {
         long long per = 1;
         for (int a = 0; a < 3; ++a) {
-            int b = (R.bc[a] == RBFIB_PERIODIC && R.n[a] % RB_TILE != 0) ? 3 : 2;
+            int b = c.kw / 2 + ((R.bc[a] == RBFIB_PERIODIC && R.n[a] % RB_TILE != 0) ? 1 : 0);
             per *= std::min(b, R.tdim[a]);
         }
         pair_cap += per * R.nm;
     }
     pair_cap = std::max(pair_cap, 1LL);
-    // tile-start offsets are int: even 27 pairs per marker must fit
-    if (27LL * c.nm > 2147483647LL) throw (int)RBFIB_EINVAL;
+    // tile-start offsets are int: even 64 pairs per marker must fit
+    if (64LL * c.nm > 2147483647LL) throw (int)RBFIB_EINVAL;
     for (int k = 0; k < 4; ++k) {
         MarkerSet &ms = c.ms[k];
         ms.r = dalloc<double>(3 * (size_t)c.nm);
@@ -1037,8 +1039,8 @@ static void build(Ctx &c, int nrep, const rbfib_grid *grids, const rbfib_bodies 
         ms.tile_fill = dalloc<int>(c.ntiles);
         ms.active = dalloc<int>(c.ntiles);
         ms.n_active = dalloc<int>(1);
-        ms.wc = dalloc<double>(36 * (size_t)std::max(c.nm, 1));
-        ms.ic = dalloc<int>(36 * (size_t)std::max(c.nm, 1));
+        ms.wc = dalloc<double>(9 * (size_t)c.kw * std::max(c.nm, 1));
+        ms.ic = dalloc<int>(9 * (size_t)c.kw * std::max(c.nm, 1));
         ms.pair_cap = pair_cap;
         ms.pair_count = dalloc<int>(c.ntiles);
         ms.pair_start = dalloc<int>(c.ntiles);
@@ -1186,6 +1188,7 @@ void rbfib_default_opts(rbfib_opts *o) {
     o->mg_cheby = 0.27;
     o->krylov_s = 2;
     o->mg_first2 = 1;
+    o->kernel = 4;
 }
 
 const char *rbfib_strerror(int code) {
@@ -1219,6 +1222,7 @@ int rbfib_create_batch(int nrep, const rbfib_grid *grids, const rbfib_bodies *bo
         HIP_OK(hipEventCreateWithFlags(&ctx->c.ev_in, hipEventDisableTiming));
         HIP_OK(hipEventCreateWithFlags(&ctx->c.ev_out, hipEventDisableTiming));
         ctx->c.opts = o;
+        ctx->c.kw = o.kernel;
         build(ctx->c, nrep, grids, bodies);
         *out = ctx;
         return RBFIB_OK;
@@ -1251,9 +1255,9 @@ int rbfib_set_opts(rbfib_ctx *ctx, const rbfib_opts *o) {
         o->mg_sweeps_p > RB_MAXSWEEP || o->krylov_s < 1 || o->krylov_s > RB_MAXS ||
         (o->mg_first2 != 0 && o->mg_first2 != 1))
         return RBFIB_EINVAL;
-    // fields fixed at creation: restart length, precision, blob radius, bottom kernel
+    // fields fixed at creation: restart length, precision, blob radius, bottom kernel, delta kernel
     if (o->restart != c.opts.restart || (o->precond_fp32 != 0) != c.mg_fp32 || o->blob_radius != c.opts.blob_radius ||
-        o->mg_bottom != c.opts.mg_bottom)
+        o->mg_bottom != c.opts.mg_bottom || o->kernel != c.kw)
         return RBFIB_EINVAL;
     if (o->mg_sweeps != c.opts.mg_sweeps || o->mg_sweeps_p != c.opts.mg_sweeps_p || o->mg_omega != c.opts.mg_omega ||
         o->mg_cheby != c.opts.mg_cheby || o->krylov_s != c.opts.krylov_s ||

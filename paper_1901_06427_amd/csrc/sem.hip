@@ -49,6 +49,7 @@ void launch_body_rfd(Ctx &c, double kT, double delta, uint64_t seed, uint64_t st
 }
 
 // slip_acc[m, c] = D^K - D^J  at every marker (Q+ in ms_p, Q- in ms_m; xR holds v^R and U^R).
+template <int W>
 __global__ void k_rfd_markers(const RepDev *reps, const int *marker_body, const int *body_rep, int nm,
                               const double *wcp, const int *icp, const double *dp, const double *wcm, const int *icm,
                               const double *dm, const double *__restrict__ xR, double inv_delta,
@@ -65,7 +66,7 @@ __global__ void k_rfd_markers(const RepDev *reps, const int *marker_body, const 
     double km[3] = {UR[4] * b[2] - UR[5] * b[1], UR[5] * b[0] - UR[3] * b[2], UR[3] * b[1] - UR[4] * b[0]};
     double DK = ((UR[c] + kp[c]) - (UR[c] + km[c])) * inv_delta;
     const double *u = xR + R.off + c * R.N;
-    double DJ = (interp_cached(R, wcp, icp, m, c, u) - interp_cached(R, wcm, icm, m, c, u)) * inv_delta;
+    double DJ = (interp_cached<W>(R, wcp, icp, m, c, u) - interp_cached<W>(R, wcm, icm, m, c, u)) * inv_delta;
     slip_acc[t] = DK - DJ;
 }
 
@@ -90,7 +91,7 @@ __global__ void k_rfd_bodies(const RepDev *reps, const int *body_rep, const int 
 void launch_rfd_terms(Ctx &c, double delta) {
     if (c.nm == 0) return;
     double inv = 1.0 / delta;
-    hipLaunchKernelGGL(k_rfd_markers, dim3((3 * c.nm + 255) / 256), dim3(256), 0, c.stream, c.d_reps,
+    hipLaunchKernelGGL(c.kw == 6 ? k_rfd_markers<6> : k_rfd_markers<4>, dim3((3 * c.nm + 255) / 256), dim3(256), 0, c.stream, c.d_reps,
                        c.d_marker_body, c.d_body_rep, c.nm, c.ms[1].wc, c.ms[1].ic, c.ms[1].d, c.ms[2].wc,
                        c.ms[2].ic, c.ms[2].d, c.xR, inv, c.slip_acc);
 }
@@ -102,6 +103,7 @@ void launch_rfd_forces(Ctx &c, double delta, const double *FT) {
 }
 
 // b_lambda[m] = -(slip + slip_acc - D^S) + J_bc, with D^S = J(Q^n) v#  (v# in xS).
+template <int W>
 __global__ void k_sem_rhs_lambda(const RepDev *reps, const int *marker_body, const int *body_rep, int nm,
                                  const double *wc, const int *ic, const double *slip, const double *slip_acc,
                                  const double *__restrict__ xS, double *__restrict__ b) {
@@ -109,14 +111,14 @@ __global__ void k_sem_rhs_lambda(const RepDev *reps, const int *marker_body, con
     if (t >= 3 * nm) return;
     int m = t / 3, c = t % 3;
     const RepDev &R = reps[body_rep[marker_body[m]]];
-    double DS = interp_cached(R, wc, ic, m, c, xS + R.off + c * R.N);
+    double DS = interp_cached<W>(R, wc, ic, m, c, xS + R.off + c * R.N);
     double s2 = slip_acc[t] - DS + (slip ? slip[t] : 0.0);
     b[R.off + 4 * R.N + 3LL * (m - R.m0) + c] = -s2;
 }
 
 void launch_sem_rhs_lambda(Ctx &c, const double *slip, double *b) {
     if (c.nm == 0) return;
-    hipLaunchKernelGGL(k_sem_rhs_lambda, dim3((3 * c.nm + 255) / 256), dim3(256), 0, c.stream, c.d_reps,
+    hipLaunchKernelGGL(c.kw == 6 ? k_sem_rhs_lambda<6> : k_sem_rhs_lambda<4>, dim3((3 * c.nm + 255) / 256), dim3(256), 0, c.stream, c.d_reps,
                        c.d_marker_body, c.d_body_rep, c.nm, c.ms[0].wc, c.ms[0].ic, slip, c.slip_acc, c.xS, b);
 }
 

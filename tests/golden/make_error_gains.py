@@ -32,7 +32,7 @@ def _gain(args):
     from oracle.saddle import Saddle
     from tests.parity_configs import gain_configs
     w = gain_configs()[name]
-    g = mac.Grid(w.n, w.bc, w.h, w.eta, w.wall_vel)
+    g = mac.Grid(w.n, w.bc, w.h, w.eta, w.wall_vel, kernel=w.kernel)
     assert g.h == 1.0, "the gains use A^T = A, which holds at h = 1"
     s = Saddle(g, w.q, w.theta, w.r_ref, w.offsets)
     e = np.zeros(6 * w.nb)

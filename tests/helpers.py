@@ -9,7 +9,7 @@ from oracle import mac
 
 
 def oracle_grid(w) -> mac.Grid:
-    return mac.Grid(w.n, w.bc, w.h, w.eta, w.wall_vel)
+    return mac.Grid(w.n, w.bc, w.h, w.eta, w.wall_vel, kernel=getattr(w, "kernel", 4))
 
 
 def pack_state(g: mac.Grid, v, p, lam, U) -> np.ndarray:
@@ -42,6 +42,9 @@ def lib_context(rb, ws, **opt_kw):
     if not isinstance(ws, (list, tuple)):
         ws = [ws]
     grids = [rb.make_grid(w.n, w.bc, w.h, w.eta, w.wall_vel) for w in ws]
+    opt_kw.setdefault("kernel", getattr(ws[0], "kernel", 4))
+    if opt_kw["kernel"] == 6:
+        opt_kw.setdefault("blob_radius", 1.4)     # the 6-point blob is larger (1.47 h)
     opts = rb.rbfib_default_opts(**opt_kw)
     return rb.rbfib_create_batch(grids, [w.r_ref for w in ws], [w.offsets for w in ws], opts)
 

@@ -44,6 +44,22 @@ def ensemble_replicas():
     return {"ensemble16_4spheres": a, "ensemble48": b}
 
 
+def kernel6_configs():
+    """The paper's 6-point kernel on walled, periodic (with a one-cell last tile and a
+    wrap), ragged, sliding-wall and ensemble-like boxes."""
+    import copy
+    base = solve_configs()
+    out = {}
+    for name in ("ragged_10x12x14", "periodic_wrap_17x12x12", "monolayer_64x32x16", "ensemble16_4spheres"):
+        w = copy.deepcopy(base[name])
+        w.kernel = 6
+        out[name + "_k6"] = w
+    w = copy.deepcopy(sem_configs()["two_spheres_16x16x32"])
+    w.kernel = 6
+    out["two_spheres_16x16x32_k6"] = w
+    return out
+
+
 def sem_configs():
     return {
         "two_spheres_16x16x32": W.spheres_in_box(31, (16, 16, 32), 2, name="two_small"),
@@ -68,4 +84,7 @@ def gain_configs():
     out.pop("periodic_wrap_17x12x12")          # apply only
     for k, w in sem_configs().items():
         out.setdefault(k, w)
+    for k, w in kernel6_configs().items():
+        if k != "monolayer_64x32x16_k6":          # apply only
+            out[k] = w
     return out

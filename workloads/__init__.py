@@ -98,6 +98,7 @@ class Workload:
     dt: float = 0.0
     tol: float = 1e-8
     seed: int = 0
+    kernel: int = 4               # width of the delta kernel (4 or 6)
 
     @property
     def nb(self) -> int:
