@@ -175,6 +175,6 @@ def inside_open_domain(g: Grid, r: np.ndarray) -> bool:
     """True when every marker lies strictly inside the box along every wall axis."""
     L = np.array(g.n) * g.h
     for a in range(3):
-        if g.bc[a] == WALL and (np.any(r[:, a] <= 0.0) or np.any(r[:, a] >= L[a])):
+        if g.bc[a] != PERIODIC and (np.any(r[:, a] <= 0.0) or np.any(r[:, a] >= L[a])):
             return False
     return bool(np.all(np.isfinite(r)))

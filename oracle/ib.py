@@ -40,7 +40,7 @@ from __future__ import annotations
 import numpy as np
 import scipy.sparse as sp
 
-from .mac import Grid, PERIODIC, WALL, _face_col
+from .mac import Grid, PERIODIC, SLIP, WALL, _face_col
 
 
 def phi4(r):
@@ -166,6 +166,9 @@ def fold(g: Grid, c: int, a: int, p: np.ndarray):
     idx = p.copy()
     sign = np.ones(p.shape)
     crossed = np.zeros(p.shape, dtype=np.int64)
+    # the reflected value's sign: the normal component is odd about any wall, a
+    # tangential one odd about a no-slip wall and even about a free-slip wall
+    refl = 1.0 if (a != c and g.bc[a] == SLIP) else -1.0
     if a == c:
         valid = (p != 0) & (p != N)
         lo = p < 0
@@ -178,7 +181,7 @@ def fold(g: Grid, c: int, a: int, p: np.ndarray):
         hi = p >= N
         idx[lo] = -1 - p[lo]
         idx[hi] = 2 * N - 1 - p[hi]
-    sign[lo | hi] = -1.0
+    sign[lo | hi] = refl
     crossed[lo] = 1
     crossed[hi] = 2
     valid &= (idx >= 0) & (idx < N)

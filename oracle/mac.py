@@ -9,17 +9,23 @@ readings used here are stated):
 * Cells (i, j, k), 0 <= i < Nx etc.; pressure at cell centres; velocity
   component c lives on c-faces: face index f along axis c is the face at
   coordinate f*h, and the other two coordinates are cell centred.
-* Along a WALL axis a, the c = a faces 0 and N_a lie on the walls and are not
-  unknowns (normal velocity vanishes).  Along a PERIODIC axis everything wraps.
+* Along a WALL (no-slip) or SLIP (free-slip) axis a, the c = a faces 0 and N_a
+  lie on the walls and are not unknowns (normal velocity vanishes).  Along a
+  PERIODIC axis everything wraps.
 * Compact unknowns: for each component the true unknown faces in x-fastest
   order; the velocity vector is [u_x | u_y | u_z].
 * Padded layout (used at the library boundary): each component stored as an
   Nx*Ny*Nz array indexed by (face index along c, cell indices otherwise); the
   wall face 0 along a wall c-axis occupies a slot that is always zero.
 * Vector Laplacian, ghost-cell form: tangential ghost u_g = 2 U_w - u_interior
-  (U_w the wall velocity), normal wall faces Dirichlet 0.  This equals
-  DT GT when the one-sided gradient on a wall edge carries weight sqrt(2)/h,
-  which is the discrete fluctuation-dissipation balance the paper requires.
+  (U_w the wall velocity) at a no-slip wall, u_g = u_interior at a free-slip
+  wall (no tangential stress), normal wall faces Dirichlet 0.  This equals
+  DT GT when the one-sided gradient on a wall edge carries weight sqrt(2)/h at
+  a no-slip wall and 0 at a free-slip wall (where the tangential gradient
+  vanishes), which is the discrete fluctuation-dissipation balance the paper
+  requires.  Free-slip walls are one of the combinations of boundary
+  conditions the paper's formulation admits (Introduction, Conclusion); they
+  do not move.
 * Noise index space W: nine families (c, b) in the order
   xx, yy, zz, xy, xz, yx, yz, zx, zy.  Family (c, c) lives on cells; family
   (c, b != c) lives on edges: node index along b (N_b + 1 nodes on a wall
@@ -35,7 +41,8 @@ import numpy as np
 import scipy.sparse as sp
 
 PERIODIC = 0
-WALL = 1
+WALL = 1          # no-slip wall (possibly sliding)
+SLIP = 2          # free-slip wall
 
 FAMILIES: List[Tuple[int, int]] = [(0, 0), (1, 1), (2, 2), (0, 1), (0, 2), (1, 0), (1, 2), (2, 0), (2, 1)]
 
@@ -45,6 +52,8 @@ class Grid:
 
     def __init__(self, n, bc, h: float = 1.0, eta: float = 1.0, wall_vel=None, kernel: int = 4):
         self.n = tuple(int(v) for v in n)
+        if any(int(b) not in (PERIODIC, WALL, SLIP) for b in bc):
+            raise ValueError("boundary conditions are PERIODIC, WALL or SLIP")
         # width of the immersed-boundary delta kernel used with this grid (ib.py): 4
         # (Peskin's 4-point function) or 6 (the 6-point function of the paper's runs)
         if kernel not in (4, 6):
@@ -64,7 +73,7 @@ class Grid:
         for c in range(3):
             idx = -np.ones(self.n[::-1], dtype=np.int64)      # indexed [k, j, i]
             mask = np.ones(self.n[::-1], dtype=bool)
-            if self.bc[c] == WALL:
+            if self.bc[c] != PERIODIC:
                 sl = [slice(None)] * 3
                 sl[2 - c] = 0
                 mask[tuple(sl)] = False
@@ -94,7 +103,7 @@ class Grid:
         return out.reshape(3, -1)
 
     def nodes(self, a: int) -> int:
-        return self.n[a] + 1 if self.bc[a] == WALL else self.n[a]
+        return self.n[a] + 1 if self.bc[a] != PERIODIC else self.n[a]
 
     def family_dims(self, fam: int) -> Tuple[int, int, int]:
         c, b = FAMILIES[fam]
@@ -161,7 +170,8 @@ def vector_gradient(g: Grid) -> sp.csr_matrix:
 
     Family (c, c): cell (i,j,k) -> (u_c(f = i_c + 1) - u_c(i_c)) / h.
     Family (c, b): node n along b -> w * (u_c(cell n) - u_c(cell n - 1)) / h, where a
-    cell outside a wall axis holds zero velocity and w = sqrt(2) on the two wall nodes.
+    cell outside a wall axis holds zero velocity and w = sqrt(2) on the two wall nodes
+    of a no-slip axis, 0 on those of a free-slip axis.
     """
     offs = g.family_offsets()
     rows, cols, vals = [], [], []
@@ -183,8 +193,8 @@ def vector_gradient(g: Grid) -> sp.csr_matrix:
                 rows.append(lin[ok]); cols.append(col[ok]); vals.append(np.full(ok.sum(), sgn / g.h))
         else:
             node = pos[b]
-            if g.bc[b] == WALL:
-                w = np.where((node == 0) | (node == g.n[b]), math.sqrt(2.0), 1.0)
+            if g.bc[b] != PERIODIC:
+                w = np.where((node == 0) | (node == g.n[b]), math.sqrt(2.0) if g.bc[b] == WALL else 0.0, 1.0)
             else:
                 w = np.ones(node.shape)
             for shift, sgn in ((0, 1.0), (-1, -1.0)):
@@ -211,8 +221,9 @@ def vector_laplacian(g: Grid) -> sp.csr_matrix:
     """Lm by the ghost-cell stencil (homogeneous part).
 
     Per axis a, face neighbours along a = c (Dirichlet 0 at wall faces) and
-    cell neighbours along a != c (ghost -u across a wall, i.e. diagonal -3/h^2
-    next to it); periodic axes wrap.
+    cell neighbours along a != c (ghost -u across a no-slip wall, i.e. diagonal
+    -3/h^2 next to it; ghost +u across a free-slip wall, diagonal -1/h^2);
+    periodic axes wrap.
     """
     rows, cols, vals = [], [], []
     for c in range(3):
@@ -243,7 +254,8 @@ def vector_laplacian(g: Grid) -> sp.csr_matrix:
                     p[a] = np.clip(nb, 0, g.n[a] - 1)
                     col = _face_col(g, c, p)
                     rows.append(me[ok]); cols.append(col[ok]); vals.append(np.full(ok.sum(), 1.0 / g.h**2))
-                    diag -= np.where(ok, 1.0, 2.0) / g.h**2
+                    # beyond the wall the ghost is -u (no-slip) or +u (free-slip)
+                    diag -= np.where(ok, 1.0, 2.0 if g.bc[a] == WALL else 0.0) / g.h**2
         rows.append(me); cols.append(me); vals.append(diag)
     return sp.csr_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
                          shape=(g.nv, g.nv))

@@ -35,7 +35,7 @@ import scipy.sparse.linalg as spla
 from . import bodies as B
 from . import ib
 from . import mac
-from .mac import Grid, PERIODIC, WALL
+from .mac import Grid, PERIODIC, SLIP, WALL
 
 
 class Saddle:
@@ -273,8 +273,9 @@ class _OraclePreconditioner:
         g = s.g
         self.comp = []
         for c in range(3):
-            dims = tuple(g.n[a] - 1 if (a == c and g.bc[a] == WALL) else g.n[a] for a in range(3))
-            kinds = tuple("fft" if g.bc[a] == PERIODIC else ("dst1" if a == c else "dst2") for a in range(3))
+            dims = tuple(g.n[a] - 1 if (a == c and g.bc[a] != PERIODIC) else g.n[a] for a in range(3))
+            kinds = tuple("fft" if g.bc[a] == PERIODIC else
+                          ("dst1" if a == c else ("dct2" if g.bc[a] == SLIP else "dst2")) for a in range(3))
             self.comp.append(_FastPoisson(dims, kinds, g.h))
         self.pres = _FastPoisson(g.n, tuple("fft" if g.bc[a] == PERIODIC else "dct2" for a in range(3)), g.h)
         self.bodies = []

@@ -204,11 +204,46 @@ def test_interp_moving_wall_affine_term(kernel):
     assert np.abs(Jv[:, 1:]).max() < 1e-12
 
 
+@pytest.mark.parametrize("kernel", [4, 6])
+@pytest.mark.parametrize("axis", [0, 1, 2])
+def test_interp_free_slip_wall(axis, kernel):
+    """At a free-slip wall the tangential ghosts are even: a tangential field that
+    does not vary along the wall normal is its own even reflection, and the normal
+    component, linear and vanishing on the wall, its own odd one, so J is exact
+    right up to the wall."""
+    bc = [mac.PERIODIC] * 3
+    bc[axis] = mac.SLIP
+    g = mac.Grid((10, 10, 10), tuple(bc), h=1.0, kernel=kernel)
+    rng = np.random.default_rng(12 + axis)
+    r = rng.uniform(0.0, 10.0, size=(25, 3))
+    r[:, axis] = rng.uniform(0.05, kernel / 2 - 0.1, 25)
+    A = rng.standard_normal((3, 3))
+    A[:, axis] = 0.0
+    b0 = rng.standard_normal(3)
+    slope = 0.9
+    others = [a for a in range(3) if a != axis]
+
+    def field(c, x, y, z):
+        X = (x, y, z)
+        if c == axis:
+            return slope * X[axis]
+        # periodic in the two other axes: a single Fourier mode along each
+        return b0[c] + A[c, others[0]] * np.cos(2 * np.pi * X[others[0]] / 10.0) + \
+            A[c, others[1]] * np.sin(2 * np.pi * X[others[1]] / 10.0)
+
+    v = _field_from_function(g, field)
+    Jv = (ib.interpolation(g, r) @ v).reshape(-1, 3)
+    # compare with the brute-force sum of the same lattice values (mirror rule above)
+    assert np.abs(Jv[:6] - _brute_force_J(g, r[:6], v)).max() < 1e-12
+    assert np.abs(Jv[:, axis] - slope * r[:, axis]).max() < 1e-12
+
+
 def _brute_force_J(g, r, v):
     """Plain loops: sum over every lattice point x_alpha within the kernel support
     of delta_h(x_alpha - r) times the field value there, where a lattice point
-    outside a wall takes minus the value at its mirror coordinate (recursively
-    for corners) and a point on a wall face of the normal component is zero."""
+    outside a wall takes the value at its mirror coordinate with a minus sign (no
+    sign for a tangential component at a free-slip wall; recursively for corners)
+    and a point on a wall face of the normal component is zero."""
     vp = g.compact_to_padded(v).reshape(3, g.n[2], g.n[1], g.n[0])
     L = [g.n[a] * g.h for a in range(3)]
     phi = ib.phi6 if g.kernel == 6 else ib.phi4
@@ -220,10 +255,12 @@ def _brute_force_J(g, r, v):
             if g.bc[a] == mac.PERIODIC:
                 X[a] = X[a] % L[a]
                 continue
+            # a mirrored value flips sign, except a tangential one at a free-slip wall
+            flip = 1.0 if (a != c and g.bc[a] == mac.SLIP) else -1.0
             if X[a] < -1e-9:
-                X[a] = -X[a]; sign = -sign
+                X[a] = -X[a]; sign = sign * flip
             elif X[a] > L[a] + 1e-9:
-                X[a] = 2 * L[a] - X[a]; sign = -sign
+                X[a] = 2 * L[a] - X[a]; sign = sign * flip
             if a == c and (abs(X[a]) < 1e-9 or abs(X[a] - L[a]) < 1e-9):
                 return 0.0
         idx = []
@@ -254,7 +291,7 @@ def _brute_force_J(g, r, v):
 
 
 @pytest.mark.parametrize("kernel", [4, 6])
-@pytest.mark.parametrize("bc", [(1, 1, 1), (0, 1, 1), (1, 0, 0)])
+@pytest.mark.parametrize("bc", [(1, 1, 1), (0, 1, 1), (1, 0, 0), (2, 1, 2), (0, 2, 2)])
 def test_interp_brute_force(bc, kernel):
     g = mac.Grid((6, 7, 6), bc, h=1.1, kernel=kernel)
     rng = np.random.default_rng(11)

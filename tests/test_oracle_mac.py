@@ -3,7 +3,10 @@
 Checked against what the mathematics fixes, not against the oracle itself:
 adjoint relations G = -D^T and Lm = DT GT (the ghost-cell Laplacian built
 independently), closed-form sine/cosine eigenpairs, and a manufactured
-divergence-free Stokes solution recovered by a solve.
+divergence-free Stokes solution recovered by a solve; no-slip (1), free-slip
+(2) and periodic (0) axes in combination.  Closed-form flows: plane Poiseuille
+between no-slip walls, plane Couette between sliding walls, and a shear-free
+cosine mode between free-slip walls.
 """
 import math
 
@@ -12,7 +15,7 @@ import pytest
 
 from oracle import mac, saddle
 
-BCS = [(1, 1, 1), (0, 1, 1), (1, 0, 1), (0, 0, 1), (1, 0, 0)]
+BCS = [(1, 1, 1), (0, 1, 1), (1, 0, 1), (0, 0, 1), (1, 0, 0), (2, 2, 2), (1, 2, 0), (0, 2, 1), (2, 1, 2)]
 
 
 @pytest.mark.parametrize("bc", BCS)
@@ -59,6 +62,8 @@ def test_vector_laplacian_eigenpairs(bc):
                     kind, k = "periodic", int(rng.integers(0, N))
                 elif a == c:
                     kind, k = "face_wall", int(rng.integers(1, N))
+                elif g.bc[a] == mac.SLIP:       # even ghosts: cosine modes
+                    kind, k = "cell_neumann", int(rng.integers(0, N))
                 else:
                     kind, k = "cell_wall", int(rng.integers(1, N + 1))
                 m, l = _mode_1d(N, kind, k, g.h)
@@ -96,7 +101,7 @@ def _curl_field(g, rng):
     def pot(dims, wall_axes):
         p = rng.standard_normal(dims[::-1])
         for a in wall_axes:
-            if g.bc[a] == mac.WALL:
+            if g.bc[a] != mac.PERIODIC:
                 sl = [slice(None)] * 3
                 sl[2 - a] = 0
                 p[tuple(sl)] = 0.0
@@ -124,7 +129,7 @@ def _curl_field(g, rng):
     return np.stack([ux, uy, uz]).reshape(3, -1) / g.h
 
 
-@pytest.mark.parametrize("bc", [(1, 1, 1), (0, 1, 1), (0, 0, 1)])
+@pytest.mark.parametrize("bc", [(1, 1, 1), (0, 1, 1), (0, 0, 1), (2, 1, 2), (0, 2, 1)])
 def test_manufactured_stokes(bc):
     g = mac.Grid((8, 6, 10), bc, h=1.0, eta=1.7)
     rng = np.random.default_rng(7)
@@ -244,3 +249,36 @@ def test_plane_couette_closed_form(wall_axis, comp):
     expect = Ulo + (Uhi - Ulo) * r[:, wall_axis] / L
     assert np.abs(Jv[:, comp] - expect).max() < 1e-12
     assert np.abs(np.delete(Jv, comp, axis=1)).max() < 1e-12
+
+
+@pytest.mark.parametrize("k", [0, 1, 3])
+def test_free_slip_channel_closed_form(k):
+    """Free-slip walls at z = 0 and z = L (zero tangential stress: even ghosts), x and
+    y periodic, body force f_x = F cos(pi k z / L) at the x faces.  The discrete
+    solution is the same cosine, divided by eta times its eigenvalue
+    (4/h^2) sin^2(pi k / (2 N)) -- a no-slip wall (odd ghosts) would have sine modes
+    instead.  k = 0 (uniform forcing) has no steady state between free-slip walls;
+    there the singular mode is checked to be in the operator's kernel."""
+    h, eta, F, nz = 0.5, 1.3, 0.7, 12
+    g = mac.Grid((4, 3, nz), (mac.PERIODIC, mac.PERIODIC, mac.SLIP), h=h, eta=eta)
+    Lm = mac.vector_laplacian(g)
+    z = (np.arange(nz) + 0.5) * h
+    L = nz * h
+    prof = np.cos(math.pi * k * z / L)
+    f = np.zeros((3, nz, 3, 4))
+    f[0] = F * prof[:, None, None]
+    fc = g.padded_to_compact(f)
+    lam = (4.0 / h ** 2) * math.sin(math.pi * k / (2 * nz)) ** 2
+    if k == 0:
+        assert np.abs(Lm @ fc).max() < 1e-12           # uniform shear-free flow is a null mode
+        return
+    s = saddle.Saddle(g, np.zeros((0, 3)), np.zeros((0, 4)), np.zeros((0, 3)), np.zeros(1, dtype=int),
+                      fluid_only=True)
+    x, info = s.solve_fgmres(s.rhs(fluid=fc, include_bc=False), tol=1e-13)
+    v = g.compact_to_padded(x[s.sl_v]).reshape(3, nz, 3, 4)
+    expect = F * prof / (eta * lam)
+    assert np.abs(v[0] - expect[:, None, None]).max() < 1e-10 * np.abs(expect).max()
+    assert np.abs(v[1:]).max() < 1e-12
+    # the no-slip rule would not reproduce it
+    gw = mac.Grid((4, 3, nz), (mac.PERIODIC, mac.PERIODIC, mac.WALL), h=h, eta=eta)
+    assert np.abs(mac.vector_laplacian(gw) @ g.padded_to_compact(f) + lam * fc).max() > 1e-3 * lam * F
