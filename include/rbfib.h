@@ -9,7 +9,7 @@
  * For rigid bodies p with tracking points q_p and unit-quaternion orientations
  * theta_p, made of markers r_i = q_p + R(theta_p) r_i^ref, suspended in a
  * Stokes fluid on a staggered grid of Nx x Ny x Nz cells with a periodic or
- * no-slip (possibly sliding) wall boundary per axis, the library applies and
+ * no-slip (possibly sliding) or free-slip wall boundary per axis, the library applies and
  * solves the constrained saddle-point system of eqs. (LangevinD1-D4):
  *
  *     [ -eta Lm   G   -S   0 ] [ v      ]   [ f_v                          ]
@@ -22,9 +22,11 @@
  * (r_i - q_p), (K^T lambda)_p = [sum lambda_i; sum (r_i - q_p) x lambda_i]),
  * and advances the bodies by the Split-Euler-Maruyama scheme of Algorithm 1
  * with the random-finite-difference drift (Sec. IV).  Walls enter S and J by
- * odd reflection of the kernel support; a wall sliding with tangential velocity
- * U_w adds 2 eta U_w / h^2 to the momentum rows next to it and J_bc to the
- * constraint rows.
+ * reflection of the kernel support (odd for the normal component and for
+ * tangential components at no-slip walls, even for tangential components at
+ * free-slip walls); a wall sliding with tangential velocity U_w adds
+ * 2 eta U_w / h^2 to the momentum rows next to it and J_bc to the constraint
+ * rows.
  *
  * Conventions
  * -----------
@@ -54,8 +56,8 @@
  * Errors
  * ------
  * Every int-returning call returns RBFIB_OK (0) or a negative code:
- *   RBFIB_EINVAL   bad argument (sizes, no wall axis, periodic axis not a
- *                  multiple of 4, too few cells, NULL pointer, bad options,
+ *   RBFIB_EINVAL   bad argument (sizes, fewer than 4 cells on an axis, a
+ *                  periodic axis with no no-slip wall axis, NULL pointer, bad options,
  *                  an orientation theta_p with | |theta_p| - 1 | > 1e-12 or
  *                  not finite -- Sec. II requires unit quaternions);
  *   RBFIB_EREJECT  unphysical configuration: a marker outside the open domain
@@ -89,17 +91,23 @@ extern "C" {
 #define RBFIB_ENOMEM   -6
 
 #define RBFIB_PERIODIC 0
-#define RBFIB_WALL     1
+#define RBFIB_WALL     1   /* no-slip wall, possibly sliding (wall_vel)                 */
+#define RBFIB_SLIP     2   /* free-slip wall: no normal flow, no tangential stress       */
 
 typedef struct rbfib_ctx rbfib_ctx;
 
-/* Grid and boundary conditions (Sec. III.A; Sec. VI for the sliding wall). */
+/* Grid and boundary conditions (Sec. III.A; Sec. VI for the sliding wall; free-slip
+ * walls are one of the combinations of boundary conditions the formulation admits,
+ * Introduction and Conclusion).  At least one axis must be RBFIB_WALL, or none
+ * periodic: otherwise a uniform flow along the periodic axes is free and the
+ * mobility problem is singular. */
 typedef struct {
     int n[3];                  /* cells per axis, x y z                              */
-    int bc[3];                 /* RBFIB_PERIODIC or RBFIB_WALL per axis (>= 1 wall)   */
+    int bc[3];                 /* RBFIB_PERIODIC, RBFIB_WALL or RBFIB_SLIP per axis   */
     double h;                  /* cell width; dV = h^3                               */
     double eta;                /* viscosity                                          */
-    double wall_vel[3][2][3];  /* [axis][0 low, 1 high][component]; tangential only  */
+    double wall_vel[3][2][3];  /* [axis][0 low, 1 high][component]; tangential only, */
+                               /*    no-slip walls only                              */
 } rbfib_grid;
 
 /* Rigid bodies as marker agglomerates (Sec. III.B).  Host memory, copied. */

@@ -27,6 +27,7 @@ RBFIB_EDEVICE = -5
 RBFIB_ENOMEM = -6
 PERIODIC = 0
 WALL = 1
+SLIP = 2
 
 EXPORTS = [
     "rbfib_default_opts", "rbfib_strerror", "rbfib_last_error", "rbfib_create", "rbfib_create_batch",

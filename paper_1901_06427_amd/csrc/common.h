@@ -138,13 +138,17 @@ __device__ __forceinline__ T mg_residual(T b, T s, T lap) { return fmad(-s, lap,
 // x + w (b - s lap)
 template <typename T>
 __device__ __forceinline__ T jacobi_step(T x, T b, T s, T lap, T w) { return fmad(mg_residual(b, s, lap), w, x); }
+// ghost beyond a wall of a cell-centred quantity: even (pressure; tangential
+// velocity at a free-slip wall) or odd (tangential velocity at a no-slip wall)
+__device__ __forceinline__ bool even_ghost(int comp, int bc) { return comp == 3 || bc == RBFIB_SLIP; }
+
 // diagonal term of axis a: -2, plus one ghost weight per wall the point touches
-// (tangential velocity odd: -1, pressure even: +1; face-normal axes have none)
+// (odd ghost: -1, even ghost: +1; face-normal axes have none)
 template <typename T>
 __device__ __forceinline__ T diag_axis(int comp, int a, int g, int n, int bc) {
     T da = (T)-2;
-    if (bc == RBFIB_WALL && a != comp) {
-        const T gg = (comp == 3) ? (T)1 : (T)-1;
+    if (bc != RBFIB_PERIODIC && a != comp) {
+        const T gg = even_ghost(comp, bc) ? (T)1 : (T)-1;
         if (g == 0) da += gg;
         if (g == n - 1) da += gg;
     }
@@ -157,7 +161,7 @@ __device__ __forceinline__ int nbr_kind(int g, int d, int n, int bc, int a, int 
     if (bc == RBFIB_PERIODIC) return 0;
     const int q = g + d;
     if (a == comp) return (q <= 0 || q >= n) ? 1 : 0;
-    if (q < 0 || q >= n) return (comp == 3) ? 2 : 3;
+    if (q < 0 || q >= n) return even_ghost(comp, bc) ? 2 : 3;
     return 0;
 }
 
@@ -201,7 +205,7 @@ __device__ __forceinline__ ProlongAxis<T> prolong_axis(int f, int nf, int nc, in
             }
             p.i1 = J; p.w1 = wj;
         }
-        if (bc == RBFIB_WALL) {          // coarse face 0 on a wall axis is the wall
+        if (bc != RBFIB_PERIODIC) {      // coarse face 0 on a wall axis is the wall
             if (p.i0 == 0) p.w0 = (T)0;
             if (p.cnt == 2 && p.i1 == 0) p.w1 = (T)0;
         }
@@ -211,7 +215,7 @@ __device__ __forceinline__ ProlongAxis<T> prolong_axis(int f, int nf, int nc, in
         T g = (T)0.25;
         if (J < 0 || J >= nc) {
             if (bc == RBFIB_PERIODIC) J = (J < 0) ? J + nc : J - nc;
-            else { J = I; g = (comp == 3) ? (T)0.25 : (T)-0.25; }
+            else { J = I; g = even_ghost(comp, bc) ? (T)0.25 : (T)-0.25; }
         }
         p.i1 = J; p.w1 = g;
     }
@@ -280,9 +284,11 @@ __device__ __forceinline__ double dphi4(double r) {
 
 // Fold a raw support index p along an axis of N cells.  normal: the axis is the
 // face-normal axis of the velocity component.  Returns false when the point is a
-// wall face (contributes nothing).  sgn = -1 for each reflection; cross = 0 (none),
-// 1 (lower wall), 2 (upper wall).  Indices are clamped into [0, N) so that even an
-// invalid marker never addresses memory out of bounds.
+// wall face (contributes nothing).  sgn is the sign of the reflection: -1 for the
+// normal component and for a tangential one at a no-slip wall, +1 for a tangential
+// one at a free-slip wall; cross = 0 (none), 1 (lower wall), 2 (upper wall).
+// Indices are clamped into [0, N) so that even an invalid marker never addresses
+// memory out of bounds.
 __device__ __forceinline__ bool fold_index(int p, int N, int bc, bool normal, int &idx, double &sgn, int &cross) {
     sgn = 1.0;
     cross = 0;
@@ -298,8 +304,9 @@ __device__ __forceinline__ bool fold_index(int p, int N, int bc, bool normal, in
         else if (p > N) { idx = 2 * N - p; sgn = -1.0; cross = 2; }
         else idx = p;
     } else {
-        if (p < 0) { idx = -1 - p; sgn = -1.0; cross = 1; }
-        else if (p >= N) { idx = 2 * N - 1 - p; sgn = -1.0; cross = 2; }
+        const double rs = bc == RBFIB_SLIP ? 1.0 : -1.0;
+        if (p < 0) { idx = -1 - p; sgn = rs; cross = 1; }
+        else if (p >= N) { idx = 2 * N - 1 - p; sgn = rs; cross = 2; }
         else idx = p;
     }
     if (idx < 0) { idx = 0; ok = false; }

@@ -5,8 +5,8 @@
 //
 // Discretisation (paper Sec. III.A): velocity on faces, pressure at cell centres,
 // G = -D^*, Lm = DT GT; on a wall axis the normal-velocity wall faces are not
-// unknowns and tangential ghosts are u_g = 2 U_w - u (the homogeneous operator
-// uses U_w = 0).  Every kernel is one thread per grid point, x fastest, so that a
+// unknowns and tangential ghosts are u_g = 2 U_w - u at a no-slip wall (the
+// homogeneous operator uses U_w = 0) and u_g = u at a free-slip wall.  Every kernel is one thread per grid point, x fastest, so that a
 // wavefront reads 64 consecutive doubles of each field.
 #include "common.h"
 
@@ -27,7 +27,7 @@ __device__ __forceinline__ T nbr(const T *u, int c, int a, int d, int idx[3], co
         if (p <= 0 || p >= n[a]) return (T)0;
         return u[lin + d * stride];
     }
-    if (p < 0 || p >= n[a]) return (c == 3) ? self : -self;   // Neumann (pressure) / odd ghost
+    if (p < 0 || p >= n[a]) return even_ghost(c, bc[a]) ? self : -self;   // even / odd ghost
     return u[lin + d * stride];
 }
 
@@ -51,7 +51,7 @@ __device__ __forceinline__ T lap_point(const T *u, int c, int idx[3], const int 
 }
 
 __device__ __forceinline__ bool pinned(int c, const int idx[3], const int bc[3]) {
-    return c < 3 && bc[c] == RBFIB_WALL && idx[c] == 0;
+    return c < 3 && bc[c] != RBFIB_PERIODIC && idx[c] == 0;
 }
 
 __device__ __forceinline__ void unlin(long long lin, const RepDev &R, int idx[3]) {
@@ -158,8 +158,8 @@ __device__ __forceinline__ void apply_row2(const RepDev &R, const BlockEnt &be, 
         } else {
             ld_pair(p + lin + (idx[c] > 0 ? -st[c] : (R.n[c] - 1) * st[c]), pm[0][c], pm[1][c]);
         }
-        pin[0][c] = R.bc[c] == RBFIB_WALL && (c == 0 ? idx[0] : idx[c]) == 0;
-        pin[1][c] = R.bc[c] == RBFIB_WALL && (c == 0 ? idx[0] + 1 : idx[c]) == 0;
+        pin[0][c] = R.bc[c] != RBFIB_PERIODIC && (c == 0 ? idx[0] : idx[c]) == 0;
+        pin[1][c] = R.bc[c] != RBFIB_PERIODIC && (c == 0 ? idx[0] + 1 : idx[c]) == 0;
     }
     double pc0, pc1;
     ld_pair(p + lin, pc0, pc1);
@@ -364,8 +364,8 @@ __device__ __forceinline__ void smooth_row4(const RepDev &R, const LevDev &Lv, c
     // tangential component on an x wall, which only the group's first and last points
     // can be (rows are a multiple of 4 long), so each weight is formed once per distinct
     // diagonal: interior, and at the row ends of the threads that hold them.
-    const bool e0 = R.bc[0] == RBFIB_WALL && comp != 0 && x0 == 0;
-    const bool e3 = R.bc[0] == RBFIB_WALL && comp != 0 && x0 + 3 == n0 - 1;
+    const bool e0 = R.bc[0] != RBFIB_PERIODIC && comp != 0 && x0 == 0;
+    const bool e3 = R.bc[0] != RBFIB_PERIODIC && comp != 0 && x0 + 3 == n0 - 1;
     const float xti = fmad(diag_axis<float>(comp, 0, x0 + 1, n0, R.bc[0]), ihx, 0.f);
     const float xte = fmad(diag_axis<float>(comp, 0, 0, n0, R.bc[0]), ihx, 0.f);
     const float wi = jacobi_w<float>(om, s, fmad(daz, ihz, fmad(day, ihy, xti)));
@@ -407,8 +407,8 @@ __device__ __forceinline__ void smooth_row4(const RepDev &R, const LevDev &Lv, c
         xl = xl * v[0];
         xr = xr * v[0];
     }
-    const bool pin_yz = (comp == 1 && R.bc[1] == RBFIB_WALL && idx[1] == 0) ||
-                        (comp == 2 && R.bc[2] == RBFIB_WALL && idx[2] == 0);
+    const bool pin_yz = (comp == 1 && R.bc[1] != RBFIB_PERIODIC && idx[1] == 0) ||
+                        (comp == 2 && R.bc[2] != RBFIB_PERIODIC && idx[2] == 0);
     float y4[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
@@ -427,7 +427,7 @@ __device__ __forceinline__ void smooth_row4(const RepDev &R, const LevDev &Lv, c
                                  acc);
             y = MODE == MG_RESID ? mg_residual<float>(b4[q], s, acc) : jacobi_step<float>(self, b4[q], s, acc, w);
         }
-        const bool pin = pin_yz || (comp == 0 && R.bc[0] == RBFIB_WALL && x0 + q == 0);
+        const bool pin = pin_yz || (comp == 0 && R.bc[0] != RBFIB_PERIODIC && x0 + q == 0);
         y4[q] = pin ? 0.f : y;
     }
     *reinterpret_cast<float4 *>(xo + lin) = make_float4(y4[0], y4[1], y4[2], y4[3]);
@@ -681,11 +681,11 @@ __device__ __forceinline__ void prolong_row4(const RepDev &R, const LevDev &F, c
         }
     const float4 v = *reinterpret_cast<const float4 *>(xf + lin);
     float x4[4] = {v.x, v.y, v.z, v.w};
-    const bool pin_yz = (comp == 1 && R.bc[1] == RBFIB_WALL && fi[1] == 0) ||
-                        (comp == 2 && R.bc[2] == RBFIB_WALL && fi[2] == 0);
+    const bool pin_yz = (comp == 1 && R.bc[1] != RBFIB_PERIODIC && fi[1] == 0) ||
+                        (comp == 2 && R.bc[2] != RBFIB_PERIODIC && fi[2] == 0);
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-        if (pin_yz || (comp == 0 && R.bc[0] == RBFIB_WALL && x0 + q == 0)) continue;
+        if (pin_yz || (comp == 0 && R.bc[0] != RBFIB_PERIODIC && x0 + q == 0)) continue;
         const ProlongAxis<float> px = prolong_axis<float>(x0 + q, F.n[0], C.n[0], R.bc[0], comp == 0, comp);
         float acc = 0.f;
 #pragma unroll
@@ -807,8 +807,8 @@ __device__ __forceinline__ void bot_sweep(const RepDev &R, const LevDev &Lv, int
         const int oyp = kyp ? 0 : (j == n1 - 1 ? -(n1 - 1) * n0 : n0);
         const T dxy = fmad(diag_axis<T>(comp, 1, j, n1, R.bc[1]), ih1,
                            fmad(diag_axis<T>(comp, 0, i, n0, R.bc[0]), ih0, (T)0));
-        const bool pin_xy = (comp == 0 && R.bc[0] == RBFIB_WALL && i == 0) ||
-                            (comp == 1 && R.bc[1] == RBFIB_WALL && j == 0);
+        const bool pin_xy = (comp == 0 && R.bc[0] != RBFIB_PERIODIC && i == 0) ||
+                            (comp == 1 && R.bc[1] != RBFIB_PERIODIC && j == 0);
         for (int k = 0; k < n2; ++k) {
             const int lin = col + k * n01;
             const T d = fmad(diag_axis<T>(comp, 2, k, n2, R.bc[2]), ih2, dxy);
@@ -826,7 +826,7 @@ __device__ __forceinline__ void bot_sweep(const RepDev &R, const LevDev &Lv, int
                 acc = lap_acc<T>(pick<T>(kzp, xi[lin + ozp], xv), xv, pick<T>(kzm, xi[lin + ozm], xv), ih2, acc);
                 y = MODE == MG_RESID ? mg_residual<T>(bb[lin], s, acc) : jacobi_step<T>(xv, bb[lin], s, acc, w);
             }
-            const bool pin = pin_xy || (comp == 2 && R.bc[2] == RBFIB_WALL && k == 0);
+            const bool pin = pin_xy || (comp == 2 && R.bc[2] != RBFIB_PERIODIC && k == 0);
             xo[lin] = pin ? (T)0 : y;
         }
     }
@@ -1018,12 +1018,12 @@ __global__ void k_proj_div(const RepDev *reps, const LevDev *levs, const BlockEn
             const float ys[4] = {a1.x, a1.y, a1.z, a1.w}, yh[4] = {h1.x, h1.y, h1.z, h1.w};
             const float zs[4] = {a2.x, a2.y, a2.z, a2.w}, zh[4] = {h2.x, h2.y, h2.z, h2.w};
             const double rr[4] = {r01.x, r01.y, r23.x, r23.y};
-            const bool piny = R.bc[1] == RBFIB_WALL && idx[1] == 0, pinz = R.bc[2] == RBFIB_WALL && idx[2] == 0;
+            const bool piny = R.bc[1] != RBFIB_PERIODIC && idx[1] == 0, pinz = R.bc[2] != RBFIB_PERIODIC && idx[2] == 0;
             float bo[4];
             double zo[4];
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                const bool pinx = R.bc[0] == RBFIB_WALL && idx[0] + q == 0;
+                const bool pinx = R.bc[0] != RBFIB_PERIODIC && idx[0] + q == 0;
                 double div = 0.0;
                 div = fmad((double)x0[q + 1] - (pinx ? 0.0 : (double)x0[q]), R.inv_h, div);
                 div = fmad((double)yh[q] - (piny ? 0.0 : (double)ys[q]), R.inv_h, div);
@@ -1087,7 +1087,7 @@ __global__ void k_proj_correct(const RepDev *reps, const LevDev *levs, const Blo
             const float pc[4] = {p4.x, p4.y, p4.z, p4.w};
             const float pmx[4] = {before, p4.x, p4.y, p4.z};
             const float pmy[4] = {py.x, py.y, py.z, py.w}, pmz[4] = {pz.x, pz.y, pz.z, pz.w};
-            const bool piny = R.bc[1] == RBFIB_WALL && idx[1] == 0, pinz = R.bc[2] == RBFIB_WALL && idx[2] == 0;
+            const bool piny = R.bc[1] != RBFIB_PERIODIC && idx[1] == 0, pinz = R.bc[2] != RBFIB_PERIODIC && idx[2] == 0;
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
                 const float4 x4 = ld_f4((const float *)xv + Lv.off + c * Lv.N + lin);
@@ -1095,7 +1095,7 @@ __global__ void k_proj_correct(const RepDev *reps, const LevDev *levs, const Blo
                 double o[4];
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
-                    const bool pin = c == 0 ? (R.bc[0] == RBFIB_WALL && idx[0] + q == 0) : (c == 1 ? piny : pinz);
+                    const bool pin = c == 0 ? (R.bc[0] != RBFIB_PERIODIC && idx[0] + q == 0) : (c == 1 ? piny : pinz);
                     const float pm = c == 0 ? pmx[q] : (c == 1 ? pmy[q] : pmz[q]);
                     o[q] = pin ? 0.0 : fmad(-((double)pc[q] - (double)pm), R.inv_h, (double)xs[q]);
                 }
@@ -1143,7 +1143,7 @@ __device__ __forceinline__ int fam_index(int c, int b) {
 __device__ __forceinline__ double noise_W(uint64_t seed, uint64_t step, const RepDev &R, const long long *fam_off,
                                           int fam, int c, int b, int i, int j, int k) {
     int dims[3] = {R.n[0], R.n[1], R.n[2]};
-    if (b != c && R.bc[b] == RBFIB_WALL) dims[b] += 1;
+    if (b != c && R.bc[b] != RBFIB_PERIODIC) dims[b] += 1;
     long long lin = (long long)i + (long long)dims[0] * ((long long)j + (long long)dims[1] * k);
     return philox_normal(seed, 1u, step, (uint64_t)(fam_off[fam] + lin));
 }
@@ -1165,7 +1165,7 @@ __global__ void k_noise(const RepDev *reps, const BlockEnt *tab, double scale_ba
     const int FB[9] = {0, 1, 2, 1, 2, 0, 2, 0, 1};
     for (int q = 0; q < 9; ++q) {
         long long sz = 1;
-        for (int a = 0; a < 3; ++a) sz *= (long long)R.n[a] + ((a == FB[q] && FB[q] != FC[q] && R.bc[a] == RBFIB_WALL) ? 1 : 0);
+        for (int a = 0; a < 3; ++a) sz *= (long long)R.n[a] + ((a == FB[q] && FB[q] != FC[q] && R.bc[a] != RBFIB_PERIODIC) ? 1 : 0);
         fam_off[q + 1] = fam_off[q] + sz;
     }
     double scale = scale_base * sqrt(R.eta / R.dV);
@@ -1187,9 +1187,12 @@ __global__ void k_noise(const RepDev *reps, const BlockEnt *tab, double scale_ba
                 int np = nb_ + 1;
                 double wlo = 1.0, whi = 1.0;
                 int pi3[3] = {idx[0], idx[1], idx[2]};
-                if (R.bc[b] == RBFIB_WALL) {
-                    if (nb_ == 0) wlo = SQ2;
-                    if (np == R.n[b]) whi = SQ2;
+                if (R.bc[b] != RBFIB_PERIODIC) {
+                    // wall edges: sqrt(2) at a no-slip wall, 0 at a free-slip wall (no
+                    // tangential stress), so that DT DT^T = -Lm with either ghost rule
+                    const double ww = R.bc[b] == RBFIB_WALL ? SQ2 : 0.0;
+                    if (nb_ == 0) wlo = ww;
+                    if (np == R.n[b]) whi = ww;
                 } else if (np == R.n[b]) np = 0;
                 double Wlo = noise_W(rseed, step, R, fam_off, fam, c, b, pi3[0], pi3[1], pi3[2]);
                 pi3[b] = np;

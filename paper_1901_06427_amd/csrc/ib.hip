@@ -410,9 +410,9 @@ __global__ __launch_bounds__(64) void k_spread(const RepDev *reps, const int *ti
             const long long lin = (long long)g0 + (long long)R.n[0] * ((long long)g1 + (long long)R.n[1] * g2);
             const long long o = levs ? levs[rep * RB_MAXLEV].off : R.off;
             const double sc = alpha / R.dV;
-            if (!(R.bc[0] == RBFIB_WALL && g0 == 0)) y[o + lin] += (TO)(sc * acc0);
-            if (!(R.bc[1] == RBFIB_WALL && g1 == 0)) y[o + R.N + lin] += (TO)(sc * acc1);
-            if (!(R.bc[2] == RBFIB_WALL && g2 == 0)) y[o + 2 * R.N + lin] += (TO)(sc * acc2);
+            if (!(R.bc[0] != RBFIB_PERIODIC && g0 == 0)) y[o + lin] += (TO)(sc * acc0);
+            if (!(R.bc[1] != RBFIB_PERIODIC && g1 == 0)) y[o + R.N + lin] += (TO)(sc * acc1);
+            if (!(R.bc[2] != RBFIB_PERIODIC && g2 == 0)) y[o + 2 * R.N + lin] += (TO)(sc * acc2);
         }
     }
 }

@@ -65,7 +65,7 @@ __device__ __forceinline__ void make_slots(PlaneSlots<T> &S, int PX, int PY, int
         S.g0[k] = g0;
         S.g1[k] = g1;
         S.gxy[k] = S.in[k] ? g0 + F.n[0] * g1 : 0;
-        S.pin[k] = (comp == 0 && R.bc[0] == RBFIB_WALL && g0 == 0) || (comp == 1 && R.bc[1] == RBFIB_WALL && g1 == 0);
+        S.pin[k] = (comp == 0 && R.bc[0] != RBFIB_PERIODIC && g0 == 0) || (comp == 1 && R.bc[1] != RBFIB_PERIODIC && g1 == 0);
         S.kinds[k] = nbr_kind(g0, -1, F.n[0], R.bc[0], 0, comp) | (nbr_kind(g0, +1, F.n[0], R.bc[0], 0, comp) << 2) |
                      (nbr_kind(g1, -1, F.n[1], R.bc[1], 1, comp) << 4) |
                      (nbr_kind(g1, +1, F.n[1], R.bc[1], 1, comp) << 6);
@@ -86,7 +86,7 @@ __device__ __forceinline__ ZPlane zplane(int z, const LevDev &F, const RepDev &R
     P.z = z;
     if (R.bc[2] == RBFIB_PERIODIC) { P.in = true; P.gz = wrap_axis(z, F.n[2]); }
     else { P.in = z >= 0 && z < F.n[2]; P.gz = P.in ? z : 0; }
-    P.pin = comp == 2 && R.bc[2] == RBFIB_WALL && P.gz == 0;
+    P.pin = comp == 2 && R.bc[2] != RBFIB_PERIODIC && P.gz == 0;
     P.km = nbr_kind(P.gz, -1, F.n[2], R.bc[2], 2, comp);
     P.kp = nbr_kind(P.gz, +1, F.n[2], R.bc[2], 2, comp);
     return P;
@@ -251,7 +251,7 @@ __global__ __launch_bounds__(256) void k_mg_down(const RepDev *reps, const LevDe
                     const int J = clo[1] + q / cex, I = clo[0] + q % cex;
                     T *out = bc + I + C.n[0] * J + c01 * K;
                     const int ci[3] = {I, J, K};
-                    if (comp < 3 && R.bc[comp] == RBFIB_WALL && ci[comp] == 0) { *out = (T)0; continue; }
+                    if (comp < 3 && R.bc[comp] != RBFIB_PERIODIC && ci[comp] == 0) { *out = (T)0; continue; }
                     const int fb0 = (crs[0] ? 2 * I - fr[0] : I) - px0;
                     const int fb1 = (crs[1] ? 2 * J - fr[1] : J) - py0;
                     const int nx = !crs[0] ? 1 : (fr[0] ? 3 : 2), ny = !crs[1] ? 1 : (fr[1] ? 3 : 2);

@@ -124,13 +124,14 @@ static int apply_noalloc(const rbfib_grid *grid, const rbfib_bodies *bodies, con
     if (!grid || !bodies || !x || !y || x == y) return RBFIB_EINVAL;
     const rbfib_grid &g = *grid;
     const rbfib_bodies &bd = *bodies;
-    int walls = 0;
+    int walls = 0, periodic = 0;
     for (int a = 0; a < 3; ++a) {
         if (g.n[a] < 4 || g.n[a] > (1 << 16)) return RBFIB_EINVAL;
-        if (g.bc[a] != RBFIB_PERIODIC && g.bc[a] != RBFIB_WALL) return RBFIB_EINVAL;
+        if (g.bc[a] != RBFIB_PERIODIC && g.bc[a] != RBFIB_WALL && g.bc[a] != RBFIB_SLIP) return RBFIB_EINVAL;
         walls += g.bc[a] == RBFIB_WALL;
+        periodic += g.bc[a] == RBFIB_PERIODIC;
     }
-    if (walls == 0 || !(g.h > 0.0) || !(g.eta > 0.0)) return RBFIB_EINVAL;
+    if ((walls == 0 && periodic > 0) || periodic == 3 || !(g.h > 0.0) || !(g.eta > 0.0)) return RBFIB_EINVAL;
     const long long N = (long long)g.n[0] * g.n[1] * g.n[2];
     const long long ntiles = (long long)((g.n[0] + 3) / 4) * ((g.n[1] + 3) / 4) * ((g.n[2] + 3) / 4);
     if (N > RBNA_MAX_CELLS || ntiles > RBNA_MAX_TILES) return RBFIB_EINVAL;

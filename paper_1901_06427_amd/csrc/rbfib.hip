@@ -71,7 +71,7 @@ static std::vector<double> coarse_inverse(const int n[3], const double ih2[3], c
         for (int j = 0; j < n[1]; ++j)
             for (int i = 0; i < n[0]; ++i) {
                 int idx[3] = {i, j, k};
-                bool pin = comp < 3 && bc[comp] == RBFIB_WALL && idx[comp] == 0;
+                bool pin = comp < 3 && bc[comp] != RBFIB_PERIODIC && idx[comp] == 0;
                 if (!pin) map[i + n[0] * (j + n[1] * k)] = nu++;
             }
     bool singular = (comp == 3);
@@ -94,7 +94,9 @@ static std::vector<double> coarse_inverse(const int n[3], const double ih2[3], c
                         } else if (a == comp) {
                             if (q[a] <= 0 || q[a] >= n[a]) continue;
                         } else if (q[a] < 0 || q[a] >= n[a]) {
-                            A[(size_t)row * nn + row] += (comp == 3 ? 1.0 : -1.0) * s * ih2[a];
+                            // even ghost (pressure; tangential velocity at a free-slip
+                            // wall) or odd ghost (tangential velocity at a no-slip wall)
+                            A[(size_t)row * nn + row] += ((comp == 3 || bc[a] == RBFIB_SLIP) ? 1.0 : -1.0) * s * ih2[a];
                             continue;
                         }
                         int col = map[q[0] + n[0] * (q[1] + n[1] * q[2])];
@@ -724,14 +726,16 @@ static void validate(int nrep, const rbfib_grid *grids, const rbfib_bodies *bodi
         throw (int)RBFIB_EINVAL;
     for (int r = 0; r < nrep; ++r) {
         const rbfib_grid &g = grids[r];
-        int walls = 0;
+        int walls = 0, periodic = 0;
         for (int a = 0; a < 3; ++a) {
             if (g.n[a] < 4 || g.n[a] > (1 << 16)) throw (int)RBFIB_EINVAL;
             if ((double)g.n[0] * g.n[1] * g.n[2] >= 2147483647.0) throw (int)RBFIB_EINVAL;
-            if (g.bc[a] != RBFIB_PERIODIC && g.bc[a] != RBFIB_WALL) throw (int)RBFIB_EINVAL;
+            if (g.bc[a] != RBFIB_PERIODIC && g.bc[a] != RBFIB_WALL && g.bc[a] != RBFIB_SLIP) throw (int)RBFIB_EINVAL;
             walls += g.bc[a] == RBFIB_WALL;
+            periodic += g.bc[a] == RBFIB_PERIODIC;
         }
-        if (walls == 0 || !(g.h > 0.0) || !(g.eta > 0.0)) throw (int)RBFIB_EINVAL;
+        // a periodic axis needs a no-slip wall somewhere, or uniform flow along it is free
+        if ((walls == 0 && periodic > 0) || periodic == 3 || !(g.h > 0.0) || !(g.eta > 0.0)) throw (int)RBFIB_EINVAL;
         const rbfib_bodies &b = bodies[r];
         if (b.nb < 0 || b.nm < 0) throw (int)RBFIB_EINVAL;
         if (b.nb > 0 && (!b.marker_offset || !b.r_ref)) throw (int)RBFIB_EINVAL;

@@ -60,6 +60,27 @@ def kernel6_configs():
     return out
 
 
+def slip_configs():
+    """Free-slip walls: a closed free-slip box; a box periodic in x with no-slip walls
+    in y and free-slip walls in z; a ragged box mixing both wall types; the 6-point
+    kernel with free-slip walls."""
+    import copy
+    out = {}
+    w = W.small_box(41, n=(12, 12, 16), n_bodies=3, R=1.5, shape="ico12")
+    w.bc = (W.SLIP, W.SLIP, W.SLIP)
+    out["slip_box_12x12x16"] = w
+    w = W.small_box(42, n=(16, 12, 12), n_bodies=3, R=1.5, shape="ico12")
+    w.bc = (W.PERIODIC, W.WALL, W.SLIP)
+    out["periodic_x_wall_y_slip_z_16x12x12"] = w
+    w = W.small_box(43, n=(10, 12, 14), n_bodies=3, R=1.5, shape="ico12")
+    w.bc = (W.SLIP, W.WALL, W.SLIP)
+    out["slip_wall_slip_10x12x14"] = w
+    w = copy.deepcopy(out["periodic_x_wall_y_slip_z_16x12x12"])
+    w.kernel = 6
+    out["periodic_x_wall_y_slip_z_16x12x12_k6"] = w
+    return out
+
+
 def sem_configs():
     return {
         "two_spheres_16x16x32": W.spheres_in_box(31, (16, 16, 32), 2, name="two_small"),
@@ -87,4 +108,5 @@ def gain_configs():
     for k, w in kernel6_configs().items():
         if k != "monolayer_64x32x16_k6":          # apply only
             out[k] = w
+    out.update(slip_configs())
     return out

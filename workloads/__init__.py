@@ -32,7 +32,8 @@ from typing import List, Optional, Sequence, Tuple
 import numpy as np
 
 PERIODIC = 0
-WALL = 1
+WALL = 1          # no-slip wall
+SLIP = 2          # free-slip wall
 
 GOLDEN = (1.0 + math.sqrt(5.0)) / 2.0
 
