@@ -34,7 +34,7 @@ EXPORTS = [
     "rbfib_destroy", "rbfib_set_opts", "rbfib_state_size", "rbfib_layout", "rbfib_markers",
     "rbfib_apply_saddle", "rbfib_precondition", "rbfib_solve_mobility", "rbfib_fluctuating_stress",
     "rbfib_sem_step", "rbfib_mobility_vjp", "rbfib_kernel_stats", "rbfib_enable_timing",
-    "rbfib_apply_saddle_noalloc",
+    "rbfib_apply_saddle_noalloc", "rbfib_launch_geometry",
 ]
 
 
@@ -97,6 +97,7 @@ def _load():
         "rbfib_mobility_vjp": (I, [P, P, P, P, P, P, P, P, P, ctypes.POINTER(rbfib_info)]),
         "rbfib_kernel_stats": (I, [P, I, ctypes.POINTER(D), ctypes.POINTER(D), ctypes.POINTER(ctypes.c_longlong)]),
         "rbfib_enable_timing": (I, [P, I]),
+        "rbfib_launch_geometry": (I, [P, ctypes.POINTER(ctypes.c_int)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -340,6 +341,12 @@ def rbfib_kernel_stats(ctx: Context, which: int):
     _check(_lib.rbfib_kernel_stats(ctx.h, int(which), ctypes.byref(a), ctypes.byref(b), ctypes.byref(n)),
            "rbfib_kernel_stats")
     return a.value, b.value, n.value
+
+
+def rbfib_launch_geometry(ctx: Context) -> dict:
+    out = (ctypes.c_int * 4)()
+    _check(_lib.rbfib_launch_geometry(ctx.h, out), "rbfib_launch_geometry")
+    return {"krylov_chunk": out[0], "spread_grid": out[1], "spread_p": out[2], "mg_npt": out[3]}
 
 
 def library_path() -> str:

@@ -19,7 +19,8 @@
 #define RB_MAXLEV 12
 #define RB_TILE 4
 #define RB_BLOCK 256
-#define RB_CHUNK 1024          // Krylov elements per block (RB_BLOCK * 4)
+#define RB_CHUNK 1024          // default Krylov elements per block (RB_BLOCK * 4); the launch-geometry
+                               // table chooses 512, 1024 or 2048 per workload class
 // Fused multigrid kernels: a workgroup owns MGF_OX x MGF_OY x MGF_ZC fine points
 // of one component (all even, so that coarse cells never straddle two blocks).
 #define MGF_OX 32
@@ -254,8 +255,21 @@ struct SweepW {         // weight of each smoothing sweep of a V-cycle (sweep k 
 
 struct BlockEnt {       // one block of work: replica and local start index
     int rep;
-    int npt;            // grid points per thread (stride RB_BLOCK) for the stencil kernels
+    int npt;            // points per thread (stride RB_BLOCK): grid points for the stencil
+                        // kernels, vector elements (chunk / RB_BLOCK) for the Krylov kernels
     long long start;
+};
+
+// Launch geometry of one context, from the table the autotuner writes (read at
+// creation; built-in defaults without one): Krylov elements per workgroup,
+// workgroups of the spreading grid-stride loop, (tile, marker) pairs staged per LDS
+// round of the spreading pass, and grid points per thread of the multigrid and
+// cell kernels (0: four on batches of at least 2^22 cells, else one).
+struct Tuning {
+    int krylov_chunk = RB_CHUNK;
+    int spread_grid = 65536;
+    int spread_p = 32;
+    int mg_npt = 0;
 };
 
 struct ShapeDev {       // per distinct body shape: body-block preconditioner data
@@ -551,6 +565,7 @@ struct Ctx {
     rbfib_opts opts;
     int nrep = 0;
     int kw = 4;               // delta-kernel width (4 or 6), fixed at creation
+    Tuning tune;              // launch geometry, fixed at creation
     std::vector<RepDev> reps;
     long long L = 0;          // state length
     int nb = 0, nm = 0;

@@ -312,7 +312,7 @@ void launch_markers(Ctx &c, MarkerSet &ms, const double *q, const double *theta,
 
 // ------------------------------------------------------------------ spreading (gather)
 // One wavefront per tile that has pairs, one lane per (x, y, z) cell of the tile.  The
-// tile's pairs are taken SPREAD_P at a time: lane i loads the cached folded 1-D
+// tile's pairs are taken SPREAD_P (16, 32 or 64) at a time: lane i loads the cached folded 1-D
 // weights of pair i's marker (3 components x 3 axes x W points, with their folded
 // indices) and its lambda, projects them onto the tile's 4-cell window on each axis
 // (several support points can fold onto one cell next to a wall), folds lambda_c into
@@ -323,7 +323,6 @@ void launch_markers(Ctx &c, MarkerSet &ms, const double *q, const double *theta,
 // result is deterministic.
 // TO = double: y is a state vector (velocity of replica r at R.off + c N);
 // with levs given: y is a multigrid pool, level 0 of each replica.
-#define SPREAD_P 32
 // the cached folded weights and indices of (marker m, component c, axis a)
 template <int W>
 __device__ __forceinline__ void load_axis(const double *__restrict__ wc, const int *__restrict__ ic, long long o,
@@ -349,7 +348,7 @@ __device__ __forceinline__ void load_axis<6>(const double *__restrict__ wc, cons
     }
 }
 
-template <typename TO, typename TL, int W>
+template <typename TO, typename TL, int W, int SPREAD_P>
 __global__ __launch_bounds__(64) void k_spread(const RepDev *reps, const int *tile_rep, const int *active,
                                                const int *n_active, const int *pair_start, const int *pair_count,
                                                long long cap, const int *__restrict__ pair_m,
@@ -420,15 +419,15 @@ __global__ __launch_bounds__(64) void k_spread(const RepDev *reps, const int *ti
 template <typename TO, typename TL>
 static void spread_into(Ctx &c, MarkerSet &ms, const TL *lam_state, TO *y, double alpha, const LevDev *levs) {
     if (c.nm == 0) return;
-    int grid = std::min(c.ntiles, 65536);   // grid-stride over the tiles that have pairs
-    if (c.kw == 6)
-        hipLaunchKernelGGL((k_spread<TO, TL, 6>), dim3(grid), dim3(64), 0, c.stream, c.d_reps, c.d_tile_rep, ms.active,
-                           ms.n_active, ms.pair_start, ms.pair_count, ms.pair_cap, ms.pair_m, ms.wc, ms.ic,
-                           lam_state, y, alpha, c.mask, levs);
-    else
-        hipLaunchKernelGGL((k_spread<TO, TL, 4>), dim3(grid), dim3(64), 0, c.stream, c.d_reps, c.d_tile_rep, ms.active,
-                           ms.n_active, ms.pair_start, ms.pair_count, ms.pair_cap, ms.pair_m, ms.wc, ms.ic,
-                           lam_state, y, alpha, c.mask, levs);
+    // grid-stride over the tiles that have pairs, with the launch geometry's grid and
+    // pairs per LDS round
+    const int grid = std::min(c.ntiles, c.tune.spread_grid);
+    const int P = c.tune.spread_p;
+    auto kern = c.kw == 6 ? (P == 16 ? k_spread<TO, TL, 6, 16> : (P == 64 ? k_spread<TO, TL, 6, 64> : k_spread<TO, TL, 6, 32>))
+                          : (P == 16 ? k_spread<TO, TL, 4, 16> : (P == 64 ? k_spread<TO, TL, 4, 64> : k_spread<TO, TL, 4, 32>));
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(64), 0, c.stream, c.d_reps, c.d_tile_rep, ms.active, ms.n_active,
+                       ms.pair_start, ms.pair_count, ms.pair_cap, ms.pair_m, ms.wc, ms.ic, lam_state, y, alpha, c.mask,
+                       levs);
 }
 
 // y_fluid += alpha * S lambda, lambda read from the lambda slots of lam_state.

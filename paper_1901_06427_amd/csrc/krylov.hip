@@ -1,7 +1,9 @@
 // Flexible GMRES building blocks, batched over independent replicas.
 // Every replica owns a contiguous segment of each state vector; blocks are
-// replica-aligned chunks of RB_CHUNK elements, so per-replica dot products are
-// block partial sums reduced in a fixed order (deterministic, no atomics).
+// replica-aligned chunks of CH elements (512, 1024 or 2048, the context's launch
+// geometry; the vector block table carries CH / RB_BLOCK as its points per thread),
+// so per-replica dot products are block partial sums reduced in a fixed order
+// (deterministic, no atomics).
 // Hessenberg, Givens rotations and the least-squares solve live on the device,
 // one thread per replica.
 #include "common.h"
@@ -20,29 +22,30 @@ __device__ __forceinline__ double wave_sum(double v) {
 // non-temporal loads keep it from displacing w and the partials in the caches
 // (about 3 percent faster on the 256-replica ensemble; the basis update, which also
 // writes w, is not helped by them).
+template <int CH>
 __global__ __launch_bounds__(RB_BLOCK) void k_dot_partial(const RepDev *reps, const BlockEnt *tab, const double *V,
                                                           long long L, int nvec, const double *__restrict__ w,
                                                           double *partial, int stride, const int *mask) {
-    __shared__ double ws[RB_CHUNK];
+    __shared__ double ws[CH];
     BlockEnt be = tab[blockIdx.x];
     if (mask && !mask[be.rep]) return;
     const RepDev &R = reps[be.rep];
     long long b = R.off + be.start;
-    int n = (int)min((long long)RB_CHUNK, R.len - be.start);
-    for (int k = threadIdx.x; k < RB_CHUNK; k += RB_BLOCK) ws[k] = (k < n) ? w[b + k] : 0.0;
+    int n = (int)min((long long)CH, R.len - be.start);
+    for (int k = threadIdx.x; k < CH; k += RB_BLOCK) ws[k] = (k < n) ? w[b + k] : 0.0;
     __syncthreads();
     int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     for (int i = wid; i < nvec; i += RB_BLOCK / 64) {
         const double *Vi = V + (long long)i * L + b;
-        double v[RB_CHUNK / 64];
+        double v[CH / 64];
 #pragma unroll
-        for (int m = 0; m < RB_CHUNK / 64; ++m) {
+        for (int m = 0; m < CH / 64; ++m) {
             const int k = lane + 64 * m;
             v[m] = k < n ? __builtin_nontemporal_load(Vi + k) : 0.0;
         }
         double acc = 0.0;
 #pragma unroll
-        for (int m = 0; m < RB_CHUNK / 64; ++m) acc = fma(v[m], ws[lane + 64 * m], acc);
+        for (int m = 0; m < CH / 64; ++m) acc = fma(v[m], ws[lane + 64 * m], acc);
         acc = wave_sum(acc);
         if (lane == 0) partial[(long long)blockIdx.x * stride + i] = acc;
     }
@@ -66,25 +69,30 @@ __global__ void k_dot_reduce(const int *first, const int *nblk, const double *pa
     if (threadIdx.x == 0) out[(long long)blockIdx.z * zout + (long long)r * out_stride + i] = take_sqrt ? sqrt(s) : s;
 }
 
+// the kernel instance of the context's Krylov chunk
+#define RB_BY_CHUNK(c, K, ...) \
+    ((c).tune.krylov_chunk == 512 ? K<__VA_ARGS__ 512> : ((c).tune.krylov_chunk == 2048 ? K<__VA_ARGS__ 2048> : K<__VA_ARGS__ 1024>))
+
 void launch_dots(Ctx &c, const double *V, int nvec, const double *w, double *out, const int *mask,
                  const double *scale) {
     int stride = c.m + 1;
-    hipLaunchKernelGGL(k_dot_partial, dim3(c.n_tab_vec), dim3(RB_BLOCK), 0, c.stream, c.d_reps, c.d_tab_vec, V,
-                       c.L, nvec, w, c.partial, stride, mask);
+    hipLaunchKernelGGL(RB_BY_CHUNK(c, k_dot_partial, ), dim3(c.n_tab_vec), dim3(RB_BLOCK), 0, c.stream, c.d_reps,
+                       c.d_tab_vec, V, c.L, nvec, w, c.partial, stride, mask);
     hipLaunchKernelGGL(k_dot_reduce, dim3(c.nrep, nvec), dim3(64), 0, c.stream, c.d_vec_first, c.d_vec_nblk,
                        c.partial, stride, out, c.m + 1, mask, 0, scale);
 }
 
 void launch_norm(Ctx &c, const double *w, double *out, const int *mask) {
     int stride = c.m + 1;
-    hipLaunchKernelGGL(k_dot_partial, dim3(c.n_tab_vec), dim3(RB_BLOCK), 0, c.stream, c.d_reps, c.d_tab_vec, w, c.L,
-                       1, w, c.partial, stride, mask);
+    hipLaunchKernelGGL(RB_BY_CHUNK(c, k_dot_partial, ), dim3(c.n_tab_vec), dim3(RB_BLOCK), 0, c.stream, c.d_reps,
+                       c.d_tab_vec, w, c.L, 1, w, c.partial, stride, mask);
     hipLaunchKernelGGL(k_dot_reduce, dim3(c.nrep, 1), dim3(64), 0, c.stream, c.d_vec_first, c.d_vec_nblk, c.partial,
                        stride, out, 1, mask, 1, (const double *)nullptr);
 }
 
 // w += sign * sum_i coef[r][i] scale[r][i] V_i (scale 1 when not given); when
 // partial is given, also the block partials of the updated w's squared norm.
+template <int CH>
 __global__ __launch_bounds__(RB_BLOCK) void k_axpy_multi(const RepDev *reps, const BlockEnt *tab, const double *V,
                                                          long long L, int nvec, const double *coef, int cstride,
                                                          const double *scale, double *__restrict__ w, double sign,
@@ -100,10 +108,10 @@ __global__ __launch_bounds__(RB_BLOCK) void k_axpy_multi(const RepDev *reps, con
     }
     __syncthreads();
     long long b = R.off + be.start;
-    int n = (int)min((long long)RB_CHUNK, R.len - be.start);
-    // four elements per thread; four basis vectors per step, so that sixteen loads
-    // are in flight; each element sums its terms in increasing i
-    constexpr int E = RB_CHUNK / RB_BLOCK;
+    int n = (int)min((long long)CH, R.len - be.start);
+    // CH / RB_BLOCK elements per thread; four basis vectors per step, so that four
+    // loads per element are in flight; each element sums its terms in increasing i
+    constexpr int E = CH / RB_BLOCK;
     double acc[E];
     bool ok[E];
 #pragma unroll
@@ -152,16 +160,16 @@ __global__ __launch_bounds__(RB_BLOCK) void k_axpy_multi(const RepDev *reps, con
 
 void launch_axpy_multi(Ctx &c, const double *V, int nvec, const double *coef, double *w, double sign, const int *mask,
                        const double *scale) {
-    hipLaunchKernelGGL(k_axpy_multi, dim3(c.n_tab_vec), dim3(RB_BLOCK), 0, c.stream, c.d_reps, c.d_tab_vec, V, c.L,
-                       nvec, coef, c.m + 1, scale, w, sign, mask, (double *)nullptr, 0);
+    hipLaunchKernelGGL(RB_BY_CHUNK(c, k_axpy_multi, ), dim3(c.n_tab_vec), dim3(RB_BLOCK), 0, c.stream, c.d_reps,
+                       c.d_tab_vec, V, c.L, nvec, coef, c.m + 1, scale, w, sign, mask, (double *)nullptr, 0);
 }
 
 // w -= sum_i coef_i scale_i V_i and nrm[r] = ||w|| in two launches.
 void launch_axpy_multi_norm(Ctx &c, const double *V, int nvec, const double *coef, double *w, double *nrm,
                             const int *mask, const double *scale) {
     int stride = c.m + 1;
-    hipLaunchKernelGGL(k_axpy_multi, dim3(c.n_tab_vec), dim3(RB_BLOCK), 0, c.stream, c.d_reps, c.d_tab_vec, V, c.L,
-                       nvec, coef, c.m + 1, scale, w, -1.0, mask, c.partial, stride);
+    hipLaunchKernelGGL(RB_BY_CHUNK(c, k_axpy_multi, ), dim3(c.n_tab_vec), dim3(RB_BLOCK), 0, c.stream, c.d_reps,
+                       c.d_tab_vec, V, c.L, nvec, coef, c.m + 1, scale, w, -1.0, mask, c.partial, stride);
     hipLaunchKernelGGL(k_dot_reduce, dim3(c.nrep, 1), dim3(64), 0, c.stream, c.d_vec_first, c.d_vec_nblk, c.partial,
                        stride, nrm, 1, mask, 1, (const double *)nullptr);
 }
@@ -178,7 +186,7 @@ __global__ void k_scale(const RepDev *reps, const BlockEnt *tab, const double *w
         f = 1.0 / f;
     }
     long long b = R.off + be.start;
-    long long e = R.off + min(be.start + (long long)RB_CHUNK, R.len);
+    long long e = R.off + min(be.start + (long long)be.npt * RB_BLOCK, R.len);
     for (long long g = b + threadIdx.x; g < e; g += RB_BLOCK) out[g] = w[g] * f;
 }
 
@@ -193,7 +201,7 @@ __global__ void k_axpby(const RepDev *reps, const BlockEnt *tab, double a, const
     if (mask && !mask[be.rep]) return;
     const RepDev &R = reps[be.rep];
     long long s = R.off + be.start;
-    long long e = R.off + min(be.start + (long long)RB_CHUNK, R.len);
+    long long e = R.off + min(be.start + (long long)be.npt * RB_BLOCK, R.len);
     for (long long g = s + threadIdx.x; g < e; g += RB_BLOCK) {
         double v = (a == 0.0 ? 0.0 : a * x[g]);
         if (b != 0.0) v += b * y[g];
@@ -286,26 +294,26 @@ void launch_givens(Ctx &c, int j, double tol) {
 // GMRES applies unchanged.  The basis is streamed once per S steps.
 
 // partial[blk * stride + t * half + i] = the block's part of V_i . w_t, w_t = W + t L
-template <int S>
+template <int S, int CH>
 __global__ __launch_bounds__(RB_BLOCK) void k_dot_partial_s(const RepDev *reps, const BlockEnt *tab, const double *V,
                                                             long long L, int nvec, const double *W, double *partial,
                                                             int stride, int half, const int *mask) {
-    __shared__ double ws[S][RB_CHUNK];
+    __shared__ double ws[S][CH];
     BlockEnt be = tab[blockIdx.x];
     if (mask && !mask[be.rep]) return;
     const RepDev &R = reps[be.rep];
     long long b = R.off + be.start;
-    int n = (int)min((long long)RB_CHUNK, R.len - be.start);
-    for (int k = threadIdx.x; k < RB_CHUNK; k += RB_BLOCK)
+    int n = (int)min((long long)CH, R.len - be.start);
+    for (int k = threadIdx.x; k < CH; k += RB_BLOCK)
 #pragma unroll
         for (int t = 0; t < S; ++t) ws[t][k] = (k < n) ? W[(long long)t * L + b + k] : 0.0;
     __syncthreads();
     int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     for (int i = wid; i < nvec; i += RB_BLOCK / 64) {
         const double *Vi = V + (long long)i * L + b;
-        double v[RB_CHUNK / 64];
+        double v[CH / 64];
 #pragma unroll
-        for (int m = 0; m < RB_CHUNK / 64; ++m) {
+        for (int m = 0; m < CH / 64; ++m) {
             const int k = lane + 64 * m;
             v[m] = k < n ? __builtin_nontemporal_load(Vi + k) : 0.0;
         }
@@ -313,7 +321,7 @@ __global__ __launch_bounds__(RB_BLOCK) void k_dot_partial_s(const RepDev *reps, 
 #pragma unroll
         for (int t = 0; t < S; ++t) a[t] = 0.0;
 #pragma unroll
-        for (int m = 0; m < RB_CHUNK / 64; ++m)
+        for (int m = 0; m < CH / 64; ++m)
 #pragma unroll
             for (int t = 0; t < S; ++t) a[t] = fma(v[m], ws[t][lane + 64 * m], a[t]);
 #pragma unroll
@@ -327,7 +335,7 @@ __global__ __launch_bounds__(RB_BLOCK) void k_dot_partial_s(const RepDev *reps, 
 // u_t -= sum_i coef[t][r][i] scale[r][i] V_i (t < S, u_t = W + t L, coef sets nrep (m+1)
 // apart), and the block partials of the upper triangle of the Gram matrix of the
 // updated u (row-major, S (S + 1) / 2 entries) at partial[blk * stride + q]
-template <int S>
+template <int S, int CH>
 __global__ __launch_bounds__(RB_BLOCK) void k_axpy_multi_s(const RepDev *reps, const BlockEnt *tab, const double *V,
                                                            long long L, int nvec, const double *coef,
                                                            long long cset, int cstride, const double *scale,
@@ -346,8 +354,8 @@ __global__ __launch_bounds__(RB_BLOCK) void k_axpy_multi_s(const RepDev *reps, c
     }
     __syncthreads();
     long long b = R.off + be.start;
-    int n = (int)min((long long)RB_CHUNK, R.len - be.start);
-    constexpr int E = RB_CHUNK / RB_BLOCK;
+    int n = (int)min((long long)CH, R.len - be.start);
+    constexpr int E = CH / RB_BLOCK;
     double a[S][E];
     bool ok[E];
 #pragma unroll
@@ -418,8 +426,8 @@ void launch_block_dots(Ctx &c, int S, const double *V, int nvec, const double *W
     const int half = c.m + 1, stride = RB_MAXS * half;
     const long long cset = (long long)c.nrep * (c.m + 1);
 #define RB_DOTS(SS)                                                                                                  \
-    hipLaunchKernelGGL(k_dot_partial_s<SS>, dim3(c.n_tab_vec), dim3(RB_BLOCK), 0, c.stream, c.d_reps, c.d_tab_vec, V, \
-                       c.L, nvec, W, c.partial, stride, half, mask)
+    hipLaunchKernelGGL(RB_BY_CHUNK(c, k_dot_partial_s, SS, ), dim3(c.n_tab_vec), dim3(RB_BLOCK), 0, c.stream, c.d_reps, \
+                       c.d_tab_vec, V, c.L, nvec, W, c.partial, stride, half, mask)
     if (S == 2) RB_DOTS(2);
     else if (S == 3) RB_DOTS(3);
     else RB_DOTS(4);
@@ -433,8 +441,8 @@ void launch_block_update(Ctx &c, int S, const double *V, int nvec, double *W, co
     const int stride = RB_MAXS * (c.m + 1);
     const long long cset = (long long)c.nrep * (c.m + 1);
 #define RB_UPD(SS)                                                                                                   \
-    hipLaunchKernelGGL(k_axpy_multi_s<SS>, dim3(c.n_tab_vec), dim3(RB_BLOCK), 0, c.stream, c.d_reps, c.d_tab_vec, V,  \
-                       c.L, nvec, c.hblk, cset, c.m + 1, scale, W, mask, c.partial, stride)
+    hipLaunchKernelGGL(RB_BY_CHUNK(c, k_axpy_multi_s, SS, ), dim3(c.n_tab_vec), dim3(RB_BLOCK), 0, c.stream, c.d_reps, \
+                       c.d_tab_vec, V, c.L, nvec, c.hblk, cset, c.m + 1, scale, W, mask, c.partial, stride)
     if (S == 2) RB_UPD(2);
     else if (S == 3) RB_UPD(3);
     else RB_UPD(4);
@@ -558,7 +566,7 @@ __global__ void k_combine_s(const RepDev *reps, const BlockEnt *tab, long long L
 #pragma unroll
         for (int k = 0; k < S; ++k) f[l][k] = T[l * RB_MAXS + k];
     long long b = R.off + be.start;
-    long long e = R.off + min(be.start + (long long)RB_CHUNK, R.len);
+    long long e = R.off + min(be.start + (long long)be.npt * RB_BLOCK, R.len);
     for (long long g = b + threadIdx.x; g < e; g += RB_BLOCK) {
         double w[S];
 #pragma unroll
@@ -621,7 +629,7 @@ __global__ __launch_bounds__(RB_BLOCK) void k_update_x(const RepDev *reps, const
     int n = jf[be.rep];
     const double *yr = y + (long long)be.rep * (m + 1);
     long long b = R.off + be.start;
-    long long e = R.off + min(be.start + (long long)RB_CHUNK, R.len);
+    long long e = R.off + min(be.start + (long long)be.npt * RB_BLOCK, R.len);
     for (long long g = b + threadIdx.x; g < e; g += RB_BLOCK) {
         double acc = 0.0;
 #pragma unroll 8

@@ -4,8 +4,12 @@
 // and the C ABI declared in include/rbfib.h.
 #include "common.h"
 
+#include <dlfcn.h>
+
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <string>
@@ -747,6 +751,50 @@ static void validate(int nrep, const rbfib_grid *grids, const rbfib_bodies *bodi
     }
 }
 
+// ------------------------------------------------------------------ launch-geometry table
+// The autotuner (paper_1901_06427_amd/autotune.py) writes one line per workload class:
+//     cells_lo cells_hi reps_lo reps_hi krylov_chunk spread_grid spread_p mg_npt
+// ('#' starts a comment).  A context takes the first line whose ranges (inclusive)
+// hold its total cell count and replica count.  The file is $RBFIB_TUNING when set
+// (empty: built-in defaults), else tuning.txt beside the library; without a file or
+// a matching line the built-in defaults apply.  Invalid values are ignored.
+static std::string library_dir() {
+    Dl_info info;
+    if (dladdr((void *)&rbfib_default_opts, &info) && info.dli_fname) {
+        std::string p(info.dli_fname);
+        size_t k = p.find_last_of('/');
+        return k == std::string::npos ? std::string(".") : p.substr(0, k);
+    }
+    return ".";
+}
+
+static Tuning load_tuning(long long cells, int nrep, std::string *source) {
+    Tuning t;
+    const char *env = getenv("RBFIB_TUNING");
+    std::string path = env ? std::string(env) : library_dir() + "/tuning.txt";
+    if (source) *source = "defaults";
+    if (path.empty()) return t;
+    FILE *f = fopen(path.c_str(), "r");
+    if (!f) return t;
+    char line[512];
+    while (fgets(line, sizeof line, f)) {
+        char *hash = strchr(line, '#');
+        if (hash) *hash = 0;
+        long long clo, chi;
+        int rlo, rhi, ch, sg, sp, np;
+        if (sscanf(line, "%lld %lld %d %d %d %d %d %d", &clo, &chi, &rlo, &rhi, &ch, &sg, &sp, &np) != 8) continue;
+        if (cells < clo || cells > chi || nrep < rlo || nrep > rhi) continue;
+        if (ch == 512 || ch == 1024 || ch == 2048) t.krylov_chunk = ch;
+        if (sg >= 64 && sg <= (1 << 20)) t.spread_grid = sg;
+        if (sp == 16 || sp == 32 || sp == 64) t.spread_p = sp;
+        if (np == 0 || np == 1 || np == 4) t.mg_npt = np;
+        if (source) *source = path;
+        break;
+    }
+    fclose(f);
+    return t;
+}
+
 static void build(Ctx &c, int nrep, const rbfib_grid *grids, const rbfib_bodies *bodies) {
     c.nrep = nrep;
     c.reps.resize(nrep);
@@ -844,10 +892,12 @@ static void build(Ctx &c, int nrep, const rbfib_grid *grids, const rbfib_bodies 
     // otherwise (keeps enough workgroups in flight on small grids).
     long long total_cells = 0;
     for (int r = 0; r < nrep; ++r) total_cells += c.reps[r].N;
-    const int mg_npt = total_cells >= (1LL << 22) ? 4 : 1;
+    const int mg_npt = c.tune.mg_npt ? c.tune.mg_npt : (total_cells >= (1LL << 22) ? 4 : 1);
     c.mg_npt = mg_npt;
+    // Krylov vector blocks: chunks of krylov_chunk elements, which the block table
+    // carries as its points per thread (chunk / RB_BLOCK)
     auto chunks = [](std::vector<BlockEnt> &tab, int rep, long long n, long long step) {
-        for (long long s = 0; s < n; s += step) tab.push_back(BlockEnt{rep, 1, s});
+        for (long long s = 0; s < n; s += step) tab.push_back(BlockEnt{rep, (int)(step / RB_BLOCK), s});
     };
     auto gchunks = [](std::vector<BlockEnt> &tab, int rep, long long n, int npt) {
         for (long long s = 0; s < n; s += (long long)RB_BLOCK * npt) tab.push_back(BlockEnt{rep, npt, s});
@@ -859,7 +909,7 @@ static void build(Ctx &c, int nrep, const rbfib_grid *grids, const rbfib_bodies 
         gchunks(tcells, r, c.reps[r].N, mg_npt);
         gchunks(tcells2, r, c.reps[r].N, 2);
         c.vec_first[r] = (int)tvec.size();
-        chunks(tvec, r, c.reps[r].len, RB_CHUNK);
+        chunks(tvec, r, c.reps[r].len, c.tune.krylov_chunk);
         c.vec_nblk[r] = (int)tvec.size() - c.vec_first[r];
     }
     c.n_tab_cells = (int)tcells.size();
@@ -1227,6 +1277,9 @@ int rbfib_create_batch(int nrep, const rbfib_grid *grids, const rbfib_bodies *bo
         HIP_OK(hipEventCreateWithFlags(&ctx->c.ev_out, hipEventDisableTiming));
         ctx->c.opts = o;
         ctx->c.kw = o.kernel;
+        long long cells = 0;
+        for (int r = 0; r < nrep; ++r) cells += (long long)grids[r].n[0] * grids[r].n[1] * grids[r].n[2];
+        ctx->c.tune = load_tuning(cells, nrep, nullptr);
         build(ctx->c, nrep, grids, bodies);
         *out = ctx;
         return RBFIB_OK;
@@ -1444,6 +1497,16 @@ int rbfib_mobility_vjp(rbfib_ctx *ctx, const double *q, const double *theta, con
     }
     return ret;
     GUARD_END
+}
+
+int rbfib_launch_geometry(const rbfib_ctx *ctx, int *out) {
+    if (!ctx || !out) return RBFIB_EINVAL;
+    const Ctx &c = ctx->c;
+    out[0] = c.tune.krylov_chunk;
+    out[1] = c.tune.spread_grid;
+    out[2] = c.tune.spread_p;
+    out[3] = c.mg_npt;
+    return RBFIB_OK;
 }
 
 int rbfib_enable_timing(rbfib_ctx *ctx, int on) {
