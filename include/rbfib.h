@@ -163,6 +163,11 @@ typedef struct {
                                /*    function, 6 = the 6-point function of Bao,      */
                                /*    Kaiser & Peskin the paper uses (blob radius     */
                                /*    1.47 h; set blob_radius to match) (4)           */
+    int no_drift;              /* 1: rbfib_sem_step drops the random finite          */
+                               /*    differences of Algorithm 1 (no RFD solves, no   */
+                               /*    stochastic drift): the naive Euler-Maruyama     */
+                               /*    scheme, whose equilibrium is biased (Appendix   */
+                               /*    A); for demonstrating that bias only (0)        */
 } rbfib_opts;
 
 typedef struct {
@@ -263,6 +268,28 @@ int rbfib_fluctuating_stress(rbfib_ctx *ctx, double kT, double dt, uint64_t seed
 int rbfib_sem_step(rbfib_ctx *ctx, double *q, double *theta, const double *FT,
                    const double *slip, double kT, double dt, uint64_t seed, uint64_t step,
                    double *U, rbfib_info *info);
+
+/* Caller-side conservative forces of the paper's confined test problems.
+ * Every marker i of body p, at r_i = q_p + d_i with d_i = R(theta_p) r_i^ref,
+ * feels the soft wall repulsion of eq. Usoft (Sec. V.A),
+ *     Phi(r) = phi0 (1 + (d - r)/b)  for r < d,   phi0 exp((d - r)/b)  for r >= d,
+ * from both faces of every non-periodic axis (r = its distance to the face,
+ * the faces at 0 and n h), plus the constant force fconst (App. A: the
+ * buoyant weight -m_e g z-hat of each blob).  Energies in the caller's units. */
+typedef struct {
+    double phi0;               /* strength of the repulsion                         */
+    double d;                  /* range where the profile turns exponential         */
+    double b;                  /* decay length (> 0)                                */
+    double fconst[3];          /* constant force on every marker                    */
+} rbfib_potential;
+
+/* FT [nb, 6] (device, FP64, overwritten) = per body [sum_i f_i ; sum_i d_i x f_i],
+ * f_i = -grad of marker i's energy; the torque is about the tracking point q_p.
+ * q [nb, 3], theta [nb, 4] device, theta unit quaternions (not checked here;
+ * rbfib_sem_step checks them).  Asynchronous on the context's stream.
+ * RBFIB_EINVAL: a null pointer, b <= 0 or a non-finite parameter. */
+int rbfib_body_forces(rbfib_ctx *ctx, const double *q, const double *theta,
+                      const rbfib_potential *pot, double *FT);
 
 /* Vector-Jacobian product of U = N(q, theta) F (no slip, no wall motion;
  * eqs. D1-D4 differentiated): given Ubar = dL/dU [nb, 6], returns

@@ -25,7 +25,9 @@ the velocities its solves produced.
 
 The random forces and torques of step 1 come from the Philox stream of
 (seed, step); ``normals = (W^f, W^tau)`` replaces them with given values (used
-to evaluate the drift at chosen directions).
+to evaluate the drift at chosen directions).  ``drift = False`` sets the random
+finite differences of step 5 to zero: the naive Euler-Maruyama scheme whose
+bias the paper shows for the boomerang (Appendix A).
 """
 from __future__ import annotations
 
@@ -60,7 +62,7 @@ class SEMResult:
 
 def sem_step(g: mac.Grid, r_ref, offsets, q, theta, FT, kT: float, dt: float, seed: int, step: int,
              delta: float = 1e-5, slip: Optional[np.ndarray] = None, min_body_dist: float = 0.0,
-             tol: float = 1e-12, noise: bool = True, normals=None) -> SEMResult:
+             tol: float = 1e-12, noise: bool = True, normals=None, drift: bool = True) -> SEMResult:
     q = np.asarray(q, dtype=np.float64).reshape(-1, 3)
     theta = np.asarray(theta, dtype=np.float64).reshape(-1, 4)
     nb = q.shape[0]
@@ -110,6 +112,9 @@ def sem_step(g: mac.Grid, r_ref, offsets, q, theta, FT, kT: float, dt: float, se
     if noise and kT > 0.0:
         W = rng.fluid_normals(seed, step, g.nW)
         fluid = mac.noise_stress_divergence(g, W, kT, dt)
+    if not drift:
+        # naive Euler-Maruyama: the random finite differences are dropped
+        DKT, DK, DJ, DS = (np.zeros_like(a) for a in (DKT, DK, DJ, DS))
     slip2 = DK - DJ - DS
     if slip is not None:
         slip2 = slip2 + np.asarray(slip).reshape(-1, 3)

@@ -34,13 +34,18 @@ EXPORTS = [
     "rbfib_destroy", "rbfib_set_opts", "rbfib_state_size", "rbfib_layout", "rbfib_markers",
     "rbfib_apply_saddle", "rbfib_precondition", "rbfib_solve_mobility", "rbfib_fluctuating_stress",
     "rbfib_sem_step", "rbfib_mobility_vjp", "rbfib_kernel_stats", "rbfib_enable_timing",
-    "rbfib_apply_saddle_noalloc", "rbfib_launch_geometry",
+    "rbfib_apply_saddle_noalloc", "rbfib_launch_geometry", "rbfib_body_forces",
 ]
 
 
 class rbfib_grid(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int * 3), ("bc", ctypes.c_int * 3), ("h", ctypes.c_double),
                 ("eta", ctypes.c_double), ("wall_vel", ctypes.c_double * 18)]
+
+
+class rbfib_potential(ctypes.Structure):
+    _fields_ = [("phi0", ctypes.c_double), ("d", ctypes.c_double), ("b", ctypes.c_double),
+                ("fconst", ctypes.c_double * 3)]
 
 
 class rbfib_bodies(ctypes.Structure):
@@ -56,7 +61,8 @@ class rbfib_opts(ctypes.Structure):
                 ("min_body_dist", ctypes.c_double), ("check_every", ctypes.c_int), ("use_graphs", ctypes.c_int),
                 ("mg_fused", ctypes.c_int), ("mg_bottom", ctypes.c_int),
                 ("mg_cheby", ctypes.c_double), ("krylov_s", ctypes.c_int),
-                ("mg_first2", ctypes.c_int), ("kernel", ctypes.c_int)]
+                ("mg_first2", ctypes.c_int), ("kernel", ctypes.c_int),
+                ("no_drift", ctypes.c_int)]
 
 
 class rbfib_info(ctypes.Structure):
@@ -98,6 +104,7 @@ def _load():
         "rbfib_kernel_stats": (I, [P, I, ctypes.POINTER(D), ctypes.POINTER(D), ctypes.POINTER(ctypes.c_longlong)]),
         "rbfib_enable_timing": (I, [P, I]),
         "rbfib_launch_geometry": (I, [P, ctypes.POINTER(ctypes.c_int)]),
+        "rbfib_body_forces": (I, [P, P, P, ctypes.POINTER(rbfib_potential), P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -279,6 +286,12 @@ def rbfib_sem_step(ctx: Context, q, theta, FT, kT: float, dt: float, seed: int, 
                                int(step), _ptr(U), info)
     _check(code, "rbfib_sem_step", allow)
     return list(info)
+
+
+def rbfib_body_forces(ctx: Context, q, theta, phi0: float, d: float, b: float, fconst, FT) -> None:
+    """FT [nb, 6] = soft wall repulsion (eq. Usoft) plus a constant force per marker, summed per body."""
+    pot = rbfib_potential(float(phi0), float(d), float(b), (ctypes.c_double * 3)(*[float(v) for v in fconst]))
+    _check(_lib.rbfib_body_forces(ctx.h, _ptr(q), _ptr(theta), ctypes.byref(pot), _ptr(FT)), "rbfib_body_forces")
 
 
 def rbfib_mobility_vjp(ctx: Context, q, theta, FT, Ubar, dFT, dq, dphi, dtheta=None,

@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "librbfib.so")
 BUILD = os.path.join(HERE, "_build")
-SOURCES = ["grid.hip", "ib.hip", "krylov.hip", "sem.hip", "adjoint.hip", "mgfused.hip", "rbfib.hip", "noalloc.hip"]
+SOURCES = ["grid.hip", "ib.hip", "krylov.hip", "sem.hip", "adjoint.hip", "mgfused.hip", "rbfib.hip", "noalloc.hip", "forces.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17", "-mcode-object-version=5",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -697,6 +697,8 @@ void launch_body_grad(Ctx &c, const double *x, const double *xa, const double *t
                       double *dphi, double *dtheta);
 void launch_set_rhs_adjoint(Ctx &c, const double *Ubar, double *b);
 void launch_copy_U(Ctx &c, const double *x, double *U, double scale);
+void launch_body_forces(Ctx &c, const double *q, const double *theta, double phi0, double d, double b,
+                        const double fconst[3], double *FT);
 void launch_set_rhs(Ctx &c, const double *FT, const double *slip, double *b);
 
 // Krylov (krylov.hip)

@@ -661,23 +661,32 @@ static int sem_step(Ctx &c, double *q, double *theta, const double *FT, const do
     const double *th_solve = stage_theta(c, theta);
     // 1. random forces/torques and displaced configurations
     launch_body_rfd(c, kT, delta, seed, step, q, theta);
-    // 2. RFD solve: force W^FT, homogeneous data
-    launch_zero(c, c.rhs, nullptr);
-    launch_set_rhs_U(c, c.WFT, c.rhs);
-    fgmres(c, c.ms[0], th_solve, c.rhs, false, inf);
-    for (int r = 0; r < c.nrep; ++r) { out[r].iters += inf[r].iters; if (inf[r].status) out[r].status = inf[r].status; }
-    HIP_OK(hipMemcpyAsync(c.xR, c.xsol, sizeof(double) * c.L, hipMemcpyDeviceToDevice, c.stream));
-    // 3. markers at Q+ and Q-
+    const bool drift = c.opts.no_drift == 0;
+    // 2. RFD solve: force W^FT, homogeneous data (naive scheme: x^R = 0)
+    if (drift) {
+        launch_zero(c, c.rhs, nullptr);
+        launch_set_rhs_U(c, c.WFT, c.rhs);
+        fgmres(c, c.ms[0], th_solve, c.rhs, false, inf);
+        for (int r = 0; r < c.nrep; ++r) { out[r].iters += inf[r].iters; if (inf[r].status) out[r].status = inf[r].status; }
+        HIP_OK(hipMemcpyAsync(c.xR, c.xsol, sizeof(double) * c.L, hipMemcpyDeviceToDevice, c.stream));
+    } else {
+        zero_device(c, c.xR, c.L);
+    }
+    // 3. markers at Q+ and Q- (also for the rejection test of step 7)
     clear_flags(c);
     launch_markers(c, c.ms[1], c.q_buf[0], c.th_buf[0]);
     launch_markers(c, c.ms[2], c.q_buf[1], c.th_buf[1]);
-    // 4. unconstrained Stokes solve with (1/delta)[S(Q+) - S(Q-)] lambda^R
-    launch_zero(c, c.rhs, nullptr);
-    launch_spread(c, c.ms[1], c.xR, c.rhs, 1.0 / delta);
-    launch_spread(c, c.ms[2], c.xR, c.rhs, -1.0 / delta);
-    fgmres(c, c.ms[0], th_solve, c.rhs, true, inf);
-    for (int r = 0; r < c.nrep; ++r) { out[r].iters += inf[r].iters; if (inf[r].status) out[r].status = inf[r].status; }
-    HIP_OK(hipMemcpyAsync(c.xS, c.xsol, sizeof(double) * c.L, hipMemcpyDeviceToDevice, c.stream));
+    // 4. unconstrained Stokes solve with (1/delta)[S(Q+) - S(Q-)] lambda^R (naive scheme: v# = 0)
+    if (drift) {
+        launch_zero(c, c.rhs, nullptr);
+        launch_spread(c, c.ms[1], c.xR, c.rhs, 1.0 / delta);
+        launch_spread(c, c.ms[2], c.xR, c.rhs, -1.0 / delta);
+        fgmres(c, c.ms[0], th_solve, c.rhs, true, inf);
+        for (int r = 0; r < c.nrep; ++r) { out[r].iters += inf[r].iters; if (inf[r].status) out[r].status = inf[r].status; }
+        HIP_OK(hipMemcpyAsync(c.xS, c.xsol, sizeof(double) * c.L, hipMemcpyDeviceToDevice, c.stream));
+    } else {
+        zero_device(c, c.xS, c.L);
+    }
     // 5. random finite differences of K, J (markers) and K^T (bodies)
     launch_rfd_terms(c, delta);
     launch_rfd_forces(c, delta, FT);
@@ -726,7 +735,7 @@ static void validate(int nrep, const rbfib_grid *grids, const rbfib_bodies *bodi
         !(o.mg_omega > 0.0) || !(o.blob_radius > 0.0) || !(o.rfd_delta > 0.0) || o.mg_bottom < 0 || o.mg_bottom > MGB_LDS / 1024 ||
         !(o.mg_cheby >= 0.0 && o.mg_cheby < 2.0) || o.mg_sweeps > RB_MAXSWEEP || o.mg_sweeps_p < 0 ||
         o.mg_sweeps_p > RB_MAXSWEEP || o.krylov_s < 1 || o.krylov_s > RB_MAXS || (o.mg_first2 != 0 && o.mg_first2 != 1) ||
-        (o.kernel != 4 && o.kernel != 6))
+        (o.kernel != 4 && o.kernel != 6) || (o.no_drift != 0 && o.no_drift != 1))
         throw (int)RBFIB_EINVAL;
     for (int r = 0; r < nrep; ++r) {
         const rbfib_grid &g = grids[r];
@@ -1243,6 +1252,7 @@ void rbfib_default_opts(rbfib_opts *o) {
     o->krylov_s = 2;
     o->mg_first2 = 1;
     o->kernel = 4;
+    o->no_drift = 0;
 }
 
 const char *rbfib_strerror(int code) {
@@ -1310,7 +1320,7 @@ int rbfib_set_opts(rbfib_ctx *ctx, const rbfib_opts *o) {
     if (!(o->tol > 0.0) || o->max_iter < 1 || o->mg_sweeps < 1 || !(o->mg_omega > 0.0) || !(o->rfd_delta > 0.0) ||
         !(o->mg_cheby >= 0.0 && o->mg_cheby < 2.0) || o->mg_sweeps > RB_MAXSWEEP || o->mg_sweeps_p < 0 ||
         o->mg_sweeps_p > RB_MAXSWEEP || o->krylov_s < 1 || o->krylov_s > RB_MAXS ||
-        (o->mg_first2 != 0 && o->mg_first2 != 1))
+        (o->mg_first2 != 0 && o->mg_first2 != 1) || (o->no_drift != 0 && o->no_drift != 1))
         return RBFIB_EINVAL;
     // fields fixed at creation: restart length, precision, blob radius, bottom kernel, delta kernel
     if (o->restart != c.opts.restart || (o->precond_fp32 != 0) != c.mg_fp32 || o->blob_radius != c.opts.blob_radius ||
@@ -1461,6 +1471,20 @@ int rbfib_sem_step(rbfib_ctx *ctx, double *q, double *theta, const double *FT, c
     HIP_OK(hipStreamSynchronize(c.stream));
     if (info) for (int r = 0; r < c.nrep; ++r) info[r] = inf[r];
     return code;
+    GUARD_END
+}
+
+int rbfib_body_forces(rbfib_ctx *ctx, const double *q, const double *theta, const rbfib_potential *pot, double *FT) {
+    if (!ctx || !pot || (ctx->c.nb > 0 && (!q || !theta || !FT))) return RBFIB_EINVAL;
+    if (!(pot->b > 0.0) || !std::isfinite(pot->b) || !std::isfinite(pot->phi0) || !std::isfinite(pot->d) ||
+        !std::isfinite(pot->fconst[0]) || !std::isfinite(pot->fconst[1]) || !std::isfinite(pot->fconst[2]))
+        return RBFIB_EINVAL;
+    GUARD_BEGIN
+    Ctx &c = ctx->c;
+    Session s(c);
+    launch_body_forces(c, q, theta, pot->phi0, pot->d, pot->b, pot->fconst, FT);
+    HIP_OK(hipGetLastError());
+    return RBFIB_OK;
     GUARD_END
 }
 

@@ -1,0 +1,177 @@
+"""Weak-accuracy study of App. A: the equilibrium of the Split-Euler-Maruyama
+scheme for one boomerang in the 64x64x16 slit against the Gibbs-Boltzmann
+distribution.
+
+R replicas of the boomerang (batched in one library context, 6-point kernel)
+start from exact Gibbs-Boltzmann draws of the oracle (height and orientation;
+x and y uniform) and take SEM steps of dimensionless size dtau = dt kT /
+(6 pi eta a^3), driven by the soft blob-wall repulsion and the buoyant weight
+(rbfib_body_forces).  After a burn-in, every step contributes each replica's
+cross-point height and the angle between p-hat and the z axis to histograms,
+which are compared with the oracle's quadrature of the Gibbs-Boltzmann
+marginals (tests/golden/boomerang_gb.json): the L2 norm of the density
+difference, and its statistical floor from batch means over groups of
+replicas.  ``--no-drift`` runs the naive scheme without the random finite
+differences, whose equilibrium is biased.
+
+Run from the repository root on a GPU, e.g.
+    python tests/boomerang_study.py --dtau 0.036 --replicas 256 --steps 400 --burn 100 \\
+        --out gpurun_out/boom_0036.json [--state-in s.npz] [--state-out s.npz]
+A run may continue another (--state-in): the replicas' configurations, the
+step counter and the histogram counts of every group are carried over.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+GOLDEN = os.path.join(ROOT, "tests", "golden", "boomerang_gb.json")
+
+
+def log(*a):
+    print(*a, flush=True)
+
+
+def initial_state(n, seed):
+    """Exact Gibbs-Boltzmann draws (oracle) of height and orientation, uniform x, y."""
+    import workloads as W
+    from oracle.gibbs import gb_samples
+    p = W.BOOMERANG_POTENTIAL
+    z, th = gb_samples(W.boomerang_shape(), float(W.BOOMERANG_N[2]), p["phi0"], p["d"], p["b"], p["weight"], n,
+                       seed=seed)
+    rng = np.random.default_rng(seed + 1)
+    xy = rng.uniform(0.0, 1.0, (n, 2)) * np.array(W.BOOMERANG_N[:2], dtype=np.float64)
+    return np.column_stack([xy, z]), th
+
+
+def observables(q, th, p_body):
+    """Cross-point height (the tracking point) and the angle of R(theta) p-hat with z (torch, on device)."""
+    import torch
+    w, x, y, z = th[:, 0], th[:, 1], th[:, 2], th[:, 3]
+    row = torch.stack([2.0 * (x * z - w * y), 2.0 * (y * z + w * x), 1.0 - 2.0 * (x * x + y * y)], dim=1)
+    pz = row @ torch.as_tensor(p_body / np.linalg.norm(p_body), dtype=torch.float64, device=q.device)
+    return q[:, 2].clone(), torch.arccos(torch.clamp(pz, -1.0, 1.0))
+
+
+def compare(counts_h, counts_a, ref):
+    """L2 density errors against the reference and their statistical floors.
+
+    counts_*: (groups, bins) sample counts per group of replicas; the groups are
+    independent, so the spread of their histograms gives each bin's standard error.
+    """
+    out = {}
+    for key, counts, edges, p_ref in (("height", counts_h, ref["z_edges"], ref["p_height"]),
+                                      ("angle", counts_a, ref["angle_edges"], ref["p_angle"])):
+        p_ref, width = np.asarray(p_ref), np.diff(np.asarray(edges))
+        h = counts.sum(axis=0) / counts.sum()
+        gh = counts / counts.sum(axis=1, keepdims=True)
+        se = gh.std(axis=0, ddof=1) / math.sqrt(counts.shape[0])
+        out[key] = {
+            "p": h.tolist(),
+            "l2": float(math.sqrt(np.sum((h - p_ref) ** 2 / width))),
+            "l2_floor": float(math.sqrt(np.sum(se ** 2 / width))),
+            "max_abs_bin_z": float(np.max(np.abs(h - p_ref) / np.maximum(se, 1e-12))),
+        }
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
+    ap.add_argument("--dtau", type=float, default=0.036)
+    ap.add_argument("--replicas", type=int, default=256)
+    ap.add_argument("--steps", type=int, default=200, help="SEM steps in this run")
+    ap.add_argument("--burn", type=int, default=50, help="steps before sampling starts (counted from step 0)")
+    ap.add_argument("--tol", type=float, default=1e-5)
+    ap.add_argument("--no-drift", action="store_true")
+    ap.add_argument("--seed", type=int, default=2024)
+    ap.add_argument("--groups", type=int, default=16)
+    ap.add_argument("--out", default=None)
+    ap.add_argument("--state-in", default=None)
+    ap.add_argument("--state-out", default=None)
+    args = ap.parse_args()
+
+    import torch
+    import paper_1901_06427_amd as rb
+    import workloads as W
+
+    R = args.replicas
+    ws = W.boomerang_slit(seed=args.seed, n_replicas=R, dtau=args.dtau, tol=args.tol)
+    dt = W.boomerang_dt(args.dtau)
+    with open(GOLDEN) as fh:
+        ref = json.load(fh)
+    ze, ae = np.asarray(ref["z_edges"]), np.asarray(ref["angle_edges"])
+    G = args.groups
+    group = np.arange(R) * G // R                        # contiguous groups of replicas
+    if args.state_in:
+        st = np.load(args.state_in)
+        q0, th0, k0 = st["q"], st["theta"], int(st["step"])
+        counts_h, counts_a = st["counts_h"], st["counts_a"]
+        assert q0.shape[0] == R and counts_h.shape[0] == G
+    else:
+        q0, th0 = initial_state(R, args.seed)
+        k0 = 0
+        counts_h = np.zeros((G, len(ze) - 1), dtype=np.int64)
+        counts_a = np.zeros((G, len(ae) - 1), dtype=np.int64)
+    grids = [rb.make_grid(w.n, w.bc, w.h, w.eta, w.wall_vel) for w in ws]
+    opts = rb.rbfib_default_opts(tol=args.tol, precond_fp32=1, kernel=6, blob_radius=1.4,
+                                 no_drift=1 if args.no_drift else 0)
+    ctx = rb.rbfib_create_batch(grids, [w.r_ref for w in ws], [w.offsets for w in ws], opts)
+    q = torch.as_tensor(q0, dtype=torch.float64).cuda().contiguous()
+    th = torch.as_tensor(th0, dtype=torch.float64).cuda().contiguous()
+    FT = torch.empty((R, 6), dtype=torch.float64, device="cuda")
+    U = torch.empty((R, 6), dtype=torch.float64, device="cuda")
+    pot = W.BOOMERANG_POTENTIAL
+    fconst = [0.0, 0.0, -pot["weight"]]
+    log("boomerang study: dtau %.4g (dt %.4g), %d replicas, steps %d..%d, burn %d, tol %g, %s" % (
+        args.dtau, dt, R, k0, k0 + args.steps, args.burn, args.tol, "no drift" if args.no_drift else "RFD drift"))
+    rejected = iters = 0
+    t0 = time.perf_counter()
+    for k in range(k0, k0 + args.steps):
+        rb.rbfib_body_forces(ctx, q, th, pot["phi0"], pot["d"], pot["b"], fconst, FT)
+        info = rb.rbfib_sem_step(ctx, q, th, FT, 1.0, dt, args.seed, k, U,
+                                 allow=(rb.RBFIB_EREJECT, rb.RBFIB_ENOCONV))
+        bad = [i.status for i in info if i.status not in (rb.RBFIB_OK, rb.RBFIB_EREJECT)]
+        if bad:
+            raise RuntimeError("solver failure at step %d: %s" % (k, bad[:4]))
+        rejected += sum(1 for i in info if i.status == rb.RBFIB_EREJECT)
+        iters += sum(i.iters for i in info)
+        if k >= args.burn:
+            z, a = observables(q, th, W.BOOMERANG_P)
+            zb = np.clip(np.searchsorted(ze, z.cpu().numpy(), side="right") - 1, 0, len(ze) - 2)
+            ab = np.clip(np.searchsorted(ae, a.cpu().numpy(), side="right") - 1, 0, len(ae) - 2)
+            np.add.at(counts_h, (group, zb), 1)
+            np.add.at(counts_a, (group, ab), 1)
+        if (k + 1 - k0) % 25 == 0:
+            el = time.perf_counter() - t0
+            log("  step %d: %.3f s/step, %d rejected so far, %.1f iterations per replica-step" % (
+                k + 1, el / (k + 1 - k0), rejected, iters / (R * (k + 1 - k0))))
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    ctx.close()
+    result = {"dtau": args.dtau, "dt": dt, "replicas": R, "steps_total": k0 + args.steps, "burn": args.burn,
+              "tol": args.tol, "no_drift": bool(args.no_drift), "seconds_per_step": el / max(args.steps, 1),
+              "rejected_this_run": rejected, "iterations_per_replica_step": iters / max(R * args.steps, 1),
+              "samples": int(counts_h.sum())}
+    if counts_h.sum() > 0:
+        result.update(compare(counts_h, counts_a, ref))
+        log("  height L2 err %.4f (floor %.4f), angle L2 err %.4f (floor %.4f)" % (
+            result["height"]["l2"], result["height"]["l2_floor"], result["angle"]["l2"],
+            result["angle"]["l2_floor"]))
+    if args.state_out:
+        np.savez(args.state_out, q=q.cpu().numpy(), theta=th.cpu().numpy(), step=k0 + args.steps,
+                 counts_h=counts_h, counts_a=counts_a)
+    if args.out:
+        with open(args.out, "w") as fh:
+            json.dump(result, fh, indent=1)
+    log(json.dumps({k: v for k, v in result.items() if k not in ("height", "angle")}))
+
+
+if __name__ == "__main__":
+    main()

@@ -89,6 +89,30 @@ def sem_configs():
     }
 
 
+def boomerang_configs():
+    """The App. A boomerang in its 64x64x16 slit (6-point kernel): tilted 40 degrees
+    about x with the x arm 1.8 h above the bottom wall (its blobs inside the
+    exponential range of the wall repulsion), and a replica whose cross point sits
+    1.0 h below the top wall (inside the linear range)."""
+    import math
+    low = W.boomerang_slit(seed=41, n_replicas=1)[0]
+    low.q = np.array([[20.3, 37.9, 1.8]])
+    a = math.radians(40.0)
+    low.theta = np.array([[math.cos(a / 2), math.sin(a / 2), 0.0, 0.0]])
+    high = W.boomerang_slit(seed=42, n_replicas=1)[0]
+    high.q = np.array([[50.2, 3.7, 15.0]])
+    a = math.radians(-25.0)
+    b = math.radians(60.0)
+    # rotation about -x by 25 degrees, then about z by 60 degrees: arms go downwards
+    qx = np.array([math.cos(a / 2), math.sin(a / 2), 0.0, 0.0])
+    qz = np.array([math.cos(b / 2), 0.0, 0.0, math.sin(b / 2)])
+    w_, x_, y_, z_ = qz
+    high.theta = np.array([[w_ * qx[0] - x_ * qx[1], w_ * qx[1] + x_ * qx[0], y_ * qx[0] + z_ * qx[1],
+                            z_ * qx[0] - y_ * qx[1]]])
+    high.theta /= np.linalg.norm(high.theta)
+    return {"boomerang_64x64x16_k6": low, "boomerang_top_64x64x16_k6": high}
+
+
 def marker_slip(w, seed=17, scale=0.05):
     """A nonzero prescribed slip on every marker (Sec. II eq. rigidBC): a seeded random
     field plus a swirl about a fixed axis through each body's tracking point (the
@@ -109,4 +133,5 @@ def gain_configs():
         if k != "monolayer_64x32x16_k6":          # apply only
             out[k] = w
     out.update(slip_configs())
+    out["boomerang_64x64x16_k6"] = boomerang_configs()["boomerang_64x64x16_k6"]
     return out

@@ -22,6 +22,9 @@ Workloads (all with h = 1 and viscosity 1):
   * ``ensemble``           -- many independent walled boxes of edge
                               16/24/32/48 with 1-4 spheres each.
   * ``many_spheres``       -- 128^3 walled box with 64 spheres.
+  * ``boomerang_slit``     -- replicas of one 15-blob L-shaped boomerang in a
+                              64x64x16 slit (periodic in x and y, no-slip
+                              walls in z), 6-point kernel (App. A).
 """
 from __future__ import annotations
 
@@ -231,3 +234,64 @@ def small_box(seed: int, n=(12, 12, 12), n_bodies: int = 1, R: float = 1.5, shap
     if wall_vel is not None:
         w.wall_vel = np.asarray(wall_vel, dtype=np.float64)
     return w
+
+
+# ---------------------------------------------------------------- App. A boomerang
+# Units: the mesh width h, the viscosity eta and kT are 1.  The blob radius of
+# the 6-point kernel is a = 1.47 h and the blobs are s = 0.925 a apart; with
+# s = 0.3 um this makes h = 0.3 um / (0.925 * 1.47) = 0.2206 um.
+BOOMERANG_A = 1.47
+BOOMERANG_S = 0.925 * BOOMERANG_A
+BOOMERANG_N = (64, 64, 16)
+_KB, _T, _G = 1.380649e-23, 300.0, 9.80665            # J/K, K, m/s^2
+_H_M = 0.3e-6 / BOOMERANG_S                          # mesh width in metres
+_M_E = 1.57e-11 * 1e-6                               # buoyant mass per blob: 1.57e-11 mg, in kg
+BOOMERANG_POTENTIAL = dict(
+    phi0=4.0,                                        # 4 kT
+    d=BOOMERANG_A,                                   # d = a
+    b=0.1 * BOOMERANG_A,                             # b = 0.1 a
+    weight=_M_E * _G * _H_M / (_KB * _T),            # m_e g in kT / h (about 8.2e-3)
+)
+
+
+def boomerang_shape(s: float = BOOMERANG_S) -> np.ndarray:
+    """15 blobs: the cross point at the origin, then 7 along +x and 7 along +y, s apart."""
+    pts = [[0.0, 0.0, 0.0]]
+    pts += [[k * s, 0.0, 0.0] for k in range(1, 8)]
+    pts += [[0.0, k * s, 0.0] for k in range(1, 8)]
+    return np.array(pts, dtype=np.float64)
+
+
+# unit vector in the plane of the boomerang bisecting the right angle at the
+# cross point, pointing from the arms towards the cross point (body frame)
+BOOMERANG_P = np.array([-1.0, -1.0, 0.0]) / math.sqrt(2.0)
+
+
+def boomerang_dt(dtau: float, a: float = BOOMERANG_A) -> float:
+    """Time step of the dimensionless step dtau = dt kT / (6 pi eta a^3)."""
+    return dtau * 6.0 * math.pi * a ** 3
+
+
+def boomerang_slit(seed: int = 1906, n_replicas: int = 1, dtau: float = 0.036, tol: float = 1e-6,
+                   z0: Optional[float] = None) -> List[Workload]:
+    """Replicas of one boomerang in the App. A slit, tracking point at the cross point.
+
+    Each replica starts flat (the L in a horizontal plane) at height z0
+    (default: mid-slit), at a seeded uniform (x, y) and a seeded rotation
+    about z.  Forces are configuration dependent (evaluated each step by the
+    caller), so FT is zero here.
+    """
+    rng = np.random.default_rng(seed)
+    nx, ny, nz = BOOMERANG_N
+    r_ref, offs = _bodies([boomerang_shape()])
+    wv = zero_wall_vel()
+    out = []
+    for r in range(n_replicas):
+        xy = rng.uniform(0.0, 1.0, 2) * np.array([nx, ny], dtype=np.float64)
+        alpha = rng.uniform(0.0, 2.0 * math.pi)
+        q = np.array([[xy[0], xy[1], nz / 2.0 if z0 is None else z0]])
+        theta = np.array([[math.cos(0.5 * alpha), 0.0, 0.0, math.sin(0.5 * alpha)]])
+        out.append(Workload("boomerang%d" % r, BOOMERANG_N, (PERIODIC, PERIODIC, WALL), 1.0, 1.0, wv.copy(),
+                            r_ref.copy(), offs.copy(), q, theta, np.zeros((1, 6)), np.array([BOOMERANG_S * 7]),
+                            kT=1.0, dt=boomerang_dt(dtau), tol=tol, seed=seed, kernel=6))
+    return out
