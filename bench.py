@@ -9,11 +9,16 @@ one unconstrained Stokes solve per replica, each to a relative residual of
 1e-6) in one batched launch sequence with the FP32 multigrid preconditioner
 and captured HIP graphs.  "plain_fp64" solves the same replicas one at a time
 with the FP64 preconditioner on the same GPU; "two_spheres" is the 32x32x64
-two-sphere box of the paper's tight-cavity example, one replica.
+two-sphere box of the paper's tight-cavity example, one replica;
+"monolayer_1024" times SEM steps of the 1024-sphere sliding-wall monolayer with
+the FP32 and the FP64 multigrid; "adjoint_128" times the forward solve and the
+vector-Jacobian product on the 128^3 box with 64 spheres.
 
 Inputs are seeded and synthetic, and resident in GPU memory before the timed
-region.  The roofline object is for the dominant kernel class, timed with HIP
-events inside the library on its own stream in a short eager run; the CPU
+region.  The roofline object is for the kernel class that dominates the
+headline's graph-mode launches (the basis update of a two-step Arnoldi block),
+timed with HIP events inside the library on its own stream in a short eager
+run; the CPU
 baseline is the FP64 oracle's SEM step on a bounded sample of replicas.
 """
 import argparse
@@ -210,6 +215,79 @@ def run_plain(ws, warmup=1, seed=2024, tol=None):
     return {"seconds": total, "steps": len(ws), "iters": iters}
 
 
+def _dev(a):
+    import torch
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64).cuda()
+
+
+def run_monolayer(steps, seed=2024):
+    """The 1024-sphere monolayer (256x128x32, periodic x, walls y and z, sliding bottom
+    wall): SEM steps with the FP32 multigrid inside FP64 FGMRES and with the all-FP64
+    preconditioner, from the same configuration with the same random numbers.  Step 0
+    of each is untimed and its velocities are compared between the two; steps 1..steps
+    are timed."""
+    import torch
+    import paper_1901_06427_amd as rb
+    import workloads as W
+    w = W.monolayer()
+    out, U0 = {}, {}
+    for fp32 in (1, 0):
+        ctx = lib_context(rb, [w], tol=w.tol, precond_fp32=fp32)
+        q, th, FT = _dev(w.q), _dev(w.theta), _dev(w.FT)
+        U = torch.empty((w.nb, 6), dtype=torch.float64, device="cuda")
+        rb.rbfib_sem_step(ctx, q, th, FT, w.kT, w.dt, seed, 0, U)
+        U0[fp32] = U.cpu().numpy()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        iters = 0
+        for k in range(1, steps + 1):
+            info = rb.rbfib_sem_step(ctx, q, th, FT, w.kT, w.dt, seed, k, U)
+            iters += info[0].iters
+        torch.cuda.synchronize()
+        sec = (time.perf_counter() - t0) / steps
+        ctx.close()
+        out["fp32_pc" if fp32 else "fp64_pc"] = {"ms_per_step": round(1e3 * sec, 2), "solves_per_s": round(2 / sec, 3),
+                                                 "fgmres_iters_per_step": round(iters / steps, 1)}
+    d = float(np.abs(U0[1] - U0[0]).max() / np.abs(U0[0]).max())
+    out.update({"grid": list(w.n), "bodies": w.nb, "markers": w.nm, "tol": w.tol, "timed_steps": steps,
+                "U_rel_diff_fp32_vs_fp64_pc": d,
+                "speedup_fp32_pc": round(out["fp64_pc"]["ms_per_step"] / out["fp32_pc"]["ms_per_step"], 3)})
+    return out
+
+
+def run_adjoint(tol=1e-10, reps=2):
+    """The differentiated solve: 64 spheres of 42 markers in a 128^3 walled box; the
+    forward mobility solve and the vector-Jacobian product (forward re-solve plus the
+    adjoint solve, then the gradient kernels), FP32 multigrid, best of reps."""
+    import torch
+    import paper_1901_06427_amd as rb
+    import workloads as W
+    w = W.many_spheres()
+    ctx = lib_context(rb, [w], tol=tol, precond_fp32=1)
+    q, th, FT = _dev(w.q), _dev(w.theta), _dev(w.FT)
+    U = torch.empty((w.nb, 6), dtype=torch.float64, device="cuda")
+    Ubar = _dev(np.random.default_rng(5).standard_normal((w.nb, 6)))
+    dFT, dq, dphi = (torch.empty((w.nb, k), dtype=torch.float64, device="cuda") for k in (6, 3, 3))
+    best_f = best_b = float("inf")
+    it_f = it_b = 0
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        inf = rb.rbfib_solve_mobility(ctx, q, th, FT, U, include_bc=False, allow=())
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        infb = rb.rbfib_mobility_vjp(ctx, q, th, FT, Ubar, dFT, dq, dphi, allow=())
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        best_f, best_b = min(best_f, t1 - t0), min(best_b, t2 - t1)
+        it_f, it_b = inf[0].iters, infb[0].iters
+    ctx.close()
+    return {"grid": list(w.n), "bodies": w.nb, "markers": w.nm, "tol": tol,
+            "forward_ms": round(1e3 * best_f, 2), "forward_iters": it_f,
+            "vjp_ms": round(1e3 * best_b, 2), "vjp_iters": it_b,
+            "forward_plus_backward_ms": round(1e3 * (best_f + best_b), 2)}
+
+
 # ----------------------------------------------------------------- CPU oracle baseline
 _CPU_ENS = None
 
@@ -292,7 +370,7 @@ def copy_ceiling():
 
 COUNTERS = os.path.join(ROOT, "profiles", "ensemble_256_sem_hbm_counters.md")
 KERNEL_SOURCES = ("paper_1901_06427_amd/csrc/grid.hip", "paper_1901_06427_amd/csrc/krylov.hip",
-                  "paper_1901_06427_amd/csrc/common.h")
+                  "paper_1901_06427_amd/csrc/common.h", "paper_1901_06427_amd/csrc/ib.hip")
 
 
 def _code_tokens(text):
@@ -353,9 +431,15 @@ def measured_traffic(kernel):
     return None
 
 
+# The kernel class with the largest share of kernel time in the headline's graph-mode
+# launches (rocprofv3 kernel trace of `bench.py --batched-only`): the basis update of a
+# two-step Arnoldi block.  Its launches are timed with HIP events in an eager launch.
+ROOFLINE_CLASS = "krylov_update"
+
+
 def roofline_of(stats, ensemble_default=True):
-    best = max(stats.items(), key=lambda kv: kv[1][0] * kv[1][2])
-    name, (avg_ms, nbytes, launches) = best
+    name = ROOFLINE_CLASS if ROOFLINE_CLASS in stats else max(stats.items(), key=lambda kv: kv[1][0] * kv[1][2])[0]
+    avg_ms, nbytes, launches = stats[name]
     achieved = nbytes / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else 0.0
     traffic = measured_traffic(name) if ensemble_default else None
     roof = {"bound": "hbm", "kernel": name, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -379,6 +463,9 @@ def main():
                     help="second batched-vs-plain comparison at this tolerance (0: skip)")
     ap.add_argument("--tight-steps", type=int, default=3, help="timed batched launches at the tight tolerance")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
+    ap.add_argument("--monolayer-steps", type=int, default=3,
+                    help="timed SEM steps of the 1024-sphere monolayer per preconditioner precision (0: skip)")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the 128^3 differentiated solve")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run one elementwise kernel reading and writing 256 MiB first (counter calibration)")
     ap.add_argument("--timing-only", action="store_true",
@@ -493,6 +580,17 @@ def main():
     two_value = 2 * two["steps"] / two["seconds"]
     log("two spheres: %.1f solves/s" % two_value)
 
+    mono = run_monolayer(args.monolayer_steps) if args.monolayer_steps > 0 else None
+    if mono:
+        log("monolayer: fp32-pc %.1f ms/step, fp64-pc %.1f ms/step, U rel diff %.2e" % (
+            mono["fp32_pc"]["ms_per_step"], mono["fp64_pc"]["ms_per_step"], mono["U_rel_diff_fp32_vs_fp64_pc"]))
+    adj = run_adjoint() if not args.no_adjoint else None
+    if adj:
+        log("128^3 adjoint: forward %.1f ms, vjp %.1f ms" % (adj["forward_ms"], adj["vjp_ms"]))
+    import paper_1901_06427_amd as rb
+    gctx = lib_context(rb, ens, tol=1e-6, precond_fp32=1)
+    geometry = rb.rbfib_launch_geometry(gctx)
+    gctx.close()
 
     n_cells = sum(int(np.prod(w.n)) for w in ens)
     line = {
@@ -513,7 +611,7 @@ def main():
                    "markers": sum(w.nm for w in ens), "kT": 1.0, "dt": 0.01, "tol": 1e-6,
                    "precond": "fp32 multigrid", "solves_per_step_per_replica": 2,
                    "fgmres_iters_per_launch": round(batched["iters"] / batched["steps"], 1),
-                   "rejected": batched["rejected"]},
+                   "rejected": batched["rejected"], "launch_geometry": geometry},
         "oracle_err": err,
         "plain_fp64": {"value": round(plain_value, 3), "unit": "mobility solves/s",
                        "sample": "first %d replicas, one SEM step each, solved one at a time" % plain["steps"],
@@ -522,6 +620,8 @@ def main():
         "two_spheres": {"value": round(two_value, 3), "unit": "mobility solves/s", "grid": [32, 32, 64],
                         "ms_per_step": round(1e3 * two["seconds"] / two["steps"], 3),
                         "fgmres_iters_per_step": round(two["iters"] / two["steps"], 1)},
+        "monolayer_1024": mono,
+        "adjoint_128": adj,
         "roofline": roofline,
         "kernels": kernels,
         "cpu_baseline": cpu,

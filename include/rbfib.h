@@ -320,15 +320,18 @@ int rbfib_kernel_stats(rbfib_ctx *ctx, int which, double *avg_ms, double *bytes_
                        long long *launches);
 int rbfib_enable_timing(rbfib_ctx *ctx, int on);
 
-/* Launch geometry of a context (host out[4]): Krylov vector elements per workgroup
+/* Launch geometry of a context (host out[5]): Krylov vector elements per workgroup
  * (512, 1024 or 2048), workgroups of the spreading pass, (tile, marker) pairs staged
- * per LDS round of spreading (16, 32 or 64), and grid points per thread of the
- * multigrid and cell kernels (1 or 4).  Chosen at creation from the table the
- * autotuner writes (the file named by the environment variable RBFIB_TUNING, else
- * tuning.txt beside the library; built-in defaults without one): the first line
- *     cells_lo cells_hi reps_lo reps_hi krylov_chunk spread_grid spread_p mg_npt
+ * per LDS round of spreading (16, 32 or 64), grid points per thread of the
+ * multigrid and cell kernels (1 or 4), and z planes per workgroup of the z-marching
+ * fluid apply (0: the two-cells-per-thread apply).  Chosen at creation from the
+ * table the autotuner writes (the file named by the environment variable
+ * RBFIB_TUNING, else tuning.txt beside the library; built-in defaults without one):
+ * the first line
+ *     cells_lo cells_hi reps_lo reps_hi krylov_chunk spread_grid spread_p mg_npt [apply_kc]
  * whose inclusive ranges hold the context's total cell count and replica count
- * (mg_npt 0: four points per thread on batches of at least 2^22 cells, else one).
+ * (mg_npt 0: four points per thread on batches of at least 2^22 cells, else one;
+ * apply_kc absent or 0: the two-cell apply).
  * The geometry changes only how work is split; results differ at most by the order
  * of floating-point sums. */
 int rbfib_launch_geometry(const rbfib_ctx *ctx, int *out);

@@ -357,9 +357,10 @@ def rbfib_kernel_stats(ctx: Context, which: int):
 
 
 def rbfib_launch_geometry(ctx: Context) -> dict:
-    out = (ctypes.c_int * 4)()
+    out = (ctypes.c_int * 5)()
     _check(_lib.rbfib_launch_geometry(ctx.h, out), "rbfib_launch_geometry")
-    return {"krylov_chunk": out[0], "spread_grid": out[1], "spread_p": out[2], "mg_npt": out[3]}
+    return {"krylov_chunk": out[0], "spread_grid": out[1], "spread_p": out[2], "mg_npt": out[3],
+            "apply_kc": out[4]}
 
 
 def library_path() -> str:

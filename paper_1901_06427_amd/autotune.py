@@ -9,12 +9,14 @@ preconditioner) under candidate launch geometries and keeps the fastest:
   spread_p      (tile, marker) pairs staged per LDS round of spreading (16, 32, 64)
   spread_grid   workgroups of the spreading grid-stride loop
   mg_npt        grid points per thread of the multigrid and cell kernels (1, 4)
+  apply_kc      z planes per workgroup of the z-marching fluid apply (0: the
+                two-cells-per-thread apply; 4, 8, 16)
 
 by coordinate descent in that order (each candidate timed twice, the faster
 kept), and writes the table that context creation reads (tuning.txt beside the
 library, or the file named by RBFIB_TUNING): one line per class,
 
-    cells_lo cells_hi reps_lo reps_hi krylov_chunk spread_grid spread_p mg_npt
+    cells_lo cells_hi reps_lo reps_hi krylov_chunk spread_grid spread_p mg_npt apply_kc
 
 followed by a comment with the measured seconds per launch of the defaults and
 of the choice.  Run from the repository root on the GPU it is for:
@@ -43,8 +45,8 @@ CLASSES = {
 }
 
 SPACE = [("krylov_chunk", (512, 1024, 2048)), ("spread_p", (16, 32, 64)),
-         ("spread_grid", (1024, 4096, 16384, 65536)), ("mg_npt", (1, 4))]
-DEFAULT = {"krylov_chunk": 1024, "spread_grid": 65536, "spread_p": 32, "mg_npt": 0}
+         ("spread_grid", (1024, 4096, 16384, 65536)), ("mg_npt", (1, 4)), ("apply_kc", (0, 4, 8, 16))]
+DEFAULT = {"krylov_chunk": 1024, "spread_grid": 65536, "spread_p": 32, "mg_npt": 0, "apply_kc": 0}
 
 
 def log(*a):
@@ -61,8 +63,8 @@ def _workloads(kind):
 
 
 def _line(cfg, cells=(0, BIG), reps=(1, 1000000)):
-    return "%d %d %d %d %d %d %d %d" % (cells[0], cells[1], reps[0], reps[1], cfg["krylov_chunk"],
-                                        cfg["spread_grid"], cfg["spread_p"], cfg["mg_npt"])
+    return "%d %d %d %d %d %d %d %d %d" % (cells[0], cells[1], reps[0], reps[1], cfg["krylov_chunk"],
+                                           cfg["spread_grid"], cfg["spread_p"], cfg["mg_npt"], cfg["apply_kc"])
 
 
 def time_geometry(ws, cfg, launches, table_dir):
@@ -78,7 +80,7 @@ def time_geometry(ws, cfg, launches, table_dir):
     ctx = rb.rbfib_create_batch(grids, [w.r_ref for w in ws], [w.offsets for w in ws],
                                 rb.rbfib_default_opts(tol=1e-6, precond_fp32=1))
     got = rb.rbfib_launch_geometry(ctx)
-    assert all(got[k] == cfg[k] for k in ("krylov_chunk", "spread_grid", "spread_p")), (got, cfg)
+    assert all(got[k] == cfg[k] for k in ("krylov_chunk", "spread_grid", "spread_p", "apply_kc")), (got, cfg)
     cat = lambda key: torch.as_tensor(np.concatenate([getattr(w, key) for w in ws]), dtype=torch.float64).cuda()
     q0, th0, FT = cat("q"), cat("theta"), cat("FT")
     U = torch.empty((sum(w.nb for w in ws), 6), dtype=torch.float64, device="cuda")
@@ -122,7 +124,7 @@ def main():
     ap.add_argument("--classes", default=",".join(CLASSES))
     args = ap.parse_args()
     lines = ["# launch geometry of librbfib, written by paper_1901_06427_amd/autotune.py on the GPU it ran on",
-             "# cells_lo cells_hi reps_lo reps_hi krylov_chunk spread_grid spread_p mg_npt"]
+             "# cells_lo cells_hi reps_lo reps_hi krylov_chunk spread_grid spread_p mg_npt apply_kc"]
     with tempfile.TemporaryDirectory() as tmp:
         for name in args.classes.split(","):
             spec = CLASSES[name]

@@ -29,6 +29,8 @@
 // A level runs fused only with at least this many workgroups (each marches
 // through its z planes, so it needs several resident workgroups per CU).
 #define MGF_MIN_BLOCKS 1024
+// z-marching fluid apply: x-y tile edge (workgroup RB_AZT^2 threads)
+#define RB_AZT 16
 #define RB_NTIMING 7           // timing classes: apply, smoother sweep, fused down, fused up (level 0),
                                // Krylov dots, Krylov update, spreading of the apply
 // LDS-resident bottom of the V-cycle: workgroup size and the largest LDS budget
@@ -270,6 +272,7 @@ struct Tuning {
     int spread_grid = 65536;
     int spread_p = 32;
     int mg_npt = 0;
+    int apply_kc = -1;      // planes per workgroup of the z-marching apply; 0: two-cell kernel; -1: rule
 };
 
 struct ShapeDev {       // per distinct body shape: body-block preconditioner data
@@ -590,6 +593,8 @@ struct Ctx {
     // block tables
     BlockEnt *d_tab_cells = nullptr; int n_tab_cells = 0;         // level 0, all replicas, per cell chunk
     BlockEnt *d_tab_cells2 = nullptr; int n_tab_cells2 = 0;       // two cells per thread (apply)
+    BlockEnt *d_tab_az = nullptr; int n_tab_az = 0;               // z-marching apply tiles (0: unused)
+    int apply_kc = 0;                                             // their planes (0: two-cell apply)
     BlockEnt *d_tab_vec = nullptr; int n_tab_vec = 0;             // state chunks
     std::vector<int> vec_first, vec_nblk;                         // per replica block range
     int *d_vec_first = nullptr, *d_vec_nblk = nullptr;

@@ -228,8 +228,135 @@ __global__ __launch_bounds__(RB_BLOCK) void k_apply_fluid(const RepDev *reps, co
     }
 }
 
+// The same apply by z-marching: a workgroup owns an RB_AZT x RB_AZT tile of x-y
+// cells and be.npt consecutive planes along z (be.start: linear index of the tile's
+// first cell).  Each thread keeps its cell's four fields at planes k-1, k and k+1 in
+// registers (plane k+2 is loaded one step ahead) and publishes plane k in LDS, where
+// the tile's x and y neighbours are read; neighbours outside the tile (tile edges,
+// periodic wraps) come from global memory.  A neighbour across a wall is never read
+// (its rule ignores the value).  The gathered values are those of k_apply_fluid, so
+// the results are identical.
+// Neighbour of cell (i, j) along a = 0 (x) or 1 (y) in direction d, wrapped on a
+// periodic axis: its slot in the tile (>= 0), or -1 with g its x-y offset in the
+// plane when it lies outside the tile, or -2 beyond a wall.
+__device__ __forceinline__ int az_nbr(int i, int j, int a, int d, int nx, int ny, int bca, int x0, int y0,
+                                      long long &g) {
+    int q0 = i, q1 = j;
+    const int n = a == 0 ? nx : ny;
+    int q = (a == 0 ? q0 : q1) + d;
+    if (q < 0 || q >= n) {
+        if (bca != RBFIB_PERIODIC) return -2;
+        q += q < 0 ? n : -n;
+    }
+    if (a == 0) q0 = q; else q1 = q;
+    const int lx = q0 - x0, ly = q1 - y0;
+    if (lx >= 0 && lx < RB_AZT && ly >= 0 && ly < RB_AZT) return lx + RB_AZT * ly;
+    g = q0 + (long long)nx * q1;
+    return -1;
+}
+
+template <typename TX>
+__device__ __forceinline__ void az_plane(const TX *__restrict__ xr, long long N, long long sxy, long long col, int k,
+                                         int nz, bool zper, bool live, double v[4]) {
+    const int kk = (k >= 0 && k < nz) ? k : (zper ? (k < 0 ? k + nz : k - nz) : -1);
+#pragma unroll
+    for (int f = 0; f < 4; ++f) v[f] = (live && kk >= 0) ? (double)xr[(long long)f * N + kk * sxy + col] : 0.0;
+}
+
+template <typename TX>
+__global__ __launch_bounds__(RB_AZT *RB_AZT) void k_apply_fluid_z(const RepDev *reps, const BlockEnt *tab,
+                                                                  const TX *__restrict__ x, double *__restrict__ y,
+                                                                  const int *__restrict__ mask) {
+    const BlockEnt be = tab[xcd_block(blockIdx.x, gridDim.x)];
+    if (mask && !mask[be.rep]) return;
+    const RepDev &R = reps[be.rep];
+    __shared__ double sh[2][4][RB_AZT * RB_AZT];
+    const int nx = R.n[0], ny = R.n[1], nz = R.n[2];
+    const long long N = R.N, sxy = (long long)nx * ny;
+    int o[3];
+    unlin(be.start, R, o);
+    const int tx = threadIdx.x % RB_AZT, ty = threadIdx.x / RB_AZT;
+    const int i = o[0] + tx, j = o[1] + ty;
+    const bool live = i < nx && j < ny;
+    const int z1 = min(o[2] + be.npt, nz);
+    const TX *xr = x + R.off;
+    double *yr = y + R.off;
+    const long long col = live ? (long long)i + (long long)nx * j : 0;
+    const bool zper = R.bc[2] == RBFIB_PERIODIC;
+    // x and y neighbours of the thread's cell: slots or global offsets (fixed along z)
+    long long gx[4] = {0, 0, 0, 0};
+    int sl[4];
+    sl[0] = az_nbr(i, j, 0, -1, nx, ny, R.bc[0], o[0], o[1], gx[0]);
+    sl[1] = az_nbr(i, j, 0, +1, nx, ny, R.bc[0], o[0], o[1], gx[1]);
+    sl[2] = az_nbr(i, j, 1, -1, nx, ny, R.bc[1], o[0], o[1], gx[2]);
+    sl[3] = az_nbr(i, j, 1, +1, nx, ny, R.bc[1], o[0], o[1], gx[3]);
+    double vm[4], v0[4], vp[4];
+    az_plane(xr, N, sxy, col, o[2] - 1, nz, zper, live, vm);
+    az_plane(xr, N, sxy, col, o[2], nz, zper, live, v0);
+    az_plane(xr, N, sxy, col, o[2] + 1, nz, zper, live, vp);
+    int b = 0;
+    for (int k = o[2]; k < z1; ++k) {
+        double vn[4];
+        az_plane(xr, N, sxy, col, k + 2, nz, zper, live, vn);
+#pragma unroll
+        for (int f = 0; f < 4; ++f) sh[b][f][threadIdx.x] = v0[f];
+        __syncthreads();
+        if (live) {
+            const int idx[3] = {i, j, k};
+            double self[3], nb[3][6], pm[3];
+            int kd[3][6];
+            bool pin[3];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    kd[c][2 * a] = nbr_kind(idx[a], -1, R.n[a], R.bc[a], a, c);
+                    kd[c][2 * a + 1] = nbr_kind(idx[a], +1, R.n[a], R.bc[a], a, c);
+                }
+                self[c] = v0[c];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    double v = 0.0;
+                    if (kd[c][q] == 0)
+                        v = sl[q] >= 0 ? sh[b][c][sl[q]]
+                                       : (sl[q] == -1 ? (double)xr[(long long)c * N + k * sxy + gx[q]] : 0.0);
+                    nb[c][q] = v;
+                }
+                nb[c][4] = vm[c];
+                nb[c][5] = vp[c];
+                pin[c] = pinned(c, idx, R.bc);
+            }
+            // pressure at -e_c (unused where the face is pinned)
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                const int q = 2 * c;
+                double v = 0.0;
+                if (!pin[c]) v = sl[q] >= 0 ? sh[b][3][sl[q]] : (sl[q] == -1 ? (double)xr[3 * N + k * sxy + gx[q]] : 0.0);
+                pm[c] = v;
+            }
+            pm[2] = vm[3];
+            double out[4];
+            apply_cell(R, self, nb, pm, v0[3], kd, pin, out);
+#pragma unroll
+            for (int c = 0; c < 4; ++c) yr[(long long)c * N + k * sxy + col] = out[c];
+        }
+        b ^= 1;
+#pragma unroll
+        for (int f = 0; f < 4; ++f) {
+            vm[f] = v0[f];
+            v0[f] = vp[f];
+            vp[f] = vn[f];
+        }
+    }
+}
+
 template <typename TX>
 void launch_apply_fluid(Ctx &c, const TX *x, double *y) {
+    if (c.n_tab_az > 0) {
+        hipLaunchKernelGGL(k_apply_fluid_z<TX>, dim3(c.n_tab_az), dim3(RB_AZT * RB_AZT), 0, c.stream, c.d_reps,
+                           c.d_tab_az, x, y, c.mask);
+        return;
+    }
     hipLaunchKernelGGL(k_apply_fluid<TX>, dim3(c.n_tab_cells2), dim3(RB_BLOCK), 0, c.stream, c.d_reps,
                        c.d_tab_cells2, x, y, c.mask);
 }

@@ -790,13 +790,15 @@ static Tuning load_tuning(long long cells, int nrep, std::string *source) {
         char *hash = strchr(line, '#');
         if (hash) *hash = 0;
         long long clo, chi;
-        int rlo, rhi, ch, sg, sp, np;
-        if (sscanf(line, "%lld %lld %d %d %d %d %d %d", &clo, &chi, &rlo, &rhi, &ch, &sg, &sp, &np) != 8) continue;
+        int rlo, rhi, ch, sg, sp, np, kc = -1;
+        const int got = sscanf(line, "%lld %lld %d %d %d %d %d %d %d", &clo, &chi, &rlo, &rhi, &ch, &sg, &sp, &np, &kc);
+        if (got != 8 && got != 9) continue;
         if (cells < clo || cells > chi || nrep < rlo || nrep > rhi) continue;
         if (ch == 512 || ch == 1024 || ch == 2048) t.krylov_chunk = ch;
         if (sg >= 64 && sg <= (1 << 20)) t.spread_grid = sg;
         if (sp == 16 || sp == 32 || sp == 64) t.spread_p = sp;
         if (np == 0 || np == 1 || np == 4) t.mg_npt = np;
+        if (kc >= 0 && kc <= 64) t.apply_kc = kc;
         if (source) *source = path;
         break;
     }
@@ -926,6 +928,22 @@ static void build(Ctx &c, int nrep, const rbfib_grid *grids, const rbfib_bodies 
     c.d_tab_cells = upload(c, tcells);
     c.n_tab_cells2 = (int)tcells2.size();
     c.d_tab_cells2 = upload(c, tcells2);
+    // z-marching apply: RB_AZT^2 tiles of each x-y plane, apply_kc planes each (x
+    // tiles fastest, then y, then z chunks); only when the table asks for it (on the
+    // ensemble it is slower than the two-cell apply at every chunk length measured)
+    c.apply_kc = c.tune.apply_kc > 0 ? c.tune.apply_kc : 0;
+    if (c.apply_kc > 0) {
+        std::vector<BlockEnt> taz;
+        for (int r = 0; r < nrep; ++r) {
+            const RepDev &R = c.reps[r];
+            for (int z0 = 0; z0 < R.n[2]; z0 += c.apply_kc)
+                for (int y0 = 0; y0 < R.n[1]; y0 += RB_AZT)
+                    for (int x0 = 0; x0 < R.n[0]; x0 += RB_AZT)
+                        taz.push_back(BlockEnt{r, c.apply_kc, x0 + (long long)R.n[0] * (y0 + (long long)R.n[1] * z0)});
+        }
+        c.n_tab_az = (int)taz.size();
+        c.d_tab_az = upload(c, taz);
+    }
     c.d_tab_vec = upload(c, tvec);
     c.d_vec_first = upload(c, c.vec_first);
     c.d_vec_nblk = upload(c, c.vec_nblk);
@@ -1190,7 +1208,7 @@ static void free_all(Ctx &c) {
     auto F = [](void *p) { if (p) (void)hipFree(p); };
     F(c.d_reps); F(c.d_levs); F(c.d_marker_body); F(c.d_body_rep); F(c.d_body_off); F(c.d_tile_rep); F(c.d_rref);
     F(c.d_body_shape); F(c.d_shapes); F(c.d_shape_data); F(c.d_body_len);
-    F(c.d_tab_cells); F(c.d_tab_cells2); F(c.d_tab_vec); F(c.d_vec_first); F(c.d_vec_nblk); F(c.d_tab_bot);
+    F(c.d_tab_cells); F(c.d_tab_cells2); F(c.d_tab_az); F(c.d_tab_vec); F(c.d_vec_first); F(c.d_vec_nblk); F(c.d_tab_bot);
     for (int l = 0; l < RB_MAXLEV; ++l) {
         F(c.d_tab_lev[l]); F(c.d_tab_crs[l]); F(c.d_tab_all[l]); F(c.d_tab_mg[l]);
     }
@@ -1530,6 +1548,7 @@ int rbfib_launch_geometry(const rbfib_ctx *ctx, int *out) {
     out[1] = c.tune.spread_grid;
     out[2] = c.tune.spread_p;
     out[3] = c.mg_npt;
+    out[4] = c.apply_kc;
     return RBFIB_OK;
 }
 

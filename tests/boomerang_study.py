@@ -95,6 +95,7 @@ def main():
     ap.add_argument("--out", default=None)
     ap.add_argument("--state-in", default=None)
     ap.add_argument("--state-out", default=None)
+    ap.add_argument("--checkpoint", type=int, default=250, help="steps between state and result writes")
     args = ap.parse_args()
 
     import torch
@@ -133,6 +134,29 @@ def main():
         args.dtau, dt, R, k0, k0 + args.steps, args.burn, args.tol, "no drift" if args.no_drift else "RFD drift"))
     rejected = iters = 0
     t0 = time.perf_counter()
+
+    def save(step_end, done, final=False):
+        """Write the state and the comparison so far (also every checkpoint interval)."""
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        result = {"dtau": args.dtau, "dt": dt, "replicas": R, "steps_total": step_end, "burn": args.burn,
+                  "tol": args.tol, "no_drift": bool(args.no_drift), "seconds_per_step": el / max(done, 1),
+                  "rejected_this_run": rejected, "iterations_per_replica_step": iters / max(R * done, 1),
+                  "samples": int(counts_h.sum())}
+        if counts_h.sum() > 0:
+            result.update(compare(counts_h, counts_a, ref))
+            log("  step %d: height L2 err %.4f (floor %.4f), angle L2 err %.4f (floor %.4f)" % (
+                step_end, result["height"]["l2"], result["height"]["l2_floor"], result["angle"]["l2"],
+                result["angle"]["l2_floor"]))
+        if args.state_out:
+            np.savez(args.state_out, q=q.cpu().numpy(), theta=th.cpu().numpy(), step=step_end,
+                     counts_h=counts_h, counts_a=counts_a)
+        if args.out:
+            with open(args.out, "w") as fh:
+                json.dump(result, fh, indent=1)
+        if final:
+            log(json.dumps({k: v for k, v in result.items() if k not in ("height", "angle")}))
+
     for k in range(k0, k0 + args.steps):
         rb.rbfib_body_forces(ctx, q, th, pot["phi0"], pot["d"], pot["b"], fconst, FT)
         info = rb.rbfib_sem_step(ctx, q, th, FT, 1.0, dt, args.seed, k, U,
@@ -152,25 +176,10 @@ def main():
             el = time.perf_counter() - t0
             log("  step %d: %.3f s/step, %d rejected so far, %.1f iterations per replica-step" % (
                 k + 1, el / (k + 1 - k0), rejected, iters / (R * (k + 1 - k0))))
-    torch.cuda.synchronize()
-    el = time.perf_counter() - t0
+        if (k + 1 - k0) % args.checkpoint == 0 and k + 1 < k0 + args.steps:
+            save(k + 1, k + 1 - k0)
+    save(k0 + args.steps, args.steps, final=True)
     ctx.close()
-    result = {"dtau": args.dtau, "dt": dt, "replicas": R, "steps_total": k0 + args.steps, "burn": args.burn,
-              "tol": args.tol, "no_drift": bool(args.no_drift), "seconds_per_step": el / max(args.steps, 1),
-              "rejected_this_run": rejected, "iterations_per_replica_step": iters / max(R * args.steps, 1),
-              "samples": int(counts_h.sum())}
-    if counts_h.sum() > 0:
-        result.update(compare(counts_h, counts_a, ref))
-        log("  height L2 err %.4f (floor %.4f), angle L2 err %.4f (floor %.4f)" % (
-            result["height"]["l2"], result["height"]["l2_floor"], result["angle"]["l2"],
-            result["angle"]["l2_floor"]))
-    if args.state_out:
-        np.savez(args.state_out, q=q.cpu().numpy(), theta=th.cpu().numpy(), step=k0 + args.steps,
-                 counts_h=counts_h, counts_a=counts_a)
-    if args.out:
-        with open(args.out, "w") as fh:
-            json.dump(result, fh, indent=1)
-    log(json.dumps({k: v for k, v in result.items() if k not in ("height", "angle")}))
 
 
 if __name__ == "__main__":
