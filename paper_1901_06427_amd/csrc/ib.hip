@@ -360,7 +360,17 @@ __global__ __launch_bounds__(64) void k_spread(const RepDev *reps, const int *ti
     const int lane = threadIdx.x;
     const int lx = lane & 3, ly = (lane >> 2) & 3, lz = lane >> 4;
     const int na = *n_active;
-    for (int it = blockIdx.x; it < na; it += gridDim.x) {
+    // each XCD takes one contiguous range of the (spatially sorted) active tiles, so
+    // the weights of a marker, which neighbouring tiles share, are fetched into one L2
+    // (workgroup b runs on XCD b mod RB_NXCD); grids smaller than RB_NXCD stride plainly
+    const int G = (int)gridDim.x;
+    const bool split = G >= RB_NXCD;
+    const int xcd = split ? (int)blockIdx.x % RB_NXCD : 0;
+    const int lb = split ? (int)blockIdx.x / RB_NXCD : (int)blockIdx.x;
+    const int nblk = split ? (G - xcd + RB_NXCD - 1) / RB_NXCD : G;
+    const int t_beg = split ? (int)((long long)na * xcd / RB_NXCD) : 0;
+    const int t_end = split ? (int)((long long)na * (xcd + 1) / RB_NXCD) : na;
+    for (int it = t_beg + lb; it < t_end; it += nblk) {
         const int t = active[it];
         const int rep = tile_rep[t];
         if (mask && !mask[rep]) continue;
