@@ -7,7 +7,9 @@
 * one Split-Euler-Maruyama step driven by those forces, with the random
   finite differences (Algorithm 1) and without them (the naive scheme whose
   equilibrium App. A shows to be biased), against the oracle's step at the
-  same seed: U^n within the bound that the GPU's solve residuals imply.
+  same seed: U^n within the bound that the GPU's solve residuals imply;
+* a short ensemble run: with the drift the boomerangs keep their
+  Gibbs-Boltzmann distance to the walls, without it they drift towards them.
 """
 import numpy as np
 import pytest
@@ -133,3 +135,42 @@ def test_drift_changes_the_step(rb):
         out.append(U.cpu().numpy())
         ctx.close()
     assert np.abs(out[0] - out[1]).max() > 1e-4 * np.abs(out[0]).max()
+
+
+def test_drift_removes_wall_bias(rb):
+    """End to end (App. A): 256 boomerangs from exact Gibbs-Boltzmann draws, 100 SEM
+    steps at dtau = 0.14.  With the random finite differences the fraction of time the
+    cross point spends within 3h of a wall stays at its Gibbs-Boltzmann value (0.160,
+    tests/golden/boomerang_gb.json); the naive scheme without the drift drives it to
+    about 0.29 within 50 steps.  Measured over steps 50-99 (long runs:
+    0.159 +- 0.005 with the drift, 0.335 +- 0.005 without)."""
+    import json
+    import os
+    import torch
+    from tests.boomerang_study import initial_state
+    ref = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "boomerang_gb.json")))
+    ze = np.asarray(ref["z_edges"])
+    zc = 0.5 * (ze[1:] + ze[:-1])
+    p_ref = float(np.sum(np.asarray(ref["p_height"])[(zc < 3) | (zc > 13)]))
+    R, dtau = 256, 0.14
+    frac = {}
+    for nd in (0, 1):
+        print("boomerang ensemble, no_drift", nd, flush=True)
+        ws = W.boomerang_slit(seed=5, n_replicas=R, dtau=dtau, tol=1e-5)
+        ctx = lib_context(rb, ws, tol=1e-5, precond_fp32=1, no_drift=nd)
+        q0, th0 = initial_state(R, 77)
+        q, th = dev(q0), dev(th0)
+        FT = torch.empty((R, 6), dtype=torch.float64, device="cuda")
+        U = torch.empty_like(FT)
+        near = []
+        for k in range(100):
+            rb.rbfib_body_forces(ctx, q, th, POT["phi0"], POT["d"], POT["b"], FCONST, FT)
+            rb.rbfib_sem_step(ctx, q, th, FT, 1.0, W.boomerang_dt(dtau), 9, k, U, allow=(rb.RBFIB_EREJECT,))
+            if k >= 50:
+                z = q[:, 2].cpu().numpy()
+                near.append(np.mean((z < 3.0) | (z > 13.0)))
+        ctx.close()
+        frac[nd] = float(np.mean(near))
+        print("  wall fraction %.3f (Gibbs-Boltzmann %.3f)" % (frac[nd], p_ref), flush=True)
+    assert abs(frac[0] - p_ref) < 0.04
+    assert frac[1] > p_ref + 0.06
