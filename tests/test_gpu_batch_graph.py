@@ -8,6 +8,12 @@
 * The FGMRES iterations replayed from captured HIP graphs give bit-identical
   results to eager launches, over several replays with eager work and
   synchronisation in between.
+
+The per-replica dot products sum Krylov chunks in a fixed order, so a batch and
+its replicas agree bit for bit when they use the same Krylov chunk; the launch-
+geometry table may choose different chunks for a large batch and a single box,
+so every context here is created under one forced table (the multigrid points
+per thread keep their size rule: four on the 10.9M-cell batch, one alone).
 """
 import numpy as np
 import pytest
@@ -22,6 +28,21 @@ pytestmark = pytest.mark.gpu
 def rb():
     import paper_1901_06427_amd as rb
     return rb
+
+
+@pytest.fixture(autouse=True)
+def one_geometry(tmp_path):
+    import os
+    p = tmp_path / "tuning.txt"
+    p.write_text("# one launch geometry for batches and single replicas\n"
+                 "0 9223372036854775807 1 1000000 1024 16384 32 0 0\n")
+    old = os.environ.get("RBFIB_TUNING")
+    os.environ["RBFIB_TUNING"] = str(p)
+    yield
+    if old is None:
+        os.environ.pop("RBFIB_TUNING", None)
+    else:
+        os.environ["RBFIB_TUNING"] = old
 
 
 def _replicas():
