@@ -136,6 +136,64 @@ def sem_step(g: mac.Grid, r_ref, offsets, q, theta, FT, kT: float, dt: float, se
     return SEMResult(ok, qn, thn, U, WFT, UR.copy(), lamR.copy(), DKT, DK, DJ, DS, x, norms)
 
 
+@dataclasses.dataclass
+class TrapezoidResult:
+    accepted: bool
+    q: np.ndarray
+    theta: np.ndarray
+    U: np.ndarray              # velocities of the corrector (the combination that moved Q^n)
+    U_em: np.ndarray           # U^n of Algorithm 1 at Q^n
+    U_det0: np.ndarray         # N(Q^n) F(Q^n) with slip and boundary data
+    U_det1: np.ndarray         # N(Q*) F(Q*) at the predictor
+    q_pred: np.ndarray
+    theta_pred: np.ndarray
+    em: SEMResult
+
+
+def sem_trapezoid_step(g: mac.Grid, r_ref, offsets, q, theta, forces, kT: float, dt: float, seed: int, step: int,
+                       delta: float = 1e-5, slip: Optional[np.ndarray] = None, slip_pred: Optional[np.ndarray] = None,
+                       tol: float = 1e-12, noise: bool = True) -> TrapezoidResult:
+    """Deterministically second-order trapezoidal variant of the SEM step.
+
+    The Conclusion names trapezoidal, midpoint and Adams-Bashforth extensions of
+    the scheme without writing one out; the reading taken here keeps the random
+    part of Algorithm 1 unchanged and treats the deterministic part with the
+    trapezoidal (Heun) rule:
+      1. Algorithm 1 at Q^n with forces F(Q^n) gives U^n;
+      2. U_det^n = N(Q^n) F(Q^n) (with the slip and boundary data, no noise, no drift);
+      3. predictor Q* = (q^n + dt u^n, Rotate(theta^n, dt omega^n)) -- the Euler-Maruyama
+         update -- and U_det* = N(Q*) F(Q*) (slip_pred at Q*, default slip);
+      4. corrector U_c = U^n + (U_det* - U_det^n)/2 and
+         Q^{n+1} = (q^n + dt u_c, Rotate(theta^n, dt omega_c)).
+    With kT = 0, U^n = U_det^n and U_c is the mean of the deterministic velocities
+    at both ends of the step (Heun's method, second order).  The step is rejected,
+    state untouched, when Algorithm 1 rejects Q* or Q^{n+1} leaves the domain.
+    ``forces(q, theta)`` returns the (nb, 6) forces and torques of a configuration.
+    """
+    q = np.asarray(q, dtype=np.float64).reshape(-1, 3)
+    theta = np.asarray(theta, dtype=np.float64).reshape(-1, 4)
+    F0 = np.asarray(forces(q, theta), dtype=np.float64)
+    em = sem_step(g, r_ref, offsets, q, theta, F0, kT, dt, seed, step, delta=delta, slip=slip, tol=tol, noise=noise)
+    nb = q.shape[0]
+    if not em.accepted:
+        z = np.zeros((nb, 6))
+        return TrapezoidResult(False, q.copy(), theta.copy(), z, em.U, z, z, q.copy(), theta.copy(), em)
+    s0 = Saddle(g, q, theta, r_ref, offsets)
+    Ud0 = s0.split(s0.solve(s0.rhs(FT=F0, slip=slip, include_bc=True), tol=tol))[3].copy()
+    qs, ths = em.q, em.theta
+    F1 = np.asarray(forces(qs, ths), dtype=np.float64)
+    s1 = Saddle(g, qs, ths, r_ref, offsets)
+    sp = slip if slip_pred is None else slip_pred
+    Ud1 = s1.split(s1.solve(s1.rhs(FT=F1, slip=sp, include_bc=True), tol=tol))[3].copy()
+    Uc = em.U + 0.5 * (Ud1 - Ud0)
+    qn = q + dt * Uc[:, :3]
+    thn = B.rotate(theta, dt * Uc[:, 3:])
+    ok = B.inside_open_domain(g, B.marker_positions(qn, thn, r_ref, offsets))
+    if not ok:
+        qn, thn = q.copy(), theta.copy()
+    return TrapezoidResult(ok, qn, thn, Uc, em.U, Ud0, Ud1, qs, ths, em)
+
+
 def drift_pointwise(g: mac.Grid, r_ref, offsets, q, theta, kT: float, seed: int, step: int,
                     delta: float = 1e-5, tol: float = 1e-12):
     """Brute-force RFD on N itself for the same random draw:

@@ -162,3 +162,61 @@ def test_rejection_on_displaced_configurations():
     res = sem.sem_step(g, w.r_ref, w.offsets, q, w.theta, zero, kT=1.0, dt=1e-6, seed=3, step=0, delta=1e-6,
                        noise=False)
     assert res.accepted
+
+
+def _trap_case():
+    from oracle.potentials import body_forces
+    g = mac.Grid((6, 6, 8), (mac.WALL, mac.WALL, mac.WALL), 1.0, 1.0)
+    r_ref = W.icosahedron(1.0)
+    offs = np.array([0, 12], dtype=np.int32)
+    q0 = np.array([[3.1, 2.9, 2.1]])
+    th0 = W.random_unit_quaternions(np.random.default_rng(3), 1)
+    F = lambda q, th: body_forces(g, q, th, r_ref, offs, 4.0, 1.0, 0.25, [0.03, 0.01, -0.05])
+    return g, r_ref, offs, q0, th0, F
+
+
+def test_trapezoid_second_order_deterministic():
+    """kT = 0: a body settling onto a wall under its weight and the wall repulsion
+    (translation and rotation couple through the wall).  Differences between runs
+    with 2, 4 and 8 steps over the same time shrink by 4 per halving for the
+    trapezoidal variant (second order) and by 2 for Algorithm 1 (Euler)."""
+    g, r_ref, offs, q0, th0, F = _trap_case()
+    T = 4.0
+
+    def run(n, trap):
+        q, th = q0.copy(), th0.copy()
+        for k in range(n):
+            if trap:
+                r = sem.sem_trapezoid_step(g, r_ref, offs, q, th, F, 0.0, T / n, 1, k)
+            else:
+                r = sem.sem_step(g, r_ref, offs, q, th, F(q, th), 0.0, T / n, 1, k)
+            assert r.accepted
+            q, th = r.q, r.theta
+        return q, th
+
+    def d(a, b):
+        return np.abs(a[0] - b[0]).max() + np.abs(B.rotation_matrices(a[1]) - B.rotation_matrices(b[1])).max()
+
+    for trap, lo, hi in ((False, 1.6, 2.6), (True, 3.2, 5.0)):
+        Q = [run(n, trap) for n in (2, 4, 8)]
+        ratio = d(Q[0], Q[1]) / d(Q[1], Q[2])
+        assert lo < ratio < hi, (trap, ratio)
+    # the body moved: the test is not trivially satisfied
+    assert np.abs(Q[2][0] - q0).max() > 0.05
+
+
+def test_trapezoid_pieces_and_rejection():
+    """With noise: the predictor is the Euler-Maruyama update of Algorithm 1 at the
+    same random numbers, the corrector adds half the change of the deterministic
+    velocity, and a predictor outside the domain rejects the step untouched."""
+    g, r_ref, offs, q0, th0, F = _trap_case()
+    r = sem.sem_trapezoid_step(g, r_ref, offs, q0, th0, F, 1.0, 0.05, 4, 2)
+    em = sem.sem_step(g, r_ref, offs, q0, th0, F(q0, th0), 1.0, 0.05, 4, 2)
+    assert r.accepted and em.accepted
+    assert np.allclose(r.q_pred, em.q, rtol=0, atol=1e-12) and np.allclose(r.U_em, em.U, rtol=0, atol=1e-12)
+    assert np.allclose(r.U, em.U + 0.5 * (r.U_det1 - r.U_det0), rtol=0, atol=1e-15)
+    assert np.allclose(r.q, q0 + 0.05 * r.U[:, :3], rtol=0, atol=1e-15)
+    # a huge step pushes the predictor through the wall: rejected, state untouched
+    big = lambda q, th: F(q, th) + np.array([0.0, 0.0, -500.0, 0.0, 0.0, 0.0])
+    r2 = sem.sem_trapezoid_step(g, r_ref, offs, q0, th0, big, 0.0, 10.0, 4, 2)
+    assert not r2.accepted and np.array_equal(r2.q, q0) and np.array_equal(r2.theta, th0)
