@@ -1194,6 +1194,11 @@ static void build(Ctx &c, int nrep, const rbfib_grid *grids, const rbfib_bodies 
     c.WFT = dalloc<double>(6 * (size_t)std::max(c.nb, 1));
     c.Fp = dalloc<double>(6 * (size_t)std::max(c.nb, 1));
     c.UR = dalloc<double>(6 * (size_t)std::max(c.nb, 1));
+    c.trap_q0 = dalloc<double>(3 * (size_t)std::max(c.nb, 1));
+    c.trap_th0 = dalloc<double>(4 * (size_t)std::max(c.nb, 1));
+    c.trap_q = dalloc<double>(3 * (size_t)std::max(c.nb, 1));
+    c.trap_th = dalloc<double>(4 * (size_t)std::max(c.nb, 1));
+    c.trap_U = dalloc<double>(18 * (size_t)std::max(c.nb, 1));
     c.slip_acc = dalloc<double>(3 * (size_t)std::max(c.nm, 1));
     c.jbc = dalloc<double>(3 * (size_t)std::max(c.nm, 1));
     for (int cls = 0; cls < RB_NTIMING; ++cls) {
@@ -1228,6 +1233,7 @@ static void free_all(Ctx &c) {
     F(c.active); F(c.cyc_active); F(c.jf); F(c.status); F(c.iters);
     for (int k = 0; k < 3; ++k) { F(c.q_buf[k]); F(c.th_buf[k]); }
     F(c.Wf); F(c.Wt); F(c.WFT); F(c.Fp); F(c.UR); F(c.slip_acc); F(c.jbc); F(c.theta_int);
+    F(c.trap_q0); F(c.trap_th0); F(c.trap_q); F(c.trap_th); F(c.trap_U);
     for (int f = 0; f < 2; ++f)
         for (auto &g : c.graphs[f]) if (g) (void)hipGraphExecDestroy(g);
     if (c.ev_in) (void)hipEventDestroy(c.ev_in);
@@ -1503,6 +1509,109 @@ int rbfib_body_forces(rbfib_ctx *ctx, const double *q, const double *theta, cons
     launch_body_forces(c, q, theta, pot->phi0, pot->d, pot->b, pot->fconst, FT);
     HIP_OK(hipGetLastError());
     return RBFIB_OK;
+    GUARD_END
+}
+
+int rbfib_sem_trapezoid_predict(rbfib_ctx *ctx, const double *q, const double *theta, const double *FT,
+                                const double *slip, double kT, double dt, uint64_t seed, uint64_t step, double *q_pred,
+                                double *theta_pred, rbfib_info *info) {
+    if (!ctx || !(dt > 0.0) || !(kT >= 0.0) ||
+        (ctx->c.nb > 0 && (!q || !theta || !FT || !q_pred || !theta_pred)))
+        return RBFIB_EINVAL;
+    GUARD_BEGIN
+    Ctx &c = ctx->c;
+    Session s(c);
+    c.trap_ready = false;
+    const size_t nb = (size_t)c.nb;
+    // configuration Q^n must be valid (the whole batch stops otherwise, as in rbfib_sem_step)
+    const int st0 = build_markers(c, c.ms[0], q, theta, true);
+    if (st0 != RBFIB_OK) {
+        if (info)
+            for (int r = 0; r < c.nrep; ++r)
+                info[r] = rbfib_info{0, 0.0, c.h_flags[r] ? ((c.h_flags[r] & 8) ? RBFIB_EINVAL : RBFIB_EREJECT) : RBFIB_OK};
+        return st0;
+    }
+    if (nb > 0) {
+        HIP_OK(hipMemcpyAsync(c.trap_q0, q, sizeof(double) * 3 * nb, hipMemcpyDeviceToDevice, c.stream));
+        HIP_OK(hipMemcpyAsync(c.trap_th0, theta, sizeof(double) * 4 * nb, hipMemcpyDeviceToDevice, c.stream));
+        HIP_OK(hipMemcpyAsync(c.trap_q, q, sizeof(double) * 3 * nb, hipMemcpyDeviceToDevice, c.stream));
+        HIP_OK(hipMemcpyAsync(c.trap_th, theta, sizeof(double) * 4 * nb, hipMemcpyDeviceToDevice, c.stream));
+    }
+    // Algorithm 1 at Q^n on the copies: U^n, and the Euler-Maruyama update Q* committed into them
+    std::vector<rbfib_info> out, inf;
+    const int code = sem_step(c, c.trap_q, c.trap_th, FT, slip, kT, dt, seed, step, c.trap_U, out);
+    if (code != RBFIB_OK && code != RBFIB_EREJECT && code != RBFIB_ENOCONV) {
+        if (info) for (int r = 0; r < c.nrep; ++r) info[r] = out[r];
+        return code;
+    }
+    // deterministic velocity at Q^n (markers and orientations of Q^n are still staged)
+    launch_zero(c, c.rhs, nullptr);
+    launch_set_rhs(c, FT, slip, c.rhs);
+    add_boundary_terms(c, c.ms[0], c.rhs);
+    fgmres(c, c.ms[0], c.theta_int, c.rhs, false, inf);
+    launch_copy_U(c, c.xsol, c.trap_U + 6 * nb, 1.0);
+    if (nb > 0) {
+        HIP_OK(hipMemcpyAsync(q_pred, c.trap_q, sizeof(double) * 3 * nb, hipMemcpyDeviceToDevice, c.stream));
+        HIP_OK(hipMemcpyAsync(theta_pred, c.trap_th, sizeof(double) * 4 * nb, hipMemcpyDeviceToDevice, c.stream));
+    }
+    HIP_OK(hipStreamSynchronize(c.stream));
+    c.trap_status.assign(c.nrep, RBFIB_OK);
+    int ret = RBFIB_OK;
+    for (int r = 0; r < c.nrep; ++r) {
+        out[r].iters += inf[r].iters;
+        if (out[r].status == RBFIB_OK && inf[r].status != RBFIB_OK) out[r].status = inf[r].status;
+        c.trap_status[r] = out[r].status;
+        if (out[r].status != RBFIB_OK && ret == RBFIB_OK) ret = out[r].status;
+    }
+    if (info) for (int r = 0; r < c.nrep; ++r) info[r] = out[r];
+    c.trap_dt = dt;
+    c.trap_ready = true;
+    return ret;
+    GUARD_END
+}
+
+int rbfib_sem_trapezoid_correct(rbfib_ctx *ctx, double *q, double *theta, const double *FT_pred,
+                                const double *slip_pred, double *U, rbfib_info *info) {
+    if (!ctx || !ctx->c.trap_ready || (ctx->c.nb > 0 && (!q || !theta || !FT_pred))) return RBFIB_EINVAL;
+    GUARD_BEGIN
+    Ctx &c = ctx->c;
+    Session s(c);
+    c.trap_ready = false;
+    const size_t nb = (size_t)c.nb;
+    std::vector<rbfib_info> out(c.nrep, rbfib_info{0, 0.0, RBFIB_OK}), inf;
+    // deterministic velocity at the predictor
+    const int st = build_markers(c, c.ms[0], c.trap_q, c.trap_th, false);
+    if (st != RBFIB_OK) return st;
+    const double *th = stage_theta(c, c.trap_th);
+    launch_zero(c, c.rhs, nullptr);
+    launch_set_rhs(c, FT_pred, slip_pred, c.rhs);
+    add_boundary_terms(c, c.ms[0], c.rhs);
+    fgmres(c, c.ms[0], th, c.rhs, false, inf);
+    launch_copy_U(c, c.xsol, c.trap_U + 12 * nb, 1.0);
+    // corrector from Q^n, then the rejection test on Q^{n+1}
+    launch_trap_update(c, c.trap_q0, c.trap_th0, c.trap_U, c.trap_U + 6 * nb, c.trap_U + 12 * nb, c.trap_dt, c.Fp);
+    clear_flags(c);
+    launch_markers(c, c.ms[3], c.q_buf[2], c.th_buf[2]);
+    launch_body_distance(c, c.opts.min_body_dist);
+    HIP_OK(hipMemcpyAsync(c.h_flags, c.d_flags, sizeof(int) * c.nrep, hipMemcpyDeviceToHost, c.stream));
+    HIP_OK(hipStreamSynchronize(c.stream));
+    for (int r = 0; r < c.nrep; ++r) {
+        out[r] = inf[r];
+        // replicas whose predictor step was rejected or failed, or whose solve failed, keep Q^n
+        if (c.trap_status[r] != RBFIB_OK || inf[r].status != RBFIB_OK) c.h_flags[r] |= 4;
+    }
+    HIP_OK(hipMemcpyAsync(c.d_flags, c.h_flags, sizeof(int) * c.nrep, hipMemcpyHostToDevice, c.stream));
+    launch_commit_positions(c, q, theta);
+    if (U && nb > 0) HIP_OK(hipMemcpyAsync(U, c.Fp, sizeof(double) * 6 * nb, hipMemcpyDeviceToDevice, c.stream));
+    read_flags(c);
+    int ret = RBFIB_OK;
+    for (int r = 0; r < c.nrep; ++r) {
+        if (c.trap_status[r] != RBFIB_OK) out[r].status = c.trap_status[r];
+        else if (out[r].status == RBFIB_OK && (c.h_flags[r] & 3)) out[r].status = RBFIB_EREJECT;
+        if (out[r].status != RBFIB_OK && ret == RBFIB_OK) ret = out[r].status;
+    }
+    if (info) for (int r = 0; r < c.nrep; ++r) info[r] = out[r];
+    return ret;
     GUARD_END
 }
 
