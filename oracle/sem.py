@@ -137,7 +137,7 @@ def sem_step(g: mac.Grid, r_ref, offsets, q, theta, FT, kT: float, dt: float, se
 
 
 @dataclasses.dataclass
-class TrapezoidResult:
+class RK2Result:
     accepted: bool
     q: np.ndarray
     theta: np.ndarray
@@ -150,48 +150,53 @@ class TrapezoidResult:
     em: SEMResult
 
 
-def sem_trapezoid_step(g: mac.Grid, r_ref, offsets, q, theta, forces, kT: float, dt: float, seed: int, step: int,
-                       delta: float = 1e-5, slip: Optional[np.ndarray] = None, slip_pred: Optional[np.ndarray] = None,
-                       tol: float = 1e-12, noise: bool = True) -> TrapezoidResult:
-    """Deterministically second-order trapezoidal variant of the SEM step.
+def sem_rk2_step(g: mac.Grid, r_ref, offsets, q, theta, forces, kT: float, dt: float, seed: int, step: int,
+                 alpha: float = 1.0, delta: float = 1e-5, slip: Optional[np.ndarray] = None,
+                 slip_pred: Optional[np.ndarray] = None, tol: float = 1e-12, noise: bool = True) -> RK2Result:
+    """Deterministically second-order variants of the SEM step (alpha = 1: trapezoidal,
+    alpha = 1/2: midpoint).
 
     The Conclusion names trapezoidal, midpoint and Adams-Bashforth extensions of
     the scheme without writing one out; the reading taken here keeps the random
     part of Algorithm 1 unchanged and treats the deterministic part with the
-    trapezoidal (Heun) rule:
-      1. Algorithm 1 at Q^n with forces F(Q^n) gives U^n;
+    two-stage Runge-Kutta rule of predictor fraction alpha:
+      1. Algorithm 1 at Q^n with forces F(Q^n) gives U^n (and its rejection test);
       2. U_det^n = N(Q^n) F(Q^n) (with the slip and boundary data, no noise, no drift);
-      3. predictor Q* = (q^n + dt u^n, Rotate(theta^n, dt omega^n)) -- the Euler-Maruyama
-         update -- and U_det* = N(Q*) F(Q*) (slip_pred at Q*, default slip);
-      4. corrector U_c = U^n + (U_det* - U_det^n)/2 and
+      3. predictor Q* = (q^n + alpha dt u^n, Rotate(theta^n, alpha dt omega^n)) and
+         U_det* = N(Q*) F(Q*) (slip_pred at Q*, default slip);
+      4. corrector U_c = U^n + (U_det* - U_det^n) / (2 alpha) and
          Q^{n+1} = (q^n + dt u_c, Rotate(theta^n, dt omega_c)).
-    With kT = 0, U^n = U_det^n and U_c is the mean of the deterministic velocities
-    at both ends of the step (Heun's method, second order).  The step is rejected,
-    state untouched, when Algorithm 1 rejects Q* or Q^{n+1} leaves the domain.
-    ``forces(q, theta)`` returns the (nb, 6) forces and torques of a configuration.
+    With kT = 0, U^n = U_det^n and U_c = (1 - 1/(2 alpha)) U_det^n + U_det* / (2 alpha):
+    Heun's method at alpha = 1 and the explicit midpoint rule at alpha = 1/2, both
+    second order.  The step is rejected, state untouched, when Algorithm 1 rejects
+    its step, or Q* or Q^{n+1} leaves the domain.  ``forces(q, theta)`` returns the
+    (nb, 6) forces and torques of a configuration.
     """
+    if not (0.0 < alpha <= 1.0):
+        raise ValueError("alpha must lie in (0, 1]")
     q = np.asarray(q, dtype=np.float64).reshape(-1, 3)
     theta = np.asarray(theta, dtype=np.float64).reshape(-1, 4)
     F0 = np.asarray(forces(q, theta), dtype=np.float64)
     em = sem_step(g, r_ref, offsets, q, theta, F0, kT, dt, seed, step, delta=delta, slip=slip, tol=tol, noise=noise)
     nb = q.shape[0]
-    if not em.accepted:
-        z = np.zeros((nb, 6))
-        return TrapezoidResult(False, q.copy(), theta.copy(), z, em.U, z, z, q.copy(), theta.copy(), em)
+    z = np.zeros((nb, 6))
+    qs = q + alpha * dt * em.U[:, :3]
+    ths = B.rotate(theta, alpha * dt * em.U[:, 3:])
+    if not em.accepted or not B.inside_open_domain(g, B.marker_positions(qs, ths, r_ref, offsets)):
+        return RK2Result(False, q.copy(), theta.copy(), z, em.U, z, z, q.copy(), theta.copy(), em)
     s0 = Saddle(g, q, theta, r_ref, offsets)
     Ud0 = s0.split(s0.solve(s0.rhs(FT=F0, slip=slip, include_bc=True), tol=tol))[3].copy()
-    qs, ths = em.q, em.theta
     F1 = np.asarray(forces(qs, ths), dtype=np.float64)
     s1 = Saddle(g, qs, ths, r_ref, offsets)
     sp = slip if slip_pred is None else slip_pred
     Ud1 = s1.split(s1.solve(s1.rhs(FT=F1, slip=sp, include_bc=True), tol=tol))[3].copy()
-    Uc = em.U + 0.5 * (Ud1 - Ud0)
+    Uc = em.U + (Ud1 - Ud0) / (2.0 * alpha)
     qn = q + dt * Uc[:, :3]
     thn = B.rotate(theta, dt * Uc[:, 3:])
     ok = B.inside_open_domain(g, B.marker_positions(qn, thn, r_ref, offsets))
     if not ok:
         qn, thn = q.copy(), theta.copy()
-    return TrapezoidResult(ok, qn, thn, Uc, em.U, Ud0, Ud1, qs, ths, em)
+    return RK2Result(ok, qn, thn, Uc, em.U, Ud0, Ud1, qs, ths, em)
 
 
 def drift_pointwise(g: mac.Grid, r_ref, offsets, q, theta, kT: float, seed: int, step: int,

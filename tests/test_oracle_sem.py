@@ -12,6 +12,7 @@
   state unchanged.
 """
 import numpy as np
+import pytest
 
 import workloads as W
 from oracle import bodies as B
@@ -175,11 +176,13 @@ def _trap_case():
     return g, r_ref, offs, q0, th0, F
 
 
-def test_trapezoid_second_order_deterministic():
+@pytest.mark.parametrize("alpha", [1.0, 0.5])
+def test_rk2_second_order_deterministic(alpha):
     """kT = 0: a body settling onto a wall under its weight and the wall repulsion
     (translation and rotation couple through the wall).  Differences between runs
     with 2, 4 and 8 steps over the same time shrink by 4 per halving for the
-    trapezoidal variant (second order) and by 2 for Algorithm 1 (Euler)."""
+    trapezoidal (alpha = 1) and midpoint (alpha = 1/2) variants (second order) and
+    by 2 for Algorithm 1 (Euler)."""
     g, r_ref, offs, q0, th0, F = _trap_case()
     T = 4.0
 
@@ -187,7 +190,7 @@ def test_trapezoid_second_order_deterministic():
         q, th = q0.copy(), th0.copy()
         for k in range(n):
             if trap:
-                r = sem.sem_trapezoid_step(g, r_ref, offs, q, th, F, 0.0, T / n, 1, k)
+                r = sem.sem_rk2_step(g, r_ref, offs, q, th, F, 0.0, T / n, 1, k, alpha=alpha)
             else:
                 r = sem.sem_step(g, r_ref, offs, q, th, F(q, th), 0.0, T / n, 1, k)
             assert r.accepted
@@ -200,23 +203,27 @@ def test_trapezoid_second_order_deterministic():
     for trap, lo, hi in ((False, 1.6, 2.6), (True, 3.2, 5.0)):
         Q = [run(n, trap) for n in (2, 4, 8)]
         ratio = d(Q[0], Q[1]) / d(Q[1], Q[2])
-        assert lo < ratio < hi, (trap, ratio)
+        assert lo < ratio < hi, (trap, alpha, ratio)
     # the body moved: the test is not trivially satisfied
     assert np.abs(Q[2][0] - q0).max() > 0.05
 
 
-def test_trapezoid_pieces_and_rejection():
+@pytest.mark.parametrize("alpha", [1.0, 0.5])
+def test_rk2_pieces_and_rejection(alpha):
     """With noise: the predictor is the Euler-Maruyama update of Algorithm 1 at the
     same random numbers, the corrector adds half the change of the deterministic
     velocity, and a predictor outside the domain rejects the step untouched."""
     g, r_ref, offs, q0, th0, F = _trap_case()
-    r = sem.sem_trapezoid_step(g, r_ref, offs, q0, th0, F, 1.0, 0.05, 4, 2)
+    r = sem.sem_rk2_step(g, r_ref, offs, q0, th0, F, 1.0, 0.05, 4, 2, alpha=alpha)
     em = sem.sem_step(g, r_ref, offs, q0, th0, F(q0, th0), 1.0, 0.05, 4, 2)
     assert r.accepted and em.accepted
-    assert np.allclose(r.q_pred, em.q, rtol=0, atol=1e-12) and np.allclose(r.U_em, em.U, rtol=0, atol=1e-12)
-    assert np.allclose(r.U, em.U + 0.5 * (r.U_det1 - r.U_det0), rtol=0, atol=1e-15)
+    assert np.allclose(r.U_em, em.U, rtol=0, atol=1e-12)
+    assert np.allclose(r.q_pred, q0 + alpha * 0.05 * em.U[:, :3], rtol=0, atol=1e-12)
+    if alpha == 1.0:
+        assert np.allclose(r.q_pred, em.q, rtol=0, atol=1e-12)
+    assert np.allclose(r.U, em.U + (r.U_det1 - r.U_det0) / (2 * alpha), rtol=0, atol=1e-15)
     assert np.allclose(r.q, q0 + 0.05 * r.U[:, :3], rtol=0, atol=1e-15)
     # a huge step pushes the predictor through the wall: rejected, state untouched
     big = lambda q, th: F(q, th) + np.array([0.0, 0.0, -500.0, 0.0, 0.0, 0.0])
-    r2 = sem.sem_trapezoid_step(g, r_ref, offs, q0, th0, big, 0.0, 10.0, 4, 2)
+    r2 = sem.sem_rk2_step(g, r_ref, offs, q0, th0, big, 0.0, 10.0, 4, 2, alpha=alpha)
     assert not r2.accepted and np.array_equal(r2.q, q0) and np.array_equal(r2.theta, th0)
