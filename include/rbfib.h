@@ -291,33 +291,37 @@ typedef struct {
 int rbfib_body_forces(rbfib_ctx *ctx, const double *q, const double *theta,
                       const rbfib_potential *pot, double *FT);
 
-/* Trapezoidal variant of the SEM step, deterministically second order (the
- * Conclusion names trapezoidal, midpoint and Adams-Bashforth extensions without
- * writing one out; this is the reading implemented).  Two calls, because the
- * caller evaluates the forces at the predicted configuration:
+/* Deterministically second-order variants of the SEM step (the Conclusion names
+ * trapezoidal, midpoint and Adams-Bashforth extensions without writing one out;
+ * this is the reading implemented): a two-stage Runge-Kutta rule on the
+ * deterministic velocity with predictor fraction alpha in (0, 1] -- alpha = 1 the
+ * trapezoidal (Heun) form, alpha = 1/2 the explicit midpoint form -- around the
+ * unchanged random part of Algorithm 1.  Two calls, because the caller evaluates
+ * the forces at the predicted configuration:
  *
- * rbfib_sem_trapezoid_predict: Algorithm 1 at Q^n = (q, theta) with forces FT =
- *   F(Q^n), the same random numbers as rbfib_sem_step (seed + r, step), giving U^n;
+ * rbfib_sem_rk2_predict: Algorithm 1 at Q^n = (q, theta) with forces FT = F(Q^n)
+ *   and the same random numbers as rbfib_sem_step (seed + r, step), giving U^n;
  *   the deterministic velocity U_det^n = N(Q^n) F(Q^n) with the slip and boundary
- *   data (one more constrained solve); and the predictor Q* = (q + dt u^n,
- *   Rotate(theta, dt omega^n)) written to q_pred [nb, 3] and theta_pred [nb, 4]
- *   (Q^n there for replicas whose step was rejected).  q and theta are not
- *   modified.  The context keeps Q^n, Q* and both velocities for the corrector.
- * rbfib_sem_trapezoid_correct: U_det* = N(Q*) F(Q*) with FT_pred = F(Q*) and
- *   slip_pred (NULL: none) at Q*, then U_c = U^n + (U_det* - U_det^n)/2 and
+ *   data (one more constrained solve); and the predictor Q* = (q + alpha dt u^n,
+ *   Rotate(theta, alpha dt omega^n)) written to q_pred [nb, 3] and theta_pred
+ *   [nb, 4] (Q^n there for replicas whose step was rejected).  q and theta are not
+ *   modified.  The context keeps Q^n, Q*, alpha and both velocities.
+ * rbfib_sem_rk2_correct: U_det* = N(Q*) F(Q*) with FT_pred = F(Q*) and slip_pred
+ *   (NULL: none) at Q*, then U_c = U^n + (U_det* - U_det^n) / (2 alpha) and
  *   Q^{n+1} = (q^n + dt u_c, Rotate(theta^n, dt omega_c)) from the stored Q^n,
  *   written to q and theta; U (may be NULL) receives U_c [nb, 6].
- * At kT = 0 this is Heun's method for dQ/dt = N(Q) F(Q).  Rejection as in
- * rbfib_sem_step: a replica rejected by the predictor (RBFIB_EREJECT in both
- * calls), whose solves fail, or whose Q^{n+1} leaves the domain keeps Q^n (q and
- * theta are then not written for it).  Five constrained solves and one
- * unconstrained solve per step.  The corrector without a preceding predictor on
- * the context returns RBFIB_EINVAL; info as for rbfib_sem_step. */
-int rbfib_sem_trapezoid_predict(rbfib_ctx *ctx, const double *q, const double *theta, const double *FT,
-                                const double *slip, double kT, double dt, uint64_t seed, uint64_t step,
-                                double *q_pred, double *theta_pred, rbfib_info *info);
-int rbfib_sem_trapezoid_correct(rbfib_ctx *ctx, double *q, double *theta, const double *FT_pred,
-                                const double *slip_pred, double *U, rbfib_info *info);
+ * At kT = 0 these are Heun's method and the midpoint rule for dQ/dt = N(Q) F(Q).
+ * Rejection as in rbfib_sem_step: a replica whose Algorithm 1 step is rejected,
+ * whose Q* or Q^{n+1} leaves the domain, or whose solves fail keeps Q^n (q and
+ * theta are not written for it; RBFIB_EREJECT or the failure in info).  Five
+ * constrained solves and one unconstrained solve per step.  The corrector without
+ * a preceding predictor on the context, or alpha outside (0, 1], returns
+ * RBFIB_EINVAL; info as for rbfib_sem_step. */
+int rbfib_sem_rk2_predict(rbfib_ctx *ctx, const double *q, const double *theta, const double *FT,
+                          const double *slip, double kT, double dt, double alpha, uint64_t seed,
+                          uint64_t step, double *q_pred, double *theta_pred, rbfib_info *info);
+int rbfib_sem_rk2_correct(rbfib_ctx *ctx, double *q, double *theta, const double *FT_pred,
+                          const double *slip_pred, double *U, rbfib_info *info);
 
 /* Vector-Jacobian product of U = N(q, theta) F (no slip, no wall motion;
  * eqs. D1-D4 differentiated): given Ubar = dL/dU [nb, 6], returns

@@ -35,7 +35,7 @@ EXPORTS = [
     "rbfib_apply_saddle", "rbfib_precondition", "rbfib_solve_mobility", "rbfib_fluctuating_stress",
     "rbfib_sem_step", "rbfib_mobility_vjp", "rbfib_kernel_stats", "rbfib_enable_timing",
     "rbfib_apply_saddle_noalloc", "rbfib_launch_geometry", "rbfib_body_forces",
-    "rbfib_sem_trapezoid_predict", "rbfib_sem_trapezoid_correct",
+    "rbfib_sem_rk2_predict", "rbfib_sem_rk2_correct",
 ]
 
 
@@ -106,8 +106,8 @@ def _load():
         "rbfib_enable_timing": (I, [P, I]),
         "rbfib_launch_geometry": (I, [P, ctypes.POINTER(ctypes.c_int)]),
         "rbfib_body_forces": (I, [P, P, P, ctypes.POINTER(rbfib_potential), P]),
-        "rbfib_sem_trapezoid_predict": (I, [P, P, P, P, P, D, D, U64, U64, P, P, ctypes.POINTER(rbfib_info)]),
-        "rbfib_sem_trapezoid_correct": (I, [P, P, P, P, P, P, ctypes.POINTER(rbfib_info)]),
+        "rbfib_sem_rk2_predict": (I, [P, P, P, P, P, D, D, D, U64, U64, P, P, ctypes.POINTER(rbfib_info)]),
+        "rbfib_sem_rk2_correct": (I, [P, P, P, P, P, P, ctypes.POINTER(rbfib_info)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -297,20 +297,20 @@ def rbfib_body_forces(ctx: Context, q, theta, phi0: float, d: float, b: float, f
     _check(_lib.rbfib_body_forces(ctx.h, _ptr(q), _ptr(theta), ctypes.byref(pot), _ptr(FT)), "rbfib_body_forces")
 
 
-def rbfib_sem_trapezoid_predict(ctx: Context, q, theta, FT, kT: float, dt: float, seed: int, step: int, q_pred,
-                                theta_pred, slip=None, allow=(RBFIB_EREJECT, RBFIB_ENOCONV)) -> List[rbfib_info]:
+def rbfib_sem_rk2_predict(ctx: Context, q, theta, FT, kT: float, dt: float, seed: int, step: int, q_pred, theta_pred,
+                          alpha: float = 1.0, slip=None, allow=(RBFIB_EREJECT, RBFIB_ENOCONV)) -> List[rbfib_info]:
     info = _infos(ctx.nrep)
-    code = _lib.rbfib_sem_trapezoid_predict(ctx.h, _ptr(q), _ptr(theta), _ptr(FT), _ptr(slip), float(kT), float(dt),
-                                            int(seed), int(step), _ptr(q_pred), _ptr(theta_pred), info)
-    _check(code, "rbfib_sem_trapezoid_predict", allow)
+    code = _lib.rbfib_sem_rk2_predict(ctx.h, _ptr(q), _ptr(theta), _ptr(FT), _ptr(slip), float(kT), float(dt),
+                                      float(alpha), int(seed), int(step), _ptr(q_pred), _ptr(theta_pred), info)
+    _check(code, "rbfib_sem_rk2_predict", allow)
     return list(info)
 
 
-def rbfib_sem_trapezoid_correct(ctx: Context, q, theta, FT_pred, U=None, slip_pred=None,
-                                allow=(RBFIB_EREJECT, RBFIB_ENOCONV)) -> List[rbfib_info]:
+def rbfib_sem_rk2_correct(ctx: Context, q, theta, FT_pred, U=None, slip_pred=None,
+                          allow=(RBFIB_EREJECT, RBFIB_ENOCONV)) -> List[rbfib_info]:
     info = _infos(ctx.nrep)
-    code = _lib.rbfib_sem_trapezoid_correct(ctx.h, _ptr(q), _ptr(theta), _ptr(FT_pred), _ptr(slip_pred), _ptr(U), info)
-    _check(code, "rbfib_sem_trapezoid_correct", allow)
+    code = _lib.rbfib_sem_rk2_correct(ctx.h, _ptr(q), _ptr(theta), _ptr(FT_pred), _ptr(slip_pred), _ptr(U), info)
+    _check(code, "rbfib_sem_rk2_correct", allow)
     return list(info)
 
 

@@ -649,11 +649,11 @@ struct Ctx {
     double *q_buf[3] = {nullptr, nullptr, nullptr};      // q+, q-, q_new  [nb, 3]
     double *th_buf[3] = {nullptr, nullptr, nullptr};     // [nb, 4]
     double *Wf = nullptr, *Wt = nullptr, *WFT = nullptr, *Fp = nullptr, *slip_acc = nullptr, *UR = nullptr;
-    // trapezoidal SEM variant, kept between its predictor and corrector calls:
+    // second-order SEM variants, kept between their predictor and corrector calls:
     // Q^n, the predictor Q*, and [U^n | U_det^n | U_det*] per body (6 each)
     double *trap_q0 = nullptr, *trap_th0 = nullptr, *trap_q = nullptr, *trap_th = nullptr, *trap_U = nullptr;
     bool trap_ready = false;
-    double trap_dt = 0.0;
+    double trap_dt = 0.0, trap_alpha = 1.0;
     std::vector<int> trap_status;
     double *jbc = nullptr;      // [nm, 3] scratch for the sliding-wall interpolation term
     double *xR = nullptr, *xS = nullptr;
@@ -708,8 +708,8 @@ void launch_body_grad(Ctx &c, const double *x, const double *xa, const double *t
                       double *dphi, double *dtheta);
 void launch_set_rhs_adjoint(Ctx &c, const double *Ubar, double *b);
 void launch_copy_U(Ctx &c, const double *x, double *U, double scale);
-void launch_trap_update(Ctx &c, const double *q, const double *theta, const double *Uem, const double *Ud0,
-                        const double *Ud1, double dt, double *Uc);
+void launch_rk2_update(Ctx &c, const double *q, const double *theta, const double *Uem, const double *Ud0,
+                       const double *Ud1, double w, double dt, double *Uc);
 void launch_body_forces(Ctx &c, const double *q, const double *theta, double phi0, double d, double b,
                         const double fconst[3], double *FT);
 void launch_set_rhs(Ctx &c, const double *FT, const double *slip, double *b);

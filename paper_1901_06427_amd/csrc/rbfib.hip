@@ -1512,10 +1512,10 @@ int rbfib_body_forces(rbfib_ctx *ctx, const double *q, const double *theta, cons
     GUARD_END
 }
 
-int rbfib_sem_trapezoid_predict(rbfib_ctx *ctx, const double *q, const double *theta, const double *FT,
-                                const double *slip, double kT, double dt, uint64_t seed, uint64_t step, double *q_pred,
-                                double *theta_pred, rbfib_info *info) {
-    if (!ctx || !(dt > 0.0) || !(kT >= 0.0) ||
+int rbfib_sem_rk2_predict(rbfib_ctx *ctx, const double *q, const double *theta, const double *FT, const double *slip,
+                          double kT, double dt, double alpha, uint64_t seed, uint64_t step, double *q_pred,
+                          double *theta_pred, rbfib_info *info) {
+    if (!ctx || !(dt > 0.0) || !(kT >= 0.0) || !(alpha > 0.0 && alpha <= 1.0) ||
         (ctx->c.nb > 0 && (!q || !theta || !FT || !q_pred || !theta_pred)))
         return RBFIB_EINVAL;
     GUARD_BEGIN
@@ -1550,6 +1550,23 @@ int rbfib_sem_trapezoid_predict(rbfib_ctx *ctx, const double *q, const double *t
     add_boundary_terms(c, c.ms[0], c.rhs);
     fgmres(c, c.ms[0], c.theta_int, c.rhs, false, inf);
     launch_copy_U(c, c.xsol, c.trap_U + 6 * nb, 1.0);
+    if (alpha != 1.0 && nb > 0) {
+        // the predictor moves Q^n by alpha dt U^n (the Euler-Maruyama update is alpha = 1);
+        // replicas already rejected keep Q^n, others are rejected if Q* leaves the domain
+        HIP_OK(hipMemcpyAsync(c.trap_q, c.trap_q0, sizeof(double) * 3 * nb, hipMemcpyDeviceToDevice, c.stream));
+        HIP_OK(hipMemcpyAsync(c.trap_th, c.trap_th0, sizeof(double) * 4 * nb, hipMemcpyDeviceToDevice, c.stream));
+        launch_rk2_update(c, c.trap_q0, c.trap_th0, c.trap_U, nullptr, nullptr, 0.0, alpha * dt, nullptr);
+        clear_flags(c);
+        launch_markers(c, c.ms[3], c.q_buf[2], c.th_buf[2]);
+        HIP_OK(hipMemcpyAsync(c.h_flags, c.d_flags, sizeof(int) * c.nrep, hipMemcpyDeviceToHost, c.stream));
+        HIP_OK(hipStreamSynchronize(c.stream));
+        for (int r = 0; r < c.nrep; ++r) {
+            if (out[r].status != RBFIB_OK) c.h_flags[r] |= 4;
+            else if (c.h_flags[r] & 3) out[r].status = RBFIB_EREJECT;
+        }
+        HIP_OK(hipMemcpyAsync(c.d_flags, c.h_flags, sizeof(int) * c.nrep, hipMemcpyHostToDevice, c.stream));
+        launch_commit_positions(c, c.trap_q, c.trap_th);
+    }
     if (nb > 0) {
         HIP_OK(hipMemcpyAsync(q_pred, c.trap_q, sizeof(double) * 3 * nb, hipMemcpyDeviceToDevice, c.stream));
         HIP_OK(hipMemcpyAsync(theta_pred, c.trap_th, sizeof(double) * 4 * nb, hipMemcpyDeviceToDevice, c.stream));
@@ -1565,13 +1582,14 @@ int rbfib_sem_trapezoid_predict(rbfib_ctx *ctx, const double *q, const double *t
     }
     if (info) for (int r = 0; r < c.nrep; ++r) info[r] = out[r];
     c.trap_dt = dt;
+    c.trap_alpha = alpha;
     c.trap_ready = true;
     return ret;
     GUARD_END
 }
 
-int rbfib_sem_trapezoid_correct(rbfib_ctx *ctx, double *q, double *theta, const double *FT_pred,
-                                const double *slip_pred, double *U, rbfib_info *info) {
+int rbfib_sem_rk2_correct(rbfib_ctx *ctx, double *q, double *theta, const double *FT_pred, const double *slip_pred,
+                          double *U, rbfib_info *info) {
     if (!ctx || !ctx->c.trap_ready || (ctx->c.nb > 0 && (!q || !theta || !FT_pred))) return RBFIB_EINVAL;
     GUARD_BEGIN
     Ctx &c = ctx->c;
@@ -1589,7 +1607,8 @@ int rbfib_sem_trapezoid_correct(rbfib_ctx *ctx, double *q, double *theta, const 
     fgmres(c, c.ms[0], th, c.rhs, false, inf);
     launch_copy_U(c, c.xsol, c.trap_U + 12 * nb, 1.0);
     // corrector from Q^n, then the rejection test on Q^{n+1}
-    launch_trap_update(c, c.trap_q0, c.trap_th0, c.trap_U, c.trap_U + 6 * nb, c.trap_U + 12 * nb, c.trap_dt, c.Fp);
+    launch_rk2_update(c, c.trap_q0, c.trap_th0, c.trap_U, c.trap_U + 6 * nb, c.trap_U + 12 * nb,
+                      0.5 / c.trap_alpha, c.trap_dt, c.Fp);
     clear_flags(c);
     launch_markers(c, c.ms[3], c.q_buf[2], c.th_buf[2]);
     launch_body_distance(c, c.opts.min_body_dist);

@@ -156,27 +156,28 @@ void launch_update_positions(Ctx &c, const double *q, const double *theta, const
                        c.nb, q, theta, x, dt, c.q_buf[2], c.th_buf[2]);
 }
 
-// Corrector of the trapezoidal variant: U_c = U^n + (U_det* - U_det^n) / 2, then
-// q_new = q + dt u_c and theta_new = Rotate(theta, dt omega_c) into q_buf[2], th_buf[2].
-__global__ void k_trap_update(int nb, const double *q, const double *theta, const double *Uem, const double *Ud0,
-                              const double *Ud1, double dt, double *Uc, double *qn, double *thn) {
+// Stage update of the second-order variants: U_c = U^n + w (U_det* - U_det^n), then
+// q_new = q + dt u_c and theta_new = Rotate(theta, dt omega_c) into q_buf[2], th_buf[2]
+// (w = 0 gives the predictor's move by U^n itself).
+__global__ void k_rk2_update(int nb, const double *q, const double *theta, const double *Uem, const double *Ud0,
+                             const double *Ud1, double w, double dt, double *Uc, double *qn, double *thn) {
     int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= nb) return;
     double u[6];
     for (int k = 0; k < 6; ++k) {
-        u[k] = Uem[6 * p + k] + 0.5 * (Ud1[6 * p + k] - Ud0[6 * p + k]);
-        Uc[6 * p + k] = u[k];
+        u[k] = w == 0.0 ? Uem[6 * p + k] : Uem[6 * p + k] + w * (Ud1[6 * p + k] - Ud0[6 * p + k]);
+        if (Uc) Uc[6 * p + k] = u[k];
     }
     for (int k = 0; k < 3; ++k) qn[3 * p + k] = q[3 * p + k] + dt * u[k];
     double ph[3] = {dt * u[3], dt * u[4], dt * u[5]};
     quat_rotate(theta + 4 * p, ph, thn + 4 * p);
 }
 
-void launch_trap_update(Ctx &c, const double *q, const double *theta, const double *Uem, const double *Ud0,
-                        const double *Ud1, double dt, double *Uc) {
+void launch_rk2_update(Ctx &c, const double *q, const double *theta, const double *Uem, const double *Ud0,
+                       const double *Ud1, double w, double dt, double *Uc) {
     if (c.nb == 0) return;
-    hipLaunchKernelGGL(k_trap_update, dim3((c.nb + 63) / 64), dim3(64), 0, c.stream, c.nb, q, theta, Uem, Ud0, Ud1,
-                       dt, Uc, c.q_buf[2], c.th_buf[2]);
+    hipLaunchKernelGGL(k_rk2_update, dim3((c.nb + 63) / 64), dim3(64), 0, c.stream, c.nb, q, theta, Uem, Ud0, Ud1,
+                       w, dt, Uc, c.q_buf[2], c.th_buf[2]);
 }
 
 // Rejection by body-centre distance (per replica flag).

@@ -1,11 +1,12 @@
-"""The trapezoidal (deterministically second-order) SEM variant on the GPU,
-through rbfib_sem_trapezoid_predict / rbfib_sem_trapezoid_correct.
+"""The deterministically second-order SEM variants on the GPU (trapezoidal,
+alpha = 1, and midpoint, alpha = 1/2), through rbfib_sem_rk2_predict /
+rbfib_sem_rk2_correct.
 
 * One step of two confined spheres driven by wall repulsion and a constant
   marker force, with noise, against the oracle's variant at the same random
-  numbers: the predictor within the bound of Algorithm 1's velocities (oracle
-  gains), the corrector's velocities and the new configuration within 1e-6
-  relative at solver tolerance 1e-11.
+  numbers: the predictor within alpha dt times the bound of Algorithm 1's
+  velocities (oracle gains), the corrector's velocities and the new
+  configuration within 1e-6 relative at solver tolerance 1e-11.
 * kT = 0, a body settling onto a wall: differences between runs with 2, 4 and 8
   steps shrink by about 4 per halving (second order), against about 2 for
   rbfib_sem_step on the same problem.
@@ -41,36 +42,37 @@ def _gpu_forces(rb, ctx, q, th, nb):
     return FT
 
 
-def _trap_step(rb, ctx, q, th, nb, kT, dt, seed, step):
+def _rk2_step(rb, ctx, q, th, nb, kT, dt, seed, step, alpha):
     """Predictor, forces at the predictor, corrector (q, th updated in place)."""
     import torch
     qp = torch.empty_like(q)
     tp = torch.empty_like(th)
     U = torch.empty((nb, 6), dtype=torch.float64, device="cuda")
-    i1 = rb.rbfib_sem_trapezoid_predict(ctx, q, th, _gpu_forces(rb, ctx, q, th, nb), kT, dt, seed, step, qp, tp,
-                                        allow=())
-    i2 = rb.rbfib_sem_trapezoid_correct(ctx, q, th, _gpu_forces(rb, ctx, qp, tp, nb), U, allow=())
+    i1 = rb.rbfib_sem_rk2_predict(ctx, q, th, _gpu_forces(rb, ctx, q, th, nb), kT, dt, seed, step, qp, tp,
+                                  alpha=alpha, allow=())
+    i2 = rb.rbfib_sem_rk2_correct(ctx, q, th, _gpu_forces(rb, ctx, qp, tp, nb), U, allow=())
     return qp, tp, U, i1, i2
 
 
-def test_trapezoid_step_matches_oracle(rb):
+@pytest.mark.parametrize("alpha", [1.0, 0.5])
+def test_rk2_step_matches_oracle(rb, alpha):
     import torch
     name = "two_spheres_16x16x32"
     w = sem_configs()[name]
-    print("trapezoid", name, flush=True)
+    print("rk2", name, "alpha", alpha, flush=True)
     g = oracle_grid(w)
     F = lambda q, th: body_forces(g, q, th, w.r_ref, w.offsets, PHI0, DW, BW, FC)
     tol, kT, dt, seed, step = 1e-11, 1.0, 0.05, 41, 6
     ctx = lib_context(rb, w, tol=tol, precond_fp32=1, max_iter=600)
     q, th = dev(w.q), dev(w.theta)
-    qp, tp, U, i1, i2 = _trap_step(rb, ctx, q, th, w.nb, kT, dt, seed, step)
+    qp, tp, U, i1, i2 = _rk2_step(rb, ctx, q, th, w.nb, kT, dt, seed, step, alpha)
     torch.cuda.synchronize()
-    ref = sem.sem_trapezoid_step(g, w.r_ref, w.offsets, w.q, w.theta, F, kT, dt, seed, step, tol=1e-12)
+    ref = sem.sem_rk2_step(g, w.r_ref, w.offsets, w.q, w.theta, F, kT, dt, seed, step, alpha=alpha, tol=1e-12)
     assert ref.accepted and i1[0].status == 0 and i2[0].status == 0
     print("  iters", i1[0].iters, i2[0].iters, flush=True)
-    # predictor: the Euler-Maruyama update of U^n, whose error is bounded by the oracle gains
+    # predictor: Q^n moved by alpha dt U^n, whose error is bounded by the oracle gains
     bound = sem_error_bound(name, ref.em.rhs_norms, tol, i1[0].rel_residual)
-    assert np.abs(qp.cpu().numpy() - ref.q_pred).max() <= dt * bound.max() + 1e-13
+    assert np.abs(qp.cpu().numpy() - ref.q_pred).max() <= alpha * dt * bound.max() + 1e-13
     # corrector velocities and the new configuration
     Ug = U.cpu().numpy()
     err = np.abs(Ug - ref.U).max() / np.abs(ref.U).max()
@@ -91,7 +93,8 @@ def _settling_case():
     return w
 
 
-def test_trapezoid_second_order_deterministic(rb):
+@pytest.mark.parametrize("alpha", [1.0, 0.5])
+def test_rk2_second_order_deterministic(rb, alpha):
     import torch
     w = _settling_case()
     T = 4.0
@@ -102,7 +105,7 @@ def test_trapezoid_second_order_deterministic(rb):
         U = torch.empty((1, 6), dtype=torch.float64, device="cuda")
         for k in range(n):
             if trap:
-                _trap_step(rb, ctx, q, th, 1, 0.0, T / n, 1, k)
+                _rk2_step(rb, ctx, q, th, 1, 0.0, T / n, 1, k, alpha)
             else:
                 rb.rbfib_sem_step(ctx, q, th, _gpu_forces(rb, ctx, q, th, 1), 0.0, T / n, 1, k, U, allow=())
         torch.cuda.synchronize()
@@ -114,13 +117,14 @@ def test_trapezoid_second_order_deterministic(rb):
     for trap, lo, hi in ((False, 1.6, 2.6), (True, 3.2, 5.0)):
         Q = [run(n, trap) for n in (2, 4, 8)]
         ratio = d(Q[0], Q[1]) / d(Q[1], Q[2])
-        print("trapezoid" if trap else "euler", "ratio %.3f" % ratio, flush=True)
+        print(("rk2 alpha %g" % alpha) if trap else "euler", "ratio %.3f" % ratio, flush=True)
         assert lo < ratio < hi
     assert np.abs(Q[2][0] - w.q).max() > 0.05
     ctx.close()
 
 
-def test_trapezoid_rejection_and_order_of_calls(rb):
+@pytest.mark.parametrize("alpha", [1.0, 0.5])
+def test_rk2_rejection_and_order_of_calls(rb, alpha):
     import torch
     w = _settling_case()
     ctx = lib_context(rb, w, tol=1e-10)
@@ -128,12 +132,14 @@ def test_trapezoid_rejection_and_order_of_calls(rb):
     FT = dev(np.array([[0.0, 0.0, -500.0, 0.0, 0.0, 0.0]]))
     # the corrector needs a predictor first
     with pytest.raises(rb.RBFIBError):
-        rb.rbfib_sem_trapezoid_correct(ctx, q, th, FT, allow=())
+        rb.rbfib_sem_rk2_correct(ctx, q, th, FT, allow=())
     qp, tp = torch.empty_like(q), torch.empty_like(th)
-    i1 = rb.rbfib_sem_trapezoid_predict(ctx, q, th, FT, 0.0, 10.0, 1, 0, qp, tp)
+    with pytest.raises(rb.RBFIBError):
+        rb.rbfib_sem_rk2_predict(ctx, q, th, FT, 0.0, 1.0, 1, 0, qp, tp, alpha=1.5)
+    i1 = rb.rbfib_sem_rk2_predict(ctx, q, th, FT, 0.0, 10.0, 1, 0, qp, tp, alpha=alpha)
     assert i1[0].status == rb.RBFIB_EREJECT
     assert np.array_equal(qp.cpu().numpy(), w.q)
-    i2 = rb.rbfib_sem_trapezoid_correct(ctx, q, th, FT)
+    i2 = rb.rbfib_sem_rk2_correct(ctx, q, th, FT)
     assert i2[0].status == rb.RBFIB_EREJECT
     assert np.array_equal(q.cpu().numpy(), w.q) and np.array_equal(th.cpu().numpy(), w.theta)
     ctx.close()
