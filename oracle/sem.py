@@ -199,6 +199,36 @@ def sem_rk2_step(g: mac.Grid, r_ref, offsets, q, theta, forces, kT: float, dt: f
     return RK2Result(ok, qn, thn, Uc, em.U, Ud0, Ud1, qs, ths, em)
 
 
+def sem_ab2_step(g: mac.Grid, r_ref, offsets, q, theta, FT, kT: float, dt: float, seed: int, step: int,
+                 U_det_prev: Optional[np.ndarray] = None, delta: float = 1e-5, slip: Optional[np.ndarray] = None,
+                 tol: float = 1e-12, noise: bool = True):
+    """Adams-Bashforth variant of the SEM step (deterministically second order).
+
+    Reading of the Conclusion's Adams-Bashforth extension: Algorithm 1 at Q^n gives
+    U^n; the deterministic velocity U_det^n = N(Q^n) F(Q^n) (slip and boundary data,
+    no noise, no drift) is extrapolated with the one of the previous step,
+    U_c = U^n + (U_det^n - U_det^{n-1}) / 2, and Q^{n+1} = (q^n + dt u_c,
+    Rotate(theta^n, dt omega_c)).  Without a previous velocity (the first step)
+    U_det^{n-1} = U_det^n, i.e. Algorithm 1 itself.  At kT = 0 this is the two-step
+    Adams-Bashforth rule 3/2 f^n - 1/2 f^{n-1}.  Rejection as in Algorithm 1 plus
+    Q^{n+1} outside the domain.  Returns (SEMResult of the step, U_det^n) -- the
+    SEMResult's U is U_c.
+    """
+    q = np.asarray(q, dtype=np.float64).reshape(-1, 3)
+    theta = np.asarray(theta, dtype=np.float64).reshape(-1, 4)
+    em = sem_step(g, r_ref, offsets, q, theta, FT, kT, dt, seed, step, delta=delta, slip=slip, tol=tol, noise=noise)
+    s0 = Saddle(g, q, theta, r_ref, offsets)
+    Ud = s0.split(s0.solve(s0.rhs(FT=FT, slip=slip, include_bc=True), tol=tol))[3].copy()
+    prev = Ud if U_det_prev is None else np.asarray(U_det_prev, dtype=np.float64).reshape(-1, 6)
+    Uc = em.U + 0.5 * (Ud - prev)
+    qn = q + dt * Uc[:, :3]
+    thn = B.rotate(theta, dt * Uc[:, 3:])
+    ok = em.accepted and B.inside_open_domain(g, B.marker_positions(qn, thn, r_ref, offsets))
+    if not ok:
+        qn, thn = q.copy(), theta.copy()
+    return dataclasses.replace(em, accepted=ok, q=qn, theta=thn, U=Uc), Ud
+
+
 def drift_pointwise(g: mac.Grid, r_ref, offsets, q, theta, kT: float, seed: int, step: int,
                     delta: float = 1e-5, tol: float = 1e-12):
     """Brute-force RFD on N itself for the same random draw:

@@ -227,3 +227,37 @@ def test_rk2_pieces_and_rejection(alpha):
     big = lambda q, th: F(q, th) + np.array([0.0, 0.0, -500.0, 0.0, 0.0, 0.0])
     r2 = sem.sem_rk2_step(g, r_ref, offs, q0, th0, big, 0.0, 10.0, 4, 2, alpha=alpha)
     assert not r2.accepted and np.array_equal(r2.q, q0) and np.array_equal(r2.theta, th0)
+
+
+def test_ab2_second_order_deterministic():
+    """kT = 0: the Adams-Bashforth variant (started by one Algorithm 1 step) on the
+    settling body: differences shrink by about 4 per halving of the step."""
+    g, r_ref, offs, q0, th0, F = _trap_case()
+    T = 4.0
+
+    def run(n):
+        q, th, prev = q0.copy(), th0.copy(), None
+        for k in range(n):
+            r, prev = sem.sem_ab2_step(g, r_ref, offs, q, th, F(q, th), 0.0, T / n, 1, k, U_det_prev=prev)
+            assert r.accepted
+            q, th = r.q, r.theta
+        return q, th
+
+    def d(a, b):
+        return np.abs(a[0] - b[0]).max() + np.abs(B.rotation_matrices(a[1]) - B.rotation_matrices(b[1])).max()
+
+    Q = [run(n) for n in (4, 8, 16)]
+    ratio = d(Q[0], Q[1]) / d(Q[1], Q[2])
+    assert 3.2 < ratio < 5.0, ratio
+
+
+def test_ab2_pieces():
+    """With noise: without a previous velocity the step is Algorithm 1's; with one,
+    U_c = U^n + (U_det^n - U_det^{n-1})/2 at the same random numbers."""
+    g, r_ref, offs, q0, th0, F = _trap_case()
+    em = sem.sem_step(g, r_ref, offs, q0, th0, F(q0, th0), 1.0, 0.05, 4, 2)
+    r0, Ud = sem.sem_ab2_step(g, r_ref, offs, q0, th0, F(q0, th0), 1.0, 0.05, 4, 2)
+    assert np.allclose(r0.U, em.U, rtol=0, atol=1e-12) and np.allclose(r0.q, em.q, rtol=0, atol=1e-12)
+    prev = Ud + 0.01
+    r1, _ = sem.sem_ab2_step(g, r_ref, offs, q0, th0, F(q0, th0), 1.0, 0.05, 4, 2, U_det_prev=prev)
+    assert np.allclose(r1.U, em.U + 0.5 * (Ud - prev), rtol=0, atol=1e-12)
