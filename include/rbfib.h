@@ -323,6 +323,23 @@ int rbfib_sem_rk2_predict(rbfib_ctx *ctx, const double *q, const double *theta, 
 int rbfib_sem_rk2_correct(rbfib_ctx *ctx, double *q, double *theta, const double *FT_pred,
                           const double *slip_pred, double *U, rbfib_info *info);
 
+/* Adams-Bashforth variant of the SEM step, deterministically second order (the
+ * Conclusion's third named extension; reading implemented): Algorithm 1 at Q^n
+ * with the same random numbers as rbfib_sem_step gives U^n, the deterministic
+ * velocity U_det^n = N(Q^n) F(Q^n) (slip and boundary data; one more constrained
+ * solve) is extrapolated with the previous step's,
+ *     U_c = U^n + (U_det^n - U_det^{n-1}) / 2,
+ * and Q^{n+1} = (q + dt u_c, Rotate(theta, dt omega_c)) is written to q and theta.
+ * U_det_prev [nb, 6] (device, caller owned) holds U_det^{n-1} on entry when
+ * have_prev = 1 (have_prev = 0: none, the step is Algorithm 1's) and receives
+ * U_det^n on return for every replica.  U (may be NULL) receives U_c.  At kT = 0
+ * this is the two-step Adams-Bashforth rule.  Rejection as in rbfib_sem_step, plus
+ * Q^{n+1} outside the domain.  Four constrained solves and one unconstrained
+ * solve per step; one call, since the forces are needed at Q^n only. */
+int rbfib_sem_ab2_step(rbfib_ctx *ctx, double *q, double *theta, const double *FT, const double *slip,
+                       double kT, double dt, uint64_t seed, uint64_t step, double *U_det_prev,
+                       int have_prev, double *U, rbfib_info *info);
+
 /* Vector-Jacobian product of U = N(q, theta) F (no slip, no wall motion;
  * eqs. D1-D4 differentiated): given Ubar = dL/dU [nb, 6], returns
  * dFT = dL/dF [nb, 6], dq = dL/dq [nb, 3], dphi [nb, 3] (gradient with respect

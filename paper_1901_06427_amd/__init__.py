@@ -35,7 +35,7 @@ EXPORTS = [
     "rbfib_apply_saddle", "rbfib_precondition", "rbfib_solve_mobility", "rbfib_fluctuating_stress",
     "rbfib_sem_step", "rbfib_mobility_vjp", "rbfib_kernel_stats", "rbfib_enable_timing",
     "rbfib_apply_saddle_noalloc", "rbfib_launch_geometry", "rbfib_body_forces",
-    "rbfib_sem_rk2_predict", "rbfib_sem_rk2_correct",
+    "rbfib_sem_rk2_predict", "rbfib_sem_rk2_correct", "rbfib_sem_ab2_step",
 ]
 
 
@@ -108,6 +108,7 @@ def _load():
         "rbfib_body_forces": (I, [P, P, P, ctypes.POINTER(rbfib_potential), P]),
         "rbfib_sem_rk2_predict": (I, [P, P, P, P, P, D, D, D, U64, U64, P, P, ctypes.POINTER(rbfib_info)]),
         "rbfib_sem_rk2_correct": (I, [P, P, P, P, P, P, ctypes.POINTER(rbfib_info)]),
+        "rbfib_sem_ab2_step": (I, [P, P, P, P, P, D, D, U64, U64, P, I, P, ctypes.POINTER(rbfib_info)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -311,6 +312,15 @@ def rbfib_sem_rk2_correct(ctx: Context, q, theta, FT_pred, U=None, slip_pred=Non
     info = _infos(ctx.nrep)
     code = _lib.rbfib_sem_rk2_correct(ctx.h, _ptr(q), _ptr(theta), _ptr(FT_pred), _ptr(slip_pred), _ptr(U), info)
     _check(code, "rbfib_sem_rk2_correct", allow)
+    return list(info)
+
+
+def rbfib_sem_ab2_step(ctx: Context, q, theta, FT, kT: float, dt: float, seed: int, step: int, U_det_prev,
+                       have_prev: bool, U=None, slip=None, allow=(RBFIB_EREJECT, RBFIB_ENOCONV)) -> List[rbfib_info]:
+    info = _infos(ctx.nrep)
+    code = _lib.rbfib_sem_ab2_step(ctx.h, _ptr(q), _ptr(theta), _ptr(FT), _ptr(slip), float(kT), float(dt), int(seed),
+                                   int(step), _ptr(U_det_prev), 1 if have_prev else 0, _ptr(U), info)
+    _check(code, "rbfib_sem_ab2_step", allow)
     return list(info)
 
 

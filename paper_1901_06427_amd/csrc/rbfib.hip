@@ -1634,6 +1634,72 @@ int rbfib_sem_rk2_correct(rbfib_ctx *ctx, double *q, double *theta, const double
     GUARD_END
 }
 
+int rbfib_sem_ab2_step(rbfib_ctx *ctx, double *q, double *theta, const double *FT, const double *slip, double kT,
+                       double dt, uint64_t seed, uint64_t step, double *U_det_prev, int have_prev, double *U,
+                       rbfib_info *info) {
+    if (!ctx || !(dt > 0.0) || !(kT >= 0.0) || (have_prev != 0 && have_prev != 1) ||
+        (ctx->c.nb > 0 && (!q || !theta || !FT || !U_det_prev)))
+        return RBFIB_EINVAL;
+    GUARD_BEGIN
+    Ctx &c = ctx->c;
+    Session s(c);
+    c.trap_ready = false;                       // the stage buffers are reused here
+    const size_t nb = (size_t)c.nb;
+    const int st0 = build_markers(c, c.ms[0], q, theta, true);
+    if (st0 != RBFIB_OK) {
+        if (info)
+            for (int r = 0; r < c.nrep; ++r)
+                info[r] = rbfib_info{0, 0.0, c.h_flags[r] ? ((c.h_flags[r] & 8) ? RBFIB_EINVAL : RBFIB_EREJECT) : RBFIB_OK};
+        return st0;
+    }
+    if (nb > 0) {
+        HIP_OK(hipMemcpyAsync(c.trap_q0, q, sizeof(double) * 3 * nb, hipMemcpyDeviceToDevice, c.stream));
+        HIP_OK(hipMemcpyAsync(c.trap_th0, theta, sizeof(double) * 4 * nb, hipMemcpyDeviceToDevice, c.stream));
+        HIP_OK(hipMemcpyAsync(c.trap_q, q, sizeof(double) * 3 * nb, hipMemcpyDeviceToDevice, c.stream));
+        HIP_OK(hipMemcpyAsync(c.trap_th, theta, sizeof(double) * 4 * nb, hipMemcpyDeviceToDevice, c.stream));
+    }
+    // Algorithm 1 at Q^n (on copies) for U^n, then the deterministic velocity at Q^n
+    std::vector<rbfib_info> out, inf;
+    const int code = sem_step(c, c.trap_q, c.trap_th, FT, slip, kT, dt, seed, step, c.trap_U, out);
+    if (code != RBFIB_OK && code != RBFIB_EREJECT && code != RBFIB_ENOCONV) {
+        if (info) for (int r = 0; r < c.nrep; ++r) info[r] = out[r];
+        return code;
+    }
+    launch_zero(c, c.rhs, nullptr);
+    launch_set_rhs(c, FT, slip, c.rhs);
+    add_boundary_terms(c, c.ms[0], c.rhs);
+    fgmres(c, c.ms[0], c.theta_int, c.rhs, false, inf);
+    double *Ud = c.trap_U + 6 * nb;
+    launch_copy_U(c, c.xsol, Ud, 1.0);
+    // U_c = U^n + (U_det^n - U_det^{n-1}) / 2 from Q^n, then the rejection test on Q^{n+1}
+    launch_rk2_update(c, c.trap_q0, c.trap_th0, c.trap_U, have_prev ? U_det_prev : Ud, Ud, 0.5, dt, c.Fp);
+    clear_flags(c);
+    launch_markers(c, c.ms[3], c.q_buf[2], c.th_buf[2]);
+    launch_body_distance(c, c.opts.min_body_dist);
+    HIP_OK(hipMemcpyAsync(c.h_flags, c.d_flags, sizeof(int) * c.nrep, hipMemcpyDeviceToHost, c.stream));
+    HIP_OK(hipStreamSynchronize(c.stream));
+    for (int r = 0; r < c.nrep; ++r) {
+        out[r].iters += inf[r].iters;
+        if (out[r].status == RBFIB_OK && inf[r].status != RBFIB_OK) out[r].status = inf[r].status;
+        if (out[r].status != RBFIB_OK) c.h_flags[r] |= 4;
+    }
+    HIP_OK(hipMemcpyAsync(c.d_flags, c.h_flags, sizeof(int) * c.nrep, hipMemcpyHostToDevice, c.stream));
+    launch_commit_positions(c, q, theta);
+    if (nb > 0) {
+        HIP_OK(hipMemcpyAsync(U_det_prev, Ud, sizeof(double) * 6 * nb, hipMemcpyDeviceToDevice, c.stream));
+        if (U) HIP_OK(hipMemcpyAsync(U, c.Fp, sizeof(double) * 6 * nb, hipMemcpyDeviceToDevice, c.stream));
+    }
+    read_flags(c);
+    int ret = RBFIB_OK;
+    for (int r = 0; r < c.nrep; ++r) {
+        if (out[r].status == RBFIB_OK && (c.h_flags[r] & 3)) out[r].status = RBFIB_EREJECT;
+        if (out[r].status != RBFIB_OK && ret == RBFIB_OK) ret = out[r].status;
+    }
+    if (info) for (int r = 0; r < c.nrep; ++r) info[r] = out[r];
+    return ret;
+    GUARD_END
+}
+
 int rbfib_mobility_vjp(rbfib_ctx *ctx, const double *q, const double *theta, const double *FT, const double *Ubar,
                        double *dFT, double *dq, double *dphi, double *dtheta, rbfib_info *info) {
     if (!ctx || (ctx->c.nb > 0 && (!q || !theta || !FT || !Ubar))) return RBFIB_EINVAL;

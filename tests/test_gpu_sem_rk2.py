@@ -12,6 +12,8 @@ rbfib_sem_rk2_correct.
   rbfib_sem_step on the same problem.
 * A predictor pushed through a wall rejects the step in both calls and leaves
   the state untouched; the corrector without a predictor is refused.
+* The Adams-Bashforth variant (rbfib_sem_ab2_step): two noisy steps against the
+  oracle's, and its kT = 0 convergence order.
 """
 import numpy as np
 import pytest
@@ -142,4 +144,57 @@ def test_rk2_rejection_and_order_of_calls(rb, alpha):
     i2 = rb.rbfib_sem_rk2_correct(ctx, q, th, FT)
     assert i2[0].status == rb.RBFIB_EREJECT
     assert np.array_equal(q.cpu().numpy(), w.q) and np.array_equal(th.cpu().numpy(), w.theta)
+    ctx.close()
+
+
+def test_ab2_steps_match_oracle(rb):
+    import torch
+    name = "two_spheres_16x16x32"
+    w = sem_configs()[name]
+    g = oracle_grid(w)
+    tol, kT, dt, seed = 1e-11, 1.0, 0.05, 41
+    ctx = lib_context(rb, w, tol=tol, precond_fp32=1, max_iter=600)
+    q, th = dev(w.q), dev(w.theta)
+    prev = torch.empty((w.nb, 6), dtype=torch.float64, device="cuda")
+    U = torch.empty_like(prev)
+    qo, tho, po = w.q.copy(), w.theta.copy(), None
+    for k in range(2):
+        info = rb.rbfib_sem_ab2_step(ctx, q, th, _gpu_forces(rb, ctx, q, th, w.nb), kT, dt, seed, k, prev, k > 0, U,
+                                     allow=())
+        torch.cuda.synchronize()
+        Fo = body_forces(g, qo, tho, w.r_ref, w.offsets, PHI0, DW, BW, FC)
+        ref, po = sem.sem_ab2_step(g, w.r_ref, w.offsets, qo, tho, Fo, kT, dt, seed, k, U_det_prev=po, tol=1e-12)
+        assert ref.accepted and info[0].status == 0
+        err = np.abs(U.cpu().numpy() - ref.U).max() / np.abs(ref.U).max()
+        print("ab2 step", k, "iters", info[0].iters, "U_c rel err %.3e" % err, flush=True)
+        assert err < 1e-6
+        assert np.abs(prev.cpu().numpy() - po).max() <= 1e-6 * np.abs(po).max()
+        # continue both from the oracle's configuration so the steps stay comparable
+        qo, tho = ref.q, ref.theta
+        q.copy_(dev(qo))
+        th.copy_(dev(tho))
+    ctx.close()
+
+
+def test_ab2_second_order_deterministic(rb):
+    import torch
+    w = _settling_case()
+    T = 4.0
+    ctx = lib_context(rb, w, tol=1e-12, precond_fp32=0, max_iter=600)
+
+    def run(n):
+        q, th = dev(w.q), dev(w.theta)
+        prev = torch.empty((1, 6), dtype=torch.float64, device="cuda")
+        for k in range(n):
+            rb.rbfib_sem_ab2_step(ctx, q, th, _gpu_forces(rb, ctx, q, th, 1), 0.0, T / n, 1, k, prev, k > 0, allow=())
+        torch.cuda.synchronize()
+        return q.cpu().numpy(), th.cpu().numpy()
+
+    def d(a, b):
+        return np.abs(a[0] - b[0]).max() + np.abs(B.rotation_matrices(a[1]) - B.rotation_matrices(b[1])).max()
+
+    Q = [run(n) for n in (4, 8, 16)]
+    ratio = d(Q[0], Q[1]) / d(Q[1], Q[2])
+    print("ab2 ratio %.3f" % ratio, flush=True)
+    assert 3.2 < ratio < 5.0
     ctx.close()
