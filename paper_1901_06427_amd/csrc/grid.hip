@@ -105,64 +105,121 @@ __device__ __forceinline__ void ld_pair(const float *q, double &a, double &b) {
 // pressure pairs move as one load each (x in FP64 or FP32, the preconditioned
 // vectors of an FP32 preconditioner), the x neighbours outside the pair as scalars;
 // the y and z rules are shared by the pair.  The output is FP64, 16-byte stores.
+//
+// Every gather is issued unconditionally (a neighbour a boundary rule ignores is
+// read at a safe offset, the cell itself), and the raw values pass through an empty
+// asm statement before the rules select among them.  Without that the compiler
+// moves each load whose value some rule discards into a branch, where it waits for
+// its data alone: the thread's twenty-odd gathers then run one after another.
+template <typename TX>
+__device__ __forceinline__ void ld_raw2(const TX *q, TX &a, TX &b);
+template <>
+__device__ __forceinline__ void ld_raw2<double>(const double *q, double &a, double &b) {
+    const double2 v = *reinterpret_cast<const double2 *>(q);
+    a = v.x;
+    b = v.y;
+}
+template <>
+__device__ __forceinline__ void ld_raw2<float>(const float *q, float &a, float &b) {
+    const float2 v = *reinterpret_cast<const float2 *>(q);
+    a = v.x;
+    b = v.y;
+}
+
+// An offset the compiler cannot see through: a neighbour a rule ignores is read at
+// offset 0 (the cell itself), and a visible 0 lets the compiler reuse the cell's own
+// load under a branch instead of issuing the gather.
+__device__ __forceinline__ int opaque(int x) {
+    asm volatile("" : "+v"(x));
+    return x;
+}
+
+template <typename TX>
+__device__ __forceinline__ void keep12(TX r[12]) {
+    asm volatile("" : "+v"(r[0]), "+v"(r[1]), "+v"(r[2]), "+v"(r[3]), "+v"(r[4]), "+v"(r[5]), "+v"(r[6]),
+                 "+v"(r[7]), "+v"(r[8]), "+v"(r[9]), "+v"(r[10]), "+v"(r[11]));
+}
+
 template <typename TX>
 __device__ __forceinline__ void apply_row2(const RepDev &R, const BlockEnt &be, const TX *__restrict__ xr,
                                            double *__restrict__ yr) {
     const long long g0 = be.start + 2LL * threadIdx.x;
     if (g0 >= R.N) return;
-    const int lin = (int)g0, N = (int)R.N, n0 = R.n[0];
+    // the grid's sizes and rules, read once (the rules below would otherwise read them
+    // lazily, each under its own branch)
+    int nn[3] = {R.n[0], R.n[1], R.n[2]}, bcc[3] = {R.bc[0], R.bc[1], R.bc[2]};
+    asm volatile("" : "+v"(nn[0]), "+v"(nn[1]), "+v"(nn[2]), "+v"(bcc[0]), "+v"(bcc[1]), "+v"(bcc[2]));
+    const int lin = (int)g0, N = (int)R.N, n0 = nn[0];
     int idx[3];
     unlin(lin, R, idx);
-    const int st[3] = {1, R.n[0], R.n[0] * R.n[1]};
+    const int st[3] = {1, nn[0], nn[0] * nn[1]};
     const TX *p = xr + 3LL * N;
-    double self[2][3], nb[2][3][6], pm[2][3];
     int kd[2][3][6];
-    bool pin[2][3];
+    // raw[c]: self pair, -y pair, +y pair, -z pair, +z pair, -x and +x beyond the pair;
+    // raw[3]: the pressure pair, its -x value, -y pair, -z pair (one slot unused)
+    TX raw[4][12];
+    const int xm = idx[0] == 0 ? n0 - 1 : -1;                        // -x of the first cell
+    const int xp = 1 + (idx[0] + 1 == n0 - 1 ? -(n0 - 1) : 1);      // +x of the second cell
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
         const TX *u = xr + (long long)c * N;
-        double spx, spy;
-        ld_pair(u + lin, spx, spy);
+        ld_raw2<TX>(u + lin, raw[c][0], raw[c][1]);
+#pragma unroll
+        for (int a = 1; a < 3; ++a) {
+            const int km = nbr_kind(idx[a], -1, nn[a], bcc[a], a, c);
+            const int kp = nbr_kind(idx[a], +1, nn[a], bcc[a], a, c);
+            const int om = opaque(km ? 0 : (idx[a] == 0 ? (nn[a] - 1) * st[a] : -st[a]));
+            const int op = opaque(kp ? 0 : (idx[a] == nn[a] - 1 ? -(nn[a] - 1) * st[a] : st[a]));
+            ld_raw2<TX>(u + lin + om, raw[c][4 * a - 2], raw[c][4 * a - 1]);
+            ld_raw2<TX>(u + lin + op, raw[c][4 * a], raw[c][4 * a + 1]);
+            kd[0][c][2 * a] = kd[1][c][2 * a] = km;
+            kd[0][c][2 * a + 1] = kd[1][c][2 * a + 1] = kp;
+        }
+        raw[c][10] = u[lin + xm];
+        raw[c][11] = u[lin + xp];
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            kd[q][c][0] = nbr_kind(idx[0] + q, -1, n0, bcc[0], 0, c);
+            kd[q][c][1] = nbr_kind(idx[0] + q, +1, n0, bcc[0], 0, c);
+        }
+    }
+    ld_raw2<TX>(p + lin, raw[3][0], raw[3][1]);
+    raw[3][2] = p[lin + (idx[0] > 0 ? -1 : n0 - 1)];
+    ld_raw2<TX>(p + lin + (idx[1] > 0 ? -st[1] : (nn[1] - 1) * st[1]), raw[3][3], raw[3][4]);
+    ld_raw2<TX>(p + lin + (idx[2] > 0 ? -st[2] : (nn[2] - 1) * st[2]), raw[3][5], raw[3][6]);
+    raw[3][7] = raw[3][8] = raw[3][9] = raw[3][10] = raw[3][11] = (TX)0;
+#pragma unroll
+    for (int g = 0; g < 4; ++g) keep12<TX>(raw[g]);
+    double self[2][3], nb[2][3][6], pm[2][3];
+    bool pin[2][3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const double spx = (double)raw[c][0], spy = (double)raw[c][1];
         self[0][c] = spx;
         self[1][c] = spy;
 #pragma unroll
         for (int a = 1; a < 3; ++a) {
-            const int km = nbr_kind(idx[a], -1, R.n[a], R.bc[a], a, c);
-            const int kp = nbr_kind(idx[a], +1, R.n[a], R.bc[a], a, c);
-            const int om = km ? 0 : (idx[a] == 0 ? (R.n[a] - 1) * st[a] : -st[a]);
-            const int op = kp ? 0 : (idx[a] == R.n[a] - 1 ? -(R.n[a] - 1) * st[a] : st[a]);
-            double vmx, vmy, vpx, vpy;
-            ld_pair(u + lin + om, vmx, vmy);
-            ld_pair(u + lin + op, vpx, vpy);
-            kd[0][c][2 * a] = kd[1][c][2 * a] = km;
-            kd[0][c][2 * a + 1] = kd[1][c][2 * a + 1] = kp;
-            nb[0][c][2 * a] = vmx;
-            nb[1][c][2 * a] = vmy;
-            nb[0][c][2 * a + 1] = vpx;
-            nb[1][c][2 * a + 1] = vpy;
-        }
-#pragma unroll
-        for (int q = 0; q < 2; ++q) {
-            kd[q][c][0] = nbr_kind(idx[0] + q, -1, n0, R.bc[0], 0, c);
-            kd[q][c][1] = nbr_kind(idx[0] + q, +1, n0, R.bc[0], 0, c);
+            nb[0][c][2 * a] = (double)raw[c][4 * a - 2];
+            nb[1][c][2 * a] = (double)raw[c][4 * a - 1];
+            nb[0][c][2 * a + 1] = (double)raw[c][4 * a];
+            nb[1][c][2 * a + 1] = (double)raw[c][4 * a + 1];
         }
         // x neighbours: inside the pair, or one cell beyond it (wrapped when periodic)
-        nb[0][c][0] = kd[0][c][0] ? spx : (double)u[lin + (idx[0] == 0 ? n0 - 1 : -1)];
+        nb[0][c][0] = kd[0][c][0] ? spx : (double)raw[c][10];
         nb[0][c][1] = spy;
         nb[1][c][0] = spx;
-        nb[1][c][1] = kd[1][c][1] ? spy : (double)u[lin + 1 + (idx[0] + 1 == n0 - 1 ? -(n0 - 1) : 1)];
-        // pressure at -e_c
-        if (c == 0) {
-            pm[0][0] = (double)p[lin + (idx[0] > 0 ? -1 : n0 - 1)];
-            pm[1][0] = (double)p[lin];
-        } else {
-            ld_pair(p + lin + (idx[c] > 0 ? -st[c] : (R.n[c] - 1) * st[c]), pm[0][c], pm[1][c]);
-        }
-        pin[0][c] = R.bc[c] != RBFIB_PERIODIC && (c == 0 ? idx[0] : idx[c]) == 0;
-        pin[1][c] = R.bc[c] != RBFIB_PERIODIC && (c == 0 ? idx[0] + 1 : idx[c]) == 0;
+        nb[1][c][1] = kd[1][c][1] ? spy : (double)raw[c][11];
+        pin[0][c] = bcc[c] != RBFIB_PERIODIC && (c == 0 ? idx[0] : idx[c]) == 0;
+        pin[1][c] = bcc[c] != RBFIB_PERIODIC && (c == 0 ? idx[0] + 1 : idx[c]) == 0;
     }
-    double pc0, pc1;
-    ld_pair(p + lin, pc0, pc1);
+    // pressure at -e_c
+    pm[0][0] = (double)raw[3][2];
+    pm[1][0] = (double)raw[3][0];
+    pm[0][1] = (double)raw[3][3];
+    pm[1][1] = (double)raw[3][4];
+    pm[0][2] = (double)raw[3][5];
+    pm[1][2] = (double)raw[3][6];
+    const double pc0 = (double)raw[3][0], pc1 = (double)raw[3][1];
     double o0[4], o1[4];
     apply_cell(R, self[0], nb[0], pm[0], pc0, kd[0], pin[0], o0);
     apply_cell(R, self[1], nb[1], pm[1], pc1, kd[1], pin[1], o1);
