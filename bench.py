@@ -232,7 +232,7 @@ def run_monolayer(steps, seed=2024):
     w = W.monolayer()
     out, U0 = {}, {}
     for fp32 in (1, 0):
-        ctx = lib_context(rb, [w], tol=w.tol, precond_fp32=fp32)
+        ctx = lib_context(rb, [w], tol=w.tol, precond_fp32=fp32, **({"mg_bottom": BOTTOM} if BOTTOM >= 0 else {}))
         q, th, FT = _dev(w.q), _dev(w.theta), _dev(w.FT)
         U = torch.empty((w.nb, 6), dtype=torch.float64, device="cuda")
         rb.rbfib_sem_step(ctx, q, th, FT, w.kT, w.dt, seed, 0, U)
@@ -485,6 +485,10 @@ def main():
                     help="blob radius of the body-block preconditioner, units of h (0: library default)")
     ap.add_argument("--batched-only", action="store_true",
                     help="only the batched ensemble launches (the command the graph-mode trace is taken on)")
+    ap.add_argument("--two-spheres-only", action="store_true",
+                    help="only the SEM steps of the 32x32x64 two-sphere box (its kernel trace)")
+    ap.add_argument("--monolayer-only", action="store_true",
+                    help="only the SEM steps of the 1024-sphere monolayer")
     ap.add_argument("--mg-fused", type=int, default=0, choices=(0, 1, 2),
                     help="multigrid level kernels: 0 separate (default), 1 fused where the level fills the "
                          "device, 2 fused on every level")
@@ -508,6 +512,21 @@ def main():
 
     cpu = None
     cb = None
+    if args.two_spheres_only or args.monolayer_only:
+        import workloads as W
+        out = {}
+        if args.two_spheres_only:
+            two = run_gpu([W.two_spheres()], args.two_spheres_steps, 2, fp32=1)
+            out["two_spheres"] = {"value": round(2 * two["steps"] / two["seconds"], 3), "unit": "mobility solves/s",
+                                  "ms_per_step": round(1e3 * two["seconds"] / two["steps"], 3),
+                                  "fgmres_iters_per_step": round(two["iters"] / two["steps"], 1),
+                                  "us_per_iter": round(1e6 * two["seconds"] / two["iters"], 1)}
+        if args.monolayer_only:
+            out["monolayer_1024"] = run_monolayer(max(1, args.monolayer_steps))
+        out["mg_bottom"] = BOTTOM
+        print(json.dumps(out), flush=True)
+        return
+
     if not args.no_cpu_baseline and not args.timing_only and not args.batched_only:
         cb = run_cpu_baseline(args.replicas, args.cpu_budget)
         cpu = {"value": round(2 * cb["steps"] / cb["seconds"], 4), "unit": "mobility solves/s",

@@ -973,15 +973,29 @@ void launch_coarse(Ctx &c, int lev, int c0, int nc, const T *b, T *x) {
 // and in the operation order of the separate kernels, so the result is the same
 // to the bit.  LDS: x_l and b_l for l = lb .. nlev-1, then one level-lb scratch
 // grid t for the Jacobi ping-pong and the residual.
-// Threads own (i, j) columns and march along k: the x and y boundary rules, the
-// x and y terms of the diagonal and the pinning in x and y are evaluated once per
-// column; consecutive lanes touch consecutive LDS words.
+// Work split of a pass: a level of n01 (i, j) columns is cut into S slices per
+// column (S = threads / columns on levels with fewer columns than threads, else 1),
+// slice s taking the planes s, s + S, ...; the x and y boundary rules, the x and y
+// terms of the diagonal and the pinning in x and y are evaluated once per column
+// slice.  Input and output grids share one LDS array, so the compiler cannot move
+// a load above an earlier store: a sweep therefore loads RB_BOTK planes of its
+// slice (clamped to the last plane, never out of the grid) before it stores any,
+// and the transfers load every point of their stencil before selecting the terms
+// that count.
+#define RB_BOTK 4
+
+__device__ __forceinline__ int bot_slices(int ncol) {
+    return ncol >= (int)blockDim.x ? 1 : (int)blockDim.x / ncol;
+}
+
 template <typename T, int MODE>
 __device__ __forceinline__ void bot_sweep(const RepDev &R, const LevDev &Lv, int comp, T s, T om,
                                           const T *xi, T *xo, const T *bb) {
     const int n0 = Lv.n[0], n1 = Lv.n[1], n2 = Lv.n[2], n01 = n0 * n1;
     const T ih0 = (T)Lv.inv_h2[0], ih1 = (T)Lv.inv_h2[1], ih2 = (T)Lv.inv_h2[2];
-    for (int col = threadIdx.x; col < n01; col += blockDim.x) {
+    const int S = bot_slices(n01);
+    for (int cs = threadIdx.x; cs < n01 * S; cs += blockDim.x) {
+        const int sl = cs / n01, col = cs - sl * n01;
         const int j = col / n0, i = col - j * n0;
         const int kxm = nbr_kind(i, -1, n0, R.bc[0], 0, comp), kxp = nbr_kind(i, +1, n0, R.bc[0], 0, comp);
         const int kym = nbr_kind(j, -1, n1, R.bc[1], 1, comp), kyp = nbr_kind(j, +1, n1, R.bc[1], 1, comp);
@@ -993,25 +1007,50 @@ __device__ __forceinline__ void bot_sweep(const RepDev &R, const LevDev &Lv, int
                            fmad(diag_axis<T>(comp, 0, i, n0, R.bc[0]), ih0, (T)0));
         const bool pin_xy = (comp == 0 && R.bc[0] != RBFIB_PERIODIC && i == 0) ||
                             (comp == 1 && R.bc[1] != RBFIB_PERIODIC && j == 0);
-        for (int k = 0; k < n2; ++k) {
-            const int lin = col + k * n01;
-            const T d = fmad(diag_axis<T>(comp, 2, k, n2, R.bc[2]), ih2, dxy);
-            const T w = jacobi_w<T>(om, s, d);
-            T y;
-            if (MODE == MG_FIRST) {
-                y = bb[lin] * w;
-            } else {
-                const int kzm = nbr_kind(k, -1, n2, R.bc[2], 2, comp), kzp = nbr_kind(k, +1, n2, R.bc[2], 2, comp);
-                const int ozm = kzm ? 0 : (k == 0 ? (n2 - 1) * n01 : -n01);
-                const int ozp = kzp ? 0 : (k == n2 - 1 ? -(n2 - 1) * n01 : n01);
-                const T xv = xi[lin];
-                T acc = lap_acc<T>(pick<T>(kxp, xi[lin + oxp], xv), xv, pick<T>(kxm, xi[lin + oxm], xv), ih0, (T)0);
-                acc = lap_acc<T>(pick<T>(kyp, xi[lin + oyp], xv), xv, pick<T>(kym, xi[lin + oym], xv), ih1, acc);
-                acc = lap_acc<T>(pick<T>(kzp, xi[lin + ozp], xv), xv, pick<T>(kzm, xi[lin + ozm], xv), ih2, acc);
-                y = MODE == MG_RESID ? mg_residual<T>(bb[lin], s, acc) : jacobi_step<T>(xv, bb[lin], s, acc, w);
+        for (int k0 = sl; k0 < n2; k0 += RB_BOTK * S) {
+            T bv[RB_BOTK], xv[RB_BOTK], vxp[RB_BOTK], vxm[RB_BOTK], vyp[RB_BOTK], vym[RB_BOTK], vzp[RB_BOTK],
+                vzm[RB_BOTK];
+            int kzm[RB_BOTK], kzp[RB_BOTK];
+#pragma unroll
+            for (int u = 0; u < RB_BOTK; ++u) {
+                const int k = min(k0 + u * S, n2 - 1);
+                const int lin = col + k * n01;
+                bv[u] = bb[lin];
+                if (MODE != MG_FIRST) {
+                    kzm[u] = nbr_kind(k, -1, n2, R.bc[2], 2, comp);
+                    kzp[u] = nbr_kind(k, +1, n2, R.bc[2], 2, comp);
+                    const int ozm = kzm[u] ? 0 : (k == 0 ? (n2 - 1) * n01 : -n01);
+                    const int ozp = kzp[u] ? 0 : (k == n2 - 1 ? -(n2 - 1) * n01 : n01);
+                    xv[u] = xi[lin];
+                    vxp[u] = xi[lin + oxp];
+                    vxm[u] = xi[lin + oxm];
+                    vyp[u] = xi[lin + oyp];
+                    vym[u] = xi[lin + oym];
+                    vzp[u] = xi[lin + ozp];
+                    vzm[u] = xi[lin + ozm];
+                }
             }
-            const bool pin = pin_xy || (comp == 2 && R.bc[2] != RBFIB_PERIODIC && k == 0);
-            xo[lin] = pin ? (T)0 : y;
+#pragma unroll
+            for (int u = 0; u < RB_BOTK; ++u) {
+                const int k = k0 + u * S;
+                if (k < n2) {
+                    const int lin = col + k * n01;
+                    const T d = fmad(diag_axis<T>(comp, 2, k, n2, R.bc[2]), ih2, dxy);
+                    const T w = jacobi_w<T>(om, s, d);
+                    T y;
+                    if (MODE == MG_FIRST) {
+                        y = bv[u] * w;
+                    } else {
+                        T acc = lap_acc<T>(pick<T>(kxp, vxp[u], xv[u]), xv[u], pick<T>(kxm, vxm[u], xv[u]), ih0, (T)0);
+                        acc = lap_acc<T>(pick<T>(kyp, vyp[u], xv[u]), xv[u], pick<T>(kym, vym[u], xv[u]), ih1, acc);
+                        acc = lap_acc<T>(pick<T>(kzp[u], vzp[u], xv[u]), xv[u], pick<T>(kzm[u], vzm[u], xv[u]), ih2,
+                                         acc);
+                        y = MODE == MG_RESID ? mg_residual<T>(bv[u], s, acc) : jacobi_step<T>(xv[u], bv[u], s, acc, w);
+                    }
+                    const bool pin = pin_xy || (comp == 2 && R.bc[2] != RBFIB_PERIODIC && k == 0);
+                    xo[lin] = pin ? (T)0 : y;
+                }
+            }
         }
     }
 }
@@ -1029,15 +1068,26 @@ __device__ __forceinline__ void bot_restrict(const RepDev &R, const LevDev &F, c
     }
     const int f01 = F.n[0] * F.n[1], c01 = C.n[0] * C.n[1];
     auto wrap = [](int f, int n) { return f < 0 ? f + n : (f >= n ? f - n : f); };
-    for (int col = threadIdx.x; col < c01; col += blockDim.x) {
+    const int S = bot_slices(c01);
+    for (int cs = threadIdx.x; cs < c01 * S; cs += blockDim.x) {
+        const int sl = cs / c01, col = cs - sl * c01;
         const int cj = col / C.n[0], cix = col - cj * C.n[0];
-        for (int ck = 0; ck < C.n[2]; ++ck) {
+        for (int ck = sl; ck < C.n[2]; ck += S) {
             const int lin = col + ck * c01;
             const int ci[3] = {cix, cj, ck};
-            if (pinned(comp, ci, R.bc)) { bc[lin] = (T)0; continue; }
             int fb[3];
 #pragma unroll
             for (int a = 0; a < 3; ++a) fb[a] = crs[a] ? 2 * ci[a] - (face[a] ? 1 : 0) : ci[a];
+            // every window point lies in the fine grid after wrapping: load all 27
+            T v[27];
+#pragma unroll
+            for (int kk = 0; kk < 3; ++kk)
+#pragma unroll
+                for (int jj = 0; jj < 3; ++jj)
+#pragma unroll
+                    for (int ii = 0; ii < 3; ++ii)
+                        v[ii + 3 * jj + 9 * kk] = rf[wrap(fb[0] + ii, F.n[0]) + F.n[0] * wrap(fb[1] + jj, F.n[1]) +
+                                                     f01 * wrap(fb[2] + kk, F.n[2])];
             T acc = (T)0;
 #pragma unroll
             for (int kk = 0; kk < 3; ++kk)
@@ -1049,25 +1099,52 @@ __device__ __forceinline__ void bot_restrict(const RepDev &R, const LevDev &F, c
                             acc = fmad(restrict_weight<T>(crs[0], face[0], ii) *
                                            restrict_weight<T>(crs[1], face[1], jj) *
                                            restrict_weight<T>(crs[2], face[2], kk),
-                                       rf[wrap(fb[0] + ii, F.n[0]) + F.n[0] * wrap(fb[1] + jj, F.n[1]) +
-                                          f01 * wrap(fb[2] + kk, F.n[2])],
-                                       acc);
-            bc[lin] = acc;
+                                       v[ii + 3 * jj + 9 * kk], acc);
+            bc[lin] = pinned(comp, ci, R.bc) ? (T)0 : acc;
         }
     }
 }
 
-// x_f += P x_c over the fine level, by columns
+// x_f += P x_c over the fine level: the eight coarse values of each point are
+// loaded at valid indices and the terms prolong_at would sum are added in its order
 template <typename T>
 __device__ __forceinline__ void bot_prolong(const RepDev &R, const LevDev &F, const LevDev &C, int comp,
                                             const T *xc, T *xf) {
     const int f01 = F.n[0] * F.n[1];
-    for (int col = threadIdx.x; col < f01; col += blockDim.x) {
+    const int c01 = C.n[0] * C.n[1];
+    const int S = bot_slices(f01);
+    for (int cs = threadIdx.x; cs < f01 * S; cs += blockDim.x) {
+        const int sl = cs / f01, col = cs - sl * f01;
         const int fj = col / F.n[0], fix = col - fj * F.n[0];
-        for (int fk = 0; fk < F.n[2]; ++fk) {
+        const ProlongAxis<T> px = prolong_axis<T>(fix, F.n[0], C.n[0], R.bc[0], comp == 0, comp);
+        const ProlongAxis<T> py = prolong_axis<T>(fj, F.n[1], C.n[1], R.bc[1], comp == 1, comp);
+        const int xi1 = px.cnt > 1 ? px.i1 : px.i0, yi1 = py.cnt > 1 ? py.i1 : py.i0;
+        for (int fk = sl; fk < F.n[2]; fk += S) {
             const int fi[3] = {fix, fj, fk};
-            if (pinned(comp, fi, R.bc)) continue;
-            xf[col + fk * f01] += prolong_at<T>(R, F, C, comp, fi, xc);
+            const ProlongAxis<T> pz = prolong_axis<T>(fk, F.n[2], C.n[2], R.bc[2], comp == 2, comp);
+            const int zi1 = pz.cnt > 1 ? pz.i1 : pz.i0;
+            T v[8];
+#pragma unroll
+            for (int kk = 0; kk < 2; ++kk)
+#pragma unroll
+                for (int jj = 0; jj < 2; ++jj)
+#pragma unroll
+                    for (int ii = 0; ii < 2; ++ii)
+                        v[ii + 2 * jj + 4 * kk] = xc[(ii ? xi1 : px.i0) + C.n[0] * (jj ? yi1 : py.i0) +
+                                                     c01 * (kk ? zi1 : pz.i0)];
+            const int lin = col + fk * f01;
+            const T old = xf[lin];
+            T acc = (T)0;
+#pragma unroll
+            for (int kk = 0; kk < 2; ++kk)
+#pragma unroll
+                for (int jj = 0; jj < 2; ++jj)
+#pragma unroll
+                    for (int ii = 0; ii < 2; ++ii)
+                        if (kk < pz.cnt && jj < py.cnt && ii < px.cnt)
+                            acc = fmad((ii ? px.w1 : px.w0) * (jj ? py.w1 : py.w0) * (kk ? pz.w1 : pz.w0),
+                                       v[ii + 2 * jj + 4 * kk], acc);
+            if (!pinned(comp, fi, R.bc)) xf[lin] = old + acc;
         }
     }
 }
