@@ -146,7 +146,7 @@ typedef struct {
                                /*    in one workgroup per (replica, component) with  */
                                /*    every grid in LDS and the same values as the    */
                                /*    separate kernels; 0: separate kernels on every  */
-                               /*    level; fixed at creation (8)                    */
+                               /*    level; fixed at creation (32)                   */
     double mg_cheby;           /* > 0: sweep k of nu has weight 1 / lambda_k, the    */
                                /*    roots of the degree-nu Chebyshev polynomial on  */
                                /*    [mg_cheby, 2]; 0: every sweep mg_omega (0.27)   */

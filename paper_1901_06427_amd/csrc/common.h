@@ -35,7 +35,7 @@
                                // Krylov dots, Krylov update, spreading of the apply
 // LDS-resident bottom of the V-cycle: workgroup size and the largest LDS budget
 // per workgroup an option may ask for
-#define MGB_THREADS 256
+#define MGB_THREADS 512
 #define MGB_LDS (64 * 1024)
 // most damped-Jacobi sweeps per level and direction
 #define RB_MAXSWEEP 16

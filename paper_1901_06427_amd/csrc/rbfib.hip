@@ -1271,7 +1271,7 @@ void rbfib_default_opts(rbfib_opts *o) {
     o->check_every = 5;
     o->use_graphs = 1;
     o->mg_fused = 0;
-    o->mg_bottom = 8;
+    o->mg_bottom = 32;
     o->mg_cheby = 0.27;
     o->krylov_s = 2;
     o->mg_first2 = 1;
