@@ -10,7 +10,8 @@ one unconstrained Stokes solve per replica, each to a relative residual of
 and captured HIP graphs.  "plain_fp64" solves the same replicas one at a time
 with the FP64 preconditioner on the same GPU; "two_spheres" is the 32x32x64
 two-sphere box of the paper's tight-cavity example, one replica;
-"monolayer_1024" times SEM steps of the 1024-sphere sliding-wall monolayer with
+"single_sphere_32" times deterministic mobility solves of one sphere in a walled
+32^3 box to 1e-8 with both preconditioner precisions; "monolayer_1024" times SEM steps of the 1024-sphere sliding-wall monolayer with
 the FP32 and the FP64 multigrid; "adjoint_128" times the forward solve and the
 vector-Jacobian product on the 128^3 box with 64 spheres.
 
@@ -255,6 +256,37 @@ def run_monolayer(steps, seed=2024):
     return out
 
 
+def run_single_sphere(solves=20, tol=1e-8):
+    """One 42-marker sphere in a walled 32^3 box: deterministic mobility solves
+    (forces and torques only) to tol, with the FP32 multigrid and with the all-FP64
+    preconditioner; two untimed solves first."""
+    import torch
+    import paper_1901_06427_amd as rb
+    import workloads as W
+    w = W.single_sphere()
+    out = {"grid": list(w.n), "bodies": w.nb, "markers": w.nm, "tol": tol, "timed_solves": solves}
+    for fp32 in (1, 0):
+        ctx = lib_context(rb, [w], tol=tol, precond_fp32=fp32)
+        q, th, FT = _dev(w.q), _dev(w.theta), _dev(w.FT)
+        U = torch.empty((w.nb, 6), dtype=torch.float64, device="cuda")
+        for _ in range(2):
+            rb.rbfib_solve_mobility(ctx, q, th, FT, U)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        iters, res = 0, 0.0
+        for _ in range(solves):
+            info = rb.rbfib_solve_mobility(ctx, q, th, FT, U)
+            iters += info[0].iters
+            res = max(res, info[0].rel_residual)
+        torch.cuda.synchronize()
+        sec = (time.perf_counter() - t0) / solves
+        ctx.close()
+        out["fp32_pc" if fp32 else "fp64_pc"] = {"solves_per_s": round(1.0 / sec, 2), "ms_per_solve": round(1e3 * sec, 3),
+                                                 "fgmres_iters_per_solve": round(iters / solves, 1),
+                                                 "max_rel_residual": res}
+    return out
+
+
 def run_adjoint(tol=1e-10, reps=2):
     """The differentiated solve: 64 spheres of 42 markers in a 128^3 walled box; the
     forward mobility solve and the vector-Jacobian product (forward re-solve plus the
@@ -489,6 +521,8 @@ def main():
                     help="only the SEM steps of the 32x32x64 two-sphere box (its kernel trace)")
     ap.add_argument("--monolayer-only", action="store_true",
                     help="only the SEM steps of the 1024-sphere monolayer")
+    ap.add_argument("--single-sphere-only", action="store_true",
+                    help="only the mobility solves of one sphere in a 32^3 box")
     ap.add_argument("--mg-fused", type=int, default=0, choices=(0, 1, 2),
                     help="multigrid level kernels: 0 separate (default), 1 fused where the level fills the "
                          "device, 2 fused on every level")
@@ -512,9 +546,11 @@ def main():
 
     cpu = None
     cb = None
-    if args.two_spheres_only or args.monolayer_only:
+    if args.two_spheres_only or args.monolayer_only or args.single_sphere_only:
         import workloads as W
         out = {}
+        if args.single_sphere_only:
+            out["single_sphere_32"] = run_single_sphere()
         if args.two_spheres_only:
             two = run_gpu([W.two_spheres()], args.two_spheres_steps, 2, fp32=1)
             out["two_spheres"] = {"value": round(2 * two["steps"] / two["seconds"], 3), "unit": "mobility solves/s",
@@ -599,6 +635,9 @@ def main():
     two_value = 2 * two["steps"] / two["seconds"]
     log("two spheres: %.1f solves/s" % two_value)
 
+    single = run_single_sphere()
+    log("single sphere 32^3: %.1f solves/s (fp32 pc), %.1f (fp64 pc)" % (
+        single["fp32_pc"]["solves_per_s"], single["fp64_pc"]["solves_per_s"]))
     mono = run_monolayer(args.monolayer_steps) if args.monolayer_steps > 0 else None
     if mono:
         log("monolayer: fp32-pc %.1f ms/step, fp64-pc %.1f ms/step, U rel diff %.2e" % (
@@ -639,6 +678,7 @@ def main():
         "two_spheres": {"value": round(two_value, 3), "unit": "mobility solves/s", "grid": [32, 32, 64],
                         "ms_per_step": round(1e3 * two["seconds"] / two["steps"], 3),
                         "fgmres_iters_per_step": round(two["iters"] / two["steps"], 1)},
+        "single_sphere_32": single,
         "monolayer_1024": mono,
         "adjoint_128": adj,
         "roofline": roofline,
