@@ -193,9 +193,7 @@ def run_gpu(ws, steps, warmup, fp32, seed=2024, timing=False, graphs=True, tol=N
     t1 = time.perf_counter()
     stats = {}
     if timing:
-        for which, name in ((0, "mac_saddle_apply"), (1, "mg_smooth_level0"), (2, "mg_down_level0"),
-                            (3, "mg_up_level0"), (4, "krylov_dots"), (5, "krylov_update"),
-                            (6, "spread")):
+        for which, name in TIMED_CLASSES:
             avg_ms, nbytes, launches = rb.rbfib_kernel_stats(ctx, which)
             if launches:
                 stats[name] = (avg_ms, nbytes, launches)
@@ -219,6 +217,26 @@ def run_plain(ws, warmup=1, seed=2024, tol=None):
 def _dev(a):
     import torch
     return torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64).cuda()
+
+
+TIMED_CLASSES = ((0, "mac_saddle_apply"), (1, "mg_smooth_level0"), (2, "mg_down_level0"), (3, "mg_up_level0"),
+                 (4, "krylov_dots"), (5, "krylov_update"), (6, "spread"))
+
+
+def class_rates(rb, ctx, run):
+    """Per-class launches, mean duration and algorithmic GB/s (HIP events inside the
+    library, eager context) over one call of run()."""
+    import torch
+    rb.rbfib_enable_timing(ctx, True)
+    run()
+    torch.cuda.synchronize()
+    out = {}
+    for which, name in TIMED_CLASSES:
+        avg_ms, nbytes, launches = rb.rbfib_kernel_stats(ctx, which)
+        if launches:
+            out[name] = {"avg_us": round(avg_ms * 1e3, 2), "launches": launches,
+                         "GB/s": round(nbytes / (avg_ms * 1e-3) / 1e9, 1) if avg_ms > 0 else 0.0}
+    return out
 
 
 def run_monolayer(steps, seed=2024):
@@ -250,6 +268,13 @@ def run_monolayer(steps, seed=2024):
         out["fp32_pc" if fp32 else "fp64_pc"] = {"ms_per_step": round(1e3 * sec, 2), "solves_per_s": round(2 / sec, 3),
                                                  "fgmres_iters_per_step": round(iters / steps, 1)}
     d = float(np.abs(U0[1] - U0[0]).max() / np.abs(U0[0]).max())
+    # kernel-class rates of one eager SEM step with the FP32 multigrid
+    ctx = lib_context(rb, [w], tol=w.tol, precond_fp32=1, use_graphs=0,
+                      **({"mg_bottom": BOTTOM} if BOTTOM >= 0 else {}))
+    q, th, FT = _dev(w.q), _dev(w.theta), _dev(w.FT)
+    U = torch.empty((w.nb, 6), dtype=torch.float64, device="cuda")
+    out["kernels_fp32_pc"] = class_rates(rb, ctx, lambda: rb.rbfib_sem_step(ctx, q, th, FT, w.kT, w.dt, seed, 1, U))
+    ctx.close()
     out.update({"grid": list(w.n), "bodies": w.nb, "markers": w.nm, "tol": w.tol, "timed_steps": steps,
                 "U_rel_diff_fp32_vs_fp64_pc": d,
                 "speedup_fp32_pc": round(out["fp64_pc"]["ms_per_step"] / out["fp32_pc"]["ms_per_step"], 3)})
@@ -314,10 +339,18 @@ def run_adjoint(tol=1e-10, reps=2):
         best_f, best_b = min(best_f, t1 - t0), min(best_b, t2 - t1)
         it_f, it_b = inf[0].iters, infb[0].iters
     ctx.close()
+    # kernel-class rates of one eager forward solve plus vector-Jacobian product
+    ctx = lib_context(rb, [w], tol=tol, precond_fp32=1, use_graphs=0)
+
+    def fwd_bwd():
+        rb.rbfib_solve_mobility(ctx, q, th, FT, U, include_bc=False, allow=())
+        rb.rbfib_mobility_vjp(ctx, q, th, FT, Ubar, dFT, dq, dphi, allow=())
+    rates = class_rates(rb, ctx, fwd_bwd)
+    ctx.close()
     return {"grid": list(w.n), "bodies": w.nb, "markers": w.nm, "tol": tol,
             "forward_ms": round(1e3 * best_f, 2), "forward_iters": it_f,
             "vjp_ms": round(1e3 * best_b, 2), "vjp_iters": it_b,
-            "forward_plus_backward_ms": round(1e3 * (best_f + best_b), 2)}
+            "forward_plus_backward_ms": round(1e3 * (best_f + best_b), 2), "kernels": rates}
 
 
 # ----------------------------------------------------------------- CPU oracle baseline
@@ -523,6 +556,8 @@ def main():
                     help="only the SEM steps of the 1024-sphere monolayer")
     ap.add_argument("--single-sphere-only", action="store_true",
                     help="only the mobility solves of one sphere in a 32^3 box")
+    ap.add_argument("--adjoint-only", action="store_true",
+                    help="only the 128^3 differentiated solve")
     ap.add_argument("--mg-fused", type=int, default=0, choices=(0, 1, 2),
                     help="multigrid level kernels: 0 separate (default), 1 fused where the level fills the "
                          "device, 2 fused on every level")
@@ -546,7 +581,7 @@ def main():
 
     cpu = None
     cb = None
-    if args.two_spheres_only or args.monolayer_only or args.single_sphere_only:
+    if args.two_spheres_only or args.monolayer_only or args.single_sphere_only or args.adjoint_only:
         import workloads as W
         out = {}
         if args.single_sphere_only:
@@ -559,6 +594,8 @@ def main():
                                   "us_per_iter": round(1e6 * two["seconds"] / two["iters"], 1)}
         if args.monolayer_only:
             out["monolayer_1024"] = run_monolayer(max(1, args.monolayer_steps))
+        if args.adjoint_only:
+            out["adjoint_128"] = run_adjoint()
         out["mg_bottom"] = BOTTOM
         print(json.dumps(out), flush=True)
         return
