@@ -155,9 +155,9 @@ typedef struct {
                                /*    basis (tol >= 1e-9; a shorter last block runs   */
                                /*    single steps) (2)                               */
     int mg_first2;             /* 1: the first two sweeps of each down pass as one   */
-                               /*    kernel on FP32 levels whose rows are a multiple */
-                               /*    of 4 (b read once, the first iterate never      */
-                               /*    stored; same values as two sweeps); 0: two (1)  */
+                               /*    kernel on every level (b read once, the first   */
+                               /*    iterate never stored; same values as two        */
+                               /*    sweeps); 0: two launches (1)                    */
     int kernel;                /* width of the delta kernel of S and J (Sec. III.B), */
                                /*    fixed at creation: 4 = Peskin's 4-point         */
                                /*    function, 6 = the 6-point function of Bao,      */

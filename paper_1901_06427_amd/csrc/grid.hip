@@ -617,11 +617,62 @@ __device__ __forceinline__ void smooth_row4(const RepDev &R, const LevDev &Lv, c
     *reinterpret_cast<float4 *>(xo + lin) = make_float4(y4[0], y4[1], y4[2], y4[3]);
 }
 
+// One-point MG_FIRST2 (any precision, any level): the first iterate at the point is
+// b w1 and at each neighbour the second sweep reads (never a pinned one) b(q) w1(q),
+// with q's own diagonal formed in the first sweep's order; every value equals the
+// separate sweeps'.
+template <typename T>
+__device__ __forceinline__ T first2_point(const RepDev &R, const LevDev &Lv, int comp, int li, const int idx[3],
+                                          const T *__restrict__ bb, T s, T om1, T om2) {
+    const int st[3] = {1, Lv.n[0], Lv.n[0] * Lv.n[1]};
+    T da[3];
+    int km[3], kp[3], om[3], op[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        da[a] = diag_axis<T>(comp, a, idx[a], Lv.n[a], R.bc[a]);
+        km[a] = nbr_kind(idx[a], -1, Lv.n[a], R.bc[a], a, comp);
+        kp[a] = nbr_kind(idx[a], +1, Lv.n[a], R.bc[a], a, comp);
+        om[a] = km[a] ? 0 : (idx[a] == 0 ? (Lv.n[a] - 1) * st[a] : -st[a]);
+        op[a] = kp[a] ? 0 : (idx[a] == Lv.n[a] - 1 ? -(Lv.n[a] - 1) * st[a] : st[a]);
+    }
+    const T ih[3] = {(T)Lv.inv_h2[0], (T)Lv.inv_h2[1], (T)Lv.inv_h2[2]};
+    const T d = fmad(da[2], ih[2], fmad(da[1], ih[1], fmad(da[0], ih[0], (T)0)));
+    const T bp = bb[li];
+    T bq[6];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        bq[2 * a] = bb[li + om[a]];
+        bq[2 * a + 1] = bb[li + op[a]];
+    }
+    const T x1p = bp * jacobi_w<T>(om1, s, d);
+    T acc = (T)0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        T nbv[2];
+#pragma unroll
+        for (int dir = 0; dir < 2; ++dir) {
+            const int kind = dir ? kp[a] : km[a];
+            T x1q = x1p;
+            if (kind == 0) {
+                int qa = idx[a] + (dir ? 1 : -1);
+                qa = qa < 0 ? qa + Lv.n[a] : (qa >= Lv.n[a] ? qa - Lv.n[a] : qa);
+                T dd[3] = {da[0], da[1], da[2]};
+                dd[a] = diag_axis<T>(comp, a, qa, Lv.n[a], R.bc[a]);
+                const T dq = fmad(dd[2], ih[2], fmad(dd[1], ih[1], fmad(dd[0], ih[0], (T)0)));
+                x1q = bq[2 * a + dir] * jacobi_w<T>(om1, s, dq);
+            }
+            nbv[dir] = x1q;
+        }
+        acc = lap_acc<T>(pick<T>(kp[a], nbv[1], x1p), x1p, pick<T>(km[a], nbv[0], x1p), ih[a], acc);
+    }
+    return jacobi_step<T>(x1p, bp, s, acc, jacobi_w<T>(om2, s, d));
+}
+
 template <typename T, int NPT, int MODE>
 __global__ __launch_bounds__(RB_BLOCK) void k_smooth(const RepDev *reps, const LevDev *levs, const BlockEnt *tab,
                                                      int lev, int c0, const T *__restrict__ xin, T *__restrict__ xout,
                                                      const T *__restrict__ b, double omega,
-                                                     const int *__restrict__ mask) {
+                                                     const int *__restrict__ mask, double omega1) {
     const BlockEnt be = tab[xcd_block(blockIdx.x, gridDim.x)];
     if (mask && !mask[be.rep]) return;
     const int comp = c0 + blockIdx.y;
@@ -635,9 +686,22 @@ __global__ __launch_bounds__(RB_BLOCK) void k_smooth(const RepDev *reps, const L
     if constexpr (sizeof(T) == 4 && NPT == 4) {
         if (Lv.n[0] % 4 == 0) {    // uniform per block: every row splits into aligned groups of 4
             smooth_row4<MODE>(R, Lv, be, comp, (const float *)xi, (float *)xo, (const float *)bb, (float)s,
-                              (float)omega, (float)omega);
+                              (float)omega, (float)omega1);
             return;
         }
+    }
+    if constexpr (MODE == MG_FIRST2) {
+#pragma unroll
+        for (int t = 0; t < NPT; ++t) {
+            const long long l = be.start + threadIdx.x + (long long)t * RB_BLOCK;
+            if (l >= Lv.N) break;
+            const int li = (int)l;
+            int idx[3];
+            unlin(li, Lv, idx);
+            const T y = first2_point<T>(R, Lv, comp, li, idx, bb, s, (T)omega1, (T)omega);
+            xo[li] = pinned(comp, idx, R.bc) ? (T)0 : y;
+        }
+        return;
     }
     const int st[3] = {1, Lv.n[0], Lv.n[0] * Lv.n[1]};
     int lin[NPT], kinds[NPT];
@@ -712,25 +776,29 @@ __global__ __launch_bounds__(RB_BLOCK) void k_smooth_row4(const RepDev *reps, co
     smooth_row4<MODE>(R, Lv, be, comp, xin + base, xout + base, b + base, s, (float)omega, (float)omega1);
 }
 
+// omega1: the first sweep's weight of MG_FIRST2 (ignored by the other modes)
 template <typename T, int NPT, int MODE>
-static void launch_stencil(Ctx &c, int lev, int c0, int nc, const T *xin, T *xout, const T *b, double omega) {
+static void launch_stencil(Ctx &c, int lev, int c0, int nc, const T *xin, T *xout, const T *b, double omega,
+                           double omega1) {
     if constexpr (sizeof(T) == 4 && NPT == 4) {
         if (c.lev_row4[lev]) {
             hipLaunchKernelGGL(k_smooth_row4<MODE>, dim3(c.n_tab_lev[lev], nc), dim3(RB_BLOCK), 0, c.stream, c.d_reps,
                                c.d_levs, c.d_tab_lev[lev], lev, c0, (const float *)xin, (float *)xout,
-                               (const float *)b, omega, c.mask, omega);
+                               (const float *)b, omega, c.mask, omega1);
             return;
         }
     }
     hipLaunchKernelGGL((k_smooth<T, NPT, MODE>), dim3(c.n_tab_lev[lev], nc), dim3(RB_BLOCK), 0, c.stream, c.d_reps,
-                       c.d_levs, c.d_tab_lev[lev], lev, c0, xin, xout, b, omega, c.mask);
+                       c.d_levs, c.d_tab_lev[lev], lev, c0, xin, xout, b, omega, c.mask, omega1);
 }
 
 template <typename T, int MODE>
-static void launch_stencil_any(Ctx &c, int lev, int c0, int nc, const T *xin, T *xout, const T *b, double omega) {
+static void launch_stencil_any(Ctx &c, int lev, int c0, int nc, const T *xin, T *xout, const T *b, double omega,
+                               double omega1 = 0.0) {
     if (c.n_tab_lev[lev] == 0) return;
-    if (c.mg_npt == 4) launch_stencil<T, 4, MODE>(c, lev, c0, nc, xin, xout, b, omega);
-    else launch_stencil<T, 1, MODE>(c, lev, c0, nc, xin, xout, b, omega);
+    if (MODE != MG_FIRST2) omega1 = omega;
+    if (c.mg_npt == 4) launch_stencil<T, 4, MODE>(c, lev, c0, nc, xin, xout, b, omega, omega1);
+    else launch_stencil<T, 1, MODE>(c, lev, c0, nc, xin, xout, b, omega, omega1);
 }
 
 // one damped-Jacobi sweep with weight omega (first: from a zero iterate)
@@ -740,19 +808,14 @@ void launch_smooth(Ctx &c, int lev, int c0, int nc, const T *xin, T *xout, const
     else launch_stencil_any<T, MG_SWEEP>(c, lev, c0, nc, xin, xout, b, omega);
 }
 
-// The first two sweeps of a down pass (weights omega1, omega2) as one launch, on FP32
-// levels whose rows are a multiple of 4; returns false (nothing launched) elsewhere.
+// The first two sweeps of a down pass (weights omega1, omega2) as one launch: the
+// four-point kernel on FP32 levels whose rows are a multiple of 4, the one-point
+// kernel elsewhere (either precision).  Returns true (something launched or nothing
+// to do).
 template <typename T>
 bool launch_smooth_first2(Ctx &c, int lev, int c0, int nc, T *xout, const T *b, double omega1, double omega2) {
-    if constexpr (sizeof(T) == 4) {
-        if (c.mg_npt != 4 || !c.lev_row4[lev]) return false;
-        if (c.n_tab_lev[lev] == 0) return true;
-        hipLaunchKernelGGL(k_smooth_row4<MG_FIRST2>, dim3(c.n_tab_lev[lev], nc), dim3(RB_BLOCK), 0, c.stream,
-                           c.d_reps, c.d_levs, c.d_tab_lev[lev], lev, c0, (const float *)b, (float *)xout,
-                           (const float *)b, omega2, c.mask, omega1);
-        return true;
-    }
-    return false;
+    launch_stencil_any<T, MG_FIRST2>(c, lev, c0, nc, b, xout, b, omega2, omega1);
+    return true;
 }
 
 // Restriction of the residual r of level lev (written by a MG_RESID pass, zero at

@@ -1,14 +1,16 @@
 """The first two smoother sweeps of a down pass as one kernel against two sweeps.
 
-With mg_first2 = 1 the FP32 four-point levels (rows a multiple of 4 long) run the
-first sweep from zero and the second sweep as one launch that rebuilds the first
-iterate from the right-hand side; other levels, FP64 pools and single-sweep cycles
-keep the separate launches.  The fused sweep computes every value with the same
+With mg_first2 = 1 every level with at least two sweeps runs the first sweep from
+zero and the second sweep as one launch that rebuilds the first iterate from the
+right-hand side: the four-point kernel on FP32 levels whose rows are a multiple of 4
+long, the one-point kernel on every other level and on FP64 pools (single-sweep
+cycles keep one launch).  The fused sweep computes every value with the same
 operations as the two separate ones, so preconditioner outputs and whole FGMRES
 solves are identical to the bit: walls on every axis (wall terms of the diagonal at
-the first and last points of a row), a periodic x axis (wrapped neighbours), ragged
-levels that fall back to the separate sweeps, constant and Chebyshev weights, two and
-three pressure sweeps, and the full 256-replica ensemble.
+the first and last points of a row, and at the neighbours whose first iterate is
+rebuilt), a periodic x axis (wrapped neighbours), ragged levels, constant and
+Chebyshev weights, two and three pressure sweeps, FP64 pools, and the full
+256-replica ensemble (four-point levels).
 """
 import numpy as np
 import pytest
@@ -67,7 +69,7 @@ def test_first2_matches_two_sweeps(rb, name, cheby, sweeps):
     assert np.array_equal(a, b), float(np.abs(a - b).max() / np.abs(b).max())
 
 
-def test_first2_fp64_pools_unchanged(rb):
+def test_first2_fp64_pools(rb):
     ws = CASES["batch_mixed_depths"]
     print("first2 fp64", flush=True)
     assert np.array_equal(_precondition(rb, ws, 1, precond_fp32=0), _precondition(rb, ws, 0, precond_fp32=0))
