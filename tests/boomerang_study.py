@@ -12,7 +12,11 @@ which are compared with the oracle's quadrature of the Gibbs-Boltzmann
 marginals (tests/golden/boomerang_gb.json): the L2 norm of the density
 difference, and its statistical floor from batch means over groups of
 replicas.  ``--no-drift`` runs the naive scheme without the random finite
-differences, whose equilibrium is biased.
+differences, whose equilibrium is biased.  ``--scheme`` selects the
+deterministically second-order variants instead of Algorithm 1: ``trap`` and
+``mid`` (the two-stage family with predictor fraction 1 and 1/2, the forces
+evaluated again at the predictor) and ``ab2`` (Adams-Bashforth extrapolation of
+the deterministic velocity).
 
 Run from the repository root on a GPU, e.g.
     python tests/boomerang_study.py --dtau 0.036 --replicas 256 --steps 400 --burn 100 \\
@@ -90,6 +94,7 @@ def main():
     ap.add_argument("--burn", type=int, default=50, help="steps before sampling starts (counted from step 0)")
     ap.add_argument("--tol", type=float, default=1e-5)
     ap.add_argument("--no-drift", action="store_true")
+    ap.add_argument("--scheme", choices=("sem", "trap", "mid", "ab2"), default="sem")
     ap.add_argument("--seed", type=int, default=2024)
     ap.add_argument("--groups", type=int, default=16)
     ap.add_argument("--out", default=None)
@@ -130,8 +135,12 @@ def main():
     U = torch.empty((R, 6), dtype=torch.float64, device="cuda")
     pot = W.BOOMERANG_POTENTIAL
     fconst = [0.0, 0.0, -pot["weight"]]
-    log("boomerang study: dtau %.4g (dt %.4g), %d replicas, steps %d..%d, burn %d, tol %g, %s" % (
-        args.dtau, dt, R, k0, k0 + args.steps, args.burn, args.tol, "no drift" if args.no_drift else "RFD drift"))
+    log("boomerang study: dtau %.4g (dt %.4g), %d replicas, steps %d..%d, burn %d, tol %g, %s, scheme %s" % (
+        args.dtau, dt, R, k0, k0 + args.steps, args.burn, args.tol, "no drift" if args.no_drift else "RFD drift",
+        args.scheme))
+    qp, thp, FTp, Udp = torch.empty_like(q), torch.empty_like(th), torch.empty_like(FT), torch.zeros_like(FT)
+    have_prev = False
+    allow = (rb.RBFIB_EREJECT, rb.RBFIB_ENOCONV)
     rejected = iters = 0
     t0 = time.perf_counter()
 
@@ -140,7 +149,8 @@ def main():
         torch.cuda.synchronize()
         el = time.perf_counter() - t0
         result = {"dtau": args.dtau, "dt": dt, "replicas": R, "steps_total": step_end, "burn": args.burn,
-                  "tol": args.tol, "no_drift": bool(args.no_drift), "seconds_per_step": el / max(done, 1),
+                  "tol": args.tol, "no_drift": bool(args.no_drift), "scheme": args.scheme,
+                  "seconds_per_step": el / max(done, 1),
                   "rejected_this_run": rejected, "iterations_per_replica_step": iters / max(R * done, 1),
                   "samples": int(counts_h.sum())}
         if counts_h.sum() > 0:
@@ -159,8 +169,18 @@ def main():
 
     for k in range(k0, k0 + args.steps):
         rb.rbfib_body_forces(ctx, q, th, pot["phi0"], pot["d"], pot["b"], fconst, FT)
-        info = rb.rbfib_sem_step(ctx, q, th, FT, 1.0, dt, args.seed, k, U,
-                                 allow=(rb.RBFIB_EREJECT, rb.RBFIB_ENOCONV))
+        if args.scheme == "sem":
+            info = rb.rbfib_sem_step(ctx, q, th, FT, 1.0, dt, args.seed, k, U, allow=allow)
+        elif args.scheme == "ab2":
+            info = rb.rbfib_sem_ab2_step(ctx, q, th, FT, 1.0, dt, args.seed, k, Udp, have_prev, U, allow=allow)
+            have_prev = True
+        else:
+            infp = rb.rbfib_sem_rk2_predict(ctx, q, th, FT, 1.0, dt, args.seed, k, qp, thp,
+                                            alpha=1.0 if args.scheme == "trap" else 0.5, allow=allow)
+            rb.rbfib_body_forces(ctx, qp, thp, pot["phi0"], pot["d"], pot["b"], fconst, FTp)
+            info = rb.rbfib_sem_rk2_correct(ctx, q, th, FTp, U, allow=allow)
+            for a, b in zip(info, infp):
+                a.iters += b.iters
         bad = [i.status for i in info if i.status not in (rb.RBFIB_OK, rb.RBFIB_EREJECT)]
         if bad:
             raise RuntimeError("solver failure at step %d: %s" % (k, bad[:4]))
