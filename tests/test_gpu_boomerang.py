@@ -9,7 +9,8 @@
   equilibrium App. A shows to be biased), against the oracle's step at the
   same seed: U^n within the bound that the GPU's solve residuals imply;
 * a short ensemble run: with the drift the boomerangs keep their
-  Gibbs-Boltzmann distance to the walls, without it they drift towards them.
+  Gibbs-Boltzmann distance to the walls, without it they drift towards them;
+  so do the midpoint and Adams-Bashforth variants of the step (with noise).
 """
 import numpy as np
 import pytest
@@ -174,3 +175,49 @@ def test_drift_removes_wall_bias(rb):
         print("  wall fraction %.3f (Gibbs-Boltzmann %.3f)" % (frac[nd], p_ref), flush=True)
     assert abs(frac[0] - p_ref) < 0.04
     assert frac[1] > p_ref + 0.06
+
+
+@pytest.mark.parametrize("scheme", ["mid", "ab2"])
+def test_second_order_variants_keep_gibbs_boltzmann(rb, scheme):
+    """The deterministically second-order variants of the SEM step (the two-stage
+    family at alpha = 1/2, with the forces evaluated again at the predictor, and the
+    Adams-Bashforth extrapolation) with noise: 256 boomerangs from exact
+    Gibbs-Boltzmann draws, 100 steps at dtau = 0.14; the fraction of time the cross
+    point spends within 3h of a wall stays at its Gibbs-Boltzmann value (0.160).
+    Long runs of 512 replicas x 1000 steps: 0.166 +- 0.004 (midpoint), 0.153 +- 0.004
+    (Adams-Bashforth)."""
+    import json
+    import os
+    import torch
+    from tests.boomerang_study import initial_state
+    ref = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "boomerang_gb.json")))
+    ze = np.asarray(ref["z_edges"])
+    zc = 0.5 * (ze[1:] + ze[:-1])
+    p_ref = float(np.sum(np.asarray(ref["p_height"])[(zc < 3) | (zc > 13)]))
+    R, dtau = 256, 0.14
+    dt = W.boomerang_dt(dtau)
+    print("boomerang ensemble, scheme", scheme, flush=True)
+    ws = W.boomerang_slit(seed=5, n_replicas=R, dtau=dtau, tol=1e-5)
+    ctx = lib_context(rb, ws, tol=1e-5, precond_fp32=1)
+    q0, th0 = initial_state(R, 78)
+    q, th = dev(q0), dev(th0)
+    FT = torch.empty((R, 6), dtype=torch.float64, device="cuda")
+    U = torch.empty_like(FT)
+    qp, thp, FTp, Udp = torch.empty_like(q), torch.empty_like(th), torch.empty_like(FT), torch.zeros_like(FT)
+    allow = (rb.RBFIB_EREJECT,)
+    near = []
+    for k in range(100):
+        rb.rbfib_body_forces(ctx, q, th, POT["phi0"], POT["d"], POT["b"], FCONST, FT)
+        if scheme == "ab2":
+            rb.rbfib_sem_ab2_step(ctx, q, th, FT, 1.0, dt, 9, k, Udp, k > 0, U, allow=allow)
+        else:
+            rb.rbfib_sem_rk2_predict(ctx, q, th, FT, 1.0, dt, 9, k, qp, thp, alpha=0.5, allow=allow)
+            rb.rbfib_body_forces(ctx, qp, thp, POT["phi0"], POT["d"], POT["b"], FCONST, FTp)
+            rb.rbfib_sem_rk2_correct(ctx, q, th, FTp, U, allow=allow)
+        if k >= 30:
+            z = q[:, 2].cpu().numpy()
+            near.append(np.mean((z < 3.0) | (z > 13.0)))
+    ctx.close()
+    frac = float(np.mean(near))
+    print("  wall fraction %.3f (Gibbs-Boltzmann %.3f)" % (frac, p_ref), flush=True)
+    assert abs(frac - p_ref) < 0.04
