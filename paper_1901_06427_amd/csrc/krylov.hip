@@ -56,17 +56,35 @@ __global__ __launch_bounds__(RB_BLOCK) void k_dot_partial(const RepDev *reps, co
 // + i] when a scale is given.
 // blockIdx.z = t selects the t-th of several sets: partial entries at + t * zin, outputs at
 // + t * zout.
-__global__ void k_dot_reduce(const int *first, const int *nblk, const double *partial, int stride, double *out,
+#define RB_RED 256   // threads of the partial-sum reduction
+__global__ __launch_bounds__(RB_RED) void k_dot_reduce(const int *first, const int *nblk, const double *partial, int stride, double *out,
                              int out_stride, const int *mask, int take_sqrt, const double *scale, int zin = 0,
                              long long zout = 0) {
     int r = blockIdx.x, i = blockIdx.y;
     if (mask && !mask[r]) return;
-    const double *pp = partial + (long long)blockIdx.z * zin;
-    double s = 0.0;
-    for (int b = threadIdx.x; b < nblk[r]; b += 64) s += pp[(long long)(first[r] + b) * stride + i];
-    s = wave_sum(s);
-    if (scale) s *= scale[(long long)r * out_stride + i];
-    if (threadIdx.x == 0) out[(long long)blockIdx.z * zout + (long long)r * out_stride + i] = take_sqrt ? sqrt(s) : s;
+    const double *pp = partial + (long long)blockIdx.z * zin + (long long)first[r] * stride + i;
+    // RB_RED threads, four independent sums each (a single large replica has
+    // thousands of block partials per vector), then the workgroup's waves combined
+    const int n = nblk[r];
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    int b = threadIdx.x;
+    for (; b + 3 * RB_RED < n; b += 4 * RB_RED) {
+        s0 += pp[(long long)b * stride];
+        s1 += pp[(long long)(b + RB_RED) * stride];
+        s2 += pp[(long long)(b + 2 * RB_RED) * stride];
+        s3 += pp[(long long)(b + 3 * RB_RED) * stride];
+    }
+    for (; b < n; b += RB_RED) s0 += pp[(long long)b * stride];
+    double s = wave_sum((s0 + s1) + (s2 + s3));
+    __shared__ double red[RB_RED / 64];
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        s = red[0];
+        for (int k = 1; k < RB_RED / 64; ++k) s += red[k];
+        if (scale) s *= scale[(long long)r * out_stride + i];
+        out[(long long)blockIdx.z * zout + (long long)r * out_stride + i] = take_sqrt ? sqrt(s) : s;
+    }
 }
 
 // the kernel instance of the context's Krylov chunk
@@ -78,7 +96,7 @@ void launch_dots(Ctx &c, const double *V, int nvec, const double *w, double *out
     int stride = c.m + 1;
     hipLaunchKernelGGL(RB_BY_CHUNK(c, k_dot_partial, ), dim3(c.n_tab_vec), dim3(RB_BLOCK), 0, c.stream, c.d_reps,
                        c.d_tab_vec, V, c.L, nvec, w, c.partial, stride, mask);
-    hipLaunchKernelGGL(k_dot_reduce, dim3(c.nrep, nvec), dim3(64), 0, c.stream, c.d_vec_first, c.d_vec_nblk,
+    hipLaunchKernelGGL(k_dot_reduce, dim3(c.nrep, nvec), dim3(RB_RED), 0, c.stream, c.d_vec_first, c.d_vec_nblk,
                        c.partial, stride, out, c.m + 1, mask, 0, scale);
 }
 
@@ -86,7 +104,7 @@ void launch_norm(Ctx &c, const double *w, double *out, const int *mask) {
     int stride = c.m + 1;
     hipLaunchKernelGGL(RB_BY_CHUNK(c, k_dot_partial, ), dim3(c.n_tab_vec), dim3(RB_BLOCK), 0, c.stream, c.d_reps,
                        c.d_tab_vec, w, c.L, 1, w, c.partial, stride, mask);
-    hipLaunchKernelGGL(k_dot_reduce, dim3(c.nrep, 1), dim3(64), 0, c.stream, c.d_vec_first, c.d_vec_nblk, c.partial,
+    hipLaunchKernelGGL(k_dot_reduce, dim3(c.nrep, 1), dim3(RB_RED), 0, c.stream, c.d_vec_first, c.d_vec_nblk, c.partial,
                        stride, out, 1, mask, 1, (const double *)nullptr);
 }
 
@@ -170,7 +188,7 @@ void launch_axpy_multi_norm(Ctx &c, const double *V, int nvec, const double *coe
     int stride = c.m + 1;
     hipLaunchKernelGGL(RB_BY_CHUNK(c, k_axpy_multi, ), dim3(c.n_tab_vec), dim3(RB_BLOCK), 0, c.stream, c.d_reps,
                        c.d_tab_vec, V, c.L, nvec, coef, c.m + 1, scale, w, -1.0, mask, c.partial, stride);
-    hipLaunchKernelGGL(k_dot_reduce, dim3(c.nrep, 1), dim3(64), 0, c.stream, c.d_vec_first, c.d_vec_nblk, c.partial,
+    hipLaunchKernelGGL(k_dot_reduce, dim3(c.nrep, 1), dim3(RB_RED), 0, c.stream, c.d_vec_first, c.d_vec_nblk, c.partial,
                        stride, nrm, 1, mask, 1, (const double *)nullptr);
 }
 
@@ -432,7 +450,7 @@ void launch_block_dots(Ctx &c, int S, const double *V, int nvec, const double *W
     else if (S == 3) RB_DOTS(3);
     else RB_DOTS(4);
 #undef RB_DOTS
-    hipLaunchKernelGGL(k_dot_reduce, dim3(c.nrep, nvec, S), dim3(64), 0, c.stream, c.d_vec_first, c.d_vec_nblk,
+    hipLaunchKernelGGL(k_dot_reduce, dim3(c.nrep, nvec, S), dim3(RB_RED), 0, c.stream, c.d_vec_first, c.d_vec_nblk,
                        c.partial, stride, c.hblk, c.m + 1, mask, 0, scale, half, cset);
 }
 
@@ -448,7 +466,7 @@ void launch_block_update(Ctx &c, int S, const double *V, int nvec, double *W, co
     else RB_UPD(4);
 #undef RB_UPD
     const int ng = S * (S + 1) / 2;
-    hipLaunchKernelGGL(k_dot_reduce, dim3(c.nrep, ng), dim3(64), 0, c.stream, c.d_vec_first, c.d_vec_nblk, c.partial,
+    hipLaunchKernelGGL(k_dot_reduce, dim3(c.nrep, ng), dim3(RB_RED), 0, c.stream, c.d_vec_first, c.d_vec_nblk, c.partial,
                        stride, c.gram, RB_MAXG, mask, 0, (const double *)nullptr, 0, 0LL);
 }
 
